@@ -1,0 +1,106 @@
+"""Pins of the oracle's plain XPBD substep (Alg. 4, reading A17) and end-to-end
+checks of the property the method exists for: no interpenetration and a
+separation of at least xi after every step (Sec. 4.3: zero remaining
+violations at the end of every frame)."""
+import numpy as np
+import pytest
+
+from paper_2607_26901_amd import scenes as S
+
+
+def test_edge_coloring_valid_and_greedy(orc):
+    for sc in (S.c0(), S.strand_bundle(), S.two_layers()):
+        col, nc = orc.color_edges(sc.n_verts, sc.edges)
+        assert nc == col.max() + 1
+        seen = {}
+        for e, (a, b) in enumerate(sc.edges.tolist()):
+            c = col[e]
+            used = seen.get(a, set()) | seen.get(b, set())
+            assert c not in used                                  # colour classes share no vertex
+            assert all(k in used for k in range(c))               # smallest free colour
+            seen.setdefault(a, set()).add(c)
+            seen.setdefault(b, set()).add(c)
+
+
+def test_free_fall_closed_form(orc):
+    """Far from everything and moving rigidly, each iteration moves the anchor by
+    at most r towards the prediction x~ = x + dt v + dt^2 g (the clamp of Alg. 4),
+    so one step moves every dynamic vertex by min(|x~ - x|, iters r) along x~ - x."""
+    sc = S.drape(n=6, side=0.1, sphere_level=1, sphere_radius=0.05, height=0.5, jitter=1e-3, r=2e-3, xi=2e-3)
+    sim = orc.Sim(sc)
+    v0 = np.array([0.3, -0.1, 0.2])
+    sim.v[:36] = v0
+    x0 = sim.x.copy()
+    sp = sc.step
+    dt = float(np.float32(sp.dt))
+    g = np.array([float(np.float32(c)) for c in sp.gravity])
+    r = float(np.float32(sc.params.r))
+    sim.step()
+    delta = dt * v0 + dt * dt * g
+    move = delta * min(1.0, sp.iters * r / np.linalg.norm(delta))
+    assert np.allclose(sim.x[:36] - x0[:36], move, rtol=0, atol=1e-12)
+    assert np.array_equal(sim.x[36:], x0[36:])                   # the static sphere stays
+    assert np.allclose(sim.v[:36], move / dt, atol=1e-9)
+
+
+def test_stiff_distance_constraint(orc):
+    """With zero compliance one Gauss-Seidel pass restores a lone edge to its rest
+    length, and equal masses keep its midpoint (momentum)."""
+    x = np.array([[0.0, 0.0, 1.0], [0.012, 0.0, 1.0]])
+    m = S._Mesh(x, np.zeros((0, 3)), [5.0, 5.0])
+    m.extra_edges = np.array([[0, 1]])
+    sc = S.assemble("edge", [m], S.Params(r=1.0, xi=1e-3),
+                    S.StepParams(dt=1e-3, iters=1, alpha=0.0, gravity=(0, 0, 0)),
+                    rest_x=np.array([[0.0, 0.0, 1.0], [0.01, 0.0, 1.0]]))
+    sim = orc.Sim(sc)
+    sim.step()
+    assert np.isclose(np.linalg.norm(sim.x[0] - sim.x[1]), float(np.float32(0.01)), rtol=0, atol=1e-15)
+    assert np.allclose(sim.x.mean(0), x.mean(0), atol=1e-15)
+
+
+def _check_state(orc, sc, x):
+    xi = float(np.float32(sc.params.xi))
+    assert orc.count_intersections(x, sc.tris, sc.edges) == 0
+    dmin, below = orc.min_separation(x, sc.inv_mass, sc.tris, sc.edges, reach=4 * xi, below=xi * (1 - 1e-3))
+    assert below.sum() == 0, (dmin, below)
+    return dmin
+
+
+def test_c0_end_to_end_no_penetration(orc):
+    """Config C0 (32x32 cloth onto an icosphere, 10 steps of 10 iterations): no
+    interpenetration and separation >= xi after every step; contact starts."""
+    sc = S.c0()
+    sim = orc.Sim(sc)
+    for _ in range(sc.step.steps):
+        sim.step()
+        _check_state(orc, sc, sim.x)
+    c = sim.counters
+    assert c[3] > 0 and c[4] > 0              # regions were built and violated
+    assert c[5] <= 0.03 * c[4] + 5             # halting stays rare (Sec. 4.3 reports <= 3%)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: S.two_layers(n=10, seed=3),
+    lambda: S.strand_bundle(nx=3, ny=3, seg=12, seed=2),
+    lambda: S.particles_in_box(nx=4, ny=4, nz=5, seed=6),
+], ids=["two_layers", "strands", "particles"])
+def test_contact_scenes_no_penetration(orc, make):
+    """Scenes driven into contact: the upper layer thrown at the lower one,
+    strands swung sideways into each other, particles dropped into the box."""
+    sc = make()
+    rng = np.random.default_rng(0)
+    v = np.zeros_like(sc.x, dtype=np.float64)
+    if sc.name.startswith("two_layers"):
+        v[sc.n_verts // 2:, 2] = -0.6
+        v += rng.normal(0, 0.05, v.shape)
+    elif sc.name.startswith("bundle"):
+        v[:, 0] = rng.normal(0, 0.3, sc.n_verts)
+        v[:, 1] = rng.normal(0, 0.3, sc.n_verts)
+    else:
+        v[:, 2] = -1.0
+    v[sc.inv_mass == 0] = 0
+    sim = orc.Sim(sc, v=v)
+    for _ in range(3):
+        sim.step()
+        _check_state(orc, sc, sim.x)
+    assert sim.counters[4] > 0
