@@ -1,0 +1,257 @@
+/*
+ * ccfr.h -- C ABI of the MI355X (gfx950) implementation of the data-parallel hot
+ * path of Convex Collision-Free Regions (Kikuchi & Kanai, "Convex Collision-Free
+ * Regions"): per solver iteration,
+ *
+ *   ccfr_build_candidates       broad phase: primitive pairs whose padded boxes
+ *                               overlap (Sec. 4.1)
+ *   ccfr_build_regions          narrow phase: every vertex's convex region as
+ *                               half-spaces on its displacement (Eq. 1-3, Alg. 3)
+ *   ccfr_project_displacements  projection of proposed displacements onto the
+ *                               regions (Alg. 2 with Alg. 1, Sec. 3.2) and the
+ *                               r-ball clamp (Alg. 4)
+ *   ccfr_xpbd_step              the plain XPBD substep that calls the three
+ *                               (Alg. 4, without response or friction)
+ *
+ * plus batched entry points that run many independent meshes in one set of
+ * launches per step.
+ *
+ * General rules
+ *  - Every function returns a ccfr_status (0 = OK, negative = error) and never
+ *    throws.  Argument errors are detected before anything is enqueued and
+ *    leave outputs untouched.
+ *  - Array arguments named `*_dev` or documented as "device" are device
+ *    pointers (for example torch tensor data pointers) owned by the caller,
+ *    contiguous, float32 or int32 as stated.  Host arrays are read during the
+ *    call only.
+ *  - All device work is enqueued on the given HIP stream and returns without
+ *    waiting.  Errors found on the device (capacity overflow, non-finite input)
+ *    set sticky bits in the context's status word, read by ccfr_sync_status,
+ *    the only call that waits for the stream.  Outputs of a call whose status
+ *    bits are set are undefined.
+ *  - A context may be used from one host thread at a time; calls that share a
+ *    context must be issued on one stream or otherwise ordered by the caller.
+ *  - Units are metres and seconds.  Positions are [N][3] float32, packed.
+ */
+#ifndef CCFR_H
+#define CCFR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* ccfr_stream;   /* hipStream_t; NULL = the null stream */
+
+typedef enum {
+    CCFR_OK = 0,
+    CCFR_ERR_INVALID_ARG = -1,   /* bad pointer, size or parameter                      */
+    CCFR_ERR_CAPACITY = -2,      /* a device list outgrew its buffer (see ccfr_status_info) */
+    CCFR_ERR_HIP = -3,           /* a HIP runtime call failed                            */
+    CCFR_ERR_NONFINITE = -4,     /* a position or displacement was NaN or infinite       */
+    CCFR_ERR_DEGENERATE = -5,    /* reserved: degenerate primitives are skipped and counted */
+    CCFR_ERR_NOT_READY = -6,     /* batch slot or graph not in a usable state           */
+    CCFR_ERR_NO_MEMORY = -7      /* a device allocation failed                          */
+} ccfr_status;
+
+/* Collision parameters of one mesh (Sec. 3.1-3.2, Sec. 4.1, App. A-B). */
+typedef struct {
+    float r;            /* search radius; pairs are kept while phi < 2r, and no vertex
+                           moves more than r per iteration (Alg. 4 clamp)              */
+    float xi;           /* offset: minimum separation (phi = distance - xi)             */
+    float delta;        /* repulsion range: only widens the boxes here (Sec. 4.1)       */
+    float guard;        /* extra box padding keeping the FP32 box test conservative     */
+    float eps_retract;  /* retraction margin of Alg. 2 (Sec. 3.2), e.g. 1e-6 m          */
+    float eps_plesnik;  /* tolerance of Alg. 1, e.g. 1e-6                                */
+    int32_t max_passes; /* pass budget of Alg. 2 (its n_maxIterations), >= 1            */
+    int32_t flags;      /* reserved, 0                                                   */
+} ccfr_params;
+
+/* One half-space of a vertex region (Alg. 2's constraint tuple): a displacement
+ * y of the vertex is admissible iff n . y + d >= 0.  phi is the pair's
+ * separation measure (distance - xi), key = kind << 62 | a << 31 | b names the
+ * primitive pair (kind 1 = vertex-face (vertex a, triangle b), 2 = edge-edge
+ * (edges a < b), 3 = point-point (particles a < b)).  32 bytes. */
+typedef struct {
+    float n[3];
+    float d;
+    float phi;
+    uint32_t flags;
+    uint64_t key;
+} ccfr_halfspace;
+
+/* Candidate pair lists (Sec. 4.1, Alg. 3 inputs).  Pointers are device memory.
+ * counts_dev[0..2] hold |VF|, |EE|, |VV| on the device after the build; a count
+ * above its capacity means the list overflowed (CCFR_ERR_CAPACITY). */
+typedef struct {
+    int32_t* vf;          /* [cap_vf][2]: (vertex, triangle), vertex not in triangle  */
+    int32_t* ee;          /* [cap_ee][2]: (e, e') with e < e', sharing no vertex       */
+    int32_t* vv;          /* [cap_vv][2]: free particles (i, j), i < j                 */
+    int32_t* counts_dev;  /* [3]                                                       */
+    int64_t cap_vf, cap_ee, cap_vv;
+} ccfr_candidates;
+
+/* Per-vertex regions in CSR form.  Pointers are device memory: the half-spaces
+ * of vertex v are hs[offsets[v] .. offsets[v+1]), in no particular order. */
+typedef struct {
+    int32_t n_verts;
+    int32_t pad_;
+    int32_t* offsets;     /* [n_verts + 1] */
+    ccfr_halfspace* hs;   /* [cap]         */
+    int64_t cap;
+} ccfr_regions;
+
+/* XPBD substep parameters (Alg. 4). */
+typedef struct {
+    float dt;
+    float gravity[3];
+    int32_t iters;       /* solver iterations; each runs candidates, regions, one
+                            stretch pass and the projection                        */
+    float alpha;         /* stretch compliance (XPBD distance constraints)         */
+    ccfr_params collision;
+} ccfr_step_params;
+
+/* Device-side status and counters, copied out by ccfr_sync_status. */
+typedef struct {
+    uint32_t status_bits;   /* sticky: 1 VF, 2 EE, 4 VV, 8 half-spaces, 16 large
+                               primitives, 32 contacts overflowed; 64 non-finite    */
+    int32_t last_counts[3]; /* |VF|, |EE|, |VV| of the last candidate build          */
+    int32_t last_contacts;  /* pairs with phi < 2r in the last region build          */
+    int32_t last_halfspaces;/* half-spaces in the last region build                  */
+    int64_t need[6];        /* largest sizes seen since the last reset: VF, EE, VV,
+                               contacts, half-spaces, large primitives               */
+    int64_t totals[10];     /* accumulated since the last reset: [0..2] VF, EE, VV
+                               pairs, [3] half-spaces, [4] violating vertices, [5]
+                               halted vertices, [6] degenerate pairs, [7] projected
+                               vertices, [8] contacts (pairs with phi < 2r), [9]
+                               region builds                                        */
+} ccfr_status_info;
+
+typedef struct ccfr_ctx ccfr_ctx;
+typedef struct ccfr_mesh ccfr_mesh;
+typedef struct ccfr_batch ccfr_batch;
+
+/* Static text for a status code. */
+const char* ccfr_status_string(int code);
+
+/* Context on HIP device `device`: owns the workspace (grid, candidate lists,
+ * regions, scratch) and the device status word.  Capacities grow on demand
+ * through ccfr_reserve; the initial sizes come from the first mesh used. */
+int ccfr_create(ccfr_ctx** out, int device);
+void ccfr_destroy(ccfr_ctx* ctx);
+
+/* Device copy of one mesh (host arrays in, copied during the call):
+ *  tris [n_tris][3], edges [n_edges][2] (a < b; NULL: derived from the
+ *  triangles, unique and sorted), inv_mass [n_verts] (0 = static or pinned),
+ *  rest_x [n_verts][3] (NULL: no stretch constraints).  Builds the stretch rest
+ *  lengths, the greedy edge colouring used by the Gauss-Seidel pass, the list of
+ *  free particles (vertices in no edge and no triangle) and the grid cell size. */
+int ccfr_mesh_create(ccfr_ctx* ctx, int32_t n_verts, const int32_t* tris, int32_t n_tris,
+                     const int32_t* edges, int32_t n_edges, const float* inv_mass,
+                     const float* rest_x, ccfr_mesh** out);
+void ccfr_mesh_destroy(ccfr_mesh* mesh);
+/* Edge count after derivation, and a copy of the (possibly derived) edges. */
+int ccfr_mesh_edges(const ccfr_mesh* mesh, int32_t* n_edges, int32_t* edges_host /* nullable */);
+/* Device pointer to the mesh's inverse masses [n_verts] (float32). */
+const float* ccfr_mesh_inv_mass_dev(const ccfr_mesh* mesh);
+
+/* Grow the workspace so that lists of the given sizes fit (0 keeps a size).
+ * Waits for the context's previous work.  Invalidates captured step graphs. */
+int ccfr_reserve(ccfr_ctx* ctx, int64_t vf, int64_t ee, int64_t vv, int64_t contacts,
+                 int64_t halfspaces, ccfr_stream stream);
+
+/* Broad phase (Sec. 4.1): every vertex-face, edge-edge and particle-particle pair
+ * whose padded FP32 boxes overlap, with pad = fl32(r + xi/2 + delta/2 + guard)
+ * and per axis lo = fl32(min - pad), hi = fl32(max + pad); pairs whose vertices
+ * all have zero inverse mass are skipped.  x_anchor_dev: [n_verts][3] device.
+ * On return `out` views the context's lists, valid until the next build on ctx. */
+int ccfr_build_candidates(ccfr_ctx* ctx, const ccfr_mesh* mesh, const float* x_anchor_dev,
+                          const ccfr_params* params, ccfr_candidates* out, ccfr_stream stream);
+
+/* Narrow phase (Alg. 3 with Eq. 1-3): for each candidate pair, the closest points,
+ * phi = distance - xi, and, while phi < 2r, the half-space (n, s phi) for every
+ * vertex of the pair with non-zero inverse mass, n pointing away from the other
+ * primitive and s the side's share w_side / (w_A + w_B) of barycentric-weighted
+ * inverse masses.  `cands` may be the context's lists or caller-owned device
+ * lists.  On return `out` views the context's regions, valid until the next build. */
+int ccfr_build_regions(ccfr_ctx* ctx, const ccfr_mesh* mesh, const float* x_anchor_dev,
+                       const ccfr_candidates* cands, const ccfr_params* params,
+                       ccfr_regions* out, ccfr_stream stream);
+
+/* Projection (Alg. 2 calling Alg. 1, with the epsilon retraction and halt
+ * fallback of Sec. 3.2, then the clamp |y| <= r of Alg. 4), per vertex v with
+ * proposed displacement y_in[v] = x'_v - x_v:
+ *   half-spaces sorted by rho = n . y_in + d ascending (ties by key), exact
+ *   duplicates dropped; up to max_passes passes of Alg. 1 over the violated
+ *   ones; a pass with no violation returns its start point; otherwise y = 0 and
+ *   halted[v] = 1.  Vertices with zero inverse mass get y = 0.
+ * regions: device CSR (the context's or caller-owned).  inv_mass_dev [N],
+ * y_in_dev, y_out_dev [N][3] device (y_out may alias y_in); halted_dev [N] uint8
+ * device or NULL.  The per-vertex arithmetic runs in FP64 registers. */
+int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const float* inv_mass_dev,
+                               const float* y_in_dev, const ccfr_params* params, float* y_out_dev,
+                               uint8_t* halted_dev, ccfr_stream stream);
+
+/* One substep (Alg. 4 without response, friction or early exit), in place on
+ * x_dev and v_dev ([n_verts][3] device):
+ *   x~ = x + dt v + dt^2 g for dynamic vertices; lambda = 0;
+ *   per iteration: candidates and regions at the anchor x; p = x~; one
+ *   Gauss-Seidel pass of XPBD distance constraints over the edge colours
+ *   (lambda kept across iterations); x += project(p - x);
+ *   finally v = (x - x_start) / dt.
+ * The first call for a (mesh, x, v, parameters) combination records a HIP graph
+ * of the whole substep; later calls replay it. */
+int ccfr_xpbd_step(ccfr_ctx* ctx, const ccfr_mesh* mesh, float* x_dev, float* v_dev,
+                   const ccfr_step_params* sp, ccfr_stream stream);
+
+/* Waits for `stream`, copies the status word and counters into *info (nullable)
+ * and returns CCFR_ERR_CAPACITY / CCFR_ERR_NONFINITE if the matching sticky bits
+ * are set, else CCFR_OK.  reset != 0 clears the bits, need[] and totals[]. */
+int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, int reset);
+
+/* ---- stage timing (measurement) ----
+ * With profiling enabled, every substep runs as individual launches (not as the
+ * recorded graph) and records HIP events around its stages on its stream:
+ *   0 grid build (counter reset, binning, bucket scan, scatter)
+ *   1 pair emission (the broad-phase query kernel alone)
+ *   2 contacts (narrow phase: closest points, per-vertex counts)
+ *   3 region fill (offset scan and half-space scatter)
+ *   4 stretch pass (prediction copy and the colour passes)
+ *   5 projection
+ * Disabling profiling returns to the recorded graph. */
+int ccfr_profile_enable(ccfr_ctx* ctx, int enable);
+/* Waits for `stream`, then writes per stage the milliseconds summed over the
+ * iterations of the most recent substep (ms[6]) and its launch count per stage
+ * (launches[6], nullable). */
+int ccfr_profile_read(ccfr_ctx* ctx, ccfr_stream stream, float* ms, int32_t* launches);
+
+/* ---- batches: many independent meshes stepped together ---- */
+/* A batch holds up to `max_slots` meshes resident on the device (positions,
+ * velocities, topology) within `max_verts`, `max_tris` and `max_edges` in total.
+ * Meshes in different slots never interact: their pairs are never formed. */
+int ccfr_batch_create(ccfr_ctx* ctx, int32_t max_slots, int64_t max_verts, int64_t max_tris,
+                      int64_t max_edges, ccfr_batch** out);
+void ccfr_batch_destroy(ccfr_batch* b);
+/* Bytes of device memory a mesh of these sizes occupies inside a batch. */
+int64_t ccfr_batch_footprint(int32_t n_verts, int32_t n_tris, int32_t n_edges);
+/* Admit a mesh (host arrays as in ccfr_mesh_create, plus initial x and v) with
+ * its own parameters; *slot receives its slot id.  CCFR_ERR_CAPACITY if it does
+ * not fit now.  Copies happen on `stream`. */
+int ccfr_batch_add(ccfr_batch* b, int32_t n_verts, const int32_t* tris, int32_t n_tris,
+                   const int32_t* edges, int32_t n_edges, const float* inv_mass,
+                   const float* rest_x, const float* x, const float* v,
+                   const ccfr_step_params* sp, int32_t* slot, ccfr_stream stream);
+/* Release a slot; its memory is reused by later admissions. */
+int ccfr_batch_remove(ccfr_batch* b, int32_t slot, ccfr_stream stream);
+/* One substep of every resident mesh (all meshes must share `iters`). */
+int ccfr_batch_step(ccfr_batch* b, ccfr_stream stream);
+/* Copy a slot's positions / velocities ([n][3] float32) to host memory (waits). */
+int ccfr_batch_read(ccfr_batch* b, int32_t slot, float* x_host, float* v_host, ccfr_stream stream);
+/* Number of resident meshes and their total vertex count. */
+int ccfr_batch_stats(const ccfr_batch* b, int32_t* n_resident, int64_t* n_verts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,343 @@
+"""Python binding of the gfx950 CCFR library (libccfr.so, C ABI in include/ccfr.h).
+
+Argument marshalling only: every step of the hot path runs in the library's HIP
+kernels.  Device arrays are torch tensors on the GPU (contiguous float32 /
+int32), which supply memory; calls are enqueued on torch's current stream.
+Importing this module does not touch the GPU; loading the library fails loudly
+when it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libccfr.so")
+
+HALFSPACE_DTYPE = np.dtype([("n", "<f4", (3,)), ("d", "<f4"), ("phi", "<f4"), ("flags", "<u4"),
+                            ("key", "<u8")])
+assert HALFSPACE_DTYPE.itemsize == 32
+
+STATUS_NAMES = {0: "ok", -1: "invalid argument", -2: "capacity", -3: "hip", -4: "non-finite",
+                -5: "degenerate", -6: "not ready", -7: "no memory"}
+
+
+class CcfrError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {STATUS_NAMES.get(code, code)} ({code})")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("r", C.c_float), ("xi", C.c_float), ("delta", C.c_float), ("guard", C.c_float),
+                ("eps_retract", C.c_float), ("eps_plesnik", C.c_float), ("max_passes", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+class Candidates(C.Structure):
+    _fields_ = [("vf", C.c_void_p), ("ee", C.c_void_p), ("vv", C.c_void_p), ("counts_dev", C.c_void_p),
+                ("cap_vf", C.c_int64), ("cap_ee", C.c_int64), ("cap_vv", C.c_int64)]
+
+
+class Regions(C.Structure):
+    _fields_ = [("n_verts", C.c_int32), ("pad_", C.c_int32), ("offsets", C.c_void_p), ("hs", C.c_void_p),
+                ("cap", C.c_int64)]
+
+
+class StepParams(C.Structure):
+    _fields_ = [("dt", C.c_float), ("gravity", C.c_float * 3), ("iters", C.c_int32), ("alpha", C.c_float),
+                ("collision", Params)]
+
+
+class StatusInfo(C.Structure):
+    _fields_ = [("status_bits", C.c_uint32), ("last_counts", C.c_int32 * 3), ("last_contacts", C.c_int32),
+                ("last_halfspaces", C.c_int32), ("need", C.c_int64 * 6), ("totals", C.c_int64 * 10)]
+
+
+EXPORTS = ["ccfr_status_string", "ccfr_create", "ccfr_destroy", "ccfr_mesh_create", "ccfr_mesh_destroy",
+           "ccfr_mesh_edges", "ccfr_mesh_inv_mass_dev", "ccfr_reserve", "ccfr_build_candidates",
+           "ccfr_build_regions", "ccfr_project_displacements", "ccfr_xpbd_step", "ccfr_sync_status",
+           "ccfr_profile_enable", "ccfr_profile_read",
+           "ccfr_batch_create", "ccfr_batch_destroy", "ccfr_batch_footprint", "ccfr_batch_add",
+           "ccfr_batch_remove", "ccfr_batch_step", "ccfr_batch_read", "ccfr_batch_stats"]
+
+_lib = None
+
+
+def load():
+    """Load libccfr.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run paper_2607_26901_amd/build.py (or __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.ccfr_status_string.restype = C.c_char_p
+    lib.ccfr_status_string.argtypes = [C.c_int]
+    lib.ccfr_create.argtypes = [C.POINTER(vp), C.c_int]
+    lib.ccfr_destroy.argtypes = [vp]
+    lib.ccfr_destroy.restype = None
+    lib.ccfr_mesh_create.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp, C.POINTER(vp)]
+    lib.ccfr_mesh_destroy.argtypes = [vp]
+    lib.ccfr_mesh_destroy.restype = None
+    lib.ccfr_mesh_edges.argtypes = [vp, C.POINTER(i32), vp]
+    lib.ccfr_mesh_inv_mass_dev.restype = vp
+    lib.ccfr_mesh_inv_mass_dev.argtypes = [vp]
+    lib.ccfr_reserve.argtypes = [vp, i64, i64, i64, i64, i64, vp]
+    lib.ccfr_build_candidates.argtypes = [vp, vp, vp, C.POINTER(Params), C.POINTER(Candidates), vp]
+    lib.ccfr_build_regions.argtypes = [vp, vp, vp, C.POINTER(Candidates), C.POINTER(Params),
+                                       C.POINTER(Regions), vp]
+    lib.ccfr_project_displacements.argtypes = [vp, C.POINTER(Regions), vp, vp, C.POINTER(Params), vp, vp, vp]
+    lib.ccfr_xpbd_step.argtypes = [vp, vp, vp, vp, C.POINTER(StepParams), vp]
+    lib.ccfr_sync_status.argtypes = [vp, vp, C.POINTER(StatusInfo), C.c_int]
+    lib.ccfr_profile_enable.argtypes = [vp, C.c_int]
+    lib.ccfr_profile_read.argtypes = [vp, vp, vp, vp]
+    if hasattr(lib, "ccfr_batch_create"):
+        lib.ccfr_batch_create.argtypes = [vp, i32, i64, i64, i64, C.POINTER(vp)]
+        lib.ccfr_batch_destroy.argtypes = [vp]
+        lib.ccfr_batch_destroy.restype = None
+        lib.ccfr_batch_footprint.restype = i64
+        lib.ccfr_batch_footprint.argtypes = [i32, i32, i32]
+        lib.ccfr_batch_add.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp, vp, vp, C.POINTER(StepParams),
+                                       C.POINTER(i32), vp]
+        lib.ccfr_batch_remove.argtypes = [vp, i32, vp]
+        lib.ccfr_batch_step.argtypes = [vp, vp]
+        lib.ccfr_batch_read.argtypes = [vp, i32, vp, vp, vp]
+        lib.ccfr_batch_stats.argtypes = [vp, C.POINTER(i32), C.POINTER(i64)]
+    _lib = lib
+    return lib
+
+
+def _check(code, where):
+    if code != 0:
+        raise CcfrError(code, where)
+
+
+def _ptr(t):
+    """Device pointer of a contiguous torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    if a is None:
+        return None, None
+    a = np.ascontiguousarray(a, dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_params(p) -> Params:
+    """From anything with r, xi, delta, guard, eps_retract, eps_plesnik, max_passes."""
+    return Params(p.r, p.xi, p.delta, p.guard, p.eps_retract, p.eps_plesnik, int(p.max_passes), 0)
+
+
+def make_step_params(step, p) -> StepParams:
+    return StepParams(step.dt, (C.c_float * 3)(*step.gravity), int(step.iters), step.alpha, make_params(p))
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        h = C.c_void_p()
+        _check(self.lib.ccfr_create(C.byref(h), int(device)), "ccfr_create")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            self.lib.ccfr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reserve(self, vf=0, ee=0, vv=0, contacts=0, halfspaces=0, stream=None):
+        _check(self.lib.ccfr_reserve(self.h, int(vf), int(ee), int(vv), int(contacts), int(halfspaces),
+                                     _stream(stream)), "ccfr_reserve")
+
+    def sync_status(self, reset=False, stream=None, raise_on_error=False):
+        info = StatusInfo()
+        code = self.lib.ccfr_sync_status(self.h, _stream(stream), C.byref(info), int(bool(reset)))
+        if code == -3 or (raise_on_error and code != 0):
+            raise CcfrError(code, "ccfr_sync_status")
+        return code, {
+            "status_bits": int(info.status_bits),
+            "last_counts": list(info.last_counts),
+            "last_contacts": int(info.last_contacts),
+            "last_halfspaces": int(info.last_halfspaces),
+            "need": list(info.need),
+            "totals": list(info.totals),
+        }
+
+
+    def profile_enable(self, on=True):
+        _check(self.lib.ccfr_profile_enable(self.h, int(bool(on))), "ccfr_profile_enable")
+
+    def profile_read(self, stream=None):
+        """(ms per stage [6], launches per stage [6]) of the most recent substep."""
+        ms = np.zeros(6, np.float32)
+        n = np.zeros(6, np.int32)
+        _check(self.lib.ccfr_profile_read(self.h, _stream(stream), ms.ctypes.data_as(C.c_void_p),
+                                          n.ctypes.data_as(C.c_void_p)), "ccfr_profile_read")
+        return ms, n
+
+
+STAGES = ["grid_build", "pair_emission", "contacts", "region_fill", "stretch", "projection"]
+
+
+class Mesh:
+    """Device copy of a mesh (topology, inverse masses, stretch data)."""
+
+    def __init__(self, ctx: Context, n_verts, tris, edges, inv_mass, rest_x=None):
+        self.ctx = ctx
+        lib = ctx.lib
+        tris_a, tris_p = _host(np.asarray(tris).reshape(-1, 3), np.int32)
+        edges_a, edges_p = _host(None if edges is None else np.asarray(edges).reshape(-1, 2), np.int32)
+        w_a, w_p = _host(inv_mass, np.float32)
+        r_a, r_p = _host(None if rest_x is None else np.asarray(rest_x).reshape(-1, 3), np.float32)
+        h = C.c_void_p()
+        _check(lib.ccfr_mesh_create(ctx.h, int(n_verts), tris_p, len(tris_a), edges_p,
+                                    0 if edges_a is None else len(edges_a), w_p, r_p, C.byref(h)),
+               "ccfr_mesh_create")
+        self.h = h
+        self.n_verts = int(n_verts)
+        ne = C.c_int32()
+        lib.ccfr_mesh_edges(h, C.byref(ne), None)
+        self.n_edges = int(ne.value)
+
+    def edges(self) -> np.ndarray:
+        out = np.zeros((self.n_edges, 2), np.int32)
+        ne = C.c_int32()
+        self.ctx.lib.ccfr_mesh_edges(self.h, C.byref(ne), out.ctypes.data_as(C.c_void_p))
+        return out
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.ccfr_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mesh_from_scene(ctx: Context, scene, stretch=True) -> Mesh:
+    return Mesh(ctx, scene.n_verts, scene.tris, scene.edges, scene.inv_mass,
+                scene.rest_x if stretch else None)
+
+
+def build_candidates(ctx: Context, mesh: Mesh, x, params, stream=None) -> Candidates:
+    out = Candidates()
+    prm = params if isinstance(params, Params) else make_params(params)
+    _check(ctx.lib.ccfr_build_candidates(ctx.h, mesh.h, _ptr(x), C.byref(prm), C.byref(out), _stream(stream)),
+           "ccfr_build_candidates")
+    return out
+
+
+def build_regions(ctx: Context, mesh: Mesh, x, cands: Candidates, params, stream=None) -> Regions:
+    out = Regions()
+    prm = params if isinstance(params, Params) else make_params(params)
+    _check(ctx.lib.ccfr_build_regions(ctx.h, mesh.h, _ptr(x), C.byref(cands), C.byref(prm), C.byref(out),
+                                      _stream(stream)), "ccfr_build_regions")
+    return out
+
+
+def project_displacements(ctx: Context, regions: Regions, inv_mass, y_in, params, y_out, halted=None,
+                          stream=None):
+    prm = params if isinstance(params, Params) else make_params(params)
+    _check(ctx.lib.ccfr_project_displacements(ctx.h, C.byref(regions), _ptr(inv_mass), _ptr(y_in), C.byref(prm),
+                                              _ptr(y_out), _ptr(halted), _stream(stream)),
+           "ccfr_project_displacements")
+
+
+def xpbd_step(ctx: Context, mesh: Mesh, x, v, step_params: StepParams, stream=None):
+    _check(ctx.lib.ccfr_xpbd_step(ctx.h, mesh.h, _ptr(x), _ptr(v), C.byref(step_params), _stream(stream)),
+           "ccfr_xpbd_step")
+
+
+def caller_candidates(vf, ee, vv, counts) -> Candidates:
+    """Candidates view over caller-owned device tensors ([P][2] int32 each, counts [3] int32)."""
+    return Candidates(vf.data_ptr(), ee.data_ptr(), vv.data_ptr(), counts.data_ptr(), vf.shape[0], ee.shape[0],
+                      vv.shape[0])
+
+
+def caller_regions(offsets, hs_bytes) -> Regions:
+    """Regions view over caller-owned device tensors: offsets [N+1] int32, hs_bytes [H*32] uint8."""
+    return Regions(offsets.shape[0] - 1, 0, offsets.data_ptr(), hs_bytes.data_ptr(), hs_bytes.numel() // 32)
+
+
+# ---- copying device lists back (for tests and counters) ----
+
+def _dev_view(ptr, count, dtype, device):
+    """Copy `count` elements of dtype from a device pointer into a host numpy array."""
+    import torch
+    nbytes = int(count) * np.dtype(dtype).itemsize
+    if nbytes == 0:
+        return np.zeros(0, dtype)
+    host = torch.empty(nbytes, dtype=torch.uint8)
+    dst = host.data_ptr()
+    # device-to-host copy through the HIP runtime torch already loaded
+    hip = _hiprt()
+    rc = hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(ptr), C.c_size_t(nbytes), 2)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed: {rc}")
+    return host.numpy().view(dtype).copy()
+
+
+_hip = None
+
+
+def _hiprt():
+    global _hip
+    if _hip is None:
+        for name in ("libamdhip64.so", "libamdhip64.so.7", "libamdhip64.so.6"):
+            try:
+                _hip = C.CDLL(name)
+                break
+            except OSError:
+                continue
+        if _hip is None:
+            raise RuntimeError("libamdhip64 not found")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    return _hip
+
+
+def read_candidates(c: Candidates) -> dict:
+    """Synchronous copy of the candidate lists (the stream must be synchronised)."""
+    counts = _dev_view(c.counts_dev, 3, np.int32, None)
+    caps = (c.cap_vf, c.cap_ee, c.cap_vv)
+    out = {}
+    for k, (name, ptr) in enumerate((("vf", c.vf), ("ee", c.ee), ("vv", c.vv))):
+        n = int(counts[k])
+        if n > caps[k]:
+            raise CcfrError(-2, f"{name} list overflow ({n} > {caps[k]})")
+        out[name] = _dev_view(ptr, 2 * n, np.int32, None).reshape(-1, 2)
+    out["counts"] = counts
+    return out
+
+
+def read_regions(r: Regions):
+    """Synchronous copy: (offsets [N+1] int32, half-spaces [H] HALFSPACE_DTYPE)."""
+    off = _dev_view(r.offsets, r.n_verts + 1, np.int32, None)
+    H = int(off[-1])
+    if H > r.cap:
+        raise CcfrError(-2, f"half-space overflow ({H} > {r.cap})")
+    hs = _dev_view(r.hs, H * 32, np.uint8, None).view(HALFSPACE_DTYPE)
+    return off, hs

@@ -1,0 +1,176 @@
+// ccfr_internal.h -- shared device-side definitions of the gfx950 CCFR library.
+//
+// Layout on the device (one "scene" = one or more concatenated meshes):
+//   x        float [N][3]   anchor positions (packed, 12 B per vertex)
+//   inv_mass float [N]
+//   tris     int   [T][3],  edges int [E][2]
+//   vmesh    u16   [N]      mesh id of every vertex (nullptr: all mesh 0)
+//   MeshParams table [M]    per-mesh collision parameters and grid cell size
+//
+// Broad phase: a multi-level spatial hash grid.  Every target primitive
+// (triangle, edge, free particle) is binned once, at the finest level where its
+// box spans at most two cells, by the cell of its box's lower corner; a query
+// scans the 3x3x3 cells (at most) its own box can reach on each occupied level.
+// The bucket of a cell keeps the low two bits of each cell coordinate verbatim
+// and hashes the rest, so the <= 27 cells a query scans on one level always land
+// in distinct buckets and no target is seen twice by one query.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ccfr.h"
+
+namespace ccfr {
+
+enum : int { KIND_VF = 1, KIND_EE = 2, KIND_VV = 3 };
+
+// status bits (sticky)
+enum : uint32_t {
+    ST_VF = 1u, ST_EE = 2u, ST_VV = 4u, ST_HS = 8u, ST_LARGE = 16u, ST_CONTACTS = 32u,
+    ST_NONFINITE = 64u,
+};
+
+struct MeshParams {
+    float r, xi, pad, two_r;
+    float eps_retract, eps_plesnik, h, inv_h;   // h: grid cell size of this mesh
+    int32_t max_passes, mesh_salt, pad0, pad1;
+};
+
+// Device counters shared by all kernels of a context.
+struct DevCounters {
+    uint32_t status;
+    int32_t n_vf, n_ee, n_vv;          // pair counts of the current build
+    int32_t n_large_t, n_large_e;      // large primitives of the current build
+    int32_t n_contacts;                // pairs inside the range
+    int32_t n_viol;                    // violating vertices (list for the slow path)
+    int32_t last_hs;
+    int32_t pad0[3];
+    long long need[6];                 // max sizes seen: vf, ee, vv, contacts, hs, large
+    long long totals[10];              // vf, ee, vv, hs, violating, halted, degenerate, projected,
+                                       // contacts, region builds
+};
+
+// One binned target of the grid: its padded box, index and flags (32 B).
+struct GridEntry {
+    float lo[3];
+    int32_t idx;
+    float hi[3];
+    uint32_t flags;   // bit 0: all vertices static; bits 8..23: mesh id
+};
+
+// A pair inside the interaction range, between the two passes of the region
+// build: normal (side A away from side B), phi, side A's share, the pair.
+struct Contact {
+    float n[3];
+    float phi;
+    float dA, dB;      // d = s phi of side A and of side B
+    int32_t a;         // kind << 30 | first primitive
+    int32_t b;         // second primitive
+};
+
+struct ParamSrc {
+    const MeshParams* table;   // device table, or nullptr for the single mesh `one`
+    const uint16_t* vmesh;     // per-vertex mesh id, or nullptr
+    MeshParams one;
+    __device__ __forceinline__ int mesh_of(int v) const { return vmesh ? (int)vmesh[v] : 0; }
+    __device__ __forceinline__ MeshParams get(int m) const { return table ? table[m] : one; }
+};
+
+__device__ __forceinline__ uint32_t mix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x7feb352dU;
+    h ^= h >> 15;
+    h *= 0x846ca68bU;
+    h ^= h >> 16;
+    return h;
+}
+
+// bucket of cell (cx, cy, cz) of mesh `salt` in a table of 2^log2s buckets (log2s >= 6)
+__device__ __forceinline__ uint32_t cell_bucket(int cx, int cy, int cz, int salt, int log2s) {
+    uint32_t low = (uint32_t)(cx & 3) | ((uint32_t)(cy & 3) << 2) | ((uint32_t)(cz & 3) << 4);
+    uint32_t h = mix32((uint32_t)(cx >> 2) * 0x9E3779B1u ^ mix32((uint32_t)(cy >> 2) * 0x85EBCA77u ^
+                       mix32((uint32_t)(cz >> 2) * 0xC2B2AE3Du ^ (uint32_t)salt)));
+    uint32_t mask = (1u << (log2s - 6)) - 1u;
+    return low | ((h & mask) << 6);
+}
+
+__device__ __forceinline__ int cell_coord(float v, float inv_h) {
+    float c = floorf(v * inv_h);
+    c = fminf(fmaxf(c, -1.0e9f), 1.0e9f);
+    return (int)c;
+}
+
+// ---- launchers (defined in the .hip files) ----
+struct Scene {
+    int32_t n_verts, n_tris, n_edges, n_free;
+    const float* x;
+    const float* inv_mass;
+    const int32_t* tris;
+    const int32_t* edges;
+    const int32_t* free_list;   // [n_free] free particles (vertices in no edge / triangle)
+    const uint8_t* is_free;     // [n_verts]
+    int32_t narrow_fp32;        // 1: narrow-phase arithmetic in FP32 instead of FP64
+    ParamSrc prm;
+};
+
+struct GridWs {
+    int log2s;                  // table size S = 2^log2s buckets per kind
+    int32_t* cnt;               // [3 S] counts, zero between builds
+    int32_t* start;             // [3 S + 1] exclusive prefix
+    int32_t* rank;              // [T + E + F] rank of each target inside its bucket
+    int32_t* key;               // [T + E + F] kind * S + bucket, -1 = large / skipped
+    GridEntry* entries;         // [T + E + F] sorted targets
+    uint32_t* level_mask;       // [n_meshes] grid levels occupied by each mesh
+    int32_t n_meshes;
+    int32_t* scan_tmp;          // block partials of the scan
+};
+
+struct PairLists {
+    int32_t* vf; int32_t* ee; int32_t* vv;
+    int64_t cap_vf, cap_ee, cap_vv;
+};
+
+void launch_reset_build(DevCounters* c, uint32_t* level_mask, int n_meshes, hipStream_t s);
+void launch_grid_count(const Scene& sc, GridWs& g, DevCounters* c, hipStream_t s);
+void launch_scan(const int32_t* in, int32_t* out, int32_t* zero_in, int n, int32_t* tmp, hipStream_t s);
+void launch_grid_scatter(const Scene& sc, GridWs& g, hipStream_t s);
+void launch_pairs(const Scene& sc, const GridWs& g, PairLists pl, DevCounters* c, hipStream_t s);
+void launch_finalize_pairs(const GridWs& g, PairLists pl, DevCounters* c, hipStream_t s);
+
+void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
+                     const int32_t* counts, int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
+                     Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c,
+                     hipStream_t s);
+void launch_fill(const Scene& sc, const Contact* contacts, int64_t cap_contacts, const int32_t* offsets,
+                 int32_t* vcount, ccfr_halfspace* hs, int64_t cap_hs, DevCounters* c, hipStream_t s);
+
+struct ProjectArgs {
+    int32_t n_verts;
+    const int32_t* offsets;
+    const ccfr_halfspace* hs;
+    int64_t cap_hs;
+    const float* inv_mass;
+    const float* y_in;       // displacement in (or nullptr: use p - x)
+    const float* p;          // proposal positions (when y_in == nullptr)
+    float* x_anchor;         // anchor, updated in place when y_out == nullptr
+    float* y_out;
+    uint8_t* halted;
+    double* sort_key;        // [cap_hs] scratch
+    int32_t* sort_idx;       // [cap_hs] scratch
+    ParamSrc prm;
+};
+void launch_project(const ProjectArgs& a, DevCounters* c, hipStream_t s);
+
+void launch_predict(int n, const float* x, const float* v, const float* inv_mass, float dt,
+                    float gx, float gy, float gz, float* x_pred, float* x_start, hipStream_t s);
+void launch_fill_zero(float* p, int64_t n, hipStream_t s);
+void launch_copy(const float* src, float* dst, int64_t n, hipStream_t s);
+void launch_stretch_color(const int32_t* edges_sorted, const float* rest_sorted, int32_t begin,
+                          int32_t count, const float* inv_mass, float* p, float* lambda_sorted,
+                          float alpha_t, hipStream_t s);
+void launch_update_velocity(int n, const float* x, const float* x_start, float inv_dt, float* v,
+                            hipStream_t s);
+void launch_check_finite(const float* a, int64_t n, DevCounters* c, hipStream_t s);
+
+}  // namespace ccfr

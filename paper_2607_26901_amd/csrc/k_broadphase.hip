@@ -1,0 +1,370 @@
+// k_broadphase.hip -- candidate primitive pairs (Sec. 4.1 broad phase) on gfx950.
+//
+// Contract (exact in FP32): pad = fl32(r + xi/2 + delta/2 + guard); a primitive's
+// box is lo = fl32(min_v x_v - pad), hi = fl32(max_v x_v + pad) per axis; two
+// primitives are a candidate pair iff their boxes overlap on all three axes.
+// Pair kinds: vertex-face (vertex not in the triangle), edge-edge (no shared
+// vertex, e < e'), free particle pairs (i < j); pairs whose vertices all have
+// zero inverse mass are skipped, and primitives of different meshes never pair.
+// The grid below only decides which pairs are tested; the set is decided by the
+// box test alone.
+//
+// Multi-level hash grid.  Level l has cells of size h 2^l (h per mesh).  Every
+// target (triangle, edge, free particle) is binned once, at the finest level
+// where its box spans at most two cells per axis, in the cell of its box's lower
+// corner.  A query whose box spans at most two cells at level l finds every
+// overlapping target of that level in the 3 x 3 x 3 cells [c(lo) - 1, c(hi)];
+// it scans the levels, at or above its own, that its mesh occupies (a bitmask
+// kept per mesh).  Pairs of two edges binned at different levels are found only
+// by the finer one; pairs at the same level by the lower index.  Uneven sizes
+// (a 4 m ground quad under 8 mm cloth triangles, large obstacles under fine
+// hair) therefore cost a few extra buckets, not a brute-force list.
+//
+// Pipeline per build:
+//   reset        counters and the per-mesh level masks
+//   grid_count   one thread per target: box, level, bucket, rank inside the
+//                bucket (atomic)
+//   scan         exclusive prefix of the per-(kind, bucket) counts
+//   grid_scatter targets to their sorted slots (32 B entries)
+//   pairs        one thread per query (vertex, then edge); found pairs are
+//                compacted per wavefront (ballot + popcount, one atomic per
+//                wave and round)
+#include "ccfr_internal.h"
+
+#include <algorithm>
+
+namespace ccfr {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxLevel = 24;
+
+__device__ __forceinline__ void load3(const float* x, int v, float o[3]) {
+    o[0] = x[3 * v + 0];
+    o[1] = x[3 * v + 1];
+    o[2] = x[3 * v + 2];
+}
+
+__device__ __forceinline__ bool finite3(const float o[3]) {
+    return isfinite(o[0]) && isfinite(o[1]) && isfinite(o[2]);
+}
+
+__device__ __forceinline__ bool overlap(const float alo[3], const float ahi[3], const float blo[3],
+                                        const float bhi[3]) {
+    return alo[0] <= bhi[0] && blo[0] <= ahi[0] && alo[1] <= bhi[1] && blo[1] <= ahi[1] &&
+           alo[2] <= bhi[2] && blo[2] <= ahi[2];
+}
+
+// Wavefront-aggregated append of (a, b) for the lanes with pred set.  Every
+// active lane of the wave must call it.
+__device__ __forceinline__ void emit_pair(int32_t* list, int32_t* counter, int64_t cap, int a, int b,
+                                          bool pred) {
+    const unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+    base = __shfl(base, leader);
+    if (pred) {
+        const long long idx = (long long)base + __popcll(mask & ((1ull << lane) - 1ull));
+        if (idx < cap) {
+            list[2 * idx + 0] = a;
+            list[2 * idx + 1] = b;
+        }
+    }
+}
+
+// The target primitive behind grid slot t: triangles, then edges, then free particles.
+struct Target {
+    int kind;      // KIND_VF (triangle), KIND_EE (edge), KIND_VV (particle)
+    int idx;
+    int nv;
+    int v[3];
+};
+
+__device__ __forceinline__ Target target_of(const Scene& sc, int t) {
+    Target g;
+    if (t < sc.n_tris) {
+        g.kind = KIND_VF; g.idx = t; g.nv = 3;
+        g.v[0] = sc.tris[3 * t]; g.v[1] = sc.tris[3 * t + 1]; g.v[2] = sc.tris[3 * t + 2];
+    } else if (t < sc.n_tris + sc.n_edges) {
+        const int e = t - sc.n_tris;
+        g.kind = KIND_EE; g.idx = e; g.nv = 2;
+        g.v[0] = sc.edges[2 * e]; g.v[1] = sc.edges[2 * e + 1]; g.v[2] = g.v[1];
+    } else {
+        const int p = sc.free_list[t - sc.n_tris - sc.n_edges];
+        g.kind = KIND_VV; g.idx = p; g.nv = 1;
+        g.v[0] = g.v[1] = g.v[2] = p;
+    }
+    return g;
+}
+
+// Box of a target and its static flag; false if a coordinate is not finite.
+__device__ __forceinline__ bool target_box(const Scene& sc, const Target& g, float pad, float lo[3],
+                                           float hi[3], bool* is_static) {
+    float p[3];
+    load3(sc.x, g.v[0], p);
+    bool fin = finite3(p);
+    float mn[3] = {p[0], p[1], p[2]}, mx[3] = {p[0], p[1], p[2]};
+    bool st = sc.inv_mass[g.v[0]] == 0.0f;
+    for (int i = 1; i < g.nv; ++i) {
+        load3(sc.x, g.v[i], p);
+        fin = fin && finite3(p);
+        st = st && (sc.inv_mass[g.v[i]] == 0.0f);
+        for (int k = 0; k < 3; ++k) {
+            mn[k] = fminf(mn[k], p[k]);
+            mx[k] = fmaxf(mx[k], p[k]);
+        }
+    }
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = __fsub_rn(mn[k], pad);
+        hi[k] = __fadd_rn(mx[k], pad);
+    }
+    *is_static = st;
+    return fin;
+}
+
+// Finest level at which the box spans at most two cells per axis (-1: none).
+__device__ __forceinline__ int box_level(const float lo[3], const float hi[3], float inv_h, int clo[3]) {
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        const float inv = ldexpf(inv_h, -l);
+        bool fits = true;
+        for (int k = 0; k < 3; ++k) {
+            clo[k] = cell_coord(lo[k], inv);
+            fits = fits && (cell_coord(hi[k], inv) - clo[k] <= 1);
+        }
+        if (fits) return l;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ int level_salt(int mesh_salt, int level) {
+    return mesh_salt ^ (int)((uint32_t)(level + 1) * 0x9E3779B9u);
+}
+
+__device__ __forceinline__ uint32_t make_flags(bool st, int level, int mesh) {
+    return (st ? 1u : 0u) | ((uint32_t)level << 1) | ((uint32_t)mesh << 8);
+}
+
+__device__ __forceinline__ bool entry_ok(const GridEntry& e, int mesh, int level, bool q_static) {
+    // same mesh, binned at the level being scanned, not a static-static pair
+    return (e.flags >> 8) == (uint32_t)mesh && ((e.flags >> 1) & 31u) == (uint32_t)level &&
+           !(q_static && (e.flags & 1u));
+}
+
+__global__ void k_reset_build(DevCounters* c, uint32_t* level_mask, int n_meshes) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c->n_vf = c->n_ee = c->n_vv = 0;
+        c->n_large_t = c->n_large_e = 0;
+        c->n_contacts = 0;
+        c->n_viol = 0;
+    }
+    for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n_meshes; m += gridDim.x * blockDim.x)
+        level_mask[m] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCounters* c) {
+    const int n_targets = sc.n_tris + sc.n_edges + sc.n_free;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n_targets) return;
+    const Target tg = target_of(sc, t);
+    const int mesh = sc.prm.mesh_of(tg.v[0]);
+    const MeshParams P = sc.prm.get(mesh);
+    float lo[3], hi[3];
+    bool st;
+    if (!target_box(sc, tg, P.pad, lo, hi, &st)) {
+        atomicOr(&c->status, ST_NONFINITE);
+        g.key[t] = -1;
+        return;
+    }
+    int clo[3];
+    const int level = box_level(lo, hi, P.inv_h, clo);
+    if (level < 0) {                      // a box wider than h 2^24: not binned
+        atomicOr(&c->status, ST_LARGE);
+        g.key[t] = -1;
+        return;
+    }
+    atomicOr(&g.level_mask[mesh], 1u << level);
+    const uint32_t b = cell_bucket(clo[0], clo[1], clo[2], level_salt(P.mesh_salt, level), g.log2s);
+    const int key = (tg.kind - 1) * (1 << g.log2s) + (int)b;
+    g.key[t] = key;
+    g.rank[t] = atomicAdd(&g.cnt[key], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g) {
+    const int n_targets = sc.n_tris + sc.n_edges + sc.n_free;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n_targets) return;
+    const int key = g.key[t];
+    if (key < 0) return;
+    const Target tg = target_of(sc, t);
+    const int mesh = sc.prm.mesh_of(tg.v[0]);
+    const MeshParams P = sc.prm.get(mesh);
+    float lo[3], hi[3];
+    bool st;
+    target_box(sc, tg, P.pad, lo, hi, &st);
+    int clo[3];
+    const int level = box_level(lo, hi, P.inv_h, clo);
+    GridEntry e;
+    for (int k = 0; k < 3; ++k) { e.lo[k] = lo[k]; e.hi[k] = hi[k]; }
+    e.idx = tg.idx;
+    e.flags = make_flags(st, level, mesh);
+    g.entries[g.start[key] + g.rank[t]] = e;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists pl, DevCounters* c) {
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    const int n_q = sc.n_verts + sc.n_edges;
+    if (q >= n_q) return;
+    const int S = 1 << g.log2s;
+    if (q < sc.n_verts) {
+        // ---- vertex query: vertex-face pairs, and particle pairs for free particles
+        const int v = q;
+        const int mesh = sc.prm.mesh_of(v);
+        const MeshParams P = sc.prm.get(mesh);
+        float p[3];
+        load3(sc.x, v, p);
+        if (!finite3(p)) return;
+        float lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = __fsub_rn(p[k], P.pad);
+            hi[k] = __fadd_rn(p[k], P.pad);
+        }
+        const bool q_static = sc.inv_mass[v] == 0.0f;
+        const bool q_free = sc.is_free[v] != 0;
+        uint32_t levels = g.level_mask[mesh];
+        while (levels) {
+            const int l = __ffs((int)levels) - 1;
+            levels &= levels - 1u;
+            const float inv = ldexpf(P.inv_h, -l);
+            const int salt = level_salt(P.mesh_salt, l);
+            int clo[3], chi[3];
+            for (int k = 0; k < 3; ++k) {
+                clo[k] = cell_coord(lo[k], inv);
+                chi[k] = cell_coord(hi[k], inv);
+            }
+            for (int cz = clo[2] - 1; cz <= chi[2]; ++cz)
+                for (int cy = clo[1] - 1; cy <= chi[1]; ++cy)
+                    for (int cx = clo[0] - 1; cx <= chi[0]; ++cx) {
+                        const uint32_t b = cell_bucket(cx, cy, cz, salt, g.log2s);
+                        const int s0 = g.start[b], s1 = g.start[b + 1];
+                        for (int i = s0; i < s1; ++i) {
+                            const GridEntry e = g.entries[i];
+                            bool hit = entry_ok(e, mesh, l, q_static) && overlap(lo, hi, e.lo, e.hi);
+                            if (hit) {
+                                const int* tv = sc.tris + 3 * e.idx;
+                                hit = tv[0] != v && tv[1] != v && tv[2] != v;
+                            }
+                            emit_pair(pl.vf, &c->n_vf, pl.cap_vf, v, e.idx, hit);
+                        }
+                        if (q_free && l == 0) {
+                            const int k0 = 2 * S + (int)b;
+                            const int u0 = g.start[k0], u1 = g.start[k0 + 1];
+                            for (int i = u0; i < u1; ++i) {
+                                const GridEntry e = g.entries[i];
+                                const bool hit = e.idx > v && entry_ok(e, mesh, 0, q_static) &&
+                                                 overlap(lo, hi, e.lo, e.hi);
+                                emit_pair(pl.vv, &c->n_vv, pl.cap_vv, v, e.idx, hit);
+                            }
+                        }
+                    }
+        }
+    } else {
+        // ---- edge query: edge-edge pairs
+        const int eq = q - sc.n_verts;
+        const int a = sc.edges[2 * eq], bb = sc.edges[2 * eq + 1];
+        const int mesh = sc.prm.mesh_of(a);
+        const MeshParams P = sc.prm.get(mesh);
+        float pa[3], pb[3];
+        load3(sc.x, a, pa);
+        load3(sc.x, bb, pb);
+        if (!finite3(pa) || !finite3(pb)) return;
+        float lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = __fsub_rn(fminf(pa[k], pb[k]), P.pad);
+            hi[k] = __fadd_rn(fmaxf(pa[k], pb[k]), P.pad);
+        }
+        int clo[3], chi[3];
+        const int lq = box_level(lo, hi, P.inv_h, clo);
+        if (lq < 0) return;
+        const bool q_static = sc.inv_mass[a] == 0.0f && sc.inv_mass[bb] == 0.0f;
+        uint32_t levels = g.level_mask[mesh] & ~((1u << lq) - 1u);
+        while (levels) {
+            const int l = __ffs((int)levels) - 1;
+            levels &= levels - 1u;
+            const float inv = ldexpf(P.inv_h, -l);
+            const int salt = level_salt(P.mesh_salt, l);
+            for (int k = 0; k < 3; ++k) {
+                clo[k] = cell_coord(lo[k], inv);
+                chi[k] = cell_coord(hi[k], inv);
+            }
+            for (int cz = clo[2] - 1; cz <= chi[2]; ++cz)
+                for (int cy = clo[1] - 1; cy <= chi[1]; ++cy)
+                    for (int cx = clo[0] - 1; cx <= chi[0]; ++cx) {
+                        const int k0 = S + (int)cell_bucket(cx, cy, cz, salt, g.log2s);
+                        const int s0 = g.start[k0], s1 = g.start[k0 + 1];
+                        for (int i = s0; i < s1; ++i) {
+                            const GridEntry e = g.entries[i];
+                            bool hit = (l > lq || e.idx > eq) && entry_ok(e, mesh, l, q_static) &&
+                                       overlap(lo, hi, e.lo, e.hi);
+                            if (hit) {
+                                const int c0 = sc.edges[2 * e.idx], c1 = sc.edges[2 * e.idx + 1];
+                                hit = c0 != a && c0 != bb && c1 != a && c1 != bb;
+                            }
+                            emit_pair(pl.ee, &c->n_ee, pl.cap_ee, min(eq, e.idx), max(eq, e.idx), hit);
+                        }
+                    }
+        }
+    }
+}
+
+// Overflow bits, largest sizes seen and running totals of one build.
+__global__ void k_finalize_pairs(PairLists pl, DevCounters* c) {
+    if (threadIdx.x != 0) return;
+    const long long nvf = c->n_vf, nee = c->n_ee, nvv = c->n_vv;
+    uint32_t st = 0;
+    if (nvf > pl.cap_vf) st |= ST_VF;
+    if (nee > pl.cap_ee) st |= ST_EE;
+    if (nvv > pl.cap_vv) st |= ST_VV;
+    if (st) c->status |= st;
+    c->need[0] = max(c->need[0], nvf);
+    c->need[1] = max(c->need[1], nee);
+    c->need[2] = max(c->need[2], nvv);
+    c->totals[0] += nvf;
+    c->totals[1] += nee;
+    c->totals[2] += nvv;
+}
+
+}  // namespace
+
+void launch_reset_build(DevCounters* c, uint32_t* level_mask, int n_meshes, hipStream_t s) {
+    const int blocks = std::max(1, std::min(64, (n_meshes + 255) / 256));
+    hipLaunchKernelGGL(k_reset_build, dim3(blocks), dim3(256), 0, s, c, level_mask, n_meshes);
+}
+
+void launch_grid_count(const Scene& sc, GridWs& g, DevCounters* c, hipStream_t s) {
+    const int n = sc.n_tris + sc.n_edges + sc.n_free;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_grid_count, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, g, c);
+}
+
+void launch_grid_scatter(const Scene& sc, GridWs& g, hipStream_t s) {
+    const int n = sc.n_tris + sc.n_edges + sc.n_free;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_grid_scatter, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, g);
+}
+
+void launch_pairs(const Scene& sc, const GridWs& g, PairLists pl, DevCounters* c, hipStream_t s) {
+    const int n = sc.n_verts + sc.n_edges;
+    if (n > 0)
+        hipLaunchKernelGGL(k_pairs, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, g, pl, c);
+}
+
+void launch_finalize_pairs(const GridWs& g, PairLists pl, DevCounters* c, hipStream_t s) {
+    (void)g;
+    hipLaunchKernelGGL(k_finalize_pairs, dim3(1), dim3(64), 0, s, pl, c);
+}
+
+}  // namespace ccfr

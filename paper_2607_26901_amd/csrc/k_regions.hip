@@ -1,0 +1,347 @@
+// k_regions.hip -- per-vertex convex regions (Alg. 3 with Eq. 1-3) on gfx950.
+//
+// Work is per candidate pair rather than per vertex: the pair's closest points
+// are computed once and its half-space is scattered to every vertex of the pair
+// with non-zero inverse mass.  This yields exactly the union of Alg. 3's three
+// per-vertex loops (VF for the vertex, EE for both edges' endpoints, FV for the
+// face's vertices), because all of them evaluate the same closest points of the
+// same pair.  Two passes build the CSR:
+//
+//   contacts  per pair: closest points in pair-local coordinates (one vertex
+//             subtracted first), phi = |x_A - x_B| - xi, kept while phi < 2r;
+//             kept pairs are compacted into 32 B Contact records (normal, phi,
+//             the two sides' d = s phi) and every receiving vertex's count is
+//             incremented.  The arithmetic runs in FP64 registers by default
+//             (FP32 in, FP32 out): near-parallel edges make the FP32 closest
+//             points lose digits as 1/sin^2 of their angle, and CDNA's FP64
+//             rate keeps this memory-bound kernel's cost unchanged.
+//   scan      counts -> offsets
+//   fill      per contact: (n, s_A phi) to side A's vertices, (-n, s_B phi) to
+//             side B's, each at offsets[v] + (atomic decrement of its count),
+//             which also returns the counts to zero for the next build
+//
+// Readings of the printed Alg. 3: d = s (|n| - xi) (A1); for the face side of a
+// vertex-face pair the normal points from the vertex towards the face and the
+// share is w_f / (w_f + w_q) (A5); effective inverse masses are
+// sum_i bary_i w_i (A6) and a pair with w_A + w_B = 0 gives no half-space;
+// parallel edges (|d1 x d2|^2 <= 1e-10 |d1|^2 |d2|^2) take the midpoint of
+// their overlap (A7); zero-area triangles, zero-length edges and coincident
+// closest points are skipped and counted (A8).
+#include "ccfr_internal.h"
+
+namespace ccfr {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <class R>
+__device__ __forceinline__ void ld3(const float* x, int v, R o[3]) {
+    o[0] = (R)x[3 * v]; o[1] = (R)x[3 * v + 1]; o[2] = (R)x[3 * v + 2];
+}
+template <class R>
+__device__ __forceinline__ R dot3(const R a[3], const R b[3]) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+template <class R>
+__device__ __forceinline__ R clamp01(R v) {
+    return v < R(0) ? R(0) : (v > R(1) ? R(1) : v);
+}
+
+// Closest point of triangle (a, b, c) to the origin (the query vertex has been
+// subtracted): Voronoi-region walk.  Returns false for a zero-area triangle.
+template <class R>
+__device__ bool closest_on_triangle(const R a[3], const R b[3], const R c[3], R q[3], R bary[3]) {
+    R ab[3], ac[3], n[3];
+    for (int k = 0; k < 3; ++k) { ab[k] = b[k] - a[k]; ac[k] = c[k] - a[k]; }
+    n[0] = ab[1] * ac[2] - ab[2] * ac[1];
+    n[1] = ab[2] * ac[0] - ab[0] * ac[2];
+    n[2] = ab[0] * ac[1] - ab[1] * ac[0];
+    if (dot3(n, n) <= R(1e-12) * dot3(ab, ab) * dot3(ac, ac)) return false;
+    // p = origin: ap = -a, bp = -b, cp = -c
+    const R d1 = -dot3(ab, a), d2 = -dot3(ac, a);
+    const R d3 = -dot3(ab, b), d4 = -dot3(ac, b);
+    const R d5 = -dot3(ab, c), d6 = -dot3(ac, c);
+    R u, v, w;   // barycentrics of a, b, c
+    if (d1 <= R(0) && d2 <= R(0)) { u = 1; v = 0; w = 0; }
+    else if (d3 >= R(0) && d4 <= d3) { u = 0; v = 1; w = 0; }
+    else if (d6 >= R(0) && d5 <= d6) { u = 0; v = 0; w = 1; }
+    else {
+        const R vc = d1 * d4 - d3 * d2;
+        const R vb = d5 * d2 - d1 * d6;
+        const R va = d3 * d6 - d5 * d4;
+        if (vc <= R(0) && d1 >= R(0) && d3 <= R(0)) {
+            v = d1 / (d1 - d3); u = R(1) - v; w = 0;
+        } else if (vb <= R(0) && d2 >= R(0) && d6 <= R(0)) {
+            w = d2 / (d2 - d6); u = R(1) - w; v = 0;
+        } else if (va <= R(0) && (d4 - d3) >= R(0) && (d5 - d6) >= R(0)) {
+            w = (d4 - d3) / ((d4 - d3) + (d5 - d6)); v = R(1) - w; u = 0;
+        } else {
+            const R den = R(1) / (va + vb + vc);
+            v = vb * den; w = vc * den; u = R(1) - v - w;
+        }
+    }
+    bary[0] = u; bary[1] = v; bary[2] = w;
+    for (int k = 0; k < 3; ++k) q[k] = u * a[k] + v * b[k] + w * c[k];
+    return true;
+}
+
+// Closest points p = a + s (b - a), q = c + t (d - c) of two segments.
+// Returns 0, 1 (parallel rule used) or -1 (zero-length segment).
+template <class R>
+__device__ int closest_on_segments(const R a[3], const R b[3], const R c[3], const R d[3], R* s_out, R* t_out) {
+    R d1[3], d2[3], r[3], cr[3];
+    for (int k = 0; k < 3; ++k) { d1[k] = b[k] - a[k]; d2[k] = d[k] - c[k]; r[k] = a[k] - c[k]; }
+    const R A = dot3(d1, d1), E = dot3(d2, d2);
+    if (A <= R(0) || E <= R(0)) return -1;
+    const R F = dot3(d2, r), C = dot3(d1, r), B = dot3(d1, d2);
+    cr[0] = d1[1] * d2[2] - d1[2] * d2[1];
+    cr[1] = d1[2] * d2[0] - d1[0] * d2[2];
+    cr[2] = d1[0] * d2[1] - d1[1] * d2[0];
+    R s, t;
+    if (dot3(cr, cr) <= R(1e-10) * A * E) {
+        R ca[3], da[3];
+        for (int k = 0; k < 3; ++k) { ca[k] = c[k] - a[k]; da[k] = d[k] - a[k]; }
+        const R tc = dot3(ca, d1) / A, td = dot3(da, d1) / A;
+        const R lo = tc < td ? tc : td, hi = tc < td ? td : tc;
+        const R olo = lo > R(0) ? lo : R(0), ohi = hi < R(1) ? hi : R(1);
+        s = olo <= ohi ? R(0.5) * (olo + ohi) : (hi < R(0) ? R(0) : R(1));
+        R pc[3];
+        for (int k = 0; k < 3; ++k) pc[k] = a[k] + s * d1[k] - c[k];
+        t = clamp01(dot3(pc, d2) / E);
+        *s_out = s; *t_out = t;
+        return 1;
+    }
+    const R den = A * E - B * B;
+    s = clamp01((B * F - C * E) / den);
+    t = (B * s + F) / E;
+    if (t < R(0)) { t = 0; s = clamp01(-C / A); }
+    else if (t > R(1)) { t = 1; s = clamp01((B - C) / A); }
+    *s_out = s; *t_out = t;
+    return 0;
+}
+
+__device__ __forceinline__ void wave_append(Contact* list, int32_t* counter, int64_t cap, const Contact& rec,
+                                            bool pred) {
+    const unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+    base = __shfl(base, leader);
+    if (pred) {
+        const long long idx = (long long)base + __popcll(mask & ((1ull << lane) - 1ull));
+        if (idx < cap) list[idx] = rec;
+    }
+}
+
+// Evaluate pair i of the concatenated lists [VF | EE | VV].  On success fills
+// the contact (normal from side B towards side A) and the vertices of both sides.
+struct PairVerts {
+    int nA, nB;
+    int a[2], b[3];
+};
+
+template <class R>
+__device__ bool eval_pair(const Scene& sc, int kind, int pa, int pb, Contact* rec, PairVerts* pv,
+                          bool* degenerate) {
+    *degenerate = false;
+    R nvec[3];
+    R wA, wB;
+    int mesh;
+    if (kind == KIND_VF) {
+        const int v = pa, t = pb;
+        const int t0 = sc.tris[3 * t], t1 = sc.tris[3 * t + 1], t2 = sc.tris[3 * t + 2];
+        mesh = sc.prm.mesh_of(v);
+        R p[3], A[3], B[3], Cc[3];
+        ld3(sc.x, v, p); ld3(sc.x, t0, A); ld3(sc.x, t1, B); ld3(sc.x, t2, Cc);
+        for (int k = 0; k < 3; ++k) { A[k] -= p[k]; B[k] -= p[k]; Cc[k] -= p[k]; }
+        R q[3], bary[3];
+        if (!closest_on_triangle(A, B, Cc, q, bary)) { *degenerate = true; return false; }
+        for (int k = 0; k < 3; ++k) nvec[k] = -q[k];
+        wA = (R)sc.inv_mass[v];
+        wB = bary[0] * (R)sc.inv_mass[t0] + bary[1] * (R)sc.inv_mass[t1] + bary[2] * (R)sc.inv_mass[t2];
+        pv->nA = 1; pv->a[0] = v;
+        pv->nB = 3; pv->b[0] = t0; pv->b[1] = t1; pv->b[2] = t2;
+    } else if (kind == KIND_EE) {
+        const int e = pa, f = pb;   // e < f
+        const int e0 = sc.edges[2 * e], e1 = sc.edges[2 * e + 1];
+        const int f0 = sc.edges[2 * f], f1 = sc.edges[2 * f + 1];
+        mesh = sc.prm.mesh_of(e0);
+        R A[3], B[3], Cc[3], D[3];
+        ld3(sc.x, e0, A); ld3(sc.x, e1, B); ld3(sc.x, f0, Cc); ld3(sc.x, f1, D);
+        for (int k = 0; k < 3; ++k) { B[k] -= A[k]; Cc[k] -= A[k]; D[k] -= A[k]; A[k] = R(0); }
+        R s, t;
+        if (closest_on_segments(A, B, Cc, D, &s, &t) < 0) { *degenerate = true; return false; }
+        for (int k = 0; k < 3; ++k) {
+            const R pp = s * B[k];
+            const R qq = Cc[k] + t * (D[k] - Cc[k]);
+            nvec[k] = pp - qq;
+        }
+        wA = (R(1) - s) * (R)sc.inv_mass[e0] + s * (R)sc.inv_mass[e1];
+        wB = (R(1) - t) * (R)sc.inv_mass[f0] + t * (R)sc.inv_mass[f1];
+        pv->nA = 2; pv->a[0] = e0; pv->a[1] = e1;
+        pv->nB = 2; pv->b[0] = f0; pv->b[1] = f1;
+    } else {
+        const int i = pa, j = pb;
+        mesh = sc.prm.mesh_of(i);
+        R A[3], B[3];
+        ld3(sc.x, i, A); ld3(sc.x, j, B);
+        for (int k = 0; k < 3; ++k) nvec[k] = A[k] - B[k];
+        wA = (R)sc.inv_mass[i];
+        wB = (R)sc.inv_mass[j];
+        pv->nA = 1; pv->a[0] = i;
+        pv->nB = 1; pv->b[0] = j;
+    }
+    const MeshParams P = sc.prm.get(mesh);
+    const R D = sqrt(dot3(nvec, nvec));
+    const R phi = D - (R)P.xi;
+    if (!(phi < (R)P.two_r)) return false;
+    if (D == R(0)) { *degenerate = true; return false; }
+    const R wsum = wA + wB;
+    if (wsum == R(0)) return false;
+    const R inv = R(1) / D;
+    for (int k = 0; k < 3; ++k) rec->n[k] = (float)(nvec[k] * inv);
+    rec->phi = (float)phi;
+    // d = s phi, formed in the working precision and stored
+    rec->dA = (float)(wA / wsum * phi);
+    rec->dB = (float)(wB / wsum * phi);
+    rec->a = pa | (kind << 30);
+    rec->b = pb;
+    return true;
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_contacts(Scene sc, const int32_t* vf, const int32_t* ee,
+                                                     const int32_t* vv, const int32_t* counts,
+                                                     int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
+                                                     Contact* contacts, int64_t cap_contacts,
+                                                     int32_t* vcount, DevCounters* c) {
+    const long long nvf = min((long long)counts[0], (long long)cap_vf);
+    const long long nee = min((long long)counts[1], (long long)cap_ee);
+    const long long nvv = min((long long)counts[2], (long long)cap_vv);
+    const long long total = nvf + nee + nvv;
+    int n_degenerate = 0;
+    // grid-stride: every lane of a wave runs the same number of rounds so that
+    // the wave-level append sees all lanes together
+    const long long stride = (long long)gridDim.x * kBlock;
+    const long long rounds = (total + stride - 1) / stride;
+    const long long i0 = (long long)blockIdx.x * kBlock + threadIdx.x;
+    for (long long rd = 0; rd < rounds; ++rd) {
+        const long long i = i0 + rd * stride;
+        bool keep = false;
+        Contact rec;
+        PairVerts pv;
+        if (i < total) {
+            int kind, pa, pb;
+            if (i < nvf) { kind = KIND_VF; pa = vf[2 * i]; pb = vf[2 * i + 1]; }
+            else if (i < nvf + nee) { const long long j = i - nvf; kind = KIND_EE; pa = ee[2 * j]; pb = ee[2 * j + 1]; }
+            else { const long long j = i - nvf - nee; kind = KIND_VV; pa = vv[2 * j]; pb = vv[2 * j + 1]; }
+            bool deg;
+            keep = eval_pair<R>(sc, kind, pa, pb, &rec, &pv, &deg);
+            n_degenerate += deg ? 1 : 0;
+            if (keep) {
+                for (int k = 0; k < pv.nA; ++k)
+                    if (sc.inv_mass[pv.a[k]] > 0.f) atomicAdd(&vcount[pv.a[k]], 1);
+                for (int k = 0; k < pv.nB; ++k)
+                    if (sc.inv_mass[pv.b[k]] > 0.f) atomicAdd(&vcount[pv.b[k]], 1);
+            }
+        }
+        wave_append(contacts, &c->n_contacts, cap_contacts, rec, keep);
+    }
+    if (n_degenerate) atomicAdd((unsigned long long*)&c->totals[6], (unsigned long long)n_degenerate);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(Scene sc, const Contact* contacts, int64_t cap_contacts,
+                                                 const int32_t* offsets, int32_t* vcount, ccfr_halfspace* hs,
+                                                 int64_t cap_hs, DevCounters* c) {
+    const long long n = min((long long)c->n_contacts, (long long)cap_contacts);
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        const Contact rec = contacts[i];
+        const int kind = (int)((uint32_t)rec.a >> 30);
+        const int pa = rec.a & 0x3fffffff, pb = rec.b;
+        int va[2], vb[3], nA, nB;
+        if (kind == KIND_VF) {
+            nA = 1; va[0] = pa;
+            nB = 3; vb[0] = sc.tris[3 * pb]; vb[1] = sc.tris[3 * pb + 1]; vb[2] = sc.tris[3 * pb + 2];
+        } else if (kind == KIND_EE) {
+            nA = 2; va[0] = sc.edges[2 * pa]; va[1] = sc.edges[2 * pa + 1];
+            nB = 2; vb[0] = sc.edges[2 * pb]; vb[1] = sc.edges[2 * pb + 1];
+        } else {
+            nA = 1; va[0] = pa;
+            nB = 1; vb[0] = pb;
+        }
+        const uint64_t key = ((uint64_t)kind << 62) | ((uint64_t)(uint32_t)pa << 31) | (uint64_t)(uint32_t)pb;
+        ccfr_halfspace h;
+        h.phi = rec.phi;
+        h.flags = 0u;
+        h.key = key;
+        for (int k = 0; k < nA; ++k) {
+            const int v = va[k];
+            if (!(sc.inv_mass[v] > 0.f)) continue;
+            const long long pos = (long long)offsets[v] + atomicSub(&vcount[v], 1) - 1;
+            h.n[0] = rec.n[0]; h.n[1] = rec.n[1]; h.n[2] = rec.n[2];
+            h.d = rec.dA;
+            if (pos < cap_hs) hs[pos] = h;
+        }
+        for (int k = 0; k < nB; ++k) {
+            const int v = vb[k];
+            if (!(sc.inv_mass[v] > 0.f)) continue;
+            const long long pos = (long long)offsets[v] + atomicSub(&vcount[v], 1) - 1;
+            h.n[0] = -rec.n[0]; h.n[1] = -rec.n[1]; h.n[2] = -rec.n[2];
+            h.d = rec.dB;
+            if (pos < cap_hs) hs[pos] = h;
+        }
+    }
+}
+
+__global__ void k_finalize_regions(int32_t n_verts, const int32_t* offsets, int64_t cap_contacts,
+                                   int64_t cap_hs, DevCounters* c) {
+    if (threadIdx.x != 0) return;
+    const long long H = offsets[n_verts];
+    const long long nc = c->n_contacts;
+    uint32_t st = 0;
+    if (nc > cap_contacts) st |= ST_CONTACTS;
+    if (H > cap_hs) st |= ST_HS;
+    if (st) c->status |= st;
+    c->need[3] = max(c->need[3], nc);
+    c->need[4] = max(c->need[4], H);
+    c->totals[3] += H;
+    c->totals[8] += nc;
+    c->totals[9] += 1;
+    c->last_hs = (int32_t)H;
+}
+
+int grid_for(long long n) {
+    long long b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > 4096) b = 4096;
+    return (int)b;
+}
+
+}  // namespace
+
+void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
+                     const int32_t* counts, int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
+                     Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c,
+                     hipStream_t s) {
+    const int blocks = grid_for(cap_vf + cap_ee + cap_vv);
+    if (sc.narrow_fp32)
+        hipLaunchKernelGGL(k_contacts<float>, dim3(blocks), dim3(kBlock), 0, s, sc, vf, ee, vv, counts, cap_vf,
+                           cap_ee, cap_vv, contacts, cap_contacts, vcount, c);
+    else
+        hipLaunchKernelGGL(k_contacts<double>, dim3(blocks), dim3(kBlock), 0, s, sc, vf, ee, vv, counts, cap_vf,
+                           cap_ee, cap_vv, contacts, cap_contacts, vcount, c);
+}
+
+void launch_fill(const Scene& sc, const Contact* contacts, int64_t cap_contacts, const int32_t* offsets,
+                 int32_t* vcount, ccfr_halfspace* hs, int64_t cap_hs, DevCounters* c, hipStream_t s) {
+    const int blocks = grid_for(cap_contacts);
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kBlock), 0, s, sc, contacts, cap_contacts, offsets, vcount, hs,
+                       cap_hs, c);
+    hipLaunchKernelGGL(k_finalize_regions, dim3(1), dim3(64), 0, s, sc.n_verts, offsets, cap_contacts, cap_hs, c);
+}
+
+}  // namespace ccfr

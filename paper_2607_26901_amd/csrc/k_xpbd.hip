@@ -1,0 +1,116 @@
+// k_xpbd.hip -- the plain XPBD substep around the CCFR calls (Alg. 4, no
+// response or friction): prediction, one Gauss-Seidel pass of XPBD distance
+// constraints per solver iteration (Macklin et al. 2016), velocity update.
+//
+// The stretch pass runs colour by colour: the edges are stored sorted by a
+// greedy colouring (edge-index order) whose classes share no vertex, so one
+// launch per colour updates its edges in parallel with the same result as the
+// sequential pass in colour order.
+#include "ccfr_internal.h"
+
+namespace ccfr {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ __launch_bounds__(kBlock) void k_predict(int n, const float* x, const float* v, const float* w,
+                                                    float dt, float gx, float gy, float gz, float* xp,
+                                                    float* xs) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const float g[3] = {gx, gy, gz};
+    const bool dyn = w[i] > 0.0f;
+    for (int k = 0; k < 3; ++k) {
+        const float xi = x[3 * i + k];
+        xs[3 * i + k] = xi;
+        xp[3 * i + k] = dyn ? xi + dt * v[3 * i + k] + dt * dt * g[k] : xi;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_zero(float* p, long long n) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy(const float* src, float* dst, long long n) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_stretch(const int32_t* edges, const float* rest, int begin, int count,
+                                                    const float* w, float* p, float* lambda, float alpha_t) {
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= count) return;
+    const int e = begin + k;
+    const int i = edges[2 * e], j = edges[2 * e + 1];
+    const float wi = w[i], wj = w[j];
+    const float W = wi + wj;
+    if (W == 0.0f) return;
+    float d[3];
+    for (int c = 0; c < 3; ++c) d[c] = p[3 * i + c] - p[3 * j + c];
+    const float len = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (len == 0.0f) return;
+    const float C = len - rest[e];
+    const float lam = lambda[e];
+    const float dl = (-C - alpha_t * lam) / (W + alpha_t);
+    const float s = dl / len;
+    for (int c = 0; c < 3; ++c) {
+        p[3 * i + c] += wi * s * d[c];
+        p[3 * j + c] -= wj * s * d[c];
+    }
+    lambda[e] = lam + dl;
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_velocity(int n, const float* x, const float* xs, float inv_dt,
+                                                            float* v) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < 3; ++k) v[3 * i + k] = (x[3 * i + k] - xs[3 * i + k]) * inv_dt;
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_finite(const float* a, long long n, DevCounters* c) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const bool bad = i < n && !isfinite(a[i]);
+    if (__ballot(bad) && __lane_id() == 0) atomicOr(&c->status, ST_NONFINITE);
+}
+
+inline int blocks_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+void launch_predict(int n, const float* x, const float* v, const float* inv_mass, float dt, float gx, float gy,
+                    float gz, float* x_pred, float* x_start, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_predict, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, x, v, inv_mass, dt, gx, gy, gz,
+                       x_pred, x_start);
+}
+
+void launch_fill_zero(float* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, (long long)n);
+}
+
+void launch_copy(const float* src, float* dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_copy, dim3(blocks_for(n)), dim3(kBlock), 0, s, src, dst, (long long)n);
+}
+
+void launch_stretch_color(const int32_t* edges_sorted, const float* rest_sorted, int32_t begin, int32_t count,
+                          const float* inv_mass, float* p, float* lambda_sorted, float alpha_t, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_stretch, dim3(blocks_for(count)), dim3(kBlock), 0, s, edges_sorted, rest_sorted, begin,
+                       count, inv_mass, p, lambda_sorted, alpha_t);
+}
+
+void launch_update_velocity(int n, const float* x, const float* x_start, float inv_dt, float* v, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_update_velocity, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, x, x_start, inv_dt, v);
+}
+
+void launch_check_finite(const float* a, int64_t n, DevCounters* c, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_check_finite, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, (long long)n, c);
+}
+
+}  // namespace ccfr
