@@ -273,14 +273,20 @@ def xpbd_step(ctx: Context, mesh: Mesh, x, v, step_params: StepParams, stream=No
 
 
 def caller_candidates(vf, ee, vv, counts) -> Candidates:
-    """Candidates view over caller-owned device tensors ([P][2] int32 each, counts [3] int32)."""
-    return Candidates(vf.data_ptr(), ee.data_ptr(), vv.data_ptr(), counts.data_ptr(), vf.shape[0], ee.shape[0],
-                      vv.shape[0])
+    """Candidates view over caller-owned device tensors ([P][2] int32 each, counts [3] int32).
+    The view keeps the tensors alive."""
+    c = Candidates(vf.data_ptr(), ee.data_ptr(), vv.data_ptr(), counts.data_ptr(), vf.shape[0], ee.shape[0],
+                   vv.shape[0])
+    c._keep = (vf, ee, vv, counts)
+    return c
 
 
 def caller_regions(offsets, hs_bytes) -> Regions:
-    """Regions view over caller-owned device tensors: offsets [N+1] int32, hs_bytes [H*32] uint8."""
-    return Regions(offsets.shape[0] - 1, 0, offsets.data_ptr(), hs_bytes.data_ptr(), hs_bytes.numel() // 32)
+    """Regions view over caller-owned device tensors: offsets [N+1] int32, hs_bytes [H*32] uint8.
+    The view keeps the tensors alive."""
+    r = Regions(offsets.shape[0] - 1, 0, offsets.data_ptr(), hs_bytes.data_ptr(), hs_bytes.numel() // 32)
+    r._keep = (offsets, hs_bytes)
+    return r
 
 
 # ---- copying device lists back (for tests and counters) ----

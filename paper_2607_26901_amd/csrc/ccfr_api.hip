@@ -100,6 +100,7 @@ struct ccfr_ctx {
     long long cap_verts = 0;
     int32_t* vcount = nullptr;
     int32_t* offsets = nullptr;
+    int32_t* slow_list = nullptr;
     ccfr_halfspace* hs = nullptr;
     double* sort_key = nullptr;
     int32_t* sort_idx = nullptr;
@@ -212,8 +213,10 @@ int ensure_regions(ccfr_ctx* ctx, long long n_verts, long long contacts, long lo
     if (n_verts > ctx->cap_verts) {
         dev_free(ctx->vcount);
         dev_free(ctx->offsets);
+        dev_free(ctx->slow_list);
         HIP_ALLOC(dev_alloc(&ctx->vcount, n_verts));
         HIP_ALLOC(dev_alloc(&ctx->offsets, n_verts + 1));
+        HIP_ALLOC(dev_alloc(&ctx->slow_list, n_verts));
         HIP_OK(hipMemset(ctx->vcount, 0, sizeof(int32_t) * (size_t)n_verts));
         const long long ntmp = (n_verts + 1023) / 1024 + 2;
         if (ntmp > ctx->cap_scan_tmp) {
@@ -406,6 +409,7 @@ void enqueue_step(ccfr_ctx* ctx, const ccfr_mesh* m, float* x, float* v, const c
         pa.halted = nullptr;
         pa.sort_key = ctx->sort_key;
         pa.sort_idx = ctx->sort_idx;
+        pa.slow_list = ctx->slow_list;
         pa.prm = sc.prm;
         mk.mark(5, 0);
         launch_project(pa, ctx->counters_d, s);
@@ -465,7 +469,8 @@ void ccfr_destroy(ccfr_ctx* ctx) {
     dev_free(ctx->cnt); dev_free(ctx->start); dev_free(ctx->rank); dev_free(ctx->key);
     dev_free(ctx->entries); dev_free(ctx->level_mask); dev_free(ctx->scan_tmp);
     dev_free(ctx->vf); dev_free(ctx->ee); dev_free(ctx->vv);
-    dev_free(ctx->contacts); dev_free(ctx->vcount); dev_free(ctx->offsets); dev_free(ctx->hs);
+    dev_free(ctx->contacts); dev_free(ctx->vcount); dev_free(ctx->offsets); dev_free(ctx->slow_list);
+    dev_free(ctx->hs);
     dev_free(ctx->sort_key); dev_free(ctx->sort_idx);
     dev_free(ctx->x_pred); dev_free(ctx->x_start); dev_free(ctx->p);
     for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
@@ -686,11 +691,11 @@ int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const
     if (!ctx || !regions || !inv_mass_dev || !y_in_dev || !y_out_dev || !params_ok(params)) return CCFR_ERR_INVALID_ARG;
     if (regions->n_verts < 0 || !regions->offsets || (regions->cap > 0 && !regions->hs) || regions->cap < 0)
         return CCFR_ERR_INVALID_ARG;
-    // scratch for the sort must cover the regions' capacity
-    if (regions->cap > ctx->cap_hs) {
+    // scratch for the sort and the list of violating vertices must cover the call
+    if (regions->cap > ctx->cap_hs || regions->n_verts > ctx->cap_verts) {
         HIP_OK(hipStreamSynchronize((hipStream_t)stream));
         const long long gen = ctx->generation;
-        int rc = ensure_regions(ctx, 0, 0, regions->cap);
+        int rc = ensure_regions(ctx, regions->n_verts, 0, regions->cap);
         if (rc) return rc;
         if (gen != ctx->generation) drop_graph(ctx);
     }
@@ -707,6 +712,7 @@ int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const
     pa.halted = halted_dev;
     pa.sort_key = ctx->sort_key;
     pa.sort_idx = ctx->sort_idx;
+    pa.slow_list = ctx->slow_list;
     pa.prm.table = nullptr;
     pa.prm.vmesh = nullptr;
     pa.prm.one = mesh_params(params, 0.f, 0);

@@ -43,9 +43,10 @@ struct DevCounters {
     int32_t n_vf, n_ee, n_vv;          // pair counts of the current build
     int32_t n_large_t, n_large_e;      // large primitives of the current build
     int32_t n_contacts;                // pairs inside the range
-    int32_t n_viol;                    // violating vertices (list for the slow path)
+    int32_t n_viol;                    // deferred vertices with small regions (slow list front)
     int32_t last_hs;
-    int32_t pad0[3];
+    int32_t n_viol_b;                  // deferred vertices with larger regions (slow list back)
+    int32_t pad0[2];
     long long need[6];                 // max sizes seen: vf, ee, vv, contacts, hs, large
     long long totals[10];              // vf, ee, vv, hs, violating, halted, degenerate, projected,
                                        // contacts, region builds
@@ -156,8 +157,9 @@ struct ProjectArgs {
     float* x_anchor;         // anchor, updated in place when y_out == nullptr
     float* y_out;
     uint8_t* halted;
-    double* sort_key;        // [cap_hs] scratch
-    int32_t* sort_idx;       // [cap_hs] scratch
+    double* sort_key;        // [cap_hs] scratch of regions larger than a wavefront sorts
+    int32_t* sort_idx;       // [cap_hs]
+    int32_t* slow_list;      // [n_verts] vertices with a violated half-space
     ParamSrc prm;
 };
 void launch_project(const ProjectArgs& a, DevCounters* c, hipStream_t s);

@@ -27,8 +27,8 @@
 //   scan         exclusive prefix of the per-(kind, bucket) counts
 //   grid_scatter targets to their sorted slots (32 B entries)
 //   pairs        one thread per query (vertex, then edge); found pairs are
-//                compacted per wavefront (ballot + popcount, one atomic per
-//                wave and round)
+//                staged per wavefront in LDS and written out in blocks of up to
+//                128 with one atomic each
 #include "ccfr_internal.h"
 
 #include <algorithm>
@@ -54,26 +54,6 @@ __device__ __forceinline__ bool overlap(const float alo[3], const float ahi[3], 
                                         const float bhi[3]) {
     return alo[0] <= bhi[0] && blo[0] <= ahi[0] && alo[1] <= bhi[1] && blo[1] <= ahi[1] &&
            alo[2] <= bhi[2] && blo[2] <= ahi[2];
-}
-
-// Wavefront-aggregated append of (a, b) for the lanes with pred set.  Every
-// active lane of the wave must call it.
-__device__ __forceinline__ void emit_pair(int32_t* list, int32_t* counter, int64_t cap, int a, int b,
-                                          bool pred) {
-    const unsigned long long mask = __ballot(pred);
-    if (mask == 0ull) return;
-    const int lane = __lane_id();
-    const int leader = __ffsll((long long)mask) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
-    base = __shfl(base, leader);
-    if (pred) {
-        const long long idx = (long long)base + __popcll(mask & ((1ull << lane) - 1ull));
-        if (idx < cap) {
-            list[2 * idx + 0] = a;
-            list[2 * idx + 1] = b;
-        }
-    }
 }
 
 // The target primitive behind grid slot t: triangles, then edges, then free particles.
@@ -154,6 +134,25 @@ __device__ __forceinline__ bool entry_ok(const GridEntry& e, int mesh, int level
            !(q_static && (e.flags & 1u));
 }
 
+// Sets bit `level` of the mesh's level mask.  The lanes of a wavefront that share
+// a mesh OR their bits together first, and a bit already visible costs no atomic.
+__device__ __forceinline__ void mark_level(uint32_t* level_mask, int mesh, uint32_t bits) {
+    const unsigned long long active = __ballot(true);
+    const int lead = __ffsll((long long)active) - 1;
+    const int m0 = __shfl(mesh, lead);
+    const bool uniform = __ballot(mesh != m0) == 0ull;
+    if (uniform) {
+        const int lane = __lane_id();
+        for (int off = 1; off < warpSize; off <<= 1) {
+            const uint32_t o = __shfl_xor(bits, off);
+            if ((active >> (lane ^ off)) & 1ull) bits |= o;     // only lanes still running
+        }
+        if (lane == lead && bits && (level_mask[mesh] & bits) != bits) atomicOr(&level_mask[mesh], bits);
+    } else if (bits && (level_mask[mesh] & bits) != bits) {
+        atomicOr(&level_mask[mesh], bits);
+    }
+}
+
 __global__ void k_reset_build(DevCounters* c, uint32_t* level_mask, int n_meshes) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         c->n_vf = c->n_ee = c->n_vv = 0;
@@ -174,19 +173,20 @@ __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCo
     const MeshParams P = sc.prm.get(mesh);
     float lo[3], hi[3];
     bool st;
+    int clo[3];
+    int level = -2;
     if (!target_box(sc, tg, P.pad, lo, hi, &st)) {
         atomicOr(&c->status, ST_NONFINITE);
+    } else {
+        level = box_level(lo, hi, P.inv_h, clo);
+        if (level < 0) atomicOr(&c->status, ST_LARGE);   // a box wider than h 2^24: not binned
+    }
+    // every lane still in the kernel takes part in the wave-wide OR
+    mark_level(g.level_mask, mesh, level < 0 ? 0u : (1u << level));
+    if (level < 0) {
         g.key[t] = -1;
         return;
     }
-    int clo[3];
-    const int level = box_level(lo, hi, P.inv_h, clo);
-    if (level < 0) {                      // a box wider than h 2^24: not binned
-        atomicOr(&c->status, ST_LARGE);
-        g.key[t] = -1;
-        return;
-    }
-    atomicOr(&g.level_mask[mesh], 1u << level);
     const uint32_t b = cell_bucket(clo[0], clo[1], clo[2], level_salt(P.mesh_salt, level), g.log2s);
     const int key = (tg.kind - 1) * (1 << g.log2s) + (int)b;
     g.key[t] = key;
@@ -214,10 +214,75 @@ __global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g) {
     g.entries[g.start[key] + g.rank[t]] = e;
 }
 
+// Per-wavefront staging of found pairs in LDS: lanes append to their wave's
+// buffer for the list (ballot + popcount), and a full buffer is written out with
+// one global atomic and coalesced stores.  Each wave only touches its own slice,
+// so no block barrier is involved.
+constexpr int kWaves = kBlock / 64;
+constexpr int kStage = 128;
+
+struct Stage {
+    int a[3][kStage];
+    int b[3][kStage];
+    int fill[3];
+};
+
+__device__ __forceinline__ void stage_flush(Stage& st, int k, int32_t* list, int32_t* counter, int64_t cap) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int f = *(volatile int*)&st.fill[k];
+    if (f == 0) return;
+    const unsigned long long act = __ballot(true);
+    const int lane = __lane_id();
+    const int lead = __ffsll((long long)act) - 1;
+    const int nact = __popcll(act);
+    const int rank = __popcll(act & ((1ull << lane) - 1ull));
+    int base = 0;
+    if (lane == lead) base = atomicAdd(counter, f);
+    base = __shfl(base, lead);
+    for (int i = rank; i < f; i += nact) {
+        const long long idx = (long long)base + i;
+        if (idx < cap) {
+            list[2 * idx + 0] = ((volatile int*)st.a[k])[i];
+            list[2 * idx + 1] = ((volatile int*)st.b[k])[i];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (lane == lead) *(volatile int*)&st.fill[k] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Every active lane of the wave must call it.
+__device__ __forceinline__ void stage_pair(Stage& st, int k, int32_t* list, int32_t* counter, int64_t cap, int a,
+                                           int b, bool pred) {
+    const unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return;
+    const int n = __popcll(mask);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    int f = *(volatile int*)&st.fill[k];
+    if (f + n > kStage) {
+        stage_flush(st, k, list, counter, cap);
+        f = 0;
+    }
+    const int lane = __lane_id();
+    if (pred) {
+        const int slot = f + __popcll(mask & ((1ull << lane) - 1ull));
+        ((volatile int*)st.a[k])[slot] = a;
+        ((volatile int*)st.b[k])[slot] = b;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (lane == __ffsll((long long)__ballot(true)) - 1) *(volatile int*)&st.fill[k] = f + n;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists pl, DevCounters* c) {
+    __shared__ Stage stages[kWaves];
+    Stage& st = stages[threadIdx.x / 64];
+    if (__lane_id() == 0) {
+        st.fill[0] = st.fill[1] = st.fill[2] = 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const int q = blockIdx.x * kBlock + threadIdx.x;
     const int n_q = sc.n_verts + sc.n_edges;
-    if (q >= n_q) return;
     const int S = 1 << g.log2s;
     if (q < sc.n_verts) {
         // ---- vertex query: vertex-face pairs, and particle pairs for free particles
@@ -226,7 +291,6 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
         const MeshParams P = sc.prm.get(mesh);
         float p[3];
         load3(sc.x, v, p);
-        if (!finite3(p)) return;
         float lo[3], hi[3];
         for (int k = 0; k < 3; ++k) {
             lo[k] = __fsub_rn(p[k], P.pad);
@@ -234,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
         }
         const bool q_static = sc.inv_mass[v] == 0.0f;
         const bool q_free = sc.is_free[v] != 0;
-        uint32_t levels = g.level_mask[mesh];
+        uint32_t levels = finite3(p) ? g.level_mask[mesh] : 0u;
         while (levels) {
             const int l = __ffs((int)levels) - 1;
             levels &= levels - 1u;
@@ -257,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
                                 const int* tv = sc.tris + 3 * e.idx;
                                 hit = tv[0] != v && tv[1] != v && tv[2] != v;
                             }
-                            emit_pair(pl.vf, &c->n_vf, pl.cap_vf, v, e.idx, hit);
+                            stage_pair(st, 0, pl.vf, &c->n_vf, pl.cap_vf, v, e.idx, hit);
                         }
                         if (q_free && l == 0) {
                             const int k0 = 2 * S + (int)b;
@@ -266,12 +330,12 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
                                 const GridEntry e = g.entries[i];
                                 const bool hit = e.idx > v && entry_ok(e, mesh, 0, q_static) &&
                                                  overlap(lo, hi, e.lo, e.hi);
-                                emit_pair(pl.vv, &c->n_vv, pl.cap_vv, v, e.idx, hit);
+                                stage_pair(st, 2, pl.vv, &c->n_vv, pl.cap_vv, v, e.idx, hit);
                             }
                         }
                     }
         }
-    } else {
+    } else if (q < n_q) {
         // ---- edge query: edge-edge pairs
         const int eq = q - sc.n_verts;
         const int a = sc.edges[2 * eq], bb = sc.edges[2 * eq + 1];
@@ -280,17 +344,15 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
         float pa[3], pb[3];
         load3(sc.x, a, pa);
         load3(sc.x, bb, pb);
-        if (!finite3(pa) || !finite3(pb)) return;
         float lo[3], hi[3];
         for (int k = 0; k < 3; ++k) {
             lo[k] = __fsub_rn(fminf(pa[k], pb[k]), P.pad);
             hi[k] = __fadd_rn(fmaxf(pa[k], pb[k]), P.pad);
         }
         int clo[3], chi[3];
-        const int lq = box_level(lo, hi, P.inv_h, clo);
-        if (lq < 0) return;
+        const int lq = (finite3(pa) && finite3(pb)) ? box_level(lo, hi, P.inv_h, clo) : -1;
         const bool q_static = sc.inv_mass[a] == 0.0f && sc.inv_mass[bb] == 0.0f;
-        uint32_t levels = g.level_mask[mesh] & ~((1u << lq) - 1u);
+        uint32_t levels = lq < 0 ? 0u : (g.level_mask[mesh] & ~((1u << lq) - 1u));
         while (levels) {
             const int l = __ffs((int)levels) - 1;
             levels &= levels - 1u;
@@ -313,11 +375,15 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
                                 const int c0 = sc.edges[2 * e.idx], c1 = sc.edges[2 * e.idx + 1];
                                 hit = c0 != a && c0 != bb && c1 != a && c1 != bb;
                             }
-                            emit_pair(pl.ee, &c->n_ee, pl.cap_ee, min(eq, e.idx), max(eq, e.idx), hit);
+                            stage_pair(st, 1, pl.ee, &c->n_ee, pl.cap_ee, min(eq, e.idx), max(eq, e.idx), hit);
                         }
                     }
         }
     }
+    // all lanes of the wave are back together: write out what is left
+    stage_flush(st, 0, pl.vf, &c->n_vf, pl.cap_vf);
+    stage_flush(st, 1, pl.ee, &c->n_ee, pl.cap_ee);
+    stage_flush(st, 2, pl.vv, &c->n_vv, pl.cap_vv);
 }
 
 // Overflow bits, largest sizes seen and running totals of one build.

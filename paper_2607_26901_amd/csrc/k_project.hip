@@ -9,14 +9,17 @@
 // is what makes the sign tests of Alg. 2 fragile in single precision (the
 // paper's Sec. 5 names single-precision robustness as open).
 //
-// Fast path: a vertex none of whose half-spaces is violated by its proposal
-// returns it unchanged (Alg. 2 with no violation in its first pass), clamped.
-// Slow path (violating vertices): the half-spaces are sorted by their initial
-// rho ascending, ties by key, into a scratch range parallel to the vertex's CSR
-// range; exact duplicates (bitwise-equal n and d) are dropped; then up to
-// max_passes passes of Alg. 1 over the violated ones, each followed by the
-// retraction by eps; a pass without violation returns its start point, and
-// otherwise the vertex halts at y = 0.
+// Fast kernel (every vertex): a vertex none of whose half-spaces is violated by
+// its proposal returns it unchanged (Alg. 2 with no violation in its first
+// pass); a vertex with exactly one violated half-space whose projection leaves
+// every other one satisfied returns that projection (the first two passes of
+// Alg. 2, which need no sort in that case).  All other vertices are compacted
+// into a list for the slow kernel: their half-spaces are sorted by initial rho
+// ascending, ties by key (in registers up to 8, by a wavefront in LDS up to 256,
+// in a scratch range parallel to the CSR range beyond), exact duplicates
+// (bitwise-equal n and d) are dropped, then up to max_passes passes of Alg. 1
+// over the violated ones, each followed by the retraction by eps; a pass without
+// violation returns its start point, and otherwise the vertex halts at y = 0.
 //
 // Readings: A12 (Alg. 1's entry j = m is the new plane, and the stored plane is
 // that plane), A14 (Alg. 1 returns its input once three planes are stored), A15
@@ -24,11 +27,15 @@
 // half-spaces; zero inverse mass gives y = 0).
 #include "ccfr_internal.h"
 
+#include <algorithm>
+
 namespace ccfr {
 
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kSmall = 8;      // regions up to this size stay in registers
+constexpr int kWave = 256;     // up to this size a wavefront sorts them in LDS
 
 struct d3 {
     double x, y, z;
@@ -162,59 +169,366 @@ __device__ bool project_slow(const ccfr_halfspace* H, int K, const d3 yprop, con
     return true;
 }
 
-__global__ __launch_bounds__(kBlock) void k_project(ProjectArgs a, DevCounters* c) {
+// ---- shared per-vertex plumbing ----
+
+__device__ __forceinline__ d3 load_prop(const ProjectArgs& a, int v) {
+    float yf[3];
+    if (a.y_in) {
+        yf[0] = a.y_in[3 * v]; yf[1] = a.y_in[3 * v + 1]; yf[2] = a.y_in[3 * v + 2];
+    } else {
+        for (int k = 0; k < 3; ++k) yf[k] = a.p[3 * v + k] - a.x_anchor[3 * v + k];
+    }
+    return mk(yf[0], yf[1], yf[2]);
+}
+
+__device__ __forceinline__ void write_result(const ProjectArgs& a, int v, d3 y, double r, bool halted) {
+    const double ny = norm(y);
+    if (ny > r) y = (r / ny) * y;                      // r-ball clamp
+    if (a.y_out) {
+        a.y_out[3 * v] = (float)y.x;
+        a.y_out[3 * v + 1] = (float)y.y;
+        a.y_out[3 * v + 2] = (float)y.z;
+    } else {
+        a.x_anchor[3 * v] += (float)y.x;
+        a.x_anchor[3 * v + 1] += (float)y.y;
+        a.x_anchor[3 * v + 2] += (float)y.z;
+    }
+    if (a.halted) a.halted[v] = halted ? 1 : 0;
+}
+
+// The vertex's CSR range, clipped to the half-space buffer (an offset outside
+// it yields an empty region, never an access outside the buffer).
+__device__ __forceinline__ int region_size(const ProjectArgs& a, int v, long long* o0) {
+    const long long lo = a.offsets[v];
+    const long long o1 = min((long long)a.offsets[v + 1], (long long)a.cap_hs);
+    *o0 = (lo < 0 || lo > a.cap_hs) ? 0 : lo;
+    return (lo >= 0 && o1 > lo) ? (int)(o1 - lo) : 0;
+}
+
+// Alg. 2's passes over a sorted, de-duplicated sequence: entry q of K gives a
+// plane (n, d) or is skipped.  Returns true if the vertex halted.
+template <class Get>
+__device__ __forceinline__ bool run_passes(int K, const Get& get, const d3 yprop, const MeshParams& P, d3& yres) {
+    const double eps_r = (double)P.eps_retract;
+    const double eps_p = (double)P.eps_plesnik;
+    d3 yp = yprop;
+    for (int pass = 0; pass < P.max_passes; ++pass) {
+        d3 yt = yp;
+        const d3 y0 = yp;
+        Ero S;
+        S.m = 0;
+        int nviol = 0;
+        for (int q = 0; q < K; ++q) {
+            d3 n;
+            double d;
+            if (!get(q, n, d)) continue;
+            if (dot(n, yt) + d >= 0.0) continue;
+            ++nviol;
+            orthogonal_projection(yt, y0, n, -d, S, eps_p);
+            const double nd = norm(yt);
+            yt = (nd > eps_r) ? ((nd - eps_r) / nd) * yt : mk(0.0, 0.0, 0.0);
+        }
+        if (nviol == 0) {
+            yres = yp;
+            return false;
+        }
+        yp = yt;
+    }
+    yres = mk(0.0, 0.0, 0.0);
+    return true;
+}
+
+// ---- fast path: every vertex; the ones with a violated half-space go to a list ----
+
+// One violated half-space: it is first in Alg. 2's sorted order, so the first
+// pass projects onto it (Alg. 1 with no stored plane), retracts, and re-checks
+// every other half-space at the new point; if none is violated there, the
+// second pass finds nothing and returns that point.  Evaluated here with the
+// same arithmetic as the passes, this gives Alg. 2's result without the sort;
+// returns false when the shortcut does not apply.
+__device__ __forceinline__ bool project_one_plane(const ccfr_halfspace* H, int K, int kv, const d3 yprop,
+                                                  const MeshParams& P, d3& yres) {
+    if (P.max_passes < 2) return false;
+    const ccfr_halfspace hv = H[kv];
+    const d3 n = load_n(hv);
+    const double beta0 = dot(n, n);
+    if (fabs(beta0) < (double)P.eps_plesnik) return false;
+    d3 yt = yprop + ((-(double)hv.d - dot(n, yprop)) / beta0) * n;
+    const double nd = norm(yt);
+    const double eps_r = (double)P.eps_retract;
+    yt = (nd > eps_r) ? ((nd - eps_r) / nd) * yt : mk(0.0, 0.0, 0.0);
+    for (int k = 0; k < K; ++k) {
+        const ccfr_halfspace h = H[k];
+        if (dot(load_n(h), yt) + (double)h.d < 0.0) return false;
+    }
+    yres = yt;
+    return true;
+}
+
+__global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCounters* c) {
     const int v = blockIdx.x * kBlock + threadIdx.x;
     const bool active = v < a.n_verts;
-    bool violated = false, halted = false, moved = false;
+    bool violated = false, deferred = false, big = false, moved = false;
     if (active) {
-        const float w = a.inv_mass[v];
-        float yf[3];
-        if (a.y_in) {
-            yf[0] = a.y_in[3 * v]; yf[1] = a.y_in[3 * v + 1]; yf[2] = a.y_in[3 * v + 2];
-        } else {
-            for (int k = 0; k < 3; ++k) yf[k] = a.p[3 * v + k] - a.x_anchor[3 * v + k];
-        }
-        d3 y = mk(0.0, 0.0, 0.0);
-        if (w > 0.0f) {
+        if (a.inv_mass[v] > 0.0f) {
             moved = true;
             const MeshParams P = a.prm.get(a.prm.mesh_of(v));
-            const d3 yprop = mk(yf[0], yf[1], yf[2]);
-            const long long o0 = a.offsets[v];
-            const long long o1 = min((long long)a.offsets[v + 1], (long long)a.cap_hs);
-            const int K = o1 > o0 ? (int)(o1 - o0) : 0;
+            const d3 yprop = load_prop(a, v);
+            long long o0;
+            const int K = region_size(a, v, &o0);
             const ccfr_halfspace* H = a.hs + o0;
-            for (int k = 0; k < K && !violated; ++k) {
+            int n_viol = 0, kv = -1;
+            for (int k = 0; k < K; ++k) {                     // independent loads, no early exit
                 const ccfr_halfspace h = H[k];
-                violated = dot(load_n(h), yprop) + (double)h.d < 0.0;
+                if (dot(load_n(h), yprop) + (double)h.d < 0.0) {
+                    ++n_viol;
+                    kv = k;
+                }
             }
-            if (!violated) {
-                y = yprop;
-            } else {
-                halted = project_slow(H, K, yprop, P, a.sort_key + o0, a.sort_idx + o0, y);
-            }
-            const double ny = norm(y);
-            const double r = (double)P.r;
-            if (ny > r) y = (r / ny) * y;
-        }
-        if (a.y_out) {
-            a.y_out[3 * v] = (float)y.x;
-            a.y_out[3 * v + 1] = (float)y.y;
-            a.y_out[3 * v + 2] = (float)y.z;
+            violated = n_viol > 0;
+            big = K > kSmall;
+            d3 y = yprop;
+            if (n_viol == 1) deferred = !project_one_plane(H, K, kv, yprop, P, y);
+            else deferred = n_viol > 1;
+            if (!deferred) write_result(a, v, y, (double)P.r, false);
         } else {
-            a.x_anchor[3 * v] += (float)y.x;
-            a.x_anchor[3 * v + 1] += (float)y.y;
-            a.x_anchor[3 * v + 2] += (float)y.z;
+            write_result(a, v, mk(0.0, 0.0, 0.0), 0.0, false);
         }
-        if (a.halted) a.halted[v] = halted ? 1 : 0;
     }
-    // one atomic per wave for the counters
+    // vertices that need the full Alg. 2 go to the slow list, one atomic per wave
+    // and list: small regions from the front, larger ones from the back
+    const unsigned long long md = __ballot(deferred && !big);
+    const unsigned long long mb = __ballot(deferred && big);
     const unsigned long long mv = __ballot(violated);
-    const unsigned long long mh = __ballot(halted);
     const unsigned long long mm = __ballot(moved);
-    if (__lane_id() == 0) {
+    const int lane = __lane_id();
+    int base = 0, base_b = 0;
+    if (lane == 0 && md) base = atomicAdd(&c->n_viol, __popcll(md));
+    if (lane == 0 && mb) base_b = atomicAdd(&c->n_viol_b, __popcll(mb));
+    base = __shfl(base, 0);
+    base_b = __shfl(base_b, 0);
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    if (deferred && !big) a.slow_list[base + __popcll(md & lt)] = v;
+    if (deferred && big) a.slow_list[a.n_verts - 1 - (base_b + __popcll(mb & lt))] = v;
+    if (lane == 0) {
         if (mv) atomicAdd((unsigned long long*)&c->totals[4], (unsigned long long)__popcll(mv));
-        if (mh) atomicAdd((unsigned long long*)&c->totals[5], (unsigned long long)__popcll(mh));
         if (mm) atomicAdd((unsigned long long*)&c->totals[7], (unsigned long long)__popcll(mm));
+    }
+}
+
+// ---- slow path: one lane per listed vertex; bigger regions cooperatively ----
+
+
+__device__ __forceinline__ bool before(double ra, uint64_t ka, double rb, uint64_t kb) {
+    return ra < rb || (ra == rb && ka < kb);
+}
+
+// compare-exchange of slots i < j of the register sort
+#define CE(i, j)                                                                   \
+    if (before(rho[j], key[j], rho[i], key[i])) {                                  \
+        double tr = rho[i]; rho[i] = rho[j]; rho[j] = tr;                           \
+        uint64_t tk = key[i]; key[i] = key[j]; key[j] = tk;                         \
+        float4 tn = R[i]; R[i] = R[j]; R[j] = tn;                                   \
+    }
+
+__device__ bool project_small(const ccfr_halfspace* H, int K, const d3 yprop, const MeshParams& P, d3& yres) {
+    float4 R[kSmall];
+    uint64_t key[kSmall];
+    double rho[kSmall];
+#pragma unroll
+    for (int j = 0; j < kSmall; ++j) {
+        if (j < K) {
+            const ccfr_halfspace h = H[j];
+            R[j] = make_float4(h.n[0], h.n[1], h.n[2], h.d);
+            key[j] = h.key;
+            rho[j] = dot(load_n(h), yprop) + (double)h.d;
+        } else {
+            R[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+            key[j] = ~0ull;
+            rho[j] = __longlong_as_double(0x7ff0000000000000ll);   // +inf: sorts last
+        }
+    }
+    // Batcher's odd-even merge sort of 8 by (rho, key)
+    CE(0, 1) CE(2, 3) CE(4, 5) CE(6, 7)
+    CE(0, 2) CE(1, 3) CE(4, 6) CE(5, 7)
+    CE(1, 2) CE(5, 6)
+    CE(0, 4) CE(1, 5) CE(2, 6) CE(3, 7)
+    CE(2, 4) CE(3, 5)
+    CE(1, 2) CE(3, 4) CE(5, 6)
+    // exact duplicates (same rho, bitwise-equal n and d) after the first are dropped
+    bool drop[kSmall];
+#pragma unroll
+    for (int j = 0; j < kSmall; ++j) {
+        drop[j] = false;
+#pragma unroll
+        for (int i = 0; i < j; ++i)
+            drop[j] = drop[j] || (rho[i] == rho[j] && R[i].x == R[j].x && R[i].y == R[j].y && R[i].z == R[j].z &&
+                                  R[i].w == R[j].w);
+    }
+    auto get = [&](int q, d3& n, double& d) -> bool {
+        bool ok = false;
+#pragma unroll
+        for (int j = 0; j < kSmall; ++j)
+            if (j == q) {
+                ok = !drop[j];
+                n = mk(R[j].x, R[j].y, R[j].z);
+                d = (double)R[j].w;
+            }
+        return ok;
+    };
+    return run_passes(K, get, yprop, P, yres);
+}
+#undef CE
+
+struct WaveLds {
+    float4 rec[kWave];
+    uint64_t key[kWave];
+    double rho[kWave];
+    int16_t idx[kWave];
+    uint8_t drop[kWave];
+};
+
+// List A (front of the slow list): regions of at most kSmall half-spaces, one
+// lane per vertex, the sort and the passes in registers.
+__global__ __launch_bounds__(kBlock) void k_project_lanes(ProjectArgs a, DevCounters* c) {
+    const int n_list = c->n_viol;
+    for (int i0 = blockIdx.x * kBlock; i0 < n_list; i0 += gridDim.x * kBlock) {
+        const int i = i0 + threadIdx.x;
+        bool halted = false;
+        if (i < n_list) {
+            const int v = a.slow_list[i];
+            long long o0;
+            const int K = region_size(a, v, &o0);
+            const MeshParams P = a.prm.get(a.prm.mesh_of(v));
+            d3 y;
+            halted = project_small(a.hs + o0, K, load_prop(a, v), P, y);
+            write_result(a, v, y, (double)P.r, halted);
+        }
+        const unsigned long long mh = __ballot(halted);
+        if (__lane_id() == 0 && mh) atomicAdd((unsigned long long*)&c->totals[5], (unsigned long long)__popcll(mh));
+    }
+}
+
+// List B (back of the slow list): larger regions, one wavefront per vertex.  The
+// half-spaces are sorted in LDS by a bitonic network; each pass of Alg. 2 then
+// advances by parallel scans: every lane evaluates rho at the current point for
+// its share of the remaining sorted entries, a ballot gives the first violated
+// one, and all lanes apply the same Alg. 1 update and retraction to their
+// (identical) copies of the state.  This visits exactly the half-spaces the
+// sequential pass would, in the same order, with the same arithmetic.
+__global__ __launch_bounds__(64) void k_project_wave(ProjectArgs a, DevCounters* c) {
+    __shared__ WaveLds L;
+    const int n_list = c->n_viol_b;
+    const int lane = threadIdx.x;
+    for (int i = blockIdx.x; i < n_list; i += gridDim.x) {
+        const int v = a.slow_list[a.n_verts - 1 - i];
+        long long o0;
+        const int K = region_size(a, v, &o0);
+        const MeshParams P = a.prm.get(a.prm.mesh_of(v));
+        const d3 yprop = load_prop(a, v);
+        d3 y = mk(0.0, 0.0, 0.0);
+        bool halted = false;
+        if (K > kWave) {
+            // beyond LDS: one lane sorts in the scratch range parallel to the CSR range
+            if (lane == 0) halted = project_slow(a.hs + o0, K, yprop, P, a.sort_key + o0, a.sort_idx + o0, y);
+            halted = __shfl(halted ? 1 : 0, 0) != 0;
+        } else {
+            int Kp = 1;
+            while (Kp < K) Kp <<= 1;
+            const ccfr_halfspace* H = a.hs + o0;
+            for (int j = lane; j < Kp; j += 64) {
+                if (j < K) {
+                    const ccfr_halfspace h = H[j];
+                    L.rec[j] = make_float4(h.n[0], h.n[1], h.n[2], h.d);
+                    L.key[j] = h.key;
+                    L.rho[j] = dot(load_n(h), yprop) + (double)h.d;
+                } else {
+                    L.key[j] = ~0ull;
+                    L.rho[j] = __longlong_as_double(0x7ff0000000000000ll);
+                }
+                L.idx[j] = (int16_t)j;
+            }
+            __syncthreads();
+            for (int size = 2; size <= Kp; size <<= 1) {
+                for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                    for (int t = lane; t < (Kp >> 1); t += 64) {
+                        const int p = 2 * t - (t & (stride - 1));
+                        const int q = p + stride;
+                        const bool up = (p & size) == 0;
+                        const bool swap = up ? before(L.rho[q], L.key[q], L.rho[p], L.key[p])
+                                             : before(L.rho[p], L.key[p], L.rho[q], L.key[q]);
+                        if (swap) {
+                            const double tr = L.rho[p]; L.rho[p] = L.rho[q]; L.rho[q] = tr;
+                            const uint64_t tk = L.key[p]; L.key[p] = L.key[q]; L.key[q] = tk;
+                            const int16_t ti = L.idx[p]; L.idx[p] = L.idx[q]; L.idx[q] = ti;
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int q = lane; q < K; q += 64) {
+                bool dup = false;
+                const float4 rq = L.rec[L.idx[q]];
+                for (int r = q - 1; r >= 0 && L.rho[r] == L.rho[q] && !dup; --r) {
+                    const float4 rr = L.rec[L.idx[r]];
+                    dup = rr.x == rq.x && rr.y == rq.y && rr.z == rq.z && rr.w == rq.w;
+                }
+                L.drop[q] = dup ? 1 : 0;
+            }
+            __syncthreads();
+            const double eps_r = (double)P.eps_retract;
+            const double eps_p = (double)P.eps_plesnik;
+            d3 yp = yprop;
+            halted = true;
+            for (int pass = 0; pass < P.max_passes; ++pass) {
+                d3 yt = yp;
+                const d3 y0 = yp;
+                Ero S;
+                S.m = 0;
+                int nviol = 0;
+                int from = 0;
+                while (true) {
+                    // first violated sorted entry at or after `from`, at the current point
+                    int hit = -1;
+                    for (int base = from & ~63; base < K && hit < 0; base += 64) {
+                        const int q = base + lane;
+                        bool viol = false;
+                        if (q >= from && q < K && L.drop[q] == 0) {
+                            const float4 rr = L.rec[L.idx[q]];
+                            viol = dot(mk(rr.x, rr.y, rr.z), yt) + (double)rr.w < 0.0;
+                        }
+                        const unsigned long long m = __ballot(viol);
+                        if (m) hit = base + __ffsll((long long)m) - 1;
+                    }
+                    if (hit < 0) break;
+                    const float4 rr = L.rec[L.idx[hit]];
+                    ++nviol;
+                    orthogonal_projection(yt, y0, mk(rr.x, rr.y, rr.z), -(double)rr.w, S, eps_p);
+                    const double nd = norm(yt);
+                    yt = (nd > eps_r) ? ((nd - eps_r) / nd) * yt : mk(0.0, 0.0, 0.0);
+                    from = hit + 1;
+                }
+                if (nviol == 0) {
+                    y = yp;
+                    halted = false;
+                    break;
+                }
+                yp = yt;
+            }
+            if (halted) y = mk(0.0, 0.0, 0.0);
+            __syncthreads();
+        }
+        if (lane == 0) {
+            write_result(a, v, y, (double)P.r, halted);
+            if (halted) atomicAdd((unsigned long long*)&c->totals[5], 1ull);
+        }
+    }
+}
+
+__global__ void k_zero_viol(DevCounters* c) {
+    if (threadIdx.x == 0) {
+        c->n_viol = 0;
+        c->n_viol_b = 0;
     }
 }
 
@@ -222,7 +536,12 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjectArgs a, DevCounters* 
 
 void launch_project(const ProjectArgs& a, DevCounters* c, hipStream_t s) {
     if (a.n_verts <= 0) return;
-    hipLaunchKernelGGL(k_project, dim3((a.n_verts + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a, c);
+    hipLaunchKernelGGL(k_zero_viol, dim3(1), dim3(64), 0, s, c);
+    hipLaunchKernelGGL(k_project_fast, dim3((a.n_verts + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a, c);
+    const int lane_blocks = std::max(1, std::min(1024, (a.n_verts + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_project_lanes, dim3(lane_blocks), dim3(kBlock), 0, s, a, c);
+    const int wave_blocks = std::max(1, std::min(4096, a.n_verts));
+    hipLaunchKernelGGL(k_project_wave, dim3(wave_blocks), dim3(64), 0, s, a, c);
 }
 
 }  // namespace ccfr

@@ -240,3 +240,58 @@ def test_determinism_and_graph_replay(env, scenes):
     for a, b, c in zip(eager, g1, g2):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
         assert np.array_equal(b[0], c[0]) and np.array_equal(b[1], c[1])
+
+
+def test_projection_tiers(env):
+    """Regions of every size the projection handles differently (in registers,
+    sorted by a wavefront in LDS, sorted in global scratch), including exact
+    duplicates and ties, against the oracle on identical FP32 inputs."""
+    ctx, ccfr, oracle, torch = env
+    rng = np.random.default_rng(42)
+    sizes = [0, 1, 2, 5, 8, 9, 17, 64, 200, 256, 257, 300]
+    verts_per_size = 6
+    Ks = np.repeat(sizes, verts_per_size)
+    N = len(Ks)
+    r = 4e-3
+    n_list, d_list = [], []
+    for K in Ks:
+        n = rng.normal(size=(K, 3))
+        n /= np.maximum(np.linalg.norm(n, axis=1, keepdims=True), 1e-12)
+        d = rng.uniform(0, 2e-3, K)
+        if K >= 4:                      # an exact duplicate and an exact rho tie
+            n[1], d[1] = n[0], d[0]
+        n_list.append(n)
+        d_list.append(d)
+    off = np.zeros(N + 1, np.int64)
+    off[1:] = np.cumsum(Ks)
+    nh = int(off[-1])
+    hs32 = np.zeros(nh, ccfr.HALFSPACE_DTYPE)
+    hs32["n"] = np.concatenate(n_list).astype(np.float32)
+    hs32["d"] = np.concatenate(d_list).astype(np.float32)
+    hs32["key"] = (np.uint64(1) << np.uint64(62)) + np.arange(nh, dtype=np.uint64)
+    y = (rng.normal(size=(N, 3)) * 3e-3).astype(np.float32)
+    w = np.ones(N, np.float32)
+    w[3] = 0.0
+    prm = S.Params(r=r, xi=1e-3)
+    regions = ccfr.caller_regions(torch.from_numpy(off.astype(np.int32)).cuda(),
+                                  torch.from_numpy(hs32.view(np.uint8)).cuda())
+    y_t = torch.from_numpy(y).cuda()
+    out = torch.empty_like(y_t)
+    halted = torch.zeros(N, dtype=torch.uint8).cuda()
+    ccfr.project_displacements(ctx, regions, torch.from_numpy(w).cuda(), y_t, prm, out, halted)
+    torch.cuda.synchronize()
+    assert ctx.sync_status(reset=True)[0] == 0
+    yg = out.cpu().numpy().astype(np.float64)
+    hg = halted.cpu().numpy()
+    _, hs_w = H.to_oracle_halfspaces(off, hs32)
+    x = np.zeros(3)
+    n_cmp = 0
+    for v in range(N):
+        yo, ho, fo = oracle.project_one(prm, float(w[v]), x, hs_w[off[v]:off[v + 1]], y[v].astype(np.float64))
+        if fo:
+            continue
+        n_cmp += 1
+        assert hg[v] == ho, (v, Ks[v])
+        assert np.linalg.norm(yg[v] - yo) <= H.DTOL * 1.0, (v, Ks[v], yg[v], yo)
+    assert n_cmp >= 0.8 * N
+
