@@ -227,26 +227,52 @@ int ccfr_profile_enable(ccfr_ctx* ctx, int enable);
 int ccfr_profile_read(ccfr_ctx* ctx, ccfr_stream stream, float* ms, int32_t* launches);
 
 /* ---- batches: many independent meshes stepped together ---- */
-/* A batch holds up to `max_slots` meshes resident on the device (positions,
- * velocities, topology) within `max_verts`, `max_tris` and `max_edges` in total.
- * Meshes in different slots never interact: their pairs are never formed. */
+/* The paper steps one scene at a time and defines no batching: these entry
+ * points run the substep of Alg. 4 (with Alg. 2-3 inside) over many unrelated
+ * meshes per launch.  Meshes are concatenated in a device pool; every vertex
+ * carries its slot id, which selects its mesh's collision parameters and keeps
+ * primitives of different slots from ever forming a pair, so each mesh evolves
+ * exactly as it would alone (same candidates, regions and projection).
+ *
+ * A batch holds up to `max_slots` (<= 65535) meshes within `max_verts`,
+ * `max_tris` and `max_edges` in total, and two copies of the pool (the second
+ * receives survivors when removed slots are compacted, and the step's entry
+ * snapshot).  It borrows `ctx`'s workspace: do not use `ctx` for other work
+ * while a batch step may still run, and destroy the batch before `ctx`.
+ * Capacity overflow of the workspace lists is reported by ccfr_sync_status on
+ * `ctx` as for single meshes: call ccfr_reserve with the reported needs, then
+ * ccfr_batch_rollback and step again. */
 int ccfr_batch_create(ccfr_ctx* ctx, int32_t max_slots, int64_t max_verts, int64_t max_tris,
                       int64_t max_edges, ccfr_batch** out);
 void ccfr_batch_destroy(ccfr_batch* b);
-/* Bytes of device memory a mesh of these sizes occupies inside a batch. */
+/* Upper bound on the device bytes a mesh of these sizes adds to a batch (both
+ * pools plus its share of the workspace at default list sizes); -1 on negative
+ * sizes.  A server admits requests while the sum stays within its budget. */
 int64_t ccfr_batch_footprint(int32_t n_verts, int32_t n_tris, int32_t n_edges);
-/* Admit a mesh (host arrays as in ccfr_mesh_create, plus initial x and v) with
- * its own parameters; *slot receives its slot id.  CCFR_ERR_CAPACITY if it does
- * not fit now.  Copies happen on `stream`. */
+/* Admit a mesh: host arrays as in ccfr_mesh_create, plus initial x and v
+ * ([n_verts][3] float32, finite) and its step parameters.  The collision part
+ * of `sp` is per mesh; dt, gravity, iters and alpha must equal those of the
+ * meshes already resident (else CCFR_ERR_INVALID_ARG).  *slot receives the
+ * lowest free slot id.  CCFR_ERR_CAPACITY if no slot or pool space is free;
+ * nothing changes then.  Copies are made on `stream`, and the call waits for
+ * them. */
 int ccfr_batch_add(ccfr_batch* b, int32_t n_verts, const int32_t* tris, int32_t n_tris,
                    const int32_t* edges, int32_t n_edges, const float* inv_mass,
                    const float* rest_x, const float* x, const float* v,
                    const ccfr_step_params* sp, int32_t* slot, ccfr_stream stream);
-/* Release a slot; its memory is reused by later admissions. */
+/* Release a slot (CCFR_ERR_INVALID_ARG if not resident).  Its pool space is
+ * reclaimed by compaction at the next add or step. */
 int ccfr_batch_remove(ccfr_batch* b, int32_t slot, ccfr_stream stream);
-/* One substep of every resident mesh (all meshes must share `iters`). */
+/* One substep of every resident mesh, enqueued on `stream` (a recorded graph,
+ * re-recorded whenever the resident set or the workspace changes).  It first
+ * snapshots x and v of every mesh for ccfr_batch_rollback. */
 int ccfr_batch_step(ccfr_batch* b, ccfr_stream stream);
-/* Copy a slot's positions / velocities ([n][3] float32) to host memory (waits). */
+/* Restore x and v of every resident mesh to what they were when the last
+ * ccfr_batch_step began.  CCFR_ERR_NOT_READY if no step ran since the last
+ * add or remove. */
+int ccfr_batch_rollback(ccfr_batch* b, ccfr_stream stream);
+/* Copy a slot's positions / velocities ([n][3] float32; either may be NULL) to
+ * host memory; waits for `stream`. */
 int ccfr_batch_read(ccfr_batch* b, int32_t slot, float* x_host, float* v_host, ccfr_stream stream);
 /* Number of resident meshes and their total vertex count. */
 int ccfr_batch_stats(const ccfr_batch* b, int32_t* n_resident, int64_t* n_verts);

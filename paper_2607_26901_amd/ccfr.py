@@ -61,7 +61,7 @@ EXPORTS = ["ccfr_status_string", "ccfr_create", "ccfr_destroy", "ccfr_mesh_creat
            "ccfr_build_regions", "ccfr_project_displacements", "ccfr_xpbd_step", "ccfr_sync_status",
            "ccfr_profile_enable", "ccfr_profile_read",
            "ccfr_batch_create", "ccfr_batch_destroy", "ccfr_batch_footprint", "ccfr_batch_add",
-           "ccfr_batch_remove", "ccfr_batch_step", "ccfr_batch_read", "ccfr_batch_stats"]
+           "ccfr_batch_remove", "ccfr_batch_step", "ccfr_batch_rollback", "ccfr_batch_read", "ccfr_batch_stats"]
 
 _lib = None
 
@@ -95,18 +95,18 @@ def load():
     lib.ccfr_sync_status.argtypes = [vp, vp, C.POINTER(StatusInfo), C.c_int]
     lib.ccfr_profile_enable.argtypes = [vp, C.c_int]
     lib.ccfr_profile_read.argtypes = [vp, vp, vp, vp]
-    if hasattr(lib, "ccfr_batch_create"):
-        lib.ccfr_batch_create.argtypes = [vp, i32, i64, i64, i64, C.POINTER(vp)]
-        lib.ccfr_batch_destroy.argtypes = [vp]
-        lib.ccfr_batch_destroy.restype = None
-        lib.ccfr_batch_footprint.restype = i64
-        lib.ccfr_batch_footprint.argtypes = [i32, i32, i32]
-        lib.ccfr_batch_add.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp, vp, vp, C.POINTER(StepParams),
-                                       C.POINTER(i32), vp]
-        lib.ccfr_batch_remove.argtypes = [vp, i32, vp]
-        lib.ccfr_batch_step.argtypes = [vp, vp]
-        lib.ccfr_batch_read.argtypes = [vp, i32, vp, vp, vp]
-        lib.ccfr_batch_stats.argtypes = [vp, C.POINTER(i32), C.POINTER(i64)]
+    lib.ccfr_batch_create.argtypes = [vp, i32, i64, i64, i64, C.POINTER(vp)]
+    lib.ccfr_batch_destroy.argtypes = [vp]
+    lib.ccfr_batch_destroy.restype = None
+    lib.ccfr_batch_footprint.restype = i64
+    lib.ccfr_batch_footprint.argtypes = [i32, i32, i32]
+    lib.ccfr_batch_add.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp, vp, vp, C.POINTER(StepParams),
+                                   C.POINTER(i32), vp]
+    lib.ccfr_batch_remove.argtypes = [vp, i32, vp]
+    lib.ccfr_batch_step.argtypes = [vp, vp]
+    lib.ccfr_batch_rollback.argtypes = [vp, vp]
+    lib.ccfr_batch_read.argtypes = [vp, i32, vp, vp, vp]
+    lib.ccfr_batch_stats.argtypes = [vp, C.POINTER(i32), C.POINTER(i64)]
     _lib = lib
     return lib
 
@@ -241,6 +241,77 @@ class Mesh:
 def mesh_from_scene(ctx: Context, scene, stretch=True) -> Mesh:
     return Mesh(ctx, scene.n_verts, scene.tris, scene.edges, scene.inv_mass,
                 scene.rest_x if stretch else None)
+
+
+def batch_footprint(n_verts, n_tris, n_edges) -> int:
+    """Device bytes a mesh of these sizes adds to a batch (an upper bound)."""
+    return int(load().ccfr_batch_footprint(int(n_verts), int(n_tris), int(n_edges)))
+
+
+class Batch:
+    """Many independent meshes stepped by one set of launches (slot ids as mesh ids)."""
+
+    def __init__(self, ctx: Context, max_slots, max_verts, max_tris, max_edges):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(ctx.lib.ccfr_batch_create(ctx.h, int(max_slots), int(max_verts), int(max_tris), int(max_edges),
+                                         C.byref(h)), "ccfr_batch_create")
+        self.h = h
+        self.sizes = {}
+
+    def add(self, n_verts, tris, edges, inv_mass, rest_x, x, v, step_params: StepParams, stream=None) -> int:
+        """Admit a mesh; returns its slot.  Raises CcfrError (CAPACITY when it does not fit)."""
+        tris_a, tris_p = _host(np.asarray(tris).reshape(-1, 3), np.int32)
+        edges_a, edges_p = _host(None if edges is None else np.asarray(edges).reshape(-1, 2), np.int32)
+        w_a, w_p = _host(inv_mass, np.float32)
+        r_a, r_p = _host(None if rest_x is None else np.asarray(rest_x).reshape(-1, 3), np.float32)
+        x_a, x_p = _host(np.asarray(x).reshape(-1, 3), np.float32)
+        v_a, v_p = _host(np.asarray(v).reshape(-1, 3), np.float32)
+        slot = C.c_int32(-1)
+        _check(self.ctx.lib.ccfr_batch_add(self.h, int(n_verts), tris_p, len(tris_a), edges_p,
+                                           0 if edges_a is None else len(edges_a), w_p, r_p, x_p, v_p,
+                                           C.byref(step_params), C.byref(slot), _stream(stream)), "ccfr_batch_add")
+        self.sizes[int(slot.value)] = int(n_verts)
+        return int(slot.value)
+
+    def add_scene(self, scene, step_params: StepParams, stretch=True, stream=None) -> int:
+        return self.add(scene.n_verts, scene.tris, scene.edges, scene.inv_mass,
+                        scene.rest_x if stretch else None, scene.x, scene.v, step_params, stream)
+
+    def remove(self, slot, stream=None):
+        _check(self.ctx.lib.ccfr_batch_remove(self.h, int(slot), _stream(stream)), "ccfr_batch_remove")
+        self.sizes.pop(int(slot), None)
+
+    def step(self, stream=None):
+        _check(self.ctx.lib.ccfr_batch_step(self.h, _stream(stream)), "ccfr_batch_step")
+
+    def rollback(self, stream=None):
+        _check(self.ctx.lib.ccfr_batch_rollback(self.h, _stream(stream)), "ccfr_batch_rollback")
+
+    def read(self, slot, stream=None):
+        n = self.sizes[int(slot)]
+        x = np.zeros((n, 3), np.float32)
+        v = np.zeros((n, 3), np.float32)
+        _check(self.ctx.lib.ccfr_batch_read(self.h, int(slot), x.ctypes.data_as(C.c_void_p),
+                                            v.ctypes.data_as(C.c_void_p), _stream(stream)), "ccfr_batch_read")
+        return x, v
+
+    def stats(self):
+        n = C.c_int32()
+        nv = C.c_int64()
+        _check(self.ctx.lib.ccfr_batch_stats(self.h, C.byref(n), C.byref(nv)), "ccfr_batch_stats")
+        return int(n.value), int(nv.value)
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.ccfr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def build_candidates(ctx: Context, mesh: Mesh, x, params, stream=None) -> Candidates:

@@ -11,131 +11,14 @@
 #include <new>
 #include <vector>
 
-#include "ccfr_internal.h"
+#include "ccfr_host.h"
 
 using namespace ccfr;
 
-namespace {
+using namespace ccfr::host;
 
-int ceil_log2(long long v) {
-    int k = 0;
-    while ((1LL << k) < v) ++k;
-    return k;
-}
-
-template <class T>
-hipError_t dev_alloc(T** p, long long count) {
-    *p = nullptr;
-    if (count <= 0) count = 1;
-    return hipMalloc((void**)p, sizeof(T) * (size_t)count);
-}
-
-template <class T>
-void dev_free(T*& p) {
-    if (p) (void)hipFree((void*)p);
-    p = nullptr;
-}
-
-}  // namespace
-
-struct ccfr_mesh {
-    ccfr_ctx* ctx = nullptr;
-    int32_t n_verts = 0, n_tris = 0, n_edges = 0, n_free = 0;
-    int32_t* tris_d = nullptr;
-    int32_t* edges_d = nullptr;
-    float* inv_mass_d = nullptr;
-    int32_t* free_list_d = nullptr;
-    uint8_t* is_free_d = nullptr;
-    // stretch constraints, edges sorted by colour
-    bool has_stretch = false;
-    int32_t* edges_sorted_d = nullptr;
-    float* rest_sorted_d = nullptr;
-    float* lambda_d = nullptr;
-    std::vector<int32_t> color_begin;   // n_colors + 1
-    float typ_len = 0.f;                // edge length the grid cell is sized for
-    std::vector<int32_t> edges_h;
-};
-
-struct StepGraph {
-    bool valid = false;
-    const ccfr_mesh* mesh = nullptr;
-    float* x = nullptr;
-    float* v = nullptr;
-    ccfr_step_params sp{};
-    long long generation = -1;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-};
-
-struct ccfr_ctx {
-    int device = 0;
-    hipStream_t capture_stream = nullptr;
-    DevCounters* counters_d = nullptr;
-    long long generation = 0;   // bumped whenever a workspace buffer moves
-    bool use_graphs = true;
-    bool narrow_fp32 = false;   // narrow-phase arithmetic in FP32 (measurement option)
-
-    // grid
-    int log2s = 0;
-    long long cap_targets = 0;
-    int32_t* cnt = nullptr;
-    int32_t* start = nullptr;
-    int32_t* rank = nullptr;
-    int32_t* key = nullptr;
-    GridEntry* entries = nullptr;
-    uint32_t* level_mask = nullptr;
-    int32_t cap_meshes = 0;
-    int32_t* scan_tmp = nullptr;
-    long long cap_scan_tmp = 0;
-
-    // candidate lists
-    int32_t* vf = nullptr;
-    int32_t* ee = nullptr;
-    int32_t* vv = nullptr;
-    long long cap_vf = 0, cap_ee = 0, cap_vv = 0;
-
-    // regions
-    Contact* contacts = nullptr;
-    long long cap_contacts = 0;
-    long long cap_verts = 0;
-    int32_t* vcount = nullptr;
-    int32_t* offsets = nullptr;
-    int32_t* slow_list = nullptr;
-    ccfr_halfspace* hs = nullptr;
-    double* sort_key = nullptr;
-    int32_t* sort_idx = nullptr;
-    long long cap_hs = 0;
-
-    // substep
-    float* x_pred = nullptr;
-    float* x_start = nullptr;
-    float* p = nullptr;
-    long long cap_step = 0;
-
-    StepGraph graph;
-
-    // stage timing: events[iteration][stage][begin/end]
-    bool profiling = false;
-    int prof_iters = 0;        // events allocated for this many iterations
-    int prof_last_iters = 0;   // iterations of the last profiled step
-    std::vector<hipEvent_t> prof_events;
-};
-
-constexpr int kStages = 6;
-
-#define HIP_OK(call)                                              \
-    do {                                                          \
-        hipError_t e_ = (call);                                   \
-        if (e_ != hipSuccess) return CCFR_ERR_HIP;                \
-    } while (0)
-
-#define HIP_ALLOC(call)                                           \
-    do {                                                          \
-        hipError_t e_ = (call);                                   \
-        if (e_ != hipSuccess) return CCFR_ERR_NO_MEMORY;          \
-    } while (0)
-
-namespace {
+namespace ccfr {
+namespace host {
 
 void drop_graph(ccfr_ctx* ctx) {
     if (ctx->graph.exec) (void)hipGraphExecDestroy(ctx->graph.exec);
@@ -260,16 +143,18 @@ int ensure_step(ccfr_ctx* ctx, long long n_verts) {
     return CCFR_OK;
 }
 
-// Default sizes from the mesh; later growth follows the observed needs.
-int ensure_for_mesh(ccfr_ctx* ctx, const ccfr_mesh* m) {
-    int rc = ensure_grid(ctx, (long long)m->n_tris + m->n_edges + m->n_free);
+// Default list sizes for a scene of these sizes; later growth follows the
+// observed needs (ccfr_reserve).
+int ensure_sizes(ccfr_ctx* ctx, long long n_verts, long long n_tris, long long n_edges, long long n_free,
+                 int n_meshes) {
+    int rc = ensure_grid(ctx, n_tris + n_edges + n_free);
     if (rc) return rc;
-    rc = ensure_meshes(ctx, 1);
+    rc = ensure_meshes(ctx, n_meshes);
     if (rc) return rc;
-    const long long vf = 8LL * m->n_verts + 4096, ee = 8LL * m->n_edges + 4096, vv = 16LL * m->n_free + 4096;
+    const long long vf = 8LL * n_verts + 4096, ee = 8LL * n_edges + 4096, vv = 16LL * n_free + 4096;
     rc = ensure_pairs(ctx, vf, ee, vv);
     if (rc) return rc;
-    return ensure_regions(ctx, m->n_verts, (vf + ee + vv) / 2, 2 * (vf + ee + vv));
+    return ensure_regions(ctx, n_verts, (vf + ee + vv) / 2, 2 * (vf + ee + vv));
 }
 
 bool params_ok(const ccfr_params* p) {
@@ -277,6 +162,12 @@ bool params_ok(const ccfr_params* p) {
            std::isfinite(p->delta) && p->delta >= 0.f && std::isfinite(p->guard) && p->guard >= 0.f &&
            std::isfinite(p->eps_retract) && p->eps_retract >= 0.f && std::isfinite(p->eps_plesnik) &&
            p->eps_plesnik >= 0.f && p->max_passes >= 1;
+}
+
+bool step_params_ok(const ccfr_step_params* sp) {
+    return sp && params_ok(&sp->collision) && sp->dt > 0.f && std::isfinite(sp->dt) && sp->iters >= 0 &&
+           std::isfinite(sp->alpha) && sp->alpha >= 0.f && std::isfinite(sp->gravity[0]) &&
+           std::isfinite(sp->gravity[1]) && std::isfinite(sp->gravity[2]);
 }
 
 // Per-mesh device parameters: the box pad (one FP32 rounding of an FP64 sum) and
@@ -297,6 +188,8 @@ MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt) {
     return m;
 }
 
+namespace {
+
 Scene make_scene(const ccfr_mesh* m, const float* x, const ccfr_params* p) {
     Scene sc{};
     sc.narrow_fp32 = m->ctx->narrow_fp32 ? 1 : 0;
@@ -316,7 +209,7 @@ Scene make_scene(const ccfr_mesh* m, const float* x, const ccfr_params* p) {
     return sc;
 }
 
-GridWs grid_ws(ccfr_ctx* ctx) {
+GridWs grid_ws(ccfr_ctx* ctx, int n_meshes) {
     GridWs g{};
     g.log2s = ctx->log2s;
     g.cnt = ctx->cnt;
@@ -325,7 +218,7 @@ GridWs grid_ws(ccfr_ctx* ctx) {
     g.key = ctx->key;
     g.entries = ctx->entries;
     g.level_mask = ctx->level_mask;
-    g.n_meshes = 1;
+    g.n_meshes = n_meshes;
     g.scan_tmp = ctx->scan_tmp;
     return g;
 }
@@ -342,8 +235,8 @@ struct Marks {
 };
 
 // broad phase into the context's lists
-void enqueue_candidates(ccfr_ctx* ctx, const Scene& sc, hipStream_t s, const Marks& mk) {
-    GridWs g = grid_ws(ctx);
+void enqueue_candidates(ccfr_ctx* ctx, const Scene& sc, int n_meshes, hipStream_t s, const Marks& mk) {
+    GridWs g = grid_ws(ctx, n_meshes);
     mk.mark(0, 0);
     launch_reset_build(ctx->counters_d, g.level_mask, g.n_meshes, s);
     launch_grid_count(sc, g, ctx->counters_d, s);
@@ -373,27 +266,39 @@ void enqueue_regions(ccfr_ctx* ctx, const Scene& sc, const int32_t* vf, const in
 
 int32_t* counts_ptr(ccfr_ctx* ctx) { return &ctx->counters_d->n_vf; }
 
-void enqueue_step(ccfr_ctx* ctx, const ccfr_mesh* m, float* x, float* v, const ccfr_step_params* sp,
-                  hipStream_t s) {
-    const Scene sc = make_scene(m, x, &sp->collision);
-    const int n = m->n_verts;
-    launch_predict(n, x, v, m->inv_mass_d, sp->dt, sp->gravity[0], sp->gravity[1], sp->gravity[2], ctx->x_pred,
-                   ctx->x_start, s);
-    if (m->has_stretch) launch_fill_zero(m->lambda_d, m->n_edges, s);
-    const float alpha_t = sp->alpha / (sp->dt * sp->dt);
-    for (int it = 0; it < sp->iters; ++it) {
+}  // namespace
+
+int ensure_prof_events(ccfr_ctx* ctx, int iters) {
+    if (!ctx->profiling || iters <= ctx->prof_iters) return CCFR_OK;
+    drop_graph(ctx);
+    const size_t need = (size_t)iters * kStages * 2;
+    while (ctx->prof_events.size() < need) {
+        hipEvent_t e = nullptr;
+        HIP_OK(hipEventCreate(&e));
+        ctx->prof_events.push_back(e);
+    }
+    ctx->prof_iters = iters;
+    return CCFR_OK;
+}
+
+// The substep of Alg. 4 (without response, friction or early exit).
+void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
+    const Scene& sc = plan.sc;
+    const int n = sc.n_verts;
+    launch_predict(n, plan.x, plan.v, sc.inv_mass, plan.dt, plan.gx, plan.gy, plan.gz, ctx->x_pred, ctx->x_start, s);
+    if (plan.has_stretch) launch_fill_zero(plan.lambda, plan.n_edges, s);
+    for (int it = 0; it < plan.iters; ++it) {
         const Marks mk{ctx, it, s};
-        enqueue_candidates(ctx, sc, s, mk);
+        enqueue_candidates(ctx, sc, plan.n_meshes, s, mk);
         enqueue_regions(ctx, sc, ctx->vf, ctx->ee, ctx->vv, counts_ptr(ctx), ctx->cap_vf, ctx->cap_ee,
                         ctx->cap_vv, s, mk);
         mk.mark(4, 0);
         launch_copy(ctx->x_pred, ctx->p, 3LL * n, s);
-        if (m->has_stretch) {
-            const int nc = (int)m->color_begin.size() - 1;
-            for (int c = 0; c < nc; ++c)
-                launch_stretch_color(m->edges_sorted_d, m->rest_sorted_d, m->color_begin[c],
-                                     m->color_begin[c + 1] - m->color_begin[c], m->inv_mass_d, ctx->p, m->lambda_d,
-                                     alpha_t, s);
+        if (plan.has_stretch) {
+            for (size_t c = 0; c < plan.col_total.size(); ++c)
+                launch_stretch_segments(plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[c],
+                                        plan.col_nseg[c], plan.col_total[c], sc.inv_mass, ctx->p, plan.lambda,
+                                        plan.alpha_t, s);
         }
         mk.mark(4, 1);
         ProjectArgs pa{};
@@ -401,10 +306,10 @@ void enqueue_step(ccfr_ctx* ctx, const ccfr_mesh* m, float* x, float* v, const c
         pa.offsets = ctx->offsets;
         pa.hs = ctx->hs;
         pa.cap_hs = ctx->cap_hs;
-        pa.inv_mass = m->inv_mass_d;
+        pa.inv_mass = sc.inv_mass;
         pa.y_in = nullptr;
         pa.p = ctx->p;
-        pa.x_anchor = x;
+        pa.x_anchor = plan.x;
         pa.y_out = nullptr;
         pa.halted = nullptr;
         pa.sort_key = ctx->sort_key;
@@ -415,7 +320,166 @@ void enqueue_step(ccfr_ctx* ctx, const ccfr_mesh* m, float* x, float* v, const c
         launch_project(pa, ctx->counters_d, s);
         mk.mark(5, 1);
     }
-    launch_update_velocity(n, x, ctx->x_start, 1.0f / sp->dt, v, s);
+    launch_update_velocity(n, plan.x, ctx->x_start, 1.0f / plan.dt, plan.v, s);
+}
+
+int launch_recorded(ccfr_ctx* ctx, StepGraph& G, const StepPlan& plan, const void* owner,
+                    const ccfr_step_params* sp, bool same, hipStream_t s) {
+    if (!same) {
+        if (G.exec) (void)hipGraphExecDestroy(G.exec);
+        if (G.graph) (void)hipGraphDestroy(G.graph);
+        G = StepGraph{};
+        HIP_OK(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+        enqueue_step(ctx, plan, ctx->capture_stream);
+        hipGraph_t graph = nullptr;
+        HIP_OK(hipStreamEndCapture(ctx->capture_stream, &graph));
+        hipGraphExec_t exec = nullptr;
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return CCFR_ERR_HIP;
+        }
+        G.valid = true;
+        G.owner = owner;
+        G.x = plan.x;
+        G.v = plan.v;
+        G.sp = *sp;
+        G.generation = ctx->generation;
+        G.graph = graph;
+        G.exec = exec;
+    }
+    HIP_OK(hipGraphLaunch(G.exec, s));
+    return CCFR_OK;
+}
+
+int prepare_mesh(int32_t n_verts, const int32_t* tris, int32_t n_tris, const int32_t* edges, int32_t n_edges,
+                 const float* inv_mass, const float* rest_x, MeshHost* out) {
+    if (n_verts < 0 || n_tris < 0 || n_edges < 0 || !inv_mass || !out) return CCFR_ERR_INVALID_ARG;
+    if (n_tris > 0 && !tris) return CCFR_ERR_INVALID_ARG;
+    for (long long i = 0; i < 3LL * n_tris; ++i)
+        if (tris[i] < 0 || tris[i] >= n_verts) return CCFR_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < n_verts; ++i)
+        if (!(inv_mass[i] >= 0.f) || !std::isfinite(inv_mass[i])) return CCFR_ERR_INVALID_ARG;
+    MeshHost& m = *out;
+    m = MeshHost{};
+    m.n_verts = n_verts;
+    m.n_tris = n_tris;
+    m.tris.assign(tris ? tris : nullptr, tris ? tris + 3LL * n_tris : nullptr);
+    std::vector<int32_t>& E = m.edges;
+    if (edges) {
+        E.assign(edges, edges + 2LL * n_edges);
+        for (int32_t e = 0; e < n_edges; ++e) {
+            const int32_t a = E[2 * e], b = E[2 * e + 1];
+            if (a < 0 || b < 0 || a >= n_verts || b >= n_verts || a == b) return CCFR_ERR_INVALID_ARG;
+        }
+    } else {
+        std::vector<long long> keys;
+        keys.reserve(3LL * n_tris);
+        for (int32_t t = 0; t < n_tris; ++t)
+            for (int k = 0; k < 3; ++k) {
+                const long long a = tris[3 * t + k], b = tris[3 * t + (k + 1) % 3];
+                keys.push_back(std::min(a, b) * (1LL << 32) + std::max(a, b));
+            }
+        std::sort(keys.begin(), keys.end());
+        keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+        for (long long k : keys) {
+            E.push_back((int32_t)(k >> 32));
+            E.push_back((int32_t)(k & 0xffffffffLL));
+        }
+        n_edges = (int32_t)(E.size() / 2);
+    }
+    m.n_edges = n_edges;
+    // free particles: vertices in no edge and no triangle
+    m.is_free.assign(n_verts, 1);
+    for (int32_t v : m.tris) m.is_free[v] = 0;
+    for (int32_t v : E) m.is_free[v] = 0;
+    for (int32_t v = 0; v < n_verts; ++v)
+        if (m.is_free[v]) m.free_list.push_back(v);
+    // edge length the grid is sized for: the longest edge not longer than 8x the median
+    if (n_edges > 0 && rest_x) {
+        std::vector<float> len(n_edges);
+        for (int32_t e = 0; e < n_edges; ++e) {
+            double d2 = 0;
+            for (int k = 0; k < 3; ++k) {
+                const double d = (double)rest_x[3 * E[2 * e] + k] - (double)rest_x[3 * E[2 * e + 1] + k];
+                d2 += d * d;
+            }
+            len[e] = (float)std::sqrt(d2);
+        }
+        std::vector<float> sorted = len;
+        std::nth_element(sorted.begin(), sorted.begin() + n_edges / 2, sorted.end());
+        const float med = sorted[n_edges / 2];
+        for (float l : len)
+            if (l <= 8.f * med) m.typ_len = std::max(m.typ_len, l);
+    }
+    // greedy colouring in edge-index order, then edges sorted by (colour, index)
+    std::vector<int32_t> color(n_edges, 0);
+    std::vector<uint64_t> used(n_verts, 0);
+    int n_colors = 0;
+    for (int32_t e = 0; e < n_edges; ++e) {
+        const int32_t a = E[2 * e], b = E[2 * e + 1];
+        const uint64_t taken = used[a] | used[b];
+        int c = 0;
+        while (c < 64 && ((taken >> c) & 1ull)) ++c;
+        if (c == 64) return CCFR_ERR_INVALID_ARG;   // a vertex with more than 32 edges
+        color[e] = c;
+        used[a] |= 1ull << c;
+        used[b] |= 1ull << c;
+        n_colors = std::max(n_colors, c + 1);
+    }
+    m.color_begin.assign(n_colors + 1, 0);
+    for (int32_t e = 0; e < n_edges; ++e) m.color_begin[color[e] + 1]++;
+    for (int c = 0; c < n_colors; ++c) m.color_begin[c + 1] += m.color_begin[c];
+    m.edges_sorted.assign(2LL * n_edges, 0);
+    m.rest_sorted.assign(n_edges, 0.f);
+    std::vector<int32_t> cur(m.color_begin.begin(), m.color_begin.end() - 1);
+    for (int32_t e = 0; e < n_edges; ++e) {
+        const int32_t pos = cur[color[e]]++;
+        m.edges_sorted[2 * pos] = E[2 * e];
+        m.edges_sorted[2 * pos + 1] = E[2 * e + 1];
+        if (rest_x) {
+            double d2 = 0;
+            for (int k = 0; k < 3; ++k) {
+                const double d = (double)rest_x[3 * E[2 * e] + k] - (double)rest_x[3 * E[2 * e + 1] + k];
+                d2 += d * d;
+            }
+            m.rest_sorted[pos] = (float)std::sqrt(d2);
+        }
+    }
+    m.has_stretch = rest_x != nullptr && n_edges > 0;
+    return CCFR_OK;
+}
+
+}  // namespace host
+}  // namespace ccfr
+
+namespace {
+
+StepPlan mesh_plan(ccfr_ctx* ctx, const ccfr_mesh* m, float* x, float* v, const ccfr_step_params* sp) {
+    StepPlan plan;
+    plan.sc = make_scene(m, x, &sp->collision);
+    plan.x = x;
+    plan.v = v;
+    plan.n_meshes = 1;
+    plan.has_stretch = m->has_stretch;
+    plan.edges_sorted = m->edges_sorted_d;
+    plan.rest_sorted = m->rest_sorted_d;
+    plan.lambda = m->lambda_d;
+    plan.n_edges = m->n_edges;
+    plan.segs = m->segs_d;
+    const int nc = (int)m->color_begin.size() - 1;
+    for (int c = 0; c < nc; ++c) {
+        plan.col_first.push_back(c);
+        plan.col_nseg.push_back(1);
+        plan.col_total.push_back(m->color_begin[c + 1] - m->color_begin[c]);
+    }
+    plan.dt = sp->dt;
+    plan.gx = sp->gravity[0];
+    plan.gy = sp->gravity[1];
+    plan.gz = sp->gravity[2];
+    plan.alpha_t = sp->alpha / (sp->dt * sp->dt);
+    plan.iters = sp->iters;
+    (void)ctx;
+    return plan;
 }
 
 }  // namespace
@@ -480,114 +544,25 @@ void ccfr_destroy(ccfr_ctx* ctx) {
 
 int ccfr_mesh_create(ccfr_ctx* ctx, int32_t n_verts, const int32_t* tris, int32_t n_tris, const int32_t* edges,
                      int32_t n_edges, const float* inv_mass, const float* rest_x, ccfr_mesh** out) {
-    if (!ctx || !out || n_verts < 0 || n_tris < 0 || n_edges < 0 || !inv_mass) return CCFR_ERR_INVALID_ARG;
-    if (n_tris > 0 && !tris) return CCFR_ERR_INVALID_ARG;
+    if (!ctx || !out) return CCFR_ERR_INVALID_ARG;
     *out = nullptr;
-    for (long long i = 0; i < 3LL * n_tris; ++i)
-        if (tris[i] < 0 || tris[i] >= n_verts) return CCFR_ERR_INVALID_ARG;
-    for (int32_t i = 0; i < n_verts; ++i)
-        if (!(inv_mass[i] >= 0.f) || !std::isfinite(inv_mass[i])) return CCFR_ERR_INVALID_ARG;
-    // edges: given, or the unique sorted edges of the triangles
-    std::vector<int32_t> E;
-    if (edges) {
-        E.assign(edges, edges + 2LL * n_edges);
-        for (int32_t e = 0; e < n_edges; ++e) {
-            const int32_t a = E[2 * e], b = E[2 * e + 1];
-            if (a < 0 || b < 0 || a >= n_verts || b >= n_verts || a == b) return CCFR_ERR_INVALID_ARG;
-        }
-    } else {
-        std::vector<long long> keys;
-        keys.reserve(3LL * n_tris);
-        for (int32_t t = 0; t < n_tris; ++t)
-            for (int k = 0; k < 3; ++k) {
-                const long long a = tris[3 * t + k], b = tris[3 * t + (k + 1) % 3];
-                keys.push_back(std::min(a, b) * (1LL << 32) + std::max(a, b));
-            }
-        std::sort(keys.begin(), keys.end());
-        keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-        for (long long k : keys) {
-            E.push_back((int32_t)(k >> 32));
-            E.push_back((int32_t)(k & 0xffffffffLL));
-        }
-        n_edges = (int32_t)(E.size() / 2);
-    }
+    MeshHost h;
+    int rc = prepare_mesh(n_verts, tris, n_tris, edges, n_edges, inv_mass, rest_x, &h);
+    if (rc) return rc;
+    HIP_OK(hipSetDevice(ctx->device));
     ccfr_mesh* m = new (std::nothrow) ccfr_mesh();
     if (!m) return CCFR_ERR_NO_MEMORY;
     m->ctx = ctx;
-    m->n_verts = n_verts;
-    m->n_tris = n_tris;
-    m->n_edges = n_edges;
-    m->edges_h = E;
-    // free particles
-    std::vector<uint8_t> is_free(n_verts, 1);
-    for (long long i = 0; i < 3LL * n_tris; ++i) is_free[tris[i]] = 0;
-    for (int32_t v : E) is_free[v] = 0;
-    std::vector<int32_t> free_list;
-    for (int32_t v = 0; v < n_verts; ++v)
-        if (is_free[v]) free_list.push_back(v);
-    m->n_free = (int32_t)free_list.size();
-    // edge length the grid is sized for: the longest edge not longer than 8x the median
-    if (n_edges > 0) {
-        std::vector<float> len(n_edges);
-        const float* px = rest_x;
-        for (int32_t e = 0; e < n_edges && px; ++e) {
-            const int32_t a = E[2 * e], b = E[2 * e + 1];
-            double d2 = 0;
-            for (int k = 0; k < 3; ++k) {
-                const double d = (double)px[3 * a + k] - (double)px[3 * b + k];
-                d2 += d * d;
-            }
-            len[e] = (float)std::sqrt(d2);
-        }
-        if (px) {
-            std::vector<float> sorted = len;
-            std::nth_element(sorted.begin(), sorted.begin() + n_edges / 2, sorted.end());
-            const float med = sorted[n_edges / 2];
-            float typ = 0.f;
-            for (float l : len)
-                if (l <= 8.f * med) typ = std::max(typ, l);
-            m->typ_len = typ;
-        }
-    }
-    // greedy colouring in edge-index order, then edges sorted by (colour, index)
-    std::vector<int32_t> color(n_edges, 0);
-    std::vector<uint64_t> used(n_verts, 0);
-    int n_colors = 0;
-    bool color_ok = true;
-    for (int32_t e = 0; e < n_edges; ++e) {
-        const int32_t a = E[2 * e], b = E[2 * e + 1];
-        const uint64_t taken = used[a] | used[b];
-        int c = 0;
-        while (c < 64 && ((taken >> c) & 1ull)) ++c;
-        if (c == 64) { color_ok = false; break; }
-        color[e] = c;
-        used[a] |= 1ull << c;
-        used[b] |= 1ull << c;
-        n_colors = std::max(n_colors, c + 1);
-    }
-    if (!color_ok) { delete m; return CCFR_ERR_INVALID_ARG; }
-    m->color_begin.assign(n_colors + 1, 0);
-    for (int32_t e = 0; e < n_edges; ++e) m->color_begin[color[e] + 1]++;
-    for (int c = 0; c < n_colors; ++c) m->color_begin[c + 1] += m->color_begin[c];
-    std::vector<int32_t> es(2LL * n_edges);
-    std::vector<float> rs(n_edges, 0.f);
-    {
-        std::vector<int32_t> cur(m->color_begin.begin(), m->color_begin.end() - 1);
-        for (int32_t e = 0; e < n_edges; ++e) {
-            const int32_t pos = cur[color[e]]++;
-            es[2 * pos] = E[2 * e];
-            es[2 * pos + 1] = E[2 * e + 1];
-            if (rest_x) {
-                double d2 = 0;
-                for (int k = 0; k < 3; ++k) {
-                    const double d = (double)rest_x[3 * E[2 * e] + k] - (double)rest_x[3 * E[2 * e + 1] + k];
-                    d2 += d * d;
-                }
-                rs[pos] = (float)std::sqrt(d2);
-            }
-        }
-    }
-    m->has_stretch = rest_x != nullptr && n_edges > 0;
+    m->n_verts = h.n_verts;
+    m->n_tris = h.n_tris;
+    m->n_edges = h.n_edges;
+    m->n_free = (int32_t)h.free_list.size();
+    m->edges_h = h.edges;
+    m->typ_len = h.typ_len;
+    m->color_begin = h.color_begin;
+    m->has_stretch = h.has_stretch;
+    std::vector<int2> segs;
+    for (size_t c = 0; c + 1 < h.color_begin.size(); ++c) segs.push_back(make_int2(h.color_begin[c], 0));
     hipError_t e = hipSuccess;
     auto put = [&](auto** dst, const auto* src, long long count) {
         if (e != hipSuccess) return;
@@ -595,19 +570,20 @@ int ccfr_mesh_create(ccfr_ctx* ctx, int32_t n_verts, const int32_t* tris, int32_
         if (e == hipSuccess && count > 0)
             e = hipMemcpy((void*)*dst, (const void*)src, sizeof(**dst) * (size_t)count, hipMemcpyHostToDevice);
     };
-    put(&m->tris_d, tris, 3LL * n_tris);
-    put(&m->edges_d, E.data(), 2LL * n_edges);
-    put(&m->inv_mass_d, inv_mass, n_verts);
-    put(&m->free_list_d, free_list.data(), (long long)free_list.size());
-    put(&m->is_free_d, is_free.data(), n_verts);
-    put(&m->edges_sorted_d, es.data(), 2LL * n_edges);
-    put(&m->rest_sorted_d, rs.data(), n_edges);
-    if (e == hipSuccess) e = dev_alloc(&m->lambda_d, std::max<long long>(n_edges, 1));
+    put(&m->tris_d, h.tris.data(), 3LL * h.n_tris);
+    put(&m->edges_d, h.edges.data(), 2LL * h.n_edges);
+    put(&m->inv_mass_d, inv_mass, h.n_verts);
+    put(&m->free_list_d, h.free_list.data(), (long long)h.free_list.size());
+    put(&m->is_free_d, h.is_free.data(), h.n_verts);
+    put(&m->edges_sorted_d, h.edges_sorted.data(), 2LL * h.n_edges);
+    put(&m->rest_sorted_d, h.rest_sorted.data(), h.n_edges);
+    put(&m->segs_d, segs.data(), (long long)segs.size());
+    if (e == hipSuccess) e = dev_alloc(&m->lambda_d, std::max<long long>(h.n_edges, 1));
     if (e != hipSuccess) {
         ccfr_mesh_destroy(m);
         return CCFR_ERR_NO_MEMORY;
     }
-    int rc = ensure_for_mesh(ctx, m);
+    rc = ensure_sizes(ctx, m->n_verts, m->n_tris, m->n_edges, m->n_free, 1);
     if (rc) {
         ccfr_mesh_destroy(m);
         return rc;
@@ -618,9 +594,10 @@ int ccfr_mesh_create(ccfr_ctx* ctx, int32_t n_verts, const int32_t* tris, int32_
 
 void ccfr_mesh_destroy(ccfr_mesh* m) {
     if (!m) return;
-    if (m->ctx && m->ctx->graph.mesh == m) drop_graph(m->ctx);
+    if (m->ctx && m->ctx->graph.owner == m) drop_graph(m->ctx);
     dev_free(m->tris_d); dev_free(m->edges_d); dev_free(m->inv_mass_d); dev_free(m->free_list_d);
     dev_free(m->is_free_d); dev_free(m->edges_sorted_d); dev_free(m->rest_sorted_d); dev_free(m->lambda_d);
+    dev_free(m->segs_d);
     delete m;
 }
 
@@ -653,7 +630,7 @@ int ccfr_build_candidates(ccfr_ctx* ctx, const ccfr_mesh* mesh, const float* x_a
     if (mesh->ctx != ctx) return CCFR_ERR_INVALID_ARG;
     const hipStream_t s = (hipStream_t)stream;
     const Scene sc = make_scene(mesh, x_anchor_dev, params);
-    enqueue_candidates(ctx, sc, s, Marks{ctx, -1, s});
+    enqueue_candidates(ctx, sc, 1, s, Marks{ctx, -1, s});
     HIP_OK(hipGetLastError());
     out->vf = ctx->vf;
     out->ee = ctx->ee;
@@ -723,59 +700,29 @@ int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const
 
 int ccfr_xpbd_step(ccfr_ctx* ctx, const ccfr_mesh* mesh, float* x_dev, float* v_dev, const ccfr_step_params* sp,
                    ccfr_stream stream) {
-    if (!ctx || !mesh || !x_dev || !v_dev || !sp || !params_ok(&sp->collision)) return CCFR_ERR_INVALID_ARG;
-    if (!(sp->dt > 0.f) || !std::isfinite(sp->dt) || sp->iters < 0 || !std::isfinite(sp->alpha) || sp->alpha < 0.f)
-        return CCFR_ERR_INVALID_ARG;
+    if (!ctx || !mesh || !x_dev || !v_dev || !step_params_ok(sp)) return CCFR_ERR_INVALID_ARG;
     if (mesh->ctx != ctx) return CCFR_ERR_INVALID_ARG;
     const hipStream_t s = (hipStream_t)stream;
     const long long gen0 = ctx->generation;
     int rc = ensure_step(ctx, mesh->n_verts);
     if (rc) return rc;
-    rc = ensure_for_mesh(ctx, mesh);
+    rc = ensure_sizes(ctx, mesh->n_verts, mesh->n_tris, mesh->n_edges, mesh->n_free, 1);
     if (rc) return rc;
     if (ctx->generation != gen0) drop_graph(ctx);
-    if (ctx->profiling && sp->iters > ctx->prof_iters) {
-        drop_graph(ctx);
-        const size_t need = (size_t)sp->iters * kStages * 2;
-        while (ctx->prof_events.size() < need) {
-            hipEvent_t e = nullptr;
-            HIP_OK(hipEventCreate(&e));
-            ctx->prof_events.push_back(e);
-        }
-        ctx->prof_iters = sp->iters;
-    }
+    rc = ensure_prof_events(ctx, sp->iters);
+    if (rc) return rc;
+    const StepPlan plan = mesh_plan(ctx, mesh, x_dev, v_dev, sp);
     if (ctx->profiling) ctx->prof_last_iters = sp->iters;
     // profiled steps run eagerly: the stage events bracket the launches on `s`
     if (!ctx->use_graphs || ctx->profiling) {
-        enqueue_step(ctx, mesh, x_dev, v_dev, sp, s);
+        enqueue_step(ctx, plan, s);
         HIP_OK(hipGetLastError());
         return CCFR_OK;
     }
-    StepGraph& G = ctx->graph;
-    const bool same = G.valid && G.mesh == mesh && G.x == x_dev && G.v == v_dev &&
+    const StepGraph& G = ctx->graph;
+    const bool same = G.valid && G.owner == mesh && G.x == x_dev && G.v == v_dev &&
                       std::memcmp(&G.sp, sp, sizeof(*sp)) == 0 && G.generation == ctx->generation;
-    if (!same) {
-        drop_graph(ctx);
-        HIP_OK(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
-        enqueue_step(ctx, mesh, x_dev, v_dev, sp, ctx->capture_stream);
-        hipGraph_t graph = nullptr;
-        HIP_OK(hipStreamEndCapture(ctx->capture_stream, &graph));
-        hipGraphExec_t exec = nullptr;
-        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-            (void)hipGraphDestroy(graph);
-            return CCFR_ERR_HIP;
-        }
-        G.valid = true;
-        G.mesh = mesh;
-        G.x = x_dev;
-        G.v = v_dev;
-        G.sp = *sp;
-        G.generation = ctx->generation;
-        G.graph = graph;
-        G.exec = exec;
-    }
-    HIP_OK(hipGraphLaunch(G.exec, s));
-    return CCFR_OK;
+    return launch_recorded(ctx, ctx->graph, plan, mesh, sp, same, s);
 }
 
 int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, int reset) {

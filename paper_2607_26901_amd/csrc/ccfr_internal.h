@@ -168,9 +168,9 @@ void launch_predict(int n, const float* x, const float* v, const float* inv_mass
                     float gx, float gy, float gz, float* x_pred, float* x_start, hipStream_t s);
 void launch_fill_zero(float* p, int64_t n, hipStream_t s);
 void launch_copy(const float* src, float* dst, int64_t n, hipStream_t s);
-void launch_stretch_color(const int32_t* edges_sorted, const float* rest_sorted, int32_t begin,
-                          int32_t count, const float* inv_mass, float* p, float* lambda_sorted,
-                          float alpha_t, hipStream_t s);
+void launch_stretch_segments(const int32_t* edges_sorted, const float* rest_sorted, const int2* segs, int32_t nseg,
+                             int32_t total, const float* inv_mass, float* p, float* lambda_sorted, float alpha_t,
+                             hipStream_t s);
 void launch_update_velocity(int n, const float* x, const float* x_start, float inv_dt, float* v,
                             hipStream_t s);
 void launch_check_finite(const float* a, int64_t n, DevCounters* c, hipStream_t s);

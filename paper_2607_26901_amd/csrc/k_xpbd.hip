@@ -38,11 +38,21 @@ __global__ __launch_bounds__(kBlock) void k_copy(const float* src, float* dst, l
     if (i < n) dst[i] = src[i];
 }
 
-__global__ __launch_bounds__(kBlock) void k_stretch(const int32_t* edges, const float* rest, int begin, int count,
-                                                    const float* w, float* p, float* lambda, float alpha_t) {
-    const int k = blockIdx.x * kBlock + threadIdx.x;
-    if (k >= count) return;
-    const int e = begin + k;
+// Colour class of the stretch pass: its edges lie in nseg segments of the
+// colour-sorted edge array, segs[k] = (first edge, exclusive prefix of segment
+// lengths); thread t finds its segment by binary search.
+__global__ __launch_bounds__(kBlock) void k_stretch(const int32_t* edges, const float* rest, const int2* segs,
+                                                    int nseg, int total, const float* w, float* p, float* lambda,
+                                                    float alpha_t) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= total) return;
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].y <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const int e = segs[lo].x + (t - segs[lo].y);
     const int i = edges[2 * e], j = edges[2 * e + 1];
     const float wi = w[i], wj = w[j];
     const float W = wi + wj;
@@ -96,11 +106,12 @@ void launch_copy(const float* src, float* dst, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_copy, dim3(blocks_for(n)), dim3(kBlock), 0, s, src, dst, (long long)n);
 }
 
-void launch_stretch_color(const int32_t* edges_sorted, const float* rest_sorted, int32_t begin, int32_t count,
-                          const float* inv_mass, float* p, float* lambda_sorted, float alpha_t, hipStream_t s) {
-    if (count <= 0) return;
-    hipLaunchKernelGGL(k_stretch, dim3(blocks_for(count)), dim3(kBlock), 0, s, edges_sorted, rest_sorted, begin,
-                       count, inv_mass, p, lambda_sorted, alpha_t);
+void launch_stretch_segments(const int32_t* edges_sorted, const float* rest_sorted, const int2* segs, int32_t nseg,
+                             int32_t total, const float* inv_mass, float* p, float* lambda_sorted, float alpha_t,
+                             hipStream_t s) {
+    if (total <= 0 || nseg <= 0) return;
+    hipLaunchKernelGGL(k_stretch, dim3(blocks_for(total)), dim3(kBlock), 0, s, edges_sorted, rest_sorted, segs, nseg,
+                       total, inv_mass, p, lambda_sorted, alpha_t);
 }
 
 void launch_update_velocity(int n, const float* x, const float* x_start, float inv_dt, float* v, hipStream_t s) {
