@@ -186,9 +186,13 @@ def edges_from_tris(tris: np.ndarray, extra=None) -> np.ndarray:
         else np.zeros((0, 2), np.int64)
     if extra is not None and len(extra):
         e = np.concatenate([e, extra], 0)
-    e = np.sort(e, 1)
-    e = np.unique(e, axis=0)           # lexicographic order
-    return e
+    e = np.sort(e, 1).astype(np.int64)
+    if not len(e):
+        return e
+    # unique rows in lexicographic order, through one 64-bit key per edge
+    n = int(e.max()) + 1
+    k = np.unique(e[:, 0] * n + e[:, 1])
+    return np.stack([k // n, k % n], 1)
 
 
 def assemble(name, meshes, params, step, rest_x=None, meta=None) -> Scene:
