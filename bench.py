@@ -107,7 +107,7 @@ def bench_served(args):
 
     t = time.perf_counter()
     reqs = S.c4_requests(n_requests=args.requests)
-    jobs = [serve.Job(r.id, r.arrival, r.scene, r.scene.step.steps) for r in reqs]
+    jobs = [serve.Job(r.rid, r.arrival, r.scene, r.scene.step.steps) for r in reqs]
     log(f"[bench] c4: {len(jobs)} requests generated in {time.perf_counter() - t:.1f} s, "
         f"{sum(j.scene.n_verts for j in jobs)} vertices in all")
     budget = int(args.budget_gib * (1 << 30))
@@ -172,6 +172,10 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the profiled pass (no roofline)")
     ap.add_argument("--requests", type=int, default=512, help="c4: number of requests of the stream")
     ap.add_argument("--budget-gib", type=float, default=4.0, help="c4: device-footprint budget of the server")
+    ap.add_argument("--no-tune", action="store_true", help="skip the cell-size autotuner (default cell)")
+    ap.add_argument("--cell-scale", type=float, default=None, help="fixed grid cell scale (skips the tuner)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (scale for HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path would shard "
@@ -182,6 +186,15 @@ def main():
     from paper_2607_26901_amd import ccfr
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n}))
+        return 0
     if args.workload == "c4":
         return bench_served(args)
     sc, desc = workload(args.workload)
@@ -218,6 +231,18 @@ def main():
                     contacts=int(nd[3] * 1.5) + 1024, halfspaces=int(nd[4] * 1.5) + 1024)
     else:
         raise RuntimeError("capacity probe did not converge")
+
+    # grid cell size: fixed, default, or picked by the autotuner on the first steps
+    tuning = None
+    if args.cell_scale is not None:
+        ctx.set_tuning(cell_scale=args.cell_scale)
+        tuning = {"cell_scale": args.cell_scale, "source": "fixed"}
+    elif not args.no_tune:
+        from paper_2607_26901_amd import autotune
+        reset()
+        tuning = autotune.tune_mesh(ctx, mesh, x, v, sp, steps=min(4, K))
+        tuning["source"] = "autotuned on the first steps"
+        log(f"[bench] tuning: {tuning}")
 
     # warmup (the first step records the step graph)
     reset()
@@ -278,6 +303,7 @@ def main():
         "per_iteration": {"pairs": P, "contacts": Cc, "halfspaces": Hh,
                           "violating_vertices": tot[4] / n_builds, "halted_vertices": tot[5] / n_builds},
         "halted_fraction_of_violating": (tot[5] / tot[4]) if tot[4] else 0.0,
+        "tuning": tuning if tuning is not None else {"cell_scale": 1.0, "source": "default"},
     }
 
     # profiled pass: the same K steps as individual launches with HIP events around

@@ -226,6 +226,20 @@ int ccfr_profile_enable(ccfr_ctx* ctx, int enable);
  * (launches[6], nullable). */
 int ccfr_profile_read(ccfr_ctx* ctx, ccfr_stream stream, float* ms, int32_t* launches);
 
+/* ---- tuning ----
+ * Knobs that change speed only: the candidate set is fixed by the box test, so
+ * every setting gives the same pairs, regions and displacements.
+ *   cell_scale  grid cell size as a multiple of the default, 1.2 x the typical
+ *               edge length + 2 pad (the cell never drops below 2.02 pad);
+ *               in [0.25, 4], default 1.
+ * Setting them invalidates recorded step graphs (they are recorded again). */
+typedef struct {
+    float cell_scale;
+    int32_t reserved[3];   /* 0 */
+} ccfr_tuning;
+int ccfr_set_tuning(ccfr_ctx* ctx, const ccfr_tuning* tuning);
+int ccfr_get_tuning(const ccfr_ctx* ctx, ccfr_tuning* tuning);
+
 /* ---- batches: many independent meshes stepped together ---- */
 /* The paper steps one scene at a time and defines no batching: these entry
  * points run the substep of Alg. 4 (with Alg. 2-3 inside) over many unrelated

@@ -1,0 +1,130 @@
+"""Autotuner of the speed-only knobs of a context.
+
+The knob is the grid cell size (`cell_scale`, a multiple of the default cell:
+1.2 x the typical edge length + 2 pad).  Smaller cells put fewer entries in the
+buckets a query scans but bin long primitives one level up; the best value
+depends on the mesh's edge lengths, its contact density and the pad.  Every
+value gives the same candidate pairs (the box test alone decides them), so the
+tuner only times: it runs the same work once per candidate value, keeps the
+fastest, and caches the choice per size class in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+from . import ccfr
+
+CELL_SCALES = (0.5, 0.6, 0.7, 0.85, 1.0, 1.2)
+
+
+def size_class(n_verts, n_tris, n_edges, r, kind="mesh") -> str:
+    """Key of a workload shape: log2 sizes and the pad's order of magnitude."""
+    def lg(v):
+        return int(math.ceil(math.log2(max(int(v), 1))))
+    return f"{kind}-v{lg(n_verts)}-t{lg(n_tris + 1)}-e{lg(n_edges + 1)}-r{int(round(math.log10(max(r, 1e-9))))}"
+
+
+def default_cache_path() -> str:
+    return os.environ.get("CCFR_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "ccfr", "tuning.json"))
+
+
+class Cache:
+    def __init__(self, path: str | None = None):
+        self.path = path or default_cache_path()
+        self.data = {}
+        if os.path.exists(self.path):
+            try:
+                with open(self.path) as f:
+                    self.data = json.load(f)
+            except (OSError, ValueError):
+                self.data = {}
+
+    def get(self, key):
+        return self.data.get(key)
+
+    def put(self, key, value):
+        self.data[key] = value
+        try:
+            os.makedirs(os.path.dirname(self.path), exist_ok=True)
+            with open(self.path, "w") as f:
+                json.dump(self.data, f, indent=1, sort_keys=True)
+        except OSError:
+            pass
+
+
+def tune(ctx: ccfr.Context, run, candidates=CELL_SCALES, repeats: int = 2) -> dict:
+    """Time `run()` (device milliseconds of a fixed piece of work, starting from
+    the same state every call) under each cell scale; leave the fastest set."""
+    times = {}
+    for c in candidates:
+        ctx.set_tuning(cell_scale=c)
+        run()                                   # records the graph for this cell size
+        times[c] = min(run() for _ in range(repeats))
+    best = min(times, key=times.get)
+    ctx.set_tuning(cell_scale=best)
+    return {"cell_scale": best, "ms": {str(k): v for k, v in times.items()}}
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, steps: int = 4,
+              candidates=CELL_SCALES, cache: Cache | None = None, key: str | None = None) -> dict:
+    """Tune on `steps` single-mesh steps from the state (x, v), which is restored."""
+    import torch
+    if cache is not None and key is not None:
+        hit = cache.get(key)
+        if hit is not None:
+            ctx.set_tuning(cell_scale=hit["cell_scale"])
+            return dict(hit, cached=True)
+    x0, v0 = x.clone(), v.clone()
+
+    def run():
+        for _ in range(4):
+            x.copy_(x0)
+            v.copy_(v0)
+            e0, e1 = _events()
+            e0.record()
+            for _ in range(steps):
+                ccfr.xpbd_step(ctx, mesh, x, v, sp)
+            e1.record()
+            code, info = ctx.sync_status(reset=True)
+            if code == 0:
+                return e0.elapsed_time(e1)
+            if code != -2:
+                raise ccfr.CcfrError(code, "tuning run")
+            ctx.grow(info)                      # lists too small: grow and time again
+        raise ccfr.CcfrError(-2, "tuning run")
+
+    out = tune(ctx, run, candidates)
+    x.copy_(x0)
+    v.copy_(v0)
+    torch.cuda.synchronize()
+    if cache is not None and key is not None:
+        cache.put(key, out)
+    return dict(out, cached=False)
+
+
+def tune_batch(ctx: ccfr.Context, batch: ccfr.Batch, candidates=CELL_SCALES) -> dict:
+    """Tune on one step of the resident batch; every trial is rolled back."""
+    def run():
+        for _ in range(4):
+            e0, e1 = _events()
+            e0.record()
+            batch.step()
+            e1.record()
+            code, info = ctx.sync_status(reset=True)
+            batch.rollback()
+            if code == 0:
+                return e0.elapsed_time(e1)
+            if code != -2:
+                raise ccfr.CcfrError(code, "tuning run")
+            ctx.grow(info)
+        raise ccfr.CcfrError(-2, "tuning run")
+
+    return tune(ctx, run, candidates)

@@ -51,6 +51,10 @@ class StepParams(C.Structure):
                 ("collision", Params)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("cell_scale", C.c_float), ("reserved", C.c_int32 * 3)]
+
+
 class StatusInfo(C.Structure):
     _fields_ = [("status_bits", C.c_uint32), ("last_counts", C.c_int32 * 3), ("last_contacts", C.c_int32),
                 ("last_halfspaces", C.c_int32), ("need", C.c_int64 * 6), ("totals", C.c_int64 * 10)]
@@ -59,7 +63,7 @@ class StatusInfo(C.Structure):
 EXPORTS = ["ccfr_status_string", "ccfr_create", "ccfr_destroy", "ccfr_mesh_create", "ccfr_mesh_destroy",
            "ccfr_mesh_edges", "ccfr_mesh_inv_mass_dev", "ccfr_reserve", "ccfr_build_candidates",
            "ccfr_build_regions", "ccfr_project_displacements", "ccfr_xpbd_step", "ccfr_sync_status",
-           "ccfr_profile_enable", "ccfr_profile_read",
+           "ccfr_profile_enable", "ccfr_profile_read", "ccfr_set_tuning", "ccfr_get_tuning",
            "ccfr_batch_create", "ccfr_batch_destroy", "ccfr_batch_footprint", "ccfr_batch_add",
            "ccfr_batch_remove", "ccfr_batch_step", "ccfr_batch_rollback", "ccfr_batch_read", "ccfr_batch_stats"]
 
@@ -95,6 +99,8 @@ def load():
     lib.ccfr_sync_status.argtypes = [vp, vp, C.POINTER(StatusInfo), C.c_int]
     lib.ccfr_profile_enable.argtypes = [vp, C.c_int]
     lib.ccfr_profile_read.argtypes = [vp, vp, vp, vp]
+    lib.ccfr_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    lib.ccfr_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
     lib.ccfr_batch_create.argtypes = [vp, i32, i64, i64, i64, C.POINTER(vp)]
     lib.ccfr_batch_destroy.argtypes = [vp]
     lib.ccfr_batch_destroy.restype = None
@@ -184,6 +190,21 @@ class Context:
             "totals": list(info.totals),
         }
 
+
+    def grow(self, info, factor=1.5):
+        """Reserve the list sizes a CAPACITY status reported (info from sync_status)."""
+        nd = info["need"]
+        self.reserve(vf=int(nd[0] * factor) + 1024, ee=int(nd[1] * factor) + 1024, vv=int(nd[2] * factor) + 1024,
+                     contacts=int(nd[3] * factor) + 1024, halfspaces=int(nd[4] * factor) + 1024)
+
+    def set_tuning(self, cell_scale=1.0):
+        t = Tuning(float(cell_scale))
+        _check(self.lib.ccfr_set_tuning(self.h, C.byref(t)), "ccfr_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(self.lib.ccfr_get_tuning(self.h, C.byref(t)), "ccfr_get_tuning")
+        return {"cell_scale": float(t.cell_scale)}
 
     def profile_enable(self, on=True):
         _check(self.lib.ccfr_profile_enable(self.h, int(bool(on))), "ccfr_profile_enable")

@@ -26,18 +26,21 @@ void drop_graph(ccfr_ctx* ctx) {
     ctx->graph = StepGraph{};
 }
 
-// Grows the grid for `targets` binned primitives.
+// Bucket table size (log2, per kind) for `entries` binned entries.
+int grid_log2s(long long entries) { return std::max(6, ceil_log2(std::max(64LL, entries))); }
+
+// Grows the grid for `targets` binned entries (primitives and vertices).
 int ensure_grid(ccfr_ctx* ctx, long long targets) {
-    const int log2s = std::max(6, ceil_log2(std::max(64LL, targets)));
+    const int log2s = grid_log2s(targets);
     if (log2s > ctx->log2s) {
         dev_free(ctx->cnt);
         dev_free(ctx->start);
-        const long long S3 = 3LL << log2s;
-        HIP_ALLOC(dev_alloc(&ctx->cnt, S3));
-        HIP_ALLOC(dev_alloc(&ctx->start, S3 + 1));
-        HIP_OK(hipMemset(ctx->cnt, 0, sizeof(int32_t) * (size_t)S3));
+        const long long S4 = 4LL << log2s;
+        HIP_ALLOC(dev_alloc(&ctx->cnt, S4));
+        HIP_ALLOC(dev_alloc(&ctx->start, S4 + 1));
+        HIP_OK(hipMemset(ctx->cnt, 0, sizeof(int32_t) * (size_t)S4));
         ctx->log2s = log2s;
-        const long long ntmp = (S3 + 1023) / 1024 + 2;
+        const long long ntmp = (S4 + 1023) / 1024 + 2;
         if (ntmp > ctx->cap_scan_tmp) {
             dev_free(ctx->scan_tmp);
             HIP_ALLOC(dev_alloc(&ctx->scan_tmp, ntmp));
@@ -147,7 +150,7 @@ int ensure_step(ccfr_ctx* ctx, long long n_verts) {
 // observed needs (ccfr_reserve).
 int ensure_sizes(ccfr_ctx* ctx, long long n_verts, long long n_tris, long long n_edges, long long n_free,
                  int n_meshes) {
-    int rc = ensure_grid(ctx, n_tris + n_edges + n_free);
+    int rc = ensure_grid(ctx, n_tris + n_edges + n_free + n_verts);
     if (rc) return rc;
     rc = ensure_meshes(ctx, n_meshes);
     if (rc) return rc;
@@ -172,7 +175,7 @@ bool step_params_ok(const ccfr_step_params* sp) {
 
 // Per-mesh device parameters: the box pad (one FP32 rounding of an FP64 sum) and
 // a grid cell large enough that typical primitives span at most two cells.
-MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt) {
+MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell_scale) {
     MeshParams m{};
     m.r = p->r;
     m.xi = p->xi;
@@ -180,7 +183,8 @@ MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt) {
     m.two_r = 2.0f * p->r;
     m.eps_retract = p->eps_retract;
     m.eps_plesnik = p->eps_plesnik;
-    const double h = std::max(2.02 * (double)m.pad, 1.2 * (double)typ_len + 2.0 * (double)m.pad);
+    const double h = std::max(2.02 * (double)m.pad,
+                              (double)cell_scale * (1.2 * (double)typ_len + 2.0 * (double)m.pad));
     m.h = (float)h;
     m.inv_h = (float)(1.0 / h);
     m.max_passes = p->max_passes;
@@ -205,13 +209,15 @@ Scene make_scene(const ccfr_mesh* m, const float* x, const ccfr_params* p) {
     sc.is_free = m->is_free_d;
     sc.prm.table = nullptr;
     sc.prm.vmesh = nullptr;
-    sc.prm.one = mesh_params(p, m->typ_len, 0);
+    sc.prm.one = mesh_params(p, m->typ_len, 0, m->ctx->cell_scale);
     return sc;
 }
 
-GridWs grid_ws(ccfr_ctx* ctx, int n_meshes) {
+// The table is sized for this build's entries (not the allocation), so the
+// scan and the bucket range follow the meshes actually present.
+GridWs grid_ws(ccfr_ctx* ctx, const Scene& sc, int n_meshes) {
     GridWs g{};
-    g.log2s = ctx->log2s;
+    g.log2s = std::min(ctx->log2s, grid_log2s((long long)sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts));
     g.cnt = ctx->cnt;
     g.start = ctx->start;
     g.rank = ctx->rank;
@@ -236,11 +242,11 @@ struct Marks {
 
 // broad phase into the context's lists
 void enqueue_candidates(ccfr_ctx* ctx, const Scene& sc, int n_meshes, hipStream_t s, const Marks& mk) {
-    GridWs g = grid_ws(ctx, n_meshes);
+    GridWs g = grid_ws(ctx, sc, n_meshes);
     mk.mark(0, 0);
     launch_reset_build(ctx->counters_d, g.level_mask, g.n_meshes, s);
     launch_grid_count(sc, g, ctx->counters_d, s);
-    launch_scan(g.cnt, g.start, g.cnt, 3 << g.log2s, g.scan_tmp, s);
+    launch_scan(g.cnt, g.start, g.cnt, 4 << g.log2s, g.scan_tmp, s);
     launch_grid_scatter(sc, g, s);
     mk.mark(0, 1);
     PairLists pl{ctx->vf, ctx->ee, ctx->vv, ctx->cap_vf, ctx->cap_ee, ctx->cap_vv};
@@ -692,7 +698,7 @@ int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const
     pa.slow_list = ctx->slow_list;
     pa.prm.table = nullptr;
     pa.prm.vmesh = nullptr;
-    pa.prm.one = mesh_params(params, 0.f, 0);
+    pa.prm.one = mesh_params(params, 0.f, 0, 1.0f);
     launch_project(pa, ctx->counters_d, (hipStream_t)stream);
     HIP_OK(hipGetLastError());
     return CCFR_OK;
@@ -749,6 +755,25 @@ int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, 
     }
     if (h.status & ST_NONFINITE) return CCFR_ERR_NONFINITE;
     if (h.status & (ST_VF | ST_EE | ST_VV | ST_HS | ST_LARGE | ST_CONTACTS)) return CCFR_ERR_CAPACITY;
+    return CCFR_OK;
+}
+
+int ccfr_set_tuning(ccfr_ctx* ctx, const ccfr_tuning* t) {
+    if (!ctx || !t || !std::isfinite(t->cell_scale) || t->cell_scale < 0.25f || t->cell_scale > 4.0f)
+        return CCFR_ERR_INVALID_ARG;
+    if (t->cell_scale != ctx->cell_scale) {
+        ctx->cell_scale = t->cell_scale;
+        ctx->tune_generation++;
+        ctx->generation++;          // recorded graphs carry the old cell size
+        drop_graph(ctx);
+    }
+    return CCFR_OK;
+}
+
+int ccfr_get_tuning(const ccfr_ctx* ctx, ccfr_tuning* t) {
+    if (!ctx || !t) return CCFR_ERR_INVALID_ARG;
+    *t = ccfr_tuning{};
+    t->cell_scale = ctx->cell_scale;
     return CCFR_OK;
 }
 

@@ -123,6 +123,9 @@ struct ccfr_batch {
     float* lambda = nullptr;
     MeshParams* table_d = nullptr;
     std::vector<MeshParams> table_h;
+    std::vector<ccfr_params> coll_h;      // per slot: collision parameters
+    std::vector<float> typ_h;             // per slot: edge length the cell is sized for
+    long long tune_generation = -1;
     Move* moves_d = nullptr;
     int2* segs_d = nullptr;
     long long cap_segs = 0;
@@ -156,6 +159,20 @@ int alloc_pool(Pool& p, long long nv, long long nt, long long ne) {
     HIP_ALLOC(dev_alloc(&p.edges_sorted, 2 * ne));
     HIP_ALLOC(dev_alloc(&p.rest_sorted, ne));
     HIP_ALLOC(dev_alloc(&p.free_list, nv));
+    return CCFR_OK;
+}
+
+int slot_salt(int slot) { return (int)(0x9E3779B1u * (uint32_t)(slot + 1)); }
+
+// Parameters of every resident slot again, after a tuning change.
+int refresh_table(ccfr_batch* b, hipStream_t s) {
+    for (int k = 0; k < b->max_slots; ++k)
+        if (b->slot_busy[k]) b->table_h[k] = mesh_params(&b->coll_h[k], b->typ_h[k], slot_salt(k), b->ctx->cell_scale);
+    HIP_OK(hipMemcpyAsync(b->table_d, b->table_h.data(), sizeof(MeshParams) * b->table_h.size(),
+                          hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    b->tune_generation = b->ctx->tune_generation;
+    b->dirty = true;
     return CCFR_OK;
 }
 
@@ -284,12 +301,13 @@ int64_t ccfr_batch_footprint(int32_t n_verts, int32_t n_tris, int32_t n_edges) {
     // edge, rest length); plus lambda (4 B per edge)
     long long bytes = 2 * (35 * N + 12 * T + 20 * E) + 4 * E;
     // workspace at the default list sizes: substep buffers (36 B per vertex),
-    // region CSR (12), grid entry + rank + key (40 per binned primitive) and at
-    // most 6 cells of 8 B each per primitive, 8 B per candidate pair slot,
+    // region CSR (12), grid entry + rank + key (40 per binned primitive or
+    // vertex) and at most 8 bucket counters and 8 offsets (4 B each) per entry,
+    // 8 B per candidate pair slot,
     // 32 B per contact slot (half the pair slots) and 44 B per half-space slot
     // (twice the pair slots: record, sort key, sort index)
     const long long pairs = 8 * N + 8 * E + 16 * F;
-    bytes += 48 * N + 88 * (T + E + F) + 8 * pairs + 32 * (pairs / 2) + 44 * (2 * pairs);
+    bytes += 48 * N + 104 * (T + E + F + N) + 8 * pairs + 32 * (pairs / 2) + 44 * (2 * pairs);
     return bytes;
 }
 
@@ -309,6 +327,9 @@ int ccfr_batch_create(ccfr_ctx* ctx, int32_t max_slots, int64_t max_verts, int64
     b->max_edges = max_edges;
     b->slot_busy.assign(max_slots, 0);
     b->table_h.assign(max_slots, MeshParams{});
+    b->coll_h.assign(max_slots, ccfr_params{});
+    b->typ_h.assign(max_slots, 0.f);
+    b->tune_generation = ctx->tune_generation;
     int rc = CCFR_OK;
     for (int k = 0; k < 2 && rc == CCFR_OK; ++k) rc = alloc_pool(b->pool[k], max_verts, max_tris, max_edges);
     if (rc == CCFR_OK && (dev_alloc(&b->lambda, std::max<long long>(max_edges, 1)) != hipSuccess ||
@@ -316,7 +337,10 @@ int ccfr_batch_create(ccfr_ctx* ctx, int32_t max_slots, int64_t max_verts, int64
                           dev_alloc(&b->moves_d, max_slots) != hipSuccess))
         rc = CCFR_ERR_NO_MEMORY;
     if (rc == CCFR_OK) rc = ensure_step(ctx, max_verts);
-    if (rc == CCFR_OK) rc = ensure_sizes(ctx, max_verts, max_tris, max_edges, max_verts, max_slots);
+    // the grid holds every primitive and vertex the pool can hold (any vertex
+    // may be a free particle); list sizes start from the meshes' topology
+    if (rc == CCFR_OK) rc = ensure_grid(ctx, max_tris + max_edges + 2 * max_verts);
+    if (rc == CCFR_OK) rc = ensure_sizes(ctx, max_verts, max_tris, max_edges, 0, max_slots);
     if (rc != CCFR_OK) {
         ccfr_batch_destroy(b);
         return rc;
@@ -394,7 +418,9 @@ int ccfr_batch_add(ccfr_batch* b, int32_t n_verts, const int32_t* tris, int32_t 
                            (long long)h.n_verts, (uint16_t)sl);
     // a mesh's stretch constraints are off when it has no rest shape
     if (!h.has_stretch) m.color_begin.assign(1, 0);
-    b->table_h[sl] = mesh_params(&sp->collision, h.typ_len, (int)(0x9E3779B1u * (uint32_t)(sl + 1)));
+    b->coll_h[sl] = sp->collision;
+    b->typ_h[sl] = h.typ_len;
+    b->table_h[sl] = mesh_params(&sp->collision, h.typ_len, slot_salt(sl), b->ctx->cell_scale);
     HIP_OK(hipMemcpyAsync(b->table_d + sl, &b->table_h[sl], sizeof(MeshParams), hipMemcpyHostToDevice, s));
     // pageable sources: the copies must finish before the host vectors go away
     HIP_OK(hipStreamSynchronize(s));
@@ -435,9 +461,15 @@ int ccfr_batch_step(ccfr_batch* b, ccfr_stream stream) {
     const long long gen0 = ctx->generation;
     rc = ensure_step(ctx, b->max_verts);
     if (rc) return rc;
-    rc = ensure_sizes(ctx, b->max_verts, b->max_tris, b->max_edges, b->max_verts, b->max_slots);
+    rc = ensure_grid(ctx, b->max_tris + b->max_edges + 2 * b->max_verts);
+    if (rc) return rc;
+    rc = ensure_sizes(ctx, b->max_verts, b->max_tris, b->max_edges, 0, b->max_slots);
     if (rc) return rc;
     if (ctx->generation != gen0) drop_graph(ctx);
+    if (b->tune_generation != ctx->tune_generation) {
+        rc = refresh_table(b, s);
+        if (rc) return rc;
+    }
     if (b->dirty) {
         rc = rebuild_plan(b, s);
         if (rc) return rc;

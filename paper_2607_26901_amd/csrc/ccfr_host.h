@@ -90,6 +90,8 @@ struct ccfr_ctx {
     long long generation = 0;   // bumped whenever a workspace buffer moves
     bool use_graphs = true;
     bool narrow_fp32 = false;   // narrow-phase arithmetic in FP32 (measurement option)
+    float cell_scale = 1.0f;    // grid cell size relative to the default
+    long long tune_generation = 0;
 
     // grid
     int log2s = 0;
@@ -183,7 +185,8 @@ int ensure_sizes(ccfr_ctx* ctx, long long n_verts, long long n_tris, long long n
                  int n_meshes);
 bool params_ok(const ccfr_params* p);
 bool step_params_ok(const ccfr_step_params* sp);
-MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt);
+MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell_scale);
+int ensure_grid(ccfr_ctx* ctx, long long targets);
 int ensure_prof_events(ccfr_ctx* ctx, int iters);
 void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s);
 // Records the plan as a graph into *g (replacing it) and launches it on s.

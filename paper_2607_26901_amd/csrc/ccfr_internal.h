@@ -117,11 +117,11 @@ struct Scene {
 
 struct GridWs {
     int log2s;                  // table size S = 2^log2s buckets per kind
-    int32_t* cnt;               // [3 S] counts, zero between builds
-    int32_t* start;             // [3 S + 1] exclusive prefix
-    int32_t* rank;              // [T + E + F] rank of each target inside its bucket
-    int32_t* key;               // [T + E + F] kind * S + bucket, -1 = large / skipped
-    GridEntry* entries;         // [T + E + F] sorted targets
+    int32_t* cnt;               // [4 S] counts, zero between builds
+    int32_t* start;             // [4 S + 1] exclusive prefix
+    int32_t* rank;              // [T + E + F + N] rank of each entry inside its bucket
+    int32_t* key;               // [T + E + F + N] (kind - 1) * S + bucket, -1 = not binned
+    GridEntry* entries;         // [T + E + F + N] sorted: triangles, edges, particles, vertices
     uint32_t* level_mask;       // [n_meshes] grid levels occupied by each mesh
     int32_t n_meshes;
     int32_t* scan_tmp;          // block partials of the scan

@@ -20,15 +20,21 @@
 // (a 4 m ground quad under 8 mm cloth triangles, large obstacles under fine
 // hair) therefore cost a few extra buckets, not a brute-force list.
 //
+// Vertices are binned too, in a fourth table, only to order the queries: the
+// pair kernel takes vertex and edge queries in bucket order, in which the 64
+// buckets of a 4 x 4 x 4 block of cells are consecutive, so the lanes of a
+// wavefront (and the workgroups of one XCD, see xcd_block) read the same
+// neighbouring buckets and the entries come from L1 / L2 instead of HBM.
+//
 // Pipeline per build:
 //   reset        counters and the per-mesh level masks
-//   grid_count   one thread per target: box, level, bucket, rank inside the
-//                bucket (atomic)
+//   grid_count   one thread per target and per vertex: box, level, bucket, rank
+//                inside the bucket (atomic)
 //   scan         exclusive prefix of the per-(kind, bucket) counts
-//   grid_scatter targets to their sorted slots (32 B entries)
-//   pairs        one thread per query (vertex, then edge); found pairs are
-//                staged per wavefront in LDS and written out in blocks of up to
-//                128 with one atomic each
+//   grid_scatter entries to their sorted slots (32 B each)
+//   pairs        one thread per query (vertex entries, then edge entries, in
+//                sorted order); found pairs are staged per wavefront in LDS and
+//                written out in blocks of up to 128 with one atomic each
 #include "ccfr_internal.h"
 
 #include <algorithm>
@@ -39,6 +45,15 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMaxLevel = 24;
+constexpr int KIND_VX = 4;     // vertex entries (query order only)
+
+// Workgroup b runs on XCD b % 8; give each XCD a contiguous run of logical
+// blocks so that spatially adjacent queries share one L2.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+    const int per = n >> 3, rem = n & 7;
+    const int x = b & 7, k = b >> 3;
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + k;
+}
 
 __device__ __forceinline__ void load3(const float* x, int v, float o[3]) {
     o[0] = x[3 * v + 0];
@@ -56,9 +71,9 @@ __device__ __forceinline__ bool overlap(const float alo[3], const float ahi[3], 
            alo[2] <= bhi[2] && blo[2] <= ahi[2];
 }
 
-// The target primitive behind grid slot t: triangles, then edges, then free particles.
+// The primitive behind grid slot t: triangles, edges, free particles, then vertices.
 struct Target {
-    int kind;      // KIND_VF (triangle), KIND_EE (edge), KIND_VV (particle)
+    int kind;      // KIND_VF (triangle), KIND_EE (edge), KIND_VV (particle), KIND_VX (vertex)
     int idx;
     int nv;
     int v[3];
@@ -73,9 +88,13 @@ __device__ __forceinline__ Target target_of(const Scene& sc, int t) {
         const int e = t - sc.n_tris;
         g.kind = KIND_EE; g.idx = e; g.nv = 2;
         g.v[0] = sc.edges[2 * e]; g.v[1] = sc.edges[2 * e + 1]; g.v[2] = g.v[1];
-    } else {
+    } else if (t < sc.n_tris + sc.n_edges + sc.n_free) {
         const int p = sc.free_list[t - sc.n_tris - sc.n_edges];
         g.kind = KIND_VV; g.idx = p; g.nv = 1;
+        g.v[0] = g.v[1] = g.v[2] = p;
+    } else {
+        const int p = t - sc.n_tris - sc.n_edges - sc.n_free;
+        g.kind = KIND_VX; g.idx = p; g.nv = 1;
         g.v[0] = g.v[1] = g.v[2] = p;
     }
     return g;
@@ -118,6 +137,18 @@ __device__ __forceinline__ int box_level(const float lo[3], const float hi[3], f
         if (fits) return l;
     }
     return -1;
+}
+
+// Order of cell c against the query's own cell o (the cell its entry is binned
+// in): -1, 0, +1, lexicographic in (z, y, x).  Two entries of one level whose
+// boxes overlap each lie in the other's query stencil, so the pair is taken
+// only by the query whose own cell comes first, or, in one cell, by the lower
+// index: every such pair is tested once instead of twice.
+__device__ __forceinline__ int cell_order(int cx, int cy, int cz, const int o[3]) {
+    if (cz != o[2]) return cz < o[2] ? -1 : 1;
+    if (cy != o[1]) return cy < o[1] ? -1 : 1;
+    if (cx != o[0]) return cx < o[0] ? -1 : 1;
+    return 0;
 }
 
 __device__ __forceinline__ int level_salt(int mesh_salt, int level) {
@@ -164,10 +195,21 @@ __global__ void k_reset_build(DevCounters* c, uint32_t* level_mask, int n_meshes
         level_mask[m] = 0u;
 }
 
+// Level and lower-corner cell of an entry (vertex entries: level 0, their box
+// is narrower than a cell); -1 if it is not binned.
+__device__ __forceinline__ int entry_level(const Target& tg, const float lo[3], const float hi[3], float inv_h,
+                                           int clo[3]) {
+    if (tg.kind == KIND_VX) {
+        for (int k = 0; k < 3; ++k) clo[k] = cell_coord(lo[k], inv_h);
+        return 0;
+    }
+    return box_level(lo, hi, inv_h, clo);
+}
+
 __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCounters* c) {
-    const int n_targets = sc.n_tris + sc.n_edges + sc.n_free;
+    const int n_all = sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts;
     const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= n_targets) return;
+    if (t >= n_all) return;
     const Target tg = target_of(sc, t);
     const int mesh = sc.prm.mesh_of(tg.v[0]);
     const MeshParams P = sc.prm.get(mesh);
@@ -178,11 +220,11 @@ __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCo
     if (!target_box(sc, tg, P.pad, lo, hi, &st)) {
         atomicOr(&c->status, ST_NONFINITE);
     } else {
-        level = box_level(lo, hi, P.inv_h, clo);
+        level = entry_level(tg, lo, hi, P.inv_h, clo);
         if (level < 0) atomicOr(&c->status, ST_LARGE);   // a box wider than h 2^24: not binned
     }
     // every lane still in the kernel takes part in the wave-wide OR
-    mark_level(g.level_mask, mesh, level < 0 ? 0u : (1u << level));
+    mark_level(g.level_mask, mesh, (level < 0 || tg.kind == KIND_VX) ? 0u : (1u << level));
     if (level < 0) {
         g.key[t] = -1;
         return;
@@ -194,9 +236,9 @@ __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCo
 }
 
 __global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g) {
-    const int n_targets = sc.n_tris + sc.n_edges + sc.n_free;
+    const int n_all = sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts;
     const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= n_targets) return;
+    if (t >= n_all) return;
     const int key = g.key[t];
     if (key < 0) return;
     const Target tg = target_of(sc, t);
@@ -206,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g) {
     bool st;
     target_box(sc, tg, P.pad, lo, hi, &st);
     int clo[3];
-    const int level = box_level(lo, hi, P.inv_h, clo);
+    const int level = entry_level(tg, lo, hi, P.inv_h, clo);
     GridEntry e;
     for (int k = 0; k < 3; ++k) { e.lo[k] = lo[k]; e.hi[k] = hi[k]; }
     e.idx = tg.idx;
@@ -281,24 +323,24 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
         st.fill[0] = st.fill[1] = st.fill[2] = 0;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const int q = blockIdx.x * kBlock + threadIdx.x;
-    const int n_q = sc.n_verts + sc.n_edges;
+    const int q = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int S = 1 << g.log2s;
-    if (q < sc.n_verts) {
+    const int v0 = g.start[3 * S], nv_q = g.start[4 * S] - v0;       // binned vertices
+    const int e0 = g.start[S], ne_q = g.start[2 * S] - e0;           // binned edges
+    if (q < nv_q) {
         // ---- vertex query: vertex-face pairs, and particle pairs for free particles
-        const int v = q;
-        const int mesh = sc.prm.mesh_of(v);
+        const GridEntry me = g.entries[v0 + q];
+        const int v = me.idx;
+        const int mesh = (int)(me.flags >> 8);
         const MeshParams P = sc.prm.get(mesh);
-        float p[3];
-        load3(sc.x, v, p);
         float lo[3], hi[3];
         for (int k = 0; k < 3; ++k) {
-            lo[k] = __fsub_rn(p[k], P.pad);
-            hi[k] = __fadd_rn(p[k], P.pad);
+            lo[k] = me.lo[k];
+            hi[k] = me.hi[k];
         }
-        const bool q_static = sc.inv_mass[v] == 0.0f;
+        const bool q_static = (me.flags & 1u) != 0u;
         const bool q_free = sc.is_free[v] != 0;
-        uint32_t levels = finite3(p) ? g.level_mask[mesh] : 0u;
+        uint32_t levels = g.level_mask[mesh];
         while (levels) {
             const int l = __ffs((int)levels) - 1;
             levels &= levels - 1u;
@@ -323,36 +365,36 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
                             }
                             stage_pair(st, 0, pl.vf, &c->n_vf, pl.cap_vf, v, e.idx, hit);
                         }
-                        if (q_free && l == 0) {
+                        const int ord = q_free && l == 0 ? cell_order(cx, cy, cz, clo) : -1;
+                        if (ord >= 0) {
+                            // particles: half shell, as for edges of one level
                             const int k0 = 2 * S + (int)b;
                             const int u0 = g.start[k0], u1 = g.start[k0 + 1];
                             for (int i = u0; i < u1; ++i) {
                                 const GridEntry e = g.entries[i];
-                                const bool hit = e.idx > v && entry_ok(e, mesh, 0, q_static) &&
+                                const bool hit = (ord > 0 || e.idx > v) && entry_ok(e, mesh, 0, q_static) &&
                                                  overlap(lo, hi, e.lo, e.hi);
-                                stage_pair(st, 2, pl.vv, &c->n_vv, pl.cap_vv, v, e.idx, hit);
+                                stage_pair(st, 2, pl.vv, &c->n_vv, pl.cap_vv, min(v, e.idx), max(v, e.idx), hit);
                             }
                         }
                     }
         }
-    } else if (q < n_q) {
+    } else if (q >= sc.n_verts && q - sc.n_verts < ne_q) {
         // ---- edge query: edge-edge pairs
-        const int eq = q - sc.n_verts;
+        const GridEntry me = g.entries[e0 + (q - sc.n_verts)];
+        const int eq = me.idx;
         const int a = sc.edges[2 * eq], bb = sc.edges[2 * eq + 1];
-        const int mesh = sc.prm.mesh_of(a);
+        const int mesh = (int)(me.flags >> 8);
+        const int lq = (int)((me.flags >> 1) & 31u);
         const MeshParams P = sc.prm.get(mesh);
-        float pa[3], pb[3];
-        load3(sc.x, a, pa);
-        load3(sc.x, bb, pb);
         float lo[3], hi[3];
         for (int k = 0; k < 3; ++k) {
-            lo[k] = __fsub_rn(fminf(pa[k], pb[k]), P.pad);
-            hi[k] = __fadd_rn(fmaxf(pa[k], pb[k]), P.pad);
+            lo[k] = me.lo[k];
+            hi[k] = me.hi[k];
         }
         int clo[3], chi[3];
-        const int lq = (finite3(pa) && finite3(pb)) ? box_level(lo, hi, P.inv_h, clo) : -1;
-        const bool q_static = sc.inv_mass[a] == 0.0f && sc.inv_mass[bb] == 0.0f;
-        uint32_t levels = lq < 0 ? 0u : (g.level_mask[mesh] & ~((1u << lq) - 1u));
+        const bool q_static = (me.flags & 1u) != 0u;
+        uint32_t levels = g.level_mask[mesh] & ~((1u << lq) - 1u);
         while (levels) {
             const int l = __ffs((int)levels) - 1;
             levels &= levels - 1u;
@@ -365,11 +407,14 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
             for (int cz = clo[2] - 1; cz <= chi[2]; ++cz)
                 for (int cy = clo[1] - 1; cy <= chi[1]; ++cy)
                     for (int cx = clo[0] - 1; cx <= chi[0]; ++cx) {
+                        // same level: half shell (see cell_order)
+                        const int ord = l == lq ? cell_order(cx, cy, cz, clo) : 1;
+                        if (ord < 0) continue;
                         const int k0 = S + (int)cell_bucket(cx, cy, cz, salt, g.log2s);
                         const int s0 = g.start[k0], s1 = g.start[k0 + 1];
                         for (int i = s0; i < s1; ++i) {
                             const GridEntry e = g.entries[i];
-                            bool hit = (l > lq || e.idx > eq) && entry_ok(e, mesh, l, q_static) &&
+                            bool hit = (ord > 0 || e.idx > eq) && entry_ok(e, mesh, l, q_static) &&
                                        overlap(lo, hi, e.lo, e.hi);
                             if (hit) {
                                 const int c0 = sc.edges[2 * e.idx], c1 = sc.edges[2 * e.idx + 1];
@@ -411,13 +456,13 @@ void launch_reset_build(DevCounters* c, uint32_t* level_mask, int n_meshes, hipS
 }
 
 void launch_grid_count(const Scene& sc, GridWs& g, DevCounters* c, hipStream_t s) {
-    const int n = sc.n_tris + sc.n_edges + sc.n_free;
+    const int n = sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts;
     if (n == 0) return;
     hipLaunchKernelGGL(k_grid_count, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, g, c);
 }
 
 void launch_grid_scatter(const Scene& sc, GridWs& g, hipStream_t s) {
-    const int n = sc.n_tris + sc.n_edges + sc.n_free;
+    const int n = sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts;
     if (n == 0) return;
     hipLaunchKernelGGL(k_grid_scatter, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, g);
 }

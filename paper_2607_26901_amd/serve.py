@@ -93,9 +93,7 @@ def footprint(scene) -> int:
 
 
 def _grow(ctx, info):
-    nd = info["need"]
-    ctx.reserve(vf=int(nd[0] * 1.5) + 1024, ee=int(nd[1] * 1.5) + 1024, vv=int(nd[2] * 1.5) + 1024,
-                contacts=int(nd[3] * 1.5) + 1024, halfspaces=int(nd[4] * 1.5) + 1024)
+    ctx.grow(info)
 
 
 class _GpuTimer:

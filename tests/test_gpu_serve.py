@@ -17,13 +17,13 @@ def test_served_stream_equals_sequential():
     assert torch.cuda.is_available()
     import oracle
     from paper_2607_26901_amd import ccfr, serve
-    reqs = S.c4_requests(n_requests=8, rate=2000.0, lo=6, hi=28, steps=7)
+    reqs = S.c4_requests(n_requests=8, rate=1e5, lo=6, hi=28, steps=7)
     jobs = []
     for r in reqs:
         sc = r.scene
         v = sc.v.copy()
         v[: sc.meta["n_cloth"], 2] = -1.5          # reach the sphere within the run
-        jobs.append(serve.Job(r.id, r.arrival, sc.with_state(v=v), sc.step.steps))
+        jobs.append(serve.Job(r.rid, r.arrival, sc.with_state(v=v), sc.step.steps))
     fps = [serve.footprint(j.scene) for j in jobs]
     budget = int(0.45 * sum(fps))
     ctx = ccfr.Context(0)

@@ -1,0 +1,77 @@
+"""The grid cell size changes speed only: candidates stay bit-exact with the
+oracle and whole substeps give the same state for every cell scale."""
+import numpy as np
+import pytest
+
+from paper_2607_26901_amd import scenes as S
+from tests import gpu_helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import oracle
+    from paper_2607_26901_amd import ccfr
+    return ccfr.Context(0), ccfr, oracle, torch
+
+
+SCENES = {
+    "two_layers": lambda: S.two_layers(n=14, seed=8, gap=2.5e-3, shift=(0.003, 0.001)),
+    "particles": lambda: S.particles_in_box(nx=5, ny=5, nz=6, seed=5),
+    "strands": lambda: S.strand_bundle(nx=4, ny=4, seg=20, seed=9),
+}
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+@pytest.mark.parametrize("scale", [0.25, 0.5, 2.0, 4.0])
+def test_candidates_exact_at_any_cell_size(env, scale, name):
+    ctx, ccfr, oracle, torch = env
+    sc = SCENES[name]()
+    ctx.set_tuning(cell_scale=scale)
+    try:
+        mesh = ccfr.mesh_from_scene(ctx, sc)
+        x = torch.from_numpy(sc.x.copy()).cuda()
+        _, got, _ = H.gpu_candidates(ctx, mesh, x, ccfr.make_params(sc.params))
+        want = oracle.candidates(oracle.Mesh(sc), sc.params)
+        for k in ("vf", "ee", "vv"):
+            assert np.array_equal(H.sorted_pairs(got[k]), H.sorted_pairs(want[k])), (k, scale)
+    finally:
+        ctx.set_tuning(cell_scale=1.0)
+
+
+def test_steps_identical_across_cell_sizes(env):
+    ctx, ccfr, oracle, torch = env
+    sc = S.c0()
+    sp = ccfr.make_step_params(sc.step, sc.params)
+    outs = []
+    for scale in (1.0, 0.5, 1.7):
+        ctx.set_tuning(cell_scale=scale)
+        mesh = ccfr.mesh_from_scene(ctx, sc)
+        x = torch.from_numpy(sc.x.copy()).cuda()
+        v = torch.from_numpy(sc.v.copy()).cuda()
+        for _ in range(sc.step.steps):
+            ccfr.xpbd_step(ctx, mesh, x, v, sp)
+        torch.cuda.synchronize()
+        code, info = ctx.sync_status(reset=True)
+        assert code == 0, info
+        outs.append(x.cpu().numpy())
+    ctx.set_tuning(cell_scale=1.0)
+    for o in outs[1:]:
+        assert np.abs(o.astype(np.float64) - outs[0]).max() <= H.step_tol(sc, sc.step.iters)
+
+
+def test_autotuner_picks_a_candidate_and_restores_state(env):
+    ctx, ccfr, oracle, torch = env
+    from paper_2607_26901_amd import autotune
+    sc = S.c0()
+    mesh = ccfr.mesh_from_scene(ctx, sc)
+    x = torch.from_numpy(sc.x.copy()).cuda()
+    v = torch.from_numpy(sc.v.copy()).cuda()
+    out = autotune.tune_mesh(ctx, mesh, x, v, ccfr.make_step_params(sc.step, sc.params), steps=2,
+                             candidates=(0.6, 1.0))
+    assert out["cell_scale"] in (0.6, 1.0) and ctx.get_tuning()["cell_scale"] == out["cell_scale"]
+    assert np.array_equal(x.cpu().numpy(), sc.x) and np.array_equal(v.cpu().numpy(), sc.v)
+    ctx.set_tuning(cell_scale=1.0)

@@ -70,8 +70,8 @@ class FakeCtx:
             return -2, {"need": [10, 20, 30, 40, 50, 0]}
         return 0, {"need": [0] * 6}
 
-    def reserve(self, **kw):
-        self.reserved.append(kw)
+    def grow(self, info):
+        self.reserved.append({"vf": int(info["need"][0] * 1.5) + 1024})
 
 
 def job(i, arrival, n_verts, steps):
