@@ -72,6 +72,7 @@ def test_autotuner_picks_a_candidate_and_restores_state(env):
     v = torch.from_numpy(sc.v.copy()).cuda()
     out = autotune.tune_mesh(ctx, mesh, x, v, ccfr.make_step_params(sc.step, sc.params), steps=2,
                              candidates=(0.6, 1.0))
-    assert out["cell_scale"] in (0.6, 1.0) and ctx.get_tuning()["cell_scale"] == out["cell_scale"]
+    assert out["cell_scale"] in (0.6, 1.0)
+    assert ctx.get_tuning()["cell_scale"] == pytest.approx(out["cell_scale"], rel=1e-6)
     assert np.array_equal(x.cpu().numpy(), sc.x) and np.array_equal(v.cpu().numpy(), sc.v)
     ctx.set_tuning(cell_scale=1.0)
