@@ -174,6 +174,7 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=4.0, help="c4: device-footprint budget of the server")
     ap.add_argument("--no-tune", action="store_true", help="skip the cell-size autotuner (default cell)")
     ap.add_argument("--cell-scale", type=float, default=None, help="fixed grid cell scale (skips the tuner)")
+    ap.add_argument("--pair-split", type=int, default=None, help="fixed lanes per broad-phase query (skips the tuner)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (scale for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -234,9 +235,9 @@ def main():
 
     # grid cell size: fixed, default, or picked by the autotuner on the first steps
     tuning = None
-    if args.cell_scale is not None:
-        ctx.set_tuning(cell_scale=args.cell_scale)
-        tuning = {"cell_scale": args.cell_scale, "source": "fixed"}
+    if args.cell_scale is not None or args.pair_split is not None:
+        ctx.set_tuning(cell_scale=args.cell_scale, pair_split=args.pair_split)
+        tuning = dict(ctx.get_tuning(), source="fixed")
     elif not args.no_tune:
         from paper_2607_26901_amd import autotune
         reset()
@@ -303,7 +304,7 @@ def main():
         "per_iteration": {"pairs": P, "contacts": Cc, "halfspaces": Hh,
                           "violating_vertices": tot[4] / n_builds, "halted_vertices": tot[5] / n_builds},
         "halted_fraction_of_violating": (tot[5] / tot[4]) if tot[4] else 0.0,
-        "tuning": tuning if tuning is not None else {"cell_scale": 1.0, "source": "default"},
+        "tuning": tuning if tuning is not None else dict(ctx.get_tuning(), source="default"),
     }
 
     # profiled pass: the same K steps as individual launches with HIP events around

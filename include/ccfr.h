@@ -232,10 +232,13 @@ int ccfr_profile_read(ccfr_ctx* ctx, ccfr_stream stream, float* ms, int32_t* lau
  *   cell_scale  grid cell size as a multiple of the default, 1.2 x the typical
  *               edge length + 2 pad (the cell never drops below 2.02 pad);
  *               in [0.25, 4], default 1.
+ *   pair_split  lanes per broad-phase query: 1 (the whole 3 x 3 x 3 stencil),
+ *               3 (one z layer each) or 9 (one row each); default 3.
  * Setting them invalidates recorded step graphs (they are recorded again). */
 typedef struct {
     float cell_scale;
-    int32_t reserved[3];   /* 0 */
+    int32_t pair_split;
+    int32_t reserved[2];   /* 0 */
 } ccfr_tuning;
 int ccfr_set_tuning(ccfr_ctx* ctx, const ccfr_tuning* tuning);
 int ccfr_get_tuning(const ccfr_ctx* ctx, ccfr_tuning* tuning);

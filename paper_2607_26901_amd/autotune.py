@@ -1,12 +1,14 @@
 """Autotuner of the speed-only knobs of a context.
 
-The knob is the grid cell size (`cell_scale`, a multiple of the default cell:
-1.2 x the typical edge length + 2 pad).  Smaller cells put fewer entries in the
-buckets a query scans but bin long primitives one level up; the best value
-depends on the mesh's edge lengths, its contact density and the pad.  Every
-value gives the same candidate pairs (the box test alone decides them), so the
-tuner only times: it runs the same work once per candidate value, keeps the
-fastest, and caches the choice per size class in a JSON file.
+The knobs are the grid cell size (`cell_scale`, a multiple of the default
+cell: 1.2 x the typical edge length + 2 pad) and the number of lanes that share
+one broad-phase query (`pair_split`).  Smaller cells put fewer entries in the
+buckets a query scans but bin long primitives one level up; more lanes per
+query shorten the walks of queries in dense folds at the price of more lanes.
+The best values depend on the mesh's edge lengths, its contact density and the
+pad.  Every setting gives the same candidate pairs (the box test alone decides
+them), so the tuner only times: it runs the same work once per setting, keeps
+the fastest, and caches the choice per size class in a JSON file.
 """
 from __future__ import annotations
 
@@ -17,6 +19,7 @@ import os
 from . import ccfr
 
 CELL_SCALES = (0.5, 0.6, 0.7, 0.85, 1.0, 1.2)
+PAIR_SPLITS = (1, 3, 9)
 
 
 def size_class(n_verts, n_tris, n_edges, r, kind="mesh") -> str:
@@ -55,17 +58,20 @@ class Cache:
             pass
 
 
-def tune(ctx: ccfr.Context, run, candidates=CELL_SCALES, repeats: int = 2) -> dict:
+def tune(ctx: ccfr.Context, run, candidates=CELL_SCALES, splits=PAIR_SPLITS, repeats: int = 2) -> dict:
     """Time `run()` (device milliseconds of a fixed piece of work, starting from
-    the same state every call) under each cell scale; leave the fastest set."""
+    the same state every call) under each (cell scale, split); leave the
+    fastest set."""
     times = {}
     for c in candidates:
-        ctx.set_tuning(cell_scale=c)
-        run()                                   # records the graph for this cell size
-        times[c] = min(run() for _ in range(repeats))
+        for sp in splits:
+            ctx.set_tuning(cell_scale=c, pair_split=sp)
+            run()                               # records the graph for this setting
+            times[(c, sp)] = min(run() for _ in range(repeats))
     best = min(times, key=times.get)
-    ctx.set_tuning(cell_scale=best)
-    return {"cell_scale": best, "ms": {str(k): v for k, v in times.items()}}
+    ctx.set_tuning(cell_scale=best[0], pair_split=best[1])
+    return {"cell_scale": best[0], "pair_split": best[1],
+            "ms": {f"{k[0]}/{k[1]}": v for k, v in times.items()}}
 
 
 def _events():
@@ -74,13 +80,14 @@ def _events():
 
 
 def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, steps: int = 4,
-              candidates=CELL_SCALES, cache: Cache | None = None, key: str | None = None) -> dict:
+              candidates=CELL_SCALES, splits=PAIR_SPLITS, cache: Cache | None = None,
+              key: str | None = None) -> dict:
     """Tune on `steps` single-mesh steps from the state (x, v), which is restored."""
     import torch
     if cache is not None and key is not None:
         hit = cache.get(key)
         if hit is not None:
-            ctx.set_tuning(cell_scale=hit["cell_scale"])
+            ctx.set_tuning(cell_scale=hit["cell_scale"], pair_split=hit["pair_split"])
             return dict(hit, cached=True)
     x0, v0 = x.clone(), v.clone()
 
@@ -101,7 +108,7 @@ def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, ste
             ctx.grow(info)                      # lists too small: grow and time again
         raise ccfr.CcfrError(-2, "tuning run")
 
-    out = tune(ctx, run, candidates)
+    out = tune(ctx, run, candidates, splits)
     x.copy_(x0)
     v.copy_(v0)
     torch.cuda.synchronize()
@@ -110,7 +117,7 @@ def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, ste
     return dict(out, cached=False)
 
 
-def tune_batch(ctx: ccfr.Context, batch: ccfr.Batch, candidates=CELL_SCALES) -> dict:
+def tune_batch(ctx: ccfr.Context, batch: ccfr.Batch, candidates=CELL_SCALES, splits=PAIR_SPLITS) -> dict:
     """Tune on one step of the resident batch; every trial is rolled back."""
     def run():
         for _ in range(4):
@@ -127,4 +134,4 @@ def tune_batch(ctx: ccfr.Context, batch: ccfr.Batch, candidates=CELL_SCALES) -> 
             ctx.grow(info)
         raise ccfr.CcfrError(-2, "tuning run")
 
-    return tune(ctx, run, candidates)
+    return tune(ctx, run, candidates, splits)

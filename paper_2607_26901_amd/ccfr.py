@@ -52,7 +52,7 @@ class StepParams(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("cell_scale", C.c_float), ("reserved", C.c_int32 * 3)]
+    _fields_ = [("cell_scale", C.c_float), ("pair_split", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class StatusInfo(C.Structure):
@@ -197,14 +197,17 @@ class Context:
         self.reserve(vf=int(nd[0] * factor) + 1024, ee=int(nd[1] * factor) + 1024, vv=int(nd[2] * factor) + 1024,
                      contacts=int(nd[3] * factor) + 1024, halfspaces=int(nd[4] * factor) + 1024)
 
-    def set_tuning(self, cell_scale=1.0):
-        t = Tuning(float(cell_scale))
+    def set_tuning(self, cell_scale=None, pair_split=None):
+        """Change any of the speed-only knobs (None keeps the current value)."""
+        cur = self.get_tuning()
+        t = Tuning(float(cur["cell_scale"] if cell_scale is None else cell_scale),
+                   int(cur["pair_split"] if pair_split is None else pair_split))
         _check(self.lib.ccfr_set_tuning(self.h, C.byref(t)), "ccfr_set_tuning")
 
     def get_tuning(self) -> dict:
         t = Tuning()
         _check(self.lib.ccfr_get_tuning(self.h, C.byref(t)), "ccfr_get_tuning")
-        return {"cell_scale": float(t.cell_scale)}
+        return {"cell_scale": float(t.cell_scale), "pair_split": int(t.pair_split)}
 
     def profile_enable(self, on=True):
         _check(self.lib.ccfr_profile_enable(self.h, int(bool(on))), "ccfr_profile_enable")

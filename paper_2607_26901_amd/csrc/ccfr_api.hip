@@ -251,7 +251,7 @@ void enqueue_candidates(ccfr_ctx* ctx, const Scene& sc, int n_meshes, hipStream_
     mk.mark(0, 1);
     PairLists pl{ctx->vf, ctx->ee, ctx->vv, ctx->cap_vf, ctx->cap_ee, ctx->cap_vv};
     mk.mark(1, 0);
-    launch_pairs(sc, g, pl, ctx->counters_d, s);
+    launch_pairs(sc, g, pl, ctx->counters_d, ctx->pair_split, s);
     mk.mark(1, 1);
     launch_finalize_pairs(g, pl, ctx->counters_d, s);
 }
@@ -759,12 +759,14 @@ int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, 
 }
 
 int ccfr_set_tuning(ccfr_ctx* ctx, const ccfr_tuning* t) {
-    if (!ctx || !t || !std::isfinite(t->cell_scale) || t->cell_scale < 0.25f || t->cell_scale > 4.0f)
+    if (!ctx || !t || !std::isfinite(t->cell_scale) || t->cell_scale < 0.25f || t->cell_scale > 4.0f ||
+        (t->pair_split != 1 && t->pair_split != 3 && t->pair_split != 9))
         return CCFR_ERR_INVALID_ARG;
-    if (t->cell_scale != ctx->cell_scale) {
+    if (t->cell_scale != ctx->cell_scale || t->pair_split != ctx->pair_split) {
         ctx->cell_scale = t->cell_scale;
+        ctx->pair_split = t->pair_split;
         ctx->tune_generation++;
-        ctx->generation++;          // recorded graphs carry the old cell size
+        ctx->generation++;          // recorded graphs carry the old settings
         drop_graph(ctx);
     }
     return CCFR_OK;
@@ -774,6 +776,7 @@ int ccfr_get_tuning(const ccfr_ctx* ctx, ccfr_tuning* t) {
     if (!ctx || !t) return CCFR_ERR_INVALID_ARG;
     *t = ccfr_tuning{};
     t->cell_scale = ctx->cell_scale;
+    t->pair_split = ctx->pair_split;
     return CCFR_OK;
 }
 

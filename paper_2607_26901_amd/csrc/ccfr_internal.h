@@ -57,7 +57,9 @@ struct GridEntry {
     float lo[3];
     int32_t idx;
     float hi[3];
-    uint32_t flags;   // bit 0: all vertices static; bits 8..23: mesh id
+    uint32_t flags;   // bit 0: all vertices static; bits 1..5: level; bits 8..23: mesh id
+    int32_t v[3];     // the primitive's vertices (an edge repeats its second, a point its only one)
+    int32_t pad;
 };
 
 // A pair inside the interaction range, between the two passes of the region
@@ -136,7 +138,7 @@ void launch_reset_build(DevCounters* c, uint32_t* level_mask, int n_meshes, hipS
 void launch_grid_count(const Scene& sc, GridWs& g, DevCounters* c, hipStream_t s);
 void launch_scan(const int32_t* in, int32_t* out, int32_t* zero_in, int n, int32_t* tmp, hipStream_t s);
 void launch_grid_scatter(const Scene& sc, GridWs& g, hipStream_t s);
-void launch_pairs(const Scene& sc, const GridWs& g, PairLists pl, DevCounters* c, hipStream_t s);
+void launch_pairs(const Scene& sc, const GridWs& g, PairLists pl, DevCounters* c, int split, hipStream_t s);
 void launch_finalize_pairs(const GridWs& g, PairLists pl, DevCounters* c, hipStream_t s);
 
 void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,

@@ -31,7 +31,8 @@
 //   grid_count   one thread per target and per vertex: box, level, bucket, rank
 //                inside the bucket (atomic)
 //   scan         exclusive prefix of the per-(kind, bucket) counts
-//   grid_scatter entries to their sorted slots (32 B each)
+//   grid_scatter entries to their sorted slots (48 B each: box, index, flags,
+//                vertices)
 //   pairs        one thread per query (vertex entries, then edge entries, in
 //                sorted order); found pairs are staged per wavefront in LDS and
 //                written out in blocks of up to 128 with one atomic each
@@ -250,9 +251,14 @@ __global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g) {
     int clo[3];
     const int level = entry_level(tg, lo, hi, P.inv_h, clo);
     GridEntry e;
-    for (int k = 0; k < 3; ++k) { e.lo[k] = lo[k]; e.hi[k] = hi[k]; }
+    for (int k = 0; k < 3; ++k) {
+        e.lo[k] = lo[k];
+        e.hi[k] = hi[k];
+        e.v[k] = tg.v[k];
+    }
     e.idx = tg.idx;
     e.flags = make_flags(st, level, mesh);
+    e.pad = 0;
     g.entries[g.start[key] + g.rank[t]] = e;
 }
 
@@ -316,14 +322,58 @@ __device__ __forceinline__ void stage_pair(Stage& st, int k, int32_t* list, int3
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-__global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists pl, DevCounters* c) {
+// Cells of the stencil [clo - 1, chi] that work item `part` of `split` walks:
+// all (split 1), one z layer (split 3) or one (z, y) row (split 9).
+__device__ __forceinline__ bool part_range(int split, int part, const int clo[3], const int chi[3], int r0[3],
+                                           int r1[3]) {
+    for (int k = 0; k < 3; ++k) {
+        r0[k] = clo[k] - 1;
+        r1[k] = chi[k];
+    }
+    if (split >= 3) {
+        r0[2] += split == 3 ? part : part / 3;
+        if (r0[2] > r1[2]) return false;
+        r1[2] = r0[2];
+    }
+    if (split == 9) {
+        r0[1] += part % 3;
+        if (r0[1] > r1[1]) return false;
+        r1[1] = r0[1];
+    }
+    return true;
+}
+
+// Bucket range of cell k (0..8, row-major in y then x) of one z layer of a
+// stencil [r0, r1]; ord is the cell's order against the query's own cell when
+// the half shell applies (`half`), else 1; an empty range is returned for a
+// cell outside the stencil or before the own cell.
+__device__ __forceinline__ void cell_range(const GridWs& g, int koff, int salt, int k, int cz, const int r0[3],
+                                           const int r1[3], const int own[3], bool half, int& s0, int& s1,
+                                           int& ord) {
+    const int cx = r0[0] + k % 3, cy = r0[1] + k / 3;
+    s0 = s1 = 0;
+    ord = -1;
+    if (cx > r1[0] || cy > r1[1]) return;
+    ord = half ? cell_order(cx, cy, cz, own) : 1;
+    if (ord < 0) return;
+    const int b = koff + (int)cell_bucket(cx, cy, cz, salt, g.log2s);
+    s0 = g.start[b];
+    s1 = g.start[b + 1];
+}
+
+// Work item = (query, part of its stencil) with `split` lanes per query.  The
+// entries carry their primitive's vertices, so the adjacency exclusions need
+// no second, dependent load; entries are read two at a time.
+__global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists pl, DevCounters* c, int split) {
     __shared__ Stage stages[kWaves];
     Stage& st = stages[threadIdx.x / 64];
     if (__lane_id() == 0) {
         st.fill[0] = st.fill[1] = st.fill[2] = 0;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const int q = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int item = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int q = item / split;
+    const int part = item - q * split;
     const int S = 1 << g.log2s;
     const int v0 = g.start[3 * S], nv_q = g.start[4 * S] - v0;       // binned vertices
     const int e0 = g.start[S], ne_q = g.start[2 * S] - e0;           // binned edges
@@ -333,11 +383,6 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
         const int v = me.idx;
         const int mesh = (int)(me.flags >> 8);
         const MeshParams P = sc.prm.get(mesh);
-        float lo[3], hi[3];
-        for (int k = 0; k < 3; ++k) {
-            lo[k] = me.lo[k];
-            hi[k] = me.hi[k];
-        }
         const bool q_static = (me.flags & 1u) != 0u;
         const bool q_free = sc.is_free[v] != 0;
         uint32_t levels = g.level_mask[mesh];
@@ -346,53 +391,55 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
             levels &= levels - 1u;
             const float inv = ldexpf(P.inv_h, -l);
             const int salt = level_salt(P.mesh_salt, l);
-            int clo[3], chi[3];
+            int clo[3], chi[3], r0[3], r1[3];
             for (int k = 0; k < 3; ++k) {
-                clo[k] = cell_coord(lo[k], inv);
-                chi[k] = cell_coord(hi[k], inv);
+                clo[k] = cell_coord(me.lo[k], inv);
+                chi[k] = cell_coord(me.hi[k], inv);
             }
-            for (int cz = clo[2] - 1; cz <= chi[2]; ++cz)
-                for (int cy = clo[1] - 1; cy <= chi[1]; ++cy)
-                    for (int cx = clo[0] - 1; cx <= chi[0]; ++cx) {
-                        const uint32_t b = cell_bucket(cx, cy, cz, salt, g.log2s);
-                        const int s0 = g.start[b], s1 = g.start[b + 1];
-                        for (int i = s0; i < s1; ++i) {
+            if (!part_range(split, part, clo, chi, r0, r1)) continue;
+            for (int cz = r0[2]; cz <= r1[2]; ++cz) {
+                // the next cell's bucket range is looked up while this one is read
+                int n0, n1, nord;
+                cell_range(g, 0, salt, 0, cz, r0, r1, clo, false, n0, n1, nord);
+                for (int k = 0; k < 9; ++k) {
+                    const int s0 = n0, s1 = n1;
+                    if (k < 8) cell_range(g, 0, salt, k + 1, cz, r0, r1, clo, false, n0, n1, nord);
+                    for (int i = s0; i < s1; i += 2) {
+                        const bool two = i + 1 < s1;
+                        const GridEntry e = g.entries[i];
+                        const GridEntry f = g.entries[two ? i + 1 : i];
+                        const bool hit = entry_ok(e, mesh, l, q_static) && overlap(me.lo, me.hi, e.lo, e.hi) &&
+                                         e.v[0] != v && e.v[1] != v && e.v[2] != v;
+                        const bool hit2 = two && entry_ok(f, mesh, l, q_static) &&
+                                          overlap(me.lo, me.hi, f.lo, f.hi) && f.v[0] != v && f.v[1] != v &&
+                                          f.v[2] != v;
+                        stage_pair(st, 0, pl.vf, &c->n_vf, pl.cap_vf, v, e.idx, hit);
+                        stage_pair(st, 0, pl.vf, &c->n_vf, pl.cap_vf, v, f.idx, hit2);
+                    }
+                }
+                if (q_free && l == 0) {
+                    // particles: half shell, as for edges of one level
+                    for (int k = 0; k < 9; ++k) {
+                        int u0, u1, ord;
+                        cell_range(g, 2 * S, salt, k, cz, r0, r1, clo, true, u0, u1, ord);
+                        for (int i = u0; i < u1; ++i) {
                             const GridEntry e = g.entries[i];
-                            bool hit = entry_ok(e, mesh, l, q_static) && overlap(lo, hi, e.lo, e.hi);
-                            if (hit) {
-                                const int* tv = sc.tris + 3 * e.idx;
-                                hit = tv[0] != v && tv[1] != v && tv[2] != v;
-                            }
-                            stage_pair(st, 0, pl.vf, &c->n_vf, pl.cap_vf, v, e.idx, hit);
-                        }
-                        const int ord = q_free && l == 0 ? cell_order(cx, cy, cz, clo) : -1;
-                        if (ord >= 0) {
-                            // particles: half shell, as for edges of one level
-                            const int k0 = 2 * S + (int)b;
-                            const int u0 = g.start[k0], u1 = g.start[k0 + 1];
-                            for (int i = u0; i < u1; ++i) {
-                                const GridEntry e = g.entries[i];
-                                const bool hit = (ord > 0 || e.idx > v) && entry_ok(e, mesh, 0, q_static) &&
-                                                 overlap(lo, hi, e.lo, e.hi);
-                                stage_pair(st, 2, pl.vv, &c->n_vv, pl.cap_vv, min(v, e.idx), max(v, e.idx), hit);
-                            }
+                            const bool hit = (ord > 0 || e.idx > v) && entry_ok(e, mesh, 0, q_static) &&
+                                             overlap(me.lo, me.hi, e.lo, e.hi);
+                            stage_pair(st, 2, pl.vv, &c->n_vv, pl.cap_vv, min(v, e.idx), max(v, e.idx), hit);
                         }
                     }
+                }
+            }
         }
     } else if (q >= sc.n_verts && q - sc.n_verts < ne_q) {
         // ---- edge query: edge-edge pairs
         const GridEntry me = g.entries[e0 + (q - sc.n_verts)];
         const int eq = me.idx;
-        const int a = sc.edges[2 * eq], bb = sc.edges[2 * eq + 1];
+        const int a = me.v[0], bb = me.v[1];
         const int mesh = (int)(me.flags >> 8);
         const int lq = (int)((me.flags >> 1) & 31u);
         const MeshParams P = sc.prm.get(mesh);
-        float lo[3], hi[3];
-        for (int k = 0; k < 3; ++k) {
-            lo[k] = me.lo[k];
-            hi[k] = me.hi[k];
-        }
-        int clo[3], chi[3];
         const bool q_static = (me.flags & 1u) != 0u;
         uint32_t levels = g.level_mask[mesh] & ~((1u << lq) - 1u);
         while (levels) {
@@ -400,29 +447,36 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
             levels &= levels - 1u;
             const float inv = ldexpf(P.inv_h, -l);
             const int salt = level_salt(P.mesh_salt, l);
+            int clo[3], chi[3], r0[3], r1[3];
             for (int k = 0; k < 3; ++k) {
-                clo[k] = cell_coord(lo[k], inv);
-                chi[k] = cell_coord(hi[k], inv);
+                clo[k] = cell_coord(me.lo[k], inv);
+                chi[k] = cell_coord(me.hi[k], inv);
             }
-            for (int cz = clo[2] - 1; cz <= chi[2]; ++cz)
-                for (int cy = clo[1] - 1; cy <= chi[1]; ++cy)
-                    for (int cx = clo[0] - 1; cx <= chi[0]; ++cx) {
-                        // same level: half shell (see cell_order)
-                        const int ord = l == lq ? cell_order(cx, cy, cz, clo) : 1;
-                        if (ord < 0) continue;
-                        const int k0 = S + (int)cell_bucket(cx, cy, cz, salt, g.log2s);
-                        const int s0 = g.start[k0], s1 = g.start[k0 + 1];
-                        for (int i = s0; i < s1; ++i) {
-                            const GridEntry e = g.entries[i];
-                            bool hit = (ord > 0 || e.idx > eq) && entry_ok(e, mesh, l, q_static) &&
-                                       overlap(lo, hi, e.lo, e.hi);
-                            if (hit) {
-                                const int c0 = sc.edges[2 * e.idx], c1 = sc.edges[2 * e.idx + 1];
-                                hit = c0 != a && c0 != bb && c1 != a && c1 != bb;
-                            }
-                            stage_pair(st, 1, pl.ee, &c->n_ee, pl.cap_ee, min(eq, e.idx), max(eq, e.idx), hit);
-                        }
+            if (!part_range(split, part, clo, chi, r0, r1)) continue;
+            for (int cz = r0[2]; cz <= r1[2]; ++cz) {
+                // same level: half shell (see cell_order); the next cell's
+                // bucket range is looked up while this one is read
+                const bool half = l == lq;
+                int n0, n1, nord;
+                cell_range(g, S, salt, 0, cz, r0, r1, clo, half, n0, n1, nord);
+                for (int k = 0; k < 9; ++k) {
+                    const int s0 = n0, s1 = n1, ord = nord;
+                    if (k < 8) cell_range(g, S, salt, k + 1, cz, r0, r1, clo, half, n0, n1, nord);
+                    for (int i = s0; i < s1; i += 2) {
+                        const bool two = i + 1 < s1;
+                        const GridEntry e = g.entries[i];
+                        const GridEntry f = g.entries[two ? i + 1 : i];
+                        const bool hit = (ord > 0 || e.idx > eq) && entry_ok(e, mesh, l, q_static) &&
+                                         overlap(me.lo, me.hi, e.lo, e.hi) && e.v[0] != a && e.v[0] != bb &&
+                                         e.v[1] != a && e.v[1] != bb;
+                        const bool hit2 = two && (ord > 0 || f.idx > eq) && entry_ok(f, mesh, l, q_static) &&
+                                          overlap(me.lo, me.hi, f.lo, f.hi) && f.v[0] != a && f.v[0] != bb &&
+                                          f.v[1] != a && f.v[1] != bb;
+                        stage_pair(st, 1, pl.ee, &c->n_ee, pl.cap_ee, min(eq, e.idx), max(eq, e.idx), hit);
+                        stage_pair(st, 1, pl.ee, &c->n_ee, pl.cap_ee, min(eq, f.idx), max(eq, f.idx), hit2);
                     }
+                }
+            }
         }
     }
     // all lanes of the wave are back together: write out what is left
@@ -467,10 +521,14 @@ void launch_grid_scatter(const Scene& sc, GridWs& g, hipStream_t s) {
     hipLaunchKernelGGL(k_grid_scatter, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, g);
 }
 
-void launch_pairs(const Scene& sc, const GridWs& g, PairLists pl, DevCounters* c, hipStream_t s) {
-    const int n = sc.n_verts + sc.n_edges;
-    if (n > 0)
-        hipLaunchKernelGGL(k_pairs, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, g, pl, c);
+void launch_pairs(const Scene& sc, const GridWs& g, PairLists pl, DevCounters* c, int split, hipStream_t s) {
+    const long long n = (long long)sc.n_verts + sc.n_edges;
+    if (n <= 0) return;
+    if (split != 3 && split != 9) split = 1;
+    while (split > 1 && n * split > (1LL << 31) - kBlock) split /= 3;
+    const long long items = n * split;
+    hipLaunchKernelGGL(k_pairs, dim3((unsigned)((items + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, sc, g, pl, c,
+                       split);
 }
 
 void launch_finalize_pairs(const GridWs& g, PairLists pl, DevCounters* c, hipStream_t s) {

@@ -26,11 +26,11 @@ SCENES = {
 
 
 @pytest.mark.parametrize("name", list(SCENES))
-@pytest.mark.parametrize("scale", [0.25, 0.5, 2.0, 4.0])
-def test_candidates_exact_at_any_cell_size(env, scale, name):
+@pytest.mark.parametrize("scale,split", [(0.25, 1), (0.5, 3), (1.0, 9), (2.0, 3), (4.0, 1), (0.7, 9)])
+def test_candidates_exact_at_any_cell_size(env, scale, split, name):
     ctx, ccfr, oracle, torch = env
     sc = SCENES[name]()
-    ctx.set_tuning(cell_scale=scale)
+    ctx.set_tuning(cell_scale=scale, pair_split=split)
     try:
         mesh = ccfr.mesh_from_scene(ctx, sc)
         x = torch.from_numpy(sc.x.copy()).cuda()
@@ -39,7 +39,7 @@ def test_candidates_exact_at_any_cell_size(env, scale, name):
         for k in ("vf", "ee", "vv"):
             assert np.array_equal(H.sorted_pairs(got[k]), H.sorted_pairs(want[k])), (k, scale)
     finally:
-        ctx.set_tuning(cell_scale=1.0)
+        ctx.set_tuning(cell_scale=1.0, pair_split=3)
 
 
 def test_steps_identical_across_cell_sizes(env):
@@ -47,8 +47,8 @@ def test_steps_identical_across_cell_sizes(env):
     sc = S.c0()
     sp = ccfr.make_step_params(sc.step, sc.params)
     outs = []
-    for scale in (1.0, 0.5, 1.7):
-        ctx.set_tuning(cell_scale=scale)
+    for scale, split in ((1.0, 3), (0.5, 1), (1.7, 9)):
+        ctx.set_tuning(cell_scale=scale, pair_split=split)
         mesh = ccfr.mesh_from_scene(ctx, sc)
         x = torch.from_numpy(sc.x.copy()).cuda()
         v = torch.from_numpy(sc.v.copy()).cuda()
@@ -58,7 +58,7 @@ def test_steps_identical_across_cell_sizes(env):
         code, info = ctx.sync_status(reset=True)
         assert code == 0, info
         outs.append(x.cpu().numpy())
-    ctx.set_tuning(cell_scale=1.0)
+    ctx.set_tuning(cell_scale=1.0, pair_split=3)
     for o in outs[1:]:
         assert np.abs(o.astype(np.float64) - outs[0]).max() <= H.step_tol(sc, sc.step.iters)
 
@@ -71,8 +71,9 @@ def test_autotuner_picks_a_candidate_and_restores_state(env):
     x = torch.from_numpy(sc.x.copy()).cuda()
     v = torch.from_numpy(sc.v.copy()).cuda()
     out = autotune.tune_mesh(ctx, mesh, x, v, ccfr.make_step_params(sc.step, sc.params), steps=2,
-                             candidates=(0.6, 1.0))
-    assert out["cell_scale"] in (0.6, 1.0)
+                             candidates=(0.6, 1.0), splits=(1, 9))
+    assert out["cell_scale"] in (0.6, 1.0) and out["pair_split"] in (1, 9)
+    assert ctx.get_tuning()["pair_split"] == out["pair_split"]
     assert ctx.get_tuning()["cell_scale"] == pytest.approx(out["cell_scale"], rel=1e-6)
     assert np.array_equal(x.cpu().numpy(), sc.x) and np.array_equal(v.cpu().numpy(), sc.v)
-    ctx.set_tuning(cell_scale=1.0)
+    ctx.set_tuning(cell_scale=1.0, pair_split=3)
