@@ -233,7 +233,7 @@ int ccfr_profile_read(ccfr_ctx* ctx, ccfr_stream stream, float* ms, int32_t* lau
  *               edge length + 2 pad (the cell never drops below 2.02 pad);
  *               in [0.25, 4], default 1.
  *   pair_split  lanes per broad-phase query: 1 (the whole 3 x 3 x 3 stencil),
- *               3 (one z layer each) or 9 (one row each); default 3.
+ *               3 (one z layer each) or 9 (one row each); default 1.
  * Setting them invalidates recorded step graphs (they are recorded again). */
 typedef struct {
     float cell_scale;

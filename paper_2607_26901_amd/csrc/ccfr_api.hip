@@ -400,7 +400,9 @@ int prepare_mesh(int32_t n_verts, const int32_t* tris, int32_t n_tris, const int
     for (int32_t v : E) m.is_free[v] = 0;
     for (int32_t v = 0; v < n_verts; ++v)
         if (m.is_free[v]) m.free_list.push_back(v);
-    // edge length the grid is sized for: the longest edge not longer than 8x the median
+    // edge length the grid is sized for: the longest edge not longer than 8x the
+    // median over all binned primitives, free particles counting as length 0 (a
+    // particle system with a few long wall edges gets cells sized by the pad)
     if (n_edges > 0 && rest_x) {
         std::vector<float> len(n_edges);
         for (int32_t e = 0; e < n_edges; ++e) {
@@ -412,8 +414,10 @@ int prepare_mesh(int32_t n_verts, const int32_t* tris, int32_t n_tris, const int
             len[e] = (float)std::sqrt(d2);
         }
         std::vector<float> sorted = len;
-        std::nth_element(sorted.begin(), sorted.begin() + n_edges / 2, sorted.end());
-        const float med = sorted[n_edges / 2];
+        sorted.resize(len.size() + m.free_list.size(), 0.f);
+        const size_t mid = sorted.size() / 2;
+        std::nth_element(sorted.begin(), sorted.begin() + mid, sorted.end());
+        const float med = sorted[mid];
         for (float l : len)
             if (l <= 8.f * med) m.typ_len = std::max(m.typ_len, l);
     }
@@ -745,6 +749,9 @@ int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, 
         info->last_halfspaces = h.last_hs;
         for (int k = 0; k < 6; ++k) info->need[k] = h.need[k];
         for (int k = 0; k < 10; ++k) info->totals[k] = h.totals[k];
+        const int slot_of[3] = {4, 5, 7};
+        for (int w = 0; w < 3; ++w)
+            for (int k = 0; k < 64; ++k) info->totals[slot_of[w]] += h.spread[w][k];
     }
     // an overflowed contact list leaves per-vertex counts behind: clear them
     if ((h.status & ST_CONTACTS) && ctx->vcount)

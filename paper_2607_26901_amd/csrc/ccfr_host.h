@@ -91,7 +91,7 @@ struct ccfr_ctx {
     bool use_graphs = true;
     bool narrow_fp32 = false;   // narrow-phase arithmetic in FP32 (measurement option)
     float cell_scale = 1.0f;    // grid cell size relative to the default
-    int pair_split = 3;         // lanes per broad-phase query (1, 3 or 9)
+    int pair_split = 1;         // lanes per broad-phase query (1, 3 or 9)
     long long tune_generation = 0;
 
     // grid

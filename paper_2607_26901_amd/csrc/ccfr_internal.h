@@ -50,9 +50,17 @@ struct DevCounters {
     long long need[6];                 // max sizes seen: vf, ee, vv, contacts, hs, large
     long long totals[10];              // vf, ee, vv, hs, violating, halted, degenerate, projected,
                                        // contacts, region builds
+    // per-vertex tallies of the projection (violating, halted, projected),
+    // spread over 64 slots by block so that the atomics do not queue on one
+    // address; the host adds them into totals[4], [5], [7]
+    long long spread[3][64];
 };
 
-// One binned target of the grid: its padded box, index and flags (32 B).
+__device__ __forceinline__ void spread_add(DevCounters* c, int which, unsigned long long n) {
+    atomicAdd((unsigned long long*)&c->spread[which][blockIdx.x & 63], n);
+}
+
+// One binned entry of the grid: its padded box, index, flags and vertices (48 B).
 struct GridEntry {
     float lo[3];
     int32_t idx;

@@ -311,8 +311,8 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
     if (deferred && !big) a.slow_list[base + __popcll(md & lt)] = v;
     if (deferred && big) a.slow_list[a.n_verts - 1 - (base_b + __popcll(mb & lt))] = v;
     if (lane == 0) {
-        if (mv) atomicAdd((unsigned long long*)&c->totals[4], (unsigned long long)__popcll(mv));
-        if (mm) atomicAdd((unsigned long long*)&c->totals[7], (unsigned long long)__popcll(mm));
+        if (mv) spread_add(c, 0, (unsigned long long)__popcll(mv));
+        if (mm) spread_add(c, 2, (unsigned long long)__popcll(mm));
     }
 }
 
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(kBlock) void k_project_lanes(ProjectArgs a, DevCoun
             write_result(a, v, y, (double)P.r, halted);
         }
         const unsigned long long mh = __ballot(halted);
-        if (__lane_id() == 0 && mh) atomicAdd((unsigned long long*)&c->totals[5], (unsigned long long)__popcll(mh));
+        if (__lane_id() == 0 && mh) spread_add(c, 1, (unsigned long long)__popcll(mh));
     }
 }
 
@@ -520,7 +520,7 @@ __global__ __launch_bounds__(64) void k_project_wave(ProjectArgs a, DevCounters*
         }
         if (lane == 0) {
             write_result(a, v, y, (double)P.r, halted);
-            if (halted) atomicAdd((unsigned long long*)&c->totals[5], 1ull);
+            if (halted) spread_add(c, 1, 1ull);
         }
     }
 }
