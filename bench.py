@@ -67,9 +67,11 @@ def workload(name):
 # pairs, C contacts, H half-spaces of that launch.
 def kernel_bytes(kernel, N, T, E, F, P, C, H):
     if kernel == "pair_emission":
-        # queries: vertex x, w, flag (17 B); edge ids, endpoint x, w (40 B);
-        # every binned target entry read once (32 B); pairs written (8 B)
-        return 17 * N + 40 * E + 32 * (T + E + F) + 8 * P
+        # every grid entry read once (48 B: box, index, flags, vertices): the
+        # targets (triangles, edges, particles) and the vertex queries (edge
+        # queries are the edge entries); free-particle flag (1 B per vertex);
+        # pairs written (8 B)
+        return 48 * (T + E + F + N) + N + 8 * P
     if kernel == "contacts":
         # pairs read (8 B), positions and inverse masses once (16 B/vertex), topology
         # (12 B/tri, 8 B/edge), contacts written (32 B), per-vertex counts (4 B/hs)
@@ -79,6 +81,26 @@ def kernel_bytes(kernel, N, T, E, F, P, C, H):
         # vertex; half-spaces read (32 B)
         return 44 * N + 32 * H
     raise KeyError(kernel)
+
+
+# Profile summaries with counter-derived HBM traffic, per (workload, kernel).
+TRAFFIC_PROFILES = {("c1", "pair_emission"): ("profiles/pair_emission_c1.md",
+                                              "paper_2607_26901_amd/csrc/k_broadphase.hip")}
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled) from the
+    committed rocprofv3 summary, or None if there is none or the kernel's source
+    has changed since it was taken."""
+    from paper_2607_26901_amd import profiling
+    entry = TRAFFIC_PROFILES.get((workload, kernel))
+    if entry is None:
+        return None
+    summ = profiling.read_summary(os.path.join(ROOT, entry[0]))
+    src = os.path.join(ROOT, entry[1])
+    if "traffic_bytes_per_launch" not in summ or summ.get("source_sha256") != profiling.sha256(src):
+        return None
+    return float(summ["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(sc, budget_s=25.0):
@@ -335,7 +357,8 @@ def main():
         B = kernel_bytes(dom, sc.n_verts, sc.n_tris, sc.n_edges, n_free, pP, pC, pH)
         achieved = B / (per_launch[i] * 1e-3) / 1e9
         result["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                              "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                              "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                              "traffic": measured_traffic(args.workload, dom),
                               "avg_launch_us": float(per_launch[i] * 1e3), "algorithmic_bytes": float(B)}
         it_ms = stage_ms.sum() / max(stage_launches[5], 1)
         Bit = 60 * sc.n_verts + 24 * sc.n_tris + 16 * sc.n_edges + 16 * pP + 52 * pH
