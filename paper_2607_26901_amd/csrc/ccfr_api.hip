@@ -26,21 +26,35 @@ void drop_graph(ccfr_ctx* ctx) {
     ctx->graph = StepGraph{};
 }
 
-// Bucket table size (log2, per kind) for `entries` binned entries.
+// Bucket table size (log2) for `entries` binned entries of one kind.
 int grid_log2s(long long entries) { return std::max(6, ceil_log2(std::max(64LL, entries))); }
 
-// Grows the grid for `targets` binned entries (primitives and vertices).
-int ensure_grid(ccfr_ctx* ctx, long long targets) {
-    const int log2s = grid_log2s(targets);
-    if (log2s > ctx->log2s) {
+// Per-kind tables (triangles, edges, particles, vertices) for these counts,
+// four buckets per entry, so that few occupied cells share a bucket: the
+// target tables are looked up by the queries, and the vertex table orders them
+// (a crowded one would interleave distant blocks in one wavefront).
+void grid_layout(long long T, long long E, long long F, long long N, int32_t log2k[4], int32_t off[5]) {
+    const long long cnt[4] = {4 * T, 4 * E, 4 * F, 4 * N};
+    off[0] = 0;
+    for (int k = 0; k < 4; ++k) {
+        log2k[k] = grid_log2s(cnt[k]);
+        off[k + 1] = off[k] + (1 << log2k[k]);
+    }
+}
+
+// Grows the grid for T triangles, E edges, F free particles and N vertices.
+int ensure_grid(ccfr_ctx* ctx, long long T, long long E, long long F, long long N) {
+    int32_t log2k[4], off[5];
+    grid_layout(T, E, F, N, log2k, off);
+    const long long buckets = off[4];
+    if (buckets > ctx->cap_buckets) {
         dev_free(ctx->cnt);
         dev_free(ctx->start);
-        const long long S4 = 4LL << log2s;
-        HIP_ALLOC(dev_alloc(&ctx->cnt, S4));
-        HIP_ALLOC(dev_alloc(&ctx->start, S4 + 1));
-        HIP_OK(hipMemset(ctx->cnt, 0, sizeof(int32_t) * (size_t)S4));
-        ctx->log2s = log2s;
-        const long long ntmp = (S4 + 1023) / 1024 + 2;
+        HIP_ALLOC(dev_alloc(&ctx->cnt, buckets));
+        HIP_ALLOC(dev_alloc(&ctx->start, buckets + 1));
+        HIP_OK(hipMemset(ctx->cnt, 0, sizeof(int32_t) * (size_t)buckets));
+        ctx->cap_buckets = buckets;
+        const long long ntmp = (buckets + 1023) / 1024 + 2;
         if (ntmp > ctx->cap_scan_tmp) {
             dev_free(ctx->scan_tmp);
             HIP_ALLOC(dev_alloc(&ctx->scan_tmp, ntmp));
@@ -48,6 +62,7 @@ int ensure_grid(ccfr_ctx* ctx, long long targets) {
         }
         ctx->generation++;
     }
+    const long long targets = T + E + F + N;
     if (targets > ctx->cap_targets) {
         dev_free(ctx->rank);
         dev_free(ctx->key);
@@ -150,7 +165,7 @@ int ensure_step(ccfr_ctx* ctx, long long n_verts) {
 // observed needs (ccfr_reserve).
 int ensure_sizes(ccfr_ctx* ctx, long long n_verts, long long n_tris, long long n_edges, long long n_free,
                  int n_meshes) {
-    int rc = ensure_grid(ctx, n_tris + n_edges + n_free + n_verts);
+    int rc = ensure_grid(ctx, n_tris, n_edges, n_free, n_verts);
     if (rc) return rc;
     rc = ensure_meshes(ctx, n_meshes);
     if (rc) return rc;
@@ -217,7 +232,7 @@ Scene make_scene(const ccfr_mesh* m, const float* x, const ccfr_params* p) {
 // scan and the bucket range follow the meshes actually present.
 GridWs grid_ws(ccfr_ctx* ctx, const Scene& sc, int n_meshes) {
     GridWs g{};
-    g.log2s = std::min(ctx->log2s, grid_log2s((long long)sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts));
+    grid_layout(sc.n_tris, sc.n_edges, sc.n_free, sc.n_verts, g.log2k, g.off);
     g.cnt = ctx->cnt;
     g.start = ctx->start;
     g.rank = ctx->rank;
@@ -240,25 +255,29 @@ struct Marks {
     }
 };
 
-// broad phase into the context's lists
-void enqueue_candidates(ccfr_ctx* ctx, const Scene& sc, int n_meshes, hipStream_t s, const Marks& mk) {
+// broad phase into the context's lists; `standalone` brackets it with its own
+// counter reset and build close (inside a substep the neighbouring kernels do both)
+void enqueue_candidates(ccfr_ctx* ctx, const Scene& sc, int n_meshes, hipStream_t s, const Marks& mk,
+                        bool standalone) {
     GridWs g = grid_ws(ctx, sc, n_meshes);
     mk.mark(0, 0);
-    launch_reset_build(ctx->counters_d, g.level_mask, g.n_meshes, s);
+    if (standalone) launch_reset_build(ctx->counters_d, g.level_mask, g.n_meshes, s);
     launch_grid_count(sc, g, ctx->counters_d, s);
-    launch_scan(g.cnt, g.start, g.cnt, 4 << g.log2s, g.scan_tmp, s);
+    launch_scan(g.cnt, g.start, g.cnt, g.off[4], g.scan_tmp, s);
     launch_grid_scatter(sc, g, s);
     mk.mark(0, 1);
     PairLists pl{ctx->vf, ctx->ee, ctx->vv, ctx->cap_vf, ctx->cap_ee, ctx->cap_vv};
     mk.mark(1, 0);
     launch_pairs(sc, g, pl, ctx->counters_d, ctx->pair_split, s);
     mk.mark(1, 1);
-    launch_finalize_pairs(g, pl, ctx->counters_d, s);
+    if (standalone) launch_finalize_pairs(g, pl, ctx->counters_d, s);
 }
 
+// narrow phase into the context's regions; inside a substep (`in_step`) both
+// builds are closed by launch_close_iteration
 void enqueue_regions(ccfr_ctx* ctx, const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
                      const int32_t* counts, long long cap_vf, long long cap_ee, long long cap_vv, hipStream_t s,
-                     const Marks& mk) {
+                     const Marks& mk, bool in_step) {
     mk.mark(2, 0);
     launch_contacts(sc, vf, ee, vv, counts, cap_vf, cap_ee, cap_vv, ctx->contacts, ctx->cap_contacts, ctx->vcount,
                     ctx->counters_d, s);
@@ -266,7 +285,7 @@ void enqueue_regions(ccfr_ctx* ctx, const Scene& sc, const int32_t* vf, const in
     mk.mark(3, 0);
     launch_scan(ctx->vcount, ctx->offsets, nullptr, sc.n_verts, ctx->scan_tmp, s);
     launch_fill(sc, ctx->contacts, ctx->cap_contacts, ctx->offsets, ctx->vcount, ctx->hs, ctx->cap_hs,
-                ctx->counters_d, s);
+                ctx->counters_d, !in_step, s);
     mk.mark(3, 1);
 }
 
@@ -293,13 +312,18 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
     const int n = sc.n_verts;
     launch_predict(n, plan.x, plan.v, sc.inv_mass, plan.dt, plan.gx, plan.gy, plan.gz, ctx->x_pred, ctx->x_start, s);
     if (plan.has_stretch) launch_fill_zero(plan.lambda, plan.n_edges, s);
+    // counters and level masks start clear; each iteration's close clears them
+    // for the next one
+    launch_reset_build(ctx->counters_d, ctx->level_mask, plan.n_meshes, s);
     for (int it = 0; it < plan.iters; ++it) {
         const Marks mk{ctx, it, s};
-        enqueue_candidates(ctx, sc, plan.n_meshes, s, mk);
+        enqueue_candidates(ctx, sc, plan.n_meshes, s, mk, false);
         enqueue_regions(ctx, sc, ctx->vf, ctx->ee, ctx->vv, counts_ptr(ctx), ctx->cap_vf, ctx->cap_ee,
-                        ctx->cap_vv, s, mk);
+                        ctx->cap_vv, s, mk, true);
         mk.mark(4, 0);
-        launch_copy(ctx->x_pred, ctx->p, 3LL * n, s);
+        launch_close_iteration(ctx->x_pred, ctx->p, 3LL * n, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
+                               ctx->offsets, PairCaps{ctx->cap_vf, ctx->cap_ee, ctx->cap_vv}, ctx->cap_contacts,
+                               ctx->cap_hs, s);
         if (plan.has_stretch) {
             for (size_t c = 0; c < plan.col_total.size(); ++c)
                 launch_stretch_segments(plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[c],
@@ -323,7 +347,7 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
         pa.slow_list = ctx->slow_list;
         pa.prm = sc.prm;
         mk.mark(5, 0);
-        launch_project(pa, ctx->counters_d, s);
+        launch_project(pa, ctx->counters_d, false, s);
         mk.mark(5, 1);
     }
     launch_update_velocity(n, plan.x, ctx->x_start, 1.0f / plan.dt, plan.v, s);
@@ -640,7 +664,7 @@ int ccfr_build_candidates(ccfr_ctx* ctx, const ccfr_mesh* mesh, const float* x_a
     if (mesh->ctx != ctx) return CCFR_ERR_INVALID_ARG;
     const hipStream_t s = (hipStream_t)stream;
     const Scene sc = make_scene(mesh, x_anchor_dev, params);
-    enqueue_candidates(ctx, sc, 1, s, Marks{ctx, -1, s});
+    enqueue_candidates(ctx, sc, 1, s, Marks{ctx, -1, s}, true);
     HIP_OK(hipGetLastError());
     out->vf = ctx->vf;
     out->ee = ctx->ee;
@@ -662,7 +686,7 @@ int ccfr_build_regions(ccfr_ctx* ctx, const ccfr_mesh* mesh, const float* x_anch
     const hipStream_t s = (hipStream_t)stream;
     const Scene sc = make_scene(mesh, x_anchor_dev, params);
     enqueue_regions(ctx, sc, c->vf, c->ee, c->vv, c->counts_dev, c->cap_vf, c->cap_ee, c->cap_vv, s,
-                    Marks{ctx, -1, s});
+                    Marks{ctx, -1, s}, false);
     HIP_OK(hipGetLastError());
     out->n_verts = mesh->n_verts;
     out->pad_ = 0;
@@ -703,7 +727,7 @@ int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const
     pa.prm.table = nullptr;
     pa.prm.vmesh = nullptr;
     pa.prm.one = mesh_params(params, 0.f, 0, 1.0f);
-    launch_project(pa, ctx->counters_d, (hipStream_t)stream);
+    launch_project(pa, ctx->counters_d, true, (hipStream_t)stream);
     HIP_OK(hipGetLastError());
     return CCFR_OK;
 }
@@ -742,10 +766,8 @@ int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, 
     HIP_OK(hipMemcpy(&h, ctx->counters_d, sizeof(h), hipMemcpyDeviceToHost));
     if (info) {
         info->status_bits = h.status;
-        info->last_counts[0] = h.n_vf;
-        info->last_counts[1] = h.n_ee;
-        info->last_counts[2] = h.n_vv;
-        info->last_contacts = h.n_contacts;
+        for (int k = 0; k < 3; ++k) info->last_counts[k] = h.last_pairs[k];
+        info->last_contacts = h.last_nc;
         info->last_halfspaces = h.last_hs;
         for (int k = 0; k < 6; ++k) info->need[k] = h.need[k];
         for (int k = 0; k < 10; ++k) info->totals[k] = h.totals[k];

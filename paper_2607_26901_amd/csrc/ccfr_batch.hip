@@ -339,7 +339,7 @@ int ccfr_batch_create(ccfr_ctx* ctx, int32_t max_slots, int64_t max_verts, int64
     if (rc == CCFR_OK) rc = ensure_step(ctx, max_verts);
     // the grid holds every primitive and vertex the pool can hold (any vertex
     // may be a free particle); list sizes start from the meshes' topology
-    if (rc == CCFR_OK) rc = ensure_grid(ctx, max_tris + max_edges + 2 * max_verts);
+    if (rc == CCFR_OK) rc = ensure_grid(ctx, max_tris, max_edges, max_verts, max_verts);
     if (rc == CCFR_OK) rc = ensure_sizes(ctx, max_verts, max_tris, max_edges, 0, max_slots);
     if (rc != CCFR_OK) {
         ccfr_batch_destroy(b);
@@ -461,7 +461,7 @@ int ccfr_batch_step(ccfr_batch* b, ccfr_stream stream) {
     const long long gen0 = ctx->generation;
     rc = ensure_step(ctx, b->max_verts);
     if (rc) return rc;
-    rc = ensure_grid(ctx, b->max_tris + b->max_edges + 2 * b->max_verts);
+    rc = ensure_grid(ctx, b->max_tris, b->max_edges, b->max_verts, b->max_verts);
     if (rc) return rc;
     rc = ensure_sizes(ctx, b->max_verts, b->max_tris, b->max_edges, 0, b->max_slots);
     if (rc) return rc;

@@ -95,7 +95,7 @@ struct ccfr_ctx {
     long long tune_generation = 0;
 
     // grid
-    int log2s = 0;
+    long long cap_buckets = 0;
     long long cap_targets = 0;
     int32_t* cnt = nullptr;
     int32_t* start = nullptr;
@@ -177,7 +177,7 @@ struct StepPlan {
 };
 
 void drop_graph(ccfr_ctx* ctx);
-int ensure_grid(ccfr_ctx* ctx, long long targets);
+int ensure_grid(ccfr_ctx* ctx, long long T, long long E, long long F, long long N);
 int ensure_meshes(ccfr_ctx* ctx, int n_meshes);
 int ensure_pairs(ccfr_ctx* ctx, long long vf, long long ee, long long vv);
 int ensure_regions(ccfr_ctx* ctx, long long n_verts, long long contacts, long long hs);
@@ -187,7 +187,6 @@ int ensure_sizes(ccfr_ctx* ctx, long long n_verts, long long n_tris, long long n
 bool params_ok(const ccfr_params* p);
 bool step_params_ok(const ccfr_step_params* sp);
 MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell_scale);
-int ensure_grid(ccfr_ctx* ctx, long long targets);
 int ensure_prof_events(ccfr_ctx* ctx, int iters);
 void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s);
 // Records the plan as a graph into *g (replacing it) and launches it on s.

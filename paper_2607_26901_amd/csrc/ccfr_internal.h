@@ -46,7 +46,9 @@ struct DevCounters {
     int32_t n_viol;                    // deferred vertices with small regions (slow list front)
     int32_t last_hs;
     int32_t n_viol_b;                  // deferred vertices with larger regions (slow list back)
-    int32_t pad0[2];
+    int32_t last_nc;                   // contacts of the last closed region build
+    int32_t last_pairs[3];             // VF, EE, VV of the last closed candidate build
+    int32_t pad0;
     long long need[6];                 // max sizes seen: vf, ee, vv, contacts, hs, large
     long long totals[10];              // vf, ee, vv, hs, violating, halted, degenerate, projected,
                                        // contacts, region builds
@@ -55,6 +57,52 @@ struct DevCounters {
     // address; the host adds them into totals[4], [5], [7]
     long long spread[3][64];
 };
+
+// End of a candidate build (one thread): overflow bits, largest sizes, totals.
+__device__ __forceinline__ void finalize_pairs_body(DevCounters* c, int64_t cap_vf, int64_t cap_ee, int64_t cap_vv) {
+    const long long nvf = c->n_vf, nee = c->n_ee, nvv = c->n_vv;
+    uint32_t st = 0;
+    if (nvf > cap_vf) st |= ST_VF;
+    if (nee > cap_ee) st |= ST_EE;
+    if (nvv > cap_vv) st |= ST_VV;
+    if (st) c->status |= st;
+    c->need[0] = max(c->need[0], nvf);
+    c->need[1] = max(c->need[1], nee);
+    c->need[2] = max(c->need[2], nvv);
+    c->totals[0] += nvf;
+    c->totals[1] += nee;
+    c->totals[2] += nvv;
+    c->last_pairs[0] = (int32_t)nvf;
+    c->last_pairs[1] = (int32_t)nee;
+    c->last_pairs[2] = (int32_t)nvv;
+}
+
+// End of a region build (one thread): overflow bits, largest sizes, totals.
+__device__ __forceinline__ void finalize_regions_body(DevCounters* c, int32_t n_verts, const int32_t* offsets,
+                                                      int64_t cap_contacts, int64_t cap_hs) {
+    const long long H = offsets[n_verts];
+    const long long nc = c->n_contacts;
+    uint32_t st = 0;
+    if (nc > cap_contacts) st |= ST_CONTACTS;
+    if (H > cap_hs) st |= ST_HS;
+    if (st) c->status |= st;
+    c->need[3] = max(c->need[3], nc);
+    c->need[4] = max(c->need[4], H);
+    c->totals[3] += H;
+    c->totals[8] += nc;
+    c->totals[9] += 1;
+    c->last_hs = (int32_t)H;
+    c->last_nc = (int32_t)nc;
+}
+
+// Per-build counters back to zero (one thread); level masks are cleared apart.
+__device__ __forceinline__ void reset_build_counters(DevCounters* c) {
+    c->n_vf = c->n_ee = c->n_vv = 0;
+    c->n_large_t = c->n_large_e = 0;
+    c->n_contacts = 0;
+    c->n_viol = 0;
+    c->n_viol_b = 0;
+}
 
 __device__ __forceinline__ void spread_add(DevCounters* c, int which, unsigned long long n) {
     atomicAdd((unsigned long long*)&c->spread[which][blockIdx.x & 63], n);
@@ -126,15 +174,22 @@ struct Scene {
 };
 
 struct GridWs {
-    int log2s;                  // table size S = 2^log2s buckets per kind
-    int32_t* cnt;               // [4 S] counts, zero between builds
-    int32_t* start;             // [4 S + 1] exclusive prefix
+    // one bucket table per entry kind (0 triangles, 1 edges, 2 particles,
+    // 3 vertices), each 2^log2k[k] buckets sized for that kind's entries,
+    // stored one after the other from bucket off[k]; off[4] = all buckets
+    int32_t log2k[4];
+    int32_t off[5];
+    int32_t* cnt;               // [off[4]] counts, zero between builds
+    int32_t* start;             // [off[4] + 1] exclusive prefix
     int32_t* rank;              // [T + E + F + N] rank of each entry inside its bucket
-    int32_t* key;               // [T + E + F + N] (kind - 1) * S + bucket, -1 = not binned
+    int32_t* key;               // [T + E + F + N] off[kind] + bucket, -1 = not binned
     GridEntry* entries;         // [T + E + F + N] sorted: triangles, edges, particles, vertices
     uint32_t* level_mask;       // [n_meshes] grid levels occupied by each mesh
     int32_t n_meshes;
     int32_t* scan_tmp;          // block partials of the scan
+    __device__ __forceinline__ int bucket(int kind0, int cx, int cy, int cz, int salt) const {
+        return off[kind0] + (int)cell_bucket(cx, cy, cz, salt, log2k[kind0]);
+    }
 };
 
 struct PairLists {
@@ -151,10 +206,11 @@ void launch_finalize_pairs(const GridWs& g, PairLists pl, DevCounters* c, hipStr
 
 void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
                      const int32_t* counts, int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
-                     Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c,
-                     hipStream_t s);
+                     Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s);
+// finalize: close the region build (overflow bits, totals) in a launch of its own
 void launch_fill(const Scene& sc, const Contact* contacts, int64_t cap_contacts, const int32_t* offsets,
-                 int32_t* vcount, ccfr_halfspace* hs, int64_t cap_hs, DevCounters* c, hipStream_t s);
+                 int32_t* vcount, ccfr_halfspace* hs, int64_t cap_hs, DevCounters* c, bool finalize,
+                 hipStream_t s);
 
 struct ProjectArgs {
     int32_t n_verts;
@@ -172,12 +228,24 @@ struct ProjectArgs {
     int32_t* slow_list;      // [n_verts] vertices with a violated half-space
     ParamSrc prm;
 };
-void launch_project(const ProjectArgs& a, DevCounters* c, hipStream_t s);
+// zero_counters: clear the slow-list counters first (the substep clears them
+// in launch_close_iteration instead)
+void launch_project(const ProjectArgs& a, DevCounters* c, bool zero_counters, hipStream_t s);
 
 void launch_predict(int n, const float* x, const float* v, const float* inv_mass, float dt,
                     float gx, float gy, float gz, float* x_pred, float* x_start, hipStream_t s);
 void launch_fill_zero(float* p, int64_t n, hipStream_t s);
 void launch_copy(const float* src, float* dst, int64_t n, hipStream_t s);
+// Between the region build and the stretch pass of a substep iteration: close
+// the candidate and region builds (overflow bits, totals), clear the per-build
+// counters and the level masks for the next build, and copy the prediction
+// into p.
+struct PairCaps {
+    int64_t vf, ee, vv;
+};
+void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounters* c, uint32_t* level_mask,
+                            int n_meshes, int32_t n_verts, const int32_t* offsets, PairCaps caps,
+                            int64_t cap_contacts, int64_t cap_hs, hipStream_t s);
 void launch_stretch_segments(const int32_t* edges_sorted, const float* rest_sorted, const int2* segs, int32_t nseg,
                              int32_t total, const float* inv_mass, float* p, float* lambda_sorted, float alpha_t,
                              hipStream_t s);

@@ -186,12 +186,7 @@ __device__ __forceinline__ void mark_level(uint32_t* level_mask, int mesh, uint3
 }
 
 __global__ void k_reset_build(DevCounters* c, uint32_t* level_mask, int n_meshes) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        c->n_vf = c->n_ee = c->n_vv = 0;
-        c->n_large_t = c->n_large_e = 0;
-        c->n_contacts = 0;
-        c->n_viol = 0;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) reset_build_counters(c);
     for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n_meshes; m += gridDim.x * blockDim.x)
         level_mask[m] = 0u;
 }
@@ -230,8 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCo
         g.key[t] = -1;
         return;
     }
-    const uint32_t b = cell_bucket(clo[0], clo[1], clo[2], level_salt(P.mesh_salt, level), g.log2s);
-    const int key = (tg.kind - 1) * (1 << g.log2s) + (int)b;
+    const int key = g.bucket(tg.kind - 1, clo[0], clo[1], clo[2], level_salt(P.mesh_salt, level));
     g.key[t] = key;
     g.rank[t] = atomicAdd(&g.cnt[key], 1);
 }
@@ -299,6 +293,18 @@ __device__ __forceinline__ void stage_flush(Stage& st, int k, int32_t* list, int
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
+// Writes a wave's staged pairs of list k from position `at` on.
+__device__ __forceinline__ void stage_write(const Stage& st, int k, int32_t* list, int64_t cap, long long at) {
+    const int f = st.fill[k];
+    for (int i = __lane_id(); i < f; i += 64) {
+        const long long idx = at + i;
+        if (idx < cap) {
+            list[2 * idx + 0] = st.a[k][i];
+            list[2 * idx + 1] = st.b[k][i];
+        }
+    }
+}
+
 // Every active lane of the wave must call it.
 __device__ __forceinline__ void stage_pair(Stage& st, int k, int32_t* list, int32_t* counter, int64_t cap, int a,
                                            int b, bool pred) {
@@ -347,7 +353,7 @@ __device__ __forceinline__ bool part_range(int split, int part, const int clo[3]
 // stencil [r0, r1]; ord is the cell's order against the query's own cell when
 // the half shell applies (`half`), else 1; an empty range is returned for a
 // cell outside the stencil or before the own cell.
-__device__ __forceinline__ void cell_range(const GridWs& g, int koff, int salt, int k, int cz, const int r0[3],
+__device__ __forceinline__ void cell_range(const GridWs& g, int kind0, int salt, int k, int cz, const int r0[3],
                                            const int r1[3], const int own[3], bool half, int& s0, int& s1,
                                            int& ord) {
     const int cx = r0[0] + k % 3, cy = r0[1] + k / 3;
@@ -356,7 +362,7 @@ __device__ __forceinline__ void cell_range(const GridWs& g, int koff, int salt, 
     if (cx > r1[0] || cy > r1[1]) return;
     ord = half ? cell_order(cx, cy, cz, own) : 1;
     if (ord < 0) return;
-    const int b = koff + (int)cell_bucket(cx, cy, cz, salt, g.log2s);
+    const int b = g.bucket(kind0, cx, cy, cz, salt);
     s0 = g.start[b];
     s1 = g.start[b + 1];
 }
@@ -364,7 +370,8 @@ __device__ __forceinline__ void cell_range(const GridWs& g, int koff, int salt, 
 // Work item = (query, part of its stencil) with `split` lanes per query.  The
 // entries carry their primitive's vertices, so the adjacency exclusions need
 // no second, dependent load; entries are read two at a time.
-__global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists pl, DevCounters* c, int split) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_pairs(Scene sc, GridWs g,
+                                                                                         PairLists pl, DevCounters* c, int split) {
     __shared__ Stage stages[kWaves];
     Stage& st = stages[threadIdx.x / 64];
     if (__lane_id() == 0) {
@@ -374,9 +381,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
     const int item = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int q = item / split;
     const int part = item - q * split;
-    const int S = 1 << g.log2s;
-    const int v0 = g.start[3 * S], nv_q = g.start[4 * S] - v0;       // binned vertices
-    const int e0 = g.start[S], ne_q = g.start[2 * S] - e0;           // binned edges
+    const int v0 = g.start[g.off[3]], nv_q = g.start[g.off[4]] - v0;     // binned vertices
+    const int e0 = g.start[g.off[1]], ne_q = g.start[g.off[2]] - e0;     // binned edges
     if (q < nv_q) {
         // ---- vertex query: vertex-face pairs, and particle pairs for free particles
         const GridEntry me = g.entries[v0 + q];
@@ -421,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
                     // particles: half shell, as for edges of one level
                     for (int k = 0; k < 9; ++k) {
                         int u0, u1, ord;
-                        cell_range(g, 2 * S, salt, k, cz, r0, r1, clo, true, u0, u1, ord);
+                        cell_range(g, 2, salt, k, cz, r0, r1, clo, true, u0, u1, ord);
                         for (int i = u0; i < u1; ++i) {
                             const GridEntry e = g.entries[i];
                             const bool hit = (ord > 0 || e.idx > v) && entry_ok(e, mesh, 0, q_static) &&
@@ -458,10 +464,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
                 // bucket range is looked up while this one is read
                 const bool half = l == lq;
                 int n0, n1, nord;
-                cell_range(g, S, salt, 0, cz, r0, r1, clo, half, n0, n1, nord);
+                cell_range(g, 1, salt, 0, cz, r0, r1, clo, half, n0, n1, nord);
                 for (int k = 0; k < 9; ++k) {
                     const int s0 = n0, s1 = n1, ord = nord;
-                    if (k < 8) cell_range(g, S, salt, k + 1, cz, r0, r1, clo, half, n0, n1, nord);
+                    if (k < 8) cell_range(g, 1, salt, k + 1, cz, r0, r1, clo, half, n0, n1, nord);
                     for (int i = s0; i < s1; i += 2) {
                         const bool two = i + 1 < s1;
                         const GridEntry e = g.entries[i];
@@ -479,27 +485,31 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
             }
         }
     }
-    // all lanes of the wave are back together: write out what is left
-    stage_flush(st, 0, pl.vf, &c->n_vf, pl.cap_vf);
-    stage_flush(st, 1, pl.ee, &c->n_ee, pl.cap_ee);
-    stage_flush(st, 2, pl.vv, &c->n_vv, pl.cap_vv);
+    // the block's waves are done: what is left in their stages goes out with
+    // one atomic per list for the whole block
+    __shared__ int pre[kWaves][3];
+    __shared__ int base[3];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t* counters[3] = {&c->n_vf, &c->n_ee, &c->n_vv};
+        for (int k = 0; k < 3; ++k) {
+            int acc = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                pre[w][k] = acc;
+                acc += stages[w].fill[k];
+            }
+            base[k] = acc ? atomicAdd(counters[k], acc) : 0;
+        }
+    }
+    __syncthreads();
+    const int wave = threadIdx.x / 64;
+    stage_write(st, 0, pl.vf, pl.cap_vf, (long long)base[0] + pre[wave][0]);
+    stage_write(st, 1, pl.ee, pl.cap_ee, (long long)base[1] + pre[wave][1]);
+    stage_write(st, 2, pl.vv, pl.cap_vv, (long long)base[2] + pre[wave][2]);
 }
 
-// Overflow bits, largest sizes seen and running totals of one build.
 __global__ void k_finalize_pairs(PairLists pl, DevCounters* c) {
-    if (threadIdx.x != 0) return;
-    const long long nvf = c->n_vf, nee = c->n_ee, nvv = c->n_vv;
-    uint32_t st = 0;
-    if (nvf > pl.cap_vf) st |= ST_VF;
-    if (nee > pl.cap_ee) st |= ST_EE;
-    if (nvv > pl.cap_vv) st |= ST_VV;
-    if (st) c->status |= st;
-    c->need[0] = max(c->need[0], nvf);
-    c->need[1] = max(c->need[1], nee);
-    c->need[2] = max(c->need[2], nvv);
-    c->totals[0] += nvf;
-    c->totals[1] += nee;
-    c->totals[2] += nvv;
+    if (threadIdx.x == 0) finalize_pairs_body(c, pl.cap_vf, pl.cap_ee, pl.cap_vv);
 }
 
 }  // namespace

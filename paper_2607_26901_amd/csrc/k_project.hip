@@ -534,9 +534,9 @@ __global__ void k_zero_viol(DevCounters* c) {
 
 }  // namespace
 
-void launch_project(const ProjectArgs& a, DevCounters* c, hipStream_t s) {
+void launch_project(const ProjectArgs& a, DevCounters* c, bool zero_counters, hipStream_t s) {
     if (a.n_verts <= 0) return;
-    hipLaunchKernelGGL(k_zero_viol, dim3(1), dim3(64), 0, s, c);
+    if (zero_counters) hipLaunchKernelGGL(k_zero_viol, dim3(1), dim3(64), 0, s, c);
     hipLaunchKernelGGL(k_project_fast, dim3((a.n_verts + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a, c);
     const int lane_blocks = std::max(1, std::min(1024, (a.n_verts + kBlock - 1) / kBlock));
     hipLaunchKernelGGL(k_project_lanes, dim3(lane_blocks), dim3(kBlock), 0, s, a, c);

@@ -121,19 +121,32 @@ __device__ int closest_on_segments(const R a[3], const R b[3], const R c[3], con
     return 0;
 }
 
-__device__ __forceinline__ void wave_append(Contact* list, int32_t* counter, int64_t cap, const Contact& rec,
-                                            bool pred) {
+// Appends the contacts of the whole block with one atomic: every thread of the
+// block must call it (the rounds of k_contacts are uniform across the block).
+constexpr int kWavesPerBlock = kBlock / 64;
+
+__device__ __forceinline__ void block_append(Contact* list, int32_t* counter, int64_t cap, const Contact& rec,
+                                             bool pred, int* wave_cnt, int* block_base) {
     const unsigned long long mask = __ballot(pred);
-    if (mask == 0ull) return;
     const int lane = __lane_id();
-    const int leader = __ffsll((long long)mask) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
-    base = __shfl(base, leader);
+    const int wave = threadIdx.x / 64;
+    if (lane == 0) wave_cnt[wave] = __popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+            const int t = wave_cnt[w];
+            wave_cnt[w] = acc;
+            acc += t;
+        }
+        *block_base = acc ? atomicAdd(counter, acc) : 0;
+    }
+    __syncthreads();
     if (pred) {
-        const long long idx = (long long)base + __popcll(mask & ((1ull << lane) - 1ull));
+        const long long idx = (long long)*block_base + wave_cnt[wave] + __popcll(mask & ((1ull << lane) - 1ull));
         if (idx < cap) list[idx] = rec;
     }
+    __syncthreads();
 }
 
 // Evaluate pair i of the concatenated lists [VF | EE | VV].  On success fills
@@ -222,9 +235,11 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Scene sc, const int32_t* vf
     const long long nee = min((long long)counts[1], (long long)cap_ee);
     const long long nvv = min((long long)counts[2], (long long)cap_vv);
     const long long total = nvf + nee + nvv;
+    __shared__ int wave_cnt[kWavesPerBlock];
+    __shared__ int block_base;
     int n_degenerate = 0;
-    // grid-stride: every lane of a wave runs the same number of rounds so that
-    // the wave-level append sees all lanes together
+    // grid-stride: every thread of the block runs the same number of rounds so
+    // that the block-level append sees all of them together
     const long long stride = (long long)gridDim.x * kBlock;
     const long long rounds = (total + stride - 1) / stride;
     const long long i0 = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -248,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Scene sc, const int32_t* vf
                     if (sc.inv_mass[pv.b[k]] > 0.f) atomicAdd(&vcount[pv.b[k]], 1);
             }
         }
-        wave_append(contacts, &c->n_contacts, cap_contacts, rec, keep);
+        block_append(contacts, &c->n_contacts, cap_contacts, rec, keep, wave_cnt, &block_base);
     }
     if (n_degenerate) atomicAdd((unsigned long long*)&c->totals[6], (unsigned long long)n_degenerate);
 }
@@ -299,19 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(Scene sc, const Contact* contac
 
 __global__ void k_finalize_regions(int32_t n_verts, const int32_t* offsets, int64_t cap_contacts,
                                    int64_t cap_hs, DevCounters* c) {
-    if (threadIdx.x != 0) return;
-    const long long H = offsets[n_verts];
-    const long long nc = c->n_contacts;
-    uint32_t st = 0;
-    if (nc > cap_contacts) st |= ST_CONTACTS;
-    if (H > cap_hs) st |= ST_HS;
-    if (st) c->status |= st;
-    c->need[3] = max(c->need[3], nc);
-    c->need[4] = max(c->need[4], H);
-    c->totals[3] += H;
-    c->totals[8] += nc;
-    c->totals[9] += 1;
-    c->last_hs = (int32_t)H;
+    if (threadIdx.x == 0) finalize_regions_body(c, n_verts, offsets, cap_contacts, cap_hs);
 }
 
 int grid_for(long long n) {
@@ -325,8 +328,7 @@ int grid_for(long long n) {
 
 void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
                      const int32_t* counts, int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
-                     Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c,
-                     hipStream_t s) {
+                     Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s) {
     const int blocks = grid_for(cap_vf + cap_ee + cap_vv);
     if (sc.narrow_fp32)
         hipLaunchKernelGGL(k_contacts<float>, dim3(blocks), dim3(kBlock), 0, s, sc, vf, ee, vv, counts, cap_vf,
@@ -337,11 +339,14 @@ void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, cons
 }
 
 void launch_fill(const Scene& sc, const Contact* contacts, int64_t cap_contacts, const int32_t* offsets,
-                 int32_t* vcount, ccfr_halfspace* hs, int64_t cap_hs, DevCounters* c, hipStream_t s) {
+                 int32_t* vcount, ccfr_halfspace* hs, int64_t cap_hs, DevCounters* c, bool finalize,
+                 hipStream_t s) {
     const int blocks = grid_for(cap_contacts);
     hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kBlock), 0, s, sc, contacts, cap_contacts, offsets, vcount, hs,
                        cap_hs, c);
-    hipLaunchKernelGGL(k_finalize_regions, dim3(1), dim3(64), 0, s, sc.n_verts, offsets, cap_contacts, cap_hs, c);
+    if (finalize)
+        hipLaunchKernelGGL(k_finalize_regions, dim3(1), dim3(64), 0, s, sc.n_verts, offsets, cap_contacts, cap_hs,
+                           c);
 }
 
 }  // namespace ccfr

@@ -1,6 +1,7 @@
 // k_scan.hip -- exclusive prefix sum of int32 counts (grid buckets, per-vertex
-// half-space counts) on gfx950: per-block totals, a one-block scan of the
-// totals, and a per-block rescan that adds its base.  out has n + 1 entries,
+// half-space counts) on gfx950 in two launches: per-block totals, then a
+// per-block rescan whose base every block sums itself from the totals before
+// it (a few thousand totals at most, read from L2).  out has n + 1 entries,
 // out[n] = total.  If zero_in is given, the input is cleared as it is read, so
 // count arrays are zero again for the next build without a separate memset.
 #include "ccfr_internal.h"
@@ -47,27 +48,24 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const int32_t* in, int
     if (threadIdx.x == kThreads - 1) partial[blockIdx.x] = inc;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_partials(int32_t* partial, int nb) {
-    __shared__ int lds[kThreads / 64 + 1];
-    __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
+// Sum of partial[0, b) by the whole block.
+__device__ __forceinline__ int block_base(const int32_t* partial, int b, int* lds_waves) {
+    int s = 0;
+    for (int i = threadIdx.x; i < b; i += kThreads) s += partial[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    const int wave = threadIdx.x / warpSize;
+    if (__lane_id() == 0) lds_waves[wave] = s;
     __syncthreads();
-    for (int b0 = 0; b0 < nb; b0 += kThreads) {
-        const int i = b0 + threadIdx.x;
-        const int v = i < nb ? partial[i] : 0;
-        const int inc = block_inclusive(v, lds);
-        const int c0 = carry;
-        if (i < nb) partial[i] = c0 + inc - v;
-        __syncthreads();
-        if (threadIdx.x == kThreads - 1) carry = c0 + inc;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[nb] = carry;
+    int t = 0;
+    for (int k = 0; k < kThreads / warpSize; ++k) t += lds_waves[k];
+    __syncthreads();
+    return t;
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_down(const int32_t* in, int32_t* out, int32_t* zero_in, int n,
                                                         const int32_t* partial, int nb) {
     __shared__ int lds[kThreads / 64 + 1];
+    const int block_base_v = block_base(partial, blockIdx.x, lds);
     const long long base = (long long)blockIdx.x * kTile + (long long)threadIdx.x * kItems;
     int vals[kItems];
     int s = 0;
@@ -76,7 +74,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const int32_t* in, int32
         s += vals[k];
     }
     const int inc = block_inclusive(s, lds);
-    int run = partial[blockIdx.x] + inc - s;
+    int run = block_base_v + inc - s;
     for (int k = 0; k < kItems; ++k) {
         if (base + k < n) {
             out[base + k] = run;
@@ -84,16 +82,15 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const int32_t* in, int32
         }
         run += vals[k];
     }
-    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = partial[nb];
+    if (blockIdx.x == nb - 1 && threadIdx.x == kThreads - 1) out[n] = run;
 }
 
 }  // namespace
 
-// tmp must hold ceil(n / 1024) + 1 ints
+// tmp must hold ceil(n / 1024) ints
 void launch_scan(const int32_t* in, int32_t* out, int32_t* zero_in, int n, int32_t* tmp, hipStream_t s) {
     const int nb = n > 0 ? (n + kTile - 1) / kTile : 1;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, in, n, tmp);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kThreads), 0, s, tmp, nb);
     hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kThreads), 0, s, in, out, zero_in, n, tmp, nb);
 }
 

@@ -38,6 +38,20 @@ __global__ __launch_bounds__(kBlock) void k_copy(const float* src, float* dst, l
     if (i < n) dst[i] = src[i];
 }
 
+__global__ __launch_bounds__(kBlock) void k_close_iteration(const float* x_pred, float* p, long long n3,
+                                                            DevCounters* c, uint32_t* level_mask, int n_meshes,
+                                                            int32_t n_verts, const int32_t* offsets,
+                                                            PairCaps caps, int64_t cap_contacts, int64_t cap_hs) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0) {
+        finalize_pairs_body(c, caps.vf, caps.ee, caps.vv);
+        finalize_regions_body(c, n_verts, offsets, cap_contacts, cap_hs);
+        reset_build_counters(c);
+    }
+    for (long long m = i; m < n_meshes; m += (long long)gridDim.x * kBlock) level_mask[m] = 0u;
+    if (i < n3) p[i] = x_pred[i];
+}
+
 // Colour class of the stretch pass: its edges lie in nseg segments of the
 // colour-sorted edge array, segs[k] = (first edge, exclusive prefix of segment
 // lengths); thread t finds its segment by binary search.
@@ -104,6 +118,15 @@ void launch_fill_zero(float* p, int64_t n, hipStream_t s) {
 void launch_copy(const float* src, float* dst, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_copy, dim3(blocks_for(n)), dim3(kBlock), 0, s, src, dst, (long long)n);
+}
+
+void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounters* c, uint32_t* level_mask,
+                            int n_meshes, int32_t n_verts, const int32_t* offsets, PairCaps caps,
+                            int64_t cap_contacts, int64_t cap_hs, hipStream_t s) {
+    long long n = n3 > n_meshes ? n3 : (long long)n_meshes;
+    if (n < 1) n = 1;
+    hipLaunchKernelGGL(k_close_iteration, dim3(blocks_for(n)), dim3(kBlock), 0, s, x_pred, p, (long long)n3, c,
+                       level_mask, n_meshes, n_verts, offsets, caps, cap_contacts, cap_hs);
 }
 
 void launch_stretch_segments(const int32_t* edges_sorted, const float* rest_sorted, const int2* segs, int32_t nseg,
