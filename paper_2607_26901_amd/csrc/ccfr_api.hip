@@ -67,9 +67,11 @@ int ensure_grid(ccfr_ctx* ctx, long long T, long long E, long long F, long long 
         dev_free(ctx->rank);
         dev_free(ctx->key);
         dev_free(ctx->entries);
+        dev_free(ctx->staged);
         HIP_ALLOC(dev_alloc(&ctx->rank, targets));
         HIP_ALLOC(dev_alloc(&ctx->key, targets));
         HIP_ALLOC(dev_alloc(&ctx->entries, targets));
+        HIP_ALLOC(dev_alloc(&ctx->staged, targets));
         ctx->cap_targets = targets;
         ctx->generation++;
     }
@@ -238,6 +240,7 @@ GridWs grid_ws(ccfr_ctx* ctx, const Scene& sc, int n_meshes) {
     g.rank = ctx->rank;
     g.key = ctx->key;
     g.entries = ctx->entries;
+    g.staged = ctx->staged;
     g.level_mask = ctx->level_mask;
     g.n_meshes = n_meshes;
     g.scan_tmp = ctx->scan_tmp;
@@ -565,7 +568,7 @@ void ccfr_destroy(ccfr_ctx* ctx) {
     drop_graph(ctx);
     dev_free(ctx->counters_d);
     dev_free(ctx->cnt); dev_free(ctx->start); dev_free(ctx->rank); dev_free(ctx->key);
-    dev_free(ctx->entries); dev_free(ctx->level_mask); dev_free(ctx->scan_tmp);
+    dev_free(ctx->entries); dev_free(ctx->staged); dev_free(ctx->level_mask); dev_free(ctx->scan_tmp);
     dev_free(ctx->vf); dev_free(ctx->ee); dev_free(ctx->vv);
     dev_free(ctx->contacts); dev_free(ctx->vcount); dev_free(ctx->offsets); dev_free(ctx->slow_list);
     dev_free(ctx->hs);

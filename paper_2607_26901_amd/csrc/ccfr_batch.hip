@@ -301,13 +301,14 @@ int64_t ccfr_batch_footprint(int32_t n_verts, int32_t n_tris, int32_t n_edges) {
     // edge, rest length); plus lambda (4 B per edge)
     long long bytes = 2 * (35 * N + 12 * T + 20 * E) + 4 * E;
     // workspace at the default list sizes: substep buffers (36 B per vertex),
-    // region CSR (12), grid entry + rank + key (56 per binned primitive or
-    // vertex) and at most 8 bucket counters and 8 offsets (4 B each) per entry,
+    // region CSR (12), grid entry twice (sorted and staged) + rank + key (104
+    // per binned primitive or vertex) and at most 8 bucket counters and 8
+    // offsets (4 B each) per entry,
     // 8 B per candidate pair slot,
     // 32 B per contact slot (half the pair slots) and 44 B per half-space slot
     // (twice the pair slots: record, sort key, sort index)
     const long long pairs = 8 * N + 8 * E + 16 * F;
-    bytes += 48 * N + 120 * (T + E + F + N) + 8 * pairs + 32 * (pairs / 2) + 44 * (2 * pairs);
+    bytes += 48 * N + 168 * (T + E + F + N) + 8 * pairs + 32 * (pairs / 2) + 44 * (2 * pairs);
     return bytes;
 }
 

@@ -102,6 +102,7 @@ struct ccfr_ctx {
     int32_t* rank = nullptr;
     int32_t* key = nullptr;
     ccfr::GridEntry* entries = nullptr;
+    ccfr::GridEntry* staged = nullptr;
     uint32_t* level_mask = nullptr;
     int32_t cap_meshes = 0;
     int32_t* scan_tmp = nullptr;

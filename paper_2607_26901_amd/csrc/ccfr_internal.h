@@ -184,6 +184,7 @@ struct GridWs {
     int32_t* rank;              // [T + E + F + N] rank of each entry inside its bucket
     int32_t* key;               // [T + E + F + N] off[kind] + bucket, -1 = not binned
     GridEntry* entries;         // [T + E + F + N] sorted: triangles, edges, particles, vertices
+    GridEntry* staged;          // [T + E + F + N] the same entries in primitive order
     uint32_t* level_mask;       // [n_meshes] grid levels occupied by each mesh
     int32_t n_meshes;
     int32_t* scan_tmp;          // block partials of the scan

@@ -31,11 +31,12 @@
 //   grid_count   one thread per target and per vertex: box, level, bucket, rank
 //                inside the bucket (atomic)
 //   scan         exclusive prefix of the per-(kind, bucket) counts
-//   grid_scatter entries to their sorted slots (48 B each: box, index, flags,
-//                vertices)
+//   grid_scatter the entries (48 B each: box, index, flags, vertices; written
+//                in primitive order by grid_count) moved to their sorted slots
 //   pairs        one thread per query (vertex entries, then edge entries, in
 //                sorted order); found pairs are staged per wavefront in LDS and
-//                written out in blocks of up to 128 with one atomic each
+//                written out in blocks of up to 192 with one atomic each
+//                (what is left at the end: one atomic per block and list)
 #include "ccfr_internal.h"
 
 #include <algorithm>
@@ -228,22 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCo
     const int key = g.bucket(tg.kind - 1, clo[0], clo[1], clo[2], level_salt(P.mesh_salt, level));
     g.key[t] = key;
     g.rank[t] = atomicAdd(&g.cnt[key], 1);
-}
-
-__global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g) {
-    const int n_all = sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts;
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= n_all) return;
-    const int key = g.key[t];
-    if (key < 0) return;
-    const Target tg = target_of(sc, t);
-    const int mesh = sc.prm.mesh_of(tg.v[0]);
-    const MeshParams P = sc.prm.get(mesh);
-    float lo[3], hi[3];
-    bool st;
-    target_box(sc, tg, P.pad, lo, hi, &st);
-    int clo[3];
-    const int level = entry_level(tg, lo, hi, P.inv_h, clo);
+    // the entry itself, in primitive order; the scatter only moves it
     GridEntry e;
     for (int k = 0; k < 3; ++k) {
         e.lo[k] = lo[k];
@@ -253,7 +239,16 @@ __global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g) {
     e.idx = tg.idx;
     e.flags = make_flags(st, level, mesh);
     e.pad = 0;
-    g.entries[g.start[key] + g.rank[t]] = e;
+    g.staged[t] = e;
+}
+
+__global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g) {
+    const int n_all = sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n_all) return;
+    const int key = g.key[t];
+    if (key < 0) return;
+    g.entries[g.start[key] + g.rank[t]] = g.staged[t];
 }
 
 // Per-wavefront staging of found pairs in LDS: lanes append to their wave's
@@ -261,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g) {
 // one global atomic and coalesced stores.  Each wave only touches its own slice,
 // so no block barrier is involved.
 constexpr int kWaves = kBlock / 64;
-constexpr int kStage = 128;
+constexpr int kStage = 192;
 
 struct Stage {
     int a[3][kStage];

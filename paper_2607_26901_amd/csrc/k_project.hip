@@ -295,25 +295,47 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
             write_result(a, v, mk(0.0, 0.0, 0.0), 0.0, false);
         }
     }
-    // vertices that need the full Alg. 2 go to the slow list, one atomic per wave
-    // and list: small regions from the front, larger ones from the back
+    // vertices that need the full Alg. 2 go to the slow list, one atomic per
+    // block and list: small regions from the front, larger ones from the back
     const unsigned long long md = __ballot(deferred && !big);
     const unsigned long long mb = __ballot(deferred && big);
     const unsigned long long mv = __ballot(violated);
     const unsigned long long mm = __ballot(moved);
     const int lane = __lane_id();
-    int base = 0, base_b = 0;
-    if (lane == 0 && md) base = atomicAdd(&c->n_viol, __popcll(md));
-    if (lane == 0 && mb) base_b = atomicAdd(&c->n_viol_b, __popcll(mb));
-    base = __shfl(base, 0);
-    base_b = __shfl(base_b, 0);
+    const int wave = threadIdx.x / 64;
+    constexpr int kW = kBlock / 64;
+    __shared__ int pre[kW][2];
+    __shared__ int tally[kW][2];
+    __shared__ int bases[2];
+    if (lane == 0) {
+        pre[wave][0] = __popcll(md);
+        pre[wave][1] = __popcll(mb);
+        tally[wave][0] = __popcll(mv);
+        tally[wave][1] = __popcll(mm);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc0 = 0, acc1 = 0, nv = 0, nm = 0;
+        for (int w = 0; w < kW; ++w) {
+            const int t0 = pre[w][0], t1 = pre[w][1];
+            pre[w][0] = acc0;
+            pre[w][1] = acc1;
+            acc0 += t0;
+            acc1 += t1;
+            nv += tally[w][0];
+            nm += tally[w][1];
+        }
+        bases[0] = acc0 ? atomicAdd(&c->n_viol, acc0) : 0;
+        bases[1] = acc1 ? atomicAdd(&c->n_viol_b, acc1) : 0;
+        if (nv) spread_add(c, 0, (unsigned long long)nv);
+        if (nm) spread_add(c, 2, (unsigned long long)nm);
+    }
+    __syncthreads();
+    const int base = bases[0] + pre[wave][0];
+    const int base_b = bases[1] + pre[wave][1];
     const unsigned long long lt = (1ull << lane) - 1ull;
     if (deferred && !big) a.slow_list[base + __popcll(md & lt)] = v;
     if (deferred && big) a.slow_list[a.n_verts - 1 - (base_b + __popcll(mb & lt))] = v;
-    if (lane == 0) {
-        if (mv) spread_add(c, 0, (unsigned long long)__popcll(mv));
-        if (mm) spread_add(c, 2, (unsigned long long)__popcll(mm));
-    }
 }
 
 // ---- slow path: one lane per listed vertex; bigger regions cooperatively ----

@@ -6,6 +6,8 @@
 // greedy colouring (edge-index order) whose classes share no vertex, so one
 // launch per colour updates its edges in parallel with the same result as the
 // sequential pass in colour order.
+#include <algorithm>
+
 #include "ccfr_internal.h"
 
 namespace ccfr {
@@ -123,8 +125,7 @@ void launch_copy(const float* src, float* dst, int64_t n, hipStream_t s) {
 void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounters* c, uint32_t* level_mask,
                             int n_meshes, int32_t n_verts, const int32_t* offsets, PairCaps caps,
                             int64_t cap_contacts, int64_t cap_hs, hipStream_t s) {
-    long long n = n3 > n_meshes ? n3 : (long long)n_meshes;
-    if (n < 1) n = 1;
+    const long long n = std::max<long long>(std::max<long long>(n3, n_meshes), 1);
     hipLaunchKernelGGL(k_close_iteration, dim3(blocks_for(n)), dim3(kBlock), 0, s, x_pred, p, (long long)n3, c,
                        level_mask, n_meshes, n_verts, offsets, caps, cap_contacts, cap_hs);
 }
