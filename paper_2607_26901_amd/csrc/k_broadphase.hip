@@ -67,10 +67,11 @@ __device__ __forceinline__ bool finite3(const float o[3]) {
     return isfinite(o[0]) && isfinite(o[1]) && isfinite(o[2]);
 }
 
+// Box overlap, evaluated without branches (every comparison, then one and).
 __device__ __forceinline__ bool overlap(const float alo[3], const float ahi[3], const float blo[3],
                                         const float bhi[3]) {
-    return alo[0] <= bhi[0] && blo[0] <= ahi[0] && alo[1] <= bhi[1] && blo[1] <= ahi[1] &&
-           alo[2] <= bhi[2] && blo[2] <= ahi[2];
+    return (alo[0] <= bhi[0]) & (blo[0] <= ahi[0]) & (alo[1] <= bhi[1]) & (blo[1] <= ahi[1]) &
+           (alo[2] <= bhi[2]) & (blo[2] <= ahi[2]);
 }
 
 // The primitive behind grid slot t: triangles, edges, free particles, then vertices.
@@ -163,8 +164,8 @@ __device__ __forceinline__ uint32_t make_flags(bool st, int level, int mesh) {
 
 __device__ __forceinline__ bool entry_ok(const GridEntry& e, int mesh, int level, bool q_static) {
     // same mesh, binned at the level being scanned, not a static-static pair
-    return (e.flags >> 8) == (uint32_t)mesh && ((e.flags >> 1) & 31u) == (uint32_t)level &&
-           !(q_static && (e.flags & 1u));
+    return ((e.flags >> 8) == (uint32_t)mesh) & (((e.flags >> 1) & 31u) == (uint32_t)level) &
+           !(q_static & ((e.flags & 1u) != 0u));
 }
 
 // Sets bit `level` of the mesh's level mask.  The lanes of a wavefront that share
@@ -264,9 +265,20 @@ struct Stage {
     int fill[3];
 };
 
-__device__ __forceinline__ void stage_flush(Stage& st, int k, int32_t* list, int32_t* counter, int64_t cap) {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const int f = *(volatile int*)&st.fill[k];
+// The stage lives in LDS; functions take it through an LDS-qualified pointer
+// so that every access is a ds_ instruction (a generic pointer would become a
+// flat access that waits for all outstanding global loads).  Lanes of one
+// wavefront exchange data through it; LDS executes a wavefront's accesses in
+// order, and the wavefront-scope fences keep the compiler from reordering or
+// caching them.
+#define LDS_PTR __attribute__((address_space(3)))
+typedef LDS_PTR Stage* StagePtr;
+
+__device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+__device__ __forceinline__ void stage_flush(StagePtr st, int k, int32_t* list, int32_t* counter, int64_t cap) {
+    wave_fence();
+    const int f = st->fill[k];
     if (f == 0) return;
     const unsigned long long act = __ballot(true);
     const int lane = __lane_id();
@@ -279,35 +291,35 @@ __device__ __forceinline__ void stage_flush(Stage& st, int k, int32_t* list, int
     for (int i = rank; i < f; i += nact) {
         const long long idx = (long long)base + i;
         if (idx < cap) {
-            list[2 * idx + 0] = ((volatile int*)st.a[k])[i];
-            list[2 * idx + 1] = ((volatile int*)st.b[k])[i];
+            list[2 * idx + 0] = st->a[k][i];
+            list[2 * idx + 1] = st->b[k][i];
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    if (lane == lead) *(volatile int*)&st.fill[k] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    wave_fence();
+    if (lane == lead) st->fill[k] = 0;
+    wave_fence();
 }
 
 // Writes a wave's staged pairs of list k from position `at` on.
-__device__ __forceinline__ void stage_write(const Stage& st, int k, int32_t* list, int64_t cap, long long at) {
-    const int f = st.fill[k];
+__device__ __forceinline__ void stage_write(StagePtr st, int k, int32_t* list, int64_t cap, long long at) {
+    const int f = st->fill[k];
     for (int i = __lane_id(); i < f; i += 64) {
         const long long idx = at + i;
         if (idx < cap) {
-            list[2 * idx + 0] = st.a[k][i];
-            list[2 * idx + 1] = st.b[k][i];
+            list[2 * idx + 0] = st->a[k][i];
+            list[2 * idx + 1] = st->b[k][i];
         }
     }
 }
 
 // Every active lane of the wave must call it.
-__device__ __forceinline__ void stage_pair(Stage& st, int k, int32_t* list, int32_t* counter, int64_t cap, int a,
+__device__ __forceinline__ void stage_pair(StagePtr st, int k, int32_t* list, int32_t* counter, int64_t cap, int a,
                                            int b, bool pred) {
     const unsigned long long mask = __ballot(pred);
     if (mask == 0ull) return;
     const int n = __popcll(mask);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    int f = *(volatile int*)&st.fill[k];
+    wave_fence();
+    int f = st->fill[k];
     if (f + n > kStage) {
         stage_flush(st, k, list, counter, cap);
         f = 0;
@@ -315,12 +327,12 @@ __device__ __forceinline__ void stage_pair(Stage& st, int k, int32_t* list, int3
     const int lane = __lane_id();
     if (pred) {
         const int slot = f + __popcll(mask & ((1ull << lane) - 1ull));
-        ((volatile int*)st.a[k])[slot] = a;
-        ((volatile int*)st.b[k])[slot] = b;
+        st->a[k][slot] = a;
+        st->b[k][slot] = b;
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    if (lane == __ffsll((long long)__ballot(true)) - 1) *(volatile int*)&st.fill[k] = f + n;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    wave_fence();
+    if (lane == __ffsll((long long)__ballot(true)) - 1) st->fill[k] = f + n;
+    wave_fence();
 }
 
 // Cells of the stencil [clo - 1, chi] that work item `part` of `split` walks:
@@ -368,9 +380,9 @@ __device__ __forceinline__ void cell_range(const GridWs& g, int kind0, int salt,
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_pairs(Scene sc, GridWs g,
                                                                                          PairLists pl, DevCounters* c, int split) {
     __shared__ Stage stages[kWaves];
-    Stage& st = stages[threadIdx.x / 64];
+    const StagePtr st = (StagePtr)&stages[threadIdx.x / 64];
     if (__lane_id() == 0) {
-        st.fill[0] = st.fill[1] = st.fill[2] = 0;
+        st->fill[0] = st->fill[1] = st->fill[2] = 0;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const int item = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
@@ -409,11 +421,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
                         const bool two = i + 1 < s1;
                         const GridEntry e = g.entries[i];
                         const GridEntry f = g.entries[two ? i + 1 : i];
-                        const bool hit = entry_ok(e, mesh, l, q_static) && overlap(me.lo, me.hi, e.lo, e.hi) &&
-                                         e.v[0] != v && e.v[1] != v && e.v[2] != v;
-                        const bool hit2 = two && entry_ok(f, mesh, l, q_static) &&
-                                          overlap(me.lo, me.hi, f.lo, f.hi) && f.v[0] != v && f.v[1] != v &&
-                                          f.v[2] != v;
+                        const bool hit = entry_ok(e, mesh, l, q_static) & overlap(me.lo, me.hi, e.lo, e.hi) &
+                                         (e.v[0] != v) & (e.v[1] != v) & (e.v[2] != v);
+                        const bool hit2 = two & entry_ok(f, mesh, l, q_static) & overlap(me.lo, me.hi, f.lo, f.hi) &
+                                          (f.v[0] != v) & (f.v[1] != v) & (f.v[2] != v);
                         stage_pair(st, 0, pl.vf, &c->n_vf, pl.cap_vf, v, e.idx, hit);
                         stage_pair(st, 0, pl.vf, &c->n_vf, pl.cap_vf, v, f.idx, hit2);
                     }
@@ -425,7 +436,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
                         cell_range(g, 2, salt, k, cz, r0, r1, clo, true, u0, u1, ord);
                         for (int i = u0; i < u1; ++i) {
                             const GridEntry e = g.entries[i];
-                            const bool hit = (ord > 0 || e.idx > v) && entry_ok(e, mesh, 0, q_static) &&
+                            const bool hit = ((ord > 0) | (e.idx > v)) & entry_ok(e, mesh, 0, q_static) &
                                              overlap(me.lo, me.hi, e.lo, e.hi);
                             stage_pair(st, 2, pl.vv, &c->n_vv, pl.cap_vv, min(v, e.idx), max(v, e.idx), hit);
                         }
@@ -467,12 +478,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
                         const bool two = i + 1 < s1;
                         const GridEntry e = g.entries[i];
                         const GridEntry f = g.entries[two ? i + 1 : i];
-                        const bool hit = (ord > 0 || e.idx > eq) && entry_ok(e, mesh, l, q_static) &&
-                                         overlap(me.lo, me.hi, e.lo, e.hi) && e.v[0] != a && e.v[0] != bb &&
-                                         e.v[1] != a && e.v[1] != bb;
-                        const bool hit2 = two && (ord > 0 || f.idx > eq) && entry_ok(f, mesh, l, q_static) &&
-                                          overlap(me.lo, me.hi, f.lo, f.hi) && f.v[0] != a && f.v[0] != bb &&
-                                          f.v[1] != a && f.v[1] != bb;
+                        const bool hit = ((ord > 0) | (e.idx > eq)) & entry_ok(e, mesh, l, q_static) &
+                                         overlap(me.lo, me.hi, e.lo, e.hi) & (e.v[0] != a) & (e.v[0] != bb) &
+                                         (e.v[1] != a) & (e.v[1] != bb);
+                        const bool hit2 = two & ((ord > 0) | (f.idx > eq)) & entry_ok(f, mesh, l, q_static) &
+                                          overlap(me.lo, me.hi, f.lo, f.hi) & (f.v[0] != a) & (f.v[0] != bb) &
+                                          (f.v[1] != a) & (f.v[1] != bb);
                         stage_pair(st, 1, pl.ee, &c->n_ee, pl.cap_ee, min(eq, e.idx), max(eq, e.idx), hit);
                         stage_pair(st, 1, pl.ee, &c->n_ee, pl.cap_ee, min(eq, f.idx), max(eq, f.idx), hit2);
                     }
