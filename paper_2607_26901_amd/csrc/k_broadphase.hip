@@ -258,6 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g) {
 // so no block barrier is involved.
 constexpr int kWaves = kBlock / 64;
 constexpr int kStage = 192;
+constexpr int kRound = 4;     // entries read per round of a bucket walk
 
 struct Stage {
     int a[3][kStage];
@@ -377,7 +378,7 @@ __device__ __forceinline__ void cell_range(const GridWs& g, int kind0, int salt,
 // Work item = (query, part of its stencil) with `split` lanes per query.  The
 // entries carry their primitive's vertices, so the adjacency exclusions need
 // no second, dependent load; entries are read two at a time.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_pairs(Scene sc, GridWs g,
+__global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g,
                                                                                          PairLists pl, DevCounters* c, int split) {
     __shared__ Stage stages[kWaves];
     const StagePtr st = (StagePtr)&stages[threadIdx.x / 64];
@@ -417,16 +418,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
                 for (int k = 0; k < 9; ++k) {
                     const int s0 = n0, s1 = n1;
                     if (k < 8) cell_range(g, 0, salt, k + 1, cz, r0, r1, clo, false, n0, n1, nord);
-                    for (int i = s0; i < s1; i += 2) {
-                        const bool two = i + 1 < s1;
-                        const GridEntry e = g.entries[i];
-                        const GridEntry f = g.entries[two ? i + 1 : i];
-                        const bool hit = entry_ok(e, mesh, l, q_static) & overlap(me.lo, me.hi, e.lo, e.hi) &
-                                         (e.v[0] != v) & (e.v[1] != v) & (e.v[2] != v);
-                        const bool hit2 = two & entry_ok(f, mesh, l, q_static) & overlap(me.lo, me.hi, f.lo, f.hi) &
-                                          (f.v[0] != v) & (f.v[1] != v) & (f.v[2] != v);
-                        stage_pair(st, 0, pl.vf, &c->n_vf, pl.cap_vf, v, e.idx, hit);
-                        stage_pair(st, 0, pl.vf, &c->n_vf, pl.cap_vf, v, f.idx, hit2);
+                    for (int i = s0; i < s1; i += kRound) {
+                        GridEntry e[kRound];
+#pragma unroll
+                        for (int u = 0; u < kRound; ++u) e[u] = g.entries[min(i + u, s1 - 1)];
+#pragma unroll
+                        for (int u = 0; u < kRound; ++u) {
+                            const bool hit = (i + u < s1) & entry_ok(e[u], mesh, l, q_static) &
+                                             overlap(me.lo, me.hi, e[u].lo, e[u].hi) & (e[u].v[0] != v) &
+                                             (e[u].v[1] != v) & (e[u].v[2] != v);
+                            stage_pair(st, 0, pl.vf, &c->n_vf, pl.cap_vf, v, e[u].idx, hit);
+                        }
                     }
                 }
                 if (q_free && l == 0) {
@@ -474,18 +476,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
                 for (int k = 0; k < 9; ++k) {
                     const int s0 = n0, s1 = n1, ord = nord;
                     if (k < 8) cell_range(g, 1, salt, k + 1, cz, r0, r1, clo, half, n0, n1, nord);
-                    for (int i = s0; i < s1; i += 2) {
-                        const bool two = i + 1 < s1;
-                        const GridEntry e = g.entries[i];
-                        const GridEntry f = g.entries[two ? i + 1 : i];
-                        const bool hit = ((ord > 0) | (e.idx > eq)) & entry_ok(e, mesh, l, q_static) &
-                                         overlap(me.lo, me.hi, e.lo, e.hi) & (e.v[0] != a) & (e.v[0] != bb) &
-                                         (e.v[1] != a) & (e.v[1] != bb);
-                        const bool hit2 = two & ((ord > 0) | (f.idx > eq)) & entry_ok(f, mesh, l, q_static) &
-                                          overlap(me.lo, me.hi, f.lo, f.hi) & (f.v[0] != a) & (f.v[0] != bb) &
-                                          (f.v[1] != a) & (f.v[1] != bb);
-                        stage_pair(st, 1, pl.ee, &c->n_ee, pl.cap_ee, min(eq, e.idx), max(eq, e.idx), hit);
-                        stage_pair(st, 1, pl.ee, &c->n_ee, pl.cap_ee, min(eq, f.idx), max(eq, f.idx), hit2);
+                    for (int i = s0; i < s1; i += kRound) {
+                        GridEntry e[kRound];
+#pragma unroll
+                        for (int u = 0; u < kRound; ++u) e[u] = g.entries[min(i + u, s1 - 1)];
+#pragma unroll
+                        for (int u = 0; u < kRound; ++u) {
+                            const bool hit = (i + u < s1) & ((ord > 0) | (e[u].idx > eq)) &
+                                             entry_ok(e[u], mesh, l, q_static) &
+                                             overlap(me.lo, me.hi, e[u].lo, e[u].hi) & (e[u].v[0] != a) &
+                                             (e[u].v[0] != bb) & (e[u].v[1] != a) & (e[u].v[1] != bb);
+                            stage_pair(st, 1, pl.ee, &c->n_ee, pl.cap_ee, min(eq, e[u].idx), max(eq, e[u].idx), hit);
+                        }
                     }
                 }
             }
