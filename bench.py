@@ -137,7 +137,7 @@ def bench_served(args):
     # warm-up: kernels loaded, graphs recorded once, workspace grown, on a few
     # small requests
     warm = [serve.Job(j.id, 0.0, j.scene, 2) for j in sorted(jobs, key=lambda j: j.scene.n_verts)[:4]]
-    srv = serve.Server(ctx, budget)
+    srv = serve.Server(ctx, budget, tune_at=None if args.no_tune else 16)
     srv.run(warm)
     serve.run_sequential(ctx, warm)
     torch.cuda.synchronize()

@@ -62,6 +62,7 @@ class RunStats:
     max_resident: int = 0
     max_resident_verts: int = 0
     retries: int = 0
+    tuning: dict | None = None
     results: dict = field(default_factory=dict)
 
     def summary(self) -> dict:
@@ -85,6 +86,7 @@ class RunStats:
             "max_resident_requests": self.max_resident,
             "max_resident_verts": self.max_resident_verts,
             "capacity_retries": self.retries,
+            "tuning": self.tuning,
         }
 
 
@@ -136,8 +138,12 @@ class Server:
 
     def __init__(self, ctx, budget_bytes: int, max_slots: int = 4096, max_verts: int | None = None,
                  max_tris: int | None = None, max_edges: int | None = None, batch=None, timer=None,
-                 footprint_fn=None):
+                 footprint_fn=None, tune_at: int | None = None):
+        """tune_at: once this many requests are resident, pick the grid cell
+        size by timing one rolled-back step per candidate (autotune)."""
         self.ctx = ctx
+        self.tune_at = tune_at
+        self.tuning = None
         self.budget = int(budget_bytes)
         self.footprint = footprint_fn or footprint
         if batch is None:
@@ -190,6 +196,9 @@ class Server:
                     sleep(max(0.0, jobs[nxt].arrival - (clock() - t0)))
                 continue
             st.max_resident = max(st.max_resident, len(resident))
+            if self.tune_at is not None and self.tuning is None and len(resident) >= self.tune_at:
+                from . import autotune
+                self.tuning = autotune.tune_batch(self.ctx, self.batch, candidates=(0.7, 0.85, 1.0), splits=(1,))
             st.max_resident_verts = max(st.max_resident_verts, sum(r[0].scene.n_verts for r in resident.values()))
             # one step of every resident request
             while True:
@@ -228,6 +237,7 @@ class Server:
                 else:
                     resident[slot] = (j, done, fp, res)
         st.makespan_s = clock() - t0
+        st.tuning = self.tuning
         return st
 
 

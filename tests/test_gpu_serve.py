@@ -2,7 +2,7 @@
 requests, admitted by device footprint under a budget that forces queueing,
 ends every request in the same state as running it alone through the
 single-mesh step (within 1e-5 of its bounding-box diagonal), free of
-penetrations."""
+penetrations, also when the grid cell size is tuned while requests run."""
 import numpy as np
 import pytest
 
@@ -27,7 +27,7 @@ def test_served_stream_equals_sequential():
     fps = [serve.footprint(j.scene) for j in jobs]
     budget = int(0.45 * sum(fps))
     ctx = ccfr.Context(0)
-    srv = serve.Server(ctx, budget, max_slots=16, max_verts=sum(j.scene.n_verts for j in jobs))
+    srv = serve.Server(ctx, budget, max_slots=16, max_verts=sum(j.scene.n_verts for j in jobs), tune_at=2)
     bst = srv.run(jobs, keep_results=True)
     srv.close()
     sst = serve.run_sequential(ccfr.Context(0), jobs, keep_results=True)
@@ -43,3 +43,7 @@ def test_served_stream_equals_sequential():
         assert oracle.count_intersections(a.x.astype(np.float64), sc.tris, sc.edges) == 0, j.id
     s = bst.summary()
     assert s["p99_request_step_ms"] >= s["p50_request_step_ms"] > 0
+    # the cell size was tuned mid-stream (rolled-back trial steps), which must
+    # not change any result
+    assert s["tuning"] is not None and s["tuning"]["cell_scale"] in (0.7, 0.85, 1.0)
+    ctx.set_tuning(cell_scale=1.0, pair_split=1)
