@@ -375,17 +375,150 @@ __device__ __forceinline__ void cell_range(const GridWs& g, int kind0, int salt,
     s1 = g.start[b + 1];
 }
 
-// Work item = (query, part of its stencil) with `split` lanes per query.  The
-// entries carry their primitive's vertices, so the adjacency exclusions need
-// no second, dependent load; entries are read two at a time.
-__global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g,
-                                                                                         PairLists pl, DevCounters* c, int split) {
+// ---- entry tests of one cell's bucket ----
+
+struct GlobalSrc {
+    const GridEntry* e;
+    __device__ __forceinline__ GridEntry get(int i) const { return e[i]; }
+};
+
+// Vertex query v against the triangle entries [i0, i1) of one cell.
+template <class Src>
+__device__ __forceinline__ void scan_vf(Src src, int i0, int i1, const GridEntry& me, int v, int mesh, int l,
+                                        bool q_static, StagePtr st, const PairLists& pl, DevCounters* c) {
+    for (int i = i0; i < i1; i += kRound) {
+        GridEntry e[kRound];
+#pragma unroll
+        for (int u = 0; u < kRound; ++u) e[u] = src.get(min(i + u, i1 - 1));
+#pragma unroll
+        for (int u = 0; u < kRound; ++u) {
+            const bool hit = (i + u < i1) & entry_ok(e[u], mesh, l, q_static) & overlap(me.lo, me.hi, e[u].lo, e[u].hi) &
+                             (e[u].v[0] != v) & (e[u].v[1] != v) & (e[u].v[2] != v);
+            stage_pair(st, 0, pl.vf, &c->n_vf, pl.cap_vf, v, e[u].idx, hit);
+        }
+    }
+}
+
+// Free particle v against the particle entries [i0, i1) of one cell (level 0,
+// half shell with the cell's order `ord`).
+template <class Src>
+__device__ __forceinline__ void scan_vv(Src src, int i0, int i1, int ord, const GridEntry& me, int v, int mesh,
+                                        bool q_static, StagePtr st, const PairLists& pl, DevCounters* c) {
+    for (int i = i0; i < i1; ++i) {
+        const GridEntry e = src.get(i);
+        const bool hit = ((ord > 0) | (e.idx > v)) & entry_ok(e, mesh, 0, q_static) & overlap(me.lo, me.hi, e.lo, e.hi);
+        stage_pair(st, 2, pl.vv, &c->n_vv, pl.cap_vv, min(v, e.idx), max(v, e.idx), hit);
+    }
+}
+
+// Edge query eq = (a, bb) of level lq against the edge entries [i0, i1) of one
+// cell of level l (half shell with the cell's order `ord` when l == lq).
+template <class Src>
+__device__ __forceinline__ void scan_ee(Src src, int i0, int i1, int ord, const GridEntry& me, int eq, int a, int bb,
+                                        int mesh, int l, bool q_static, StagePtr st, const PairLists& pl,
+                                        DevCounters* c) {
+    for (int i = i0; i < i1; i += kRound) {
+        GridEntry e[kRound];
+#pragma unroll
+        for (int u = 0; u < kRound; ++u) e[u] = src.get(min(i + u, i1 - 1));
+#pragma unroll
+        for (int u = 0; u < kRound; ++u) {
+            const bool hit = (i + u < i1) & ((ord > 0) | (e[u].idx > eq)) & entry_ok(e[u], mesh, l, q_static) &
+                             overlap(me.lo, me.hi, e[u].lo, e[u].hi) & (e[u].v[0] != a) & (e[u].v[0] != bb) &
+                             (e[u].v[1] != a) & (e[u].v[1] != bb);
+            stage_pair(st, 1, pl.ee, &c->n_ee, pl.cap_ee, min(eq, e[u].idx), max(eq, e[u].idx), hit);
+        }
+    }
+}
+
+// ---- per-lane walks of one level's stencil through global memory ----
+
+__device__ __forceinline__ void stencil_cells(const GridEntry& me, float inv, int clo[3], int chi[3]) {
+    for (int k = 0; k < 3; ++k) {
+        clo[k] = cell_coord(me.lo[k], inv);
+        chi[k] = cell_coord(me.hi[k], inv);
+    }
+}
+
+__device__ void walk_vf_global(const GridWs& g, const GridEntry& me, int v, int mesh, int l, int salt, bool q_static,
+                               const int clo[3], const int r0[3], const int r1[3], StagePtr st,
+                               const PairLists& pl, DevCounters* c) {
+    const GlobalSrc src{g.entries};
+    for (int cz = r0[2]; cz <= r1[2]; ++cz) {
+        // the next cell's bucket range is looked up while this one is read
+        int n0, n1, nord;
+        cell_range(g, 0, salt, 0, cz, r0, r1, clo, false, n0, n1, nord);
+        for (int k = 0; k < 9; ++k) {
+            const int s0 = n0, s1 = n1;
+            if (k < 8) cell_range(g, 0, salt, k + 1, cz, r0, r1, clo, false, n0, n1, nord);
+            scan_vf(src, s0, s1, me, v, mesh, l, q_static, st, pl, c);
+        }
+    }
+}
+
+__device__ void walk_vv_global(const GridWs& g, const GridEntry& me, int v, int mesh, int salt, bool q_static,
+                               const int clo[3], const int r0[3], const int r1[3], StagePtr st,
+                               const PairLists& pl, DevCounters* c) {
+    const GlobalSrc src{g.entries};
+    for (int cz = r0[2]; cz <= r1[2]; ++cz)
+        for (int k = 0; k < 9; ++k) {
+            int u0, u1, ord;
+            cell_range(g, 2, salt, k, cz, r0, r1, clo, true, u0, u1, ord);
+            scan_vv(src, u0, u1, ord, me, v, mesh, q_static, st, pl, c);
+        }
+}
+
+__device__ void walk_ee_global(const GridWs& g, const GridEntry& me, int eq, int a, int bb, int mesh, int lq, int l,
+                               int salt, bool q_static, const int clo[3], const int r0[3], const int r1[3],
+                               StagePtr st, const PairLists& pl, DevCounters* c) {
+    const GlobalSrc src{g.entries};
+    const bool half = l == lq;
+    for (int cz = r0[2]; cz <= r1[2]; ++cz) {
+        int n0, n1, nord;
+        cell_range(g, 1, salt, 0, cz, r0, r1, clo, half, n0, n1, nord);
+        for (int k = 0; k < 9; ++k) {
+            const int s0 = n0, s1 = n1, ord = nord;
+            if (k < 8) cell_range(g, 1, salt, k + 1, cz, r0, r1, clo, half, n0, n1, nord);
+            scan_ee(src, s0, s1, ord, me, eq, a, bb, mesh, l, q_static, st, pl, c);
+        }
+    }
+}
+
+// The block's waves are done: what is left in their stages goes out with one
+// atomic per list for the whole block.  Every thread of the block calls it.
+template <int W>
+__device__ void block_flush(LDS_PTR Stage* stages, const PairLists& pl, DevCounters* c) {
+    __shared__ int pre[W][3];
+    __shared__ int base[3];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t* counters[3] = {&c->n_vf, &c->n_ee, &c->n_vv};
+        for (int k = 0; k < 3; ++k) {
+            int acc = 0;
+            for (int w = 0; w < W; ++w) {
+                pre[w][k] = acc;
+                acc += stages[w].fill[k];
+            }
+            base[k] = acc ? atomicAdd(counters[k], acc) : 0;
+        }
+    }
+    __syncthreads();
+    const int wave = threadIdx.x / 64;
+    const StagePtr st = stages + wave;
+    stage_write(st, 0, pl.vf, pl.cap_vf, (long long)base[0] + pre[wave][0]);
+    stage_write(st, 1, pl.ee, pl.cap_ee, (long long)base[1] + pre[wave][1]);
+    stage_write(st, 2, pl.vv, pl.cap_vv, (long long)base[2] + pre[wave][2]);
+}
+
+// Work item = (query, part of its stencil) with `split` lanes per query; every
+// lane walks its stencil through global memory.
+__global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists pl, DevCounters* c, int split) {
     __shared__ Stage stages[kWaves];
     const StagePtr st = (StagePtr)&stages[threadIdx.x / 64];
     if (__lane_id() == 0) {
         st->fill[0] = st->fill[1] = st->fill[2] = 0;
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    wave_fence();
     const int item = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int q = item / split;
     const int part = item - q * split;
@@ -403,48 +536,12 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g,
         while (levels) {
             const int l = __ffs((int)levels) - 1;
             levels &= levels - 1u;
-            const float inv = ldexpf(P.inv_h, -l);
             const int salt = level_salt(P.mesh_salt, l);
             int clo[3], chi[3], r0[3], r1[3];
-            for (int k = 0; k < 3; ++k) {
-                clo[k] = cell_coord(me.lo[k], inv);
-                chi[k] = cell_coord(me.hi[k], inv);
-            }
+            stencil_cells(me, ldexpf(P.inv_h, -l), clo, chi);
             if (!part_range(split, part, clo, chi, r0, r1)) continue;
-            for (int cz = r0[2]; cz <= r1[2]; ++cz) {
-                // the next cell's bucket range is looked up while this one is read
-                int n0, n1, nord;
-                cell_range(g, 0, salt, 0, cz, r0, r1, clo, false, n0, n1, nord);
-                for (int k = 0; k < 9; ++k) {
-                    const int s0 = n0, s1 = n1;
-                    if (k < 8) cell_range(g, 0, salt, k + 1, cz, r0, r1, clo, false, n0, n1, nord);
-                    for (int i = s0; i < s1; i += kRound) {
-                        GridEntry e[kRound];
-#pragma unroll
-                        for (int u = 0; u < kRound; ++u) e[u] = g.entries[min(i + u, s1 - 1)];
-#pragma unroll
-                        for (int u = 0; u < kRound; ++u) {
-                            const bool hit = (i + u < s1) & entry_ok(e[u], mesh, l, q_static) &
-                                             overlap(me.lo, me.hi, e[u].lo, e[u].hi) & (e[u].v[0] != v) &
-                                             (e[u].v[1] != v) & (e[u].v[2] != v);
-                            stage_pair(st, 0, pl.vf, &c->n_vf, pl.cap_vf, v, e[u].idx, hit);
-                        }
-                    }
-                }
-                if (q_free && l == 0) {
-                    // particles: half shell, as for edges of one level
-                    for (int k = 0; k < 9; ++k) {
-                        int u0, u1, ord;
-                        cell_range(g, 2, salt, k, cz, r0, r1, clo, true, u0, u1, ord);
-                        for (int i = u0; i < u1; ++i) {
-                            const GridEntry e = g.entries[i];
-                            const bool hit = ((ord > 0) | (e.idx > v)) & entry_ok(e, mesh, 0, q_static) &
-                                             overlap(me.lo, me.hi, e.lo, e.hi);
-                            stage_pair(st, 2, pl.vv, &c->n_vv, pl.cap_vv, min(v, e.idx), max(v, e.idx), hit);
-                        }
-                    }
-                }
-            }
+            walk_vf_global(g, me, v, mesh, l, salt, q_static, clo, r0, r1, st, pl, c);
+            if (q_free && l == 0) walk_vv_global(g, me, v, mesh, salt, q_static, clo, r0, r1, st, pl, c);
         }
     } else if (q >= sc.n_verts && q - sc.n_verts < ne_q) {
         // ---- edge query: edge-edge pairs
@@ -459,61 +556,14 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g,
         while (levels) {
             const int l = __ffs((int)levels) - 1;
             levels &= levels - 1u;
-            const float inv = ldexpf(P.inv_h, -l);
             const int salt = level_salt(P.mesh_salt, l);
             int clo[3], chi[3], r0[3], r1[3];
-            for (int k = 0; k < 3; ++k) {
-                clo[k] = cell_coord(me.lo[k], inv);
-                chi[k] = cell_coord(me.hi[k], inv);
-            }
+            stencil_cells(me, ldexpf(P.inv_h, -l), clo, chi);
             if (!part_range(split, part, clo, chi, r0, r1)) continue;
-            for (int cz = r0[2]; cz <= r1[2]; ++cz) {
-                // same level: half shell (see cell_order); the next cell's
-                // bucket range is looked up while this one is read
-                const bool half = l == lq;
-                int n0, n1, nord;
-                cell_range(g, 1, salt, 0, cz, r0, r1, clo, half, n0, n1, nord);
-                for (int k = 0; k < 9; ++k) {
-                    const int s0 = n0, s1 = n1, ord = nord;
-                    if (k < 8) cell_range(g, 1, salt, k + 1, cz, r0, r1, clo, half, n0, n1, nord);
-                    for (int i = s0; i < s1; i += kRound) {
-                        GridEntry e[kRound];
-#pragma unroll
-                        for (int u = 0; u < kRound; ++u) e[u] = g.entries[min(i + u, s1 - 1)];
-#pragma unroll
-                        for (int u = 0; u < kRound; ++u) {
-                            const bool hit = (i + u < s1) & ((ord > 0) | (e[u].idx > eq)) &
-                                             entry_ok(e[u], mesh, l, q_static) &
-                                             overlap(me.lo, me.hi, e[u].lo, e[u].hi) & (e[u].v[0] != a) &
-                                             (e[u].v[0] != bb) & (e[u].v[1] != a) & (e[u].v[1] != bb);
-                            stage_pair(st, 1, pl.ee, &c->n_ee, pl.cap_ee, min(eq, e[u].idx), max(eq, e[u].idx), hit);
-                        }
-                    }
-                }
-            }
+            walk_ee_global(g, me, eq, a, bb, mesh, lq, l, salt, q_static, clo, r0, r1, st, pl, c);
         }
     }
-    // the block's waves are done: what is left in their stages goes out with
-    // one atomic per list for the whole block
-    __shared__ int pre[kWaves][3];
-    __shared__ int base[3];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t* counters[3] = {&c->n_vf, &c->n_ee, &c->n_vv};
-        for (int k = 0; k < 3; ++k) {
-            int acc = 0;
-            for (int w = 0; w < kWaves; ++w) {
-                pre[w][k] = acc;
-                acc += stages[w].fill[k];
-            }
-            base[k] = acc ? atomicAdd(counters[k], acc) : 0;
-        }
-    }
-    __syncthreads();
-    const int wave = threadIdx.x / 64;
-    stage_write(st, 0, pl.vf, pl.cap_vf, (long long)base[0] + pre[wave][0]);
-    stage_write(st, 1, pl.ee, pl.cap_ee, (long long)base[1] + pre[wave][1]);
-    stage_write(st, 2, pl.vv, pl.cap_vv, (long long)base[2] + pre[wave][2]);
+    block_flush<kWaves>((LDS_PTR Stage*)stages, pl, c);
 }
 
 __global__ void k_finalize_pairs(PairLists pl, DevCounters* c) {
