@@ -164,7 +164,9 @@ int ccfr_reserve(ccfr_ctx* ctx, int64_t vf, int64_t ee, int64_t vv, int64_t cont
 /* Broad phase (Sec. 4.1): every vertex-face, edge-edge and particle-particle pair
  * whose padded FP32 boxes overlap, with pad = fl32(r + xi/2 + delta/2 + guard)
  * and per axis lo = fl32(min - pad), hi = fl32(max + pad); pairs whose vertices
- * all have zero inverse mass are skipped.  x_anchor_dev: [n_verts][3] device.
+ * all have zero inverse mass are skipped.  x_anchor_dev: [n_verts][3] device
+ * (may be NULL for a mesh with no vertices).  A primitive with a non-finite
+ * coordinate is left out and raises the non-finite status bit.
  * On return `out` views the context's lists, valid until the next build on ctx. */
 int ccfr_build_candidates(ccfr_ctx* ctx, const ccfr_mesh* mesh, const float* x_anchor_dev,
                           const ccfr_params* params, ccfr_candidates* out, ccfr_stream stream);
@@ -188,7 +190,9 @@ int ccfr_build_regions(ccfr_ctx* ctx, const ccfr_mesh* mesh, const float* x_anch
  *   halted[v] = 1.  Vertices with zero inverse mass get y = 0.
  * regions: device CSR (the context's or caller-owned).  inv_mass_dev [N],
  * y_in_dev, y_out_dev [N][3] device (y_out may alias y_in); halted_dev [N] uint8
- * device or NULL.  The per-vertex arithmetic runs in FP64 registers. */
+ * device or NULL (all pointers may be NULL when regions->n_verts is 0).  A
+ * proposal with a non-finite component gives y = 0, halted = 1 and raises the
+ * non-finite status bit.  The per-vertex arithmetic runs in FP64 registers. */
 int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const float* inv_mass_dev,
                                const float* y_in_dev, const ccfr_params* params, float* y_out_dev,
                                uint8_t* halted_dev, ccfr_stream stream);
@@ -201,13 +205,16 @@ int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const
  *   (lambda kept across iterations); x += project(p - x);
  *   finally v = (x - x_start) / dt.
  * The first call for a (mesh, x, v, parameters) combination records a HIP graph
- * of the whole substep; later calls replay it. */
+ * of the whole substep; later calls replay it.  A mesh with no vertices is a
+ * no-op (x_dev and v_dev may then be NULL). */
 int ccfr_xpbd_step(ccfr_ctx* ctx, const ccfr_mesh* mesh, float* x_dev, float* v_dev,
                    const ccfr_step_params* sp, ccfr_stream stream);
 
 /* Waits for `stream`, copies the status word and counters into *info (nullable)
  * and returns CCFR_ERR_CAPACITY / CCFR_ERR_NONFINITE if the matching sticky bits
- * are set, else CCFR_OK.  reset != 0 clears the bits, need[] and totals[]. */
+ * are set, else CCFR_OK.  reset != 0 clears the whole device record: the bits,
+ * need[], totals[] and also the list lengths behind ccfr_candidates.counts_dev,
+ * so read the lists of a standalone build before resetting. */
 int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, int reset);
 
 /* ---- stage timing (measurement) ----

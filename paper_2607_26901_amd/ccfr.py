@@ -122,13 +122,34 @@ def _check(code, where):
         raise CcfrError(code, where)
 
 
-def _ptr(t):
-    """Device pointer of a contiguous torch tensor (or None)."""
+def _dev(t, dtype: str, numel: int, name: str, optional: bool = False):
+    """Device pointer of `t` after checking it is a contiguous device tensor of
+    `dtype` ("float32", "int32", "uint8") holding exactly `numel` elements: the
+    kernels index these buffers by the mesh's sizes, so a shorter buffer would
+    be read or written past its end."""
     if t is None:
-        return None
+        if optional or numel == 0:
+            return None
+        raise ValueError(f"{name}: a device tensor is required")
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{name}: must be a device tensor")
+    if str(t.dtype) != "torch." + dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {numel}")
     if not t.is_contiguous():
-        raise ValueError("tensor must be contiguous")
-    return C.c_void_p(t.data_ptr())
+        raise ValueError(f"{name}: must be contiguous")
+    return C.c_void_p(t.data_ptr()) if numel else None
+
+
+def _host_exact(a, dtype, rows: int, cols: int, name: str):
+    """Host array of exactly rows x cols elements (cols = 1: a vector)."""
+    if a is None:
+        return None, None
+    a = np.ascontiguousarray(a, dtype)
+    if a.size != rows * cols:
+        raise ValueError(f"{name}: {a.size} elements, expected {rows * cols}")
+    return a, a.ctypes.data_as(C.c_void_p)
 
 
 def _host(a, dtype):
@@ -232,8 +253,8 @@ class Mesh:
         lib = ctx.lib
         tris_a, tris_p = _host(np.asarray(tris).reshape(-1, 3), np.int32)
         edges_a, edges_p = _host(None if edges is None else np.asarray(edges).reshape(-1, 2), np.int32)
-        w_a, w_p = _host(inv_mass, np.float32)
-        r_a, r_p = _host(None if rest_x is None else np.asarray(rest_x).reshape(-1, 3), np.float32)
+        w_a, w_p = _host_exact(inv_mass, np.float32, n_verts, 1, "inv_mass")
+        r_a, r_p = _host_exact(rest_x, np.float32, n_verts, 3, "rest_x")
         h = C.c_void_p()
         _check(lib.ccfr_mesh_create(ctx.h, int(n_verts), tris_p, len(tris_a), edges_p,
                                     0 if edges_a is None else len(edges_a), w_p, r_p, C.byref(h)),
@@ -287,10 +308,10 @@ class Batch:
         """Admit a mesh; returns its slot.  Raises CcfrError (CAPACITY when it does not fit)."""
         tris_a, tris_p = _host(np.asarray(tris).reshape(-1, 3), np.int32)
         edges_a, edges_p = _host(None if edges is None else np.asarray(edges).reshape(-1, 2), np.int32)
-        w_a, w_p = _host(inv_mass, np.float32)
-        r_a, r_p = _host(None if rest_x is None else np.asarray(rest_x).reshape(-1, 3), np.float32)
-        x_a, x_p = _host(np.asarray(x).reshape(-1, 3), np.float32)
-        v_a, v_p = _host(np.asarray(v).reshape(-1, 3), np.float32)
+        w_a, w_p = _host_exact(inv_mass, np.float32, n_verts, 1, "inv_mass")
+        r_a, r_p = _host_exact(rest_x, np.float32, n_verts, 3, "rest_x")
+        x_a, x_p = _host_exact(x, np.float32, n_verts, 3, "x")
+        v_a, v_p = _host_exact(v, np.float32, n_verts, 3, "v")
         slot = C.c_int32(-1)
         _check(self.ctx.lib.ccfr_batch_add(self.h, int(n_verts), tris_p, len(tris_a), edges_p,
                                            0 if edges_a is None else len(edges_a), w_p, r_p, x_p, v_p,
@@ -341,7 +362,8 @@ class Batch:
 def build_candidates(ctx: Context, mesh: Mesh, x, params, stream=None) -> Candidates:
     out = Candidates()
     prm = params if isinstance(params, Params) else make_params(params)
-    _check(ctx.lib.ccfr_build_candidates(ctx.h, mesh.h, _ptr(x), C.byref(prm), C.byref(out), _stream(stream)),
+    xp = _dev(x, "float32", 3 * mesh.n_verts, "x")
+    _check(ctx.lib.ccfr_build_candidates(ctx.h, mesh.h, xp, C.byref(prm), C.byref(out), _stream(stream)),
            "ccfr_build_candidates")
     return out
 
@@ -349,7 +371,8 @@ def build_candidates(ctx: Context, mesh: Mesh, x, params, stream=None) -> Candid
 def build_regions(ctx: Context, mesh: Mesh, x, cands: Candidates, params, stream=None) -> Regions:
     out = Regions()
     prm = params if isinstance(params, Params) else make_params(params)
-    _check(ctx.lib.ccfr_build_regions(ctx.h, mesh.h, _ptr(x), C.byref(cands), C.byref(prm), C.byref(out),
+    xp = _dev(x, "float32", 3 * mesh.n_verts, "x")
+    _check(ctx.lib.ccfr_build_regions(ctx.h, mesh.h, xp, C.byref(cands), C.byref(prm), C.byref(out),
                                       _stream(stream)), "ccfr_build_regions")
     return out
 
@@ -357,19 +380,31 @@ def build_regions(ctx: Context, mesh: Mesh, x, cands: Candidates, params, stream
 def project_displacements(ctx: Context, regions: Regions, inv_mass, y_in, params, y_out, halted=None,
                           stream=None):
     prm = params if isinstance(params, Params) else make_params(params)
-    _check(ctx.lib.ccfr_project_displacements(ctx.h, C.byref(regions), _ptr(inv_mass), _ptr(y_in), C.byref(prm),
-                                              _ptr(y_out), _ptr(halted), _stream(stream)),
+    n = int(regions.n_verts)
+    wp = _dev(inv_mass, "float32", n, "inv_mass")
+    yp = _dev(y_in, "float32", 3 * n, "y_in")
+    op = _dev(y_out, "float32", 3 * n, "y_out")
+    hp = _dev(halted, "uint8", n, "halted", optional=True)
+    _check(ctx.lib.ccfr_project_displacements(ctx.h, C.byref(regions), wp, yp, C.byref(prm), op, hp,
+                                              _stream(stream)),
            "ccfr_project_displacements")
 
 
 def xpbd_step(ctx: Context, mesh: Mesh, x, v, step_params: StepParams, stream=None):
-    _check(ctx.lib.ccfr_xpbd_step(ctx.h, mesh.h, _ptr(x), _ptr(v), C.byref(step_params), _stream(stream)),
+    xp = _dev(x, "float32", 3 * mesh.n_verts, "x")
+    vp = _dev(v, "float32", 3 * mesh.n_verts, "v")
+    _check(ctx.lib.ccfr_xpbd_step(ctx.h, mesh.h, xp, vp, C.byref(step_params), _stream(stream)),
            "ccfr_xpbd_step")
 
 
 def caller_candidates(vf, ee, vv, counts) -> Candidates:
     """Candidates view over caller-owned device tensors ([P][2] int32 each, counts [3] int32).
     The view keeps the tensors alive."""
+    for name, t in (("vf", vf), ("ee", ee), ("vv", vv)):
+        _dev(t, "int32", t.numel(), name)
+        if t.dim() != 2 or t.shape[1] != 2:
+            raise ValueError(f"{name}: shape {tuple(t.shape)}, expected [P][2]")
+    _dev(counts, "int32", 3, "counts")
     c = Candidates(vf.data_ptr(), ee.data_ptr(), vv.data_ptr(), counts.data_ptr(), vf.shape[0], ee.shape[0],
                    vv.shape[0])
     c._keep = (vf, ee, vv, counts)
@@ -379,6 +414,12 @@ def caller_candidates(vf, ee, vv, counts) -> Candidates:
 def caller_regions(offsets, hs_bytes) -> Regions:
     """Regions view over caller-owned device tensors: offsets [N+1] int32, hs_bytes [H*32] uint8.
     The view keeps the tensors alive."""
+    if offsets.dim() != 1 or offsets.shape[0] < 1:
+        raise ValueError("offsets: expected [N+1]")
+    _dev(offsets, "int32", offsets.numel(), "offsets")
+    _dev(hs_bytes, "uint8", hs_bytes.numel(), "hs_bytes")
+    if hs_bytes.numel() % 32:
+        raise ValueError("hs_bytes: not a whole number of 32-byte half-spaces")
     r = Regions(offsets.shape[0] - 1, 0, offsets.data_ptr(), hs_bytes.data_ptr(), hs_bytes.numel() // 32)
     r._keep = (offsets, hs_bytes)
     return r

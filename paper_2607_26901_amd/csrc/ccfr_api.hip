@@ -663,7 +663,8 @@ int ccfr_reserve(ccfr_ctx* ctx, int64_t vf, int64_t ee, int64_t vv, int64_t cont
 
 int ccfr_build_candidates(ccfr_ctx* ctx, const ccfr_mesh* mesh, const float* x_anchor_dev, const ccfr_params* params,
                           ccfr_candidates* out, ccfr_stream stream) {
-    if (!ctx || !mesh || !x_anchor_dev || !out || !params_ok(params)) return CCFR_ERR_INVALID_ARG;
+    if (!ctx || !mesh || !out || !params_ok(params)) return CCFR_ERR_INVALID_ARG;
+    if (!x_anchor_dev && mesh->n_verts > 0) return CCFR_ERR_INVALID_ARG;
     if (mesh->ctx != ctx) return CCFR_ERR_INVALID_ARG;
     const hipStream_t s = (hipStream_t)stream;
     const Scene sc = make_scene(mesh, x_anchor_dev, params);
@@ -681,7 +682,8 @@ int ccfr_build_candidates(ccfr_ctx* ctx, const ccfr_mesh* mesh, const float* x_a
 
 int ccfr_build_regions(ccfr_ctx* ctx, const ccfr_mesh* mesh, const float* x_anchor_dev, const ccfr_candidates* c,
                        const ccfr_params* params, ccfr_regions* out, ccfr_stream stream) {
-    if (!ctx || !mesh || !x_anchor_dev || !c || !out || !params_ok(params)) return CCFR_ERR_INVALID_ARG;
+    if (!ctx || !mesh || !c || !out || !params_ok(params)) return CCFR_ERR_INVALID_ARG;
+    if (!x_anchor_dev && mesh->n_verts > 0) return CCFR_ERR_INVALID_ARG;
     if (!c->counts_dev || c->cap_vf < 0 || c->cap_ee < 0 || c->cap_vv < 0) return CCFR_ERR_INVALID_ARG;
     if ((c->cap_vf > 0 && !c->vf) || (c->cap_ee > 0 && !c->ee) || (c->cap_vv > 0 && !c->vv))
         return CCFR_ERR_INVALID_ARG;
@@ -702,7 +704,8 @@ int ccfr_build_regions(ccfr_ctx* ctx, const ccfr_mesh* mesh, const float* x_anch
 int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const float* inv_mass_dev,
                                const float* y_in_dev, const ccfr_params* params, float* y_out_dev,
                                uint8_t* halted_dev, ccfr_stream stream) {
-    if (!ctx || !regions || !inv_mass_dev || !y_in_dev || !y_out_dev || !params_ok(params)) return CCFR_ERR_INVALID_ARG;
+    if (!ctx || !regions || !params_ok(params)) return CCFR_ERR_INVALID_ARG;
+    if ((!inv_mass_dev || !y_in_dev || !y_out_dev) && regions->n_verts > 0) return CCFR_ERR_INVALID_ARG;
     if (regions->n_verts < 0 || !regions->offsets || (regions->cap > 0 && !regions->hs) || regions->cap < 0)
         return CCFR_ERR_INVALID_ARG;
     // scratch for the sort and the list of violating vertices must cover the call
@@ -737,8 +740,10 @@ int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const
 
 int ccfr_xpbd_step(ccfr_ctx* ctx, const ccfr_mesh* mesh, float* x_dev, float* v_dev, const ccfr_step_params* sp,
                    ccfr_stream stream) {
-    if (!ctx || !mesh || !x_dev || !v_dev || !step_params_ok(sp)) return CCFR_ERR_INVALID_ARG;
+    if (!ctx || !mesh || !step_params_ok(sp)) return CCFR_ERR_INVALID_ARG;
+    if ((!x_dev || !v_dev) && mesh->n_verts > 0) return CCFR_ERR_INVALID_ARG;
     if (mesh->ctx != ctx) return CCFR_ERR_INVALID_ARG;
+    if (mesh->n_verts == 0) return CCFR_OK;     // nothing moves
     const hipStream_t s = (hipStream_t)stream;
     const long long gen0 = ctx->generation;
     int rc = ensure_step(ctx, mesh->n_verts);

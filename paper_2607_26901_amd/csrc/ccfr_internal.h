@@ -252,6 +252,5 @@ void launch_stretch_segments(const int32_t* edges_sorted, const float* rest_sort
                              hipStream_t s);
 void launch_update_velocity(int n, const float* x, const float* x_start, float inv_dt, float* v,
                             hipStream_t s);
-void launch_check_finite(const float* a, int64_t n, DevCounters* c, hipStream_t s);
 
 }  // namespace ccfr

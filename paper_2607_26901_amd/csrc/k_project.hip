@@ -268,12 +268,16 @@ __device__ __forceinline__ bool project_one_plane(const ccfr_halfspace* H, int K
 __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCounters* c) {
     const int v = blockIdx.x * kBlock + threadIdx.x;
     const bool active = v < a.n_verts;
-    bool violated = false, deferred = false, big = false, moved = false;
+    bool violated = false, deferred = false, big = false, moved = false, bad = false;
     if (active) {
-        if (a.inv_mass[v] > 0.0f) {
+        const d3 yprop = a.inv_mass[v] > 0.0f ? load_prop(a, v) : mk(0.0, 0.0, 0.0);
+        bad = !(isfinite(yprop.x) && isfinite(yprop.y) && isfinite(yprop.z));
+        if (bad) {
+            // a non-finite proposal is not moved and raises the status bit
+            write_result(a, v, mk(0.0, 0.0, 0.0), 0.0, true);
+        } else if (a.inv_mass[v] > 0.0f) {
             moved = true;
             const MeshParams P = a.prm.get(a.prm.mesh_of(v));
-            const d3 yprop = load_prop(a, v);
             long long o0;
             const int K = region_size(a, v, &o0);
             const ccfr_halfspace* H = a.hs + o0;
@@ -302,6 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
     const unsigned long long mv = __ballot(violated);
     const unsigned long long mm = __ballot(moved);
     const int lane = __lane_id();
+    if (__ballot(bad) && lane == 0) atomicOr(&c->status, ST_NONFINITE);
     const int wave = threadIdx.x / 64;
     constexpr int kW = kBlock / 64;
     __shared__ int pre[kW][2];

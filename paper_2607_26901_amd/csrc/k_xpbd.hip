@@ -95,12 +95,6 @@ __global__ __launch_bounds__(kBlock) void k_update_velocity(int n, const float* 
     for (int k = 0; k < 3; ++k) v[3 * i + k] = (x[3 * i + k] - xs[3 * i + k]) * inv_dt;
 }
 
-__global__ __launch_bounds__(kBlock) void k_check_finite(const float* a, long long n, DevCounters* c) {
-    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-    const bool bad = i < n && !isfinite(a[i]);
-    if (__ballot(bad) && __lane_id() == 0) atomicOr(&c->status, ST_NONFINITE);
-}
-
 inline int blocks_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -141,11 +135,6 @@ void launch_stretch_segments(const int32_t* edges_sorted, const float* rest_sort
 void launch_update_velocity(int n, const float* x, const float* x_start, float inv_dt, float* v, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_update_velocity, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, x, x_start, inv_dt, v);
-}
-
-void launch_check_finite(const float* a, int64_t n, DevCounters* c, hipStream_t s) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_check_finite, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, (long long)n, c);
 }
 
 }  // namespace ccfr

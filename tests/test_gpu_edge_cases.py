@@ -1,0 +1,353 @@
+"""Edge cases of the hot-path calls through the C ABI: list overflow and
+recovery, non-finite inputs, degenerate primitives, empty and all-static
+meshes, and argument checks.  Results that the oracle defines are compared
+with it to the parity bar (candidates bit-exact, regions within 1e-5 of the
+bounding-box diagonal); the rest are the error contracts the header states."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2607_26901_amd import scenes as S
+from tests import gpu_helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import oracle
+    from paper_2607_26901_amd import ccfr
+    return ccfr, oracle, torch
+
+
+def _dense_particles():
+    """512 particles on an exact 4 mm lattice with 7.5 mm box pads: about 83
+    particle pairs per particle, several times the lists' default room."""
+    return S.particles_in_box(nx=8, ny=8, nz=8, spacing=4e-3, jitter=0.0, seed=3)
+
+
+def _build_with_growth(ctx, ccfr, torch, mesh, x_t, params):
+    """Candidates and regions, growing the lists to the reported need until the
+    build fits.  Returns (candidate lists read back, regions, number of
+    overflowing builds).  The list lengths live in the device counters, which
+    a status reset clears, so the lists are read before it."""
+    overflows = 0
+    for _ in range(6):
+        c = ccfr.build_candidates(ctx, mesh, x_t, params)
+        r = ccfr.build_regions(ctx, mesh, x_t, c, params)
+        torch.cuda.synchronize()
+        code, info = ctx.sync_status(reset=False)
+        got = ccfr.read_candidates(c) if code == 0 else None
+        ctx.sync_status(reset=True)
+        if code == 0:
+            return got, r, overflows
+        assert code == -2, info
+        assert info["status_bits"] & 0x3f, info
+        overflows += 1
+        ctx.grow(info)
+    raise AssertionError("capacity did not converge")
+
+
+def test_capacity_overflow_then_exact(env):
+    """A build whose lists overflow reports CAPACITY with the sizes it needed;
+    after growing to them, the same build is bit-exact against the oracle and
+    the regions match it."""
+    ccfr, oracle, torch = env
+    ctx = ccfr.Context(0)                     # sized by this mesh alone
+    sc = _dense_particles()
+    om = oracle.Mesh(sc)
+    ref = oracle.candidates(om, sc.params)
+    mesh = ccfr.mesh_from_scene(ctx, sc)
+    x = torch.from_numpy(sc.x).cuda()
+    prm = ccfr.make_params(sc.params)
+    c = ccfr.build_candidates(ctx, mesh, x, prm)
+    torch.cuda.synchronize()
+    code, info = ctx.sync_status(reset=False)
+    assert code == -2 and (info["status_bits"] & 4), info           # the particle list overflowed
+    assert info["need"][2] == len(ref["vv"]) > c.cap_vv
+    assert info["last_counts"][2] == len(ref["vv"])
+    ctx.sync_status(reset=True)
+    got, r, overflows = _build_with_growth(ctx, ccfr, torch, mesh, x, prm)
+    assert overflows >= 1                    # contacts and half-spaces outgrow their room too
+    for kind in ("vf", "ee", "vv"):
+        assert np.array_equal(H.sorted_pairs(got[kind]), H.sorted_pairs(ref[kind])), kind
+    off, hs = ccfr.read_regions(r)
+    off_o, hs_o, _ = oracle.regions(om, sc.params, ref)
+    n = H.compare_regions(sc, sc.params, off, hs, off_o, hs_o, float(np.float32(sc.params.xi)),
+                          float(np.float32(sc.params.r)))
+    assert n > 10000
+    mesh.close()
+    ctx.close()
+
+
+def test_reserve_up_front(env):
+    """Lists reserved to the oracle's sizes before the first build never overflow."""
+    ccfr, oracle, torch = env
+    ctx = ccfr.Context(0)
+    sc = _dense_particles()
+    om = oracle.Mesh(sc)
+    ref = oracle.candidates(om, sc.params)
+    off_o, hs_o, _ = oracle.regions(om, sc.params, ref)
+    mesh = ccfr.mesh_from_scene(ctx, sc)
+    ctx.reserve(vf=len(ref["vf"]), ee=len(ref["ee"]), vv=len(ref["vv"]),
+                contacts=len(ref["vf"]) + len(ref["ee"]) + len(ref["vv"]), halfspaces=len(hs_o))
+    x = torch.from_numpy(sc.x).cuda()
+    got, r, overflows = _build_with_growth(ctx, ccfr, torch, mesh, x, ccfr.make_params(sc.params))
+    assert overflows == 0
+    assert np.array_equal(H.sorted_pairs(got["vv"]), H.sorted_pairs(ref["vv"]))
+    mesh.close()
+    ctx.close()
+
+
+def test_nonfinite_position(env):
+    """A NaN or infinite coordinate leaves its primitives out of the build and
+    reports NONFINITE; the lists hold exactly the pairs among the other
+    primitives, and the context works normally afterwards."""
+    ccfr, oracle, torch = env
+    ctx = ccfr.Context(0)
+    sc = S.particles_in_box(nx=5, ny=5, nz=6, seed=5)
+    bad = [7, 31]
+    x = sc.x.copy()
+    x[bad[0], 1] = np.nan
+    x[bad[1], 2] = np.inf
+    mesh = ccfr.mesh_from_scene(ctx, sc)
+    prm = ccfr.make_params(sc.params)
+    c = ccfr.build_candidates(ctx, mesh, torch.from_numpy(x).cuda(), prm)
+    torch.cuda.synchronize()
+    got = ccfr.read_candidates(c)
+    code, info = ctx.sync_status(reset=True)
+    assert code == -4 and (info["status_bits"] & 64), info
+    ref = oracle.candidates(oracle.Mesh(sc), sc.params)      # the same scene, all finite
+    for kind in ("vf", "ee", "vv"):
+        want = H.sorted_pairs(ref[kind])
+        if kind == "vv":
+            want = want[~np.isin(want, bad).any(1)]
+        elif kind == "vf":
+            want = want[~np.isin(want[:, 0], bad)]
+        assert np.array_equal(H.sorted_pairs(got[kind]), want), kind
+    # a clean build on the same context
+    _, got, _ = H.gpu_candidates(ctx, mesh, torch.from_numpy(sc.x).cuda(), prm)
+    assert np.array_equal(H.sorted_pairs(got["vv"]), H.sorted_pairs(ref["vv"]))
+    ctx.sync_status(reset=True)
+    mesh.close()
+    ctx.close()
+
+
+def test_nonfinite_proposal(env):
+    """A proposal with a non-finite component is not moved (y = 0, halted) and
+    reports NONFINITE; every other vertex's output is unchanged, bit for bit."""
+    ccfr, oracle, torch = env
+    ctx = ccfr.Context(0)
+    sc = S.two_layers(n=10, seed=3)
+    om = oracle.Mesh(sc)
+    ref = oracle.candidates(om, sc.params)
+    off_o, hs_o, _ = oracle.regions(om, sc.params, ref)
+    hs32 = H.oracle_to_fp32(hs_o)
+    regions = ccfr.caller_regions(torch.from_numpy(off_o.astype(np.int32)).cuda(),
+                                  torch.from_numpy(hs32.view(np.uint8)).cuda())
+    rng = np.random.default_rng(4)
+    r32 = float(np.float32(sc.params.r))
+    y = (rng.normal(0.0, 2 * r32, sc.x.shape)).astype(np.float32)
+    with_regions = np.nonzero(np.diff(off_o) > 0)[0]
+    bad = [int(with_regions[0]), int(with_regions[-1]), 3]
+    y_bad = y.copy()
+    y_bad[bad[0], 0] = np.nan
+    y_bad[bad[1], 2] = -np.inf
+    y_bad[bad[2], 1] = np.inf
+    w_t = torch.from_numpy(sc.inv_mass).cuda()
+    outs = []
+    for yy in (y, y_bad):
+        out = torch.empty((sc.n_verts, 3), dtype=torch.float32).cuda()
+        halted = torch.zeros(sc.n_verts, dtype=torch.uint8).cuda()
+        ccfr.project_displacements(ctx, regions, w_t, torch.from_numpy(yy).cuda(), sc.params, out, halted)
+        torch.cuda.synchronize()
+        code, info = ctx.sync_status(reset=True)
+        outs.append((code, info, out.cpu().numpy(), halted.cpu().numpy()))
+    assert outs[0][0] == 0
+    code, info, yo, ho = outs[1]
+    assert code == -4 and (info["status_bits"] & 64), info
+    assert np.all(yo[bad] == 0.0) and np.all(ho[bad] == 1)
+    keep = np.setdiff1d(np.arange(sc.n_verts), bad)
+    assert np.array_equal(yo[keep], outs[0][2][keep])
+    assert np.array_equal(ho[keep], outs[0][3][keep])
+    ctx.close()
+
+
+def test_nonfinite_velocity_step(env):
+    """A NaN velocity makes its vertex's proposal non-finite: the substep
+    reports NONFINITE, no position or velocity becomes non-finite, and the
+    next substep from a clean state runs normally."""
+    ccfr, oracle, torch = env
+    ctx = ccfr.Context(0)
+    sc = S.two_layers(n=10, seed=3)
+    mesh = ccfr.mesh_from_scene(ctx, sc)
+    sp = ccfr.make_step_params(sc.step, sc.params)
+    x = torch.from_numpy(sc.x.copy()).cuda()
+    v0 = sc.v.copy()
+    v0[17] = np.nan
+    v = torch.from_numpy(v0).cuda()
+    ccfr.xpbd_step(ctx, mesh, x, v, sp)
+    code, info = ctx.sync_status(reset=True)
+    assert code == -4, info
+    assert np.isfinite(x.cpu().numpy()).all() and np.isfinite(v.cpu().numpy()).all()
+    v.copy_(torch.from_numpy(sc.v.copy()))
+    ccfr.xpbd_step(ctx, mesh, x, v, sp)
+    code, info = ctx.sync_status(reset=True)
+    assert code == 0, info
+    mesh.close()
+    ctx.close()
+
+
+def _degenerate_scene(n_pairs=5):
+    """`n_pairs` coincident particle pairs (D = 0), a zero-area triangle (three
+    collinear vertices) with an ordinary triangle's vertex in its box, and a
+    zero-length edge (two coincident vertices) beside an ordinary strand."""
+    pts = []
+    for k in range(n_pairs):
+        p = [0.1 * k, 0.0, 0.0]
+        pts += [p, p]
+    pts.append([0.1 * (n_pairs - 1) + 1e-3, 2e-3, 0.0])   # an ordinary partner of the last pair
+    parts = S.particles_mesh(np.array(pts), 1e4)
+    flat = S._Mesh(np.array([[0.0, 0.5, 0.0], [0.001, 0.5, 0.0], [0.002, 0.5, 0.0]]), [[0, 1, 2]], [1.0] * 3)
+    near = S._Mesh(np.array([[0.001, 0.501, 0.0], [0.01, 0.503, 0.0], [0.009, 0.51, 0.0]]), [[0, 1, 2]],
+                   [1.0] * 3)
+    zero = S.strands_mesh(np.array([[[0.002, 1.0, 0.0], [0.002, 1.0, 0.0]]]), np.ones(2))
+    line = S.strands_mesh(np.array([[[0.0, 1.001, 0.0], [0.002, 1.001, 0.001], [0.004, 1.001, 0.002]]]),
+                          np.ones(3))
+    return S.assemble("degenerate", [parts, flat, near, zero, line], S.Params(r=2e-3, xi=1e-3),
+                      S.StepParams(dt=1.0 / 240.0, iters=2, steps=1))
+
+
+def _expected_degenerate_pairs(sc, ref):
+    """Pairs whose closest points are undefined, by definition: coincident
+    particles, a triangle with exactly zero cross product, an edge of zero
+    length (the scene is built so that no other pair touches exactly)."""
+    x = sc.x.astype(np.float64)
+    n = 0
+    for a, b in np.asarray(ref["vv"]).reshape(-1, 2):
+        n += int(np.array_equal(x[a], x[b]))
+    for v, t in np.asarray(ref["vf"]).reshape(-1, 2):
+        a, b, c = x[sc.tris[t]]
+        n += int(np.all(np.cross(b - a, c - a) == 0.0))
+    for e, f in np.asarray(ref["ee"]).reshape(-1, 2):
+        ea, eb = sc.edges[e], sc.edges[f]
+        n += int(np.array_equal(x[ea[0]], x[ea[1]]) or np.array_equal(x[eb[0]], x[eb[1]]))
+    return n
+
+
+def test_degenerate_primitives(env):
+    """Degenerate pairs make no half-space on either side, the other pairs'
+    regions match the oracle, and the device counts each degenerate pair once."""
+    ccfr, oracle, torch = env
+    ctx = ccfr.Context(0)
+    sc = _degenerate_scene()
+    om = oracle.Mesh(sc)
+    ref = oracle.candidates(om, sc.params)
+    n_deg = _expected_degenerate_pairs(sc, ref)
+    assert n_deg == 8                        # 5 particle pairs, 1 vertex-face, 2 edge-edge
+    mesh = ccfr.mesh_from_scene(ctx, sc)
+    x = torch.from_numpy(sc.x).cuda()
+    c, got, _ = H.gpu_candidates(ctx, mesh, x, sc.params)
+    for kind in ("vf", "ee", "vv"):
+        assert np.array_equal(H.sorted_pairs(got[kind]), H.sorted_pairs(ref[kind])), kind
+    _, off, hs, info = H.gpu_regions(ctx, mesh, x, c, sc.params)
+    assert info["totals"][6] == n_deg, (info["totals"][6], n_deg)
+    off_o, hs_o, nd_o = oracle.regions(om, sc.params, ref)
+    assert nd_o >= n_deg                     # the oracle counts per vertex side
+    assert H.compare_regions(sc, sc.params, off, hs, off_o, hs_o, float(np.float32(sc.params.xi)),
+                             float(np.float32(sc.params.r))) > 0
+    mesh.close()
+    ctx.close()
+
+
+def test_all_static_and_empty(env):
+    """A mesh whose vertices all have zero inverse mass yields no pairs, no
+    half-spaces and zero displacements; a mesh with no vertices is accepted by
+    every call and yields nothing."""
+    ccfr, oracle, torch = env
+    ctx = ccfr.Context(0)
+    sc = S.two_layers(n=8, seed=2)
+    sc.inv_mass = np.zeros_like(sc.inv_mass)
+    assert sum(len(v) for k, v in oracle.candidates(oracle.Mesh(sc), sc.params).items()
+               if k in ("vf", "ee", "vv")) == 0
+    mesh = ccfr.mesh_from_scene(ctx, sc)
+    x = torch.from_numpy(sc.x).cuda()
+    c, got, _ = H.gpu_candidates(ctx, mesh, x, sc.params)
+    assert all(len(got[k]) == 0 for k in ("vf", "ee", "vv"))
+    r, off, hs, _ = H.gpu_regions(ctx, mesh, x, c, sc.params)
+    assert off[-1] == 0 and len(hs) == 0
+    y = torch.full((sc.n_verts, 3), 1e-3, dtype=torch.float32).cuda()
+    out = torch.empty_like(y)
+    ccfr.project_displacements(ctx, r, torch.from_numpy(sc.inv_mass).cuda(), y, sc.params, out)
+    torch.cuda.synchronize()
+    assert ctx.sync_status(reset=True)[0] == 0
+    assert np.all(out.cpu().numpy() == 0.0)
+    v = torch.zeros_like(x)
+    x1 = x.clone()
+    ccfr.xpbd_step(ctx, mesh, x1, v, ccfr.make_step_params(sc.step, sc.params))
+    assert ctx.sync_status(reset=True)[0] == 0
+    assert torch.equal(x1, x) and torch.count_nonzero(v).item() == 0
+    mesh.close()
+
+    empty = ccfr.Mesh(ctx, 0, np.zeros((0, 3), np.int32), None, np.zeros(0, np.float32))
+    x0 = torch.zeros((0, 3), dtype=torch.float32).cuda()
+    c, got, _ = H.gpu_candidates(ctx, empty, x0, sc.params)
+    assert all(len(got[k]) == 0 for k in ("vf", "ee", "vv"))
+    r, off, hs, _ = H.gpu_regions(ctx, empty, x0, c, sc.params)
+    assert list(off) == [0] and len(hs) == 0
+    ccfr.project_displacements(ctx, r, torch.zeros(0).cuda(), x0, sc.params, torch.zeros((0, 3)).cuda())
+    ccfr.xpbd_step(ctx, empty, x0, torch.zeros((0, 3)).cuda(), ccfr.make_step_params(sc.step, sc.params))
+    assert ctx.sync_status(reset=True)[0] == 0
+    empty.close()
+    ctx.close()
+
+
+def test_invalid_arguments(env):
+    """Out-of-range parameters, indices and masses are INVALID_ARG; buffers of
+    the wrong size, type or device are refused before any launch."""
+    ccfr, oracle, torch = env
+    ctx = ccfr.Context(0)
+    other = ccfr.Context(0)
+    sc = S.two_layers(n=6, seed=1)
+    mesh = ccfr.mesh_from_scene(ctx, sc)
+    x = torch.from_numpy(sc.x).cuda()
+
+    def code_of(fn):
+        with pytest.raises(ccfr.CcfrError) as e:
+            fn()
+        return e.value.code
+
+    for bad in (dict(r=0.0), dict(r=math.nan), dict(xi=-1e-3), dict(max_passes=0), dict(eps_retract=-1.0)):
+        p = S.Params(**{**dict(r=sc.params.r, xi=sc.params.xi), **bad})
+        assert code_of(lambda: ccfr.build_candidates(ctx, mesh, x, p)) == -1, bad
+    bad_step = S.StepParams(dt=0.0)
+    assert code_of(lambda: ccfr.xpbd_step(ctx, mesh, x.clone(), torch.zeros_like(x),
+                                          ccfr.make_step_params(bad_step, sc.params))) == -1
+    # a mesh of another context
+    assert code_of(lambda: ccfr.build_candidates(other, mesh, x, sc.params)) == -1
+    # topology and masses
+    n = sc.n_verts
+    assert code_of(lambda: ccfr.Mesh(ctx, n, np.array([[0, 1, n]]), None, sc.inv_mass)) == -1
+    assert code_of(lambda: ccfr.Mesh(ctx, n, np.zeros((0, 3)), np.array([[2, 2]]), sc.inv_mass)) == -1
+    w = sc.inv_mass.copy()
+    w[3] = -1.0
+    assert code_of(lambda: ccfr.Mesh(ctx, n, sc.tris, None, w)) == -1
+    w[3] = np.nan
+    assert code_of(lambda: ccfr.Mesh(ctx, n, sc.tris, None, w)) == -1
+    assert code_of(lambda: ctx.set_tuning(cell_scale=0.1)) == -1
+    assert code_of(lambda: ctx.set_tuning(pair_split=2)) == -1
+    # buffers the kernels would index past their end, or could not read
+    for xx in (x[:-1], x.double(), x.cpu(), x.t()):
+        with pytest.raises(ValueError):
+            ccfr.build_candidates(ctx, mesh, xx, sc.params)
+    with pytest.raises(ValueError):
+        ccfr.Mesh(ctx, n, sc.tris, None, sc.inv_mass[:-1])
+    # nothing above reached the device
+    torch.cuda.synchronize()
+    assert ctx.sync_status(reset=True)[0] == 0
+    mesh.close()
+    other.close()
+    ctx.close()
