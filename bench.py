@@ -88,10 +88,10 @@ TRAFFIC_PROFILES = {("c1", "pair_emission"): ("profiles/pair_emission_c1.md",
                                               "paper_2607_26901_amd/csrc/k_broadphase.hip")}
 
 
-def measured_traffic(workload, kernel):
+def measured_traffic(workload, kernel, knobs):
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled) from the
-    committed rocprofv3 summary, or None if there is none or the kernel's source
-    has changed since it was taken."""
+    committed rocprofv3 summary, or None if there is none, the kernel's source
+    has changed since it was taken, or it was taken with other knobs."""
     from paper_2607_26901_amd import profiling
     entry = TRAFFIC_PROFILES.get((workload, kernel))
     if entry is None:
@@ -99,6 +99,8 @@ def measured_traffic(workload, kernel):
     summ = profiling.read_summary(os.path.join(ROOT, entry[0]))
     src = os.path.join(ROOT, entry[1])
     if "traffic_bytes_per_launch" not in summ or summ.get("source_sha256") != profiling.sha256(src):
+        return None
+    if summ.get("knobs") != profiling.knobs_key(knobs):
         return None
     return float(summ["traffic_bytes_per_launch"])
 
@@ -197,6 +199,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the cell-size autotuner (default cell)")
     ap.add_argument("--cell-scale", type=float, default=None, help="fixed grid cell scale (skips the tuner)")
     ap.add_argument("--pair-split", type=int, default=None, help="fixed lanes per broad-phase query (skips the tuner)")
+    ap.add_argument("--pair-reuse", type=int, default=None,
+                    help="fixed solver iterations per candidate build (skips the tuner)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (scale for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -237,35 +241,46 @@ def main():
         x.copy_(x0)
         v.copy_(v0)
 
-    # capacity probe: run the steps once and grow any list that overflowed
-    for attempt in range(4):
-        reset()
-        ctx.sync_status(reset=True)
-        for _ in range(K):
-            ccfr.xpbd_step(ctx, mesh, x, v, sp)
-        code, info = ctx.sync_status(reset=True)
-        log(f"[bench] capacity probe {attempt}: status {code} need {info['need']}")
-        if code == 0:
-            break
-        if code != -2:
-            raise ccfr.CcfrError(code, "capacity probe")
-        nd = info["need"]
-        ctx.reserve(vf=int(nd[0] * 1.5) + 1024, ee=int(nd[1] * 1.5) + 1024, vv=int(nd[2] * 1.5) + 1024,
-                    contacts=int(nd[3] * 1.5) + 1024, halfspaces=int(nd[4] * 1.5) + 1024)
-    else:
+    def capacity_probe(keep_at=None):
+        """Run the K steps once, growing any list that overflowed; returns the
+        state after step `keep_at` of the run that fitted."""
+        kept = None
+        for attempt in range(4):
+            reset()
+            ctx.sync_status(reset=True)
+            for k in range(K):
+                ccfr.xpbd_step(ctx, mesh, x, v, sp)
+                if k + 1 == keep_at:
+                    kept = (x.clone(), v.clone())
+            code, info = ctx.sync_status(reset=True)
+            log(f"[bench] capacity probe {attempt}: status {code} need {info['need']}")
+            if code == 0:
+                return kept
+            if code != -2:
+                raise ccfr.CcfrError(code, "capacity probe")
+            ctx.grow(info)
         raise RuntimeError("capacity probe did not converge")
 
-    # grid cell size: fixed, default, or picked by the autotuner on the first steps
+    # knobs: fixed, default, or picked by the autotuner on steps from the
+    # middle of the run (the contact state the timed steps spend most time in)
+    fixed = {k: val for k, val in (("cell_scale", args.cell_scale), ("pair_split", args.pair_split),
+                                    ("pair_reuse", args.pair_reuse)) if val is not None}
     tuning = None
-    if args.cell_scale is not None or args.pair_split is not None:
-        ctx.set_tuning(cell_scale=args.cell_scale, pair_split=args.pair_split)
+    if fixed:
+        ctx.set_tuning(**fixed)
+        capacity_probe()
         tuning = dict(ctx.get_tuning(), source="fixed")
     elif not args.no_tune:
         from paper_2607_26901_amd import autotune
-        reset()
+        mid = capacity_probe(keep_at=max(1, K // 2))
+        x.copy_(mid[0])
+        v.copy_(mid[1])
         tuning = autotune.tune_mesh(ctx, mesh, x, v, sp, steps=min(4, K))
-        tuning["source"] = "autotuned on the first steps"
+        tuning["source"] = f"autotuned on {min(4, K)} steps from step {max(1, K // 2)}"
         log(f"[bench] tuning: {tuning}")
+        capacity_probe()                     # list sizes for the chosen knobs
+    else:
+        capacity_probe()
 
     # warmup (the first step records the step graph)
     reset()
@@ -298,7 +313,9 @@ def main():
     value = updates / wall
     tot = info["totals"]
     n_builds = max(tot[9], 1)
-    P = (tot[0] + tot[1] + tot[2]) / n_builds
+    reuse = ctx.get_tuning()["pair_reuse"]
+    n_cand_builds = K * ((iters + reuse - 1) // reuse)
+    P = (tot[0] + tot[1] + tot[2]) / n_cand_builds
     Hh = tot[3] / n_builds
     Cc = tot[8] / n_builds
     used = np.zeros(sc.n_verts, bool)
@@ -323,7 +340,8 @@ def main():
         "p50_step_ms": float(np.percentile(step_ms, 50)),
         "p99_step_ms": float(np.percentile(step_ms, 99)),
         "gpu_ms_per_step": float(step_ms.mean()),
-        "per_iteration": {"pairs": P, "contacts": Cc, "halfspaces": Hh,
+        "per_iteration": {"pairs_per_candidate_build": P, "candidate_builds_per_step": n_cand_builds // K,
+                          "contacts": Cc, "halfspaces": Hh,
                           "violating_vertices": tot[4] / n_builds, "halted_vertices": tot[5] / n_builds},
         "halted_fraction_of_violating": (tot[5] / tot[4]) if tot[4] else 0.0,
         "tuning": tuning if tuning is not None else dict(ctx.get_tuning(), source="default"),
@@ -348,20 +366,25 @@ def main():
             raise ccfr.CcfrError(code, "profiled pass")
         ptot = pinfo["totals"]
         nb = max(ptot[9], 1)
-        pP, pC, pH = (ptot[0] + ptot[1] + ptot[2]) / nb, ptot[8] / nb, ptot[3] / nb
+        # pairs of one candidate list (written once per build, read by every
+        # iteration's narrow phase), contacts and half-spaces per iteration
+        n_lists = max(stage_launches[1], 1)
+        pP, pC, pH = (ptot[0] + ptot[1] + ptot[2]) / n_lists, ptot[8] / nb, ptot[3] / nb
         per_launch = stage_ms / np.maximum(stage_launches, 1)
         result["stage_ms_per_step"] = {name: float(stage_ms[i] / K) for i, name in enumerate(ccfr.STAGES)}
-        singles = {"pair_emission": 1, "contacts": 2, "projection": 5}
+        # stages that are one kernel each (the projection stage is three)
+        singles = {"pair_emission": 1, "contacts": 2}
         dom = max(singles, key=lambda k: stage_ms[singles[k]])
         i = singles[dom]
         B = kernel_bytes(dom, sc.n_verts, sc.n_tris, sc.n_edges, n_free, pP, pC, pH)
         achieved = B / (per_launch[i] * 1e-3) / 1e9
         result["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                              "traffic": measured_traffic(args.workload, dom),
+                              "traffic": measured_traffic(args.workload, dom, ctx.get_tuning()),
                               "avg_launch_us": float(per_launch[i] * 1e3), "algorithmic_bytes": float(B)}
         it_ms = stage_ms.sum() / max(stage_launches[5], 1)
-        Bit = 60 * sc.n_verts + 24 * sc.n_tris + 16 * sc.n_edges + 16 * pP + 52 * pH
+        Bit = (60 * sc.n_verts + 24 * sc.n_tris + 16 * sc.n_edges + 8 * pP * (1 + n_lists / max(nb, 1))
+               + 52 * pH)
         result["iteration_roofline"] = {"bytes": float(Bit), "ms": float(it_ms),
                                         "achieved_GBs": float(Bit / (it_ms * 1e-3) / 1e9),
                                         "frac": float(Bit / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)}

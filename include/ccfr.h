@@ -229,8 +229,9 @@ int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, 
  * Disabling profiling returns to the recorded graph. */
 int ccfr_profile_enable(ccfr_ctx* ctx, int enable);
 /* Waits for `stream`, then writes per stage the milliseconds summed over the
- * iterations of the most recent substep (ms[6]) and its launch count per stage
- * (launches[6], nullable). */
+ * iterations of the most recent substep (ms[6]) and how often each stage ran
+ * (launches[6], nullable: the iterations, or for stages 0 and 1 the candidate
+ * builds). */
 int ccfr_profile_read(ccfr_ctx* ctx, ccfr_stream stream, float* ms, int32_t* launches);
 
 /* ---- tuning ----
@@ -241,11 +242,22 @@ int ccfr_profile_read(ccfr_ctx* ctx, ccfr_stream stream, float* ms, int32_t* lau
  *               in [0.25, 4], default 1.
  *   pair_split  lanes per broad-phase query: 1 (the whole 3 x 3 x 3 stencil),
  *               3 (one z layer each) or 9 (one row each); default 1.
+ *   pair_reuse  solver iterations of a substep (ccfr_xpbd_step, ccfr_batch_step)
+ *               that share one candidate build, 1..4 (0 reads as 1); default 1.
+ *               A build serving k iterations widens the box of every primitive
+ *               with a moving vertex by k - 1 times the most a vertex can move in
+ *               one iteration (r, from the clamp of Alg. 4, plus the FP32
+ *               rounding of the position update), so its list holds every pair
+ *               whose boxes overlap at any of those iterations.  The narrow
+ *               phase still keeps exactly the pairs with phi < 2r at the current
+ *               positions, so regions and results are those of a build per
+ *               iteration, bit for bit; the lists are longer.
  * Setting them invalidates recorded step graphs (they are recorded again). */
 typedef struct {
     float cell_scale;
     int32_t pair_split;
-    int32_t reserved[2];   /* 0 */
+    int32_t pair_reuse;
+    int32_t reserved;      /* 0 */
 } ccfr_tuning;
 int ccfr_set_tuning(ccfr_ctx* ctx, const ccfr_tuning* tuning);
 int ccfr_get_tuning(const ccfr_ctx* ctx, ccfr_tuning* tuning);

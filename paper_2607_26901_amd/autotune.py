@@ -1,14 +1,17 @@
 """Autotuner of the speed-only knobs of a context.
 
 The knobs are the grid cell size (`cell_scale`, a multiple of the default
-cell: 1.2 x the typical edge length + 2 pad) and the number of lanes that share
-one broad-phase query (`pair_split`).  Smaller cells put fewer entries in the
-buckets a query scans but bin long primitives one level up; more lanes per
-query shorten the walks of queries in dense folds at the price of more lanes.
-The best values depend on the mesh's edge lengths, its contact density and the
-pad.  Every setting gives the same candidate pairs (the box test alone decides
-them), so the tuner only times: it runs the same work once per setting, keeps
-the fastest, and caches the choice per size class in a JSON file.
+cell: 1.2 x the typical edge length + 2 pad), the number of lanes that share
+one broad-phase query (`pair_split`) and the number of solver iterations that
+share one candidate build inside a substep (`pair_reuse`).  Smaller cells put
+fewer entries in the buckets a query scans but bin long primitives one level
+up; more lanes per query shorten the walks of queries in dense folds at the
+price of more lanes; sharing a build saves grid builds and queries at the price
+of longer lists (the boxes are widened by the motion the shared iterations can
+make).  The best values depend on the mesh's edge lengths, its contact density
+and the pad.  Every setting gives the same regions and results, so the tuner
+only times: it runs the same work once per setting, keeps the fastest, and
+caches the choice per size class in a JSON file.
 """
 from __future__ import annotations
 
@@ -20,6 +23,7 @@ from . import ccfr
 
 CELL_SCALES = (0.5, 0.6, 0.7, 0.85, 1.0, 1.2)
 PAIR_SPLITS = (1, 3, 9)
+PAIR_REUSES = (1, 2, 3, 4)
 
 
 def size_class(n_verts, n_tris, n_edges, r, kind="mesh") -> str:
@@ -58,20 +62,22 @@ class Cache:
             pass
 
 
-def tune(ctx: ccfr.Context, run, candidates=CELL_SCALES, splits=PAIR_SPLITS, repeats: int = 2) -> dict:
+def tune(ctx: ccfr.Context, run, candidates=CELL_SCALES, splits=PAIR_SPLITS, reuses=(1,),
+         repeats: int = 2) -> dict:
     """Time `run()` (device milliseconds of a fixed piece of work, starting from
-    the same state every call) under each (cell scale, split); leave the
+    the same state every call) under each (cell scale, split, reuse); leave the
     fastest set."""
     times = {}
     for c in candidates:
         for sp in splits:
-            ctx.set_tuning(cell_scale=c, pair_split=sp)
-            run()                               # records the graph for this setting
-            times[(c, sp)] = min(run() for _ in range(repeats))
+            for ru in reuses:
+                ctx.set_tuning(cell_scale=c, pair_split=sp, pair_reuse=ru)
+                run()                           # records the graph for this setting
+                times[(c, sp, ru)] = min(run() for _ in range(repeats))
     best = min(times, key=times.get)
-    ctx.set_tuning(cell_scale=best[0], pair_split=best[1])
-    return {"cell_scale": best[0], "pair_split": best[1],
-            "ms": {f"{k[0]}/{k[1]}": v for k, v in times.items()}}
+    ctx.set_tuning(cell_scale=best[0], pair_split=best[1], pair_reuse=best[2])
+    return {"cell_scale": best[0], "pair_split": best[1], "pair_reuse": best[2],
+            "ms": {f"{k[0]}/{k[1]}/{k[2]}": v for k, v in times.items()}}
 
 
 def _events():
@@ -80,14 +86,15 @@ def _events():
 
 
 def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, steps: int = 4,
-              candidates=CELL_SCALES, splits=PAIR_SPLITS, cache: Cache | None = None,
+              candidates=CELL_SCALES, splits=PAIR_SPLITS, reuses=PAIR_REUSES, cache: Cache | None = None,
               key: str | None = None) -> dict:
     """Tune on `steps` single-mesh steps from the state (x, v), which is restored."""
     import torch
     if cache is not None and key is not None:
         hit = cache.get(key)
         if hit is not None:
-            ctx.set_tuning(cell_scale=hit["cell_scale"], pair_split=hit["pair_split"])
+            ctx.set_tuning(cell_scale=hit["cell_scale"], pair_split=hit["pair_split"],
+                           pair_reuse=hit.get("pair_reuse", 1))
             return dict(hit, cached=True)
     x0, v0 = x.clone(), v.clone()
 
@@ -108,7 +115,7 @@ def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, ste
             ctx.grow(info)                      # lists too small: grow and time again
         raise ccfr.CcfrError(-2, "tuning run")
 
-    out = tune(ctx, run, candidates, splits)
+    out = tune(ctx, run, candidates, splits, reuses)
     x.copy_(x0)
     v.copy_(v0)
     torch.cuda.synchronize()
@@ -117,7 +124,8 @@ def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, ste
     return dict(out, cached=False)
 
 
-def tune_batch(ctx: ccfr.Context, batch: ccfr.Batch, candidates=CELL_SCALES, splits=PAIR_SPLITS) -> dict:
+def tune_batch(ctx: ccfr.Context, batch: ccfr.Batch, candidates=CELL_SCALES, splits=PAIR_SPLITS,
+               reuses=PAIR_REUSES) -> dict:
     """Tune on one step of the resident batch; every trial is rolled back."""
     def run():
         for _ in range(4):
@@ -134,4 +142,4 @@ def tune_batch(ctx: ccfr.Context, batch: ccfr.Batch, candidates=CELL_SCALES, spl
             ctx.grow(info)
         raise ccfr.CcfrError(-2, "tuning run")
 
-    return tune(ctx, run, candidates, splits)
+    return tune(ctx, run, candidates, splits, reuses)

@@ -52,7 +52,8 @@ class StepParams(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("cell_scale", C.c_float), ("pair_split", C.c_int32), ("reserved", C.c_int32 * 2)]
+    _fields_ = [("cell_scale", C.c_float), ("pair_split", C.c_int32), ("pair_reuse", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class StatusInfo(C.Structure):
@@ -213,22 +214,28 @@ class Context:
 
 
     def grow(self, info, factor=1.5):
-        """Reserve the list sizes a CAPACITY status reported (info from sync_status)."""
+        """Reserve the list sizes a CAPACITY status reported (info from sync_status).
+        A primitive too large to bin (status bit 16) is not fixed by larger
+        lists: that raises CcfrError."""
+        if info["status_bits"] & 16:
+            raise CcfrError(-2, "a primitive's box is too large to bin (coordinates out of range)")
         nd = info["need"]
         self.reserve(vf=int(nd[0] * factor) + 1024, ee=int(nd[1] * factor) + 1024, vv=int(nd[2] * factor) + 1024,
                      contacts=int(nd[3] * factor) + 1024, halfspaces=int(nd[4] * factor) + 1024)
 
-    def set_tuning(self, cell_scale=None, pair_split=None):
+    def set_tuning(self, cell_scale=None, pair_split=None, pair_reuse=None):
         """Change any of the speed-only knobs (None keeps the current value)."""
         cur = self.get_tuning()
         t = Tuning(float(cur["cell_scale"] if cell_scale is None else cell_scale),
-                   int(cur["pair_split"] if pair_split is None else pair_split))
+                   int(cur["pair_split"] if pair_split is None else pair_split),
+                   int(cur["pair_reuse"] if pair_reuse is None else pair_reuse), 0)
         _check(self.lib.ccfr_set_tuning(self.h, C.byref(t)), "ccfr_set_tuning")
 
     def get_tuning(self) -> dict:
         t = Tuning()
         _check(self.lib.ccfr_get_tuning(self.h, C.byref(t)), "ccfr_get_tuning")
-        return {"cell_scale": float(t.cell_scale), "pair_split": int(t.pair_split)}
+        return {"cell_scale": float(t.cell_scale), "pair_split": int(t.pair_split),
+                "pair_reuse": int(t.pair_reuse)}
 
     def profile_enable(self, on=True):
         _check(self.lib.ccfr_profile_enable(self.h, int(bool(on))), "ccfr_profile_enable")

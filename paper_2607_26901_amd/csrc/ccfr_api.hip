@@ -191,8 +191,11 @@ bool step_params_ok(const ccfr_step_params* sp) {
 }
 
 // Per-mesh device parameters: the box pad (one FP32 rounding of an FP64 sum) and
-// a grid cell large enough that typical primitives span at most two cells.
-MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell_scale) {
+// a grid cell large enough that typical primitives span at most two cells.  A
+// build that serves skin_iters more iterations widens moving boxes by about
+// skin_iters r per side; the cell is sized for that width (with slack for the
+// rounding term), so that a particle's box still fits one cell.
+MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell_scale, int skin_iters) {
     MeshParams m{};
     m.r = p->r;
     m.xi = p->xi;
@@ -200,8 +203,8 @@ MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell
     m.two_r = 2.0f * p->r;
     m.eps_retract = p->eps_retract;
     m.eps_plesnik = p->eps_plesnik;
-    const double h = std::max(2.02 * (double)m.pad,
-                              (double)cell_scale * (1.2 * (double)typ_len + 2.0 * (double)m.pad));
+    const double wide = (double)m.pad + 1.25 * skin_iters * (double)p->r;
+    const double h = std::max(2.02 * wide, (double)cell_scale * (1.2 * (double)typ_len + 2.0 * wide));
     m.h = (float)h;
     m.inv_h = (float)(1.0 / h);
     m.max_passes = p->max_passes;
@@ -211,7 +214,7 @@ MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell
 
 namespace {
 
-Scene make_scene(const ccfr_mesh* m, const float* x, const ccfr_params* p) {
+Scene make_scene(const ccfr_mesh* m, const float* x, const ccfr_params* p, int skin_iters = 0) {
     Scene sc{};
     sc.narrow_fp32 = m->ctx->narrow_fp32 ? 1 : 0;
     sc.n_verts = m->n_verts;
@@ -226,7 +229,7 @@ Scene make_scene(const ccfr_mesh* m, const float* x, const ccfr_params* p) {
     sc.is_free = m->is_free_d;
     sc.prm.table = nullptr;
     sc.prm.vmesh = nullptr;
-    sc.prm.one = mesh_params(p, m->typ_len, 0, m->ctx->cell_scale);
+    sc.prm.one = mesh_params(p, m->typ_len, 0, m->ctx->cell_scale, skin_iters);
     return sc;
 }
 
@@ -318,15 +321,30 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
     // counters and level masks start clear; each iteration's close clears them
     // for the next one
     launch_reset_build(ctx->counters_d, ctx->level_mask, plan.n_meshes, s);
+    // a candidate build serves `reuse` consecutive iterations (the last group
+    // of the substep may be shorter); its boxes are widened for the iterations
+    // after the first
+    const int reuse = std::max(1, ctx->pair_reuse);
     for (int it = 0; it < plan.iters; ++it) {
         const Marks mk{ctx, it, s};
-        enqueue_candidates(ctx, sc, plan.n_meshes, s, mk, false);
+        const int first = it - it % reuse;
+        const int group = std::min(reuse, plan.iters - first);
+        if (it == first) {
+            Scene sb = sc;
+            sb.skin_iters = group - 1;
+            enqueue_candidates(ctx, sb, plan.n_meshes, s, mk, false);
+        } else {
+            for (int st = 0; st < 2; ++st) {      // no build: empty stage marks
+                mk.mark(st, 0);
+                mk.mark(st, 1);
+            }
+        }
         enqueue_regions(ctx, sc, ctx->vf, ctx->ee, ctx->vv, counts_ptr(ctx), ctx->cap_vf, ctx->cap_ee,
                         ctx->cap_vv, s, mk, true);
         mk.mark(4, 0);
         launch_close_iteration(ctx->x_pred, ctx->p, 3LL * n, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
                                ctx->offsets, PairCaps{ctx->cap_vf, ctx->cap_ee, ctx->cap_vv}, ctx->cap_contacts,
-                               ctx->cap_hs, s);
+                               ctx->cap_hs, it == first + group - 1, s);
         if (plan.has_stretch) {
             for (size_t c = 0; c < plan.col_total.size(); ++c)
                 launch_stretch_segments(plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[c],
@@ -493,7 +511,7 @@ namespace {
 
 StepPlan mesh_plan(ccfr_ctx* ctx, const ccfr_mesh* m, float* x, float* v, const ccfr_step_params* sp) {
     StepPlan plan;
-    plan.sc = make_scene(m, x, &sp->collision);
+    plan.sc = make_scene(m, x, &sp->collision, ctx->pair_reuse - 1);
     plan.x = x;
     plan.v = v;
     plan.n_meshes = 1;
@@ -754,7 +772,10 @@ int ccfr_xpbd_step(ccfr_ctx* ctx, const ccfr_mesh* mesh, float* x_dev, float* v_
     rc = ensure_prof_events(ctx, sp->iters);
     if (rc) return rc;
     const StepPlan plan = mesh_plan(ctx, mesh, x_dev, v_dev, sp);
-    if (ctx->profiling) ctx->prof_last_iters = sp->iters;
+    if (ctx->profiling) {
+        ctx->prof_last_iters = sp->iters;
+        ctx->prof_last_reuse = ctx->pair_reuse;
+    }
     // profiled steps run eagerly: the stage events bracket the launches on `s`
     if (!ctx->use_graphs || ctx->profiling) {
         enqueue_step(ctx, plan, s);
@@ -797,11 +818,13 @@ int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, 
 
 int ccfr_set_tuning(ccfr_ctx* ctx, const ccfr_tuning* t) {
     if (!ctx || !t || !std::isfinite(t->cell_scale) || t->cell_scale < 0.25f || t->cell_scale > 4.0f ||
-        (t->pair_split != 1 && t->pair_split != 3 && t->pair_split != 9))
+        (t->pair_split != 1 && t->pair_split != 3 && t->pair_split != 9) || t->pair_reuse < 0 || t->pair_reuse > 4)
         return CCFR_ERR_INVALID_ARG;
-    if (t->cell_scale != ctx->cell_scale || t->pair_split != ctx->pair_split) {
+    const int reuse = std::max(1, (int)t->pair_reuse);
+    if (t->cell_scale != ctx->cell_scale || t->pair_split != ctx->pair_split || reuse != ctx->pair_reuse) {
         ctx->cell_scale = t->cell_scale;
         ctx->pair_split = t->pair_split;
+        ctx->pair_reuse = reuse;
         ctx->tune_generation++;
         ctx->generation++;          // recorded graphs carry the old settings
         drop_graph(ctx);
@@ -814,6 +837,7 @@ int ccfr_get_tuning(const ccfr_ctx* ctx, ccfr_tuning* t) {
     *t = ccfr_tuning{};
     t->cell_scale = ctx->cell_scale;
     t->pair_split = ctx->pair_split;
+    t->pair_reuse = ctx->pair_reuse;
     return CCFR_OK;
 }
 
@@ -841,7 +865,9 @@ int ccfr_profile_read(ccfr_ctx* ctx, ccfr_stream stream, float* ms, int32_t* lau
             total += t;
         }
         ms[st] = total;
-        if (launches) launches[st] = std::min(iters, ctx->prof_iters);
+        // stages 0 and 1 run once per candidate build
+        const int reuse = st < 2 ? std::max(1, ctx->prof_last_reuse) : 1;
+        if (launches) launches[st] = (std::min(iters, ctx->prof_iters) + reuse - 1) / reuse;
     }
     return CCFR_OK;
 }

@@ -167,7 +167,7 @@ int slot_salt(int slot) { return (int)(0x9E3779B1u * (uint32_t)(slot + 1)); }
 // Parameters of every resident slot again, after a tuning change.
 int refresh_table(ccfr_batch* b, hipStream_t s) {
     for (int k = 0; k < b->max_slots; ++k)
-        if (b->slot_busy[k]) b->table_h[k] = mesh_params(&b->coll_h[k], b->typ_h[k], slot_salt(k), b->ctx->cell_scale);
+        if (b->slot_busy[k]) b->table_h[k] = mesh_params(&b->coll_h[k], b->typ_h[k], slot_salt(k), b->ctx->cell_scale, b->ctx->pair_reuse - 1);
     HIP_OK(hipMemcpyAsync(b->table_d, b->table_h.data(), sizeof(MeshParams) * b->table_h.size(),
                           hipMemcpyHostToDevice, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -421,7 +421,7 @@ int ccfr_batch_add(ccfr_batch* b, int32_t n_verts, const int32_t* tris, int32_t 
     if (!h.has_stretch) m.color_begin.assign(1, 0);
     b->coll_h[sl] = sp->collision;
     b->typ_h[sl] = h.typ_len;
-    b->table_h[sl] = mesh_params(&sp->collision, h.typ_len, slot_salt(sl), b->ctx->cell_scale);
+    b->table_h[sl] = mesh_params(&sp->collision, h.typ_len, slot_salt(sl), b->ctx->cell_scale, b->ctx->pair_reuse - 1);
     HIP_OK(hipMemcpyAsync(b->table_d + sl, &b->table_h[sl], sizeof(MeshParams), hipMemcpyHostToDevice, s));
     // pageable sources: the copies must finish before the host vectors go away
     HIP_OK(hipStreamSynchronize(s));
@@ -477,7 +477,10 @@ int ccfr_batch_step(ccfr_batch* b, ccfr_stream stream) {
     }
     rc = ensure_prof_events(ctx, b->sp.iters);
     if (rc) return rc;
-    if (ctx->profiling) ctx->prof_last_iters = b->sp.iters;
+    if (ctx->profiling) {
+        ctx->prof_last_iters = b->sp.iters;
+        ctx->prof_last_reuse = ctx->pair_reuse;
+    }
     {
         const Pool& P = b->pool[b->cur];
         const Pool& Q = b->pool[1 - b->cur];

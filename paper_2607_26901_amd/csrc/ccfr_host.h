@@ -92,6 +92,7 @@ struct ccfr_ctx {
     bool narrow_fp32 = false;   // narrow-phase arithmetic in FP32 (measurement option)
     float cell_scale = 1.0f;    // grid cell size relative to the default
     int pair_split = 1;         // lanes per broad-phase query (1, 3 or 9)
+    int pair_reuse = 1;         // solver iterations per candidate build inside a substep
     long long tune_generation = 0;
 
     // grid
@@ -138,6 +139,7 @@ struct ccfr_ctx {
     bool profiling = false;
     int prof_iters = 0;        // events allocated for this many iterations
     int prof_last_iters = 0;   // iterations of the last profiled step
+    int prof_last_reuse = 1;   // iterations per candidate build in that step
     std::vector<hipEvent_t> prof_events;
 };
 
@@ -187,7 +189,7 @@ int ensure_sizes(ccfr_ctx* ctx, long long n_verts, long long n_tris, long long n
                  int n_meshes);
 bool params_ok(const ccfr_params* p);
 bool step_params_ok(const ccfr_step_params* sp);
-MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell_scale);
+MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell_scale, int skin_iters = 0);
 int ensure_prof_events(ccfr_ctx* ctx, int iters);
 void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s);
 // Records the plan as a graph into *g (replacing it) and launches it on s.

@@ -96,12 +96,16 @@ __device__ __forceinline__ void finalize_regions_body(DevCounters* c, int32_t n_
 }
 
 // Per-build counters back to zero (one thread); level masks are cleared apart.
-__device__ __forceinline__ void reset_build_counters(DevCounters* c) {
-    c->n_vf = c->n_ee = c->n_vv = 0;
-    c->n_large_t = c->n_large_e = 0;
+__device__ __forceinline__ void reset_region_counters(DevCounters* c) {
     c->n_contacts = 0;
     c->n_viol = 0;
     c->n_viol_b = 0;
+}
+
+__device__ __forceinline__ void reset_build_counters(DevCounters* c) {
+    c->n_vf = c->n_ee = c->n_vv = 0;
+    c->n_large_t = c->n_large_e = 0;
+    reset_region_counters(c);
 }
 
 __device__ __forceinline__ void spread_add(DevCounters* c, int which, unsigned long long n) {
@@ -170,6 +174,7 @@ struct Scene {
     const int32_t* free_list;   // [n_free] free particles (vertices in no edge / triangle)
     const uint8_t* is_free;     // [n_verts]
     int32_t narrow_fp32;        // 1: narrow-phase arithmetic in FP32 instead of FP64
+    int32_t skin_iters;         // candidate builds: further iterations the lists must cover
     ParamSrc prm;
 };
 
@@ -238,15 +243,15 @@ void launch_predict(int n, const float* x, const float* v, const float* inv_mass
 void launch_fill_zero(float* p, int64_t n, hipStream_t s);
 void launch_copy(const float* src, float* dst, int64_t n, hipStream_t s);
 // Between the region build and the stretch pass of a substep iteration: close
-// the candidate and region builds (overflow bits, totals), clear the per-build
-// counters and the level masks for the next build, and copy the prediction
-// into p.
+// the region build and, unless the next iteration reuses the lists, the
+// candidate build (overflow bits, totals), clear the per-build counters (and
+// then the level masks) for the next build, and copy the prediction into p.
 struct PairCaps {
     int64_t vf, ee, vv;
 };
 void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounters* c, uint32_t* level_mask,
                             int n_meshes, int32_t n_verts, const int32_t* offsets, PairCaps caps,
-                            int64_t cap_contacts, int64_t cap_hs, hipStream_t s);
+                            int64_t cap_contacts, int64_t cap_hs, bool close_pairs, hipStream_t s);
 void launch_stretch_segments(const int32_t* edges_sorted, const float* rest_sorted, const int2* segs, int32_t nseg,
                              int32_t total, const float* inv_mass, float* p, float* lambda_sorted, float alpha_t,
                              hipStream_t s);

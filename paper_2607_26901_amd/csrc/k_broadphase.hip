@@ -103,9 +103,22 @@ __device__ __forceinline__ Target target_of(const Scene& sc, int t) {
     return g;
 }
 
+// How far a box must reach beyond `pad` so that a list built now holds every
+// pair whose pad-boxes overlap within the next `k` iterations.  A vertex moves
+// by the projected displacement, |y| <= r (per coordinate, after its rounding
+// to FP32, r (1 + 2^-23)), plus the rounding of x + y (at most 2^-24 |x + y|);
+// the bound below takes each term with ample slack.  The FP32 sum pad + reach
+// is rounded up by one step so that it is never below the exact sum.
+__device__ __forceinline__ float skin_pad(float pad, float r, int k, float maxabs) {
+    const float kf = (float)k;
+    const float reach = kf * (r * (1.0f + 0x1p-18f) + (maxabs + (kf + 1.0f) * 2.0f * r) * 0x1p-21f);
+    return __int_as_float(__float_as_int(pad + reach) + 1);    // positive and finite: one step up
+}
+
 // Box of a target and its static flag; false if a coordinate is not finite.
-__device__ __forceinline__ bool target_box(const Scene& sc, const Target& g, float pad, float lo[3],
-                                           float hi[3], bool* is_static) {
+// skin > 0 widens the box of a target with a moving vertex (skin_pad).
+__device__ __forceinline__ bool target_box(const Scene& sc, const Target& g, float pad, float r, int skin,
+                                           float lo[3], float hi[3], bool* is_static) {
     float p[3];
     load3(sc.x, g.v[0], p);
     bool fin = finite3(p);
@@ -119,6 +132,11 @@ __device__ __forceinline__ bool target_box(const Scene& sc, const Target& g, flo
             mn[k] = fminf(mn[k], p[k]);
             mx[k] = fmaxf(mx[k], p[k]);
         }
+    }
+    if (skin > 0 && !st) {
+        float m = 0.0f;
+        for (int k = 0; k < 3; ++k) m = fmaxf(m, fmaxf(fabsf(mn[k]), fabsf(mx[k])));
+        pad = skin_pad(pad, r, skin, m);
     }
     for (int k = 0; k < 3; ++k) {
         lo[k] = __fsub_rn(mn[k], pad);
@@ -215,11 +233,15 @@ __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCo
     bool st;
     int clo[3];
     int level = -2;
-    if (!target_box(sc, tg, P.pad, lo, hi, &st)) {
+    if (!target_box(sc, tg, P.pad, P.r, sc.skin_iters, lo, hi, &st)) {
         atomicOr(&c->status, ST_NONFINITE);
     } else {
         level = entry_level(tg, lo, hi, P.inv_h, clo);
-        if (level < 0) atomicOr(&c->status, ST_LARGE);   // a box wider than h 2^24: not binned
+        // a box wider than h 2^24 is not binned; nor is a particle box wider
+        // than a cell (particle pairs are looked up on the finest level only),
+        // which takes coordinates so large that their FP32 spacing nears the pad
+        if (tg.kind == KIND_VV && level > 0) level = -1;
+        if (level < 0) atomicOr(&c->status, ST_LARGE);
     }
     // every lane still in the kernel takes part in the wave-wide OR
     mark_level(g.level_mask, mesh, (level < 0 || tg.kind == KIND_VX) ? 0u : (1u << level));

@@ -40,17 +40,23 @@ __global__ __launch_bounds__(kBlock) void k_copy(const float* src, float* dst, l
     if (i < n) dst[i] = src[i];
 }
 
+// End of an iteration's builds: closes the region build, and the candidate
+// build too when no later iteration reuses its lists (close_pairs), then
+// clears what the next build counts; p starts again from the prediction.
 __global__ __launch_bounds__(kBlock) void k_close_iteration(const float* x_pred, float* p, long long n3,
                                                             DevCounters* c, uint32_t* level_mask, int n_meshes,
                                                             int32_t n_verts, const int32_t* offsets,
-                                                            PairCaps caps, int64_t cap_contacts, int64_t cap_hs) {
+                                                            PairCaps caps, int64_t cap_contacts, int64_t cap_hs,
+                                                            int close_pairs) {
     const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (i == 0) {
-        finalize_pairs_body(c, caps.vf, caps.ee, caps.vv);
+        if (close_pairs) finalize_pairs_body(c, caps.vf, caps.ee, caps.vv);
         finalize_regions_body(c, n_verts, offsets, cap_contacts, cap_hs);
-        reset_build_counters(c);
+        if (close_pairs) reset_build_counters(c);
+        else reset_region_counters(c);
     }
-    for (long long m = i; m < n_meshes; m += (long long)gridDim.x * kBlock) level_mask[m] = 0u;
+    if (close_pairs)
+        for (long long m = i; m < n_meshes; m += (long long)gridDim.x * kBlock) level_mask[m] = 0u;
     if (i < n3) p[i] = x_pred[i];
 }
 
@@ -118,10 +124,10 @@ void launch_copy(const float* src, float* dst, int64_t n, hipStream_t s) {
 
 void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounters* c, uint32_t* level_mask,
                             int n_meshes, int32_t n_verts, const int32_t* offsets, PairCaps caps,
-                            int64_t cap_contacts, int64_t cap_hs, hipStream_t s) {
+                            int64_t cap_contacts, int64_t cap_hs, bool close_pairs, hipStream_t s) {
     const long long n = std::max<long long>(std::max<long long>(n3, n_meshes), 1);
     hipLaunchKernelGGL(k_close_iteration, dim3(blocks_for(n)), dim3(kBlock), 0, s, x_pred, p, (long long)n3, c,
-                       level_mask, n_meshes, n_verts, offsets, caps, cap_contacts, cap_hs);
+                       level_mask, n_meshes, n_verts, offsets, caps, cap_contacts, cap_hs, close_pairs ? 1 : 0);
 }
 
 void launch_stretch_segments(const int32_t* edges_sorted, const float* rest_sorted, const int2* segs, int32_t nseg,

@@ -68,6 +68,12 @@ def sha256(path: str) -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
+def knobs_key(t: dict) -> str:
+    """The speed knobs a profile was taken with, as one comparable string."""
+    return f"cell_scale={float(t['cell_scale']):.3f} pair_split={int(t['pair_split'])} " \
+           f"pair_reuse={int(t.get('pair_reuse', 1))}"
+
+
 def read_summary(path: str) -> dict:
     """Machine-readable `key: value` lines of a summary written by main()."""
     out = {}
@@ -114,6 +120,8 @@ def main(argv=None) -> int:
             b = json.loads(f.readline())
         rl = b.get("roofline", {})
         facts["bench_avg_launch_us"] = f"{rl.get('avg_launch_us', float('nan')):.2f}"
+        if "tuning" in b:
+            facts["knobs"] = knobs_key(b["tuning"])
         facts["algorithmic_bytes_per_launch"] = f"{rl.get('algorithmic_bytes', float('nan')):.0f}"
     if a.fetch and a.write and a.copy_fetch and a.copy_write:
         fs, ws = copy_scale(a.copy_fetch, a.copy_mib), copy_scale(a.copy_write, a.copy_mib)

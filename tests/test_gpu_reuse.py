@@ -1,0 +1,122 @@
+"""A candidate build shared by several solver iterations of a substep (its
+boxes widened by the motion those iterations can make) changes speed only:
+whole substeps give the same positions and velocities, bit for bit, as a build
+per iteration, alone and in a batch."""
+import numpy as np
+import pytest
+
+from paper_2607_26901_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2607_26901_amd import ccfr
+    return ccfr.Context(0), ccfr, torch
+
+
+def _falling_layers(offset=0.0):
+    """Two stacked patches, the upper one moving down fast enough that the
+    clamp |y| <= r binds: vertices move the full bound in most iterations."""
+    sc = S.two_layers(n=14, seed=8, gap=2.5e-3, shift=(0.003, 0.001))
+    v = np.zeros_like(sc.x)
+    v[sc.n_verts // 2:, 2] = -0.6
+    x = sc.x.astype(np.float64) + offset
+    return sc.with_state(x=x.astype(np.float32), v=v.astype(np.float32))
+
+
+SCENES = {
+    "falling_layers": _falling_layers,
+    "falling_layers_far": lambda: _falling_layers(offset=300.0),      # FP32 spacing of 3e-5 m
+    "particles": lambda: S.particles_in_box(nx=5, ny=5, nz=6, seed=5),
+    "strands": lambda: S.strand_bundle(nx=4, ny=4, seg=20, seed=9),
+    "c1_folded": lambda: S.folded_cloth_state(S.c1(n=24, side=0.19), seed=3),
+}
+
+
+def _run(ctx, ccfr, torch, sc, steps):
+    mesh = ccfr.mesh_from_scene(ctx, sc)
+    x = torch.from_numpy(sc.x.copy()).cuda()
+    v = torch.from_numpy(sc.v.copy()).cuda()
+    sp = ccfr.make_step_params(sc.step, sc.params)
+    for _ in range(4):
+        x.copy_(torch.from_numpy(sc.x))
+        v.copy_(torch.from_numpy(sc.v))
+        for _ in range(steps):
+            ccfr.xpbd_step(ctx, mesh, x, v, sp)
+        code, info = ctx.sync_status(reset=True)
+        if code == 0:
+            mesh.close()
+            return x.cpu().numpy(), v.cpu().numpy(), info
+        assert code == -2, info
+        ctx.grow(info)
+    raise AssertionError("capacity did not converge")
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_reuse_is_bitwise_identical(env, name):
+    ctx, ccfr, torch = env
+    sc = SCENES[name]()
+    steps = 3
+    try:
+        ctx.set_tuning(pair_reuse=1)
+        x1, v1, info1 = _run(ctx, ccfr, torch, sc, steps)
+        assert info1["totals"][8] > 0                      # the steps have contacts
+        for reuse in (2, 3, 4):
+            ctx.set_tuning(pair_reuse=reuse)
+            assert ctx.get_tuning()["pair_reuse"] == reuse
+            x, v, info = _run(ctx, ccfr, torch, sc, steps)
+            assert np.array_equal(x, x1) and np.array_equal(v, v1), (name, reuse)
+            # the same contacts and half-spaces every iteration; longer lists
+            assert info["totals"][8] == info1["totals"][8] and info["totals"][3] == info1["totals"][3]
+            assert info["totals"][9] == info1["totals"][9]
+    finally:
+        ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1)
+
+
+def test_reuse_in_batch_equals_alone(env):
+    """Meshes of a batch stepped with shared builds end where each one ends
+    alone with a build per iteration."""
+    ctx, ccfr, torch = env
+    scs = [SCENES["falling_layers"](), SCENES["particles"](), SCENES["strands"]()]
+    for sc in scs[1:]:
+        sc.step = scs[0].step                 # one batch steps with one dt, gravity and iteration count
+    steps = 3
+    try:
+        ctx.set_tuning(pair_reuse=1)
+        alone = [_run(ctx, ccfr, torch, sc, steps)[:2] for sc in scs]
+        ctx.set_tuning(pair_reuse=3, cell_scale=0.85)
+        nv = sum(s.n_verts for s in scs)
+        b = ccfr.Batch(ctx, 8, nv, sum(len(s.tris) for s in scs) + 8, sum(len(s.edges) for s in scs) + 8)
+        slots = [b.add_scene(sc, ccfr.make_step_params(sc.step, sc.params)) for sc in scs]
+        done = 0
+        for _ in range(12):
+            b.step()
+            code, info = ctx.sync_status(reset=True)
+            if code == -2:
+                ctx.grow(info)
+                b.rollback()
+                continue
+            assert code == 0, info
+            done += 1
+            if done == steps:
+                break
+        assert done == steps
+        for sl, sc, (xa, va) in zip(slots, scs, alone):
+            xb, vb = b.read(sl)
+            assert np.array_equal(xb, xa) and np.array_equal(vb, va), sc.name
+        b.close()
+    finally:
+        ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1)
+
+
+def test_reuse_argument_range(env):
+    ctx, ccfr, torch = env
+    for bad in (-1, 5):
+        with pytest.raises(ccfr.CcfrError):
+            ctx.set_tuning(pair_reuse=bad)
+    ctx.set_tuning(pair_reuse=0)                           # reads as 1
+    assert ctx.get_tuning()["pair_reuse"] == 1

@@ -1,0 +1,50 @@
+"""Host logic of the rocprofv3 summaries: kernel statistics, per-dispatch
+counters, the copy-calibrated byte scale and the summary round trip that
+bench.py reads its traffic figure from."""
+import json
+
+import pytest
+
+from paper_2607_26901_amd import profiling
+
+
+def _write(path, header, rows):
+    path.write_text(",".join(header) + "\n" + "\n".join(",".join(str(c) for c in r) for r in rows) + "\n")
+    return str(path)
+
+
+def test_summary_round_trip(tmp_path):
+    stats = _write(tmp_path / "s.csv", ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"],
+                   [['"ccfr::k_pairs(ccfr::Scene, int)"', 4, 400000, 100000, 60.0],
+                    ["k_fill", 8, 80000, 10000, 12.0]])
+    cnt = ["Kernel_Name", "Counter_Value"]
+    fetch = _write(tmp_path / "f.csv", cnt, [["k_pairs", 1000.0], ["k_pairs", 3000.0], ["k_fill", 10.0]])
+    write = _write(tmp_path / "w.csv", cnt, [["k_pairs", 500.0], ["k_pairs", 500.0]])
+    # a 1 MiB copy counted as 512 KiB fetched and 1024 KiB written
+    cf = _write(tmp_path / "cf.csv", cnt, [["copy", 256.0], ["copy", 512.0]])
+    cw = _write(tmp_path / "cw.csv", cnt, [["copy", 1024.0]])
+    bench = tmp_path / "b.json"
+    bench.write_text(json.dumps({"roofline": {"avg_launch_us": 101.0, "algorithmic_bytes": 2.5e6},
+                                 "tuning": {"cell_scale": 0.7, "pair_split": 1, "pair_reuse": 3}}) + "\n")
+    src = tmp_path / "k.hip"
+    src.write_text("kernel source\n")
+    out = tmp_path / "summary.md"
+    assert profiling.main(["--stats", stats, "--fetch", fetch, "--write", write, "--copy-fetch", cf,
+                           "--copy-write", cw, "--copy-mib", "1", "--kernel", "k_pairs", "--source", str(src),
+                           "--bench", str(bench), "--command", "cmd", "--out", str(out)]) == 0
+    facts = profiling.read_summary(str(out))
+    assert facts["kernel"] == "k_pairs"
+    assert float(facts["rocprof_avg_us"]) == pytest.approx(100.0)
+    assert facts["fetch_kib_per_dispatch"] == "2000.0" and facts["write_kib_per_dispatch"] == "500.0"
+    assert float(facts["fetch_scale"]) == pytest.approx(2.0) and float(facts["write_scale"]) == pytest.approx(1.0)
+    # bytes = KiB counted x bytes per counted KiB
+    assert float(facts["traffic_bytes_per_launch"]) == pytest.approx(2000 * 2048 + 500 * 1024)
+    assert facts["source_sha256"] == profiling.sha256(str(src))
+    assert facts["knobs"] == profiling.knobs_key({"cell_scale": 0.7, "pair_split": 1, "pair_reuse": 3})
+    assert facts["dispatches_counted"] == "2/2"
+
+
+def test_knobs_key_defaults_and_distinguishes():
+    a = profiling.knobs_key({"cell_scale": 0.7, "pair_split": 1})
+    assert a == profiling.knobs_key({"cell_scale": 0.7000001, "pair_split": 1, "pair_reuse": 1})
+    assert a != profiling.knobs_key({"cell_scale": 0.7, "pair_split": 1, "pair_reuse": 3})
