@@ -188,7 +188,7 @@ int ccfr_build_regions(ccfr_ctx* ctx, const ccfr_mesh* mesh, const float* x_anch
  *   duplicates dropped; up to max_passes passes of Alg. 1 over the violated
  *   ones; a pass with no violation returns its start point; otherwise y = 0 and
  *   halted[v] = 1.  Vertices with zero inverse mass get y = 0.
- * regions: device CSR (the context's or caller-owned).  inv_mass_dev [N],
+ * regions: device CSR (the context's or caller-owned; hs 16-byte aligned).  inv_mass_dev [N],
  * y_in_dev, y_out_dev [N][3] device (y_out may alias y_in); halted_dev [N] uint8
  * device or NULL (all pointers may be NULL when regions->n_verts is 0).  A
  * proposal with a non-finite component gives y = 0, halted = 1 and raises the

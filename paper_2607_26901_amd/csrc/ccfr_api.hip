@@ -726,6 +726,7 @@ int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const
     if ((!inv_mass_dev || !y_in_dev || !y_out_dev) && regions->n_verts > 0) return CCFR_ERR_INVALID_ARG;
     if (regions->n_verts < 0 || !regions->offsets || (regions->cap > 0 && !regions->hs) || regions->cap < 0)
         return CCFR_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(regions->hs) % 16 != 0) return CCFR_ERR_INVALID_ARG;   // 16-byte plane loads
     // scratch for the sort and the list of violating vertices must cover the call
     if (regions->cap > ctx->cap_hs || regions->n_verts > ctx->cap_verts) {
         HIP_OK(hipStreamSynchronize((hipStream_t)stream));

@@ -240,31 +240,41 @@ __device__ __forceinline__ bool run_passes(int K, const Get& get, const d3 yprop
 
 // ---- fast path: every vertex; the ones with a violated half-space go to a list ----
 
+__device__ __forceinline__ float4 load_plane(const ccfr_halfspace* h) {
+    return *reinterpret_cast<const float4*>(h);          // n[3], d: the first 16 bytes
+}
+
+__device__ __forceinline__ double rho_at(const float4 r, const d3 y) {
+    return dot(mk(r.x, r.y, r.z), y) + (double)r.w;
+}
+
 // One violated half-space: it is first in Alg. 2's sorted order, so the first
 // pass projects onto it (Alg. 1 with no stored plane), retracts, and re-checks
 // every other half-space at the new point; if none is violated there, the
 // second pass finds nothing and returns that point.  Evaluated here with the
 // same arithmetic as the passes, this gives Alg. 2's result without the sort;
 // returns false when the shortcut does not apply.
-__device__ __forceinline__ bool project_one_plane(const ccfr_halfspace* H, int K, int kv, const d3 yprop,
-                                                  const MeshParams& P, d3& yres) {
+__device__ __forceinline__ bool one_plane_regs(const float4 (&R)[kSmall], int K, const float4 hv, const d3 yprop,
+                                               const MeshParams& P, d3& yres) {
     if (P.max_passes < 2) return false;
-    const ccfr_halfspace hv = H[kv];
-    const d3 n = load_n(hv);
+    const d3 n = mk(hv.x, hv.y, hv.z);
     const double beta0 = dot(n, n);
     if (fabs(beta0) < (double)P.eps_plesnik) return false;
-    d3 yt = yprop + ((-(double)hv.d - dot(n, yprop)) / beta0) * n;
+    d3 yt = yprop + ((-(double)hv.w - dot(n, yprop)) / beta0) * n;
     const double nd = norm(yt);
     const double eps_r = (double)P.eps_retract;
     yt = (nd > eps_r) ? ((nd - eps_r) / nd) * yt : mk(0.0, 0.0, 0.0);
-    for (int k = 0; k < K; ++k) {
-        const ccfr_halfspace h = H[k];
-        if (dot(load_n(h), yt) + (double)h.d < 0.0) return false;
-    }
-    yres = yt;
-    return true;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < kSmall; ++k)
+        if (k < K) ok = ok && !(rho_at(R[k], yt) < 0.0);
+    if (ok) yres = yt;
+    return ok;
 }
 
+// Regions of at most kSmall half-spaces are read into registers (independent
+// loads, 16 bytes each); larger ones go to the wavefront path unexamined, so
+// that no lane walks a long region while the rest of its wavefront waits.
 __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCounters* c) {
     const int v = blockIdx.x * kBlock + threadIdx.x;
     const bool active = v < a.n_verts;
@@ -281,20 +291,28 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
             long long o0;
             const int K = region_size(a, v, &o0);
             const ccfr_halfspace* H = a.hs + o0;
-            int n_viol = 0, kv = -1;
-            for (int k = 0; k < K; ++k) {                     // independent loads, no early exit
-                const ccfr_halfspace h = H[k];
-                if (dot(load_n(h), yprop) + (double)h.d < 0.0) {
-                    ++n_viol;
-                    kv = k;
-                }
-            }
-            violated = n_viol > 0;
             big = K > kSmall;
-            d3 y = yprop;
-            if (n_viol == 1) deferred = !project_one_plane(H, K, kv, yprop, P, y);
-            else deferred = n_viol > 1;
-            if (!deferred) write_result(a, v, y, (double)P.r, false);
+            if (big) {
+                deferred = true;                 // checked and counted by the wavefront path
+            } else {
+                float4 R[kSmall];
+#pragma unroll
+                for (int k = 0; k < kSmall; ++k)
+                    R[k] = k < K ? load_plane(H + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+                int n_viol = 0;
+                float4 hv = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int k = 0; k < kSmall; ++k) {
+                    const bool vk = k < K && rho_at(R[k], yprop) < 0.0;
+                    n_viol += vk ? 1 : 0;
+                    if (vk) hv = R[k];
+                }
+                violated = n_viol > 0;
+                d3 y = yprop;
+                if (n_viol == 1) deferred = !one_plane_regs(R, K, hv, yprop, P, y);
+                else deferred = n_viol > 1;
+                if (!deferred) write_result(a, v, y, (double)P.r, false);
+            }
         } else {
             write_result(a, v, mk(0.0, 0.0, 0.0), 0.0, false);
         }
@@ -412,14 +430,186 @@ struct WaveLds {
     uint64_t key[kWave];
     double rho[kWave];
     int16_t idx[kWave];
-    uint8_t drop[kWave];
 };
 
-// List A (front of the slow list): regions of at most kSmall half-spaces, one
-// lane per vertex, the sort and the passes in registers.
-__global__ __launch_bounds__(kBlock) void k_project_lanes(ProjectArgs a, DevCounters* c) {
+// Orders the LDS writes and reads of one wavefront (its lanes run together, so
+// completing the wavefront's own LDS operations is all a barrier has to do).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+constexpr int kChunks = kWave / 64;   // sorted entries held per lane
+
+__device__ __forceinline__ float lane_value(float x, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
+}
+
+// Lane `src`'s copy of a wave-uniform chunk's record: every chunk is read out
+// of that lane and the chunk picked afterwards, so that R is only ever indexed
+// by constants (a runtime index would move it to scratch memory).
+__device__ __forceinline__ float4 take(const float4 (&R)[kChunks], int chunk, int src) {
+    float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        const float4 t = make_float4(lane_value(R[c].x, src), lane_value(R[c].y, src), lane_value(R[c].z, src),
+                                     lane_value(R[c].w, src));
+        if (chunk == c) r = t;
+    }
+    return r;
+}
+
+// One vertex of list B by one wavefront: its half-spaces are sorted in LDS by a
+// bitonic network, then held in registers in sorted order (lane l keeps entries
+// l, l + 64, ...; dropped duplicates and padding read as never violated).  Each
+// pass of Alg. 2 advances by ballots: every lane evaluates rho at the current
+// point for its entries at or after the last hit, the lowest violated one is
+// the next hit, and all lanes apply the same Alg. 1 update and retraction to
+// their (identical) copies of the state.  This visits exactly the half-spaces
+// the sequential pass would, in the same order, with the same arithmetic.
+__device__ __forceinline__ void project_wave_vertex(const ProjectArgs& a, DevCounters* c, WaveLds* L, int v) {
+    const int lane = __lane_id();
+    long long o0;
+    const int K = region_size(a, v, &o0);
+    const MeshParams P = a.prm.get(a.prm.mesh_of(v));
+    const d3 yprop = load_prop(a, v);
+    d3 y = yprop;
+    bool halted = false;
+    const ccfr_halfspace* H = a.hs + o0;
+    if (K > kWave) {
+        // beyond LDS: one lane sorts in the scratch range parallel to the CSR range
+        bool any = false;
+        for (int j = lane; j < K; j += 64) any = any || rho_at(load_plane(H + j), yprop) < 0.0;
+        if (__ballot(any)) {
+            if (lane == 0) {
+                halted = project_slow(H, K, yprop, P, a.sort_key + o0, a.sort_idx + o0, y);
+                spread_add(c, 0, 1ull);
+            }
+            halted = __shfl(halted ? 1 : 0, 0) != 0;
+        }
+    } else {
+        int Kp = 1;
+        while (Kp < K) Kp <<= 1;
+        bool any = false;
+        for (int j = lane; j < Kp; j += 64) {
+            if (j < K) {
+                const ccfr_halfspace h = H[j];
+                L->rec[j] = make_float4(h.n[0], h.n[1], h.n[2], h.d);
+                L->key[j] = h.key;
+                const double r = dot(load_n(h), yprop) + (double)h.d;
+                L->rho[j] = r;
+                any = any || r < 0.0;
+            } else {
+                L->key[j] = ~0ull;
+                L->rho[j] = __longlong_as_double(0x7ff0000000000000ll);   // +inf: sorts last
+            }
+            L->idx[j] = (int16_t)j;
+        }
+        // no violation: the first pass returns the proposal (no sort needed)
+        if (__ballot(any)) {
+            if (lane == 0) spread_add(c, 0, 1ull);
+            wave_sync();
+            for (int size = 2; size <= Kp; size <<= 1) {
+                for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                    for (int t = lane; t < (Kp >> 1); t += 64) {
+                        const int p = 2 * t - (t & (stride - 1));
+                        const int q = p + stride;
+                        const bool up = (p & size) == 0;
+                        const bool swap = up ? before(L->rho[q], L->key[q], L->rho[p], L->key[p])
+                                             : before(L->rho[p], L->key[p], L->rho[q], L->key[q]);
+                        if (swap) {
+                            const double tr = L->rho[p]; L->rho[p] = L->rho[q]; L->rho[q] = tr;
+                            const uint64_t tk = L->key[p]; L->key[p] = L->key[q]; L->key[q] = tk;
+                            const int16_t ti = L->idx[p]; L->idx[p] = L->idx[q]; L->idx[q] = ti;
+                        }
+                    }
+                    wave_sync();
+                }
+            }
+            // sorted records into registers; exact duplicates after the first of
+            // their rho run, and the padding, get d = +inf (never violated)
+            float4 R[kChunks];
+#pragma unroll
+            for (int ch = 0; ch < kChunks; ++ch) {
+                const int q = ch * 64 + lane;
+                R[ch] = make_float4(0.f, 0.f, 0.f, __builtin_inff());
+                if (q < K) {
+                    const float4 rq = L->rec[L->idx[q]];
+                    bool dup = false;
+                    for (int r = q - 1; r >= 0 && L->rho[r] == L->rho[q] && !dup; --r) {
+                        const float4 rr = L->rec[L->idx[r]];
+                        dup = rr.x == rq.x && rr.y == rq.y && rr.z == rq.z && rr.w == rq.w;
+                    }
+                    if (!dup) R[ch] = rq;
+                }
+            }
+            const int n_chunks = (K + 63) >> 6;
+            const double eps_r = (double)P.eps_retract;
+            const double eps_p = (double)P.eps_plesnik;
+            d3 yp = yprop;
+            halted = true;
+            for (int pass = 0; pass < P.max_passes; ++pass) {
+                d3 yt = yp;
+                const d3 y0 = yp;
+                Ero S;
+                S.m = 0;
+                int nviol = 0;
+                int from = 0;
+                while (true) {
+                    // lowest violated sorted entry at or after `from`, at the current point
+                    int hit = -1;
+#pragma unroll
+                    for (int ch = 0; ch < kChunks; ++ch) {
+                        if (hit < 0 && ch < n_chunks && ch * 64 + 63 >= from) {
+                            const int q = ch * 64 + lane;
+                            const bool viol = q >= from && rho_at(R[ch], yt) < 0.0;
+                            const unsigned long long m = __ballot(viol);
+                            if (m) hit = ch * 64 + __ffsll((long long)m) - 1;
+                        }
+                    }
+                    if (hit < 0) break;
+                    const float4 rr = take(R, hit >> 6, hit & 63);
+                    ++nviol;
+                    orthogonal_projection(yt, y0, mk(rr.x, rr.y, rr.z), -(double)rr.w, S, eps_p);
+                    const double nd = norm(yt);
+                    yt = (nd > eps_r) ? ((nd - eps_r) / nd) * yt : mk(0.0, 0.0, 0.0);
+                    from = hit + 1;
+                }
+                if (nviol == 0) {
+                    y = yp;
+                    halted = false;
+                    break;
+                }
+                yp = yt;
+            }
+            if (halted) y = mk(0.0, 0.0, 0.0);
+        }
+        wave_sync();   // the LDS slice is reused by the wavefront's next vertex
+    }
+    if (lane == 0) {
+        write_result(a, v, y, (double)P.r, halted);
+        if (halted) spread_add(c, 1, 1ull);
+    }
+}
+
+// Both slow lists in one launch.  Blocks [0, wave_blocks) run list B (larger
+// regions), one vertex per wavefront, first, since their vertices take the
+// longest; the remaining blocks run list A (regions of at most kSmall
+// half-spaces), one lane per vertex, the sort and the passes in registers.
+__global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCounters* c, int wave_blocks) {
+    __shared__ WaveLds lds[kBlock / 64];
+    if ((int)blockIdx.x < wave_blocks) {
+        const int wave = threadIdx.x / 64;
+        const int n_list = c->n_viol_b;
+        const int workers = wave_blocks * (kBlock / 64);
+        WaveLds* L = &lds[wave];
+        for (int i = blockIdx.x * (kBlock / 64) + wave; i < n_list; i += workers)
+            project_wave_vertex(a, c, L, a.slow_list[a.n_verts - 1 - i]);
+        return;
+    }
+    const int lane_blocks = gridDim.x - wave_blocks;
     const int n_list = c->n_viol;
-    for (int i0 = blockIdx.x * kBlock; i0 < n_list; i0 += gridDim.x * kBlock) {
+    for (int i0 = (blockIdx.x - wave_blocks) * kBlock; i0 < n_list; i0 += lane_blocks * kBlock) {
         const int i = i0 + threadIdx.x;
         bool halted = false;
         if (i < n_list) {
@@ -436,122 +626,6 @@ __global__ __launch_bounds__(kBlock) void k_project_lanes(ProjectArgs a, DevCoun
     }
 }
 
-// List B (back of the slow list): larger regions, one wavefront per vertex.  The
-// half-spaces are sorted in LDS by a bitonic network; each pass of Alg. 2 then
-// advances by parallel scans: every lane evaluates rho at the current point for
-// its share of the remaining sorted entries, a ballot gives the first violated
-// one, and all lanes apply the same Alg. 1 update and retraction to their
-// (identical) copies of the state.  This visits exactly the half-spaces the
-// sequential pass would, in the same order, with the same arithmetic.
-__global__ __launch_bounds__(64) void k_project_wave(ProjectArgs a, DevCounters* c) {
-    __shared__ WaveLds L;
-    const int n_list = c->n_viol_b;
-    const int lane = threadIdx.x;
-    for (int i = blockIdx.x; i < n_list; i += gridDim.x) {
-        const int v = a.slow_list[a.n_verts - 1 - i];
-        long long o0;
-        const int K = region_size(a, v, &o0);
-        const MeshParams P = a.prm.get(a.prm.mesh_of(v));
-        const d3 yprop = load_prop(a, v);
-        d3 y = mk(0.0, 0.0, 0.0);
-        bool halted = false;
-        if (K > kWave) {
-            // beyond LDS: one lane sorts in the scratch range parallel to the CSR range
-            if (lane == 0) halted = project_slow(a.hs + o0, K, yprop, P, a.sort_key + o0, a.sort_idx + o0, y);
-            halted = __shfl(halted ? 1 : 0, 0) != 0;
-        } else {
-            int Kp = 1;
-            while (Kp < K) Kp <<= 1;
-            const ccfr_halfspace* H = a.hs + o0;
-            for (int j = lane; j < Kp; j += 64) {
-                if (j < K) {
-                    const ccfr_halfspace h = H[j];
-                    L.rec[j] = make_float4(h.n[0], h.n[1], h.n[2], h.d);
-                    L.key[j] = h.key;
-                    L.rho[j] = dot(load_n(h), yprop) + (double)h.d;
-                } else {
-                    L.key[j] = ~0ull;
-                    L.rho[j] = __longlong_as_double(0x7ff0000000000000ll);
-                }
-                L.idx[j] = (int16_t)j;
-            }
-            __syncthreads();
-            for (int size = 2; size <= Kp; size <<= 1) {
-                for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                    for (int t = lane; t < (Kp >> 1); t += 64) {
-                        const int p = 2 * t - (t & (stride - 1));
-                        const int q = p + stride;
-                        const bool up = (p & size) == 0;
-                        const bool swap = up ? before(L.rho[q], L.key[q], L.rho[p], L.key[p])
-                                             : before(L.rho[p], L.key[p], L.rho[q], L.key[q]);
-                        if (swap) {
-                            const double tr = L.rho[p]; L.rho[p] = L.rho[q]; L.rho[q] = tr;
-                            const uint64_t tk = L.key[p]; L.key[p] = L.key[q]; L.key[q] = tk;
-                            const int16_t ti = L.idx[p]; L.idx[p] = L.idx[q]; L.idx[q] = ti;
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-            for (int q = lane; q < K; q += 64) {
-                bool dup = false;
-                const float4 rq = L.rec[L.idx[q]];
-                for (int r = q - 1; r >= 0 && L.rho[r] == L.rho[q] && !dup; --r) {
-                    const float4 rr = L.rec[L.idx[r]];
-                    dup = rr.x == rq.x && rr.y == rq.y && rr.z == rq.z && rr.w == rq.w;
-                }
-                L.drop[q] = dup ? 1 : 0;
-            }
-            __syncthreads();
-            const double eps_r = (double)P.eps_retract;
-            const double eps_p = (double)P.eps_plesnik;
-            d3 yp = yprop;
-            halted = true;
-            for (int pass = 0; pass < P.max_passes; ++pass) {
-                d3 yt = yp;
-                const d3 y0 = yp;
-                Ero S;
-                S.m = 0;
-                int nviol = 0;
-                int from = 0;
-                while (true) {
-                    // first violated sorted entry at or after `from`, at the current point
-                    int hit = -1;
-                    for (int base = from & ~63; base < K && hit < 0; base += 64) {
-                        const int q = base + lane;
-                        bool viol = false;
-                        if (q >= from && q < K && L.drop[q] == 0) {
-                            const float4 rr = L.rec[L.idx[q]];
-                            viol = dot(mk(rr.x, rr.y, rr.z), yt) + (double)rr.w < 0.0;
-                        }
-                        const unsigned long long m = __ballot(viol);
-                        if (m) hit = base + __ffsll((long long)m) - 1;
-                    }
-                    if (hit < 0) break;
-                    const float4 rr = L.rec[L.idx[hit]];
-                    ++nviol;
-                    orthogonal_projection(yt, y0, mk(rr.x, rr.y, rr.z), -(double)rr.w, S, eps_p);
-                    const double nd = norm(yt);
-                    yt = (nd > eps_r) ? ((nd - eps_r) / nd) * yt : mk(0.0, 0.0, 0.0);
-                    from = hit + 1;
-                }
-                if (nviol == 0) {
-                    y = yp;
-                    halted = false;
-                    break;
-                }
-                yp = yt;
-            }
-            if (halted) y = mk(0.0, 0.0, 0.0);
-            __syncthreads();
-        }
-        if (lane == 0) {
-            write_result(a, v, y, (double)P.r, halted);
-            if (halted) spread_add(c, 1, 1ull);
-        }
-    }
-}
-
 __global__ void k_zero_viol(DevCounters* c) {
     if (threadIdx.x == 0) {
         c->n_viol = 0;
@@ -565,10 +639,11 @@ void launch_project(const ProjectArgs& a, DevCounters* c, bool zero_counters, hi
     if (a.n_verts <= 0) return;
     if (zero_counters) hipLaunchKernelGGL(k_zero_viol, dim3(1), dim3(64), 0, s, c);
     hipLaunchKernelGGL(k_project_fast, dim3((a.n_verts + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a, c);
+    // list sizes are known on the device only: enough blocks for a few
+    // thousand wavefront vertices and a grid-stride over the lane list
     const int lane_blocks = std::max(1, std::min(1024, (a.n_verts + kBlock - 1) / kBlock));
-    hipLaunchKernelGGL(k_project_lanes, dim3(lane_blocks), dim3(kBlock), 0, s, a, c);
-    const int wave_blocks = std::max(1, std::min(4096, a.n_verts));
-    hipLaunchKernelGGL(k_project_wave, dim3(wave_blocks), dim3(64), 0, s, a, c);
+    const int wave_blocks = std::max(1, std::min(1024, (a.n_verts + kBlock / 64 - 1) / (kBlock / 64)));
+    hipLaunchKernelGGL(k_project_slow, dim3(wave_blocks + lane_blocks), dim3(kBlock), 0, s, a, c, wave_blocks);
 }
 
 }  // namespace ccfr
