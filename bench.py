@@ -201,6 +201,8 @@ def main():
     ap.add_argument("--pair-split", type=int, default=None, help="fixed lanes per broad-phase query (skips the tuner)")
     ap.add_argument("--pair-reuse", type=int, default=None,
                     help="fixed solver iterations per candidate build (skips the tuner)")
+    ap.add_argument("--pair-skin", type=int, default=None,
+                    help="candidate builds that follow the motion, widened by this many r (skips the tuner)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (scale for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -264,7 +266,8 @@ def main():
     # knobs: fixed, default, or picked by the autotuner on steps from the
     # middle of the run (the contact state the timed steps spend most time in)
     fixed = {k: val for k, val in (("cell_scale", args.cell_scale), ("pair_split", args.pair_split),
-                                    ("pair_reuse", args.pair_reuse)) if val is not None}
+                                    ("pair_reuse", args.pair_reuse), ("pair_skin", args.pair_skin))
+             if val is not None}
     tuning = None
     if fixed:
         ctx.set_tuning(**fixed)
@@ -313,8 +316,7 @@ def main():
     value = updates / wall
     tot = info["totals"]
     n_builds = max(tot[9], 1)
-    reuse = ctx.get_tuning()["pair_reuse"]
-    n_cand_builds = K * ((iters + reuse - 1) // reuse)
+    n_cand_builds = max(info["candidate_builds"], 1)
     P = (tot[0] + tot[1] + tot[2]) / n_cand_builds
     Hh = tot[3] / n_builds
     Cc = tot[8] / n_builds
@@ -340,7 +342,7 @@ def main():
         "p50_step_ms": float(np.percentile(step_ms, 50)),
         "p99_step_ms": float(np.percentile(step_ms, 99)),
         "gpu_ms_per_step": float(step_ms.mean()),
-        "per_iteration": {"pairs_per_candidate_build": P, "candidate_builds_per_step": n_cand_builds // K,
+        "per_iteration": {"pairs_per_candidate_build": P, "candidate_builds_per_step": n_cand_builds / K,
                           "contacts": Cc, "halfspaces": Hh,
                           "violating_vertices": tot[4] / n_builds, "halted_vertices": tot[5] / n_builds},
         "halted_fraction_of_violating": (tot[5] / tot[4]) if tot[4] else 0.0,
@@ -368,7 +370,7 @@ def main():
         nb = max(ptot[9], 1)
         # pairs of one candidate list (written once per build, read by every
         # iteration's narrow phase), contacts and half-spaces per iteration
-        n_lists = max(stage_launches[1], 1)
+        n_lists = max(pinfo["candidate_builds"], 1)
         pP, pC, pH = (ptot[0] + ptot[1] + ptot[2]) / n_lists, ptot[8] / nb, ptot[3] / nb
         per_launch = stage_ms / np.maximum(stage_launches, 1)
         result["stage_ms_per_step"] = {name: float(stage_ms[i] / K) for i, name in enumerate(ccfr.STAGES)}
@@ -377,6 +379,10 @@ def main():
         dom = max(singles, key=lambda k: stage_ms[singles[k]])
         i = singles[dom]
         B = kernel_bytes(dom, sc.n_verts, sc.n_tris, sc.n_edges, n_free, pP, pC, pH)
+        if dom == "pair_emission":
+            # builds that follow the motion launch the kernel every iteration and
+            # it returns at once when no build is due: bytes per launch on average
+            B *= n_lists / max(stage_launches[1], 1)
         achieved = B / (per_launch[i] * 1e-3) / 1e9
         result["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -126,6 +126,8 @@ typedef struct {
                                halted vertices, [6] degenerate pairs, [7] projected
                                vertices, [8] contacts (pairs with phi < 2r), [9]
                                region builds                                        */
+    int64_t candidate_builds; /* candidate builds closed since the last reset (the
+                               pair totals are summed over these)                   */
 } ccfr_status_info;
 
 typedef struct ccfr_ctx ccfr_ctx;
@@ -252,12 +254,21 @@ int ccfr_profile_read(ccfr_ctx* ctx, ccfr_stream stream, float* ms, int32_t* lau
  *               phase still keeps exactly the pairs with phi < 2r at the current
  *               positions, so regions and results are those of a build per
  *               iteration, bit for bit; the lists are longer.
+ *   pair_skin   0 (default): builds grouped by pair_reuse.  s in 1..4: builds
+ *               that follow the motion instead (pair_reuse is then unused):
+ *               every build widens the boxes of primitives with a moving
+ *               vertex by at least s r, and from the second iteration of a
+ *               substep on, the device sums the largest coordinate move of each
+ *               projection since the last build and builds again only once the
+ *               sum may exceed the widening (every pair whose boxes overlap now
+ *               had widened boxes overlapping at the build).  Results are again
+ *               those of a build per iteration, bit for bit.
  * Setting them invalidates recorded step graphs (they are recorded again). */
 typedef struct {
     float cell_scale;
     int32_t pair_split;
     int32_t pair_reuse;
-    int32_t reserved;      /* 0 */
+    int32_t pair_skin;
 } ccfr_tuning;
 int ccfr_set_tuning(ccfr_ctx* ctx, const ccfr_tuning* tuning);
 int ccfr_get_tuning(const ccfr_ctx* ctx, ccfr_tuning* tuning);

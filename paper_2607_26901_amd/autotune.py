@@ -2,8 +2,9 @@
 
 The knobs are the grid cell size (`cell_scale`, a multiple of the default
 cell: 1.2 x the typical edge length + 2 pad), the number of lanes that share
-one broad-phase query (`pair_split`) and the number of solver iterations that
-share one candidate build inside a substep (`pair_reuse`).  Smaller cells put
+one broad-phase query (`pair_split`) and how solver iterations share candidate
+builds inside a substep: a fixed number per build (`pair_reuse`) or as many as
+the measured motion allows within a widening of s r (`pair_skin` = s).  Smaller cells put
 fewer entries in the buckets a query scans but bin long primitives one level
 up; more lanes per query shorten the walks of queries in dense folds at the
 price of more lanes; sharing a build saves grid builds and queries at the price
@@ -23,7 +24,9 @@ from . import ccfr
 
 CELL_SCALES = (0.5, 0.6, 0.7, 0.85, 1.0, 1.2)
 PAIR_SPLITS = (1, 3, 9)
-PAIR_REUSES = (1, 2, 3, 4)
+# (pair_reuse, pair_skin): fixed groups of 1-4 iterations, or builds that follow
+# the motion with a skin of 1-3 r
+PAIR_MODES = ((1, 0), (2, 0), (3, 0), (4, 0), (1, 1), (1, 2), (1, 3))
 
 
 def size_class(n_verts, n_tris, n_edges, r, kind="mesh") -> str:
@@ -62,22 +65,22 @@ class Cache:
             pass
 
 
-def tune(ctx: ccfr.Context, run, candidates=CELL_SCALES, splits=PAIR_SPLITS, reuses=(1,),
+def tune(ctx: ccfr.Context, run, candidates=CELL_SCALES, splits=PAIR_SPLITS, modes=((1, 0),),
          repeats: int = 2) -> dict:
     """Time `run()` (device milliseconds of a fixed piece of work, starting from
-    the same state every call) under each (cell scale, split, reuse); leave the
-    fastest set."""
+    the same state every call) under each (cell scale, split, (reuse, skin));
+    leave the fastest set."""
     times = {}
     for c in candidates:
         for sp in splits:
-            for ru in reuses:
-                ctx.set_tuning(cell_scale=c, pair_split=sp, pair_reuse=ru)
+            for ru, sk in modes:
+                ctx.set_tuning(cell_scale=c, pair_split=sp, pair_reuse=ru, pair_skin=sk)
                 run()                           # records the graph for this setting
-                times[(c, sp, ru)] = min(run() for _ in range(repeats))
+                times[(c, sp, ru, sk)] = min(run() for _ in range(repeats))
     best = min(times, key=times.get)
-    ctx.set_tuning(cell_scale=best[0], pair_split=best[1], pair_reuse=best[2])
-    return {"cell_scale": best[0], "pair_split": best[1], "pair_reuse": best[2],
-            "ms": {f"{k[0]}/{k[1]}/{k[2]}": v for k, v in times.items()}}
+    ctx.set_tuning(cell_scale=best[0], pair_split=best[1], pair_reuse=best[2], pair_skin=best[3])
+    return {"cell_scale": best[0], "pair_split": best[1], "pair_reuse": best[2], "pair_skin": best[3],
+            "ms": {f"{k[0]}/{k[1]}/{k[2]}/{k[3]}": v for k, v in times.items()}}
 
 
 def _events():
@@ -86,7 +89,7 @@ def _events():
 
 
 def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, steps: int = 4,
-              candidates=CELL_SCALES, splits=PAIR_SPLITS, reuses=PAIR_REUSES, cache: Cache | None = None,
+              candidates=CELL_SCALES, splits=PAIR_SPLITS, modes=PAIR_MODES, cache: Cache | None = None,
               key: str | None = None) -> dict:
     """Tune on `steps` single-mesh steps from the state (x, v), which is restored."""
     import torch
@@ -94,7 +97,7 @@ def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, ste
         hit = cache.get(key)
         if hit is not None:
             ctx.set_tuning(cell_scale=hit["cell_scale"], pair_split=hit["pair_split"],
-                           pair_reuse=hit.get("pair_reuse", 1))
+                           pair_reuse=hit.get("pair_reuse", 1), pair_skin=hit.get("pair_skin", 0))
             return dict(hit, cached=True)
     x0, v0 = x.clone(), v.clone()
 
@@ -115,7 +118,7 @@ def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, ste
             ctx.grow(info)                      # lists too small: grow and time again
         raise ccfr.CcfrError(-2, "tuning run")
 
-    out = tune(ctx, run, candidates, splits, reuses)
+    out = tune(ctx, run, candidates, splits, modes)
     x.copy_(x0)
     v.copy_(v0)
     torch.cuda.synchronize()
@@ -125,7 +128,7 @@ def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, ste
 
 
 def tune_batch(ctx: ccfr.Context, batch: ccfr.Batch, candidates=CELL_SCALES, splits=PAIR_SPLITS,
-               reuses=PAIR_REUSES) -> dict:
+               modes=PAIR_MODES) -> dict:
     """Tune on one step of the resident batch; every trial is rolled back."""
     def run():
         for _ in range(4):
@@ -142,4 +145,4 @@ def tune_batch(ctx: ccfr.Context, batch: ccfr.Batch, candidates=CELL_SCALES, spl
             ctx.grow(info)
         raise ccfr.CcfrError(-2, "tuning run")
 
-    return tune(ctx, run, candidates, splits, reuses)
+    return tune(ctx, run, candidates, splits, modes)

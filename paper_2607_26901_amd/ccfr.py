@@ -53,12 +53,13 @@ class StepParams(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("cell_scale", C.c_float), ("pair_split", C.c_int32), ("pair_reuse", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("pair_skin", C.c_int32)]
 
 
 class StatusInfo(C.Structure):
     _fields_ = [("status_bits", C.c_uint32), ("last_counts", C.c_int32 * 3), ("last_contacts", C.c_int32),
-                ("last_halfspaces", C.c_int32), ("need", C.c_int64 * 6), ("totals", C.c_int64 * 10)]
+                ("last_halfspaces", C.c_int32), ("need", C.c_int64 * 6), ("totals", C.c_int64 * 10),
+                ("candidate_builds", C.c_int64)]
 
 
 EXPORTS = ["ccfr_status_string", "ccfr_create", "ccfr_destroy", "ccfr_mesh_create", "ccfr_mesh_destroy",
@@ -210,6 +211,7 @@ class Context:
             "last_halfspaces": int(info.last_halfspaces),
             "need": list(info.need),
             "totals": list(info.totals),
+            "candidate_builds": int(info.candidate_builds),
         }
 
 
@@ -223,19 +225,20 @@ class Context:
         self.reserve(vf=int(nd[0] * factor) + 1024, ee=int(nd[1] * factor) + 1024, vv=int(nd[2] * factor) + 1024,
                      contacts=int(nd[3] * factor) + 1024, halfspaces=int(nd[4] * factor) + 1024)
 
-    def set_tuning(self, cell_scale=None, pair_split=None, pair_reuse=None):
+    def set_tuning(self, cell_scale=None, pair_split=None, pair_reuse=None, pair_skin=None):
         """Change any of the speed-only knobs (None keeps the current value)."""
         cur = self.get_tuning()
         t = Tuning(float(cur["cell_scale"] if cell_scale is None else cell_scale),
                    int(cur["pair_split"] if pair_split is None else pair_split),
-                   int(cur["pair_reuse"] if pair_reuse is None else pair_reuse), 0)
+                   int(cur["pair_reuse"] if pair_reuse is None else pair_reuse),
+                   int(cur["pair_skin"] if pair_skin is None else pair_skin))
         _check(self.lib.ccfr_set_tuning(self.h, C.byref(t)), "ccfr_set_tuning")
 
     def get_tuning(self) -> dict:
         t = Tuning()
         _check(self.lib.ccfr_get_tuning(self.h, C.byref(t)), "ccfr_get_tuning")
         return {"cell_scale": float(t.cell_scale), "pair_split": int(t.pair_split),
-                "pair_reuse": int(t.pair_reuse)}
+                "pair_reuse": int(t.pair_reuse), "pair_skin": int(t.pair_skin)}
 
     def profile_enable(self, on=True):
         _check(self.lib.ccfr_profile_enable(self.h, int(bool(on))), "ccfr_profile_enable")

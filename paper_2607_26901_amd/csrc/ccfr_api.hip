@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <vector>
 
@@ -193,9 +194,12 @@ bool step_params_ok(const ccfr_step_params* sp) {
 // Per-mesh device parameters: the box pad (one FP32 rounding of an FP64 sum) and
 // a grid cell large enough that typical primitives span at most two cells.  A
 // build that serves skin_iters more iterations widens moving boxes by about
-// skin_iters r per side; the cell is sized for that width (with slack for the
-// rounding term), so that a particle's box still fits one cell.
-MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell_scale, int skin_iters) {
+// skin_iters r per side, one that adapts to the motion by skin_mult r (pad_wide:
+// the FP32 sum rounded up one step, so that pad_wide - pad >= skin_mult r); the
+// cell is sized for that width (with slack for the rounding term), so that a
+// particle's box still fits one cell.
+MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell_scale, int skin_iters,
+                       int skin_mult) {
     MeshParams m{};
     m.r = p->r;
     m.xi = p->xi;
@@ -203,7 +207,14 @@ MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell
     m.two_r = 2.0f * p->r;
     m.eps_retract = p->eps_retract;
     m.eps_plesnik = p->eps_plesnik;
-    const double wide = (double)m.pad + 1.25 * skin_iters * (double)p->r;
+    m.pad_wide = m.pad;
+    if (skin_mult > 0) {
+        const double want = (double)skin_mult * (double)p->r;
+        m.pad_wide = (float)((double)m.pad + want);
+        while ((double)m.pad_wide - (double)m.pad < want)
+            m.pad_wide = std::nextafter(m.pad_wide, std::numeric_limits<float>::infinity());
+    }
+    const double wide = (double)m.pad + 1.25 * std::max(skin_iters, skin_mult) * (double)p->r;
     const double h = std::max(2.02 * wide, (double)cell_scale * (1.2 * (double)typ_len + 2.0 * wide));
     m.h = (float)h;
     m.inv_h = (float)(1.0 / h);
@@ -214,7 +225,8 @@ MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell
 
 namespace {
 
-Scene make_scene(const ccfr_mesh* m, const float* x, const ccfr_params* p, int skin_iters = 0) {
+Scene make_scene(const ccfr_mesh* m, const float* x, const ccfr_params* p, int skin_iters = 0,
+                 int skin_mult = 0) {
     Scene sc{};
     sc.narrow_fp32 = m->ctx->narrow_fp32 ? 1 : 0;
     sc.n_verts = m->n_verts;
@@ -229,7 +241,7 @@ Scene make_scene(const ccfr_mesh* m, const float* x, const ccfr_params* p, int s
     sc.is_free = m->is_free_d;
     sc.prm.table = nullptr;
     sc.prm.vmesh = nullptr;
-    sc.prm.one = mesh_params(p, m->typ_len, 0, m->ctx->cell_scale, skin_iters);
+    sc.prm.one = mesh_params(p, m->typ_len, 0, m->ctx->cell_scale, skin_iters, skin_mult);
     return sc;
 }
 
@@ -269,8 +281,8 @@ void enqueue_candidates(ccfr_ctx* ctx, const Scene& sc, int n_meshes, hipStream_
     mk.mark(0, 0);
     if (standalone) launch_reset_build(ctx->counters_d, g.level_mask, g.n_meshes, s);
     launch_grid_count(sc, g, ctx->counters_d, s);
-    launch_scan(g.cnt, g.start, g.cnt, g.off[4], g.scan_tmp, s);
-    launch_grid_scatter(sc, g, s);
+    launch_scan(g.cnt, g.start, g.cnt, g.off[4], g.scan_tmp, s, &ctx->counters_d->rebuild);
+    launch_grid_scatter(sc, g, ctx->counters_d, s);
     mk.mark(0, 1);
     PairLists pl{ctx->vf, ctx->ee, ctx->vv, ctx->cap_vf, ctx->cap_ee, ctx->cap_vv};
     mk.mark(1, 0);
@@ -321,15 +333,26 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
     // counters and level masks start clear; each iteration's close clears them
     // for the next one
     launch_reset_build(ctx->counters_d, ctx->level_mask, plan.n_meshes, s);
-    // a candidate build serves `reuse` consecutive iterations (the last group
-    // of the substep may be shorter); its boxes are widened for the iterations
-    // after the first
-    const int reuse = std::max(1, ctx->pair_reuse);
+    // Fixed grouping: a candidate build serves `reuse` consecutive iterations
+    // (the last group of the substep may be shorter); its boxes are widened for
+    // the iterations after the first.  Adaptive (plan.skin > 0): every build's
+    // moving boxes are widened by the skin, and from the second iteration on a
+    // decision kernel asks for a new build only once the summed anchor moves
+    // since the last one may exceed it; the stage's kernels run every iteration
+    // and return at once when no build is asked for.
+    const bool adaptive = plan.skin > 0.0;
+    const int reuse = adaptive ? 1 : std::max(1, ctx->pair_reuse);
+    const PairCaps caps{ctx->cap_vf, ctx->cap_ee, ctx->cap_vv};
     for (int it = 0; it < plan.iters; ++it) {
         const Marks mk{ctx, it, s};
         const int first = it - it % reuse;
         const int group = std::min(reuse, plan.iters - first);
-        if (it == first) {
+        if (adaptive) {
+            if (it > 0) launch_decide_build(ctx->counters_d, ctx->level_mask, plan.n_meshes, plan.skin, caps, s);
+            Scene sb = sc;
+            sb.skin_wide = 1;
+            enqueue_candidates(ctx, sb, plan.n_meshes, s, mk, false);
+        } else if (it == first) {
             Scene sb = sc;
             sb.skin_iters = group - 1;
             enqueue_candidates(ctx, sb, plan.n_meshes, s, mk, false);
@@ -343,8 +366,8 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
                         ctx->cap_vv, s, mk, true);
         mk.mark(4, 0);
         launch_close_iteration(ctx->x_pred, ctx->p, 3LL * n, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
-                               ctx->offsets, PairCaps{ctx->cap_vf, ctx->cap_ee, ctx->cap_vv}, ctx->cap_contacts,
-                               ctx->cap_hs, it == first + group - 1, s);
+                               ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs,
+                               adaptive ? it == plan.iters - 1 : it == first + group - 1, s);
         if (plan.has_stretch) {
             for (size_t c = 0; c < plan.col_total.size(); ++c)
                 launch_stretch_segments(plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[c],
@@ -366,6 +389,7 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
         pa.sort_key = ctx->sort_key;
         pa.sort_idx = ctx->sort_idx;
         pa.slow_list = ctx->slow_list;
+        pa.motion_max = adaptive ? &ctx->counters_d->motion_max : nullptr;
         pa.prm = sc.prm;
         mk.mark(5, 0);
         launch_project(pa, ctx->counters_d, false, s);
@@ -511,7 +535,8 @@ namespace {
 
 StepPlan mesh_plan(ccfr_ctx* ctx, const ccfr_mesh* m, float* x, float* v, const ccfr_step_params* sp) {
     StepPlan plan;
-    plan.sc = make_scene(m, x, &sp->collision, ctx->pair_reuse - 1);
+    plan.sc = make_scene(m, x, &sp->collision, ctx_skin_iters(ctx), ctx_skin_mult(ctx));
+    if (ctx_skin_mult(ctx) > 0) plan.skin = (double)plan.sc.prm.one.pad_wide - (double)plan.sc.prm.one.pad;
     plan.x = x;
     plan.v = v;
     plan.n_meshes = 1;
@@ -775,7 +800,7 @@ int ccfr_xpbd_step(ccfr_ctx* ctx, const ccfr_mesh* mesh, float* x_dev, float* v_
     const StepPlan plan = mesh_plan(ctx, mesh, x_dev, v_dev, sp);
     if (ctx->profiling) {
         ctx->prof_last_iters = sp->iters;
-        ctx->prof_last_reuse = ctx->pair_reuse;
+        ctx->prof_last_reuse = ctx->pair_skin > 0 ? 1 : ctx->pair_reuse;
     }
     // profiled steps run eagerly: the stage events bracket the launches on `s`
     if (!ctx->use_graphs || ctx->profiling) {
@@ -801,6 +826,7 @@ int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, 
         info->last_halfspaces = h.last_hs;
         for (int k = 0; k < 6; ++k) info->need[k] = h.need[k];
         for (int k = 0; k < 10; ++k) info->totals[k] = h.totals[k];
+        info->candidate_builds = h.builds;
         const int slot_of[3] = {4, 5, 7};
         for (int w = 0; w < 3; ++w)
             for (int k = 0; k < 64; ++k) info->totals[slot_of[w]] += h.spread[w][k];
@@ -819,13 +845,16 @@ int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, 
 
 int ccfr_set_tuning(ccfr_ctx* ctx, const ccfr_tuning* t) {
     if (!ctx || !t || !std::isfinite(t->cell_scale) || t->cell_scale < 0.25f || t->cell_scale > 4.0f ||
-        (t->pair_split != 1 && t->pair_split != 3 && t->pair_split != 9) || t->pair_reuse < 0 || t->pair_reuse > 4)
+        (t->pair_split != 1 && t->pair_split != 3 && t->pair_split != 9) || t->pair_reuse < 0 || t->pair_reuse > 4 ||
+        t->pair_skin < 0 || t->pair_skin > 4)
         return CCFR_ERR_INVALID_ARG;
     const int reuse = std::max(1, (int)t->pair_reuse);
-    if (t->cell_scale != ctx->cell_scale || t->pair_split != ctx->pair_split || reuse != ctx->pair_reuse) {
+    if (t->cell_scale != ctx->cell_scale || t->pair_split != ctx->pair_split || reuse != ctx->pair_reuse ||
+        t->pair_skin != ctx->pair_skin) {
         ctx->cell_scale = t->cell_scale;
         ctx->pair_split = t->pair_split;
         ctx->pair_reuse = reuse;
+        ctx->pair_skin = t->pair_skin;
         ctx->tune_generation++;
         ctx->generation++;          // recorded graphs carry the old settings
         drop_graph(ctx);
@@ -839,6 +868,7 @@ int ccfr_get_tuning(const ccfr_ctx* ctx, ccfr_tuning* t) {
     t->cell_scale = ctx->cell_scale;
     t->pair_split = ctx->pair_split;
     t->pair_reuse = ctx->pair_reuse;
+    t->pair_skin = ctx->pair_skin;
     return CCFR_OK;
 }
 

@@ -167,7 +167,8 @@ int slot_salt(int slot) { return (int)(0x9E3779B1u * (uint32_t)(slot + 1)); }
 // Parameters of every resident slot again, after a tuning change.
 int refresh_table(ccfr_batch* b, hipStream_t s) {
     for (int k = 0; k < b->max_slots; ++k)
-        if (b->slot_busy[k]) b->table_h[k] = mesh_params(&b->coll_h[k], b->typ_h[k], slot_salt(k), b->ctx->cell_scale, b->ctx->pair_reuse - 1);
+        if (b->slot_busy[k]) b->table_h[k] = mesh_params(&b->coll_h[k], b->typ_h[k], slot_salt(k), b->ctx->cell_scale,
+                                  ctx_skin_iters(b->ctx), ctx_skin_mult(b->ctx));
     HIP_OK(hipMemcpyAsync(b->table_d, b->table_h.data(), sizeof(MeshParams) * b->table_h.size(),
                           hipMemcpyHostToDevice, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -242,6 +243,16 @@ int rebuild_plan(ccfr_batch* b, hipStream_t s) {
     pl.x = P.x;
     pl.v = P.v;
     pl.n_meshes = b->max_slots;
+    // builds that adapt to the motion: the least widening over the resident meshes
+    if (ctx_skin_mult(ctx) > 0) {
+        double skin = 0.0;
+        for (int k = 0; k < b->max_slots; ++k)
+            if (b->slot_busy[k]) {
+                const double w = (double)b->table_h[k].pad_wide - (double)b->table_h[k].pad;
+                skin = skin > 0.0 ? std::min(skin, w) : w;
+            }
+        pl.skin = skin;
+    }
     // colour c of every mesh: one segment each
     int n_colors = 0;
     for (const BatchMesh& m : b->meshes) n_colors = std::max(n_colors, (int)m.color_begin.size() - 1);
@@ -421,7 +432,8 @@ int ccfr_batch_add(ccfr_batch* b, int32_t n_verts, const int32_t* tris, int32_t 
     if (!h.has_stretch) m.color_begin.assign(1, 0);
     b->coll_h[sl] = sp->collision;
     b->typ_h[sl] = h.typ_len;
-    b->table_h[sl] = mesh_params(&sp->collision, h.typ_len, slot_salt(sl), b->ctx->cell_scale, b->ctx->pair_reuse - 1);
+    b->table_h[sl] = mesh_params(&sp->collision, h.typ_len, slot_salt(sl), b->ctx->cell_scale,
+                                  ctx_skin_iters(b->ctx), ctx_skin_mult(b->ctx));
     HIP_OK(hipMemcpyAsync(b->table_d + sl, &b->table_h[sl], sizeof(MeshParams), hipMemcpyHostToDevice, s));
     // pageable sources: the copies must finish before the host vectors go away
     HIP_OK(hipStreamSynchronize(s));
@@ -479,7 +491,7 @@ int ccfr_batch_step(ccfr_batch* b, ccfr_stream stream) {
     if (rc) return rc;
     if (ctx->profiling) {
         ctx->prof_last_iters = b->sp.iters;
-        ctx->prof_last_reuse = ctx->pair_reuse;
+        ctx->prof_last_reuse = ctx->pair_skin > 0 ? 1 : ctx->pair_reuse;
     }
     {
         const Pool& P = b->pool[b->cur];

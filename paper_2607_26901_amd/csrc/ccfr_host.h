@@ -93,6 +93,7 @@ struct ccfr_ctx {
     float cell_scale = 1.0f;    // grid cell size relative to the default
     int pair_split = 1;         // lanes per broad-phase query (1, 3 or 9)
     int pair_reuse = 1;         // solver iterations per candidate build inside a substep
+    int pair_skin = 0;          // > 0: builds widened by pair_skin r, rebuilt when the motion needs it
     long long tune_generation = 0;
 
     // grid
@@ -177,6 +178,9 @@ struct StepPlan {
     std::vector<int32_t> col_first, col_nseg, col_total;
     float dt = 0.f, gx = 0.f, gy = 0.f, gz = 0.f, alpha_t = 0.f;
     int iters = 0;
+    // builds that adapt to the motion: the least widening (pad_wide - pad) of
+    // any mesh's moving boxes; 0 = fixed grouping of iterations
+    double skin = 0.0;
 };
 
 void drop_graph(ccfr_ctx* ctx);
@@ -189,7 +193,13 @@ int ensure_sizes(ccfr_ctx* ctx, long long n_verts, long long n_tris, long long n
                  int n_meshes);
 bool params_ok(const ccfr_params* p);
 bool step_params_ok(const ccfr_step_params* sp);
-MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell_scale, int skin_iters = 0);
+MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell_scale, int skin_iters = 0,
+                       int skin_mult = 0);
+// The widening a context's tuning asks of the boxes of a substep's builds:
+// iterations covered beyond the first (fixed grouping) or multiples of r
+// (builds that adapt to the motion); at most one of them is non-zero.
+inline int ctx_skin_iters(const ccfr_ctx* c) { return c->pair_skin > 0 ? 0 : c->pair_reuse - 1; }
+inline int ctx_skin_mult(const ccfr_ctx* c) { return c->pair_skin; }
 int ensure_prof_events(ccfr_ctx* ctx, int iters);
 void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s);
 // Records the plan as a graph into *g (replacing it) and launches it on s.

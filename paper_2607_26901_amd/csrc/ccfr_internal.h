@@ -34,7 +34,9 @@ enum : uint32_t {
 struct MeshParams {
     float r, xi, pad, two_r;
     float eps_retract, eps_plesnik, h, inv_h;   // h: grid cell size of this mesh
-    int32_t max_passes, mesh_salt, pad0, pad1;
+    int32_t max_passes, mesh_salt;
+    float pad_wide;     // box pad of moving primitives in builds widened by a fixed skin
+    int32_t pad1;
 };
 
 // Device counters shared by all kernels of a context.
@@ -49,6 +51,12 @@ struct DevCounters {
     int32_t last_nc;                   // contacts of the last closed region build
     int32_t last_pairs[3];             // VF, EE, VV of the last closed candidate build
     int32_t pad0;
+    // substeps whose candidate builds adapt to the motion: whether this
+    // iteration builds, the largest coordinate move of the last projection
+    // (FP32 bits, rounded up), and the moves summed since the last build
+    uint32_t rebuild, motion_max;
+    double motion_acc;
+    long long builds;                  // candidate builds closed
     long long need[6];                 // max sizes seen: vf, ee, vv, contacts, hs, large
     long long totals[10];              // vf, ee, vv, hs, violating, halted, degenerate, projected,
                                        // contacts, region builds
@@ -75,6 +83,7 @@ __device__ __forceinline__ void finalize_pairs_body(DevCounters* c, int64_t cap_
     c->last_pairs[0] = (int32_t)nvf;
     c->last_pairs[1] = (int32_t)nee;
     c->last_pairs[2] = (int32_t)nvv;
+    c->builds += 1;
 }
 
 // End of a region build (one thread): overflow bits, largest sizes, totals.
@@ -175,6 +184,7 @@ struct Scene {
     const uint8_t* is_free;     // [n_verts]
     int32_t narrow_fp32;        // 1: narrow-phase arithmetic in FP32 instead of FP64
     int32_t skin_iters;         // candidate builds: further iterations the lists must cover
+    int32_t skin_wide;          // candidate builds: moving boxes padded by MeshParams::pad_wide
     ParamSrc prm;
 };
 
@@ -205,8 +215,10 @@ struct PairLists {
 
 void launch_reset_build(DevCounters* c, uint32_t* level_mask, int n_meshes, hipStream_t s);
 void launch_grid_count(const Scene& sc, GridWs& g, DevCounters* c, hipStream_t s);
-void launch_scan(const int32_t* in, int32_t* out, int32_t* zero_in, int n, int32_t* tmp, hipStream_t s);
-void launch_grid_scatter(const Scene& sc, GridWs& g, hipStream_t s);
+// run_flag (nullable): the scan does nothing when *run_flag is 0
+void launch_scan(const int32_t* in, int32_t* out, int32_t* zero_in, int n, int32_t* tmp, hipStream_t s,
+                 const uint32_t* run_flag = nullptr);
+void launch_grid_scatter(const Scene& sc, GridWs& g, DevCounters* c, hipStream_t s);
 void launch_pairs(const Scene& sc, const GridWs& g, PairLists pl, DevCounters* c, int split, hipStream_t s);
 void launch_finalize_pairs(const GridWs& g, PairLists pl, DevCounters* c, hipStream_t s);
 
@@ -232,6 +244,7 @@ struct ProjectArgs {
     double* sort_key;        // [cap_hs] scratch of regions larger than a wavefront sorts
     int32_t* sort_idx;       // [cap_hs]
     int32_t* slow_list;      // [n_verts] vertices with a violated half-space
+    uint32_t* motion_max;    // nullable: largest coordinate move of an anchor update (FP32 bits)
     ParamSrc prm;
 };
 // zero_counters: clear the slow-list counters first (the substep clears them
@@ -252,6 +265,13 @@ struct PairCaps {
 void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounters* c, uint32_t* level_mask,
                             int n_meshes, int32_t n_verts, const int32_t* offsets, PairCaps caps,
                             int64_t cap_contacts, int64_t cap_hs, bool close_pairs, hipStream_t s);
+// Before the candidate stage of an iteration in a substep whose builds adapt to
+// the motion: adds the last projection's largest move to the moves summed
+// since the last build; if the sum may exceed `skin` (the least widening of
+// any mesh's moving boxes), closes the last build and asks for a new one
+// (DevCounters::rebuild), else the stage's kernels leave the lists as they are.
+void launch_decide_build(DevCounters* c, uint32_t* level_mask, int n_meshes, double skin, PairCaps caps,
+                         hipStream_t s);
 void launch_stretch_segments(const int32_t* edges_sorted, const float* rest_sorted, const int2* segs, int32_t nseg,
                              int32_t total, const float* inv_mass, float* p, float* lambda_sorted, float alpha_t,
                              hipStream_t s);

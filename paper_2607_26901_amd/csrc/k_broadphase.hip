@@ -116,9 +116,11 @@ __device__ __forceinline__ float skin_pad(float pad, float r, int k, float maxab
 }
 
 // Box of a target and its static flag; false if a coordinate is not finite.
-// skin > 0 widens the box of a target with a moving vertex (skin_pad).
-__device__ __forceinline__ bool target_box(const Scene& sc, const Target& g, float pad, float r, int skin,
-                                           float lo[3], float hi[3], bool* is_static) {
+// The box of a target with a moving vertex is widened: by skin_pad when
+// sc.skin_iters > 0, to pad_wide when sc.skin_wide is set.
+__device__ __forceinline__ bool target_box(const Scene& sc, const Target& g, const MeshParams& P, float lo[3],
+                                           float hi[3], bool* is_static) {
+    float pad = P.pad;
     float p[3];
     load3(sc.x, g.v[0], p);
     bool fin = finite3(p);
@@ -133,10 +135,12 @@ __device__ __forceinline__ bool target_box(const Scene& sc, const Target& g, flo
             mx[k] = fmaxf(mx[k], p[k]);
         }
     }
-    if (skin > 0 && !st) {
+    if (sc.skin_iters > 0 && !st) {
         float m = 0.0f;
         for (int k = 0; k < 3; ++k) m = fmaxf(m, fmaxf(fabsf(mn[k]), fabsf(mx[k])));
-        pad = skin_pad(pad, r, skin, m);
+        pad = skin_pad(pad, P.r, sc.skin_iters, m);
+    } else if (sc.skin_wide && !st) {
+        pad = P.pad_wide;
     }
     for (int k = 0; k < 3; ++k) {
         lo[k] = __fsub_rn(mn[k], pad);
@@ -206,7 +210,12 @@ __device__ __forceinline__ void mark_level(uint32_t* level_mask, int mesh, uint3
 }
 
 __global__ void k_reset_build(DevCounters* c, uint32_t* level_mask, int n_meshes) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) reset_build_counters(c);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        reset_build_counters(c);
+        c->rebuild = 1u;            // the first build of a substep or a standalone build
+        c->motion_max = 0u;
+        c->motion_acc = 0.0;
+    }
     for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n_meshes; m += gridDim.x * blockDim.x)
         level_mask[m] = 0u;
 }
@@ -223,6 +232,7 @@ __device__ __forceinline__ int entry_level(const Target& tg, const float lo[3], 
 }
 
 __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCounters* c) {
+    if (!c->rebuild) return;                 // the lists of an earlier build still hold
     const int n_all = sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= n_all) return;
@@ -233,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCo
     bool st;
     int clo[3];
     int level = -2;
-    if (!target_box(sc, tg, P.pad, P.r, sc.skin_iters, lo, hi, &st)) {
+    if (!target_box(sc, tg, P, lo, hi, &st)) {
         atomicOr(&c->status, ST_NONFINITE);
     } else {
         level = entry_level(tg, lo, hi, P.inv_h, clo);
@@ -265,7 +275,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCo
     g.staged[t] = e;
 }
 
-__global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g) {
+__global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g, const DevCounters* c) {
+    if (!c->rebuild) return;
     const int n_all = sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= n_all) return;
@@ -535,6 +546,7 @@ __device__ void block_flush(LDS_PTR Stage* stages, const PairLists& pl, DevCount
 // Work item = (query, part of its stencil) with `split` lanes per query; every
 // lane walks its stencil through global memory.
 __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists pl, DevCounters* c, int split) {
+    if (!c->rebuild) return;
     __shared__ Stage stages[kWaves];
     const StagePtr st = (StagePtr)&stages[threadIdx.x / 64];
     if (__lane_id() == 0) {
@@ -605,10 +617,10 @@ void launch_grid_count(const Scene& sc, GridWs& g, DevCounters* c, hipStream_t s
     hipLaunchKernelGGL(k_grid_count, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, g, c);
 }
 
-void launch_grid_scatter(const Scene& sc, GridWs& g, hipStream_t s) {
+void launch_grid_scatter(const Scene& sc, GridWs& g, DevCounters* c, hipStream_t s) {
     const int n = sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts;
     if (n == 0) return;
-    hipLaunchKernelGGL(k_grid_scatter, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, g);
+    hipLaunchKernelGGL(k_grid_scatter, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, g, c);
 }
 
 void launch_pairs(const Scene& sc, const GridWs& g, PairLists pl, DevCounters* c, int split, hipStream_t s) {

@@ -181,19 +181,44 @@ __device__ __forceinline__ d3 load_prop(const ProjectArgs& a, int v) {
     return mk(yf[0], yf[1], yf[2]);
 }
 
-__device__ __forceinline__ void write_result(const ProjectArgs& a, int v, d3 y, double r, bool halted) {
+// Writes the clamped displacement (or adds it to the anchor) and returns the
+// largest coordinate move of the anchor, exact in FP64 and rounded up to FP32
+// (0 when the anchor is not updated).
+__device__ __forceinline__ float write_result(const ProjectArgs& a, int v, d3 y, double r, bool halted) {
     const double ny = norm(y);
     if (ny > r) y = (r / ny) * y;                      // r-ball clamp
+    float move = 0.0f;
     if (a.y_out) {
         a.y_out[3 * v] = (float)y.x;
         a.y_out[3 * v + 1] = (float)y.y;
         a.y_out[3 * v + 2] = (float)y.z;
     } else {
-        a.x_anchor[3 * v] += (float)y.x;
-        a.x_anchor[3 * v + 1] += (float)y.y;
-        a.x_anchor[3 * v + 2] += (float)y.z;
+        const float y3[3] = {(float)y.x, (float)y.y, (float)y.z};
+        double m = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const float o = a.x_anchor[3 * v + k];
+            const float n = o + y3[k];
+            a.x_anchor[3 * v + k] = n;
+            m = fmax(m, fabs((double)n - (double)o));    // the difference of two floats: exact
+        }
+        move = (float)m;
+        if ((double)move < m) move = __int_as_float(__float_as_int(move) + 1);
     }
     if (a.halted) a.halted[v] = halted ? 1 : 0;
+    return move;
+}
+
+__device__ __forceinline__ float wave_max(float x) {
+    for (int off = 32; off > 0; off >>= 1) x = fmaxf(x, __shfl_xor(x, off));
+    return x;
+}
+
+// Largest move of a wavefront's lanes into the device maximum (non-negative
+// floats order like their bit patterns).
+__device__ __forceinline__ void record_motion(const ProjectArgs& a, float move) {
+    if (!a.motion_max) return;
+    const float m = wave_max(move);
+    if (__lane_id() == 0 && m > 0.0f) atomicMax(a.motion_max, __float_as_uint(m));
 }
 
 // The vertex's CSR range, clipped to the half-space buffer (an offset outside
@@ -279,12 +304,13 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
     const int v = blockIdx.x * kBlock + threadIdx.x;
     const bool active = v < a.n_verts;
     bool violated = false, deferred = false, big = false, moved = false, bad = false;
+    float move = 0.0f;
     if (active) {
         const d3 yprop = a.inv_mass[v] > 0.0f ? load_prop(a, v) : mk(0.0, 0.0, 0.0);
         bad = !(isfinite(yprop.x) && isfinite(yprop.y) && isfinite(yprop.z));
         if (bad) {
             // a non-finite proposal is not moved and raises the status bit
-            write_result(a, v, mk(0.0, 0.0, 0.0), 0.0, true);
+            move = write_result(a, v, mk(0.0, 0.0, 0.0), 0.0, true);
         } else if (a.inv_mass[v] > 0.0f) {
             moved = true;
             const MeshParams P = a.prm.get(a.prm.mesh_of(v));
@@ -311,12 +337,13 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
                 d3 y = yprop;
                 if (n_viol == 1) deferred = !one_plane_regs(R, K, hv, yprop, P, y);
                 else deferred = n_viol > 1;
-                if (!deferred) write_result(a, v, y, (double)P.r, false);
+                if (!deferred) move = write_result(a, v, y, (double)P.r, false);
             }
         } else {
-            write_result(a, v, mk(0.0, 0.0, 0.0), 0.0, false);
+            move = write_result(a, v, mk(0.0, 0.0, 0.0), 0.0, false);
         }
     }
+    record_motion(a, move);
     // vertices that need the full Alg. 2 go to the slow list, one atomic per
     // block and list: small regions from the front, larger ones from the back
     const unsigned long long md = __ballot(deferred && !big);
@@ -467,7 +494,8 @@ __device__ __forceinline__ float4 take(const float4 (&R)[kChunks], int chunk, in
 // the next hit, and all lanes apply the same Alg. 1 update and retraction to
 // their (identical) copies of the state.  This visits exactly the half-spaces
 // the sequential pass would, in the same order, with the same arithmetic.
-__device__ __forceinline__ void project_wave_vertex(const ProjectArgs& a, DevCounters* c, WaveLds* L, int v) {
+// Returns the anchor's largest coordinate move (on lane 0; 0 elsewhere).
+__device__ __forceinline__ float project_wave_vertex(const ProjectArgs& a, DevCounters* c, WaveLds* L, int v) {
     const int lane = __lane_id();
     long long o0;
     const int K = region_size(a, v, &o0);
@@ -586,10 +614,12 @@ __device__ __forceinline__ void project_wave_vertex(const ProjectArgs& a, DevCou
         }
         wave_sync();   // the LDS slice is reused by the wavefront's next vertex
     }
+    float move = 0.0f;
     if (lane == 0) {
-        write_result(a, v, y, (double)P.r, halted);
+        move = write_result(a, v, y, (double)P.r, halted);
         if (halted) spread_add(c, 1, 1ull);
     }
+    return move;
 }
 
 // Both slow lists in one launch.  Blocks [0, wave_blocks) run list B (larger
@@ -603,12 +633,15 @@ __global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCount
         const int n_list = c->n_viol_b;
         const int workers = wave_blocks * (kBlock / 64);
         WaveLds* L = &lds[wave];
+        float move = 0.0f;
         for (int i = blockIdx.x * (kBlock / 64) + wave; i < n_list; i += workers)
-            project_wave_vertex(a, c, L, a.slow_list[a.n_verts - 1 - i]);
+            move = fmaxf(move, project_wave_vertex(a, c, L, a.slow_list[a.n_verts - 1 - i]));
+        record_motion(a, move);
         return;
     }
     const int lane_blocks = gridDim.x - wave_blocks;
     const int n_list = c->n_viol;
+    float move = 0.0f;
     for (int i0 = (blockIdx.x - wave_blocks) * kBlock; i0 < n_list; i0 += lane_blocks * kBlock) {
         const int i = i0 + threadIdx.x;
         bool halted = false;
@@ -619,11 +652,12 @@ __global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCount
             const MeshParams P = a.prm.get(a.prm.mesh_of(v));
             d3 y;
             halted = project_small(a.hs + o0, K, load_prop(a, v), P, y);
-            write_result(a, v, y, (double)P.r, halted);
+            move = fmaxf(move, write_result(a, v, y, (double)P.r, halted));
         }
         const unsigned long long mh = __ballot(halted);
         if (__lane_id() == 0 && mh) spread_add(c, 1, (unsigned long long)__popcll(mh));
     }
+    record_motion(a, move);
 }
 
 __global__ void k_zero_viol(DevCounters* c) {

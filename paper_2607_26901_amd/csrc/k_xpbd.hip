@@ -60,6 +60,30 @@ __global__ __launch_bounds__(kBlock) void k_close_iteration(const float* x_pred,
     if (i < n3) p[i] = x_pred[i];
 }
 
+// One block.  Thread 0 decides (only it reads and writes the motion fields);
+// the block then clears the level masks of a build to come.
+__global__ __launch_bounds__(kBlock) void k_decide_build(DevCounters* c, uint32_t* level_mask, int n_meshes,
+                                                         double skin, PairCaps caps) {
+    __shared__ int go;
+    if (threadIdx.x == 0) {
+        const double acc = c->motion_acc + (double)__uint_as_float(c->motion_max);
+        // the sum is rounded: compare with a relative margin far above its error
+        const bool rebuild = acc * (1.0 + 1e-12) > skin;
+        if (rebuild) {
+            finalize_pairs_body(c, caps.vf, caps.ee, caps.vv);
+            c->n_vf = c->n_ee = c->n_vv = 0;
+            c->n_large_t = c->n_large_e = 0;
+        }
+        c->motion_acc = rebuild ? 0.0 : acc;
+        c->motion_max = 0u;
+        c->rebuild = rebuild ? 1u : 0u;
+        go = rebuild ? 1 : 0;
+    }
+    __syncthreads();
+    if (go)
+        for (int m = threadIdx.x; m < n_meshes; m += kBlock) level_mask[m] = 0u;
+}
+
 // Colour class of the stretch pass: its edges lie in nseg segments of the
 // colour-sorted edge array, segs[k] = (first edge, exclusive prefix of segment
 // lengths); thread t finds its segment by binary search.
@@ -128,6 +152,11 @@ void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounte
     const long long n = std::max<long long>(std::max<long long>(n3, n_meshes), 1);
     hipLaunchKernelGGL(k_close_iteration, dim3(blocks_for(n)), dim3(kBlock), 0, s, x_pred, p, (long long)n3, c,
                        level_mask, n_meshes, n_verts, offsets, caps, cap_contacts, cap_hs, close_pairs ? 1 : 0);
+}
+
+void launch_decide_build(DevCounters* c, uint32_t* level_mask, int n_meshes, double skin, PairCaps caps,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_decide_build, dim3(1), dim3(kBlock), 0, s, c, level_mask, n_meshes, skin, caps);
 }
 
 void launch_stretch_segments(const int32_t* edges_sorted, const float* rest_sorted, const int2* segs, int32_t nseg,

@@ -162,7 +162,7 @@ def run_steps(ctx, ccfr, torch, sc, steps, tuned=True):
         v.copy_(v0)
     else:
         raise AssertionError("capacity did not converge")
-    ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1)
+    ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1, pair_skin=0)
     return x.cpu().numpy(), v.cpu().numpy()
 
 

@@ -1,7 +1,8 @@
 """A candidate build shared by several solver iterations of a substep (its
-boxes widened by the motion those iterations can make) changes speed only:
-whole substeps give the same positions and velocities, bit for bit, as a build
-per iteration, alone and in a batch."""
+boxes widened by the motion those iterations can make, or by a fixed skin with
+a new build once the measured motion may exceed it) changes speed only: whole
+substeps give the same positions and velocities, bit for bit, as a build per
+iteration, alone and in a batch."""
 import numpy as np
 import pytest
 
@@ -56,25 +57,39 @@ def _run(ctx, ccfr, torch, sc, steps):
     raise AssertionError("capacity did not converge")
 
 
+MODES = [(2, 0), (3, 0), (4, 0), (1, 1), (1, 2), (1, 3)]      # (pair_reuse, pair_skin)
+
+
 @pytest.mark.parametrize("name", list(SCENES))
 def test_reuse_is_bitwise_identical(env, name):
+    """Fixed groups of 2-4 iterations per build, and builds that follow the
+    measured motion within a skin of 1-3 r, against a build per iteration."""
     ctx, ccfr, torch = env
     sc = SCENES[name]()
     steps = 3
+    n_iters = steps * sc.step.iters
     try:
-        ctx.set_tuning(pair_reuse=1)
+        ctx.set_tuning(pair_reuse=1, pair_skin=0)
         x1, v1, info1 = _run(ctx, ccfr, torch, sc, steps)
         assert info1["totals"][8] > 0                      # the steps have contacts
-        for reuse in (2, 3, 4):
-            ctx.set_tuning(pair_reuse=reuse)
-            assert ctx.get_tuning()["pair_reuse"] == reuse
+        assert info1["candidate_builds"] == n_iters
+        for reuse, skin in MODES:
+            ctx.set_tuning(pair_reuse=reuse, pair_skin=skin)
+            t = ctx.get_tuning()
+            assert (t["pair_reuse"], t["pair_skin"]) == (reuse, skin)
             x, v, info = _run(ctx, ccfr, torch, sc, steps)
-            assert np.array_equal(x, x1) and np.array_equal(v, v1), (name, reuse)
-            # the same contacts and half-spaces every iteration; longer lists
+            assert np.array_equal(x, x1) and np.array_equal(v, v1), (name, reuse, skin)
+            # the same contacts and half-spaces every iteration; longer lists, fewer builds
             assert info["totals"][8] == info1["totals"][8] and info["totals"][3] == info1["totals"][3]
             assert info["totals"][9] == info1["totals"][9]
+            if skin == 0:
+                assert info["candidate_builds"] == steps * -(-sc.step.iters // reuse)
+            else:
+                assert steps <= info["candidate_builds"] <= n_iters
+                if skin == 3:
+                    assert info["candidate_builds"] < n_iters      # a vertex moves at most r per iteration
     finally:
-        ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1)
+        ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1, pair_skin=0)
 
 
 def test_reuse_in_batch_equals_alone(env):
@@ -86,31 +101,32 @@ def test_reuse_in_batch_equals_alone(env):
         sc.step = scs[0].step                 # one batch steps with one dt, gravity and iteration count
     steps = 3
     try:
-        ctx.set_tuning(pair_reuse=1)
+        ctx.set_tuning(pair_reuse=1, pair_skin=0)
         alone = [_run(ctx, ccfr, torch, sc, steps)[:2] for sc in scs]
-        ctx.set_tuning(pair_reuse=3, cell_scale=0.85)
         nv = sum(s.n_verts for s in scs)
-        b = ccfr.Batch(ctx, 8, nv, sum(len(s.tris) for s in scs) + 8, sum(len(s.edges) for s in scs) + 8)
-        slots = [b.add_scene(sc, ccfr.make_step_params(sc.step, sc.params)) for sc in scs]
-        done = 0
-        for _ in range(12):
-            b.step()
-            code, info = ctx.sync_status(reset=True)
-            if code == -2:
-                ctx.grow(info)
-                b.rollback()
-                continue
-            assert code == 0, info
-            done += 1
-            if done == steps:
-                break
-        assert done == steps
-        for sl, sc, (xa, va) in zip(slots, scs, alone):
-            xb, vb = b.read(sl)
-            assert np.array_equal(xb, xa) and np.array_equal(vb, va), sc.name
-        b.close()
+        for reuse, skin in ((3, 0), (1, 2)):
+            ctx.set_tuning(pair_reuse=reuse, pair_skin=skin, cell_scale=0.85)
+            b = ccfr.Batch(ctx, 8, nv, sum(len(s.tris) for s in scs) + 8, sum(len(s.edges) for s in scs) + 8)
+            slots = [b.add_scene(sc, ccfr.make_step_params(sc.step, sc.params)) for sc in scs]
+            done = 0
+            for _ in range(12):
+                b.step()
+                code, info = ctx.sync_status(reset=True)
+                if code == -2:
+                    ctx.grow(info)
+                    b.rollback()
+                    continue
+                assert code == 0, info
+                done += 1
+                if done == steps:
+                    break
+            assert done == steps
+            for sl, sc, (xa, va) in zip(slots, scs, alone):
+                xb, vb = b.read(sl)
+                assert np.array_equal(xb, xa) and np.array_equal(vb, va), (sc.name, reuse, skin)
+            b.close()
     finally:
-        ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1)
+        ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1, pair_skin=0)
 
 
 def test_reuse_argument_range(env):
@@ -118,5 +134,7 @@ def test_reuse_argument_range(env):
     for bad in (-1, 5):
         with pytest.raises(ccfr.CcfrError):
             ctx.set_tuning(pair_reuse=bad)
+        with pytest.raises(ccfr.CcfrError):
+            ctx.set_tuning(pair_skin=bad)
     ctx.set_tuning(pair_reuse=0)                           # reads as 1
     assert ctx.get_tuning()["pair_reuse"] == 1

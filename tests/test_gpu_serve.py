@@ -46,4 +46,4 @@ def test_served_stream_equals_sequential():
     # the cell size was tuned mid-stream (rolled-back trial steps), which must
     # not change any result
     assert s["tuning"] is not None and s["tuning"]["cell_scale"] in (0.7, 0.85, 1.0)
-    ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1)
+    ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1, pair_skin=0)

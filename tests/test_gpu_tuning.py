@@ -39,7 +39,7 @@ def test_candidates_exact_at_any_cell_size(env, scale, split, name):
         for k in ("vf", "ee", "vv"):
             assert np.array_equal(H.sorted_pairs(got[k]), H.sorted_pairs(want[k])), (k, scale)
     finally:
-        ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1)
+        ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1, pair_skin=0)
 
 
 def test_steps_identical_across_cell_sizes(env):
@@ -58,7 +58,7 @@ def test_steps_identical_across_cell_sizes(env):
         code, info = ctx.sync_status(reset=True)
         assert code == 0, info
         outs.append(x.cpu().numpy())
-    ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1)
+    ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1, pair_skin=0)
     for o in outs[1:]:
         assert np.abs(o.astype(np.float64) - outs[0]).max() <= H.step_tol(sc, sc.step.iters)
 
@@ -76,4 +76,4 @@ def test_autotuner_picks_a_candidate_and_restores_state(env):
     assert ctx.get_tuning()["pair_split"] == out["pair_split"]
     assert ctx.get_tuning()["cell_scale"] == pytest.approx(out["cell_scale"], rel=1e-6)
     assert np.array_equal(x.cpu().numpy(), sc.x) and np.array_equal(v.cpu().numpy(), sc.v)
-    ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1)
+    ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1, pair_skin=0)
