@@ -281,7 +281,8 @@ void enqueue_candidates(ccfr_ctx* ctx, const Scene& sc, int n_meshes, hipStream_
     mk.mark(0, 0);
     if (standalone) launch_reset_build(ctx->counters_d, g.level_mask, g.n_meshes, s);
     launch_grid_count(sc, g, ctx->counters_d, s);
-    launch_scan(g.cnt, g.start, g.cnt, g.off[4], g.scan_tmp, s, &ctx->counters_d->rebuild);
+    launch_scan(g.cnt, g.start, g.cnt, g.off[4], g.scan_tmp, s,
+                sc.build_gated ? &ctx->counters_d->rebuild : nullptr);
     launch_grid_scatter(sc, g, ctx->counters_d, s);
     mk.mark(0, 1);
     PairLists pl{ctx->vf, ctx->ee, ctx->vv, ctx->cap_vf, ctx->cap_ee, ctx->cap_vv};
@@ -291,16 +292,28 @@ void enqueue_candidates(ccfr_ctx* ctx, const Scene& sc, int n_meshes, hipStream_
     if (standalone) launch_finalize_pairs(g, pl, ctx->counters_d, s);
 }
 
+// Slots per vertex when a substep's regions go into per-vertex slots (the
+// context's half-space buffer divided evenly), or 0 for CSR regions.
+int32_t step_slot_stride(const ccfr_ctx* ctx, int n_verts) {
+    if (ctx->csr_in_step || n_verts <= 0) return 0;
+    return (int32_t)std::max<long long>(1, std::min<long long>(ctx->cap_hs / n_verts, 1LL << 20));
+}
+
 // narrow phase into the context's regions; inside a substep (`in_step`) both
-// builds are closed by launch_close_iteration
+// builds are closed by launch_close_iteration, and with slot_stride > 0 the
+// half-spaces go into per-vertex slots (no scan or fill)
 void enqueue_regions(ccfr_ctx* ctx, const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
                      const int32_t* counts, long long cap_vf, long long cap_ee, long long cap_vv, hipStream_t s,
-                     const Marks& mk, bool in_step) {
+                     const Marks& mk, bool in_step, int32_t slot_stride = 0) {
     mk.mark(2, 0);
     launch_contacts(sc, vf, ee, vv, counts, cap_vf, cap_ee, cap_vv, ctx->contacts, ctx->cap_contacts, ctx->vcount,
-                    ctx->counters_d, s);
+                    ctx->counters_d, s, ctx->hs, in_step ? slot_stride : 0);
     mk.mark(2, 1);
     mk.mark(3, 0);
+    if (in_step && slot_stride > 0) {
+        mk.mark(3, 1);
+        return;
+    }
     launch_scan(ctx->vcount, ctx->offsets, nullptr, sc.n_verts, ctx->scan_tmp, s);
     launch_fill(sc, ctx->contacts, ctx->cap_contacts, ctx->offsets, ctx->vcount, ctx->hs, ctx->cap_hs,
                 ctx->counters_d, !in_step, s);
@@ -343,6 +356,7 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
     const bool adaptive = plan.skin > 0.0;
     const int reuse = adaptive ? 1 : std::max(1, ctx->pair_reuse);
     const PairCaps caps{ctx->cap_vf, ctx->cap_ee, ctx->cap_vv};
+    const int32_t slots = step_slot_stride(ctx, n);
     for (int it = 0; it < plan.iters; ++it) {
         const Marks mk{ctx, it, s};
         const int first = it - it % reuse;
@@ -351,6 +365,7 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
             if (it > 0) launch_decide_build(ctx->counters_d, ctx->level_mask, plan.n_meshes, plan.skin, caps, s);
             Scene sb = sc;
             sb.skin_wide = 1;
+            sb.build_gated = 1;
             enqueue_candidates(ctx, sb, plan.n_meshes, s, mk, false);
         } else if (it == first) {
             Scene sb = sc;
@@ -363,11 +378,11 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
             }
         }
         enqueue_regions(ctx, sc, ctx->vf, ctx->ee, ctx->vv, counts_ptr(ctx), ctx->cap_vf, ctx->cap_ee,
-                        ctx->cap_vv, s, mk, true);
+                        ctx->cap_vv, s, mk, true, slots);
         mk.mark(4, 0);
         launch_close_iteration(ctx->x_pred, ctx->p, 3LL * n, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
                                ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs,
-                               adaptive ? it == plan.iters - 1 : it == first + group - 1, s);
+                               adaptive ? it == plan.iters - 1 : it == first + group - 1, s, slots);
         if (plan.has_stretch) {
             for (size_t c = 0; c < plan.col_total.size(); ++c)
                 launch_stretch_segments(plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[c],
@@ -390,6 +405,8 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
         pa.sort_idx = ctx->sort_idx;
         pa.slow_list = ctx->slow_list;
         pa.motion_max = adaptive ? &ctx->counters_d->motion_max : nullptr;
+        pa.slot_counts = ctx->vcount;
+        pa.slot_stride = slots;
         pa.prm = sc.prm;
         mk.mark(5, 0);
         launch_project(pa, ctx->counters_d, false, s);
@@ -594,6 +611,8 @@ int ccfr_create(ccfr_ctx** out, int device) {
     ctx->use_graphs = !(ng && ng[0] == '1');
     const char* nf = std::getenv("CCFR_NARROW_FP32");
     ctx->narrow_fp32 = nf && nf[0] == '1';
+    const char* cs = std::getenv("CCFR_CSR_IN_STEP");
+    ctx->csr_in_step = cs && cs[0] == '1';
     if (dev_alloc(&ctx->counters_d, 1) != hipSuccess ||
         hipMemset(ctx->counters_d, 0, sizeof(DevCounters)) != hipSuccess ||
         hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess) {

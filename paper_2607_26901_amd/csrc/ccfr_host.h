@@ -90,6 +90,7 @@ struct ccfr_ctx {
     long long generation = 0;   // bumped whenever a workspace buffer moves
     bool use_graphs = true;
     bool narrow_fp32 = false;   // narrow-phase arithmetic in FP32 (measurement option)
+    bool csr_in_step = false;   // substeps build CSR regions instead of slots (measurement option)
     float cell_scale = 1.0f;    // grid cell size relative to the default
     int pair_split = 1;         // lanes per broad-phase query (1, 3 or 9)
     int pair_reuse = 1;         // solver iterations per candidate build inside a substep

@@ -56,6 +56,9 @@ struct DevCounters {
     // (FP32 bits, rounded up), and the moves summed since the last build
     uint32_t rebuild, motion_max;
     double motion_acc;
+    // region builds into per-vertex slots: half-spaces written, and the largest
+    // number any vertex received (beyond its slots they are dropped)
+    int32_t n_hs, max_slot;
     long long builds;                  // candidate builds closed
     long long need[6];                 // max sizes seen: vf, ee, vv, contacts, hs, large
     long long totals[10];              // vf, ee, vv, hs, violating, halted, degenerate, projected,
@@ -109,6 +112,26 @@ __device__ __forceinline__ void reset_region_counters(DevCounters* c) {
     c->n_contacts = 0;
     c->n_viol = 0;
     c->n_viol_b = 0;
+    c->n_hs = 0;
+    c->max_slot = 0;
+}
+
+// End of a region build into per-vertex slots of `stride` entries (one thread):
+// a vertex that received more half-spaces than its slots sets the overflow bit,
+// and the need is reported as the half-space buffer that would hold them all.
+__device__ __forceinline__ void finalize_slot_regions_body(DevCounters* c, int32_t n_verts, int32_t stride,
+                                                           int64_t cap_contacts) {
+    const long long H = c->n_hs;
+    const long long nc = c->n_contacts;
+    if (c->max_slot > stride) c->status |= ST_HS;
+    if (nc > cap_contacts) c->status |= ST_CONTACTS;
+    c->need[3] = max(c->need[3], nc);
+    c->need[4] = max(c->need[4], (long long)c->max_slot * (long long)n_verts);
+    c->totals[3] += H;
+    c->totals[8] += nc;
+    c->totals[9] += 1;
+    c->last_hs = (int32_t)H;
+    c->last_nc = (int32_t)nc;
 }
 
 __device__ __forceinline__ void reset_build_counters(DevCounters* c) {
@@ -185,6 +208,7 @@ struct Scene {
     int32_t narrow_fp32;        // 1: narrow-phase arithmetic in FP32 instead of FP64
     int32_t skin_iters;         // candidate builds: further iterations the lists must cover
     int32_t skin_wide;          // candidate builds: moving boxes padded by MeshParams::pad_wide
+    int32_t build_gated;        // candidate builds: run only when DevCounters::rebuild is set
     ParamSrc prm;
 };
 
@@ -222,9 +246,13 @@ void launch_grid_scatter(const Scene& sc, GridWs& g, DevCounters* c, hipStream_t
 void launch_pairs(const Scene& sc, const GridWs& g, PairLists pl, DevCounters* c, int split, hipStream_t s);
 void launch_finalize_pairs(const GridWs& g, PairLists pl, DevCounters* c, hipStream_t s);
 
+// slot_stride > 0: the half-spaces go straight into per-vertex slots,
+// slot_hs[v * slot_stride + k] for the k-th one vertex v receives (vcount[v]
+// counts them), instead of a contact list for launch_fill
 void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
                      const int32_t* counts, int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
-                     Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s);
+                     Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s,
+                     ccfr_halfspace* slot_hs = nullptr, int32_t slot_stride = 0);
 // finalize: close the region build (overflow bits, totals) in a launch of its own
 void launch_fill(const Scene& sc, const Contact* contacts, int64_t cap_contacts, const int32_t* offsets,
                  int32_t* vcount, ccfr_halfspace* hs, int64_t cap_hs, DevCounters* c, bool finalize,
@@ -245,6 +273,11 @@ struct ProjectArgs {
     int32_t* sort_idx;       // [cap_hs]
     int32_t* slow_list;      // [n_verts] vertices with a violated half-space
     uint32_t* motion_max;    // nullable: largest coordinate move of an anchor update (FP32 bits)
+    // regions in per-vertex slots (slot_stride > 0, offsets unused): vertex v's
+    // half-spaces are hs[v * slot_stride ...] and slot_counts[v] of them; the
+    // projection sets each count back to zero once it has read it
+    int32_t* slot_counts;
+    int32_t slot_stride;
     ParamSrc prm;
 };
 // zero_counters: clear the slow-list counters first (the substep clears them
@@ -262,9 +295,11 @@ void launch_copy(const float* src, float* dst, int64_t n, hipStream_t s);
 struct PairCaps {
     int64_t vf, ee, vv;
 };
+// slot_stride > 0: the region build went into per-vertex slots (offsets unused)
 void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounters* c, uint32_t* level_mask,
                             int n_meshes, int32_t n_verts, const int32_t* offsets, PairCaps caps,
-                            int64_t cap_contacts, int64_t cap_hs, bool close_pairs, hipStream_t s);
+                            int64_t cap_contacts, int64_t cap_hs, bool close_pairs, hipStream_t s,
+                            int32_t slot_stride = 0);
 // Before the candidate stage of an iteration in a substep whose builds adapt to
 // the motion: adds the last projection's largest move to the moves summed
 // since the last build; if the sum may exceed `skin` (the least widening of

@@ -232,7 +232,7 @@ __device__ __forceinline__ int entry_level(const Target& tg, const float lo[3], 
 }
 
 __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCounters* c) {
-    if (!c->rebuild) return;                 // the lists of an earlier build still hold
+    if (sc.build_gated && !c->rebuild) return;   // the lists of an earlier build still hold
     const int n_all = sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= n_all) return;
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCo
 }
 
 __global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g, const DevCounters* c) {
-    if (!c->rebuild) return;
+    if (sc.build_gated && !c->rebuild) return;
     const int n_all = sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= n_all) return;
@@ -546,7 +546,7 @@ __device__ void block_flush(LDS_PTR Stage* stages, const PairLists& pl, DevCount
 // Work item = (query, part of its stencil) with `split` lanes per query; every
 // lane walks its stencil through global memory.
 __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists pl, DevCounters* c, int split) {
-    if (!c->rebuild) return;
+    if (sc.build_gated && !c->rebuild) return;
     __shared__ Stage stages[kWaves];
     const StagePtr st = (StagePtr)&stages[threadIdx.x / 64];
     if (__lane_id() == 0) {

@@ -222,8 +222,16 @@ __device__ __forceinline__ void record_motion(const ProjectArgs& a, float move) 
 }
 
 // The vertex's CSR range, clipped to the half-space buffer (an offset outside
-// it yields an empty region, never an access outside the buffer).
+// it yields an empty region, never an access outside the buffer); or its slots.
+__device__ __forceinline__ void slots_consumed(const ProjectArgs& a, int v) {
+    if (a.slot_stride > 0) a.slot_counts[v] = 0;     // clear for the next region build
+}
+
 __device__ __forceinline__ int region_size(const ProjectArgs& a, int v, long long* o0) {
+    if (a.slot_stride > 0) {
+        *o0 = (long long)v * a.slot_stride;
+        return min(a.slot_counts[v], a.slot_stride);
+    }
     const long long lo = a.offsets[v];
     const long long o1 = min((long long)a.offsets[v + 1], (long long)a.cap_hs);
     *o0 = (lo < 0 || lo > a.cap_hs) ? 0 : lo;
@@ -343,6 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
             move = write_result(a, v, mk(0.0, 0.0, 0.0), 0.0, false);
         }
     }
+    if (active && !deferred) slots_consumed(a, v);
     record_motion(a, move);
     // vertices that need the full Alg. 2 go to the slow list, one atomic per
     // block and list: small regions from the front, larger ones from the back
@@ -618,6 +627,7 @@ __device__ __forceinline__ float project_wave_vertex(const ProjectArgs& a, DevCo
     if (lane == 0) {
         move = write_result(a, v, y, (double)P.r, halted);
         if (halted) spread_add(c, 1, 1ull);
+        slots_consumed(a, v);
     }
     return move;
 }
@@ -653,6 +663,7 @@ __global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCount
             d3 y;
             halted = project_small(a.hs + o0, K, load_prop(a, v), P, y);
             move = fmaxf(move, write_result(a, v, y, (double)P.r, halted));
+            slots_consumed(a, v);
         }
         const unsigned long long mh = __ballot(halted);
         if (__lane_id() == 0 && mh) spread_add(c, 1, (unsigned long long)__popcll(mh));

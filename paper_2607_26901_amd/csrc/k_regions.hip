@@ -154,6 +154,7 @@ __device__ __forceinline__ void block_append(Contact* list, int32_t* counter, in
 struct PairVerts {
     int nA, nB;
     int a[2], b[3];
+    float wa[2], wb[3];   // their inverse masses (filled for pairs in range)
 };
 
 template <class R>
@@ -163,18 +164,18 @@ __device__ bool eval_pair(const Scene& sc, int kind, int pa, int pb, Contact* re
     R nvec[3];
     R wA, wB;
     int mesh;
+    // geometry first: the inverse masses are read only for the few pairs in range
+    R bary[3], s = R(0), t = R(0);
     if (kind == KIND_VF) {
-        const int v = pa, t = pb;
-        const int t0 = sc.tris[3 * t], t1 = sc.tris[3 * t + 1], t2 = sc.tris[3 * t + 2];
+        const int v = pa, tr = pb;
+        const int t0 = sc.tris[3 * tr], t1 = sc.tris[3 * tr + 1], t2 = sc.tris[3 * tr + 2];
         mesh = sc.prm.mesh_of(v);
         R p[3], A[3], B[3], Cc[3];
         ld3(sc.x, v, p); ld3(sc.x, t0, A); ld3(sc.x, t1, B); ld3(sc.x, t2, Cc);
         for (int k = 0; k < 3; ++k) { A[k] -= p[k]; B[k] -= p[k]; Cc[k] -= p[k]; }
-        R q[3], bary[3];
+        R q[3];
         if (!closest_on_triangle(A, B, Cc, q, bary)) { *degenerate = true; return false; }
         for (int k = 0; k < 3; ++k) nvec[k] = -q[k];
-        wA = (R)sc.inv_mass[v];
-        wB = bary[0] * (R)sc.inv_mass[t0] + bary[1] * (R)sc.inv_mass[t1] + bary[2] * (R)sc.inv_mass[t2];
         pv->nA = 1; pv->a[0] = v;
         pv->nB = 3; pv->b[0] = t0; pv->b[1] = t1; pv->b[2] = t2;
     } else if (kind == KIND_EE) {
@@ -185,15 +186,12 @@ __device__ bool eval_pair(const Scene& sc, int kind, int pa, int pb, Contact* re
         R A[3], B[3], Cc[3], D[3];
         ld3(sc.x, e0, A); ld3(sc.x, e1, B); ld3(sc.x, f0, Cc); ld3(sc.x, f1, D);
         for (int k = 0; k < 3; ++k) { B[k] -= A[k]; Cc[k] -= A[k]; D[k] -= A[k]; A[k] = R(0); }
-        R s, t;
         if (closest_on_segments(A, B, Cc, D, &s, &t) < 0) { *degenerate = true; return false; }
         for (int k = 0; k < 3; ++k) {
             const R pp = s * B[k];
             const R qq = Cc[k] + t * (D[k] - Cc[k]);
             nvec[k] = pp - qq;
         }
-        wA = (R(1) - s) * (R)sc.inv_mass[e0] + s * (R)sc.inv_mass[e1];
-        wB = (R(1) - t) * (R)sc.inv_mass[f0] + t * (R)sc.inv_mass[f1];
         pv->nA = 2; pv->a[0] = e0; pv->a[1] = e1;
         pv->nB = 2; pv->b[0] = f0; pv->b[1] = f1;
     } else {
@@ -202,8 +200,6 @@ __device__ bool eval_pair(const Scene& sc, int kind, int pa, int pb, Contact* re
         R A[3], B[3];
         ld3(sc.x, i, A); ld3(sc.x, j, B);
         for (int k = 0; k < 3; ++k) nvec[k] = A[k] - B[k];
-        wA = (R)sc.inv_mass[i];
-        wB = (R)sc.inv_mass[j];
         pv->nA = 1; pv->a[0] = i;
         pv->nB = 1; pv->b[0] = j;
     }
@@ -212,6 +208,22 @@ __device__ bool eval_pair(const Scene& sc, int kind, int pa, int pb, Contact* re
     const R phi = D - (R)P.xi;
     if (!(phi < (R)P.two_r)) return false;
     if (D == R(0)) { *degenerate = true; return false; }
+    // all five inverse masses at once (unused slots repeat a vertex of the pair)
+    pv->wa[0] = sc.inv_mass[pv->a[0]];
+    pv->wa[1] = sc.inv_mass[pv->nA > 1 ? pv->a[1] : pv->a[0]];
+    pv->wb[0] = sc.inv_mass[pv->b[0]];
+    pv->wb[1] = sc.inv_mass[pv->nB > 1 ? pv->b[1] : pv->b[0]];
+    pv->wb[2] = sc.inv_mass[pv->nB > 2 ? pv->b[2] : pv->b[0]];
+    if (kind == KIND_VF) {
+        wA = (R)pv->wa[0];
+        wB = bary[0] * (R)pv->wb[0] + bary[1] * (R)pv->wb[1] + bary[2] * (R)pv->wb[2];
+    } else if (kind == KIND_EE) {
+        wA = (R(1) - s) * (R)pv->wa[0] + s * (R)pv->wa[1];
+        wB = (R(1) - t) * (R)pv->wb[0] + t * (R)pv->wb[1];
+    } else {
+        wA = (R)pv->wa[0];
+        wB = (R)pv->wb[0];
+    }
     const R wsum = wA + wB;
     if (wsum == R(0)) return false;
     const R inv = R(1) / D;
@@ -256,16 +268,87 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Scene sc, const int32_t* vf
             bool deg;
             keep = eval_pair<R>(sc, kind, pa, pb, &rec, &pv, &deg);
             n_degenerate += deg ? 1 : 0;
-            if (keep) {
+            if (keep && vcount) {
                 for (int k = 0; k < pv.nA; ++k)
-                    if (sc.inv_mass[pv.a[k]] > 0.f) atomicAdd(&vcount[pv.a[k]], 1);
+                    if (pv.wa[k] > 0.f) atomicAdd(&vcount[pv.a[k]], 1);
                 for (int k = 0; k < pv.nB; ++k)
-                    if (sc.inv_mass[pv.b[k]] > 0.f) atomicAdd(&vcount[pv.b[k]], 1);
+                    if (pv.wb[k] > 0.f) atomicAdd(&vcount[pv.b[k]], 1);
             }
         }
         block_append(contacts, &c->n_contacts, cap_contacts, rec, keep, wave_cnt, &block_base);
     }
     if (n_degenerate) atomicAdd((unsigned long long*)&c->totals[6], (unsigned long long)n_degenerate);
+}
+
+// Inside a substep the regions go into per-vertex slots instead of a CSR: the
+// contact list is built as for the CSR (without per-vertex counts), then every
+// contact claims the next slot of each receiving vertex with one atomic and
+// writes its half-space there, so no count scan is needed.  A vertex that
+// receives more half-spaces than it has slots keeps the first ones it got and
+// the largest count is reported (the step is then repeated with more room).
+__global__ __launch_bounds__(kBlock) void k_fill_slots(Scene sc, const Contact* contacts, int64_t cap_contacts,
+                                                       int32_t* counts, ccfr_halfspace* hs, int32_t stride,
+                                                       DevCounters* c) {
+    const long long n = min((long long)c->n_contacts, (long long)cap_contacts);
+    const long long stride_g = (long long)gridDim.x * kBlock;
+    int n_hs = 0, top = 0;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride_g) {
+        const Contact rec = contacts[i];
+        const int kind = (int)((uint32_t)rec.a >> 30);
+        const int pa = rec.a & 0x3fffffff, pb = rec.b;
+        int rv[5] = {-1, -1, -1, -1, -1};
+        if (kind == KIND_VF) {
+            rv[0] = pa;
+            rv[2] = sc.tris[3 * pb]; rv[3] = sc.tris[3 * pb + 1]; rv[4] = sc.tris[3 * pb + 2];
+        } else if (kind == KIND_EE) {
+            rv[0] = sc.edges[2 * pa]; rv[1] = sc.edges[2 * pa + 1];
+            rv[2] = sc.edges[2 * pb]; rv[3] = sc.edges[2 * pb + 1];
+        } else {
+            rv[0] = pa; rv[2] = pb;
+        }
+        bool dyn[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) dyn[k] = rv[k] >= 0 && sc.inv_mass[rv[k] >= 0 ? rv[k] : 0] > 0.f;
+        int slot[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) slot[k] = dyn[k] ? atomicAdd(&counts[rv[k]], 1) : 0;
+        ccfr_halfspace h;
+        h.phi = rec.phi;
+        h.flags = 0u;
+        h.key = ((uint64_t)kind << 62) | ((uint64_t)(uint32_t)pa << 31) | (uint64_t)(uint32_t)pb;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            if (!dyn[k]) continue;
+            const float sg = k < 2 ? 1.0f : -1.0f;
+            h.n[0] = sg * rec.n[0]; h.n[1] = sg * rec.n[1]; h.n[2] = sg * rec.n[2];
+            h.d = k < 2 ? rec.dA : rec.dB;
+            top = max(top, slot[k] + 1);
+            if (slot[k] < stride) {
+                hs[(long long)rv[k] * stride + slot[k]] = h;
+                ++n_hs;
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        n_hs += __shfl_xor(n_hs, off);
+        top = max(top, __shfl_xor(top, off));
+    }
+    __shared__ int red[kWavesPerBlock][2];
+    const int wave = threadIdx.x / 64;
+    if (__lane_id() == 0) {
+        red[wave][0] = n_hs;
+        red[wave][1] = top;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int b = 0, t = 0;
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+            b += red[w][0];
+            t = max(t, red[w][1]);
+        }
+        if (b) atomicAdd(&c->n_hs, b);
+        if (t > 0) atomicMax(&c->max_slot, t);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill(Scene sc, const Contact* contacts, int64_t cap_contacts,
@@ -328,14 +411,19 @@ int grid_for(long long n) {
 
 void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
                      const int32_t* counts, int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
-                     Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s) {
+                     Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s,
+                     ccfr_halfspace* slot_hs, int32_t slot_stride) {
     const int blocks = grid_for(cap_vf + cap_ee + cap_vv);
+    int32_t* per_vertex = slot_stride > 0 ? nullptr : vcount;     // slots: counted by the fill
     if (sc.narrow_fp32)
         hipLaunchKernelGGL(k_contacts<float>, dim3(blocks), dim3(kBlock), 0, s, sc, vf, ee, vv, counts, cap_vf,
-                           cap_ee, cap_vv, contacts, cap_contacts, vcount, c);
+                           cap_ee, cap_vv, contacts, cap_contacts, per_vertex, c);
     else
         hipLaunchKernelGGL(k_contacts<double>, dim3(blocks), dim3(kBlock), 0, s, sc, vf, ee, vv, counts, cap_vf,
-                           cap_ee, cap_vv, contacts, cap_contacts, vcount, c);
+                           cap_ee, cap_vv, contacts, cap_contacts, per_vertex, c);
+    if (slot_stride > 0)
+        hipLaunchKernelGGL(k_fill_slots, dim3(grid_for(cap_contacts)), dim3(kBlock), 0, s, sc, contacts,
+                           cap_contacts, vcount, slot_hs, slot_stride, c);
 }
 
 void launch_fill(const Scene& sc, const Contact* contacts, int64_t cap_contacts, const int32_t* offsets,

@@ -47,11 +47,12 @@ __global__ __launch_bounds__(kBlock) void k_close_iteration(const float* x_pred,
                                                             DevCounters* c, uint32_t* level_mask, int n_meshes,
                                                             int32_t n_verts, const int32_t* offsets,
                                                             PairCaps caps, int64_t cap_contacts, int64_t cap_hs,
-                                                            int close_pairs) {
+                                                            int close_pairs, int32_t slot_stride) {
     const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (i == 0) {
         if (close_pairs) finalize_pairs_body(c, caps.vf, caps.ee, caps.vv);
-        finalize_regions_body(c, n_verts, offsets, cap_contacts, cap_hs);
+        if (slot_stride > 0) finalize_slot_regions_body(c, n_verts, slot_stride, cap_contacts);
+        else finalize_regions_body(c, n_verts, offsets, cap_contacts, cap_hs);
         if (close_pairs) reset_build_counters(c);
         else reset_region_counters(c);
     }
@@ -148,10 +149,12 @@ void launch_copy(const float* src, float* dst, int64_t n, hipStream_t s) {
 
 void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounters* c, uint32_t* level_mask,
                             int n_meshes, int32_t n_verts, const int32_t* offsets, PairCaps caps,
-                            int64_t cap_contacts, int64_t cap_hs, bool close_pairs, hipStream_t s) {
+                            int64_t cap_contacts, int64_t cap_hs, bool close_pairs, hipStream_t s,
+                            int32_t slot_stride) {
     const long long n = std::max<long long>(std::max<long long>(n3, n_meshes), 1);
     hipLaunchKernelGGL(k_close_iteration, dim3(blocks_for(n)), dim3(kBlock), 0, s, x_pred, p, (long long)n3, c,
-                       level_mask, n_meshes, n_verts, offsets, caps, cap_contacts, cap_hs, close_pairs ? 1 : 0);
+                       level_mask, n_meshes, n_verts, offsets, caps, cap_contacts, cap_hs, close_pairs ? 1 : 0,
+                       slot_stride);
 }
 
 void launch_decide_build(DevCounters* c, uint32_t* level_mask, int n_meshes, double skin, PairCaps caps,
