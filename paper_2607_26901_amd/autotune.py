@@ -19,6 +19,7 @@ from __future__ import annotations
 import json
 import math
 import os
+import sys
 
 from . import ccfr
 
@@ -65,18 +66,48 @@ class Cache:
             pass
 
 
+class TooLarge(Exception):
+    """A setting whose lists would outgrow the tuner's memory limit."""
+
+
+def list_bytes(info) -> int:
+    """Device bytes of the lists a status record's needs call for."""
+    nd = info["need"]
+    return 8 * (nd[0] + nd[1] + nd[2]) + 32 * nd[3] + 44 * nd[4]
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
 def tune(ctx: ccfr.Context, run, candidates=CELL_SCALES, splits=PAIR_SPLITS, modes=((1, 0),),
-         repeats: int = 2) -> dict:
-    """Time `run()` (device milliseconds of a fixed piece of work, starting from
-    the same state every call) under each (cell scale, split, (reuse, skin));
-    leave the fastest set."""
+         repeats: int = 2, log=_log, grow_factor: float = 4.0) -> dict:
+    """Time `run(limit)` (device milliseconds of a fixed piece of work, starting
+    from the same state every call, and the list bytes it needed) under each
+    (cell scale, split, (reuse, skin)); leave the fastest set.  A setting whose
+    lists would need more than grow_factor times those of the first setting is
+    skipped (run raises TooLarge), and one whose first timing is three times the
+    best so far is not timed again."""
     times = {}
+    limit = None
+    best_ms = math.inf
     for c in candidates:
         for sp in splits:
             for ru, sk in modes:
+                key = (c, sp, ru, sk)
                 ctx.set_tuning(cell_scale=c, pair_split=sp, pair_reuse=ru, pair_skin=sk)
-                run()                           # records the graph for this setting
-                times[(c, sp, ru, sk)] = min(run() for _ in range(repeats))
+                try:
+                    ms, nbytes = run(limit)     # records the graph for this setting
+                    if limit is None:
+                        limit = grow_factor * max(nbytes, 1 << 28)
+                    if ms < 3.0 * best_ms:
+                        ms = min(run(limit)[0] for _ in range(repeats))
+                except TooLarge:
+                    ms = math.inf
+                times[key] = ms
+                best_ms = min(best_ms, ms)
+                if log:
+                    log(f"[tune] cell {c} split {sp} reuse {ru} skin {sk}: {ms:.3f} ms")
     best = min(times, key=times.get)
     ctx.set_tuning(cell_scale=best[0], pair_split=best[1], pair_reuse=best[2], pair_skin=best[3])
     return {"cell_scale": best[0], "pair_split": best[1], "pair_reuse": best[2], "pair_skin": best[3],
@@ -90,7 +121,7 @@ def _events():
 
 def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, steps: int = 4,
               candidates=CELL_SCALES, splits=PAIR_SPLITS, modes=PAIR_MODES, cache: Cache | None = None,
-              key: str | None = None) -> dict:
+              key: str | None = None, log=_log) -> dict:
     """Tune on `steps` single-mesh steps from the state (x, v), which is restored."""
     import torch
     if cache is not None and key is not None:
@@ -101,7 +132,7 @@ def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, ste
             return dict(hit, cached=True)
     x0, v0 = x.clone(), v.clone()
 
-    def run():
+    def run(limit=None):
         for _ in range(4):
             x.copy_(x0)
             v.copy_(v0)
@@ -112,13 +143,15 @@ def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, ste
             e1.record()
             code, info = ctx.sync_status(reset=True)
             if code == 0:
-                return e0.elapsed_time(e1)
+                return e0.elapsed_time(e1), list_bytes(info)
             if code != -2:
                 raise ccfr.CcfrError(code, "tuning run")
+            if limit is not None and list_bytes(info) > limit:
+                raise TooLarge()
             ctx.grow(info)                      # lists too small: grow and time again
         raise ccfr.CcfrError(-2, "tuning run")
 
-    out = tune(ctx, run, candidates, splits, modes)
+    out = tune(ctx, run, candidates, splits, modes, log=log)
     x.copy_(x0)
     v.copy_(v0)
     torch.cuda.synchronize()
@@ -128,9 +161,9 @@ def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, ste
 
 
 def tune_batch(ctx: ccfr.Context, batch: ccfr.Batch, candidates=CELL_SCALES, splits=PAIR_SPLITS,
-               modes=PAIR_MODES) -> dict:
+               modes=PAIR_MODES, log=_log) -> dict:
     """Tune on one step of the resident batch; every trial is rolled back."""
-    def run():
+    def run(limit=None):
         for _ in range(4):
             e0, e1 = _events()
             e0.record()
@@ -139,10 +172,12 @@ def tune_batch(ctx: ccfr.Context, batch: ccfr.Batch, candidates=CELL_SCALES, spl
             code, info = ctx.sync_status(reset=True)
             batch.rollback()
             if code == 0:
-                return e0.elapsed_time(e1)
+                return e0.elapsed_time(e1), list_bytes(info)
             if code != -2:
                 raise ccfr.CcfrError(code, "tuning run")
+            if limit is not None and list_bytes(info) > limit:
+                raise TooLarge()
             ctx.grow(info)
         raise ccfr.CcfrError(-2, "tuning run")
 
-    return tune(ctx, run, candidates, splits, modes)
+    return tune(ctx, run, candidates, splits, modes, log=log)

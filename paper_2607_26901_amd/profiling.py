@@ -71,7 +71,7 @@ def sha256(path: str) -> str:
 def knobs_key(t: dict) -> str:
     """The speed knobs a profile was taken with, as one comparable string."""
     return f"cell_scale={float(t['cell_scale']):.3f} pair_split={int(t['pair_split'])} " \
-           f"pair_reuse={int(t.get('pair_reuse', 1))}"
+           f"pair_reuse={int(t.get('pair_reuse', 1))} pair_skin={int(t.get('pair_skin', 0))}"
 
 
 def read_summary(path: str) -> dict:

@@ -48,3 +48,4 @@ def test_knobs_key_defaults_and_distinguishes():
     a = profiling.knobs_key({"cell_scale": 0.7, "pair_split": 1})
     assert a == profiling.knobs_key({"cell_scale": 0.7000001, "pair_split": 1, "pair_reuse": 1})
     assert a != profiling.knobs_key({"cell_scale": 0.7, "pair_split": 1, "pair_reuse": 3})
+    assert a != profiling.knobs_key({"cell_scale": 0.7, "pair_split": 1, "pair_skin": 2})
