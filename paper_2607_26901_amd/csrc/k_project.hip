@@ -35,6 +35,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kSmall = 8;      // regions up to this size stay in registers
+constexpr int kScan = 32;      // up to this size the fast kernel checks for a violation
 constexpr int kWave = 256;     // up to this size a wavefront sorts them in LDS
 
 struct d3 {
@@ -306,8 +307,9 @@ __device__ __forceinline__ bool one_plane_regs(const float4 (&R)[kSmall], int K,
 }
 
 // Regions of at most kSmall half-spaces are read into registers (independent
-// loads, 16 bytes each); larger ones go to the wavefront path unexamined, so
-// that no lane walks a long region while the rest of its wavefront waits.
+// loads, 16 bytes each); up to kScan the lane only checks for a violated one
+// (none: done); larger ones go to the wavefront path unexamined, so that no
+// lane walks a long region while the rest of its wavefront waits.
 __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCounters* c) {
     const int v = blockIdx.x * kBlock + threadIdx.x;
     const bool active = v < a.n_verts;
@@ -326,8 +328,22 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
             const int K = region_size(a, v, &o0);
             const ccfr_halfspace* H = a.hs + o0;
             big = K > kSmall;
-            if (big) {
+            if (K > kScan) {
                 deferred = true;                 // checked and counted by the wavefront path
+            } else if (big) {
+                // a mid-size region: no violated half-space finishes it here
+                // (Alg. 2's first pass returns the proposal); else the
+                // wavefront path takes it (and counts it)
+                bool any = false;
+                for (int k0 = 0; k0 < K; k0 += 4) {
+                    float4 R4[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) R4[k] = k0 + k < K ? load_plane(H + k0 + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) any = any || (k0 + k < K && rho_at(R4[k], yprop) < 0.0);
+                }
+                deferred = any;
+                if (!deferred) move = write_result(a, v, yprop, (double)P.r, false);
             } else {
                 float4 R[kSmall];
 #pragma unroll

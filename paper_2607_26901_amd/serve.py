@@ -198,7 +198,9 @@ class Server:
             st.max_resident = max(st.max_resident, len(resident))
             if self.tune_at is not None and self.tuning is None and len(resident) >= self.tune_at:
                 from . import autotune
-                self.tuning = autotune.tune_batch(self.ctx, self.batch, candidates=(0.7, 0.85, 1.0), splits=(1,))
+                # a short search: every setting re-records the step graph while requests wait
+                self.tuning = autotune.tune_batch(self.ctx, self.batch, candidates=(0.7, 0.85, 1.0), splits=(1,),
+                                                  modes=((1, 0),))
             st.max_resident_verts = max(st.max_resident_verts, sum(r[0].scene.n_verts for r in resident.values()))
             # one step of every resident request
             while True:
