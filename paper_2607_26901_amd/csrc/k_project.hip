@@ -518,7 +518,10 @@ __device__ __forceinline__ float4 take(const float4 (&R)[kChunks], int chunk, in
 // point for its entries at or after the last hit, the lowest violated one is
 // the next hit, and all lanes apply the same Alg. 1 update and retraction to
 // their (identical) copies of the state.  This visits exactly the half-spaces
-// the sequential pass would, in the same order, with the same arithmetic.
+// the sequential pass would, in the same order, with the same arithmetic up to
+// the third stored plane of a pass; from there on the pass only retracts, and
+// the rest of it runs on the length of yt (one subtraction per violation; the
+// result differs from the step-by-step rescaling by rounding only).
 // Returns the anchor's largest coordinate move (on lane 0; 0 elsewhere).
 __device__ __forceinline__ float project_wave_vertex(const ProjectArgs& a, DevCounters* c, WaveLds* L, int v) {
     const int lane = __lane_id();
@@ -627,6 +630,38 @@ __device__ __forceinline__ float project_wave_vertex(const ProjectArgs& a, DevCo
                     const double nd = norm(yt);
                     yt = (nd > eps_r) ? ((nd - eps_r) / nd) * yt : mk(0.0, 0.0, 0.0);
                     from = hit + 1;
+                    if (S.m == 3) {
+                        // Alg. 1 holds three planes and returns its input from now
+                        // on, so every further violation of this pass only
+                        // retracts: yt keeps its direction u and loses eps in
+                        // length.  With yt = lam u, rho of entry q is
+                        // lam (n_q . u) + d_q, and the rest of the pass runs on
+                        // the scalar lam (the same steps, without a square root
+                        // and a division per violation).
+                        double lam = norm(yt);
+                        const d3 u = lam > 0.0 ? (1.0 / lam) * yt : mk(0.0, 0.0, 0.0);
+                        double au[kChunks];
+#pragma unroll
+                        for (int ch = 0; ch < kChunks; ++ch) au[ch] = dot(mk(R[ch].x, R[ch].y, R[ch].z), u);
+                        while (true) {
+                            int hit2 = -1;
+#pragma unroll
+                            for (int ch = 0; ch < kChunks; ++ch) {
+                                if (hit2 < 0 && ch < n_chunks && ch * 64 + 63 >= from) {
+                                    const int q = ch * 64 + lane;
+                                    const bool viol = q >= from && lam * au[ch] + (double)R[ch].w < 0.0;
+                                    const unsigned long long m = __ballot(viol);
+                                    if (m) hit2 = ch * 64 + __ffsll((long long)m) - 1;
+                                }
+                            }
+                            if (hit2 < 0) break;
+                            ++nviol;
+                            lam = lam > eps_r ? lam - eps_r : 0.0;
+                            from = hit2 + 1;
+                        }
+                        yt = lam * u;
+                        break;
+                    }
                 }
                 if (nviol == 0) {
                     y = yp;
