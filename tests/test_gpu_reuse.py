@@ -138,3 +138,23 @@ def test_reuse_argument_range(env):
             ctx.set_tuning(pair_skin=bad)
     ctx.set_tuning(pair_reuse=0)                           # reads as 1
     assert ctx.get_tuning()["pair_reuse"] == 1
+
+
+@pytest.mark.parametrize("name", ["falling_layers", "particles", "c1_folded"])
+def test_slot_regions_equal_csr_regions(env, name):
+    """Inside a substep the regions go into per-vertex slots; a context made to
+    build CSR regions there instead (the measurement option) gives the same
+    substeps, bit for bit."""
+    import os
+    ctx, ccfr, torch = env
+    sc = SCENES[name]()
+    x1, v1, info1 = _run(ctx, ccfr, torch, sc, 3)
+    os.environ["CCFR_CSR_IN_STEP"] = "1"
+    try:
+        csr_ctx = ccfr.Context(0)
+    finally:
+        del os.environ["CCFR_CSR_IN_STEP"]
+    x2, v2, info2 = _run(csr_ctx, ccfr, torch, sc, 3)
+    assert np.array_equal(x1, x2) and np.array_equal(v1, v2)
+    assert info1["totals"][3] == info2["totals"][3] and info1["totals"][8] == info2["totals"][8]
+    csr_ctx.close()
