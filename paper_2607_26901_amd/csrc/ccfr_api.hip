@@ -30,24 +30,29 @@ void drop_graph(ccfr_ctx* ctx) {
 // Bucket table size (log2) for `entries` binned entries of one kind.
 int grid_log2s(long long entries) { return std::max(6, ceil_log2(std::max(64LL, entries))); }
 
-// Per-kind tables (triangles, edges, particles, vertices) for these counts,
-// four buckets per entry, so that few occupied cells share a bucket: the
-// target tables are looked up by the queries, and the vertex table orders them
-// (a crowded one would interleave distant blocks in one wavefront).
-void grid_layout(long long T, long long E, long long F, long long N, int32_t log2k[4], int32_t off[5]) {
-    const long long cnt[4] = {4 * T, 4 * E, 4 * F, 4 * N};
+// Bucket tables (see TB_*) for these counts: four buckets per entry for the
+// level-0 tables, so that few occupied cells share a bucket (the target tables
+// are looked up by the queries, and the vertex table orders them: a crowded one
+// would interleave distant blocks in one wavefront); the tables of the coarser
+// levels get an eighth of their level-0 table, since few entries are binned
+// above level 0 when the cell size follows the typical edge.
+void grid_layout(long long T, long long E, long long F, long long N, int32_t log2k[TB_COUNT],
+                 int32_t off[TB_COUNT + 1]) {
+    log2k[TB_TRI0] = grid_log2s(4 * T);
+    log2k[TB_TRIC] = std::max(6, log2k[TB_TRI0] - 3);
+    log2k[TB_EDGE0] = grid_log2s(4 * E);
+    log2k[TB_EDGEC] = std::max(6, log2k[TB_EDGE0] - 3);
+    log2k[TB_PART] = grid_log2s(4 * F);
+    log2k[TB_VERT] = grid_log2s(4 * N);
     off[0] = 0;
-    for (int k = 0; k < 4; ++k) {
-        log2k[k] = grid_log2s(cnt[k]);
-        off[k + 1] = off[k] + (1 << log2k[k]);
-    }
+    for (int k = 0; k < TB_COUNT; ++k) off[k + 1] = off[k] + (1 << log2k[k]);
 }
 
 // Grows the grid for T triangles, E edges, F free particles and N vertices.
 int ensure_grid(ccfr_ctx* ctx, long long T, long long E, long long F, long long N) {
-    int32_t log2k[4], off[5];
+    int32_t log2k[TB_COUNT], off[TB_COUNT + 1];
     grid_layout(T, E, F, N, log2k, off);
-    const long long buckets = off[4];
+    const long long buckets = off[TB_COUNT];
     if (buckets > ctx->cap_buckets) {
         dev_free(ctx->cnt);
         dev_free(ctx->start);
@@ -281,7 +286,7 @@ void enqueue_candidates(ccfr_ctx* ctx, const Scene& sc, int n_meshes, hipStream_
     mk.mark(0, 0);
     if (standalone) launch_reset_build(ctx->counters_d, g.level_mask, g.n_meshes, s);
     launch_grid_count(sc, g, ctx->counters_d, s);
-    launch_scan(g.cnt, g.start, g.cnt, g.off[4], g.scan_tmp, s,
+    launch_scan(g.cnt, g.start, g.cnt, g.off[TB_COUNT], g.scan_tmp, s,
                 sc.build_gated ? &ctx->counters_d->rebuild : nullptr);
     launch_grid_scatter(sc, g, ctx->counters_d, s);
     mk.mark(0, 1);

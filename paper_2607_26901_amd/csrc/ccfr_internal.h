@@ -181,17 +181,30 @@ __device__ __forceinline__ uint32_t mix32(uint32_t h) {
     return h;
 }
 
-// bucket of cell (cx, cy, cz) of mesh `salt` in a table of 2^log2s buckets (log2s >= 6)
+// Bucket of cell (cx, cy, cz) of mesh `salt` in a table of 2^log2s buckets
+// (log2s >= 6): the 64 cells of a 4 x 4 x 4 block share the high bits, a hash
+// of the block; the hash is taken in three steps (z, then y, then x) so that a
+// walk over neighbouring cells can share the first two.
+__device__ __forceinline__ uint32_t hash_z(int cz, int salt) {
+    return mix32((uint32_t)(cz >> 2) * 0xC2B2AE3Du ^ (uint32_t)salt);
+}
+__device__ __forceinline__ uint32_t hash_y(int cy, uint32_t hz) { return mix32((uint32_t)(cy >> 2) * 0x85EBCA77u ^ hz); }
+__device__ __forceinline__ uint32_t bucket_x(int cx, int cy, int cz, uint32_t hy, int log2s) {
+    const uint32_t low = (uint32_t)(cx & 3) | ((uint32_t)(cy & 3) << 2) | ((uint32_t)(cz & 3) << 4);
+    const uint32_t h = mix32((uint32_t)(cx >> 2) * 0x9E3779B1u ^ hy);
+    return low | ((h & ((1u << (log2s - 6)) - 1u)) << 6);
+}
 __device__ __forceinline__ uint32_t cell_bucket(int cx, int cy, int cz, int salt, int log2s) {
-    uint32_t low = (uint32_t)(cx & 3) | ((uint32_t)(cy & 3) << 2) | ((uint32_t)(cz & 3) << 4);
-    uint32_t h = mix32((uint32_t)(cx >> 2) * 0x9E3779B1u ^ mix32((uint32_t)(cy >> 2) * 0x85EBCA77u ^
-                       mix32((uint32_t)(cz >> 2) * 0xC2B2AE3Du ^ (uint32_t)salt)));
-    uint32_t mask = (1u << (log2s - 6)) - 1u;
-    return low | ((h & mask) << 6);
+    return bucket_x(cx, cy, cz, hash_y(cy, hash_z(cz, salt)), log2s);
 }
 
+// Grid cell of coordinate v (cell size 1 / inv_h).  The cells are shifted by
+// half a cell so that a plane through the origin (the usual ground) lies inside
+// a cell row at every level instead of on a cell boundary, which would put
+// every box resting on it across two cell rows.  The map is monotone in v,
+// which is all the stencil argument needs.
 __device__ __forceinline__ int cell_coord(float v, float inv_h) {
-    float c = floorf(v * inv_h);
+    float c = floorf(v * inv_h + 0.5f);
     c = fminf(fmaxf(c, -1.0e9f), 1.0e9f);
     return (int)c;
 }
@@ -212,23 +225,39 @@ struct Scene {
     ParamSrc prm;
 };
 
+// Bucket tables, stored one after the other: triangles of level 0, triangles
+// of the coarser levels, edges of level 0, edges of the coarser levels, free
+// particles (level 0 only), vertices (query order only, level 0).  Splitting
+// off the coarser levels keeps their few entries from sharing buckets with the
+// many of level 0: a lookup at a coarse level then meets (nearly) only entries
+// of its own level.
+enum : int { TB_TRI0 = 0, TB_TRIC = 1, TB_EDGE0 = 2, TB_EDGEC = 3, TB_PART = 4, TB_VERT = 5, TB_COUNT = 6 };
+
+// Table of an entry kind (0 triangles, 1 edges, 2 particles, 3 vertices) at a level.
+__device__ __forceinline__ int table_of(int kind0, int level) {
+    return kind0 == 0 ? (level ? TB_TRIC : TB_TRI0) : kind0 == 1 ? (level ? TB_EDGEC : TB_EDGE0)
+                                                    : (kind0 == 2 ? TB_PART : TB_VERT);
+}
+
 struct GridWs {
-    // one bucket table per entry kind (0 triangles, 1 edges, 2 particles,
-    // 3 vertices), each 2^log2k[k] buckets sized for that kind's entries,
-    // stored one after the other from bucket off[k]; off[4] = all buckets
-    int32_t log2k[4];
-    int32_t off[5];
-    int32_t* cnt;               // [off[4]] counts, zero between builds
-    int32_t* start;             // [off[4] + 1] exclusive prefix
+    // table t has 2^log2k[t] buckets starting at bucket off[t]; off[TB_COUNT] = all buckets
+    int32_t log2k[TB_COUNT];
+    int32_t off[TB_COUNT + 1];
+    int32_t* cnt;               // [off[TB_COUNT]] counts, zero between builds
+    int32_t* start;             // [off[TB_COUNT] + 1] exclusive prefix
     int32_t* rank;              // [T + E + F + N] rank of each entry inside its bucket
-    int32_t* key;               // [T + E + F + N] off[kind] + bucket, -1 = not binned
-    GridEntry* entries;         // [T + E + F + N] sorted: triangles, edges, particles, vertices
+    int32_t* key;               // [T + E + F + N] global bucket, -1 = not binned
+    GridEntry* entries;         // [T + E + F + N] sorted in table order
     GridEntry* staged;          // [T + E + F + N] the same entries in primitive order
     uint32_t* level_mask;       // [n_meshes] grid levels occupied by each mesh
     int32_t n_meshes;
     int32_t* scan_tmp;          // block partials of the scan
-    __device__ __forceinline__ int bucket(int kind0, int cx, int cy, int cz, int salt) const {
-        return off[kind0] + (int)cell_bucket(cx, cy, cz, salt, log2k[kind0]);
+    __device__ __forceinline__ int bucket(int table, int cx, int cy, int cz, int salt) const {
+        return off[table] + (int)cell_bucket(cx, cy, cz, salt, log2k[table]);
+    }
+    // the same with the z and y steps of the hash already taken (hy)
+    __device__ __forceinline__ int bucket_hy(int table, int cx, int cy, int cz, uint32_t hy) const {
+        return off[table] + (int)bucket_x(cx, cy, cz, hy, log2k[table]);
     }
 };
 

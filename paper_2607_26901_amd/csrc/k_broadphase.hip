@@ -20,7 +20,11 @@
 // (a 4 m ground quad under 8 mm cloth triangles, large obstacles under fine
 // hair) therefore cost a few extra buckets, not a brute-force list.
 //
-// Vertices are binned too, in a fourth table, only to order the queries: the
+// The coarser levels of triangles and of edges have bucket tables of their own
+// (few entries live there; sharing the level-0 tables would fill their buckets
+// with level-0 entries that every coarse lookup reads and rejects).
+//
+// Vertices are binned too, in a table of their own, only to order the queries: the
 // pair kernel takes vertex and edge queries in bucket order, in which the 64
 // buckets of a 4 x 4 x 4 block of cells are consecutive, so the lanes of a
 // wavefront (and the workgroups of one XCD, see xcd_block) read the same
@@ -34,9 +38,10 @@
 //   grid_scatter the entries (48 B each: box, index, flags, vertices; written
 //                in primitive order by grid_count) moved to their sorted slots
 //   pairs        one thread per query (vertex entries, then edge entries, in
-//                sorted order); found pairs are staged per wavefront in LDS and
-//                written out in blocks of up to 192 with one atomic each
-//                (what is left at the end: one atomic per block and list)
+//                sorted order); each lane keeps the pairs it finds in its own
+//                LDS slice (a register counts them), a wavefront writes its
+//                slices out when one is nearly full, and what is left at the
+//                end goes out with one atomic per block and list
 #include "ccfr_internal.h"
 
 #include <algorithm>
@@ -259,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCo
         g.key[t] = -1;
         return;
     }
-    const int key = g.bucket(tg.kind - 1, clo[0], clo[1], clo[2], level_salt(P.mesh_salt, level));
+    const int key = g.bucket(table_of(tg.kind - 1, level), clo[0], clo[1], clo[2], level_salt(P.mesh_salt, level));
     g.key[t] = key;
     g.rank[t] = atomicAdd(&g.cnt[key], 1);
     // the entry itself, in primitive order; the scatter only moves it
@@ -285,34 +290,101 @@ __global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g, con
     g.entries[g.start[key] + g.rank[t]] = g.staged[t];
 }
 
-// Per-wavefront staging of found pairs in LDS: lanes append to their wave's
-// buffer for the list (ballot + popcount), and a full buffer is written out with
-// one global atomic and coalesced stores.  Each wave only touches its own slice,
-// so no block barrier is involved.
+// Found pairs are staged in LDS.  Vertex-face and edge-edge pairs: every lane
+// owns a slice of kLaneCap pairs of the block's array lane_pairs[slot][thread]
+// and counts its pairs in a register, so an append is one LDS store and needs
+// no exchange with other lanes; a lane appends to the list of its query's kind
+// (vertex query: vertex-face, edge query: edge-edge).  Before a round of
+// kRound entries, a wavefront whose lanes might overflow their slices writes
+// them out (one atomic per list).  Particle pairs, rare, go through one shared
+// buffer per wavefront (ballot + popcount), written out when full.
 constexpr int kWaves = kBlock / 64;
-constexpr int kStage = 192;
-constexpr int kRound = 4;     // entries read per round of a bucket walk
+constexpr int kRound = 4;      // entries read per round of a bucket walk
+constexpr int kLaneCap = 16;   // pairs per lane slice
+constexpr int kStage = 192;    // particle pairs per wavefront buffer
 
-struct Stage {
-    int a[3][kStage];
-    int b[3][kStage];
-    int fill[3];
+#define LDS_PTR __attribute__((address_space(3)))
+
+struct LaneBuf {
+    LDS_PTR uint64_t* slot0;   // &lane_pairs[0][thread]; slot s at slot0[s * kBlock], pair (a, b) as a | b << 32
+    int fill;
+    bool vert;                 // vertex query (vertex-face list) or edge query (edge-edge list)
 };
 
-// The stage lives in LDS; functions take it through an LDS-qualified pointer
-// so that every access is a ds_ instruction (a generic pointer would become a
-// flat access that waits for all outstanding global loads).  Lanes of one
-// wavefront exchange data through it; LDS executes a wavefront's accesses in
-// order, and the wavefront-scope fences keep the compiler from reordering or
-// caching them.
-#define LDS_PTR __attribute__((address_space(3)))
+__device__ __forceinline__ void lane_put(LaneBuf& lb, int a, int b, bool pred) {
+    if (pred) {
+        lb.slot0[lb.fill * kBlock] = (uint64_t)(uint32_t)a | ((uint64_t)(uint32_t)b << 32);
+        ++lb.fill;
+    }
+}
+
+// Exclusive prefix (over the lanes below this one) and total of `n` (0..31)
+// among the active lanes for which `mine` holds; lanes outside take no part.
+__device__ __forceinline__ void wave_prefix(int n, bool mine, int& pre, int& tot) {
+    const unsigned long long below = (1ull << __lane_id()) - 1ull;
+    pre = tot = 0;
+#pragma unroll
+    for (int bit = 0; bit < 5; ++bit) {
+        const unsigned long long m = __ballot(mine && ((n >> bit) & 1));
+        pre += __popcll(m & below) << bit;
+        tot += __popcll(m) << bit;
+    }
+}
+
+__device__ __forceinline__ void lane_write(const LaneBuf& lb, const PairLists& pl, long long at) {
+    int32_t* list = lb.vert ? pl.vf : pl.ee;
+    const int64_t cap = lb.vert ? pl.cap_vf : pl.cap_ee;
+    for (int s = 0; s < lb.fill; ++s) {
+        const long long idx = at + s;
+        if (idx < cap) {
+            const uint64_t pr = lb.slot0[s * kBlock];
+            list[2 * idx + 0] = (int32_t)(uint32_t)pr;
+            list[2 * idx + 1] = (int32_t)(uint32_t)(pr >> 32);
+        }
+    }
+}
+
+// The active lanes of a wavefront write their slices out.
+__device__ __forceinline__ void lane_flush(LaneBuf& lb, const PairLists& pl, DevCounters* c) {
+    int pv, tv, pe, te;
+    wave_prefix(lb.fill, lb.vert, pv, tv);
+    wave_prefix(lb.fill, !lb.vert, pe, te);
+    const int lead = __ffsll((long long)__ballot(true)) - 1;
+    int bv = 0, be = 0;
+    if (__lane_id() == lead) {
+        if (tv) bv = atomicAdd(&c->n_vf, tv);
+        if (te) be = atomicAdd(&c->n_ee, te);
+    }
+    bv = __shfl(bv, lead);
+    be = __shfl(be, lead);
+    lane_write(lb, pl, lb.vert ? (long long)bv + pv : (long long)be + pe);
+    lb.fill = 0;
+}
+
+// Called by the active lanes before a round that may append up to kRound pairs each.
+__device__ __forceinline__ void lane_room(LaneBuf& lb, const PairLists& pl, DevCounters* c) {
+    if (__ballot(lb.fill > kLaneCap - kRound) != 0ull) lane_flush(lb, pl, c);
+}
+
+struct Stage {
+    int a[kStage];
+    int b[kStage];
+    int fill;
+};
+
+// The particle stage lives in LDS; functions take it through an LDS-qualified
+// pointer so that every access is a ds_ instruction (a generic pointer would
+// become a flat access that waits for all outstanding global loads).  Lanes of
+// one wavefront exchange data through it; LDS executes a wavefront's accesses
+// in order, and the wavefront-scope fences keep the compiler from reordering
+// or caching them.
 typedef LDS_PTR Stage* StagePtr;
 
 __device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
-__device__ __forceinline__ void stage_flush(StagePtr st, int k, int32_t* list, int32_t* counter, int64_t cap) {
+__device__ __forceinline__ void stage_flush(StagePtr st, int32_t* list, int32_t* counter, int64_t cap) {
     wave_fence();
-    const int f = st->fill[k];
+    const int f = st->fill;
     if (f == 0) return;
     const unsigned long long act = __ballot(true);
     const int lane = __lane_id();
@@ -325,47 +397,35 @@ __device__ __forceinline__ void stage_flush(StagePtr st, int k, int32_t* list, i
     for (int i = rank; i < f; i += nact) {
         const long long idx = (long long)base + i;
         if (idx < cap) {
-            list[2 * idx + 0] = st->a[k][i];
-            list[2 * idx + 1] = st->b[k][i];
+            list[2 * idx + 0] = st->a[i];
+            list[2 * idx + 1] = st->b[i];
         }
     }
     wave_fence();
-    if (lane == lead) st->fill[k] = 0;
+    if (lane == lead) st->fill = 0;
     wave_fence();
-}
-
-// Writes a wave's staged pairs of list k from position `at` on.
-__device__ __forceinline__ void stage_write(StagePtr st, int k, int32_t* list, int64_t cap, long long at) {
-    const int f = st->fill[k];
-    for (int i = __lane_id(); i < f; i += 64) {
-        const long long idx = at + i;
-        if (idx < cap) {
-            list[2 * idx + 0] = st->a[k][i];
-            list[2 * idx + 1] = st->b[k][i];
-        }
-    }
 }
 
 // Every active lane of the wave must call it.
-__device__ __forceinline__ void stage_pair(StagePtr st, int k, int32_t* list, int32_t* counter, int64_t cap, int a,
-                                           int b, bool pred) {
+__device__ __forceinline__ void stage_pair(StagePtr st, int32_t* list, int32_t* counter, int64_t cap, int a, int b,
+                                           bool pred) {
     const unsigned long long mask = __ballot(pred);
     if (mask == 0ull) return;
     const int n = __popcll(mask);
     wave_fence();
-    int f = st->fill[k];
+    int f = st->fill;
     if (f + n > kStage) {
-        stage_flush(st, k, list, counter, cap);
+        stage_flush(st, list, counter, cap);
         f = 0;
     }
     const int lane = __lane_id();
     if (pred) {
         const int slot = f + __popcll(mask & ((1ull << lane) - 1ull));
-        st->a[k][slot] = a;
-        st->b[k][slot] = b;
+        st->a[slot] = a;
+        st->b[slot] = b;
     }
     wave_fence();
-    if (lane == __ffsll((long long)__ballot(true)) - 1) st->fill[k] = f + n;
+    if (lane == __ffsll((long long)__ballot(true)) - 1) st->fill = f + n;
     wave_fence();
 }
 
@@ -390,11 +450,11 @@ __device__ __forceinline__ bool part_range(int split, int part, const int clo[3]
     return true;
 }
 
-// Bucket range of cell k (0..8, row-major in y then x) of one z layer of a
-// stencil [r0, r1]; ord is the cell's order against the query's own cell when
+// Bucket range in table `table` of cell k (0..8, row-major in y then x) of one
+// z layer of a stencil [r0, r1]; ord is the cell's order against the query's own cell when
 // the half shell applies (`half`), else 1; an empty range is returned for a
 // cell outside the stencil or before the own cell.
-__device__ __forceinline__ void cell_range(const GridWs& g, int kind0, int salt, int k, int cz, const int r0[3],
+__device__ __forceinline__ void cell_range(const GridWs& g, int table, int salt, int k, int cz, const int r0[3],
                                            const int r1[3], const int own[3], bool half, int& s0, int& s1,
                                            int& ord) {
     const int cx = r0[0] + k % 3, cy = r0[1] + k / 3;
@@ -403,9 +463,55 @@ __device__ __forceinline__ void cell_range(const GridWs& g, int kind0, int salt,
     if (cx > r1[0] || cy > r1[1]) return;
     ord = half ? cell_order(cx, cy, cz, own) : 1;
     if (ord < 0) return;
-    const int b = g.bucket(kind0, cx, cy, cz, salt);
+    const int b = g.bucket(table, cx, cy, cz, salt);
     s0 = g.start[b];
     s1 = g.start[b + 1];
+}
+
+// Bucket ranges in table `table` of the nine cells of z layer cz of a stencil
+// [r0, r1] (row-major in y then x), all looked up at once so that their loads
+// are in flight together; a cell outside the stencil, or before the query's
+// own cell when the half shell applies (`half`), gets an empty range.  Returns
+// the position of the own cell in the layer, or -1.
+struct Layer {
+    int s0[9], s1[9];
+    // moves cell k + 1 to position k (constant indices: the ranges stay in registers)
+    __device__ __forceinline__ void shift() {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            s0[k] = s0[k + 1];
+            s1[k] = s1[k + 1];
+        }
+    }
+};
+
+__device__ __forceinline__ int layer_ranges(const GridWs& g, int table, int salt, int cz, const int r0[3],
+                                            const int r1[3], const int own[3], bool half, Layer& L) {
+    const uint32_t hz = hash_z(cz, salt);
+    int k_own = -1;
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky) {
+        const int cy = r0[1] + ky;
+        const uint32_t hy = hash_y(cy, hz);
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+            const int cx = r0[0] + kx;
+            const int k = 3 * ky + kx;
+            bool in = (cx <= r1[0]) & (cy <= r1[1]);
+            if (half) {
+                const int o = cell_order(cx, cy, cz, own);
+                in = in & (o >= 0);
+                if (in & (o == 0)) k_own = k;
+            }
+            L.s0[k] = L.s1[k] = 0;
+            if (in) {
+                const int b = g.bucket_hy(table, cx, cy, cz, hy);
+                L.s0[k] = g.start[b];
+                L.s1[k] = g.start[b + 1];
+            }
+        }
+    }
+    return k_own;
 }
 
 // ---- entry tests of one cell's bucket ----
@@ -418,8 +524,9 @@ struct GlobalSrc {
 // Vertex query v against the triangle entries [i0, i1) of one cell.
 template <class Src>
 __device__ __forceinline__ void scan_vf(Src src, int i0, int i1, const GridEntry& me, int v, int mesh, int l,
-                                        bool q_static, StagePtr st, const PairLists& pl, DevCounters* c) {
+                                        bool q_static, LaneBuf& lb, const PairLists& pl, DevCounters* c) {
     for (int i = i0; i < i1; i += kRound) {
+        lane_room(lb, pl, c);
         GridEntry e[kRound];
 #pragma unroll
         for (int u = 0; u < kRound; ++u) e[u] = src.get(min(i + u, i1 - 1));
@@ -427,7 +534,7 @@ __device__ __forceinline__ void scan_vf(Src src, int i0, int i1, const GridEntry
         for (int u = 0; u < kRound; ++u) {
             const bool hit = (i + u < i1) & entry_ok(e[u], mesh, l, q_static) & overlap(me.lo, me.hi, e[u].lo, e[u].hi) &
                              (e[u].v[0] != v) & (e[u].v[1] != v) & (e[u].v[2] != v);
-            stage_pair(st, 0, pl.vf, &c->n_vf, pl.cap_vf, v, e[u].idx, hit);
+            lane_put(lb, v, e[u].idx, hit);
         }
     }
 }
@@ -440,7 +547,7 @@ __device__ __forceinline__ void scan_vv(Src src, int i0, int i1, int ord, const 
     for (int i = i0; i < i1; ++i) {
         const GridEntry e = src.get(i);
         const bool hit = ((ord > 0) | (e.idx > v)) & entry_ok(e, mesh, 0, q_static) & overlap(me.lo, me.hi, e.lo, e.hi);
-        stage_pair(st, 2, pl.vv, &c->n_vv, pl.cap_vv, min(v, e.idx), max(v, e.idx), hit);
+        stage_pair(st, pl.vv, &c->n_vv, pl.cap_vv, min(v, e.idx), max(v, e.idx), hit);
     }
 }
 
@@ -448,9 +555,10 @@ __device__ __forceinline__ void scan_vv(Src src, int i0, int i1, int ord, const 
 // cell of level l (half shell with the cell's order `ord` when l == lq).
 template <class Src>
 __device__ __forceinline__ void scan_ee(Src src, int i0, int i1, int ord, const GridEntry& me, int eq, int a, int bb,
-                                        int mesh, int l, bool q_static, StagePtr st, const PairLists& pl,
+                                        int mesh, int l, bool q_static, LaneBuf& lb, const PairLists& pl,
                                         DevCounters* c) {
     for (int i = i0; i < i1; i += kRound) {
+        lane_room(lb, pl, c);
         GridEntry e[kRound];
 #pragma unroll
         for (int u = 0; u < kRound; ++u) e[u] = src.get(min(i + u, i1 - 1));
@@ -459,7 +567,7 @@ __device__ __forceinline__ void scan_ee(Src src, int i0, int i1, int ord, const 
             const bool hit = (i + u < i1) & ((ord > 0) | (e[u].idx > eq)) & entry_ok(e[u], mesh, l, q_static) &
                              overlap(me.lo, me.hi, e[u].lo, e[u].hi) & (e[u].v[0] != a) & (e[u].v[0] != bb) &
                              (e[u].v[1] != a) & (e[u].v[1] != bb);
-            stage_pair(st, 1, pl.ee, &c->n_ee, pl.cap_ee, min(eq, e[u].idx), max(eq, e[u].idx), hit);
+            lane_put(lb, min(eq, e[u].idx), max(eq, e[u].idx), hit);
         }
     }
 }
@@ -474,17 +582,18 @@ __device__ __forceinline__ void stencil_cells(const GridEntry& me, float inv, in
 }
 
 __device__ void walk_vf_global(const GridWs& g, const GridEntry& me, int v, int mesh, int l, int salt, bool q_static,
-                               const int clo[3], const int r0[3], const int r1[3], StagePtr st,
+                               const int clo[3], const int r0[3], const int r1[3], LaneBuf& lb,
                                const PairLists& pl, DevCounters* c) {
     const GlobalSrc src{g.entries};
+    const int tb = table_of(0, l);
     for (int cz = r0[2]; cz <= r1[2]; ++cz) {
-        // the next cell's bucket range is looked up while this one is read
-        int n0, n1, nord;
-        cell_range(g, 0, salt, 0, cz, r0, r1, clo, false, n0, n1, nord);
+        Layer L;
+        layer_ranges(g, tb, salt, cz, r0, r1, clo, false, L);
+#pragma unroll 1
         for (int k = 0; k < 9; ++k) {
-            const int s0 = n0, s1 = n1;
-            if (k < 8) cell_range(g, 0, salt, k + 1, cz, r0, r1, clo, false, n0, n1, nord);
-            scan_vf(src, s0, s1, me, v, mesh, l, q_static, st, pl, c);
+            const int s0 = L.s0[0], s1 = L.s1[0];
+            L.shift();
+            scan_vf(src, s0, s1, me, v, mesh, l, q_static, lb, pl, c);
         }
     }
 }
@@ -496,69 +605,96 @@ __device__ void walk_vv_global(const GridWs& g, const GridEntry& me, int v, int 
     for (int cz = r0[2]; cz <= r1[2]; ++cz)
         for (int k = 0; k < 9; ++k) {
             int u0, u1, ord;
-            cell_range(g, 2, salt, k, cz, r0, r1, clo, true, u0, u1, ord);
+            cell_range(g, TB_PART, salt, k, cz, r0, r1, clo, true, u0, u1, ord);
             scan_vv(src, u0, u1, ord, me, v, mesh, q_static, st, pl, c);
         }
 }
 
 __device__ void walk_ee_global(const GridWs& g, const GridEntry& me, int eq, int a, int bb, int mesh, int lq, int l,
                                int salt, bool q_static, const int clo[3], const int r0[3], const int r1[3],
-                               StagePtr st, const PairLists& pl, DevCounters* c) {
+                               LaneBuf& lb, const PairLists& pl, DevCounters* c) {
     const GlobalSrc src{g.entries};
     const bool half = l == lq;
+    const int tb = table_of(1, l);
     for (int cz = r0[2]; cz <= r1[2]; ++cz) {
-        int n0, n1, nord;
-        cell_range(g, 1, salt, 0, cz, r0, r1, clo, half, n0, n1, nord);
+        Layer L;
+        const int k_own = layer_ranges(g, tb, salt, cz, r0, r1, clo, half, L);
+#pragma unroll 1
         for (int k = 0; k < 9; ++k) {
-            const int s0 = n0, s1 = n1, ord = nord;
-            if (k < 8) cell_range(g, 1, salt, k + 1, cz, r0, r1, clo, half, n0, n1, nord);
-            scan_ee(src, s0, s1, ord, me, eq, a, bb, mesh, l, q_static, st, pl, c);
+            const int s0 = L.s0[0], s1 = L.s1[0];
+            L.shift();
+            scan_ee(src, s0, s1, k == k_own ? 0 : 1, me, eq, a, bb, mesh, l, q_static, lb, pl, c);
         }
     }
 }
 
-// The block's waves are done: what is left in their stages goes out with one
-// atomic per list for the whole block.  Every thread of the block calls it.
-template <int W>
-__device__ void block_flush(LDS_PTR Stage* stages, const PairLists& pl, DevCounters* c) {
-    __shared__ int pre[W][3];
-    __shared__ int base[3];
+// The block is done: what is left in the lane slices and the particle stages
+// goes out with one atomic per list for the whole block.  Every thread of the
+// block calls it.
+__device__ void block_flush(LaneBuf& lb, LDS_PTR Stage* stages, const PairLists& pl, DevCounters* c) {
+    __shared__ int wsum[kWaves][3];
+    __shared__ int base[kWaves][3];
+    const int wave = threadIdx.x / 64;
+    int pv, tv, pe, te;
+    wave_prefix(lb.fill, lb.vert, pv, tv);
+    wave_prefix(lb.fill, !lb.vert, pe, te);
+    if (__lane_id() == 0) {
+        wsum[wave][0] = tv;
+        wsum[wave][1] = te;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         int32_t* counters[3] = {&c->n_vf, &c->n_ee, &c->n_vv};
         for (int k = 0; k < 3; ++k) {
             int acc = 0;
-            for (int w = 0; w < W; ++w) {
-                pre[w][k] = acc;
-                acc += stages[w].fill[k];
+            for (int w = 0; w < kWaves; ++w) {
+                base[w][k] = acc;
+                acc += k < 2 ? wsum[w][k] : stages[w].fill;
             }
-            base[k] = acc ? atomicAdd(counters[k], acc) : 0;
+            const int b0 = acc ? atomicAdd(counters[k], acc) : 0;
+            for (int w = 0; w < kWaves; ++w) base[w][k] += b0;
         }
     }
     __syncthreads();
-    const int wave = threadIdx.x / 64;
+    lane_write(lb, pl, lb.vert ? (long long)base[wave][0] + pv : (long long)base[wave][1] + pe);
     const StagePtr st = stages + wave;
-    stage_write(st, 0, pl.vf, pl.cap_vf, (long long)base[0] + pre[wave][0]);
-    stage_write(st, 1, pl.ee, pl.cap_ee, (long long)base[1] + pre[wave][1]);
-    stage_write(st, 2, pl.vv, pl.cap_vv, (long long)base[2] + pre[wave][2]);
+    const int f = st->fill;
+    for (int i = __lane_id(); i < f; i += 64) {
+        const long long idx = (long long)base[wave][2] + i;
+        if (idx < pl.cap_vv) {
+            pl.vv[2 * idx + 0] = st->a[i];
+            pl.vv[2 * idx + 1] = st->b[i];
+        }
+    }
 }
 
 // Work item = (query, part of its stencil) with `split` lanes per query; every
-// lane walks its stencil through global memory.
-__global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists pl, DevCounters* c, int split) {
+// lane walks its stencil through global memory.  A wavefront takes 64
+// consecutive items of one kind: vertex items (vertex-face and particle pairs)
+// or edge items.  The vertex wavefronts are spread evenly among the edge
+// wavefronts over the whole grid (Bresenham), so that every XCD, and every SIMD,
+// gets both kinds in proportion instead of some taking all the heavier vertex
+// queries.
+__global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists pl, DevCounters* c, int split,
+                                                  long long vwaves, long long waves) {
     if (sc.build_gated && !c->rebuild) return;
     __shared__ Stage stages[kWaves];
+    __shared__ uint64_t lane_pairs[kLaneCap][kBlock];
     const StagePtr st = (StagePtr)&stages[threadIdx.x / 64];
-    if (__lane_id() == 0) {
-        st->fill[0] = st->fill[1] = st->fill[2] = 0;
-    }
+    if (__lane_id() == 0) st->fill = 0;
     wave_fence();
-    const int item = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    const int q = item / split;
-    const int part = item - q * split;
-    const int v0 = g.start[g.off[3]], nv_q = g.start[g.off[4]] - v0;     // binned vertices
-    const int e0 = g.start[g.off[1]], ne_q = g.start[g.off[2]] - e0;     // binned edges
-    if (q < nv_q) {
+    LaneBuf lb{(LDS_PTR uint64_t*)&lane_pairs[0][threadIdx.x], 0, true};
+    const long long w = (long long)xcd_block(blockIdx.x, gridDim.x) * kWaves + threadIdx.x / 64;
+    const long long vw = w * vwaves / waves;                 // vertex wavefronts before w
+    const bool vwave = (w + 1) * vwaves / waves > vw;
+    const long long item = (vwave ? vw : w - vw) * 64 + __lane_id();
+    const int q = (int)(item / split);
+    const int part = (int)(item - (long long)q * split);
+    const int v0 = g.start[g.off[TB_VERT]], nv_q = g.start[g.off[TB_VERT + 1]] - v0;     // binned vertices
+    const int e0 = g.start[g.off[TB_EDGE0]], ne_q = g.start[g.off[TB_EDGEC + 1]] - e0;   // binned edges
+    if (w >= waves) {
+        // past the last wavefront: no query
+    } else if (vwave && q < nv_q) {
         // ---- vertex query: vertex-face pairs, and particle pairs for free particles
         const GridEntry me = g.entries[v0 + q];
         const int v = me.idx;
@@ -574,12 +710,13 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
             int clo[3], chi[3], r0[3], r1[3];
             stencil_cells(me, ldexpf(P.inv_h, -l), clo, chi);
             if (!part_range(split, part, clo, chi, r0, r1)) continue;
-            walk_vf_global(g, me, v, mesh, l, salt, q_static, clo, r0, r1, st, pl, c);
+            walk_vf_global(g, me, v, mesh, l, salt, q_static, clo, r0, r1, lb, pl, c);
             if (q_free && l == 0) walk_vv_global(g, me, v, mesh, salt, q_static, clo, r0, r1, st, pl, c);
         }
-    } else if (q >= sc.n_verts && q - sc.n_verts < ne_q) {
+    } else if (!vwave && q < ne_q) {
         // ---- edge query: edge-edge pairs
-        const GridEntry me = g.entries[e0 + (q - sc.n_verts)];
+        lb.vert = false;
+        const GridEntry me = g.entries[e0 + q];
         const int eq = me.idx;
         const int a = me.v[0], bb = me.v[1];
         const int mesh = (int)(me.flags >> 8);
@@ -594,10 +731,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
             int clo[3], chi[3], r0[3], r1[3];
             stencil_cells(me, ldexpf(P.inv_h, -l), clo, chi);
             if (!part_range(split, part, clo, chi, r0, r1)) continue;
-            walk_ee_global(g, me, eq, a, bb, mesh, lq, l, salt, q_static, clo, r0, r1, st, pl, c);
+            walk_ee_global(g, me, eq, a, bb, mesh, lq, l, salt, q_static, clo, r0, r1, lb, pl, c);
         }
     }
-    block_flush<kWaves>((LDS_PTR Stage*)stages, pl, c);
+    block_flush(lb, (LDS_PTR Stage*)stages, pl, c);
 }
 
 __global__ void k_finalize_pairs(PairLists pl, DevCounters* c) {
@@ -628,9 +765,12 @@ void launch_pairs(const Scene& sc, const GridWs& g, PairLists pl, DevCounters* c
     if (n <= 0) return;
     if (split != 3 && split != 9) split = 1;
     while (split > 1 && n * split > (1LL << 31) - kBlock) split /= 3;
-    const long long items = n * split;
-    hipLaunchKernelGGL(k_pairs, dim3((unsigned)((items + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, sc, g, pl, c,
-                       split);
+    // wavefronts of vertex items and of edge items (the binned counts are known
+    // on the device only: the items cover every vertex and every edge)
+    const long long vwaves = ((long long)sc.n_verts * split + 63) / 64;
+    const long long waves = vwaves + ((long long)sc.n_edges * split + 63) / 64;
+    hipLaunchKernelGGL(k_pairs, dim3((unsigned)((waves + kWaves - 1) / kWaves)), dim3(kBlock), 0, s, sc, g, pl, c,
+                       split, vwaves, waves);
 }
 
 void launch_finalize_pairs(const GridWs& g, PairLists pl, DevCounters* c, hipStream_t s) {

@@ -422,7 +422,7 @@ void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, cons
         hipLaunchKernelGGL(k_contacts<double>, dim3(blocks), dim3(kBlock), 0, s, sc, vf, ee, vv, counts, cap_vf,
                            cap_ee, cap_vv, contacts, cap_contacts, per_vertex, c);
     if (slot_stride > 0)
-        hipLaunchKernelGGL(k_fill_slots, dim3(grid_for(cap_contacts)), dim3(kBlock), 0, s, sc, contacts,
+        hipLaunchKernelGGL(k_fill_slots, dim3(grid_for(cap_contacts / 16)), dim3(kBlock), 0, s, sc, contacts,
                            cap_contacts, vcount, slot_hs, slot_stride, c);
 }
 
