@@ -74,12 +74,12 @@ def kernel_bytes(kernel, N, T, E, F, P, C, H):
         return 48 * (T + E + F + N) + N + 8 * P
     if kernel == "contacts":
         # pairs read (8 B), positions and inverse masses once (16 B/vertex), topology
-        # (12 B/tri, 8 B/edge), per-vertex counts (4 B/hs); inside a substep the
-        # half-spaces are written straight into their slots (32 B each), else
-        # contact records (32 B) for the fill pass
+        # (12 B/tri, 8 B/edge), contact records written (32 B) for the fill pass;
+        # for CSR regions also the per-vertex counts (4 B/hs; inside a substep the
+        # slot fill counts them instead)
         if os.environ.get("CCFR_CSR_IN_STEP") == "1":
             return 8 * P + 16 * N + 12 * T + 8 * E + 32 * C + 4 * H
-        return 8 * P + 16 * N + 12 * T + 8 * E + 36 * H
+        return 8 * P + 16 * N + 12 * T + 8 * E + 32 * C
     if kernel == "projection":
         # offsets (4), proposal and anchor (24), w (4), anchor written (12) per
         # vertex; half-spaces read (32 B)

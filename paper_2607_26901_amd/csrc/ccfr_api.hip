@@ -243,7 +243,7 @@ Scene make_scene(const ccfr_mesh* m, const float* x, const ccfr_params* p, int s
     sc.tris = m->tris_d;
     sc.edges = m->edges_d;
     sc.free_list = m->free_list_d;
-    sc.is_free = m->is_free_d;
+    sc.vflags = m->vflags_d;
     sc.prm.table = nullptr;
     sc.prm.vmesh = nullptr;
     sc.prm.one = mesh_params(p, m->typ_len, 0, m->ctx->cell_scale, skin_iters, skin_mult);
@@ -385,11 +385,16 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
         enqueue_regions(ctx, sc, ctx->vf, ctx->ee, ctx->vv, counts_ptr(ctx), ctx->cap_vf, ctx->cap_ee,
                         ctx->cap_vv, s, mk, true, slots);
         mk.mark(4, 0);
+        // the first stretch colour runs in the closing kernel, on p = x_pred
+        StretchColor0 c0{};
+        if (plan.has_stretch && !plan.col_total.empty())
+            c0 = StretchColor0{plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[0], plan.col_nseg[0],
+                               plan.col_total[0], sc.inv_mass, plan.lambda, plan.alpha_t, sc.vflags};
         launch_close_iteration(ctx->x_pred, ctx->p, 3LL * n, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
                                ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs,
-                               adaptive ? it == plan.iters - 1 : it == first + group - 1, s, slots);
+                               adaptive ? it == plan.iters - 1 : it == first + group - 1, s, slots, &c0);
         if (plan.has_stretch) {
-            for (size_t c = 0; c < plan.col_total.size(); ++c)
+            for (size_t c = 1; c < plan.col_total.size(); ++c)
                 launch_stretch_segments(plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[c],
                                         plan.col_nseg[c], plan.col_total[c], sc.inv_mass, ctx->p, plan.lambda,
                                         plan.alpha_t, s);
@@ -486,11 +491,11 @@ int prepare_mesh(int32_t n_verts, const int32_t* tris, int32_t n_tris, const int
     }
     m.n_edges = n_edges;
     // free particles: vertices in no edge and no triangle
-    m.is_free.assign(n_verts, 1);
-    for (int32_t v : m.tris) m.is_free[v] = 0;
-    for (int32_t v : E) m.is_free[v] = 0;
+    m.vflags.assign(n_verts, VF_FREE);
+    for (int32_t v : m.tris) m.vflags[v] = 0;
+    for (int32_t v : E) m.vflags[v] = 0;
     for (int32_t v = 0; v < n_verts; ++v)
-        if (m.is_free[v]) m.free_list.push_back(v);
+        if (m.vflags[v] & VF_FREE) m.free_list.push_back(v);
     // edge length the grid is sized for: the longest edge not longer than 8x the
     // median over all binned primitives, free particles counting as length 0 (a
     // particle system with a few long wall edges gets cells sized by the pad)
@@ -547,6 +552,11 @@ int prepare_mesh(int32_t n_verts, const int32_t* tris, int32_t n_tris, const int
         }
     }
     m.has_stretch = rest_x != nullptr && n_edges > 0;
+    if (m.has_stretch)
+        for (int32_t e = m.color_begin[0]; e < m.color_begin[1]; ++e) {
+            m.vflags[m.edges_sorted[2 * e]] |= VF_COLOR0;
+            m.vflags[m.edges_sorted[2 * e + 1]] |= VF_COLOR0;
+        }
     return CCFR_OK;
 }
 
@@ -678,7 +688,7 @@ int ccfr_mesh_create(ccfr_ctx* ctx, int32_t n_verts, const int32_t* tris, int32_
     put(&m->edges_d, h.edges.data(), 2LL * h.n_edges);
     put(&m->inv_mass_d, inv_mass, h.n_verts);
     put(&m->free_list_d, h.free_list.data(), (long long)h.free_list.size());
-    put(&m->is_free_d, h.is_free.data(), h.n_verts);
+    put(&m->vflags_d, h.vflags.data(), h.n_verts);
     put(&m->edges_sorted_d, h.edges_sorted.data(), 2LL * h.n_edges);
     put(&m->rest_sorted_d, h.rest_sorted.data(), h.n_edges);
     put(&m->segs_d, segs.data(), (long long)segs.size());
@@ -700,7 +710,7 @@ void ccfr_mesh_destroy(ccfr_mesh* m) {
     if (!m) return;
     if (m->ctx && m->ctx->graph.owner == m) drop_graph(m->ctx);
     dev_free(m->tris_d); dev_free(m->edges_d); dev_free(m->inv_mass_d); dev_free(m->free_list_d);
-    dev_free(m->is_free_d); dev_free(m->edges_sorted_d); dev_free(m->rest_sorted_d); dev_free(m->lambda_d);
+    dev_free(m->vflags_d); dev_free(m->edges_sorted_d); dev_free(m->rest_sorted_d); dev_free(m->lambda_d);
     dev_free(m->segs_d);
     delete m;
 }

@@ -34,7 +34,7 @@ struct Pool {
     float* v = nullptr;
     float* w = nullptr;
     uint16_t* vmesh = nullptr;
-    uint8_t* is_free = nullptr;
+    uint8_t* vflags = nullptr;
     int32_t* tris = nullptr;
     int32_t* edges = nullptr;
     int32_t* edges_sorted = nullptr;
@@ -82,7 +82,7 @@ __global__ void k_compact(Pool src, Pool dst, const Move* mv, int n_moves, long 
         }
         dst.w[i] = src.w[j];
         dst.vmesh[i] = src.vmesh[j];
-        dst.is_free[i] = src.is_free[j];
+        dst.vflags[i] = src.vflags[j];
     }
     if (i < nt) {
         const Move& m = mv[find_move(mv, n_moves, i, 1)];
@@ -144,7 +144,7 @@ struct ccfr_batch {
 namespace {
 
 void free_pool(Pool& p) {
-    dev_free(p.x); dev_free(p.v); dev_free(p.w); dev_free(p.vmesh); dev_free(p.is_free);
+    dev_free(p.x); dev_free(p.v); dev_free(p.w); dev_free(p.vmesh); dev_free(p.vflags);
     dev_free(p.tris); dev_free(p.edges); dev_free(p.edges_sorted); dev_free(p.rest_sorted); dev_free(p.free_list);
 }
 
@@ -153,7 +153,7 @@ int alloc_pool(Pool& p, long long nv, long long nt, long long ne) {
     HIP_ALLOC(dev_alloc(&p.v, 3 * nv));
     HIP_ALLOC(dev_alloc(&p.w, nv));
     HIP_ALLOC(dev_alloc(&p.vmesh, nv));
-    HIP_ALLOC(dev_alloc(&p.is_free, nv));
+    HIP_ALLOC(dev_alloc(&p.vflags, nv));
     HIP_ALLOC(dev_alloc(&p.tris, 3 * nt));
     HIP_ALLOC(dev_alloc(&p.edges, 2 * ne));
     HIP_ALLOC(dev_alloc(&p.edges_sorted, 2 * ne));
@@ -236,7 +236,7 @@ int rebuild_plan(ccfr_batch* b, hipStream_t s) {
     sc.tris = P.tris;
     sc.edges = P.edges;
     sc.free_list = P.free_list;
-    sc.is_free = P.is_free;
+    sc.vflags = P.vflags;
     sc.narrow_fp32 = ctx->narrow_fp32 ? 1 : 0;
     sc.prm.table = b->table_d;
     sc.prm.vmesh = P.vmesh;
@@ -412,7 +412,7 @@ int ccfr_batch_add(ccfr_batch* b, int32_t n_verts, const int32_t* tris, int32_t 
     HIP_OK(hipMemcpyAsync(P.x + 3 * m.v0, x, sizeof(float) * 3 * h.n_verts, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(P.v + 3 * m.v0, v, sizeof(float) * 3 * h.n_verts, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(P.w + m.v0, inv_mass, sizeof(float) * h.n_verts, hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(P.is_free + m.v0, h.is_free.data(), h.n_verts, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(P.vflags + m.v0, h.vflags.data(), h.n_verts, hipMemcpyHostToDevice, s));
     if (h.n_tris)
         HIP_OK(hipMemcpyAsync(P.tris + 3 * m.t0, h.tris.data(), sizeof(int32_t) * 3 * h.n_tris, hipMemcpyHostToDevice, s));
     if (h.n_edges) {

@@ -41,7 +41,7 @@ struct MeshHost {
     std::vector<int32_t> edges_sorted;         // [E][2] by (colour, index)
     std::vector<float> rest_sorted;            // [E]
     std::vector<int32_t> free_list;
-    std::vector<uint8_t> is_free;
+    std::vector<uint8_t> vflags;               // per vertex: VF_FREE, VF_COLOR0
     float typ_len = 0.f;
     bool has_stretch = false;
 };
@@ -60,7 +60,7 @@ struct ccfr_mesh {
     int32_t* edges_d = nullptr;
     float* inv_mass_d = nullptr;
     int32_t* free_list_d = nullptr;
-    uint8_t* is_free_d = nullptr;
+    uint8_t* vflags_d = nullptr;
     // stretch constraints, edges sorted by colour; one segment per colour
     bool has_stretch = false;
     int32_t* edges_sorted_d = nullptr;

@@ -25,6 +25,11 @@ namespace ccfr {
 
 enum : int { KIND_VF = 1, KIND_EE = 2, KIND_VV = 3 };
 
+// Per-vertex flags: a free particle (in no edge and no triangle); an endpoint
+// of an edge of the first stretch colour (the pass starts in the iteration's
+// closing kernel, which then leaves such a vertex to its edge)
+enum : uint8_t { VF_FREE = 1, VF_COLOR0 = 2 };
+
 // status bits (sticky)
 enum : uint32_t {
     ST_VF = 1u, ST_EE = 2u, ST_VV = 4u, ST_HS = 8u, ST_LARGE = 16u, ST_CONTACTS = 32u,
@@ -217,7 +222,7 @@ struct Scene {
     const int32_t* tris;
     const int32_t* edges;
     const int32_t* free_list;   // [n_free] free particles (vertices in no edge / triangle)
-    const uint8_t* is_free;     // [n_verts]
+    const uint8_t* vflags;      // [n_verts] VF_FREE | VF_COLOR0
     int32_t narrow_fp32;        // 1: narrow-phase arithmetic in FP32 instead of FP64
     int32_t skin_iters;         // candidate builds: further iterations the lists must cover
     int32_t skin_wide;          // candidate builds: moving boxes padded by MeshParams::pad_wide
@@ -325,10 +330,22 @@ struct PairCaps {
     int64_t vf, ee, vv;
 };
 // slot_stride > 0: the region build went into per-vertex slots (offsets unused)
+// The first colour of the stretch pass, run by the iteration's closing kernel
+// (total == 0: none).
+struct StretchColor0 {
+    const int32_t* edges_sorted;
+    const float* rest_sorted;
+    const int2* segs;
+    int32_t nseg, total;
+    const float* inv_mass;
+    float* lambda_sorted;
+    float alpha_t;
+    const uint8_t* vflags;
+};
 void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounters* c, uint32_t* level_mask,
                             int n_meshes, int32_t n_verts, const int32_t* offsets, PairCaps caps,
                             int64_t cap_contacts, int64_t cap_hs, bool close_pairs, hipStream_t s,
-                            int32_t slot_stride = 0);
+                            int32_t slot_stride = 0, const StretchColor0* c0 = nullptr);
 // Before the candidate stage of an iteration in a substep whose builds adapt to
 // the motion: adds the last projection's largest move to the moves summed
 // since the last build; if the sum may exceed `skin` (the least widening of

@@ -701,7 +701,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
         const int mesh = (int)(me.flags >> 8);
         const MeshParams P = sc.prm.get(mesh);
         const bool q_static = (me.flags & 1u) != 0u;
-        const bool q_free = sc.is_free[v] != 0;
+        const bool q_free = (sc.vflags[v] & VF_FREE) != 0;
         uint32_t levels = g.level_mask[mesh];
         while (levels) {
             const int l = __ffs((int)levels) - 1;
