@@ -99,7 +99,8 @@ TUNED = {
 
 # Profile summaries with counter-derived HBM traffic, per (workload, kernel).
 TRAFFIC_PROFILES = {("c1", "pair_emission"): ("profiles/pair_emission_c1.md",
-                                              "paper_2607_26901_amd/csrc/k_broadphase.hip")}
+                                              "paper_2607_26901_amd/csrc/k_broadphase.hip"),
+                    ("c1", "contacts"): ("profiles/contacts_c1.md", "paper_2607_26901_amd/csrc/k_regions.hip")}
 
 
 def measured_traffic(workload, kernel, knobs):

@@ -97,6 +97,9 @@ def main(argv=None) -> int:
     ap.add_argument("--copy-write")
     ap.add_argument("--copy-mib", type=int, default=512)
     ap.add_argument("--kernel", default="k_pairs")
+    ap.add_argument("--stage", default="pair_emission",
+                    help="bench.py's name of the kernel's stage; the bench figures are recorded only when the "
+                         "bench's roofline is for this stage")
     ap.add_argument("--source", required=True)
     ap.add_argument("--bench", help="bench.py JSON line of the same workload")
     ap.add_argument("--command", action="append", default=[], help="a command that produced the inputs")
@@ -119,10 +122,11 @@ def main(argv=None) -> int:
         with open(a.bench) as f:
             b = json.loads(f.readline())
         rl = b.get("roofline", {})
-        facts["bench_avg_launch_us"] = f"{rl.get('avg_launch_us', float('nan')):.2f}"
         if "tuning" in b:
             facts["knobs"] = knobs_key(b["tuning"])
-        facts["algorithmic_bytes_per_launch"] = f"{rl.get('algorithmic_bytes', float('nan')):.0f}"
+        if rl.get("kernel") == a.stage:
+            facts["bench_avg_launch_us"] = f"{rl.get('avg_launch_us', float('nan')):.2f}"
+            facts["algorithmic_bytes_per_launch"] = f"{rl.get('algorithmic_bytes', float('nan')):.0f}"
     if a.fetch and a.write and a.copy_fetch and a.copy_write:
         fs, ws = copy_scale(a.copy_fetch, a.copy_mib), copy_scale(a.copy_write, a.copy_mib)
         fd, wd = counter_per_dispatch(a.fetch), counter_per_dispatch(a.write)
