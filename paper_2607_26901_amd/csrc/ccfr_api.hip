@@ -310,12 +310,14 @@ int32_t step_slot_stride(const ccfr_ctx* ctx, int n_verts) {
 void enqueue_regions(ccfr_ctx* ctx, const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
                      const int32_t* counts, long long cap_vf, long long cap_ee, long long cap_vv, hipStream_t s,
                      const Marks& mk, bool in_step, int32_t slot_stride = 0) {
+    const bool slots = in_step && slot_stride > 0;
     mk.mark(2, 0);
     launch_contacts(sc, vf, ee, vv, counts, cap_vf, cap_ee, cap_vv, ctx->contacts, ctx->cap_contacts, ctx->vcount,
-                    ctx->counters_d, s, ctx->hs, in_step ? slot_stride : 0);
+                    ctx->counters_d, s, slots);
     mk.mark(2, 1);
     mk.mark(3, 0);
-    if (in_step && slot_stride > 0) {
+    if (slots) {
+        launch_fill_slots(sc, ctx->contacts, ctx->cap_contacts, ctx->vcount, ctx->hs, slot_stride, ctx->counters_d, s);
         mk.mark(3, 1);
         return;
     }

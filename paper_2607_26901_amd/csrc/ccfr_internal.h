@@ -280,13 +280,16 @@ void launch_grid_scatter(const Scene& sc, GridWs& g, DevCounters* c, hipStream_t
 void launch_pairs(const Scene& sc, const GridWs& g, PairLists pl, DevCounters* c, int split, hipStream_t s);
 void launch_finalize_pairs(const GridWs& g, PairLists pl, DevCounters* c, hipStream_t s);
 
-// slot_stride > 0: the half-spaces go straight into per-vertex slots,
-// slot_hs[v * slot_stride + k] for the k-th one vertex v receives (vcount[v]
-// counts them), instead of a contact list for launch_fill
+// The contact list of the candidate pairs; vcount counts each vertex's
+// half-spaces for the CSR unless `for_slots` (launch_fill_slots counts them)
 void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
                      const int32_t* counts, int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
                      Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s,
-                     ccfr_halfspace* slot_hs = nullptr, int32_t slot_stride = 0);
+                     bool for_slots = false);
+// The contacts' half-spaces into per-vertex slots: slot_hs[v * slot_stride + k]
+// for the k-th one vertex v receives (vcount[v] counts them)
+void launch_fill_slots(const Scene& sc, const Contact* contacts, int64_t cap_contacts, int32_t* vcount,
+                       ccfr_halfspace* slot_hs, int32_t slot_stride, DevCounters* c, hipStream_t s);
 // finalize: close the region build (overflow bits, totals) in a launch of its own
 void launch_fill(const Scene& sc, const Contact* contacts, int64_t cap_contacts, const int32_t* offsets,
                  int32_t* vcount, ccfr_halfspace* hs, int64_t cap_hs, DevCounters* c, bool finalize,

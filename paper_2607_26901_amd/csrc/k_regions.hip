@@ -412,18 +412,22 @@ int grid_for(long long n) {
 void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
                      const int32_t* counts, int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
                      Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s,
-                     ccfr_halfspace* slot_hs, int32_t slot_stride) {
+                     bool for_slots) {
     const int blocks = grid_for(cap_vf + cap_ee + cap_vv);
-    int32_t* per_vertex = slot_stride > 0 ? nullptr : vcount;     // slots: counted by the fill
+    int32_t* per_vertex = for_slots ? nullptr : vcount;     // slots: counted by the fill
     if (sc.narrow_fp32)
         hipLaunchKernelGGL(k_contacts<float>, dim3(blocks), dim3(kBlock), 0, s, sc, vf, ee, vv, counts, cap_vf,
                            cap_ee, cap_vv, contacts, cap_contacts, per_vertex, c);
     else
         hipLaunchKernelGGL(k_contacts<double>, dim3(blocks), dim3(kBlock), 0, s, sc, vf, ee, vv, counts, cap_vf,
                            cap_ee, cap_vv, contacts, cap_contacts, per_vertex, c);
-    if (slot_stride > 0)
-        hipLaunchKernelGGL(k_fill_slots, dim3(grid_for(cap_contacts / 16)), dim3(kBlock), 0, s, sc, contacts,
-                           cap_contacts, vcount, slot_hs, slot_stride, c);
+}
+
+void launch_fill_slots(const Scene& sc, const Contact* contacts, int64_t cap_contacts, int32_t* vcount,
+                       ccfr_halfspace* slot_hs, int32_t slot_stride, DevCounters* c, hipStream_t s) {
+    // grid-stride over the contacts: a sixteenth of the capacity's blocks
+    hipLaunchKernelGGL(k_fill_slots, dim3(grid_for(cap_contacts / 16)), dim3(kBlock), 0, s, sc, contacts,
+                       cap_contacts, vcount, slot_hs, slot_stride, c);
 }
 
 void launch_fill(const Scene& sc, const Contact* contacts, int64_t cap_contacts, const int32_t* offsets,
