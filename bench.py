@@ -29,6 +29,8 @@ import time
 
 import numpy as np
 
+from paper_2607_26901_amd.scenes import BENCH_KNOBS as S_BENCH_KNOBS
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -89,12 +91,7 @@ def kernel_bytes(kernel, N, T, E, F, P, C, H):
 
 # Speed knobs the autotuner chose per workload (bench.py --tune, on four steps
 # from the middle of the run); the default run times these.
-TUNED = {
-    "c0": dict(cell_scale=0.7, pair_split=9, pair_reuse=4, pair_skin=0),
-    "c1": dict(cell_scale=0.7, pair_split=1, pair_reuse=3, pair_skin=0),
-    "c2": dict(cell_scale=0.85, pair_split=1, pair_reuse=4, pair_skin=0),
-    "c3": dict(cell_scale=1.2, pair_split=3, pair_reuse=1, pair_skin=0),
-}
+TUNED = S_BENCH_KNOBS
 
 
 # Profile summaries with counter-derived HBM traffic, per (workload, kernel).

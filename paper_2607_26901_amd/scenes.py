@@ -244,6 +244,18 @@ def drape(n=32, side=1.0, sphere_level=3, sphere_radius=0.3, height=0.1, jitter=
                     meta=dict(cloth_n=n, n_cloth=n * n))
 
 
+# Speed knobs (cell scale, lanes per query, iterations per candidate build,
+# adaptive skin) that the autotuner chose for each workload on four steps from
+# the middle of its run; the benchmark times these, and the full-size GPU
+# tests run the workloads with them.
+BENCH_KNOBS = {
+    "c0": dict(cell_scale=0.7, pair_split=9, pair_reuse=4, pair_skin=0),
+    "c1": dict(cell_scale=0.7, pair_split=1, pair_reuse=3, pair_skin=0),
+    "c2": dict(cell_scale=0.85, pair_split=1, pair_reuse=4, pair_skin=0),
+    "c3": dict(cell_scale=1.2, pair_split=3, pair_reuse=1, pair_skin=0),
+}
+
+
 def c0() -> Scene:
     """32x32 cloth (1 m) 0.1 m above a static 642-vertex icosphere of radius 0.3 m."""
     return drape(name="c0")

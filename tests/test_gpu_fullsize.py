@@ -103,9 +103,12 @@ def check_sampled(oracle, sc, x32, got, off_g, hs_g, y, yg, n_sample=48, seed=0)
     return len(verts), n_cmp, len(with_regions)
 
 
-def sampled_parity(ctx, ccfr, oracle, torch, sc, x32, n_sample=48, seed=0):
-    """The three calls on the GPU at state x32, then check_sampled."""
+def sampled_parity(ctx, ccfr, oracle, torch, sc, x32, n_sample=48, seed=0, knobs=None):
+    """The three calls on the GPU at state x32 (with the workload's benchmark
+    knobs when given), then check_sampled."""
     x32 = np.ascontiguousarray(x32, np.float32)
+    if knobs:
+        ctx.set_tuning(**knobs)
     mesh = ccfr.mesh_from_scene(ctx, sc.with_state(x=x32))
     x_t = torch.from_numpy(x32).cuda()
     prm = ccfr.make_params(sc.params)
@@ -126,6 +129,7 @@ def sampled_parity(ctx, ccfr, oracle, torch, sc, x32, n_sample=48, seed=0):
     got = ccfr.read_candidates(c)
     off_g, hs_g = ccfr.read_regions(regions)
     ctx.sync_status(reset=True)
+    ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1, pair_skin=0)
     rng = np.random.default_rng(seed + 1000)
     r32 = float(np.float32(sc.params.r))
     y = (rng.normal(0.0, 1.0, (sc.n_verts, 3)) * r32).astype(np.float32)
@@ -140,15 +144,14 @@ def sampled_parity(ctx, ccfr, oracle, torch, sc, x32, n_sample=48, seed=0):
     return check_sampled(oracle, sc, x32, got, off_g, hs_g, y, yg, n_sample, seed)
 
 
-def run_steps(ctx, ccfr, torch, sc, steps, tuned=True):
-    """`steps` graph-replayed substeps, as the benchmark runs them."""
-    from paper_2607_26901_amd import autotune
+def run_steps(ctx, ccfr, torch, sc, steps, knobs):
+    """`steps` graph-replayed substeps with the benchmark's knobs for the
+    workload, as the benchmark runs them."""
     mesh = ccfr.mesh_from_scene(ctx, sc)
     x = torch.from_numpy(sc.x.copy()).cuda()
     v = torch.from_numpy(sc.v.copy()).cuda()
     sp = ccfr.make_step_params(sc.step, sc.params)
-    if tuned:
-        autotune.tune_mesh(ctx, mesh, x, v, sp, steps=1, candidates=(0.7, 1.0), splits=(1,))
+    ctx.set_tuning(**knobs)
     for _ in range(4):
         x0, v0 = x.clone(), v.clone()
         for _ in range(steps):
@@ -171,7 +174,7 @@ def test_c1_folded_state(env):
     ctx, ccfr, oracle, torch = env
     sc = S.c1()
     st = S.folded_cloth_state(sc, seed=5)
-    n, n_cmp, n_reg = sampled_parity(ctx, ccfr, oracle, torch, sc, st.x, seed=1)
+    n, n_cmp, n_reg = sampled_parity(ctx, ccfr, oracle, torch, sc, st.x, seed=1, knobs=S.BENCH_KNOBS["c1"])
     assert n_reg > 1000 and n_cmp > 50
 
 
@@ -181,13 +184,13 @@ def test_c1_after_steps(env):
     three calls at that state."""
     ctx, ccfr, oracle, torch = env
     sc = S.c1()
-    x, v = run_steps(ctx, ccfr, torch, sc, 40)
+    x, v = run_steps(ctx, ccfr, torch, sc, 40, S.BENCH_KNOBS["c1"])
     xg = x.astype(np.float64)
     assert oracle.count_intersections(xg, sc.tris, sc.edges) == 0
     xi = float(np.float32(sc.params.xi))
     _, below = oracle.min_separation(xg, sc.inv_mass, sc.tris, sc.edges, 4 * xi, xi * (1 - 1e-3))
     assert below.sum() == 0
-    n, n_cmp, n_reg = sampled_parity(ctx, ccfr, oracle, torch, sc, x, seed=2)
+    n, n_cmp, n_reg = sampled_parity(ctx, ccfr, oracle, torch, sc, x, seed=2, knobs=S.BENCH_KNOBS["c1"])
     assert n_reg > 100 and n_cmp > 10
 
 
@@ -196,13 +199,13 @@ def test_c2_strands(env):
     steps; segment separation >= xi after them."""
     ctx, ccfr, oracle, torch = env
     sc = S.c2()
-    sampled_parity(ctx, ccfr, oracle, torch, sc, sc.x, n_sample=32, seed=3)
-    x, v = run_steps(ctx, ccfr, torch, sc, 10)
+    sampled_parity(ctx, ccfr, oracle, torch, sc, sc.x, n_sample=32, seed=3, knobs=S.BENCH_KNOBS["c2"])
+    x, v = run_steps(ctx, ccfr, torch, sc, 10, S.BENCH_KNOBS["c2"])
     xi = float(np.float32(sc.params.xi))
     _, below = oracle.min_separation(x.astype(np.float64), sc.inv_mass, sc.tris, sc.edges, 4 * xi,
                                      xi * (1 - 1e-3))
     assert below.sum() == 0
-    sampled_parity(ctx, ccfr, oracle, torch, sc, x, n_sample=32, seed=4)
+    sampled_parity(ctx, ccfr, oracle, torch, sc, x, n_sample=32, seed=4, knobs=S.BENCH_KNOBS["c2"])
 
 
 def test_c3_particles(env):
@@ -211,8 +214,8 @@ def test_c3_particles(env):
     from scipy.spatial import cKDTree
     ctx, ccfr, oracle, torch = env
     sc = S.c3()
-    sampled_parity(ctx, ccfr, oracle, torch, sc, sc.x, n_sample=32, seed=5)
-    x, v = run_steps(ctx, ccfr, torch, sc, 6)
+    sampled_parity(ctx, ccfr, oracle, torch, sc, sc.x, n_sample=32, seed=5, knobs=S.BENCH_KNOBS["c3"])
+    x, v = run_steps(ctx, ccfr, torch, sc, 6, S.BENCH_KNOBS["c3"])
     dyn = sc.inv_mass > 0
     xi = float(np.float32(sc.params.xi))
     pairs = cKDTree(x[dyn].astype(np.float64)).query_pairs(xi * (1 - 1e-3))
@@ -221,4 +224,4 @@ def test_c3_particles(env):
     hi = sc.x[~dyn].max(0).astype(np.float64)
     xd = x[dyn].astype(np.float64)
     assert np.all(xd >= lo + xi * (1 - 1e-3)) and np.all(xd <= hi - xi * (1 - 1e-3))
-    sampled_parity(ctx, ccfr, oracle, torch, sc, x, n_sample=32, seed=6)
+    sampled_parity(ctx, ccfr, oracle, torch, sc, x, n_sample=32, seed=6, knobs=S.BENCH_KNOBS["c3"])
