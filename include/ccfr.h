@@ -224,9 +224,12 @@ int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, 
  * recorded graph) and records HIP events around its stages on its stream:
  *   0 grid build (counter reset, binning, bucket scan, scatter)
  *   1 pair emission (the broad-phase query kernel alone)
- *   2 contacts (narrow phase: closest points, per-vertex counts)
- *   3 region fill (offset scan and half-space scatter)
- *   4 stretch pass (prediction copy and the colour passes)
+ *   2 contacts (narrow phase: closest points, the contact list; per-vertex
+ *     counts for CSR regions)
+ *   3 region fill (CSR regions: offset scan and half-space scatter; inside a
+ *     substep with per-vertex slots: the slot fill)
+ *   4 stretch pass (the iteration's closing kernel, which also copies the
+ *     prediction and runs the first colour, then the other colours)
  *   5 projection
  * Disabling profiling returns to the recorded graph. */
 int ccfr_profile_enable(ccfr_ctx* ctx, int enable);
