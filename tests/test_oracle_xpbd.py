@@ -58,6 +58,35 @@ def test_stiff_distance_constraint(orc):
     assert np.allclose(sim.x.mean(0), x.mean(0), atol=1e-15)
 
 
+def test_stretch_step_conserves_linear_momentum(orc):
+    """Each distance-constraint update moves its two endpoints by w_i s d and
+    -w_j s d, impulses that cancel, and p restarts from the prediction every
+    iteration: with no contact, no gravity and no clamped move, a step keeps the
+    total momentum sum m_i v_i to rounding, whatever the masses and strains.  A
+    wrong endpoint, sign or mass weighting in the pass breaks it."""
+    rng = np.random.default_rng(11)
+    cloth = S.cloth_grid(8, 0.16, (0.0, 0.0, 1.0))            # 20 mm edges: no self-contact
+    n = len(cloth.x)
+    cloth.inv_mass = rng.uniform(0.5, 2.0, n)
+    cloth.v = rng.normal(0.0, 0.01, (n, 3))
+    rest = cloth.x * (1.0 - 2e-4) + rng.normal(0.0, 1e-6, cloth.x.shape)   # strained by ~4 um
+    sc = S.assemble("momentum", [cloth], S.Params(r=1e-4, xi=1e-4),
+                    S.StepParams(dt=1e-3, iters=5, alpha=1e-7, gravity=(0.0, 0.0, 0.0)), rest_x=rest)
+    sim = orc.Sim(sc)
+    m = 1.0 / sim.w
+    x0, v0 = sim.x.copy(), sim.v.copy()
+    mom0 = (m[:, None] * v0).sum(0)
+    sim.step()
+    mom1 = (m[:, None] * sim.v).sum(0)
+    scale = (m[:, None] * np.abs(v0)).sum(0).max()
+    assert np.allclose(mom1, mom0, rtol=0, atol=1e-9 * scale), (mom0, mom1)
+    # not vacuous: the pass moved the vertices away from the free prediction
+    # by far more than rounding, and no move reached the clamp r
+    free = x0 + float(np.float32(1e-3)) * v0
+    assert np.abs(sim.x - free).max() > 1e-7
+    assert np.linalg.norm(sim.x - x0, axis=1).max() < 5 * float(np.float32(1e-4))
+
+
 def _check_state(orc, sc, x):
     xi = float(np.float32(sc.params.xi))
     assert orc.count_intersections(x, sc.tris, sc.edges) == 0
