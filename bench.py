@@ -64,9 +64,9 @@ def workload(name):
     return sc, desc
 
 
-# Algorithmic bytes of one launch of each single kernel (per-unit figures in
-# the design doc): N vertices, E edges, T triangles, F free particles, P candidate
-# pairs, C contacts, H half-spaces of that launch.
+# Algorithmic bytes of one launch of each single kernel (inputs read once,
+# outputs written once): N vertices, E edges, T triangles, F free particles,
+# P candidate pairs, C contacts, H half-spaces of that launch.
 def kernel_bytes(kernel, N, T, E, F, P, C, H):
     if kernel == "pair_emission":
         # every grid entry read once (48 B: box, index, flags, vertices): the
@@ -223,7 +223,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path would shard "
-              f"by spatial slabs with a halo exchange, which this build does not implement)", file=sys.stderr)
+              f"by spatial slabs with a halo exchange, which the library does not implement)", file=sys.stderr)
         return 2
 
     import torch

@@ -78,7 +78,7 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: run paper_2607_26901_amd/build.py (or __graft_entry__.build())")
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2607_26901_amd/build.py")
     lib = C.CDLL(LIB_PATH)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     lib.ccfr_status_string.restype = C.c_char_p

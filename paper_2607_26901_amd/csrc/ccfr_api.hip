@@ -250,7 +250,7 @@ Scene make_scene(const ccfr_mesh* m, const float* x, const ccfr_params* p, int s
     return sc;
 }
 
-// The table is sized for this build's entries (not the allocation), so the
+// The table is sized for the entries of the grid build at hand (not the allocation), so the
 // scan and the bucket range follow the meshes actually present.
 GridWs grid_ws(ccfr_ctx* ctx, const Scene& sc, int n_meshes) {
     GridWs g{};
