@@ -294,37 +294,41 @@ __global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g, con
 // owns a slice of kLaneCap pairs of the block's array lane_pairs[slot][thread]
 // and counts its pairs in a register, so an append is one LDS store and needs
 // no exchange with other lanes; a lane appends to the list of its query's kind
-// (vertex query: vertex-face, edge query: edge-edge).  Before a round of
+// (vertex query: vertex-face, edge query: edge-edge).  A slice holds only the
+// partner of each pair, the other primitive being the lane's own query, so
+// that the block's LDS leaves room for every block of a launch at once.  Before a round of
 // kRound entries, a wavefront whose lanes might overflow their slices writes
 // them out (one atomic per list).  Particle pairs, rare, go through one shared
 // buffer per wavefront (ballot + popcount), written out when full.
 constexpr int kWaves = kBlock / 64;
 constexpr int kRound = 4;      // entries read per round of a bucket walk
-constexpr int kLaneCap = 16;   // pairs per lane slice
+constexpr int kLaneCap = 32;   // pairs per lane slice
 constexpr int kStage = 192;    // particle pairs per wavefront buffer
 
 #define LDS_PTR __attribute__((address_space(3)))
 
 struct LaneBuf {
-    LDS_PTR uint64_t* slot0;   // &lane_pairs[0][thread]; slot s at slot0[s * kBlock], pair (a, b) as a | b << 32
+    LDS_PTR int32_t* slot0;    // &lane_pairs[0][thread]; slot s at slot0[s * kBlock]: a partner
     int fill;
     bool vert;                 // vertex query (vertex-face list) or edge query (edge-edge list)
+    int self;                  // the query: vertex (pairs (self, triangle)) or edge (pairs of min, max)
 };
 
-__device__ __forceinline__ void lane_put(LaneBuf& lb, int a, int b, bool pred) {
+__device__ __forceinline__ void lane_put(LaneBuf& lb, int partner, bool pred) {
     if (pred) {
-        lb.slot0[lb.fill * kBlock] = (uint64_t)(uint32_t)a | ((uint64_t)(uint32_t)b << 32);
+        lb.slot0[lb.fill * kBlock] = partner;
         ++lb.fill;
     }
 }
 
-// Exclusive prefix (over the lanes below this one) and total of `n` (0..31)
-// among the active lanes for which `mine` holds; lanes outside take no part.
+// Exclusive prefix (over the lanes below this one) and total of `n`
+// (0..kLaneCap) among the active lanes for which `mine` holds; lanes outside
+// take no part.
 __device__ __forceinline__ void wave_prefix(int n, bool mine, int& pre, int& tot) {
     const unsigned long long below = (1ull << __lane_id()) - 1ull;
     pre = tot = 0;
 #pragma unroll
-    for (int bit = 0; bit < 5; ++bit) {
+    for (int bit = 0; (1 << bit) <= kLaneCap; ++bit) {
         const unsigned long long m = __ballot(mine && ((n >> bit) & 1));
         pre += __popcll(m & below) << bit;
         tot += __popcll(m) << bit;
@@ -337,9 +341,9 @@ __device__ __forceinline__ void lane_write(const LaneBuf& lb, const PairLists& p
     for (int s = 0; s < lb.fill; ++s) {
         const long long idx = at + s;
         if (idx < cap) {
-            const uint64_t pr = lb.slot0[s * kBlock];
-            list[2 * idx + 0] = (int32_t)(uint32_t)pr;
-            list[2 * idx + 1] = (int32_t)(uint32_t)(pr >> 32);
+            const int pr = lb.slot0[s * kBlock];
+            list[2 * idx + 0] = lb.vert ? lb.self : min(lb.self, pr);
+            list[2 * idx + 1] = lb.vert ? pr : max(lb.self, pr);
         }
     }
 }
@@ -534,7 +538,7 @@ __device__ __forceinline__ void scan_vf(Src src, int i0, int i1, const GridEntry
         for (int u = 0; u < kRound; ++u) {
             const bool hit = (i + u < i1) & entry_ok(e[u], mesh, l, q_static) & overlap(me.lo, me.hi, e[u].lo, e[u].hi) &
                              (e[u].v[0] != v) & (e[u].v[1] != v) & (e[u].v[2] != v);
-            lane_put(lb, v, e[u].idx, hit);
+            lane_put(lb, e[u].idx, hit);
         }
     }
 }
@@ -567,7 +571,7 @@ __device__ __forceinline__ void scan_ee(Src src, int i0, int i1, int ord, const 
             const bool hit = (i + u < i1) & ((ord > 0) | (e[u].idx > eq)) & entry_ok(e[u], mesh, l, q_static) &
                              overlap(me.lo, me.hi, e[u].lo, e[u].hi) & (e[u].v[0] != a) & (e[u].v[0] != bb) &
                              (e[u].v[1] != a) & (e[u].v[1] != bb);
-            lane_put(lb, min(eq, e[u].idx), max(eq, e[u].idx), hit);
+            lane_put(lb, e[u].idx, hit);
         }
     }
 }
@@ -679,11 +683,11 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
                                                   long long vwaves, long long waves) {
     if (sc.build_gated && !c->rebuild) return;
     __shared__ Stage stages[kWaves];
-    __shared__ uint64_t lane_pairs[kLaneCap][kBlock];
+    __shared__ int32_t lane_pairs[kLaneCap][kBlock];
     const StagePtr st = (StagePtr)&stages[threadIdx.x / 64];
     if (__lane_id() == 0) st->fill = 0;
     wave_fence();
-    LaneBuf lb{(LDS_PTR uint64_t*)&lane_pairs[0][threadIdx.x], 0, true};
+    LaneBuf lb{(LDS_PTR int32_t*)&lane_pairs[0][threadIdx.x], 0, true, 0};
     const long long w = (long long)xcd_block(blockIdx.x, gridDim.x) * kWaves + threadIdx.x / 64;
     const long long vw = w * vwaves / waves;                 // vertex wavefronts before w
     const bool vwave = (w + 1) * vwaves / waves > vw;
@@ -698,6 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
         // ---- vertex query: vertex-face pairs, and particle pairs for free particles
         const GridEntry me = g.entries[v0 + q];
         const int v = me.idx;
+        lb.self = v;
         const int mesh = (int)(me.flags >> 8);
         const MeshParams P = sc.prm.get(mesh);
         const bool q_static = (me.flags & 1u) != 0u;
@@ -718,6 +723,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
         lb.vert = false;
         const GridEntry me = g.entries[e0 + q];
         const int eq = me.idx;
+        lb.self = eq;
         const int a = me.v[0], bb = me.v[1];
         const int mesh = (int)(me.flags >> 8);
         const int lq = (int)((me.flags >> 1) & 31u);
