@@ -293,31 +293,39 @@ __global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g, con
 // Found pairs are staged in LDS.  Vertex-face and edge-edge pairs: every lane
 // owns a slice of kLaneCap pairs of the block's array lane_pairs[slot][thread]
 // and counts its pairs in a register, so an append is one LDS store and needs
-// no exchange with other lanes; a lane appends to the list of its query's kind
-// (vertex query: vertex-face, edge query: edge-edge).  A slice holds only the
-// partner of each pair, the other primitive being the lane's own query, so
-// that the block's LDS leaves room for every block of a launch at once.  Before a round of
-// kRound entries, a wavefront whose lanes might overflow their slices writes
-// them out (one atomic per list).  Particle pairs, rare, go through one shared
-// buffer per wavefront (ballot + popcount), written out when full.
+// no exchange with other lanes.  A slice holds only the partner of each pair,
+// the other primitive being the lane's own query, so that the block's LDS
+// leaves room for every block of a launch at once: a vertex query's partners
+// are triangles (vertex-face list) and, for a free particle, particles (the
+// particle list; tagged by the top bit), an edge query's are edges.  Before a
+// round of kRound entries, a wavefront whose lanes might overflow their slices
+// writes them out (one atomic per list).
 constexpr int kWaves = kBlock / 64;
 constexpr int kRound = 4;      // entries read per round of a bucket walk
 constexpr int kLaneCap = 32;   // pairs per lane slice
-constexpr int kStage = 192;    // particle pairs per wavefront buffer
 
 #define LDS_PTR __attribute__((address_space(3)))
 
 struct LaneBuf {
     LDS_PTR int32_t* slot0;    // &lane_pairs[0][thread]; slot s at slot0[s * kBlock]: a partner
-    int fill;
-    bool vert;                 // vertex query (vertex-face list) or edge query (edge-edge list)
-    int self;                  // the query: vertex (pairs (self, triangle)) or edge (pairs of min, max)
+    int fill;                  // entries in the slice
+    int n_vv;                  // of them particle partners (top bit set)
+    bool vert;                 // vertex query: pairs (self, triangle); edge query: edge pairs (min, max)
+    int self;                  // the query: vertex or edge
 };
 
 __device__ __forceinline__ void lane_put(LaneBuf& lb, int partner, bool pred) {
     if (pred) {
         lb.slot0[lb.fill * kBlock] = partner;
         ++lb.fill;
+    }
+}
+
+__device__ __forceinline__ void lane_put_vv(LaneBuf& lb, int partner, bool pred) {
+    if (pred) {
+        lb.slot0[lb.fill * kBlock] = partner | (int)0x80000000;
+        ++lb.fill;
+        ++lb.n_vv;
     }
 }
 
@@ -335,102 +343,62 @@ __device__ __forceinline__ void wave_prefix(int n, bool mine, int& pre, int& tot
     }
 }
 
-__device__ __forceinline__ void lane_write(const LaneBuf& lb, const PairLists& pl, long long at) {
+// Writes a lane's slice: its first-list pairs (vertex-face or edge-edge) from
+// position `at`, its particle pairs from `at_vv`.
+__device__ __forceinline__ void lane_write(const LaneBuf& lb, const PairLists& pl, long long at, long long at_vv) {
     int32_t* list = lb.vert ? pl.vf : pl.ee;
     const int64_t cap = lb.vert ? pl.cap_vf : pl.cap_ee;
     for (int s = 0; s < lb.fill; ++s) {
-        const long long idx = at + s;
-        if (idx < cap) {
-            const int pr = lb.slot0[s * kBlock];
-            list[2 * idx + 0] = lb.vert ? lb.self : min(lb.self, pr);
-            list[2 * idx + 1] = lb.vert ? pr : max(lb.self, pr);
+        const int pr = lb.slot0[s * kBlock];
+        if (pr < 0) {
+            const int q = pr & 0x7fffffff;
+            if (at_vv < pl.cap_vv) {
+                pl.vv[2 * at_vv + 0] = min(lb.self, q);
+                pl.vv[2 * at_vv + 1] = max(lb.self, q);
+            }
+            ++at_vv;
+        } else {
+            if (at < cap) {
+                list[2 * at + 0] = lb.vert ? lb.self : min(lb.self, pr);
+                list[2 * at + 1] = lb.vert ? pr : max(lb.self, pr);
+            }
+            ++at;
         }
     }
 }
 
+// The slice counts' prefix and total per list among the active lanes.
+struct KindPrefix {
+    int pv, tv, pe, te, pp, tp;
+    __device__ __forceinline__ explicit KindPrefix(const LaneBuf& lb) {
+        const int main = lb.fill - lb.n_vv;
+        wave_prefix(main, lb.vert, pv, tv);
+        wave_prefix(main, !lb.vert, pe, te);
+        wave_prefix(lb.n_vv, true, pp, tp);
+    }
+};
+
 // The active lanes of a wavefront write their slices out.
 __device__ __forceinline__ void lane_flush(LaneBuf& lb, const PairLists& pl, DevCounters* c) {
-    int pv, tv, pe, te;
-    wave_prefix(lb.fill, lb.vert, pv, tv);
-    wave_prefix(lb.fill, !lb.vert, pe, te);
+    const KindPrefix kp(lb);
     const int lead = __ffsll((long long)__ballot(true)) - 1;
-    int bv = 0, be = 0;
+    int bv = 0, be = 0, bp = 0;
     if (__lane_id() == lead) {
-        if (tv) bv = atomicAdd(&c->n_vf, tv);
-        if (te) be = atomicAdd(&c->n_ee, te);
+        if (kp.tv) bv = atomicAdd(&c->n_vf, kp.tv);
+        if (kp.te) be = atomicAdd(&c->n_ee, kp.te);
+        if (kp.tp) bp = atomicAdd(&c->n_vv, kp.tp);
     }
     bv = __shfl(bv, lead);
     be = __shfl(be, lead);
-    lane_write(lb, pl, lb.vert ? (long long)bv + pv : (long long)be + pe);
+    bp = __shfl(bp, lead);
+    lane_write(lb, pl, lb.vert ? (long long)bv + kp.pv : (long long)be + kp.pe, (long long)bp + kp.pp);
     lb.fill = 0;
+    lb.n_vv = 0;
 }
 
 // Called by the active lanes before a round that may append up to kRound pairs each.
 __device__ __forceinline__ void lane_room(LaneBuf& lb, const PairLists& pl, DevCounters* c) {
     if (__ballot(lb.fill > kLaneCap - kRound) != 0ull) lane_flush(lb, pl, c);
-}
-
-struct Stage {
-    int a[kStage];
-    int b[kStage];
-    int fill;
-};
-
-// The particle stage lives in LDS; functions take it through an LDS-qualified
-// pointer so that every access is a ds_ instruction (a generic pointer would
-// become a flat access that waits for all outstanding global loads).  Lanes of
-// one wavefront exchange data through it; LDS executes a wavefront's accesses
-// in order, and the wavefront-scope fences keep the compiler from reordering
-// or caching them.
-typedef LDS_PTR Stage* StagePtr;
-
-__device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
-
-__device__ __forceinline__ void stage_flush(StagePtr st, int32_t* list, int32_t* counter, int64_t cap) {
-    wave_fence();
-    const int f = st->fill;
-    if (f == 0) return;
-    const unsigned long long act = __ballot(true);
-    const int lane = __lane_id();
-    const int lead = __ffsll((long long)act) - 1;
-    const int nact = __popcll(act);
-    const int rank = __popcll(act & ((1ull << lane) - 1ull));
-    int base = 0;
-    if (lane == lead) base = atomicAdd(counter, f);
-    base = __shfl(base, lead);
-    for (int i = rank; i < f; i += nact) {
-        const long long idx = (long long)base + i;
-        if (idx < cap) {
-            list[2 * idx + 0] = st->a[i];
-            list[2 * idx + 1] = st->b[i];
-        }
-    }
-    wave_fence();
-    if (lane == lead) st->fill = 0;
-    wave_fence();
-}
-
-// Every active lane of the wave must call it.
-__device__ __forceinline__ void stage_pair(StagePtr st, int32_t* list, int32_t* counter, int64_t cap, int a, int b,
-                                           bool pred) {
-    const unsigned long long mask = __ballot(pred);
-    if (mask == 0ull) return;
-    const int n = __popcll(mask);
-    wave_fence();
-    int f = st->fill;
-    if (f + n > kStage) {
-        stage_flush(st, list, counter, cap);
-        f = 0;
-    }
-    const int lane = __lane_id();
-    if (pred) {
-        const int slot = f + __popcll(mask & ((1ull << lane) - 1ull));
-        st->a[slot] = a;
-        st->b[slot] = b;
-    }
-    wave_fence();
-    if (lane == __ffsll((long long)__ballot(true)) - 1) st->fill = f + n;
-    wave_fence();
 }
 
 // Cells of the stencil [clo - 1, chi] that work item `part` of `split` walks:
@@ -547,11 +515,18 @@ __device__ __forceinline__ void scan_vf(Src src, int i0, int i1, const GridEntry
 // half shell with the cell's order `ord`).
 template <class Src>
 __device__ __forceinline__ void scan_vv(Src src, int i0, int i1, int ord, const GridEntry& me, int v, int mesh,
-                                        bool q_static, StagePtr st, const PairLists& pl, DevCounters* c) {
-    for (int i = i0; i < i1; ++i) {
-        const GridEntry e = src.get(i);
-        const bool hit = ((ord > 0) | (e.idx > v)) & entry_ok(e, mesh, 0, q_static) & overlap(me.lo, me.hi, e.lo, e.hi);
-        stage_pair(st, pl.vv, &c->n_vv, pl.cap_vv, min(v, e.idx), max(v, e.idx), hit);
+                                        bool q_static, LaneBuf& lb, const PairLists& pl, DevCounters* c) {
+    for (int i = i0; i < i1; i += kRound) {
+        lane_room(lb, pl, c);
+        GridEntry e[kRound];
+#pragma unroll
+        for (int u = 0; u < kRound; ++u) e[u] = src.get(min(i + u, i1 - 1));
+#pragma unroll
+        for (int u = 0; u < kRound; ++u) {
+            const bool hit = (i + u < i1) & ((ord > 0) | (e[u].idx > v)) & entry_ok(e[u], mesh, 0, q_static) &
+                             overlap(me.lo, me.hi, e[u].lo, e[u].hi);
+            lane_put_vv(lb, e[u].idx, hit);
+        }
     }
 }
 
@@ -603,14 +578,14 @@ __device__ void walk_vf_global(const GridWs& g, const GridEntry& me, int v, int 
 }
 
 __device__ void walk_vv_global(const GridWs& g, const GridEntry& me, int v, int mesh, int salt, bool q_static,
-                               const int clo[3], const int r0[3], const int r1[3], StagePtr st,
+                               const int clo[3], const int r0[3], const int r1[3], LaneBuf& lb,
                                const PairLists& pl, DevCounters* c) {
     const GlobalSrc src{g.entries};
     for (int cz = r0[2]; cz <= r1[2]; ++cz)
         for (int k = 0; k < 9; ++k) {
             int u0, u1, ord;
             cell_range(g, TB_PART, salt, k, cz, r0, r1, clo, true, u0, u1, ord);
-            scan_vv(src, u0, u1, ord, me, v, mesh, q_static, st, pl, c);
+            scan_vv(src, u0, u1, ord, me, v, mesh, q_static, lb, pl, c);
         }
 }
 
@@ -632,19 +607,17 @@ __device__ void walk_ee_global(const GridWs& g, const GridEntry& me, int eq, int
     }
 }
 
-// The block is done: what is left in the lane slices and the particle stages
-// goes out with one atomic per list for the whole block.  Every thread of the
-// block calls it.
-__device__ void block_flush(LaneBuf& lb, LDS_PTR Stage* stages, const PairLists& pl, DevCounters* c) {
+// The block is done: what is left in the lane slices goes out with one atomic
+// per list for the whole block.  Every thread of the block calls it.
+__device__ void block_flush(LaneBuf& lb, const PairLists& pl, DevCounters* c) {
     __shared__ int wsum[kWaves][3];
     __shared__ int base[kWaves][3];
     const int wave = threadIdx.x / 64;
-    int pv, tv, pe, te;
-    wave_prefix(lb.fill, lb.vert, pv, tv);
-    wave_prefix(lb.fill, !lb.vert, pe, te);
+    const KindPrefix kp(lb);
     if (__lane_id() == 0) {
-        wsum[wave][0] = tv;
-        wsum[wave][1] = te;
+        wsum[wave][0] = kp.tv;
+        wsum[wave][1] = kp.te;
+        wsum[wave][2] = kp.tp;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -653,23 +626,15 @@ __device__ void block_flush(LaneBuf& lb, LDS_PTR Stage* stages, const PairLists&
             int acc = 0;
             for (int w = 0; w < kWaves; ++w) {
                 base[w][k] = acc;
-                acc += k < 2 ? wsum[w][k] : stages[w].fill;
+                acc += wsum[w][k];
             }
             const int b0 = acc ? atomicAdd(counters[k], acc) : 0;
             for (int w = 0; w < kWaves; ++w) base[w][k] += b0;
         }
     }
     __syncthreads();
-    lane_write(lb, pl, lb.vert ? (long long)base[wave][0] + pv : (long long)base[wave][1] + pe);
-    const StagePtr st = stages + wave;
-    const int f = st->fill;
-    for (int i = __lane_id(); i < f; i += 64) {
-        const long long idx = (long long)base[wave][2] + i;
-        if (idx < pl.cap_vv) {
-            pl.vv[2 * idx + 0] = st->a[i];
-            pl.vv[2 * idx + 1] = st->b[i];
-        }
-    }
+    lane_write(lb, pl, lb.vert ? (long long)base[wave][0] + kp.pv : (long long)base[wave][1] + kp.pe,
+               (long long)base[wave][2] + kp.pp);
 }
 
 // Work item = (query, part of its stencil) with `split` lanes per query; every
@@ -682,12 +647,8 @@ __device__ void block_flush(LaneBuf& lb, LDS_PTR Stage* stages, const PairLists&
 __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists pl, DevCounters* c, int split,
                                                   long long vwaves, long long waves) {
     if (sc.build_gated && !c->rebuild) return;
-    __shared__ Stage stages[kWaves];
     __shared__ int32_t lane_pairs[kLaneCap][kBlock];
-    const StagePtr st = (StagePtr)&stages[threadIdx.x / 64];
-    if (__lane_id() == 0) st->fill = 0;
-    wave_fence();
-    LaneBuf lb{(LDS_PTR int32_t*)&lane_pairs[0][threadIdx.x], 0, true, 0};
+    LaneBuf lb{(LDS_PTR int32_t*)&lane_pairs[0][threadIdx.x], 0, 0, true, 0};
     const long long w = (long long)xcd_block(blockIdx.x, gridDim.x) * kWaves + threadIdx.x / 64;
     const long long vw = w * vwaves / waves;                 // vertex wavefronts before w
     const bool vwave = (w + 1) * vwaves / waves > vw;
@@ -716,7 +677,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
             stencil_cells(me, ldexpf(P.inv_h, -l), clo, chi);
             if (!part_range(split, part, clo, chi, r0, r1)) continue;
             walk_vf_global(g, me, v, mesh, l, salt, q_static, clo, r0, r1, lb, pl, c);
-            if (q_free && l == 0) walk_vv_global(g, me, v, mesh, salt, q_static, clo, r0, r1, st, pl, c);
+            if (q_free && l == 0) walk_vv_global(g, me, v, mesh, salt, q_static, clo, r0, r1, lb, pl, c);
         }
     } else if (!vwave && q < ne_q) {
         // ---- edge query: edge-edge pairs
@@ -740,7 +701,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
             walk_ee_global(g, me, eq, a, bb, mesh, lq, l, salt, q_static, clo, r0, r1, lb, pl, c);
         }
     }
-    block_flush(lb, (LDS_PTR Stage*)stages, pl, c);
+    block_flush(lb, pl, c);
 }
 
 __global__ void k_finalize_pairs(PairLists pl, DevCounters* c) {
