@@ -160,9 +160,11 @@ int ensure_step(ccfr_ctx* ctx, long long n_verts) {
         dev_free(ctx->x_pred);
         dev_free(ctx->x_start);
         dev_free(ctx->p);
+        dev_free(ctx->y_def);
         HIP_ALLOC(dev_alloc(&ctx->x_pred, 3 * n_verts));
         HIP_ALLOC(dev_alloc(&ctx->x_start, 3 * n_verts));
         HIP_ALLOC(dev_alloc(&ctx->p, 3 * n_verts));
+        HIP_ALLOC(dev_alloc(&ctx->y_def, 3 * n_verts));
         ctx->cap_step = n_verts;
         ctx->generation++;
     }
@@ -395,8 +397,10 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
         launch_close_iteration(ctx->x_pred, ctx->p, 3LL * n, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
                                ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs,
                                adaptive ? it == plan.iters - 1 : it == first + group - 1, s, slots, &c0);
+        // the last one (of two or more) runs in the projection, which reads its result
+        const bool fold = plan.has_stretch && plan.col_total.size() >= 2 && plan.last_edge && plan.lambda_alt;
         if (plan.has_stretch) {
-            for (size_t c = 1; c < plan.col_total.size(); ++c)
+            for (size_t c = 1; c + (fold ? 1 : 0) < plan.col_total.size(); ++c)
                 launch_stretch_segments(plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[c],
                                         plan.col_nseg[c], plan.col_total[c], sc.inv_mass, ctx->p, plan.lambda,
                                         plan.alpha_t, s);
@@ -420,6 +424,10 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
         pa.slot_counts = ctx->vcount;
         pa.slot_stride = slots;
         pa.prm = sc.prm;
+        if (fold)   // the multipliers of the folded colour alternate between two arrays
+            pa.sl = StretchLast{plan.last_edge, plan.edges_sorted, plan.rest_sorted,
+                                (it & 1) ? plan.lambda_alt : plan.lambda, (it & 1) ? plan.lambda : plan.lambda_alt,
+                                plan.alpha_t, ctx->y_def};
         mk.mark(5, 0);
         launch_project(pa, ctx->counters_d, false, s);
         mk.mark(5, 1);
@@ -578,6 +586,8 @@ StepPlan mesh_plan(ccfr_ctx* ctx, const ccfr_mesh* m, float* x, float* v, const 
     plan.edges_sorted = m->edges_sorted_d;
     plan.rest_sorted = m->rest_sorted_d;
     plan.lambda = m->lambda_d;
+    plan.lambda_alt = m->lambda_alt_d;
+    plan.last_edge = m->last_edge_d;
     plan.n_edges = m->n_edges;
     plan.segs = m->segs_d;
     const int nc = (int)m->color_begin.size() - 1;
@@ -652,7 +662,7 @@ void ccfr_destroy(ccfr_ctx* ctx) {
     dev_free(ctx->contacts); dev_free(ctx->vcount); dev_free(ctx->offsets); dev_free(ctx->slow_list);
     dev_free(ctx->hs);
     dev_free(ctx->sort_key); dev_free(ctx->sort_idx);
-    dev_free(ctx->x_pred); dev_free(ctx->x_start); dev_free(ctx->p);
+    dev_free(ctx->x_pred); dev_free(ctx->x_start); dev_free(ctx->p); dev_free(ctx->y_def);
     for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     delete ctx;
@@ -695,6 +705,17 @@ int ccfr_mesh_create(ccfr_ctx* ctx, int32_t n_verts, const int32_t* tris, int32_
     put(&m->rest_sorted_d, h.rest_sorted.data(), h.n_edges);
     put(&m->segs_d, segs.data(), (long long)segs.size());
     if (e == hipSuccess) e = dev_alloc(&m->lambda_d, std::max<long long>(h.n_edges, 1));
+    // the map of the last stretch colour, run inside the projection
+    const int nc = (int)h.color_begin.size() - 1;
+    if (e == hipSuccess && h.has_stretch && nc >= 2) {
+        e = dev_alloc(&m->lambda_alt_d, h.n_edges);
+        if (e == hipSuccess) e = dev_alloc(&m->last_edge_d, h.n_verts);
+        if (e == hipSuccess) {
+            launch_last_colour_map(m->edges_sorted_d, m->segs_d + (nc - 1), 1,
+                                   h.color_begin[nc] - h.color_begin[nc - 1], h.n_verts, m->last_edge_d, nullptr);
+            e = hipDeviceSynchronize();
+        }
+    }
     if (e != hipSuccess) {
         ccfr_mesh_destroy(m);
         return CCFR_ERR_NO_MEMORY;
@@ -713,7 +734,7 @@ void ccfr_mesh_destroy(ccfr_mesh* m) {
     if (m->ctx && m->ctx->graph.owner == m) drop_graph(m->ctx);
     dev_free(m->tris_d); dev_free(m->edges_d); dev_free(m->inv_mass_d); dev_free(m->free_list_d);
     dev_free(m->vflags_d); dev_free(m->edges_sorted_d); dev_free(m->rest_sorted_d); dev_free(m->lambda_d);
-    dev_free(m->segs_d);
+    dev_free(m->segs_d); dev_free(m->lambda_alt_d); dev_free(m->last_edge_d);
     delete m;
 }
 

@@ -67,6 +67,10 @@ struct ccfr_mesh {
     float* rest_sorted_d = nullptr;
     float* lambda_d = nullptr;
     int2* segs_d = nullptr;             // (first edge, 0) per colour
+    // two or more colours: the last one's multipliers alternate between
+    // lambda_d and lambda_alt_d; last_edge_d maps a vertex to its edge there
+    float* lambda_alt_d = nullptr;
+    int2* last_edge_d = nullptr;
     std::vector<int32_t> color_begin;   // n_colors + 1
     float typ_len = 0.f;                // edge length the grid cell is sized for
     std::vector<int32_t> edges_h;
@@ -133,6 +137,7 @@ struct ccfr_ctx {
     float* x_pred = nullptr;
     float* x_start = nullptr;
     float* p = nullptr;
+    float* y_def = nullptr;      // proposals the fast projection hands to the slow one
     long long cap_step = 0;
 
     StepGraph graph;
@@ -174,6 +179,11 @@ struct StepPlan {
     const int32_t* edges_sorted = nullptr;
     const float* rest_sorted = nullptr;
     float* lambda = nullptr;
+    // the last colour runs inside the projection when both are set (two or
+    // more colours): vertex -> its edge in that colour, and the second array
+    // its multipliers alternate with
+    const int2* last_edge = nullptr;
+    float* lambda_alt = nullptr;
     long long n_edges = 0;
     const int2* segs = nullptr;
     std::vector<int32_t> col_first, col_nseg, col_total;

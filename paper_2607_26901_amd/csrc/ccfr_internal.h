@@ -295,6 +295,24 @@ void launch_fill(const Scene& sc, const Contact* contacts, int64_t cap_contacts,
                  int32_t* vcount, ccfr_halfspace* hs, int64_t cap_hs, DevCounters* c, bool finalize,
                  hipStream_t s);
 
+// The last colour of the stretch pass, folded into the projection that reads
+// its result (last_edge == nullptr: none): last_edge[v] = (v's edge e in that
+// colour, with bit 31 set when v is its second endpoint; the other endpoint),
+// or (0, -1) for a vertex in no such edge.  The projection takes as v's
+// proposal the position the edge's update gives it, computed from p as the
+// colour's own launch would, and the edge's first endpoint writes the new
+// multiplier to lambda_out (both endpoints read lambda_in, so the two arrays
+// alternate between iterations).  The fast kernel hands the displacement of a
+// vertex it defers to the slow one in y_def (3 floats per vertex).
+struct StretchLast {
+    const int2* last_edge;
+    const int32_t* edges_sorted;
+    const float* rest_sorted;
+    const float* lambda_in;
+    float* lambda_out;
+    float alpha_t;
+    float* y_def;
+};
 struct ProjectArgs {
     int32_t n_verts;
     const int32_t* offsets;
@@ -316,6 +334,7 @@ struct ProjectArgs {
     int32_t* slot_counts;
     int32_t slot_stride;
     ParamSrc prm;
+    StretchLast sl;
 };
 // zero_counters: clear the slow-list counters first (the substep clears them
 // in launch_close_iteration instead)
@@ -359,6 +378,10 @@ void launch_decide_build(DevCounters* c, uint32_t* level_mask, int n_meshes, dou
 void launch_stretch_segments(const int32_t* edges_sorted, const float* rest_sorted, const int2* segs, int32_t nseg,
                              int32_t total, const float* inv_mass, float* p, float* lambda_sorted, float alpha_t,
                              hipStream_t s);
+// last_edge[v] for the colour class (edges as in a stretch colour: nseg
+// segments, total edges) as StretchLast reads it; n_verts entries.
+void launch_last_colour_map(const int32_t* edges_sorted, const int2* segs, int32_t nseg, int32_t total,
+                            int32_t n_verts, int2* last_edge, hipStream_t s);
 void launch_update_velocity(int n, const float* x, const float* x_start, float inv_dt, float* v,
                             hipStream_t s);
 

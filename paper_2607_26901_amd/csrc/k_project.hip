@@ -172,13 +172,69 @@ __device__ bool project_slow(const ccfr_halfspace* H, int K, const d3 yprop, con
 
 // ---- shared per-vertex plumbing ----
 
+// Vertex v's position after the folded last stretch colour: p, or, for an
+// endpoint of an edge of that colour, the endpoint's position after the edge's
+// XPBD distance update (Macklin et al. 2016), computed from p with the same
+// arithmetic as a colour launch.  p is not written during the projection, so
+// both endpoints compute the same step; the first one stores the multiplier
+// when write_lambda.
+__device__ __forceinline__ void folded_position(const ProjectArgs& a, int v, float pv[3], bool write_lambda) {
+    for (int k = 0; k < 3; ++k) pv[k] = a.p[3 * v + k];
+    const int2 m = a.sl.last_edge[v];
+    if (m.y < 0) return;
+    const bool second = m.x < 0;
+    const int e = m.x & 0x7fffffff;
+    const int i = second ? m.y : v, j = second ? v : m.y;
+    const float wi = a.inv_mass[i], wj = a.inv_mass[j];
+    const float W = wi + wj;
+    float pi[3], pj[3], d[3];
+    for (int k = 0; k < 3; ++k) {
+        pi[k] = a.p[3 * i + k];
+        pj[k] = a.p[3 * j + k];
+        d[k] = pi[k] - pj[k];
+    }
+    const float len = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const float lam = a.sl.lambda_in[e];
+    if (W == 0.0f || len == 0.0f) {
+        if (write_lambda && v == i) a.sl.lambda_out[e] = lam;
+        return;
+    }
+    const float C = len - a.sl.rest_sorted[e];
+    const float dl = (-C - a.sl.alpha_t * lam) / (W + a.sl.alpha_t);
+    const float s = dl / len;
+    if (v == i) {
+        for (int k = 0; k < 3; ++k) pv[k] = pi[k] + wi * s * d[k];
+        if (write_lambda) a.sl.lambda_out[e] = lam + dl;
+    } else {
+        for (int k = 0; k < 3; ++k) pv[k] = pj[k] - wj * s * d[k];
+    }
+}
+
 __device__ __forceinline__ d3 load_prop(const ProjectArgs& a, int v) {
     float yf[3];
     if (a.y_in) {
         yf[0] = a.y_in[3 * v]; yf[1] = a.y_in[3 * v + 1]; yf[2] = a.y_in[3 * v + 2];
     } else {
-        for (int k = 0; k < 3; ++k) yf[k] = a.p[3 * v + k] - a.x_anchor[3 * v + k];
+        if (a.sl.last_edge) {
+            // a deferred vertex: the fast kernel left its displacement
+            for (int k = 0; k < 3; ++k) yf[k] = a.sl.y_def[3 * v + k];
+        } else {
+            for (int k = 0; k < 3; ++k) yf[k] = a.p[3 * v + k] - a.x_anchor[3 * v + k];
+        }
     }
+    return mk(yf[0], yf[1], yf[2]);
+}
+
+// The first read of every vertex's proposal (zero for a pinned vertex); with
+// the folded colour it also stores the colour's multipliers, for pinned
+// endpoints too.
+__device__ __forceinline__ d3 load_prop_first(const ProjectArgs& a, int v) {
+    if (a.y_in || !a.sl.last_edge) return a.inv_mass[v] > 0.0f ? load_prop(a, v) : mk(0.0, 0.0, 0.0);
+    float pv[3];
+    folded_position(a, v, pv, true);
+    if (!(a.inv_mass[v] > 0.0f)) return mk(0.0, 0.0, 0.0);
+    float yf[3];
+    for (int k = 0; k < 3; ++k) yf[k] = pv[k] - a.x_anchor[3 * v + k];
     return mk(yf[0], yf[1], yf[2]);
 }
 
@@ -315,8 +371,10 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
     const bool active = v < a.n_verts;
     bool violated = false, deferred = false, big = false, moved = false, bad = false;
     float move = 0.0f;
+    d3 ykeep = mk(0.0, 0.0, 0.0);
     if (active) {
-        const d3 yprop = a.inv_mass[v] > 0.0f ? load_prop(a, v) : mk(0.0, 0.0, 0.0);
+        const d3 yprop = load_prop_first(a, v);
+        ykeep = yprop;
         bad = !(isfinite(yprop.x) && isfinite(yprop.y) && isfinite(yprop.z));
         if (bad) {
             // a non-finite proposal is not moved and raises the status bit
@@ -368,6 +426,12 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
         }
     }
     if (active && !deferred) slots_consumed(a, v);
+    if (deferred && a.sl.last_edge && !a.y_in)
+    {
+        a.sl.y_def[3 * v] = (float)ykeep.x;         // exact: the values came from floats
+        a.sl.y_def[3 * v + 1] = (float)ykeep.y;
+        a.sl.y_def[3 * v + 2] = (float)ykeep.z;
+    }
     record_motion(a, move);
     // vertices that need the full Alg. 2 go to the slow list, one atomic per
     // block and list: small regions from the front, larger ones from the back

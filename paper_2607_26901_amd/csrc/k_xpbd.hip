@@ -149,6 +149,23 @@ __global__ __launch_bounds__(kBlock) void k_stretch(const int32_t* edges, const 
     stretch_edge(colour_edge(segs, nseg, t), edges, rest, w, p, p, lambda, alpha_t, false);
 }
 
+__global__ __launch_bounds__(kBlock) void k_fill_no_edge(int2* a, int n) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) a[i] = make_int2(0, -1);
+}
+
+// The endpoints of a colour class's edges point at their edge and each other.
+__global__ __launch_bounds__(kBlock) void k_last_colour_map(const int32_t* edges, const int2* segs, int nseg,
+                                                            int total, int n_verts, int2* last_edge) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= total) return;
+    const int e = colour_edge(segs, nseg, t);
+    const int i = edges[2 * e], j = edges[2 * e + 1];
+    if (i < 0 || i >= n_verts || j < 0 || j >= n_verts) return;
+    last_edge[i] = make_int2(e, j);
+    last_edge[j] = make_int2((int)(0x80000000u | (uint32_t)e), i);
+}
+
 __global__ __launch_bounds__(kBlock) void k_update_velocity(int n, const float* x, const float* xs, float inv_dt,
                                                             float* v) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -200,6 +217,15 @@ void launch_stretch_segments(const int32_t* edges_sorted, const float* rest_sort
     if (total <= 0 || nseg <= 0) return;
     hipLaunchKernelGGL(k_stretch, dim3(blocks_for(total)), dim3(kBlock), 0, s, edges_sorted, rest_sorted, segs, nseg,
                        total, inv_mass, p, lambda_sorted, alpha_t);
+}
+
+void launch_last_colour_map(const int32_t* edges_sorted, const int2* segs, int32_t nseg, int32_t total,
+                            int32_t n_verts, int2* last_edge, hipStream_t s) {
+    if (n_verts <= 0) return;
+    hipLaunchKernelGGL(k_fill_no_edge, dim3(blocks_for(n_verts)), dim3(kBlock), 0, s, last_edge, n_verts);
+    if (total <= 0 || nseg <= 0) return;
+    hipLaunchKernelGGL(k_last_colour_map, dim3(blocks_for(total)), dim3(kBlock), 0, s, edges_sorted, segs, nseg,
+                       total, n_verts, last_edge);
 }
 
 void launch_update_velocity(int n, const float* x, const float* x_start, float inv_dt, float* v, hipStream_t s) {
