@@ -311,15 +311,17 @@ int32_t step_slot_stride(const ccfr_ctx* ctx, int n_verts) {
 // half-spaces go into per-vertex slots (no scan or fill)
 void enqueue_regions(ccfr_ctx* ctx, const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
                      const int32_t* counts, long long cap_vf, long long cap_ee, long long cap_vv, hipStream_t s,
-                     const Marks& mk, bool in_step, int32_t slot_stride = 0) {
+                     const Marks& mk, bool in_step, int32_t slot_stride = 0,
+                     const ColourJob* job_contacts = nullptr, const ColourJob* job_fill = nullptr) {
     const bool slots = in_step && slot_stride > 0;
     mk.mark(2, 0);
     launch_contacts(sc, vf, ee, vv, counts, cap_vf, cap_ee, cap_vv, ctx->contacts, ctx->cap_contacts, ctx->vcount,
-                    ctx->counters_d, s, slots);
+                    ctx->counters_d, s, slots, job_contacts);
     mk.mark(2, 1);
     mk.mark(3, 0);
     if (slots) {
-        launch_fill_slots(sc, ctx->contacts, ctx->cap_contacts, ctx->vcount, ctx->hs, slot_stride, ctx->counters_d, s);
+        launch_fill_slots(sc, ctx->contacts, ctx->cap_contacts, ctx->vcount, ctx->hs, slot_stride, ctx->counters_d, s,
+                          job_fill);
         mk.mark(3, 1);
         return;
     }
@@ -366,6 +368,33 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
     const int reuse = adaptive ? 1 : std::max(1, ctx->pair_reuse);
     const PairCaps caps{ctx->cap_vf, ctx->cap_ee, ctx->cap_vv};
     const int32_t slots = step_slot_stride(ctx, n);
+    // The stretch pass: the first colour runs with p's reset to the
+    // prediction, the last one (of two or more) inside the projection's fast
+    // kernel, which reads its result.  With per-vertex slots the pass runs in
+    // blocks of kernels already on the path, since none of them reads p: the
+    // next iteration's reset and first colour in extra blocks of the slow
+    // projection (the first iteration's in a launch of their own), the second,
+    // third and fourth colours in the first blocks of the narrow phase, the
+    // slot fill and the closing kernel; further colours get launches of their own.
+    StretchColor0 c0{};
+    if (plan.has_stretch && !plan.col_total.empty())
+        c0 = StretchColor0{plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[0], plan.col_nseg[0],
+                           plan.col_total[0], sc.inv_mass, plan.lambda, plan.alpha_t, sc.vflags};
+    const int n_col = (int)plan.col_total.size();
+    const bool fold = plan.has_stretch && n_col >= 2 && plan.last_edge && plan.lambda_alt;
+    const bool hosted = fold && slots > 0;
+    const RestartJob restart{ctx->x_pred, ctx->p, 3LL * n, c0};
+    auto colour_job = [&](int c) {
+        ColourJob j{};
+        if (hosted && c >= 1 && c < n_col - 1)
+            j = ColourJob{plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[c], plan.col_nseg[c],
+                          plan.col_total[c], sc.inv_mass, ctx->p, plan.lambda, plan.alpha_t};
+        return j;
+    };
+    const ColourJob job_contacts = colour_job(1), job_fill = colour_job(2), job_close = colour_job(3);
+    if (hosted)
+        launch_close_iteration(ctx->x_pred, ctx->p, 3LL * n, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
+                               ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs, false, s, slots, &c0, false);
     for (int it = 0; it < plan.iters; ++it) {
         const Marks mk{ctx, it, s};
         const int first = it - it % reuse;
@@ -387,24 +416,21 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
             }
         }
         enqueue_regions(ctx, sc, ctx->vf, ctx->ee, ctx->vv, counts_ptr(ctx), ctx->cap_vf, ctx->cap_ee,
-                        ctx->cap_vv, s, mk, true, slots);
+                        ctx->cap_vv, s, mk, true, slots, &job_contacts, &job_fill);
         mk.mark(4, 0);
-        // the first stretch colour runs in the closing kernel, on p = x_pred
-        StretchColor0 c0{};
-        if (plan.has_stretch && !plan.col_total.empty())
-            c0 = StretchColor0{plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[0], plan.col_nseg[0],
-                               plan.col_total[0], sc.inv_mass, plan.lambda, plan.alpha_t, sc.vflags};
-        launch_close_iteration(ctx->x_pred, ctx->p, 3LL * n, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
-                               ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs,
-                               adaptive ? it == plan.iters - 1 : it == first + group - 1, s, slots, &c0);
-        // the last one (of two or more) runs in the projection, which reads its result
-        const bool fold = plan.has_stretch && plan.col_total.size() >= 2 && plan.last_edge && plan.lambda_alt;
-        if (plan.has_stretch) {
-            for (size_t c = 1; c + (fold ? 1 : 0) < plan.col_total.size(); ++c)
+        const bool close_pairs = adaptive ? it == plan.iters - 1 : it == first + group - 1;
+        if (hosted)
+            launch_close_iteration(nullptr, nullptr, 0, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
+                                   ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs, close_pairs, s, slots, nullptr,
+                                   true, &job_close);
+        else
+            launch_close_iteration(ctx->x_pred, ctx->p, 3LL * n, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
+                                   ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs, close_pairs, s, slots, &c0);
+        if (plan.has_stretch)
+            for (int c = hosted ? 4 : 1; c + (fold ? 1 : 0) < n_col; ++c)
                 launch_stretch_segments(plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[c],
                                         plan.col_nseg[c], plan.col_total[c], sc.inv_mass, ctx->p, plan.lambda,
                                         plan.alpha_t, s);
-        }
         mk.mark(4, 1);
         ProjectArgs pa{};
         pa.n_verts = n;
@@ -428,6 +454,7 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
             pa.sl = StretchLast{plan.last_edge, plan.edges_sorted, plan.rest_sorted,
                                 (it & 1) ? plan.lambda_alt : plan.lambda, (it & 1) ? plan.lambda : plan.lambda_alt,
                                 plan.alpha_t, ctx->y_def};
+        if (hosted && it + 1 < plan.iters) pa.next = restart;
         mk.mark(5, 0);
         launch_project(pa, ctx->counters_d, false, s);
         mk.mark(5, 1);

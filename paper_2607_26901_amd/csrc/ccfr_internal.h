@@ -282,18 +282,125 @@ void launch_finalize_pairs(const GridWs& g, PairLists pl, DevCounters* c, hipStr
 
 // The contact list of the candidate pairs; vcount counts each vertex's
 // half-spaces for the CSR unless `for_slots` (launch_fill_slots counts them)
+struct ColourJob;
 void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
                      const int32_t* counts, int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
                      Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s,
-                     bool for_slots = false);
+                     bool for_slots = false, const ColourJob* job = nullptr);
 // The contacts' half-spaces into per-vertex slots: slot_hs[v * slot_stride + k]
 // for the k-th one vertex v receives (vcount[v] counts them)
 void launch_fill_slots(const Scene& sc, const Contact* contacts, int64_t cap_contacts, int32_t* vcount,
-                       ccfr_halfspace* slot_hs, int32_t slot_stride, DevCounters* c, hipStream_t s);
+                       ccfr_halfspace* slot_hs, int32_t slot_stride, DevCounters* c, hipStream_t s,
+                       const ColourJob* job = nullptr);
 // finalize: close the region build (overflow bits, totals) in a launch of its own
 void launch_fill(const Scene& sc, const Contact* contacts, int64_t cap_contacts, const int32_t* offsets,
                  int32_t* vcount, ccfr_halfspace* hs, int64_t cap_hs, DevCounters* c, bool finalize,
                  hipStream_t s);
+
+// The first colour of the stretch pass, run by the iteration's closing kernel
+// (total == 0: none).
+struct StretchColor0 {
+    const int32_t* edges_sorted;
+    const float* rest_sorted;
+    const int2* segs;
+    int32_t nseg, total;
+    const float* inv_mass;
+    float* lambda_sorted;
+    float alpha_t;
+    const uint8_t* vflags;
+};
+// Edge t of a colour class whose edges lie in nseg segments of the
+// colour-sorted edge array, segs[k] = (first edge, exclusive prefix of segment
+// lengths): binary search for its segment.
+__device__ __forceinline__ int colour_edge(const int2* segs, int nseg, int t) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].y <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return segs[lo].x + (t - segs[lo].y);
+}
+
+// One XPBD distance-constraint update of edge e (Macklin et al. 2016): reads
+// the endpoints from `src`, writes them to `dst` (the same array inside the
+// pass; the first colour reads the prediction and writes p, so both endpoints
+// are always written), and accumulates the edge's multiplier.
+__device__ __forceinline__ void stretch_edge(int e, const int32_t* edges, const float* rest, const float* w,
+                                             const float* src, float* dst, float* lambda, float alpha_t,
+                                             bool always_write) {
+    const int i = edges[2 * e], j = edges[2 * e + 1];
+    const float wi = w[i], wj = w[j];
+    const float W = wi + wj;
+    float pi[3], pj[3], d[3];
+    for (int c = 0; c < 3; ++c) {
+        pi[c] = src[3 * i + c];
+        pj[c] = src[3 * j + c];
+        d[c] = pi[c] - pj[c];
+    }
+    const float len = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (W == 0.0f || len == 0.0f) {
+        if (always_write)
+            for (int c = 0; c < 3; ++c) {
+                dst[3 * i + c] = pi[c];
+                dst[3 * j + c] = pj[c];
+            }
+        return;
+    }
+    const float C = len - rest[e];
+    const float lam = lambda[e];
+    const float dl = (-C - alpha_t * lam) / (W + alpha_t);
+    const float s = dl / len;
+    for (int c = 0; c < 3; ++c) {
+        dst[3 * i + c] = pi[c] + wi * s * d[c];
+        dst[3 * j + c] = pj[c] - wj * s * d[c];
+    }
+    lambda[e] = lam + dl;
+}
+
+// A colour class of the stretch pass (edges as in colour_edge, total == 0:
+// none) run by the first blocks of a kernel that precedes the next colour and
+// touches neither p nor the multipliers: one thread per edge.
+struct ColourJob {
+    const int32_t* edges_sorted;
+    const float* rest_sorted;
+    const int2* segs;
+    int32_t nseg, total;
+    const float* inv_mass;
+    float* p;
+    float* lambda_sorted;
+    float alpha_t;
+};
+inline int colour_job_blocks(const ColourJob& j, int block) {
+    return j.total > 0 && j.nseg > 0 ? (int)((j.total + block - 1) / block) : 0;
+}
+__device__ __forceinline__ void run_colour_job(const ColourJob& j, int t) {
+    if (t < j.total)
+        stretch_edge(colour_edge(j.segs, j.nseg, t), j.edges_sorted, j.rest_sorted, j.inv_mass, j.p, j.p,
+                     j.lambda_sorted, j.alpha_t, false);
+}
+
+// The start of an iteration's stretch pass: p = x_pred (n3 entries), and the
+// first colour (c0.total edges) on it: an endpoint of such an edge gets its p
+// from the edge's update, every other vertex a copy.  Entry i of the grid.
+__device__ __forceinline__ void restart_pass(const float* x_pred, float* p, long long n3, const StretchColor0& c0,
+                                             long long i) {
+    if (i < n3 && !(c0.total > 0 && (c0.vflags[i / 3] & VF_COLOR0))) p[i] = x_pred[i];
+    if (i < c0.total)
+        stretch_edge(colour_edge(c0.segs, c0.nseg, (int)i), c0.edges_sorted, c0.rest_sorted, c0.inv_mass, x_pred, p,
+                     c0.lambda_sorted, c0.alpha_t, true);
+}
+// restart_pass run by extra blocks of another kernel (n3 == 0: none)
+struct RestartJob {
+    const float* x_pred;
+    float* p;
+    long long n3;
+    StretchColor0 c0;
+};
+inline int restart_job_blocks(const RestartJob& r, int block) {
+    const long long n = r.n3 > r.c0.total ? r.n3 : (long long)r.c0.total;
+    return r.n3 > 0 ? (int)((n + block - 1) / block) : 0;
+}
 
 // The last colour of the stretch pass, folded into the projection that reads
 // its result (last_edge == nullptr: none): last_edge[v] = (v's edge e in that
@@ -335,6 +442,7 @@ struct ProjectArgs {
     int32_t slot_stride;
     ParamSrc prm;
     StretchLast sl;
+    RestartJob next;         // the next iteration's stretch start, in extra blocks of the slow kernel
 };
 // zero_counters: clear the slow-list counters first (the substep clears them
 // in launch_close_iteration instead)
@@ -352,22 +460,11 @@ struct PairCaps {
     int64_t vf, ee, vv;
 };
 // slot_stride > 0: the region build went into per-vertex slots (offsets unused)
-// The first colour of the stretch pass, run by the iteration's closing kernel
-// (total == 0: none).
-struct StretchColor0 {
-    const int32_t* edges_sorted;
-    const float* rest_sorted;
-    const int2* segs;
-    int32_t nseg, total;
-    const float* inv_mass;
-    float* lambda_sorted;
-    float alpha_t;
-    const uint8_t* vflags;
-};
 void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounters* c, uint32_t* level_mask,
                             int n_meshes, int32_t n_verts, const int32_t* offsets, PairCaps caps,
                             int64_t cap_contacts, int64_t cap_hs, bool close_pairs, hipStream_t s,
-                            int32_t slot_stride = 0, const StretchColor0* c0 = nullptr);
+                            int32_t slot_stride = 0, const StretchColor0* c0 = nullptr, bool finalize = true,
+                            const ColourJob* job = nullptr);
 // Before the candidate stage of an iteration in a substep whose builds adapt to
 // the motion: adds the last projection's largest move to the moves summed
 // since the last build; if the sum may exceed `skin` (the least widening of

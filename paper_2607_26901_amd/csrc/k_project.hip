@@ -751,8 +751,15 @@ __device__ __forceinline__ float project_wave_vertex(const ProjectArgs& a, DevCo
 // regions), one vertex per wavefront, first, since their vertices take the
 // longest; the remaining blocks run list A (regions of at most kSmall
 // half-spaces), one lane per vertex, the sort and the passes in registers.
-__global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCounters* c, int wave_blocks) {
+__global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCounters* c, int wave_blocks,
+                                                         int lane_blocks) {
     __shared__ WaveLds lds[kBlock / 64];
+    if ((int)blockIdx.x >= wave_blocks + lane_blocks) {
+        // the next iteration's stretch start: the slow path reads no p
+        restart_pass(a.next.x_pred, a.next.p, a.next.n3, a.next.c0,
+                     (long long)(blockIdx.x - wave_blocks - lane_blocks) * kBlock + threadIdx.x);
+        return;
+    }
     if ((int)blockIdx.x < wave_blocks) {
         const int wave = threadIdx.x / 64;
         const int n_list = c->n_viol_b;
@@ -764,7 +771,6 @@ __global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCount
         record_motion(a, move);
         return;
     }
-    const int lane_blocks = gridDim.x - wave_blocks;
     const int n_list = c->n_viol;
     float move = 0.0f;
     for (int i0 = (blockIdx.x - wave_blocks) * kBlock; i0 < n_list; i0 += lane_blocks * kBlock) {
@@ -803,7 +809,9 @@ void launch_project(const ProjectArgs& a, DevCounters* c, bool zero_counters, hi
     // thousand wavefront vertices and a grid-stride over the lane list
     const int lane_blocks = std::max(1, std::min(1024, (a.n_verts + kBlock - 1) / kBlock));
     const int wave_blocks = std::max(1, std::min(1024, (a.n_verts + kBlock / 64 - 1) / (kBlock / 64)));
-    hipLaunchKernelGGL(k_project_slow, dim3(wave_blocks + lane_blocks), dim3(kBlock), 0, s, a, c, wave_blocks);
+    const int restart_blocks = restart_job_blocks(a.next, kBlock);
+    hipLaunchKernelGGL(k_project_slow, dim3(wave_blocks + lane_blocks + restart_blocks), dim3(kBlock), 0, s, a, c,
+                       wave_blocks, lane_blocks);
 }
 
 }  // namespace ccfr

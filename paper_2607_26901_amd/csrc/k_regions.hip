@@ -242,7 +242,13 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Scene sc, const int32_t* vf
                                                      const int32_t* vv, const int32_t* counts,
                                                      int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
                                                      Contact* contacts, int64_t cap_contacts,
-                                                     int32_t* vcount, DevCounters* c) {
+                                                     int32_t* vcount, DevCounters* c, ColourJob job,
+                                                     int job_blocks) {
+    // the first job_blocks blocks run a stretch colour (the pairs read no p)
+    if ((int)blockIdx.x < job_blocks) {
+        run_colour_job(job, blockIdx.x * kBlock + threadIdx.x);
+        return;
+    }
     const long long nvf = min((long long)counts[0], (long long)cap_vf);
     const long long nee = min((long long)counts[1], (long long)cap_ee);
     const long long nvv = min((long long)counts[2], (long long)cap_vv);
@@ -252,9 +258,9 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Scene sc, const int32_t* vf
     int n_degenerate = 0;
     // grid-stride: every thread of the block runs the same number of rounds so
     // that the block-level append sees all of them together
-    const long long stride = (long long)gridDim.x * kBlock;
+    const long long stride = (long long)(gridDim.x - job_blocks) * kBlock;
     const long long rounds = (total + stride - 1) / stride;
-    const long long i0 = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long i0 = (long long)(blockIdx.x - job_blocks) * kBlock + threadIdx.x;
     for (long long rd = 0; rd < rounds; ++rd) {
         const long long i = i0 + rd * stride;
         bool keep = false;
@@ -288,11 +294,15 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Scene sc, const int32_t* vf
 // the largest count is reported (the step is then repeated with more room).
 __global__ __launch_bounds__(kBlock) void k_fill_slots(Scene sc, const Contact* contacts, int64_t cap_contacts,
                                                        int32_t* counts, ccfr_halfspace* hs, int32_t stride,
-                                                       DevCounters* c) {
+                                                       DevCounters* c, ColourJob job, int job_blocks) {
+    if ((int)blockIdx.x < job_blocks) {
+        run_colour_job(job, blockIdx.x * kBlock + threadIdx.x);
+        return;
+    }
     const long long n = min((long long)c->n_contacts, (long long)cap_contacts);
-    const long long stride_g = (long long)gridDim.x * kBlock;
+    const long long stride_g = (long long)(gridDim.x - job_blocks) * kBlock;
     int n_hs = 0, top = 0;
-    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride_g) {
+    for (long long i = (long long)(blockIdx.x - job_blocks) * kBlock + threadIdx.x; i < n; i += stride_g) {
         const Contact rec = contacts[i];
         const int kind = (int)((uint32_t)rec.a >> 30);
         const int pa = rec.a & 0x3fffffff, pb = rec.b;
@@ -412,22 +422,29 @@ int grid_for(long long n) {
 void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
                      const int32_t* counts, int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
                      Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s,
-                     bool for_slots) {
-    const int blocks = grid_for(cap_vf + cap_ee + cap_vv);
+                     bool for_slots, const ColourJob* job) {
+    ColourJob hosted{};
+    if (job) hosted = *job;
+    const int jb = colour_job_blocks(hosted, kBlock);
+    const int blocks = grid_for(cap_vf + cap_ee + cap_vv) + jb;
     int32_t* per_vertex = for_slots ? nullptr : vcount;     // slots: counted by the fill
     if (sc.narrow_fp32)
         hipLaunchKernelGGL(k_contacts<float>, dim3(blocks), dim3(kBlock), 0, s, sc, vf, ee, vv, counts, cap_vf,
-                           cap_ee, cap_vv, contacts, cap_contacts, per_vertex, c);
+                           cap_ee, cap_vv, contacts, cap_contacts, per_vertex, c, hosted, jb);
     else
         hipLaunchKernelGGL(k_contacts<double>, dim3(blocks), dim3(kBlock), 0, s, sc, vf, ee, vv, counts, cap_vf,
-                           cap_ee, cap_vv, contacts, cap_contacts, per_vertex, c);
+                           cap_ee, cap_vv, contacts, cap_contacts, per_vertex, c, hosted, jb);
 }
 
 void launch_fill_slots(const Scene& sc, const Contact* contacts, int64_t cap_contacts, int32_t* vcount,
-                       ccfr_halfspace* slot_hs, int32_t slot_stride, DevCounters* c, hipStream_t s) {
+                       ccfr_halfspace* slot_hs, int32_t slot_stride, DevCounters* c, hipStream_t s,
+                       const ColourJob* job) {
+    ColourJob hosted{};
+    if (job) hosted = *job;
+    const int jb = colour_job_blocks(hosted, kBlock);
     // grid-stride over the contacts: a sixteenth of the capacity's blocks
-    hipLaunchKernelGGL(k_fill_slots, dim3(grid_for(cap_contacts / 16)), dim3(kBlock), 0, s, sc, contacts,
-                       cap_contacts, vcount, slot_hs, slot_stride, c);
+    hipLaunchKernelGGL(k_fill_slots, dim3(grid_for(cap_contacts / 16) + jb), dim3(kBlock), 0, s, sc, contacts,
+                       cap_contacts, vcount, slot_hs, slot_stride, c, hosted, jb);
 }
 
 void launch_fill(const Scene& sc, const Contact* contacts, int64_t cap_contacts, const int32_t* offsets,

@@ -40,80 +40,34 @@ __global__ __launch_bounds__(kBlock) void k_copy(const float* src, float* dst, l
     if (i < n) dst[i] = src[i];
 }
 
-// Edge t of a colour class whose edges lie in nseg segments of the
-// colour-sorted edge array, segs[k] = (first edge, exclusive prefix of segment
-// lengths): binary search for its segment.
-__device__ __forceinline__ int colour_edge(const int2* segs, int nseg, int t) {
-    int lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (segs[mid].y <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    return segs[lo].x + (t - segs[lo].y);
-}
-
-// One XPBD distance-constraint update of edge e: reads the endpoints from
-// `src`, writes them to `dst` (the same array inside the pass; the first
-// colour reads the prediction and writes p, so both endpoints are always
-// written), and accumulates the edge's multiplier.
-__device__ __forceinline__ void stretch_edge(int e, const int32_t* edges, const float* rest, const float* w,
-                                             const float* src, float* dst, float* lambda, float alpha_t,
-                                             bool always_write) {
-    const int i = edges[2 * e], j = edges[2 * e + 1];
-    const float wi = w[i], wj = w[j];
-    const float W = wi + wj;
-    float pi[3], pj[3], d[3];
-    for (int c = 0; c < 3; ++c) {
-        pi[c] = src[3 * i + c];
-        pj[c] = src[3 * j + c];
-        d[c] = pi[c] - pj[c];
-    }
-    const float len = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    if (W == 0.0f || len == 0.0f) {
-        if (always_write)
-            for (int c = 0; c < 3; ++c) {
-                dst[3 * i + c] = pi[c];
-                dst[3 * j + c] = pj[c];
-            }
-        return;
-    }
-    const float C = len - rest[e];
-    const float lam = lambda[e];
-    const float dl = (-C - alpha_t * lam) / (W + alpha_t);
-    const float s = dl / len;
-    for (int c = 0; c < 3; ++c) {
-        dst[3 * i + c] = pi[c] + wi * s * d[c];
-        dst[3 * j + c] = pj[c] - wj * s * d[c];
-    }
-    lambda[e] = lam + dl;
-}
-
-// End of an iteration's builds: closes the region build, and the candidate
-// build too when no later iteration reuses its lists (close_pairs), then
-// clears what the next build counts; p starts again from the prediction, and
-// the first stretch colour (c0.total edges) runs here on it: an endpoint of
-// such an edge gets its p from the edge's update, every other vertex a copy.
+// End of an iteration's builds (finalize): closes the region build, and the
+// candidate build too when no later iteration reuses its lists (close_pairs),
+// then clears what the next build counts.  The stretch pass starts here
+// (restart_pass on n3 entries and c0), or, when it started earlier, the first
+// job_blocks blocks run one of its colours.
 __global__ __launch_bounds__(kBlock) void k_close_iteration(const float* x_pred, float* p, long long n3,
                                                             DevCounters* c, uint32_t* level_mask, int n_meshes,
                                                             int32_t n_verts, const int32_t* offsets,
                                                             PairCaps caps, int64_t cap_contacts, int64_t cap_hs,
                                                             int close_pairs, int32_t slot_stride,
-                                                            StretchColor0 c0) {
-    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (i == 0) {
+                                                            StretchColor0 c0, int finalize, ColourJob job,
+                                                            int job_blocks) {
+    if ((int)blockIdx.x < job_blocks) {
+        run_colour_job(job, blockIdx.x * kBlock + threadIdx.x);
+        return;
+    }
+    const long long i = (long long)(blockIdx.x - job_blocks) * kBlock + threadIdx.x;
+    const long long n_threads = (long long)(gridDim.x - job_blocks) * kBlock;
+    if (i == 0 && finalize) {
         if (close_pairs) finalize_pairs_body(c, caps.vf, caps.ee, caps.vv);
         if (slot_stride > 0) finalize_slot_regions_body(c, n_verts, slot_stride, cap_contacts);
         else finalize_regions_body(c, n_verts, offsets, cap_contacts, cap_hs);
         if (close_pairs) reset_build_counters(c);
         else reset_region_counters(c);
     }
-    if (close_pairs)
-        for (long long m = i; m < n_meshes; m += (long long)gridDim.x * kBlock) level_mask[m] = 0u;
-    if (i < n3 && !(c0.total > 0 && (c0.vflags[i / 3] & VF_COLOR0))) p[i] = x_pred[i];
-    if (i < c0.total)
-        stretch_edge(colour_edge(c0.segs, c0.nseg, (int)i), c0.edges_sorted, c0.rest_sorted, c0.inv_mass, x_pred, p,
-                     c0.lambda_sorted, c0.alpha_t, true);
+    if (close_pairs && finalize)
+        for (long long m = i; m < n_meshes; m += n_threads) level_mask[m] = 0u;
+    restart_pass(x_pred, p, n3, c0, i);
 }
 
 // One block.  Thread 0 decides (only it reads and writes the motion fields);
@@ -197,13 +151,17 @@ void launch_copy(const float* src, float* dst, int64_t n, hipStream_t s) {
 void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounters* c, uint32_t* level_mask,
                             int n_meshes, int32_t n_verts, const int32_t* offsets, PairCaps caps,
                             int64_t cap_contacts, int64_t cap_hs, bool close_pairs, hipStream_t s,
-                            int32_t slot_stride, const StretchColor0* c0) {
+                            int32_t slot_stride, const StretchColor0* c0, bool finalize, const ColourJob* job) {
     StretchColor0 first{};
     if (c0 && c0->total > 0 && c0->nseg > 0) first = *c0;
-    const long long n = std::max<long long>(std::max<long long>(std::max<long long>(n3, n_meshes), first.total), 1);
-    hipLaunchKernelGGL(k_close_iteration, dim3(blocks_for(n)), dim3(kBlock), 0, s, x_pred, p, (long long)n3, c,
+    ColourJob hosted{};
+    if (job) hosted = *job;
+    const int jb = colour_job_blocks(hosted, kBlock);
+    const long long n = std::max<long long>(
+        std::max<long long>(std::max<long long>(n3, finalize ? n_meshes : 0), first.total), 1);
+    hipLaunchKernelGGL(k_close_iteration, dim3(blocks_for(n) + jb), dim3(kBlock), 0, s, x_pred, p, (long long)n3, c,
                        level_mask, n_meshes, n_verts, offsets, caps, cap_contacts, cap_hs, close_pairs ? 1 : 0,
-                       slot_stride, first);
+                       slot_stride, first, finalize ? 1 : 0, hosted, jb);
 }
 
 void launch_decide_build(DevCounters* c, uint32_t* level_mask, int n_meshes, double skin, PairCaps caps,
