@@ -370,7 +370,8 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
     const int32_t slots = step_slot_stride(ctx, n);
     // The stretch pass: the first colour runs with p's reset to the
     // prediction, the last one (of two or more) inside the projection's fast
-    // kernel, which reads its result.  With per-vertex slots the pass runs in
+    // kernel, which reads its result, and with three or more colours the one
+    // before the last too.  With per-vertex slots the pass runs in
     // blocks of kernels already on the path, since none of them reads p: the
     // next iteration's reset and first colour in extra blocks of the slow
     // projection (the first iteration's in a launch of their own), the second,
@@ -382,11 +383,13 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
                            plan.col_total[0], sc.inv_mass, plan.lambda, plan.alpha_t, sc.vflags};
     const int n_col = (int)plan.col_total.size();
     const bool fold = plan.has_stretch && n_col >= 2 && plan.last_edge && plan.lambda_alt;
+    const bool fold2 = fold && n_col >= 3 && plan.prev_edge;
+    const int n_launched = n_col - (fold2 ? 2 : fold ? 1 : 0);     // colours before the folded ones
     const bool hosted = fold && slots > 0;
     const RestartJob restart{ctx->x_pred, ctx->p, 3LL * n, c0};
     auto colour_job = [&](int c) {
         ColourJob j{};
-        if (hosted && c >= 1 && c < n_col - 1)
+        if (hosted && c >= 1 && c < n_launched)
             j = ColourJob{plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[c], plan.col_nseg[c],
                           plan.col_total[c], sc.inv_mass, ctx->p, plan.lambda, plan.alpha_t};
         return j;
@@ -427,7 +430,7 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
             launch_close_iteration(ctx->x_pred, ctx->p, 3LL * n, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
                                    ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs, close_pairs, s, slots, &c0);
         if (plan.has_stretch)
-            for (int c = hosted ? 4 : 1; c + (fold ? 1 : 0) < n_col; ++c)
+            for (int c = hosted ? 4 : 1; c < n_launched; ++c)
                 launch_stretch_segments(plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[c],
                                         plan.col_nseg[c], plan.col_total[c], sc.inv_mass, ctx->p, plan.lambda,
                                         plan.alpha_t, s);
@@ -451,7 +454,7 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
         pa.slot_stride = slots;
         pa.prm = sc.prm;
         if (fold)   // the multipliers of the folded colour alternate between two arrays
-            pa.sl = StretchLast{plan.last_edge, plan.edges_sorted, plan.rest_sorted,
+            pa.sl = StretchLast{plan.last_edge, fold2 ? plan.prev_edge : nullptr, plan.rest_sorted,
                                 (it & 1) ? plan.lambda_alt : plan.lambda, (it & 1) ? plan.lambda : plan.lambda_alt,
                                 plan.alpha_t, ctx->y_def};
         if (hosted && it + 1 < plan.iters) pa.next = restart;
@@ -615,6 +618,7 @@ StepPlan mesh_plan(ccfr_ctx* ctx, const ccfr_mesh* m, float* x, float* v, const 
     plan.lambda = m->lambda_d;
     plan.lambda_alt = m->lambda_alt_d;
     plan.last_edge = m->last_edge_d;
+    plan.prev_edge = m->prev_edge_d;
     plan.n_edges = m->n_edges;
     plan.segs = m->segs_d;
     const int nc = (int)m->color_begin.size() - 1;
@@ -737,9 +741,14 @@ int ccfr_mesh_create(ccfr_ctx* ctx, int32_t n_verts, const int32_t* tris, int32_
     if (e == hipSuccess && h.has_stretch && nc >= 2) {
         e = dev_alloc(&m->lambda_alt_d, h.n_edges);
         if (e == hipSuccess) e = dev_alloc(&m->last_edge_d, h.n_verts);
+        if (e == hipSuccess && nc >= 3) e = dev_alloc(&m->prev_edge_d, h.n_verts);
         if (e == hipSuccess) {
             launch_last_colour_map(m->edges_sorted_d, m->segs_d + (nc - 1), 1,
                                    h.color_begin[nc] - h.color_begin[nc - 1], h.n_verts, m->last_edge_d, nullptr);
+            if (nc >= 3)
+                launch_last_colour_map(m->edges_sorted_d, m->segs_d + (nc - 2), 1,
+                                       h.color_begin[nc - 1] - h.color_begin[nc - 2], h.n_verts, m->prev_edge_d,
+                                       nullptr);
             e = hipDeviceSynchronize();
         }
     }
@@ -761,7 +770,7 @@ void ccfr_mesh_destroy(ccfr_mesh* m) {
     if (m->ctx && m->ctx->graph.owner == m) drop_graph(m->ctx);
     dev_free(m->tris_d); dev_free(m->edges_d); dev_free(m->inv_mass_d); dev_free(m->free_list_d);
     dev_free(m->vflags_d); dev_free(m->edges_sorted_d); dev_free(m->rest_sorted_d); dev_free(m->lambda_d);
-    dev_free(m->segs_d); dev_free(m->lambda_alt_d); dev_free(m->last_edge_d);
+    dev_free(m->segs_d); dev_free(m->lambda_alt_d); dev_free(m->last_edge_d); dev_free(m->prev_edge_d);
     delete m;
 }
 

@@ -123,6 +123,7 @@ struct ccfr_batch {
     float* lambda = nullptr;
     float* lambda_alt = nullptr;          // the last stretch colour's multipliers alternate
     int2* last_edge = nullptr;            // vertex -> (its edge in the last colour, partner)
+    int2* prev_edge = nullptr;            // the same for the colour before the last
     MeshParams* table_d = nullptr;
     std::vector<MeshParams> table_h;
     std::vector<ccfr_params> coll_h;      // per slot: collision parameters
@@ -281,11 +282,13 @@ int rebuild_plan(ccfr_batch* b, hipStream_t s) {
     }
     if (!segs.empty()) {
         HIP_OK(hipMemcpyAsync(b->segs_d, segs.data(), sizeof(int2) * segs.size(), hipMemcpyHostToDevice, s));
-        if (n_colors >= 2) {
+        if (n_colors >= 2)
             launch_last_colour_map(P.edges_sorted, b->segs_d + pl.col_first[n_colors - 1], pl.col_nseg[n_colors - 1],
                                    pl.col_total[n_colors - 1], (int32_t)b->used_v, b->last_edge, s);
-            HIP_OK(hipGetLastError());
-        }
+        if (n_colors >= 3)
+            launch_last_colour_map(P.edges_sorted, b->segs_d + pl.col_first[n_colors - 2], pl.col_nseg[n_colors - 2],
+                                   pl.col_total[n_colors - 2], (int32_t)b->used_v, b->prev_edge, s);
+        HIP_OK(hipGetLastError());
         HIP_OK(hipStreamSynchronize(s));
     }
     pl.has_stretch = !segs.empty();
@@ -296,6 +299,7 @@ int rebuild_plan(ccfr_batch* b, hipStream_t s) {
         pl.lambda_alt = b->lambda_alt;
         pl.last_edge = b->last_edge;
     }
+    if (n_colors >= 3) pl.prev_edge = b->prev_edge;
     pl.n_edges = b->used_e;
     pl.segs = b->segs_d;
     pl.dt = b->sp.dt;
@@ -321,8 +325,8 @@ int64_t ccfr_batch_footprint(int32_t n_verts, int32_t n_tris, int32_t n_edges) {
     // two pools: x, v (12 B each), w (4), mesh id (2), free flag (1), free
     // list entry (4) per vertex; 12 B per triangle; 20 B per edge (edge, sorted
     // edge, rest length); plus lambda twice (8 B per edge) and the last stretch
-    // colour's vertex map (4 B per vertex)
-    long long bytes = 2 * (35 * N + 12 * T + 20 * E) + 8 * E + 4 * N;
+    // colours' vertex maps (16 B per vertex)
+    long long bytes = 2 * (35 * N + 12 * T + 20 * E) + 8 * E + 16 * N;
     // workspace at the default list sizes: substep buffers (36 B per vertex),
     // region CSR (12), grid entry twice (sorted and staged) + rank + key (104
     // per binned primitive or vertex) and at most 8 bucket counters and 8
@@ -359,6 +363,7 @@ int ccfr_batch_create(ccfr_ctx* ctx, int32_t max_slots, int64_t max_verts, int64
     if (rc == CCFR_OK && (dev_alloc(&b->lambda, std::max<long long>(max_edges, 1)) != hipSuccess ||
                           dev_alloc(&b->lambda_alt, std::max<long long>(max_edges, 1)) != hipSuccess ||
                           dev_alloc(&b->last_edge, max_verts) != hipSuccess ||
+                          dev_alloc(&b->prev_edge, max_verts) != hipSuccess ||
                           dev_alloc(&b->table_d, max_slots) != hipSuccess ||
                           dev_alloc(&b->moves_d, max_slots) != hipSuccess))
         rc = CCFR_ERR_NO_MEMORY;
@@ -385,6 +390,7 @@ void ccfr_batch_destroy(ccfr_batch* b) {
     dev_free(b->lambda);
     dev_free(b->lambda_alt);
     dev_free(b->last_edge);
+    dev_free(b->prev_edge);
     dev_free(b->table_d);
     dev_free(b->moves_d);
     dev_free(b->segs_d);

@@ -71,6 +71,7 @@ struct ccfr_mesh {
     // lambda_d and lambda_alt_d; last_edge_d maps a vertex to its edge there
     float* lambda_alt_d = nullptr;
     int2* last_edge_d = nullptr;
+    int2* prev_edge_d = nullptr;        // three or more colours: the same for the one before the last
     std::vector<int32_t> color_begin;   // n_colors + 1
     float typ_len = 0.f;                // edge length the grid cell is sized for
     std::vector<int32_t> edges_h;
@@ -183,6 +184,7 @@ struct StepPlan {
     // more colours): vertex -> its edge in that colour, and the second array
     // its multipliers alternate with
     const int2* last_edge = nullptr;
+    const int2* prev_edge = nullptr;    // three or more colours: the one before the last is folded too
     float* lambda_alt = nullptr;
     long long n_edges = 0;
     const int2* segs = nullptr;

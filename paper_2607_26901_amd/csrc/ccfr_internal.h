@@ -411,9 +411,12 @@ inline int restart_job_blocks(const RestartJob& r, int block) {
 // multiplier to lambda_out (both endpoints read lambda_in, so the two arrays
 // alternate between iterations).  The fast kernel hands the displacement of a
 // vertex it defers to the slow one in y_def (3 floats per vertex).
+// With prev_edge (the same kind of map for the colour before the last), that
+// colour is folded in as well: each vertex recomputes its own and its
+// last-colour partner's positions after it.
 struct StretchLast {
     const int2* last_edge;
-    const int32_t* edges_sorted;
+    const int2* prev_edge;
     const float* rest_sorted;
     const float* lambda_in;
     float* lambda_out;

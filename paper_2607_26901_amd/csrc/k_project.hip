@@ -172,42 +172,77 @@ __device__ bool project_slow(const ccfr_halfspace* H, int K, const d3 yprop, con
 
 // ---- shared per-vertex plumbing ----
 
-// Vertex v's position after the folded last stretch colour: p, or, for an
-// endpoint of an edge of that colour, the endpoint's position after the edge's
-// XPBD distance update (Macklin et al. 2016), computed from p with the same
-// arithmetic as a colour launch.  p is not written during the projection, so
-// both endpoints compute the same step; the first one stores the multiplier
-// when write_lambda.
-__device__ __forceinline__ void folded_position(const ProjectArgs& a, int v, float pv[3], bool write_lambda) {
-    for (int k = 0; k < 3; ++k) pv[k] = a.p[3 * v + k];
-    const int2 m = a.sl.last_edge[v];
+// One endpoint's side of an edge's XPBD distance update (Macklin et al.
+// 2016) in a folded colour: x is the vertex, m its map entry (edge, with bit 31
+// set when x is the second endpoint; partner), px and po the positions of x
+// and its partner before the colour.  The arithmetic is that of a colour
+// launch, so both endpoints take the same step; the first one stores the
+// multiplier when write_lambda.
+__device__ __forceinline__ void edge_side(const ProjectArgs& a, int2 m, int x, const float px[3], const float po[3],
+                                          float out[3], bool write_lambda) {
+    for (int k = 0; k < 3; ++k) out[k] = px[k];
     if (m.y < 0) return;
     const bool second = m.x < 0;
     const int e = m.x & 0x7fffffff;
-    const int i = second ? m.y : v, j = second ? v : m.y;
+    const int i = second ? m.y : x, j = second ? x : m.y;
     const float wi = a.inv_mass[i], wj = a.inv_mass[j];
     const float W = wi + wj;
     float pi[3], pj[3], d[3];
     for (int k = 0; k < 3; ++k) {
-        pi[k] = a.p[3 * i + k];
-        pj[k] = a.p[3 * j + k];
+        pi[k] = second ? po[k] : px[k];
+        pj[k] = second ? px[k] : po[k];
         d[k] = pi[k] - pj[k];
     }
     const float len = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     const float lam = a.sl.lambda_in[e];
     if (W == 0.0f || len == 0.0f) {
-        if (write_lambda && v == i) a.sl.lambda_out[e] = lam;
+        if (write_lambda && !second) a.sl.lambda_out[e] = lam;
         return;
     }
     const float C = len - a.sl.rest_sorted[e];
     const float dl = (-C - a.sl.alpha_t * lam) / (W + a.sl.alpha_t);
     const float s = dl / len;
-    if (v == i) {
-        for (int k = 0; k < 3; ++k) pv[k] = pi[k] + wi * s * d[k];
+    if (!second) {
+        for (int k = 0; k < 3; ++k) out[k] = pi[k] + wi * s * d[k];
         if (write_lambda) a.sl.lambda_out[e] = lam + dl;
     } else {
-        for (int k = 0; k < 3; ++k) pv[k] = pj[k] - wj * s * d[k];
+        for (int k = 0; k < 3; ++k) out[k] = pj[k] - wj * s * d[k];
     }
+}
+
+// Vertex v's position after the folded colours: the last one, and, with
+// prev_edge, the one before it.  p is not written during the projection, so
+// v's update of an edge and its partner's agree.  With two colours v needs
+// its own and its last-colour partner's positions after the earlier colour;
+// both come out of the same instructions (a loop that is not unrolled), so
+// that v and the partner, each computing both, use the same values.
+__device__ __forceinline__ void folded_position(const ProjectArgs& a, int v, float pv[3], bool write_lambda) {
+    const int2 m = a.sl.last_edge[v];
+    const int b = m.y >= 0 ? m.y : v;
+    float q0[3], q1[3];
+    if (a.sl.prev_edge) {
+#pragma unroll 1
+        for (int r = 0; r < 2; ++r) {
+            const int x = r == 0 ? v : b;
+            const int2 mp = a.sl.prev_edge[x];
+            float px[3], po[3], out[3];
+            for (int k = 0; k < 3; ++k) {
+                px[k] = a.p[3 * x + k];
+                po[k] = a.p[3 * (mp.y >= 0 ? mp.y : x) + k];
+            }
+            edge_side(a, mp, x, px, po, out, write_lambda && r == 0);
+            for (int k = 0; k < 3; ++k) {
+                if (r == 0) q0[k] = out[k];
+                else q1[k] = out[k];
+            }
+        }
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            q0[k] = a.p[3 * v + k];
+            q1[k] = a.p[3 * b + k];
+        }
+    }
+    edge_side(a, m, v, q0, q1, pv, write_lambda);
 }
 
 __device__ __forceinline__ d3 load_prop(const ProjectArgs& a, int v) {
