@@ -228,8 +228,10 @@ int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, 
  *     counts for CSR regions)
  *   3 region fill (CSR regions: offset scan and half-space scatter; inside a
  *     substep with per-vertex slots: the slot fill)
- *   4 stretch pass (the iteration's closing kernel, which also copies the
- *     prediction and runs the first colour, then the other colours)
+ *   4 stretch pass (the iteration's closing kernel and the colours launched
+ *     on their own; with per-vertex slots the reset of p and the first colour
+ *     run in the previous projection, the next three colours inside stages 2,
+ *     3 and this one, and the last two inside stage 5)
  *   5 projection
  * Disabling profiling returns to the recorded graph. */
 int ccfr_profile_enable(ccfr_ctx* ctx, int enable);
