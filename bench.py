@@ -80,8 +80,8 @@ def kernel_bytes(kernel, N, T, E, F, P, C, H):
         # for CSR regions also the per-vertex counts (4 B/hs; inside a substep the
         # slot fill counts them instead)
         if os.environ.get("CCFR_CSR_IN_STEP") == "1":
-            return 8 * P + 16 * N + 12 * T + 8 * E + 32 * C + 4 * H
-        return 8 * P + 16 * N + 12 * T + 8 * E + 32 * C
+            return 8 * P + 16 * N + 12 * T + 8 * E + 48 * C + 4 * H
+        return 8 * P + 16 * N + 12 * T + 8 * E + 48 * C
     if kernel == "projection":
         # offsets (4), proposal and anchor (24), w (4), anchor written (12) per
         # vertex; half-spaces read (32 B)

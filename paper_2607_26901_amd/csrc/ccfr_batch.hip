@@ -332,10 +332,10 @@ int64_t ccfr_batch_footprint(int32_t n_verts, int32_t n_tris, int32_t n_edges) {
     // per binned primitive or vertex) and at most 8 bucket counters and 8
     // offsets (4 B each) per entry,
     // 8 B per candidate pair slot,
-    // 32 B per contact slot (half the pair slots) and 44 B per half-space slot
+    // 48 B per contact slot (half the pair slots) and 44 B per half-space slot
     // (twice the pair slots: record, sort key, sort index)
     const long long pairs = 8 * N + 8 * E + 16 * F;
-    bytes += 48 * N + 168 * (T + E + F + N) + 8 * pairs + 32 * (pairs / 2) + 44 * (2 * pairs);
+    bytes += 48 * N + 168 * (T + E + F + N) + 8 * pairs + 48 * (pairs / 2) + 44 * (2 * pairs);
     return bytes;
 }
 

@@ -161,12 +161,15 @@ struct GridEntry {
 
 // A pair inside the interaction range, between the two passes of the region
 // build: normal (side A away from side B), phi, side A's share, the pair.
-struct Contact {
+struct alignas(16) Contact {
     float n[3];
     float phi;
     float dA, dB;      // d = s phi of side A and of side B
     int32_t a;         // kind << 30 | first primitive
     int32_t b;         // second primitive
+    // the vertices that receive a half-space, side A first (one for a vertex or
+    // particle, two for an edge), then side B; -1 for a static vertex or none
+    int32_t rv[4];
 };
 
 struct ParamSrc {

@@ -273,6 +273,19 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Scene sc, const int32_t* vf
             else { const long long j = i - nvf - nee; kind = KIND_VV; pa = vv[2 * j]; pb = vv[2 * j + 1]; }
             bool deg;
             keep = eval_pair<R>(sc, kind, pa, pb, &rec, &pv, &deg);
+            if (keep) {
+                // the receiving vertices, so that the fill reads no topology or masses
+                const int a1 = kind == KIND_EE ? pv.a[1] : pv.b[0];
+                const float wa1 = kind == KIND_EE ? pv.wa[1] : pv.wb[0];
+                const int b0 = kind == KIND_EE ? pv.b[0] : pv.b[1];
+                const float wb0 = kind == KIND_EE ? pv.wb[0] : pv.wb[1];
+                const int b1 = kind == KIND_EE ? pv.b[1] : pv.b[2];
+                const float wb1 = kind == KIND_EE ? pv.wb[1] : pv.wb[2];
+                rec.rv[0] = pv.wa[0] > 0.f ? pv.a[0] : -1;
+                rec.rv[1] = wa1 > 0.f ? a1 : -1;
+                rec.rv[2] = kind != KIND_VV && wb0 > 0.f ? b0 : -1;
+                rec.rv[3] = kind != KIND_VV && wb1 > 0.f ? b1 : -1;
+            }
             n_degenerate += deg ? 1 : 0;
             if (keep && vcount) {
                 for (int k = 0; k < pv.nA; ++k)
@@ -306,35 +319,23 @@ __global__ __launch_bounds__(kBlock) void k_fill_slots(Scene sc, const Contact* 
         const Contact rec = contacts[i];
         const int kind = (int)((uint32_t)rec.a >> 30);
         const int pa = rec.a & 0x3fffffff, pb = rec.b;
-        int rv[5] = {-1, -1, -1, -1, -1};
-        if (kind == KIND_VF) {
-            rv[0] = pa;
-            rv[2] = sc.tris[3 * pb]; rv[3] = sc.tris[3 * pb + 1]; rv[4] = sc.tris[3 * pb + 2];
-        } else if (kind == KIND_EE) {
-            rv[0] = sc.edges[2 * pa]; rv[1] = sc.edges[2 * pa + 1];
-            rv[2] = sc.edges[2 * pb]; rv[3] = sc.edges[2 * pb + 1];
-        } else {
-            rv[0] = pa; rv[2] = pb;
-        }
-        bool dyn[5];
+        const int nA = kind == KIND_EE ? 2 : 1;     // receiving vertices of side A come first
+        int slot[4];
 #pragma unroll
-        for (int k = 0; k < 5; ++k) dyn[k] = rv[k] >= 0 && sc.inv_mass[rv[k] >= 0 ? rv[k] : 0] > 0.f;
-        int slot[5];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) slot[k] = dyn[k] ? atomicAdd(&counts[rv[k]], 1) : 0;
+        for (int k = 0; k < 4; ++k) slot[k] = rec.rv[k] >= 0 ? atomicAdd(&counts[rec.rv[k]], 1) : 0;
         ccfr_halfspace h;
         h.phi = rec.phi;
         h.flags = 0u;
         h.key = ((uint64_t)kind << 62) | ((uint64_t)(uint32_t)pa << 31) | (uint64_t)(uint32_t)pb;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            if (!dyn[k]) continue;
-            const float sg = k < 2 ? 1.0f : -1.0f;
+        for (int k = 0; k < 4; ++k) {
+            if (rec.rv[k] < 0) continue;
+            const float sg = k < nA ? 1.0f : -1.0f;
             h.n[0] = sg * rec.n[0]; h.n[1] = sg * rec.n[1]; h.n[2] = sg * rec.n[2];
-            h.d = k < 2 ? rec.dA : rec.dB;
+            h.d = k < nA ? rec.dA : rec.dB;
             top = max(top, slot[k] + 1);
             if (slot[k] < stride) {
-                hs[(long long)rv[k] * stride + slot[k]] = h;
+                hs[(long long)rec.rv[k] * stride + slot[k]] = h;
                 ++n_hs;
             }
         }
@@ -370,36 +371,18 @@ __global__ __launch_bounds__(kBlock) void k_fill(Scene sc, const Contact* contac
         const Contact rec = contacts[i];
         const int kind = (int)((uint32_t)rec.a >> 30);
         const int pa = rec.a & 0x3fffffff, pb = rec.b;
-        int va[2], vb[3], nA, nB;
-        if (kind == KIND_VF) {
-            nA = 1; va[0] = pa;
-            nB = 3; vb[0] = sc.tris[3 * pb]; vb[1] = sc.tris[3 * pb + 1]; vb[2] = sc.tris[3 * pb + 2];
-        } else if (kind == KIND_EE) {
-            nA = 2; va[0] = sc.edges[2 * pa]; va[1] = sc.edges[2 * pa + 1];
-            nB = 2; vb[0] = sc.edges[2 * pb]; vb[1] = sc.edges[2 * pb + 1];
-        } else {
-            nA = 1; va[0] = pa;
-            nB = 1; vb[0] = pb;
-        }
-        const uint64_t key = ((uint64_t)kind << 62) | ((uint64_t)(uint32_t)pa << 31) | (uint64_t)(uint32_t)pb;
+        const int nA = kind == KIND_EE ? 2 : 1;     // receiving vertices of side A come first
         ccfr_halfspace h;
         h.phi = rec.phi;
         h.flags = 0u;
-        h.key = key;
-        for (int k = 0; k < nA; ++k) {
-            const int v = va[k];
-            if (!(sc.inv_mass[v] > 0.f)) continue;
+        h.key = ((uint64_t)kind << 62) | ((uint64_t)(uint32_t)pa << 31) | (uint64_t)(uint32_t)pb;
+        for (int k = 0; k < 4; ++k) {
+            const int v = rec.rv[k];
+            if (v < 0) continue;
+            const float sg = k < nA ? 1.0f : -1.0f;
             const long long pos = (long long)offsets[v] + atomicSub(&vcount[v], 1) - 1;
-            h.n[0] = rec.n[0]; h.n[1] = rec.n[1]; h.n[2] = rec.n[2];
-            h.d = rec.dA;
-            if (pos < cap_hs) hs[pos] = h;
-        }
-        for (int k = 0; k < nB; ++k) {
-            const int v = vb[k];
-            if (!(sc.inv_mass[v] > 0.f)) continue;
-            const long long pos = (long long)offsets[v] + atomicSub(&vcount[v], 1) - 1;
-            h.n[0] = -rec.n[0]; h.n[1] = -rec.n[1]; h.n[2] = -rec.n[2];
-            h.d = rec.dB;
+            h.n[0] = sg * rec.n[0]; h.n[1] = sg * rec.n[1]; h.n[2] = sg * rec.n[2];
+            h.d = k < nA ? rec.dA : rec.dB;
             if (pos < cap_hs) hs[pos] = h;
         }
     }
