@@ -238,7 +238,7 @@ __device__ bool eval_pair(const Scene& sc, int kind, int pa, int pb, Contact* re
 }
 
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_contacts(Scene sc, const int32_t* vf, const int32_t* ee,
+__global__ __launch_bounds__(kBlock, 5) void k_contacts(Scene sc, const int32_t* vf, const int32_t* ee,
                                                      const int32_t* vv, const int32_t* counts,
                                                      int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
                                                      Contact* contacts, int64_t cap_contacts,
