@@ -72,11 +72,17 @@ def load():
         lib.orc_closest_points_segments.argtypes = [vp] * 6
         lib.orc_color_edges.restype = i32
         lib.orc_color_edges.argtypes = [i32, i32, vp, vp]
-        lib.orc_xpbd_step.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
+        lib.orc_xpbd_step.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
         lib.orc_count_edge_tri_intersections.restype = i64
         lib.orc_count_edge_tri_intersections.argtypes = [i32, vp, i32, vp, i32, vp]
         lib.orc_min_separation.restype = dbl
         lib.orc_min_separation.argtypes = [i32, vp, vp, i32, vp, i32, vp, dbl, dbl, vp]
+        lib.orc_motion_check.restype = dbl
+        lib.orc_motion_check.argtypes = [i32, vp, vp, vp, i32, vp, i32, vp, dbl, dbl, i64, vp, vp, vp]
+        lib.orc_orient3d_sign.restype = C.c_int
+        lib.orc_orient3d_sign.argtypes = [vp] * 4
+        lib.orc_orient2d_sign.restype = C.c_int
+        lib.orc_orient2d_sign.argtypes = [vp] * 3
         lib.orc_num_threads.restype = C.c_int
         lib.orc_fragile_reasons.argtypes = [vp, C.c_int]
         _lib = lib
@@ -291,17 +297,21 @@ class Sim:
         self.color, self.n_colors = color_edges(len(self.x), self.edges)
         self.counters = np.zeros(8, np.int64)
 
-    def step(self, iters=None):
+    def step(self, iters=None, trace=False):
+        """One substep; with trace=True returns the anchor after every iteration
+        ([iters][N][3])."""
         sp = self.scene.step
         osp = OrcStepParams(float(np.float32(sp.dt)), (C.c_double * 3)(*[float(np.float32(g)) for g in sp.gravity]),
                             int(sp.iters if iters is None else iters), self.n_colors,
                             float(np.float32(sp.alpha)))
         prm = params(self.scene.params)
+        tr = np.zeros((osp.iters, len(self.x), 3)) if trace else None
         load().orc_xpbd_step(len(self.x), len(self.tris), len(self.edges), _p(self.tris),
                              _p(self.edges), _p(self.w), _p(self.rest),
                              _p(self.color if len(self.color) else np.zeros(1, np.int32)),
                              self.n_colors, _p(self.x), _p(self.v), C.byref(prm), C.byref(osp),
-                             _p(self.counters))
+                             _p(self.counters), None if tr is None else _p(tr))
+        return tr
 
 
 def count_intersections(x, tris, edges) -> int:
@@ -322,6 +332,33 @@ def min_separation(x, inv_mass, tris, edges, reach, below):
     d = load().orc_min_separation(len(x), _p(x), _p(w), len(tris), _p(tris), len(edges), _p(edges),
                                   float(reach), float(below), _p(cnt))
     return float(d), cnt
+
+
+def motion_check(x0, x1, inv_mass, tris, edges, floor, reach, max_samples=10000):
+    """Certified sampled check of the straight-line motion x0 -> x1.  Returns
+    (smallest sampled distance, certified, samples, t of the smallest)."""
+    x0 = np.ascontiguousarray(x0, np.float64)
+    x1 = np.ascontiguousarray(x1, np.float64)
+    w = np.ascontiguousarray(inv_mass, np.float64)
+    tris = np.ascontiguousarray(tris, np.int32)
+    edges = np.ascontiguousarray(edges, np.int32)
+    cert = C.c_int32(0)
+    ns = C.c_int64(0)
+    tm = C.c_double(0)
+    d = load().orc_motion_check(len(x0), _p(x0), _p(x1), _p(w), len(tris), _p(tris), len(edges), _p(edges),
+                                float(floor), float(reach), int(max_samples), C.byref(cert), C.byref(ns),
+                                C.byref(tm))
+    return float(d), bool(cert.value), int(ns.value), float(tm.value)
+
+
+def orient3d_sign(a, b, c, d) -> int:
+    arr = [np.ascontiguousarray(v, np.float64) for v in (a, b, c, d)]
+    return int(load().orc_orient3d_sign(*[_p(v) for v in arr]))
+
+
+def orient2d_sign(a, b, c) -> int:
+    arr = [np.ascontiguousarray(v, np.float64) for v in (a, b, c)]
+    return int(load().orc_orient2d_sign(*[_p(v) for v in arr]))
 
 
 def num_threads() -> int:

@@ -142,16 +142,24 @@ int32_t orc_color_edges(int32_t n_verts, int32_t n_edges, const int32_t* edges, 
 /* One substep in place on x, v ([N][3], FP64).  rest_len [E].  color [E].
  * counters (nullable, summed over iterations): [0] VF, [1] EE, [2] VV candidates,
  * [3] half-spaces, [4] violating vertices, [5] halted vertices, [6] fragile
- * vertices, [7] degenerate pairs. */
+ * vertices, [7] degenerate pairs.  trace (nullable, [iters][N][3]) receives the
+ * anchor after every iteration. */
 void orc_xpbd_step(int32_t n_verts, int32_t n_tris, int32_t n_edges,
                    const int32_t* tris, const int32_t* edges, const double* inv_mass,
                    const double* rest_len, const int32_t* color, int32_t n_colors,
                    double* x, double* v, const orc_params* prm, const orc_step_params* sp,
-                   int64_t counters[8]);
+                   int64_t counters[8], double* trace);
 
 /* ---- checks (independent of the routines above) ---- */
-/* Number of (edge, triangle) pairs sharing no vertex whose segment meets the
- * triangle: any such pair means two triangles interpenetrate. */
+/* Exact signs of orientation determinants (Shewchuk's floating-point filter
+ * with an exact expansion-arithmetic fallback): orient3d is the sign of
+ * (b - a) . ((c - a) x (d - a)), orient2d of the 2-D (b - a) x (c - a). */
+int orc_orient3d_sign(const double* a, const double* b, const double* c, const double* d);
+int orc_orient2d_sign(const double* a, const double* b, const double* c);
+/* Number of (edge, triangle) pairs sharing no vertex whose closed segment meets
+ * the closed triangle, decided with the exact predicates (a coplanar segment
+ * that touches the triangle counts; a triangle of zero area is skipped): any
+ * such pair means two triangles interpenetrate or touch. */
 int64_t orc_count_edge_tri_intersections(int32_t n_verts, const double* x, int32_t n_tris,
                                          const int32_t* tris, int32_t n_edges,
                                          const int32_t* edges);
@@ -162,6 +170,16 @@ int64_t orc_count_edge_tri_intersections(int32_t n_verts, const double* x, int32
 double orc_min_separation(int32_t n_verts, const double* x, const double* inv_mass, int32_t n_tris,
                           const int32_t* tris, int32_t n_edges, const int32_t* edges, double reach,
                           double below, int64_t out_counts[3]);
+
+/* Certified sampled check of the straight-line motion from x0 to x1 (one
+ * iteration's anchor update): conservative advancement in t with the Lipschitz
+ * bound 2 max |x1 - x0| of every pair distance.  Returns the smallest sampled
+ * minimum distance (capped at reach); *certified = 1 when every distance stays
+ * above floor_dist along the whole motion. */
+double orc_motion_check(int32_t n_verts, const double* x0, const double* x1, const double* inv_mass,
+                        int32_t n_tris, const int32_t* tris, int32_t n_edges, const int32_t* edges,
+                        double floor_dist, double reach, int64_t max_samples, int32_t* certified,
+                        int64_t* n_samples, double* t_min);
 
 int orc_num_threads(void);
 

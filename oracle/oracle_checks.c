@@ -84,26 +84,181 @@ static double seg_seg2(const double* a, const double* b, const double* c, const 
     return best;
 }
 
-static double orient(const double* a, const double* b, const double* c, const double* d) {
-    double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
-    double v[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
-    double w[3] = {d[0] - a[0], d[1] - a[1], d[2] - a[2]};
-    return u[0] * (v[1] * w[2] - v[2] * w[1]) - u[1] * (v[0] * w[2] - v[2] * w[0]) +
-           u[2] * (v[0] * w[1] - v[1] * w[0]);
+/* ---- exact orientation predicates ----
+ *
+ * The sign of a 3x3 (2x2) orientation determinant decides the intersection
+ * tests below, so it is computed exactly: a floating-point evaluation with a
+ * static error bound first, and where that bound cannot certify the sign, an
+ * exact evaluation in floating-point expansion arithmetic.  Both are the
+ * published method of J. R. Shewchuk, "Adaptive Precision Floating-Point
+ * Arithmetic and Fast Robust Geometric Predicates" (Discrete Comput. Geom. 18,
+ * 1997): exact sums (Two-Sum), exact products (here through a fused
+ * multiply-add), nonoverlapping expansions grown one component at a time
+ * (Grow-Expansion), and the first error bound of his orient3d.  The exact
+ * stage here does not use his adaptive intermediate stages: it expands the
+ * 4x4 (3x3) determinant with a column of ones into its 24 (6) signed products
+ * of coordinates, each of which is an exact expansion of four (two) doubles,
+ * and sums them exactly.  Inputs are assumed free of overflow and of underflow
+ * in the products (coordinates of metres, far from both limits). */
+
+static void two_sum(double a, double b, double* x, double* y) {
+    double s = a + b;
+    double bv = s - a;
+    double av = s - bv;
+    *x = s;
+    *y = (a - av) + (b - bv);
 }
 
-static int seg_hits_tri(const double* p0, const double* p1, const double* a, const double* b, const double* c) {
-    double o0 = orient(a, b, c, p0), o1 = orient(a, b, c, p1);
-    if ((o0 > 0 && o1 > 0) || (o0 < 0 && o1 < 0)) return 0;
-    if (o0 == 0 && o1 == 0) {   /* coplanar: touching iff some distance is zero */
-        if (pt_tri2(p0, a, b, c) == 0 || pt_tri2(p1, a, b, c) == 0) return 1;
-        return seg_seg2(p0, p1, a, b) == 0 || seg_seg2(p0, p1, b, c) == 0 || seg_seg2(p0, p1, c, a) == 0;
+static void two_prod(double a, double b, double* x, double* y) {
+    double p = a * b;
+    *x = p;
+    *y = fma(a, b, -p);
+}
+
+/* h = e + b for a nonoverlapping expansion e[0..m) in increasing magnitude;
+ * h has m + 1 components and is nonoverlapping too. */
+static int grow(const double* e, int m, double b, double* h) {
+    double q = b;
+    for (int i = 0; i < m; ++i) {
+        double qn, hi;
+        two_sum(q, e[i], &qn, &hi);
+        h[i] = hi;
+        q = qn;
     }
-    double s1 = orient(p0, p1, a, b), s2 = orient(p0, p1, b, c), s3 = orient(p0, p1, c, a);
+    h[m] = q;
+    return m + 1;
+}
+
+/* sign of a nonoverlapping expansion: that of its largest nonzero component */
+static int expansion_sign(const double* e, int m) {
+    for (int i = m - 1; i >= 0; --i)
+        if (e[i] != 0.0) return e[i] > 0.0 ? 1 : -1;
+    return 0;
+}
+
+/* exact sign of det [[p_i, 1]] for k + 1 points p_i of dimension k (k = 2, 3) */
+static int det_ones_sign(const double* const* p, int k) {
+    static const int perm3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    static const int par3[6] = {0, 1, 1, 0, 0, 1};
+    double acc[2][100];
+    int cur = 0, m = 0;
+    /* det = sum over the row o holding the 1 and the bijection of the other
+     * rows onto the coordinate columns; the permutation's sign is the parity of
+     * the column order times (-1)^(o + k) */
+    for (int o = 0; o <= k; ++o) {
+        int rows[3], nr = 0;
+        for (int i = 0; i <= k; ++i)
+            if (i != o) rows[nr++] = i;
+        const int sign_o = ((o + k) & 1) ? -1 : 1;
+        if (k == 2) {
+            for (int q = 0; q < 2; ++q) {
+                int c0 = q, c1 = 1 - q;
+                int sg = sign_o * (q ? -1 : 1);
+                double hi, lo;
+                two_prod(p[rows[0]][c0], p[rows[1]][c1], &hi, &lo);
+                double t[2] = {sg * lo, sg * hi};
+                for (int j = 0; j < 2; ++j) {
+                    m = grow(acc[cur], m, t[j], acc[1 - cur]);
+                    cur = 1 - cur;
+                }
+            }
+        } else {
+            for (int q = 0; q < 6; ++q) {
+                int sg = sign_o * (par3[q] ? -1 : 1);
+                double a = p[rows[0]][perm3[q][0]], b = p[rows[1]][perm3[q][1]], c = p[rows[2]][perm3[q][2]];
+                double h, l, h1, l1, h2, l2;
+                two_prod(a, b, &h, &l);      /* a b = h + l exactly         */
+                two_prod(h, c, &h1, &l1);    /* h c = h1 + l1               */
+                two_prod(l, c, &h2, &l2);    /* l c = h2 + l2               */
+                double t[4] = {sg * l2, sg * l1, sg * h2, sg * h1};
+                for (int j = 0; j < 4; ++j) {
+                    m = grow(acc[cur], m, t[j], acc[1 - cur]);
+                    cur = 1 - cur;
+                }
+            }
+        }
+    }
+    return expansion_sign(acc[cur], m);
+}
+
+/* sign of (b - a) . ((c - a) x (d - a)): positive when d lies on the side of
+ * plane abc that the right-hand normal (b - a) x (c - a) points to */
+int orc_orient3d_sign(const double* a, const double* b, const double* c, const double* d) {
+    const double eps = ldexp(1.0, -53);
+    const double errA = (7.0 + 56.0 * eps) * eps;
+    /* Shewchuk's orient3d first stage, in his form with d as the origin */
+    double adx = a[0] - d[0], bdx = b[0] - d[0], cdx = c[0] - d[0];
+    double ady = a[1] - d[1], bdy = b[1] - d[1], cdy = c[1] - d[1];
+    double adz = a[2] - d[2], bdz = b[2] - d[2], cdz = c[2] - d[2];
+    double bdxcdy = bdx * cdy, cdxbdy = cdx * bdy;
+    double cdxady = cdx * ady, adxcdy = adx * cdy;
+    double adxbdy = adx * bdy, bdxady = bdx * ady;
+    double det = adz * (bdxcdy - cdxbdy) + bdz * (cdxady - adxcdy) + cdz * (adxbdy - bdxady);
+    double perm = (fabs(bdxcdy) + fabs(cdxbdy)) * fabs(adz) + (fabs(cdxady) + fabs(adxcdy)) * fabs(bdz) +
+                  (fabs(adxbdy) + fabs(bdxady)) * fabs(cdz);
+    /* det here is det[a-d; b-d; c-d] = det[[a,1];[b,1];[c,1];[d,1]], which is
+     * minus the triple product (b - a) . ((c - a) x (d - a)) */
+    if (det > errA * perm) return -1;
+    if (-det > errA * perm) return 1;
+    const double* pts[4] = {a, b, c, d};
+    return -det_ones_sign(pts, 3);
+}
+
+/* sign of the 2-D cross product (b - a) x (c - a) of 2-vectors, exact */
+int orc_orient2d_sign(const double* a, const double* b, const double* c) {
+    const double* pts[3] = {a, b, c};
+    return det_ones_sign(pts, 2);
+}
+
+/* closed segments pq and rs in the plane meet (exact) */
+static int seg_seg_2d(const double* p, const double* q, const double* r, const double* s) {
+    int d1 = orc_orient2d_sign(r, s, p), d2 = orc_orient2d_sign(r, s, q);
+    int d3 = orc_orient2d_sign(p, q, r), d4 = orc_orient2d_sign(p, q, s);
+    if (d1 * d2 < 0 && d3 * d4 < 0) return 1;
+#define ON_SEG(u, v, w) (fmin(u[0], v[0]) <= w[0] && w[0] <= fmax(u[0], v[0]) && \
+                         fmin(u[1], v[1]) <= w[1] && w[1] <= fmax(u[1], v[1]))
+    if (d1 == 0 && ON_SEG(r, s, p)) return 1;
+    if (d2 == 0 && ON_SEG(r, s, q)) return 1;
+    if (d3 == 0 && ON_SEG(p, q, r)) return 1;
+    if (d4 == 0 && ON_SEG(p, q, s)) return 1;
+#undef ON_SEG
+    return 0;
+}
+
+/* closed triangle abc (non-degenerate) contains p, in the plane (exact) */
+static int tri_has_2d(const double* a, const double* b, const double* c, const double* p) {
+    int s1 = orc_orient2d_sign(a, b, p), s2 = orc_orient2d_sign(b, c, p), s3 = orc_orient2d_sign(c, a, p);
     return (s1 >= 0 && s2 >= 0 && s3 >= 0) || (s1 <= 0 && s2 <= 0 && s3 <= 0);
 }
 
-typedef struct { double lo[3], hi[3]; int32_t kind, id; } item_t;
+/* A segment lying in the plane of triangle abc: drop one coordinate axis along
+ * which the projected triangle keeps a non-zero area (incidence is preserved by
+ * such a projection) and test in 2-D.  A triangle of zero area is skipped. */
+static int coplanar_hit(const double* p0, const double* p1, const double* a, const double* b, const double* c) {
+    for (int drop = 2; drop >= 0; --drop) {
+        const int i = drop == 0 ? 1 : 0, j = drop == 2 ? 1 : 2;
+        double A[2] = {a[i], a[j]}, B[2] = {b[i], b[j]}, Cc[2] = {c[i], c[j]};
+        double P[2] = {p0[i], p0[j]}, Q[2] = {p1[i], p1[j]};
+        if (orc_orient2d_sign(A, B, Cc) == 0) continue;
+        if (tri_has_2d(A, B, Cc, P) || tri_has_2d(A, B, Cc, Q)) return 1;
+        return seg_seg_2d(P, Q, A, B) || seg_seg_2d(P, Q, B, Cc) || seg_seg_2d(P, Q, Cc, A);
+    }
+    return 0;
+}
+
+/* the closed segment p0 p1 meets the closed triangle abc */
+static int seg_hits_tri(const double* p0, const double* p1, const double* a, const double* b, const double* c) {
+    int o0 = orc_orient3d_sign(a, b, c, p0), o1 = orc_orient3d_sign(a, b, c, p1);
+    if (o0 * o1 > 0) return 0;
+    if (o0 == 0 && o1 == 0) return coplanar_hit(p0, p1, a, b, c);
+    /* the line p0 p1 crosses the plane inside the closed segment; it passes
+     * through the triangle iff it sees the three edges with one orientation */
+    int s1 = orc_orient3d_sign(p0, p1, a, b), s2 = orc_orient3d_sign(p0, p1, b, c),
+        s3 = orc_orient3d_sign(p0, p1, c, a);
+    return (s1 >= 0 && s2 >= 0 && s3 >= 0) || (s1 <= 0 && s2 <= 0 && s3 <= 0);
+}
+
+typedef struct { double lo[3], hi[3]; int32_t kind, id; int32_t stat, pad_; } item_t;
 
 static int cmp_lo(const void* a, const void* b) {
     double x = ((const item_t*)a)->lo[0], y = ((const item_t*)b)->lo[0];
@@ -124,6 +279,8 @@ static item_t make_item(const double* x, const int32_t* vids, int nv, double gro
     }
     it.kind = kind;
     it.id = id;
+    it.stat = 0;
+    it.pad_ = 0;
     return it;
 }
 
@@ -171,14 +328,14 @@ double orc_min_separation(int32_t n_verts, const double* x, const double* inv_ma
     for (int32_t v = 0; v < n_verts; ++v) it[v] = make_item(x, &v, 1, g, 0, v);
     for (int32_t t = 0; t < n_tris; ++t) it[n_verts + t] = make_item(x, tris + 3 * t, 3, g, 1, t);
     for (int32_t e = 0; e < n_edges; ++e) it[n_verts + n_tris + e] = make_item(x, edges + 2 * e, 2, g, 2, e);
-    /* static[k]: every vertex of item k has zero inverse mass (such pairs never move) */
-    unsigned char* st = (unsigned char*)malloc((size_t)n + 1);
+    /* stat: every vertex of the item has zero inverse mass (two such items
+     * never move relative to each other); set before the sort reorders items */
     for (int64_t k = 0; k < n; ++k) {
         const int32_t* vs = it[k].kind == 0 ? &it[k].id : (it[k].kind == 1 ? tris + 3 * it[k].id : edges + 2 * it[k].id);
         int nv = it[k].kind == 0 ? 1 : (it[k].kind == 1 ? 3 : 2);
         int s = 1;
         for (int q = 0; q < nv; ++q) s &= (inv_mass == NULL ? 0 : inv_mass[vs[q]] == 0.0);
-        st[k] = (unsigned char)s;
+        it[k].stat = s;
     }
     qsort(it, (size_t)n, sizeof(item_t), cmp_lo);
     double best2 = reach * reach;
@@ -189,7 +346,7 @@ double orc_min_separation(int32_t n_verts, const double* x, const double* inv_ma
         for (int64_t j = i + 1; j < n && it[j].lo[0] <= it[i].hi[0]; ++j) {
             if (it[j].lo[1] > it[i].hi[1] || it[i].lo[1] > it[j].hi[1]) continue;
             if (it[j].lo[2] > it[i].hi[2] || it[i].lo[2] > it[j].hi[2]) continue;
-            if (st[i] && st[j]) continue;
+            if (it[i].stat && it[j].stat) continue;
             int ki = it[i].kind, kj = it[j].kind;
             double dist2 = -1.0;
             int kind = -1;
@@ -226,6 +383,51 @@ double orc_min_separation(int32_t n_verts, const double* x, const double* inv_ma
     if (out_counts) { out_counts[0] = c0; out_counts[1] = c1; out_counts[2] = c2; }
     free(it);
     free(fr);
-    free(st);
     return sqrt(best2);
+}
+
+/* Certified sampled check of a straight-line motion x(t) = (1 - t) x0 + t x1,
+ * t in [0, 1] (one solver iteration moves every vertex along such a line: the
+ * anchor update of Alg. 4).  The distance between a vertex and a triangle, two
+ * edges or two particles whose vertices move linearly changes with t at a rate
+ * of at most L = 2 max_v |x1_v - x0_v|, since each closest point is a convex
+ * combination of vertices that move at most that far.  So from a sample at t
+ * with minimum distance d > floor, no pair can come closer than floor before
+ * t + (d - floor) / L: the samples advance by exactly that step (conservative
+ * advancement), and reaching t = 1 certifies that the minimum distance stays
+ * above `floor` along the whole motion.  Returns the smallest sampled minimum
+ * distance (capped at `reach`); *certified = 1 if t = 1 was reached, 0 if a
+ * sample came to `floor` or below, or if more than max_samples were needed.
+ * *n_samples receives the samples taken, *t_min the time of the smallest. */
+double orc_motion_check(int32_t n_verts, const double* x0, const double* x1, const double* inv_mass,
+                        int32_t n_tris, const int32_t* tris, int32_t n_edges, const int32_t* edges,
+                        double floor_dist, double reach, int64_t max_samples, int32_t* certified,
+                        int64_t* n_samples, double* t_min) {
+    double L = 0.0;
+    for (int32_t v = 0; v < n_verts; ++v) {
+        double d[3] = {x1[3 * v] - x0[3 * v], x1[3 * v + 1] - x0[3 * v + 1], x1[3 * v + 2] - x0[3 * v + 2]};
+        double m = sqrt(d3(d, d));
+        if (m > L) L = m;
+    }
+    L *= 2.0;
+    double* xt = (double*)malloc(sizeof(double) * (3 * (size_t)n_verts + 1));
+    double t = 0.0, best = reach, tbest = 0.0;
+    int64_t ns = 0;
+    int ok = 0;
+    while (ns < max_samples) {
+        for (size_t k = 0; k < 3 * (size_t)n_verts; ++k) xt[k] = (1.0 - t) * x0[k] + t * x1[k];
+        double d = orc_min_separation(n_verts, xt, inv_mass, n_tris, tris, n_edges, edges, reach, 0.0, NULL);
+        ++ns;
+        if (d < best) { best = d; tbest = t; }
+        if (!(d > floor_dist)) break;
+        if (t >= 1.0) { ok = 1; break; }
+        if (L == 0.0) { ok = 1; break; }
+        t += (d - floor_dist) / L;
+        if (t > 1.0) t = 1.0;
+    }
+    free(xt);
+    if (certified) *certified = ok;
+    if (n_samples) *n_samples = ns;
+    if (t_min) *t_min = tbest;
+    return best;
 }

@@ -89,7 +89,7 @@ void orc_xpbd_step(int32_t n_verts, int32_t n_tris, int32_t n_edges,
                    const int32_t* tris, const int32_t* edges, const double* inv_mass,
                    const double* rest_len, const int32_t* color, int32_t n_colors,
                    double* x, double* v, const orc_params* prm, const orc_step_params* sp,
-                   int64_t counters[8]) {
+                   int64_t counters[8], double* trace) {
     const size_t N3 = 3 * (size_t)n_verts;
     double* x_old = (double*)malloc(sizeof(double) * N3);
     double* xt = (double*)malloc(sizeof(double) * N3);
@@ -128,6 +128,7 @@ void orc_xpbd_step(int32_t n_verts, int32_t n_tris, int32_t n_edges,
         int64_t pstats[4];
         orc_project(&m, prm, offsets, hs, y, ys, NULL, NULL, pstats);
         for (size_t k = 0; k < N3; ++k) x[k] += ys[k];
+        if (trace) memcpy(trace + (size_t)it * N3, x, sizeof(double) * N3);
         if (counters) {
             counters[0] += cnt[0]; counters[1] += cnt[1]; counters[2] += cnt[2];
             counters[3] += H; counters[4] += pstats[0]; counters[5] += pstats[1];

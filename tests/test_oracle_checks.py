@@ -1,0 +1,199 @@
+"""Pins of the oracle's independent checkers, the ground on which every
+"zero remaining violations" claim stands (Sec. 4.3: no remaining violation at
+the end of every frame).
+
+Each checker must find violations constructed on purpose: an edge through a
+triangle (interior, through a triangle edge, coplanar crossing and coplanar
+touching), vertex-face, edge-edge and particle-particle pairs closer than xi
+with static geometry present, and motions that pass through a triangle
+between two separated end states.  The orientation predicates must agree with
+exact rational arithmetic (Python's fractions) on near-degenerate inputs where
+a plain FP64 determinant gets the sign wrong."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+
+def _orient3d_fraction(a, b, c, d):
+    a, b, c, d = ([Fraction(float(t)) for t in p] for p in (a, b, c, d))
+    u = [b[k] - a[k] for k in range(3)]
+    v = [c[k] - a[k] for k in range(3)]
+    w = [d[k] - a[k] for k in range(3)]
+    det = (u[0] * (v[1] * w[2] - v[2] * w[1]) - u[1] * (v[0] * w[2] - v[2] * w[0])
+           + u[2] * (v[0] * w[1] - v[1] * w[0]))
+    return (det > 0) - (det < 0)
+
+
+def _orient2d_fraction(a, b, c):
+    a, b, c = ([Fraction(float(t)) for t in p] for p in (a, b, c))
+    det = (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0])
+    return (det > 0) - (det < 0)
+
+
+def _orient3d_naive(a, b, c, d):
+    u, v, w = b - a, c - a, d - a
+    det = np.dot(u, np.cross(v, w))
+    return int(np.sign(det))
+
+
+def test_orient3d_exact_on_near_degenerate_inputs(orc):
+    """Points on (or within rounding of) a common plane, far from the origin:
+    the exact sign equals the rational one, including where FP64 fails."""
+    rng = np.random.default_rng(5)
+    naive_wrong = 0
+    n = 0
+    for trial in range(3000):
+        off = rng.uniform(-1, 1, 3) * 10.0 ** rng.integers(0, 9)
+        a, b, c = off + rng.uniform(-1, 1, (3, 3))
+        s, t = rng.uniform(-2, 2, 2)
+        d = a + s * (b - a) + t * (c - a)              # on the plane up to rounding
+        if trial % 3 == 0:
+            d = d + rng.normal(0, 1e-14) * np.cross(b - a, c - a)
+        exact = _orient3d_fraction(a, b, c, d)
+        got = orc.orient3d_sign(a, b, c, d)
+        assert got == exact, (trial, a, b, c, d, got, exact)
+        naive_wrong += _orient3d_naive(a, b, c, d) != exact
+        n += 1
+    # the inputs are hard enough that a plain determinant is not a pin
+    assert naive_wrong > 20, naive_wrong
+    # exactly coplanar integer points give zero; the sign follows the handedness
+    z = np.zeros(3)
+    ex, ey, ez = np.eye(3)
+    assert orc.orient3d_sign(z, ex, ey, 2 * ex + 3 * ey) == 0
+    assert orc.orient3d_sign(z, ex, ey, ez) == 1
+    assert orc.orient3d_sign(z, ey, ex, ez) == -1
+
+
+def test_orient2d_exact_on_near_degenerate_inputs(orc):
+    rng = np.random.default_rng(6)
+    for trial in range(3000):
+        off = rng.uniform(-1, 1, 2) * 10.0 ** rng.integers(0, 9)
+        a, b = off + rng.uniform(-1, 1, (2, 2))
+        c = a + rng.uniform(-3, 3) * (b - a)
+        assert orc.orient2d_sign(a, b, c) == _orient2d_fraction(a, b, c), trial
+    assert orc.orient2d_sign([0, 0], [1, 0], [0, 1]) == 1
+    assert orc.orient2d_sign([0, 0], [0, 1], [1, 0]) == -1
+
+
+TRI = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+
+
+def _tri_and_segment(p0, p1):
+    x = np.vstack([TRI, np.asarray(p0, float), np.asarray(p1, float)])
+    return x, np.array([[0, 1, 2]], np.int32), np.array([[3, 4]], np.int32)
+
+
+@pytest.mark.parametrize("p0,p1,hit", [
+    ((0.2, 0.2, -1.0), (0.2, 0.2, 1.0), 1),        # through the interior
+    ((0.5, 0.0, -1.0), (0.5, 0.0, 1.0), 1),        # through the midpoint of a triangle edge
+    ((0.0, 0.0, -1.0), (0.0, 0.0, 1.0), 1),        # through a triangle vertex
+    ((0.2, 0.2, 0.0), (0.2, 0.2, 1.0), 1),         # ends on the triangle
+    ((-0.2, 0.3, 0.0), (0.8, 0.3, 0.0), 1),        # coplanar, crossing the interior
+    ((1.0, 0.0, 0.0), (2.0, 0.0, 0.0), 1),         # coplanar, touching a vertex only
+    ((0.5, 0.5, 0.0), (1.0, 1.0, 0.0), 1),         # coplanar, touching the hypotenuse
+    ((0.6, 0.6, 0.0), (1.0, 1.0, 0.0), 0),         # coplanar, outside
+    ((0.2, 0.2, 1e-300), (0.2, 0.2, 1.0), 0),      # just above the plane
+    ((0.6, 0.6, -1.0), (0.6, 0.6, 1.0), 0),        # beside the triangle
+    ((0.2, 0.2, -1.0), (0.2, 0.2, -1e-12), 0),     # below it, not reaching
+])
+def test_edge_triangle_checker_finds_constructed_crossings(orc, p0, p1, hit):
+    x, tris, edges = _tri_and_segment(p0, p1)
+    assert orc.count_intersections(x, tris, edges) == hit
+
+
+def test_edge_triangle_checker_skips_adjacent_and_counts_each_pair(orc):
+    # two triangles piercing each other: each has one edge through the other
+    x = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0],
+                  [0.2, 0.2, -0.5], [0.2, 0.2, 0.5], [-0.5, 0.2, 0.0]], float)
+    tris = np.array([[0, 1, 2], [3, 4, 5]], np.int32)
+    edges = np.array([[0, 1], [0, 2], [1, 2], [3, 4], [3, 5], [4, 5]], np.int32)
+    assert orc.count_intersections(x, tris, edges) == 2
+    # an edge that shares a vertex with the triangle is incident, not a crossing
+    x2 = np.vstack([TRI, [[0.2, 0.2, 1.0]]])
+    assert orc.count_intersections(x2, np.array([[0, 1, 2]], np.int32), np.array([[0, 3]], np.int32)) == 0
+
+
+def _far_static(k, start=10.0):
+    return np.array([[start + 0.1 * i, 5.0, 5.0] for i in range(k)])
+
+
+def test_min_separation_finds_vf_pair_with_static_geometry(orc):
+    """A moving vertex 0.9 xi above a moving triangle, with ten unrelated static
+    particles far away (static items interleave with moving ones in the sweep)."""
+    xi = 1e-3
+    x = np.vstack([TRI, [[0.2, 0.2, 0.9 * xi]], _far_static(10)])
+    w = np.concatenate([np.ones(4), np.zeros(10)])
+    tris = np.array([[0, 1, 2]], np.int32)
+    edges = np.array([[0, 1], [0, 2], [1, 2]], np.int32)
+    d, below = orc.min_separation(x, w, tris, edges, reach=8e-3, below=xi)
+    assert np.isclose(d, 0.9 * xi, rtol=1e-12)
+    assert below.tolist() == [1, 0, 0]
+    # the triangle static, the vertex moving: still a pair
+    w2 = w.copy()
+    w2[:3] = 0.0
+    d, below = orc.min_separation(x, w2, tris, edges, reach=8e-3, below=xi)
+    assert np.isclose(d, 0.9 * xi, rtol=1e-12) and below.tolist() == [1, 0, 0]
+    # both static: never moves, not reported
+    w3 = w2.copy()
+    w3[3] = 0.0
+    d, below = orc.min_separation(x, w3, tris, edges, reach=8e-3, below=xi)
+    assert d == 8e-3 and below.tolist() == [0, 0, 0]
+
+
+def test_min_separation_finds_ee_and_vv_pairs(orc):
+    xi = 1e-3
+    # two skew segments crossing at 0.9 xi, static particles around
+    x = np.array([[-1, 0, 0], [1, 0, 0], [0, -1, 0.9 * xi], [0, 1, 0.9 * xi]], float)
+    x = np.vstack([x, _far_static(6)])
+    w = np.concatenate([np.ones(4), np.zeros(6)])
+    edges = np.array([[0, 1], [2, 3]], np.int32)
+    tris = np.zeros((0, 3), np.int32)
+    d, below = orc.min_separation(x, w, tris, edges, reach=4e-3, below=xi)
+    assert np.isclose(d, 0.9 * xi, rtol=1e-12) and below.tolist() == [0, 1, 0]
+    # free particles: a moving pair at 0.9 xi, a static pair at 0.5 xi (skipped)
+    x = np.vstack([[[0, 0, 0], [0.9 * xi, 0, 0], [1, 1, 1], [1, 1, 1 + 0.5 * xi]], _far_static(5)])
+    w = np.concatenate([[1.0, 2.0, 0.0, 0.0], np.zeros(5)])
+    d, below = orc.min_separation(x, w, tris, np.zeros((0, 2), np.int32), reach=4e-3, below=xi)
+    assert np.isclose(d, 0.9 * xi, rtol=1e-12) and below.tolist() == [0, 0, 1]
+
+
+def test_motion_check_catches_crossing_between_separated_end_states(orc):
+    """A vertex that passes through a triangle within one straight-line motion
+    ends as far below it as it started above: both end states pass the
+    separation check, the motion check must not certify it."""
+    xi = 1e-3
+    x0 = np.vstack([TRI, [[0.2, 0.2, 3 * xi]]])
+    x1 = np.vstack([TRI, [[0.2, 0.2, -3 * xi]]])
+    w = np.ones(4)
+    tris = np.array([[0, 1, 2]], np.int32)
+    edges = np.array([[0, 1], [0, 2], [1, 2]], np.int32)
+    for x in (x0, x1):
+        assert orc.min_separation(x, w, tris, edges, 8e-3, xi)[1].sum() == 0
+    dmin, cert, ns, tmin = orc.motion_check(x0, x1, w, tris, edges, floor=0.5 * xi, reach=8e-3)
+    assert not cert and dmin <= 0.5 * xi and 0.0 < tmin < 0.5
+    # two particles swapping places
+    p0 = np.array([[0, 0, 0], [3 * xi, 0, 0]], float)
+    p1 = p0[::-1].copy()
+    z2 = np.zeros((0, 2), np.int32)
+    dmin, cert, _, _ = orc.motion_check(p0, p1, np.ones(2), np.zeros((0, 3), np.int32), z2, 0.5 * xi, 8e-3)
+    assert not cert
+    # an edge sweeping through another edge
+    e0 = np.array([[-1, 0, 0], [1, 0, 0], [0, -1, 2 * xi], [0, 1, 2 * xi]], float)
+    e1 = e0.copy()
+    e1[2:, 2] = -2 * xi
+    dmin, cert, _, _ = orc.motion_check(e0, e1, np.ones(4), np.zeros((0, 3), np.int32),
+                                        np.array([[0, 1], [2, 3]], np.int32), 0.5 * xi, 8e-3)
+    assert not cert
+
+
+def test_motion_check_certifies_a_safe_motion(orc):
+    """A vertex sliding parallel to a triangle at 2 xi: certified, and the
+    sampled minimum is the true 2 xi."""
+    xi = 1e-3
+    x0 = np.vstack([TRI, [[0.1, 0.1, 2 * xi]]])
+    x1 = np.vstack([TRI, [[0.4, 0.4, 2 * xi]]])
+    dmin, cert, ns, _ = orc.motion_check(x0, x1, np.ones(4), np.array([[0, 1, 2]], np.int32),
+                                         np.array([[0, 1], [0, 2], [1, 2]], np.int32), 0.5 * xi, 8e-3)
+    assert cert and np.isclose(dmin, 2 * xi, rtol=1e-12)
+    assert 2 <= ns <= 2 + int(2 * 0.3 * np.sqrt(2) / (1.5 * xi)) + 1

@@ -95,17 +95,41 @@ def _check_state(orc, sc, x):
     return dmin
 
 
+def _check_motions(orc, sc, x_start, trace):
+    """Every iteration's straight-line anchor motion (x before -> x after the
+    iteration): certified to stay above xi / 2 (so nothing crosses), and no
+    sampled distance below xi (1 - 1e-3)."""
+    xi = float(np.float32(sc.params.xi))
+    prev = x_start
+    worst = np.inf
+    for it in range(len(trace)):
+        dmin, cert, ns, _ = orc.motion_check(prev, trace[it], sc.inv_mass, sc.tris, sc.edges,
+                                             floor=0.5 * xi, reach=4 * xi)
+        assert cert, (it, dmin, ns)
+        assert dmin >= xi * (1 - 1e-3), (it, dmin)
+        worst = min(worst, dmin)
+        prev = trace[it]
+    return worst
+
+
 def test_c0_end_to_end_no_penetration(orc):
     """Config C0 (32x32 cloth onto an icosphere, 10 steps of 10 iterations): no
-    interpenetration and separation >= xi after every step; contact starts."""
+    interpenetration and separation >= xi after every step, and every
+    iteration's motion certified free of crossings; contact starts."""
     sc = S.c0()
     sim = orc.Sim(sc)
+    xi = float(np.float32(sc.params.xi))
+    worst = np.inf
     for _ in range(sc.step.steps):
-        sim.step()
+        x0 = sim.x.copy()
+        trace = sim.step(trace=True)
+        assert np.array_equal(trace[-1], sim.x)
         _check_state(orc, sc, sim.x)
+        worst = min(worst, _check_motions(orc, sc, x0, trace))
     c = sim.counters
     assert c[3] > 0 and c[4] > 0              # regions were built and violated
     assert c[5] <= 0.03 * c[4] + 5             # halting stays rare (Sec. 4.3 reports <= 3%)
+    assert worst < 1.5 * xi                   # the motions did come close: the check was exercised
 
 
 @pytest.mark.parametrize("make", [
@@ -130,6 +154,8 @@ def test_contact_scenes_no_penetration(orc, make):
     v[sc.inv_mass == 0] = 0
     sim = orc.Sim(sc, v=v)
     for _ in range(3):
-        sim.step()
+        x0 = sim.x.copy()
+        trace = sim.step(trace=True)
         _check_state(orc, sc, sim.x)
+        _check_motions(orc, sc, x0, trace)
     assert sim.counters[4] > 0
