@@ -65,6 +65,8 @@ def load():
         lib.orc_project.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.orc_project_one.restype = C.c_int
         lib.orc_project_one.argtypes = [vp, dbl, vp, vp, i64, vp, vp, vp]
+        lib.orc_project_branches.restype = C.c_int
+        lib.orc_project_branches.argtypes = [vp, dbl, vp, vp, i64, vp, vp, vp, C.c_int, vp]
         lib.orc_orthogonal_projection.argtypes = [vp, vp, vp, dbl, vp, dbl]
         lib.orc_closest_point_triangle.restype = C.c_int
         lib.orc_closest_point_triangle.argtypes = [vp] * 6
@@ -77,6 +79,8 @@ def load():
         lib.orc_count_edge_tri_intersections.argtypes = [i32, vp, i32, vp, i32, vp]
         lib.orc_min_separation.restype = dbl
         lib.orc_min_separation.argtypes = [i32, vp, vp, i32, vp, i32, vp, dbl, dbl, vp]
+        lib.orc_min_separation_grid.restype = dbl
+        lib.orc_min_separation_grid.argtypes = [i32, vp, vp, i32, vp, i32, vp, dbl, dbl, vp]
         lib.orc_motion_check.restype = dbl
         lib.orc_motion_check.argtypes = [i32, vp, vp, vp, i32, vp, i32, vp, dbl, dbl, i64, vp, vp, vp]
         lib.orc_orient3d_sign.restype = C.c_int
@@ -229,6 +233,23 @@ def project_one(p, inv_mass, x, hs, y):
     return out, int(h), int(frag.value)
 
 
+def project_branches(p, inv_mass, x, hs, y, cap=256):
+    """Every result of Alg. 2 for one vertex over the branches of its
+    near-threshold decisions.  Returns (y_outs [k][3], halts [k], complete)."""
+    lib = load()
+    prm = params(p)
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    hs = np.ascontiguousarray(hs, HS_DTYPE)
+    hs1 = hs if len(hs) else np.zeros(1, HS_DTYPE)
+    outs = np.zeros((cap, 3))
+    halts = np.zeros(cap, np.int8)
+    comp = C.c_int(0)
+    n = lib.orc_project_branches(C.byref(prm), float(inv_mass), _p(x), _p(hs1), len(hs), _p(y), _p(outs),
+                                 _p(halts), int(cap), C.byref(comp))
+    return outs[:n].copy(), halts[:n].copy(), bool(comp.value)
+
+
 def make_halfspaces(n, d, keys=None, phi=None) -> np.ndarray:
     n = np.asarray(n, np.float64).reshape(-1, 3)
     hs = np.zeros(len(n), HS_DTYPE)
@@ -331,6 +352,18 @@ def min_separation(x, inv_mass, tris, edges, reach, below):
     cnt = np.zeros(3, np.int64)
     d = load().orc_min_separation(len(x), _p(x), _p(w), len(tris), _p(tris), len(edges), _p(edges),
                                   float(reach), float(below), _p(cnt))
+    return float(d), cnt
+
+
+def min_separation_grid(x, inv_mass, tris, edges, reach, below):
+    """min_separation through a uniform grid, for large meshes."""
+    x = np.ascontiguousarray(x, np.float64)
+    w = np.ascontiguousarray(inv_mass, np.float64)
+    tris = np.ascontiguousarray(tris, np.int32)
+    edges = np.ascontiguousarray(edges, np.int32)
+    cnt = np.zeros(3, np.int64)
+    d = load().orc_min_separation_grid(len(x), _p(x), _p(w), len(tris), _p(tris), len(edges), _p(edges),
+                                       float(reach), float(below), _p(cnt))
     return float(d), cnt
 
 

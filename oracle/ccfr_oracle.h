@@ -120,6 +120,14 @@ void orc_project(const orc_mesh* m, const orc_params* prm,
 int orc_project_one(const orc_params* prm, double inv_mass, const double x[3],
                     const orc_halfspace* hs, int64_t n_hs, const double y_in[3],
                     double y_out[3], int* fragile);
+/* Every result the projection of one vertex can take when its near-threshold
+ * decisions (those that make a vertex fragile) go either way: one run per
+ * branch of the decision tree, at most cap runs.  Writes y_outs [n][3] and
+ * halts [n], returns n; *complete = 0 if the tree had more than cap branches
+ * (or a branch more than 64 decisions). */
+int orc_project_branches(const orc_params* prm, double inv_mass, const double x[3],
+                         const orc_halfspace* hs, int64_t n_hs, const double y_in[3],
+                         double* y_outs, int8_t* halts, int cap, int* complete);
 /* Counts of fragility flags raised so far, by rule: [0] sign of rho, [1] order of
  * two violated half-spaces, [2] comparison with eps_plesnik. */
 void orc_fragile_reasons(int64_t out[3], int reset);
@@ -171,6 +179,11 @@ double orc_min_separation(int32_t n_verts, const double* x, const double* inv_ma
                           const int32_t* tris, int32_t n_edges, const int32_t* edges, double reach,
                           double below, int64_t out_counts[3]);
 
+/* The same check through a uniform grid (for large meshes): same pairs and
+ * results as orc_min_separation. */
+double orc_min_separation_grid(int32_t n_verts, const double* x, const double* inv_mass, int32_t n_tris,
+                               const int32_t* tris, int32_t n_edges, const int32_t* edges, double reach,
+                               double below, int64_t out_counts[3]);
 /* Certified sampled check of the straight-line motion from x0 to x1 (one
  * iteration's anchor update): conservative advancement in t with the Lipschitz
  * bound 2 max |x1 - x0| of every pair distance.  Returns the smallest sampled

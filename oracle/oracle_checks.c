@@ -431,3 +431,158 @@ double orc_motion_check(int32_t n_verts, const double* x0, const double* x1, con
     if (t_min) *t_min = tbest;
     return best;
 }
+
+/* ---- the same separation check for large meshes: a uniform grid ----
+ * Items (vertices, triangles, edges, boxes grown by reach / 2) whose largest
+ * box extent is at most the cell size h are put in the cell of their box's
+ * lower corner; two such boxes can only overlap if those cells are neighbours
+ * (each box spans at most h), so every item looks up the 27 cells around its
+ * own.  Items larger than h (walls, ground planes) are tested against every
+ * item.  Same pairs, rules and results as orc_min_separation. */
+
+typedef struct { uint64_t key; int64_t item; } cell_ref;
+
+static int cmp_cell(const void* a, const void* b) {
+    uint64_t x = ((const cell_ref*)a)->key, y = ((const cell_ref*)b)->key;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static uint64_t pack_cell(int64_t cx, int64_t cy, int64_t cz) {
+    const int64_t o = (int64_t)1 << 20;
+    return ((uint64_t)(cx + o) << 42) | ((uint64_t)(cy + o) << 21) | (uint64_t)(cz + o);
+}
+
+static int cmp_dbl(const void* a, const void* b) {
+    double x = *(const double*)a, y = *(const double*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* distance of one pair of items (kind 0 vertex, 1 triangle, 2 edge), or -1 if
+ * the pair is not one the check covers */
+static double item_pair_dist2(const item_t* A, const item_t* B, const double* x, const int32_t* tris,
+                              const int32_t* edges, const unsigned char* fr, int* kind) {
+    int ki = A->kind, kj = B->kind;
+    if (A->stat && B->stat) return -1.0;
+    if ((ki == 0 && kj == 1) || (ki == 1 && kj == 0)) {
+        int32_t v = ki == 0 ? A->id : B->id;
+        int32_t t = ki == 1 ? A->id : B->id;
+        const int32_t* tv = tris + 3 * t;
+        if (tv[0] == v || tv[1] == v || tv[2] == v) return -1.0;
+        *kind = 0;
+        return pt_tri2(x + 3 * v, x + 3 * tv[0], x + 3 * tv[1], x + 3 * tv[2]);
+    }
+    if (ki == 2 && kj == 2) {
+        const int32_t* a = edges + 2 * A->id;
+        const int32_t* b = edges + 2 * B->id;
+        if (a[0] == b[0] || a[0] == b[1] || a[1] == b[0] || a[1] == b[1]) return -1.0;
+        *kind = 1;
+        return seg_seg2(x + 3 * a[0], x + 3 * a[1], x + 3 * b[0], x + 3 * b[1]);
+    }
+    if (ki == 0 && kj == 0) {
+        int32_t a = A->id, b = B->id;
+        if (!fr[a] || !fr[b]) return -1.0;
+        double dv[3] = {x[3 * a] - x[3 * b], x[3 * a + 1] - x[3 * b + 1], x[3 * a + 2] - x[3 * b + 2]};
+        *kind = 2;
+        return d3(dv, dv);
+    }
+    return -1.0;
+}
+
+static int boxes_overlap(const item_t* A, const item_t* B) {
+    for (int k = 0; k < 3; ++k)
+        if (A->lo[k] > B->hi[k] || B->lo[k] > A->hi[k]) return 0;
+    return 1;
+}
+
+double orc_min_separation_grid(int32_t n_verts, const double* x, const double* inv_mass, int32_t n_tris,
+                               const int32_t* tris, int32_t n_edges, const int32_t* edges, double reach,
+                               double below, int64_t out_counts[3]) {
+    unsigned char* fr = (unsigned char*)malloc((size_t)n_verts + 1);
+    memset(fr, 1, (size_t)n_verts);
+    for (int32_t t = 0; t < 3 * n_tris; ++t) fr[tris[t]] = 0;
+    for (int32_t e = 0; e < 2 * n_edges; ++e) fr[edges[e]] = 0;
+    const int64_t n = (int64_t)n_verts + n_tris + n_edges;
+    item_t* it = (item_t*)malloc(sizeof(item_t) * (size_t)(n + 1));
+    const double g = 0.5 * reach;
+    for (int32_t v = 0; v < n_verts; ++v) it[v] = make_item(x, &v, 1, g, 0, v);
+    for (int32_t t = 0; t < n_tris; ++t) it[n_verts + t] = make_item(x, tris + 3 * t, 3, g, 1, t);
+    for (int32_t e = 0; e < n_edges; ++e) it[n_verts + n_tris + e] = make_item(x, edges + 2 * e, 2, g, 2, e);
+    double* ext = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+    for (int64_t k = 0; k < n; ++k) {
+        const int32_t* vs = it[k].kind == 0 ? &it[k].id : (it[k].kind == 1 ? tris + 3 * it[k].id : edges + 2 * it[k].id);
+        int nv = it[k].kind == 0 ? 1 : (it[k].kind == 1 ? 3 : 2);
+        int s = 1;
+        for (int q = 0; q < nv; ++q) s &= (inv_mass == NULL ? 0 : inv_mass[vs[q]] == 0.0);
+        it[k].stat = s;
+        double e = 0.0;
+        for (int a = 0; a < 3; ++a) e = fmax(e, it[k].hi[a] - it[k].lo[a]);
+        ext[k] = e;
+    }
+    /* cell size: the largest extent among items up to 8 times the median */
+    double* sorted = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+    memcpy(sorted, ext, sizeof(double) * (size_t)n);
+    qsort(sorted, (size_t)n, sizeof(double), cmp_dbl);
+    double h = n > 0 ? sorted[n / 2] : reach;
+    const double cap = 8.0 * h;
+    for (int64_t k = 0; k < n; ++k)
+        if (sorted[k] <= cap && sorted[k] > h) h = sorted[k];
+    if (!(h > 0.0)) h = reach > 0.0 ? reach : 1.0;
+    free(sorted);
+    int64_t* large = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    cell_ref* cells = (cell_ref*)malloc(sizeof(cell_ref) * (size_t)(n + 1));
+    int64_t nl = 0, nc = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        if (ext[k] > h) { large[nl++] = k; continue; }
+        cells[nc].key = pack_cell((int64_t)floor(it[k].lo[0] / h), (int64_t)floor(it[k].lo[1] / h),
+                                  (int64_t)floor(it[k].lo[2] / h));
+        cells[nc].item = k;
+        nc++;
+    }
+    qsort(cells, (size_t)nc, sizeof(cell_ref), cmp_cell);
+    double best2 = reach * reach;
+    int64_t c0 = 0, c1 = 0, c2 = 0;
+    const double below2 = below * below;
+#pragma omp parallel for schedule(dynamic, 512) reduction(min : best2) reduction(+ : c0, c1, c2)
+    for (int64_t q = 0; q < nc; ++q) {
+        const int64_t i = cells[q].item;
+        const int64_t cx = (int64_t)floor(it[i].lo[0] / h), cy = (int64_t)floor(it[i].lo[1] / h),
+                      cz = (int64_t)floor(it[i].lo[2] / h);
+        for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dz = -1; dz <= 1; ++dz) {
+                    const uint64_t key = pack_cell(cx + dx, cy + dy, cz + dz);
+                    int64_t lo = 0, hi = nc;                 /* first entry with this key */
+                    while (lo < hi) {
+                        int64_t mid = (lo + hi) / 2;
+                        if (cells[mid].key < key) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    for (int64_t r = lo; r < nc && cells[r].key == key; ++r) {
+                        const int64_t j = cells[r].item;
+                        if (j <= i || !boxes_overlap(&it[i], &it[j])) continue;
+                        int kind = -1;
+                        double dist2 = item_pair_dist2(&it[i], &it[j], x, tris, edges, fr, &kind);
+                        if (dist2 < 0.0) continue;
+                        if (dist2 < best2) best2 = dist2;
+                        if (dist2 < below2) { if (kind == 0) c0++; else if (kind == 1) c1++; else c2++; }
+                    }
+                }
+    }
+    /* large items against every item (each large-large pair once) */
+#pragma omp parallel for schedule(dynamic, 4096) reduction(min : best2) reduction(+ : c0, c1, c2)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t a = 0; a < nl; ++a) {
+            const int64_t i = large[a];
+            if (i == j || (ext[j] > h && j < i)) continue;
+            if (!boxes_overlap(&it[i], &it[j])) continue;
+            int kind = -1;
+            double dist2 = item_pair_dist2(&it[i], &it[j], x, tris, edges, fr, &kind);
+            if (dist2 < 0.0) continue;
+            if (dist2 < best2) best2 = dist2;
+            if (dist2 < below2) { if (kind == 0) c0++; else if (kind == 1) c1++; else c2++; }
+        }
+    }
+    if (out_counts) { out_counts[0] = c0; out_counts[1] = c1; out_counts[2] = c2; }
+    free(it); free(fr); free(ext); free(large); free(cells);
+    return sqrt(best2);
+}

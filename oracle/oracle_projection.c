@@ -26,6 +26,10 @@
  * (the sign of rho, the order of two violated half-spaces, a comparison with
  * eps_plesnik) sat within a relative margin of its threshold, so that a
  * different rounding order could flip it.  The margins are test-side only.
+ * Each such decision is numbered in the order it is met, and a caller may ask
+ * for any of them to take its other outcome (orc_project_branches walks every
+ * combination): the results of all branches are the results a correct
+ * implementation that rounds differently may return.
  */
 #include "ccfr_oracle.h"
 
@@ -46,7 +50,11 @@ typedef struct {
     double B[3];       /* plane RHS       */
 } ero_t;
 
-typedef struct { int fragile; } flags_t;
+typedef struct {
+    int fragile;
+    int n_dec;         /* near-threshold decisions met so far                */
+    uint64_t flip;     /* decision k takes its other outcome if bit k is set */
+} flags_t;
 
 /* which rule flagged a vertex: [0] rho sign, [1] order of violated rho, [2] eps */
 static int64_t g_reasons[3];
@@ -58,13 +66,19 @@ void orc_fragile_reasons(int64_t out[3], int reset) {
     }
 }
 
-static void note_eps(flags_t* f, double mag, double eps) {
-    if (f && fabs(mag - eps) <= REL_EPS * eps) {
-        f->fragile = 1;
+/* A discrete decision whose default outcome is `out`: when it sits near its
+ * threshold (`near`) the vertex is fragile and the decision may be flipped. */
+static int decide(flags_t* f, int out, int near, int reason) {
+    if (!f || !near) return out;
+    f->fragile = 1;
 #pragma omp atomic
-        g_reasons[2]++;
-    }
+    g_reasons[reason]++;
+    const int k = f->n_dec++;
+    if (k < 64 && ((f->flip >> k) & 1u)) return !out;
+    return out;
 }
+
+static int near_eps(double mag, double eps) { return fabs(mag - eps) <= REL_EPS * eps; }
 
 static void push(ero_t* S, const double v[3], const double n[3], double b) {
     memcpy(S->V[S->m], v, sizeof(double) * 3);
@@ -80,8 +94,7 @@ static void orthogonal_projection(double xt[3], const double x0[3], const double
     if (S->m == 0) {
         double v0[3] = {n[0], n[1], n[2]};
         double beta0 = dot3(n, v0);
-        note_eps(fl, fabs(beta0), eps);
-        if (fabs(beta0) < eps) return;
+        if (decide(fl, fabs(beta0) < eps, near_eps(fabs(beta0), eps), 2)) return;
         double c = (b - dot3(n, xt)) / beta0;
         for (int k = 0; k < 3; ++k) xt[k] += c * v0[k];
         push(S, v0, n, b);
@@ -96,8 +109,7 @@ static void orthogonal_projection(double xt[3], const double x0[3], const double
     double dn[3] = {nm[0] - n0[0], nm[1] - n0[1], nm[2] - n0[2]};
     double beta_u = dot3(dn, S->V[m - 1]);
     double alpha_u = bm - dot3(nm, xt);
-    note_eps(fl, fabs(beta_u), eps);
-    if (fabs(beta_u) < eps) return;
+    if (decide(fl, fabs(beta_u) < eps, near_eps(fabs(beta_u), eps), 2)) return;
     double u[3], w[3];
     for (int k = 0; k < 3; ++k) u[k] = xt[k] + (alpha_u / beta_u) * S->V[m - 1][k];
     for (int k = 0; k < 3; ++k) w[k] = x0[k] + nm[k];
@@ -106,18 +118,15 @@ static void orthogonal_projection(double xt[3], const double x0[3], const double
         const double bj = (j < m) ? S->B[j] : bm;
         double dnj[3] = {nj[0] - n0[0], nj[1] - n0[1], nj[2] - n0[2]};
         double beta_w = dot3(dnj, S->V[j - 1]);
-        note_eps(fl, fabs(beta_w), eps);
-        if (fabs(beta_w) > eps) {
+        if (decide(fl, fabs(beta_w) > eps, near_eps(fabs(beta_w), eps), 2)) {
             double alpha_w = bj - b0 - dot3(dnj, w);
             for (int k = 0; k < 3; ++k) w[k] += (alpha_w / beta_w) * S->V[j - 1][k];
         }
     }
     double vnew[3] = {w[0] - u[0], w[1] - u[1], w[2] - u[2]};
-    note_eps(fl, norm3(vnew), eps);
-    if (norm3(vnew) > eps) {
+    if (decide(fl, norm3(vnew) > eps, near_eps(norm3(vnew), eps), 2)) {
         double beta_new = dot3(n0, vnew);
-        note_eps(fl, fabs(beta_new), eps);
-        if (fabs(beta_new) < eps) {
+        if (decide(fl, fabs(beta_new) < eps, near_eps(fabs(beta_new), eps), 2)) {
             memcpy(xt, u, sizeof(double) * 3);
         } else {
             double alpha_new = b0 - dot3(n0, u);
@@ -191,10 +200,10 @@ static int project_vertex(const orc_params* prm, double w, const double x[3], co
                 const orc_halfspace* b = &C[it[k - 1].idx];
                 double dn[3] = {a->n[0] - b->n[0], a->n[1] - b->n[1], a->n[2] - b->n[2]};
                 int differ = norm3(dn) > 1e-7 || fabs(a->d - b->d) > 1e-7 * (fabs(a->d) + fabs(b->d)) + 1e-15;
-                if (differ && it[k].rho - it[k - 1].rho <= REL_RHO * sc) {
-                    fl->fragile = 1;
-#pragma omp atomic
-                    g_reasons[1]++;
+                if (decide(fl, 0, differ && it[k].rho - it[k - 1].rho <= REL_RHO * sc, 1)) {
+                    sort_item t = it[k];
+                    it[k] = it[k - 1];
+                    it[k - 1] = t;
                 }
             }
         }
@@ -212,12 +221,7 @@ static int project_vertex(const orc_params* prm, double w, const double x[3], co
                 double dx[3] = {xt[0] - x[0], xt[1] - x[1], xt[2] - x[2]};
                 double rho = dot3(dx, c->n) + c->d;
                 double sc = norm3(dx) + fabs(c->d);
-                if (sc > 0.0 && fabs(rho) <= REL_RHO * sc) {
-                    fl->fragile = 1;
-#pragma omp atomic
-                    g_reasons[0]++;
-                }
-                if (rho >= 0.0) continue;
+                if (decide(fl, rho >= 0.0, sc > 0.0 && fabs(rho) <= REL_RHO * sc, 0)) continue;
                 double b = dot3(c->n, x) - c->d;
                 nviol++;
                 orthogonal_projection(xt, x0, c->n, b, &S, prm->eps_plesnik, fl);
@@ -250,7 +254,7 @@ static int project_vertex(const orc_params* prm, double w, const double x[3], co
 int orc_project_one(const orc_params* prm, double inv_mass, const double x[3],
                     const orc_halfspace* hs, int64_t n_hs, const double y_in[3],
                     double y_out[3], int* fragile) {
-    flags_t fl = {0};
+    flags_t fl = {0, 0, 0};
     int violated;
     int h = project_vertex(prm, inv_mass, x, hs, n_hs, y_in, y_out, &violated, &fl);
     if (fragile) *fragile = fl.fragile;
@@ -264,7 +268,7 @@ void orc_project(const orc_mesh* m, const orc_params* prm,
     int64_t n_viol = 0, n_halt = 0, n_frag = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : n_viol, n_halt, n_frag)
     for (int32_t v = 0; v < m->n_verts; ++v) {
-        flags_t fl = {0};
+        flags_t fl = {0, 0, 0};
         int violated;
         int h = project_vertex(prm, m->inv_mass[v], m->x + 3 * (size_t)v, hs + offsets[v],
                                offsets[v + 1] - offsets[v], y_in + 3 * (size_t)v,
@@ -276,4 +280,35 @@ void orc_project(const orc_mesh* m, const orc_params* prm,
         n_frag += fl.fragile;
     }
     if (stats) { stats[0] = n_viol; stats[1] = n_halt; stats[2] = n_frag; stats[3] = 0; }
+}
+
+int orc_project_branches(const orc_params* prm, double inv_mass, const double x[3],
+                         const orc_halfspace* hs, int64_t n_hs, const double y_in[3],
+                         double* y_outs, int8_t* halts, int cap, int* complete) {
+    /* Breadth-first walk of the tree of near-threshold decisions: a node fixes
+     * the outcomes of its first `depth` decisions by `mask` (the rest default);
+     * its children flip one later decision each. */
+    typedef struct { uint64_t mask; int depth; } node_t;
+    node_t* q = (node_t*)malloc(sizeof(node_t) * (size_t)(cap > 0 ? cap : 1));
+    int head = 0, tail = 0, n_out = 0, full = 1;
+    if (cap > 0) q[tail++] = (node_t){0, 0};
+    while (head < tail) {
+        node_t nd = q[head++];
+        flags_t fl = {0, 0, nd.mask};
+        int violated;
+        double y[3];
+        int h = project_vertex(prm, inv_mass, x, hs, n_hs, y_in, y, &violated, &fl);
+        memcpy(y_outs + 3 * (size_t)n_out, y, sizeof(double) * 3);
+        halts[n_out] = (int8_t)h;
+        n_out++;
+        const int nd_max = fl.n_dec < 64 ? fl.n_dec : 64;
+        if (fl.n_dec > 64) full = 0;
+        for (int i = nd.depth; i < nd_max; ++i) {
+            if (tail >= cap) { full = 0; break; }
+            q[tail++] = (node_t){nd.mask | ((uint64_t)1 << i), i + 1};
+        }
+    }
+    free(q);
+    if (complete) *complete = full;
+    return n_out;
 }

@@ -235,7 +235,6 @@ namespace {
 Scene make_scene(const ccfr_mesh* m, const float* x, const ccfr_params* p, int skin_iters = 0,
                  int skin_mult = 0) {
     Scene sc{};
-    sc.narrow_fp32 = m->ctx->narrow_fp32 ? 1 : 0;
     sc.n_verts = m->n_verts;
     sc.n_tris = m->n_tris;
     sc.n_edges = m->n_edges;
@@ -667,8 +666,6 @@ int ccfr_create(ccfr_ctx** out, int device) {
     ctx->device = device;
     const char* ng = std::getenv("CCFR_NO_GRAPHS");
     ctx->use_graphs = !(ng && ng[0] == '1');
-    const char* nf = std::getenv("CCFR_NARROW_FP32");
-    ctx->narrow_fp32 = nf && nf[0] == '1';
     const char* cs = std::getenv("CCFR_CSR_IN_STEP");
     ctx->csr_in_step = cs && cs[0] == '1';
     if (dev_alloc(&ctx->counters_d, 1) != hipSuccess ||

@@ -240,7 +240,6 @@ int rebuild_plan(ccfr_batch* b, hipStream_t s) {
     sc.edges = P.edges;
     sc.free_list = P.free_list;
     sc.vflags = P.vflags;
-    sc.narrow_fp32 = ctx->narrow_fp32 ? 1 : 0;
     sc.prm.table = b->table_d;
     sc.prm.vmesh = P.vmesh;
     pl.x = P.x;

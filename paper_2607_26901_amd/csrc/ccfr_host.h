@@ -94,7 +94,6 @@ struct ccfr_ctx {
     ccfr::DevCounters* counters_d = nullptr;
     long long generation = 0;   // bumped whenever a workspace buffer moves
     bool use_graphs = true;
-    bool narrow_fp32 = false;   // narrow-phase arithmetic in FP32 (measurement option)
     bool csr_in_step = false;   // substeps build CSR regions instead of slots (measurement option)
     float cell_scale = 1.0f;    // grid cell size relative to the default
     int pair_split = 1;         // lanes per broad-phase query (1, 3 or 9)

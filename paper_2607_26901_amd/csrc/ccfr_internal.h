@@ -226,7 +226,6 @@ struct Scene {
     const int32_t* edges;
     const int32_t* free_list;   // [n_free] free particles (vertices in no edge / triangle)
     const uint8_t* vflags;      // [n_verts] VF_FREE | VF_COLOR0
-    int32_t narrow_fp32;        // 1: narrow-phase arithmetic in FP32 instead of FP64
     int32_t skin_iters;         // candidate builds: further iterations the lists must cover
     int32_t skin_wide;          // candidate builds: moving boxes padded by MeshParams::pad_wide
     int32_t build_gated;        // candidate builds: run only when DevCounters::rebuild is set

@@ -411,12 +411,8 @@ void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, cons
     const int jb = colour_job_blocks(hosted, kBlock);
     const int blocks = grid_for(cap_vf + cap_ee + cap_vv) + jb;
     int32_t* per_vertex = for_slots ? nullptr : vcount;     // slots: counted by the fill
-    if (sc.narrow_fp32)
-        hipLaunchKernelGGL(k_contacts<float>, dim3(blocks), dim3(kBlock), 0, s, sc, vf, ee, vv, counts, cap_vf,
-                           cap_ee, cap_vv, contacts, cap_contacts, per_vertex, c, hosted, jb);
-    else
-        hipLaunchKernelGGL(k_contacts<double>, dim3(blocks), dim3(kBlock), 0, s, sc, vf, ee, vv, counts, cap_vf,
-                           cap_ee, cap_vv, contacts, cap_contacts, per_vertex, c, hosted, jb);
+    hipLaunchKernelGGL(k_contacts<double>, dim3(blocks), dim3(kBlock), 0, s, sc, vf, ee, vv, counts, cap_vf,
+                       cap_ee, cap_vv, contacts, cap_contacts, per_vertex, c, hosted, jb);
 }
 
 void launch_fill_slots(const Scene& sc, const Contact* contacts, int64_t cap_contacts, int32_t* vcount,

@@ -348,8 +348,10 @@ def helix_strands(n_strands=16, seg=64, length=0.3, root_radius=0.2, center=(0.0
                   root_spacing_scale=1.0) -> Scene:
     """Strands rooted on a Fibonacci lattice over a sphere (roots pinned), each a
     helix about its outward radial axis.  The curl radius is ramped in from zero over
-    the first 10 mm and clipped against the local strand spacing so that neighbouring
-    strands start well apart."""
+    the first 10 mm and clipped against the local strand spacing (times
+    `root_spacing_scale`) so that neighbouring strands start well apart; a strand
+    that still comes within 2r + xi of an earlier one has its curl radius halved
+    until none does."""
     rng = np.random.Generator(np.random.PCG64(seed))
     k = seg + 1
     i = np.arange(n_strands) + 0.5
@@ -368,23 +370,74 @@ def helix_strands(n_strands=16, seg=64, length=0.3, root_radius=0.2, center=(0.0
     ph0 = rng.uniform(0, 2 * np.pi, n_strands)
     a = np.linspace(0.0, length, k)                         # axial distance from the root
     band = 2 * r + xi
-    pts = np.empty((n_strands, k, 3))
+    frames = []
     for s in range(n_strands):
         d = dirs[s]
         t1 = np.cross(d, [0.0, 0.0, 1.0] if abs(d[2]) < 0.9 else [1.0, 0.0, 0.0])
         t1 /= np.linalg.norm(t1)
-        t2 = np.cross(d, t1)
-        spacing = dnn[s] * (root_radius + a) / root_radius
-        rad = np.minimum(R[s] * np.clip(a / 0.01, 0.0, 1.0),
+        frames.append((d, t1, np.cross(d, t1)))
+
+    def strand_points(s, radius):
+        d, t1, t2 = frames[s]
+        spacing = root_spacing_scale * dnn[s] * (root_radius + a) / root_radius
+        rad = np.minimum(radius * np.clip(a / 0.01, 0.0, 1.0),
                          np.maximum(0.5 * spacing - band - 1e-4, 0.0))
         ang = ph0[s] + 2 * np.pi * a / pitch
-        pts[s] = roots[s] + a[:, None] * d + rad[:, None] * (np.cos(ang)[:, None] * t1 + np.sin(ang)[:, None] * t2)
+        return roots[s] + a[:, None] * d + rad[:, None] * (np.cos(ang)[:, None] * t1 + np.sin(ang)[:, None] * t2)
+
+    pts = np.empty((n_strands, k, 3))
+    for s in range(n_strands):
+        pts[s] = strand_points(s, R[s])
+    # Strands that may still come within 2r + xi of another strand get their
+    # curl radius halved, repeatedly.  The test samples segments and compares
+    # sample points only, conservatively: two segments closer than `band` have
+    # samples closer than band + delta, with delta the largest spacing of their
+    # samples.  A coarse pass (4 samples per segment) finds the segment pairs of
+    # different strands worth a look, a fine pass (32 per segment) decides.
+    from scipy.spatial import cKDTree
+    halvings = 0
+    sub, fine = 4, 32
+    tt = np.arange(sub) / sub
+    tf = np.linspace(0.0, 1.0, fine + 1)
+    for _ in range(40):
+        dense = (pts[:, :-1, None, :] * (1 - tt)[None, None, :, None]
+                 + pts[:, 1:, None, :] * tt[None, None, :, None]).reshape(n_strands, -1, 3)
+        dense = np.concatenate([dense, pts[:, -1:, :]], 1)
+        delta = float(np.max(np.linalg.norm(np.diff(dense, axis=1), axis=2)))
+        per = dense.shape[1]
+        close = cKDTree(dense.reshape(-1, 3)).query_pairs(band + delta, output_type="ndarray")
+        sa, sb = close[:, 0] // per, close[:, 1] // per
+        cross = sa != sb
+        ga = np.minimum((close[cross, 0] % per) // sub, k - 2)
+        gb = np.minimum((close[cross, 1] % per) // sub, k - 2)
+        cand = np.unique(np.stack([sa[cross], ga, sb[cross], gb], 1), axis=0)
+        flagged = []
+        for c in range(0, len(cand), 256):
+            q = cand[c:c + 256]
+            A = pts[q[:, 0], q[:, 1]][:, None, :] * (1 - tf)[None, :, None] + \
+                pts[q[:, 0], q[:, 1] + 1][:, None, :] * tf[None, :, None]
+            B = pts[q[:, 2], q[:, 3]][:, None, :] * (1 - tf)[None, :, None] + \
+                pts[q[:, 2], q[:, 3] + 1][:, None, :] * tf[None, :, None]
+            dmin = np.sqrt(((A[:, :, None, :] - B[:, None, :, :]) ** 2).sum(-1).min((1, 2)))
+            step = np.maximum(np.linalg.norm(A[:, 1] - A[:, 0], axis=1), np.linalg.norm(B[:, 1] - B[:, 0], axis=1))
+            flagged.append(q[dmin < band + step])
+        flagged = np.concatenate(flagged, 0) if flagged else np.zeros((0, 4), np.int64)
+        if not len(flagged):
+            break
+        # of each close pair of strands the later one is halved (the earlier is
+        # accepted), unless its curl is already negligible: then the earlier one
+        lo_s, hi_s = np.minimum(flagged[:, 0], flagged[:, 2]), np.maximum(flagged[:, 0], flagged[:, 2])
+        halve = np.unique(np.where(R[hi_s] > 1e-4, hi_s, lo_s))
+        halvings += len(halve)
+        R[halve] *= 0.5
+        for s in halve.tolist():
+            pts[s] = strand_points(s, R[s])
     w = np.full((n_strands, k), 1.0 / STRAND_VERTEX_MASS)
     w[:, 0] = 0.0
     m = strands_mesh(pts, w)
     return assemble(f"strands{n_strands}x{seg}_s{seed}", [m], Params(r=r, xi=xi),
                     StepParams(dt=1.0 / 240.0, iters=10, steps=30),
-                    meta=dict(n_strands=n_strands, seg=seg))
+                    meta=dict(n_strands=n_strands, seg=seg, curl_halvings=halvings))
 
 
 def strand_bundle(nx=3, ny=3, seg=16, spacing=1.2e-3, seg_len=4.69e-3, wiggle=1e-4, seed=21,

@@ -93,3 +93,27 @@ def oracle_to_fp32(hs_o):
     out["phi"] = hs_o["phi"].astype(np.float32)
     out["key"] = hs_o["key"]
     return out
+
+
+def match_projection(oracle, params, inv_mass, x, hv, y, yg, hg, tol):
+    """Compare one GPU projection (yg, halted flag hg or None) with the oracle.
+
+    A vertex whose decisions all sit clear of their thresholds must match the
+    oracle's result.  A fragile one must match the result of one branch of its
+    near-threshold decisions (each branch is what Alg. 2 returns when rounding
+    flips those decisions), within the same tolerance.  Returns "stable",
+    "branch", or "unresolved" when the decision tree had more branches than
+    the oracle walks and none of those it walked matched."""
+    yo, ho, fo = oracle.project_one(params, inv_mass, x, hv, y)
+    if not fo:
+        assert np.linalg.norm(yg - yo) <= tol, ("stable", yg, yo)
+        assert hg is None or int(hg) == int(ho), ("stable halted", hg, ho)
+        return "stable"
+    outs, halts, complete = oracle.project_branches(params, inv_mass, x, hv, y)
+    ok = np.linalg.norm(outs - yg[None, :], axis=1) <= tol
+    if hg is not None:
+        ok &= halts.astype(int) == int(hg)
+    if ok.any():
+        return "branch"
+    assert not complete, ("no branch matches", yg, hg, outs, halts)
+    return "unresolved"

@@ -88,6 +88,50 @@ def test_regions_parity(env, scenes, k):
         assert n > 0
 
 
+@pytest.mark.parametrize("k", range(2, len(SCENE_IDS)), ids=SCENE_IDS[2:])
+def test_regions_against_independent_distances(env, scenes, k):
+    """GPU half-spaces checked against distances computed without the oracle
+    (tests/indep_geometry.py: minimisers characterised by the normal equations
+    and point-segment distances): every half-space's phi equals its pair's
+    distance minus xi, and every pair closer than 2r + xi gives a half-space to
+    each of its dynamic vertices."""
+    from tests.indep_geometry import all_pair_distances
+    ctx, ccfr, oracle, torch = env
+    sc = scenes[k]
+    mesh = ccfr.mesh_from_scene(ctx, sc)
+    x = torch.from_numpy(sc.x).cuda()
+    c, _, _ = H.gpu_candidates(ctx, mesh, x, sc.params)
+    _, off, hs, _ = H.gpu_regions(ctx, mesh, x, c, sc.params)
+    diag = sc.bbox_diag()
+    xi32, r32 = float(np.float32(sc.params.xi)), float(np.float32(sc.params.r))
+    allp = all_pair_distances(sc.x, sc.inv_mass, sc.tris, sc.edges)
+    dist = {}
+    for kind, code in (("vf", 1), ("ee", 2), ("vv", 3)):
+        pairs, d = allp[kind]
+        for (a, b), dd in zip(pairs.tolist(), d.tolist()):
+            dist[(code << 62) | (a << 31) | b] = dd
+    owner = np.repeat(np.arange(sc.n_verts), np.diff(off))
+    got = {}
+    for v, h in zip(owner.tolist(), hs):
+        key = int(h["key"])
+        assert key in dist, ("half-space of an illegal pair", v, key)
+        assert abs(float(h["phi"]) - (dist[key] - xi32)) <= H.DTOL * diag, (v, key, float(h["phi"]), dist[key])
+        got.setdefault(key, set()).add(v)
+    # completeness: pairs of dynamic vertices inside the range reach every vertex
+    tris, edges, w = sc.tris, sc.edges, sc.inv_mass
+    n_in = 0
+    for key, dd in dist.items():
+        if not dd - xi32 < 2 * r32 - H.DTOL * diag:
+            continue
+        kind, a, b = key >> 62, (key >> 31) & 0x7FFFFFFF, key & 0x7FFFFFFF
+        vs = ([a] + tris[b].tolist()) if kind == 1 else (edges[a].tolist() + edges[b].tolist() if kind == 2 else [a, b])
+        if min(w[v] for v in vs) == 0:      # a static side can make both shares' weights zero
+            continue
+        assert set(vs) <= got.get(key, set()), (key, vs, got.get(key))
+        n_in += 1
+    assert n_in > 0
+
+
 def test_regions_from_caller_candidates(env, scenes):
     """ccfr_build_regions on candidate lists the caller owns (here the oracle's,
     uploaded), isolating the narrow phase from the broad phase."""
@@ -150,6 +194,16 @@ def test_projection_parity(env, scenes, k):
         err = np.linalg.norm(yg - yo, axis=1)
         assert np.all(err[stable] <= H.DTOL * diag), (np.max(err[stable]), int(np.argmax(np.where(stable, err, 0))))
         assert np.array_equal(hg[stable], ho[stable].astype(np.uint8))
+        # fragile vertices: the GPU result is one branch of their near-threshold decisions
+        kinds = {"branch": 0, "unresolved": 0}
+        for v in np.nonzero(~stable)[0]:
+            hv = hs_w[off_o[v]:off_o[v + 1]]
+            kinds[H.match_projection(oracle, sc.params, float(sc.inv_mass[v]), sc.x[v].astype(np.float64), hv,
+                                     y[v].astype(np.float64), yg[v], hg[v], H.DTOL * diag)] += 1
+        n_cmp = int(stable.sum()) + kinds["branch"]
+        print(f"{SCENE_IDS[k]} seed {seed}: {int(stable.sum())} stable, {kinds['branch']} fragile matched "
+              f"a branch, {kinds['unresolved']} unresolved of {sc.n_verts}")
+        assert n_cmp >= 0.99 * sc.n_verts
         # every vertex, fragile or not: the output is admissible or halted, within r
         assert np.all(np.linalg.norm(yg, axis=1) <= r32 * (1 + 1e-6))
         owner = np.repeat(np.arange(sc.n_verts), np.diff(off_o))
@@ -285,13 +339,9 @@ def test_projection_tiers(env):
     hg = halted.cpu().numpy()
     _, hs_w = H.to_oracle_halfspaces(off, hs32)
     x = np.zeros(3)
-    n_cmp = 0
+    kinds = {"stable": 0, "branch": 0, "unresolved": 0}
     for v in range(N):
-        yo, ho, fo = oracle.project_one(prm, float(w[v]), x, hs_w[off[v]:off[v + 1]], y[v].astype(np.float64))
-        if fo:
-            continue
-        n_cmp += 1
-        assert hg[v] == ho, (v, Ks[v])
-        assert np.linalg.norm(yg[v] - yo) <= H.DTOL * 1.0, (v, Ks[v], yg[v], yo)
-    assert n_cmp >= 0.8 * N
-
+        kinds[H.match_projection(oracle, prm, float(w[v]), x, hs_w[off[v]:off[v + 1]], y[v].astype(np.float64),
+                                 yg[v], hg[v], H.DTOL * 1.0)] += 1
+    print("projection tiers:", kinds)
+    assert kinds["stable"] + kinds["branch"] >= 0.97 * N

@@ -197,3 +197,22 @@ def test_motion_check_certifies_a_safe_motion(orc):
                                          np.array([[0, 1], [0, 2], [1, 2]], np.int32), 0.5 * xi, 8e-3)
     assert cert and np.isclose(dmin, 2 * xi, rtol=1e-12)
     assert 2 <= ns <= 2 + int(2 * 0.3 * np.sqrt(2) / (1.5 * xi)) + 1
+
+
+def test_grid_separation_check_equals_sweep(orc):
+    """The grid form of the separation check (used on the full-size workloads)
+    finds the same minimum and the same close pairs as the sweep form, on
+    scenes with static geometry, strands, particles and large walls."""
+    from paper_2607_26901_amd import scenes as S
+    rng = np.random.default_rng(3)
+    scenes = [S.c0(), S.two_layers(n=10, seed=3), S.strand_bundle(nx=4, ny=4, seg=20, seed=9),
+              S.particles_in_box(nx=5, ny=5, nz=6, seed=5),
+              S.folded_cloth_state(S.c1(n=24, side=0.19), seed=3)]
+    for sc in scenes:
+        for trial in range(3):
+            x = sc.x.astype(np.float64) + rng.normal(0, 0.3 * sc.params.xi, sc.x.shape) * (trial > 0)
+            xi = float(np.float32(sc.params.xi))
+            a = orc.min_separation(x, sc.inv_mass, sc.tris, sc.edges, 4 * xi, 1.5 * xi)
+            b = orc.min_separation_grid(x, sc.inv_mass, sc.tris, sc.edges, 4 * xi, 1.5 * xi)
+            assert a[0] == b[0], (sc.name, trial, a, b)
+            assert a[1].tolist() == b[1].tolist(), (sc.name, trial, a, b)

@@ -266,3 +266,32 @@ def test_alg2_sort_order_and_duplicates(orc):
         dup["key"][5:] = [100, 200]
         y2, h2, _ = orc.project_one(p, 1.0, np.zeros(3), dup, y0)
         assert h2 == h and np.array_equal(y, y2)
+
+
+def test_branches_of_near_threshold_decisions(orc):
+    """A proposal lying exactly on a plane (rho = 0) is a decision at its
+    threshold: the default branch keeps it (rho >= 0 is satisfied), the other
+    treats the plane as violated, projects onto it and retracts by eps.  Both
+    are results of Alg. 2 under a rounding that flips the sign; every branch is
+    admissible.  A vertex with no decision near a threshold has one branch,
+    equal to the plain projection."""
+    prm = _prm(r=5e-3, xi=1e-3)
+    x = np.zeros(3)
+    hs = orc.make_halfspaces([[0, 0, 1], [1, 0, 0]], [1e-3, 2e-3])
+    y = np.array([-2e-3, 0.3e-3, -1e-3])          # on plane 0, on plane 1
+    outs, halts, complete = orc.project_branches(prm, 1.0, x, hs, y)
+    yo, ho, fo = orc.project_one(prm, 1.0, x, hs, y)
+    assert fo and complete and len(outs) >= 2
+    assert np.array_equal(outs[0], yo) and halts[0] == ho
+    assert np.allclose(outs[0], y, atol=0)
+    # the flipped branches move the point off the planes by the retraction,
+    # towards the anchor, and stay admissible
+    moved = [o for o in outs if not np.array_equal(o, y)]
+    assert moved
+    for o in outs:
+        assert np.all(hs["n"] @ o + hs["d"] >= -1e-15)
+        assert np.linalg.norm(o) <= np.linalg.norm(y) + 1e-15
+    y2 = np.array([0.3e-3, 0.2e-3, -3e-3])        # clearly violating plane 0 only
+    outs, halts, complete = orc.project_branches(prm, 1.0, x, hs, y2)
+    yo, ho, fo = orc.project_one(prm, 1.0, x, hs, y2)
+    assert not fo and complete and len(outs) == 1 and np.array_equal(outs[0], yo)
