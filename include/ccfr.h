@@ -212,6 +212,15 @@ int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const
 int ccfr_xpbd_step(ccfr_ctx* ctx, const ccfr_mesh* mesh, float* x_dev, float* v_dev,
                    const ccfr_step_params* sp, ccfr_stream stream);
 
+/* The same substep, launched directly (never recorded), that also copies the
+ * anchor after every iteration into trace_dev ([iters][n_verts][3] float32,
+ * device, caller-owned): the straight-line motion of each iteration is
+ * trace[i-1] -> trace[i] (from x_dev's entry value for i = 0), which is what the
+ * paper's claim of no remaining violation (Sec. 4.3) is checked on.  Results
+ * are bitwise those of ccfr_xpbd_step. */
+int ccfr_xpbd_step_traced(ccfr_ctx* ctx, const ccfr_mesh* mesh, float* x_dev, float* v_dev,
+                          const ccfr_step_params* sp, float* trace_dev, ccfr_stream stream);
+
 /* Waits for `stream`, copies the status word and counters into *info (nullable)
  * and returns CCFR_ERR_CAPACITY / CCFR_ERR_NONFINITE if the matching sticky bits
  * are set, else CCFR_OK.  reset != 0 clears the whole device record: the bits,

@@ -64,7 +64,8 @@ class StatusInfo(C.Structure):
 
 EXPORTS = ["ccfr_status_string", "ccfr_create", "ccfr_destroy", "ccfr_mesh_create", "ccfr_mesh_destroy",
            "ccfr_mesh_edges", "ccfr_mesh_inv_mass_dev", "ccfr_reserve", "ccfr_build_candidates",
-           "ccfr_build_regions", "ccfr_project_displacements", "ccfr_xpbd_step", "ccfr_sync_status",
+           "ccfr_build_regions", "ccfr_project_displacements", "ccfr_xpbd_step", "ccfr_xpbd_step_traced",
+           "ccfr_sync_status",
            "ccfr_profile_enable", "ccfr_profile_read", "ccfr_set_tuning", "ccfr_get_tuning",
            "ccfr_batch_create", "ccfr_batch_destroy", "ccfr_batch_footprint", "ccfr_batch_add",
            "ccfr_batch_remove", "ccfr_batch_step", "ccfr_batch_rollback", "ccfr_batch_read", "ccfr_batch_stats"]
@@ -98,6 +99,7 @@ def load():
                                        C.POINTER(Regions), vp]
     lib.ccfr_project_displacements.argtypes = [vp, C.POINTER(Regions), vp, vp, C.POINTER(Params), vp, vp, vp]
     lib.ccfr_xpbd_step.argtypes = [vp, vp, vp, vp, C.POINTER(StepParams), vp]
+    lib.ccfr_xpbd_step_traced.argtypes = [vp, vp, vp, vp, C.POINTER(StepParams), vp, vp]
     lib.ccfr_sync_status.argtypes = [vp, vp, C.POINTER(StatusInfo), C.c_int]
     lib.ccfr_profile_enable.argtypes = [vp, C.c_int]
     lib.ccfr_profile_read.argtypes = [vp, vp, vp, vp]
@@ -405,6 +407,16 @@ def xpbd_step(ctx: Context, mesh: Mesh, x, v, step_params: StepParams, stream=No
     vp = _dev(v, "float32", 3 * mesh.n_verts, "v")
     _check(ctx.lib.ccfr_xpbd_step(ctx.h, mesh.h, xp, vp, C.byref(step_params), _stream(stream)),
            "ccfr_xpbd_step")
+
+
+def xpbd_step_traced(ctx: Context, mesh: Mesh, x, v, step_params: StepParams, trace, stream=None):
+    """xpbd_step that writes the anchor after every iteration into `trace`
+    ([iters][n_verts][3] float32 on the device)."""
+    xp = _dev(x, "float32", 3 * mesh.n_verts, "x")
+    vp = _dev(v, "float32", 3 * mesh.n_verts, "v")
+    tp = _dev(trace, "float32", 3 * mesh.n_verts * max(step_params.iters, 1), "trace")
+    _check(ctx.lib.ccfr_xpbd_step_traced(ctx.h, mesh.h, xp, vp, C.byref(step_params), tp, _stream(stream)),
+           "ccfr_xpbd_step_traced")
 
 
 def caller_candidates(vf, ee, vv, counts) -> Candidates:

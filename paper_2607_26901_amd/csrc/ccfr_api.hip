@@ -460,6 +460,7 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
         mk.mark(5, 0);
         launch_project(pa, ctx->counters_d, false, s);
         mk.mark(5, 1);
+        if (plan.trace) launch_copy(plan.x, plan.trace + (size_t)it * 3 * (size_t)n, 3LL * n, s);
     }
     launch_update_velocity(n, plan.x, ctx->x_start, 1.0f / plan.dt, plan.v, s);
 }
@@ -902,6 +903,28 @@ int ccfr_xpbd_step(ccfr_ctx* ctx, const ccfr_mesh* mesh, float* x_dev, float* v_
     const bool same = G.valid && G.owner == mesh && G.x == x_dev && G.v == v_dev &&
                       std::memcmp(&G.sp, sp, sizeof(*sp)) == 0 && G.generation == ctx->generation;
     return launch_recorded(ctx, ctx->graph, plan, mesh, sp, same, s);
+}
+
+int ccfr_xpbd_step_traced(ccfr_ctx* ctx, const ccfr_mesh* mesh, float* x_dev, float* v_dev,
+                          const ccfr_step_params* sp, float* trace_dev, ccfr_stream stream) {
+    if (!ctx || !mesh || !step_params_ok(sp)) return CCFR_ERR_INVALID_ARG;
+    if ((!x_dev || !v_dev || !trace_dev) && mesh->n_verts > 0 && sp->iters > 0) return CCFR_ERR_INVALID_ARG;
+    if (mesh->ctx != ctx) return CCFR_ERR_INVALID_ARG;
+    if (mesh->n_verts == 0) return CCFR_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    const long long gen0 = ctx->generation;
+    int rc = ensure_step(ctx, mesh->n_verts);
+    if (rc) return rc;
+    rc = ensure_sizes(ctx, mesh->n_verts, mesh->n_tris, mesh->n_edges, mesh->n_free, 1);
+    if (rc) return rc;
+    if (ctx->generation != gen0) drop_graph(ctx);
+    rc = ensure_prof_events(ctx, sp->iters);
+    if (rc) return rc;
+    StepPlan plan = mesh_plan(ctx, mesh, x_dev, v_dev, sp);
+    plan.trace = trace_dev;
+    enqueue_step(ctx, plan, s);      // launched directly, never recorded
+    HIP_OK(hipGetLastError());
+    return CCFR_OK;
 }
 
 int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, int reset) {

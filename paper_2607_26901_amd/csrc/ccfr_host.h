@@ -193,6 +193,8 @@ struct StepPlan {
     // builds that adapt to the motion: the least widening (pad_wide - pad) of
     // any mesh's moving boxes; 0 = fixed grouping of iterations
     double skin = 0.0;
+    // nullable: [iters][N][3] receives the anchor after every iteration
+    float* trace = nullptr;
 };
 
 void drop_graph(ccfr_ctx* ctx);

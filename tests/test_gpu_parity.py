@@ -240,25 +240,43 @@ def test_xpbd_step_parity_and_no_penetration(env, scenes):
 
 def test_c0_end_to_end_on_gpu(env):
     """Config C0 run on the GPU for its 10 steps: no interpenetration and
-    separation >= xi after every step (checked by the oracle's independent
-    checkers on the GPU state)."""
+    separation >= xi after every step, and every iteration's straight-line
+    motion (read back through the traced substep) certified by the oracle's
+    motion check to keep every pair above xi / 2, with no sampled distance
+    below xi (1 - 1e-3).  The traced substep equals the recorded one bit for bit."""
     ctx, ccfr, oracle, torch = env
     sc = S.c0()
     mesh = ccfr.mesh_from_scene(ctx, sc)
     x = torch.from_numpy(sc.x.copy()).cuda()
     v = torch.from_numpy(sc.v.copy()).cuda()
+    x2, v2 = x.clone(), v.clone()
     sp = ccfr.make_step_params(sc.step, sc.params)
     xi = float(np.float32(sc.params.xi))
+    trace = torch.zeros((sc.step.iters, sc.n_verts, 3), dtype=torch.float32).cuda()
+    worst = np.inf
     for step in range(sc.step.steps):
-        ccfr.xpbd_step(ctx, mesh, x, v, sp)
+        x_before = x.cpu().numpy().astype(np.float64)
+        ccfr.xpbd_step_traced(ctx, mesh, x, v, sp, trace)
+        ccfr.xpbd_step(ctx, mesh, x2, v2, sp)
         torch.cuda.synchronize()
+        assert torch.equal(x, x2) and torch.equal(v, v2), step
         xg = x.cpu().numpy().astype(np.float64)
+        tr = trace.cpu().numpy().astype(np.float64)
+        assert np.array_equal(tr[-1], xg)
         assert oracle.count_intersections(xg, sc.tris, sc.edges) == 0, step
         _, below = oracle.min_separation(xg, sc.inv_mass, sc.tris, sc.edges, 4 * xi, xi * (1 - 1e-3))
         assert below.sum() == 0, step
+        prev = x_before
+        for it in range(sc.step.iters):
+            dmin, cert, ns, _ = oracle.motion_check(prev, tr[it], sc.inv_mass, sc.tris, sc.edges,
+                                                    floor=0.5 * xi, reach=4 * xi)
+            assert cert and dmin >= xi * (1 - 1e-3), (step, it, dmin, cert, ns)
+            worst = min(worst, dmin)
+            prev = tr[it]
     code, info = ctx.sync_status(reset=True)
     assert code == 0, info
     assert info["totals"][3] > 0 and info["totals"][4] > 0
+    assert worst < 1.5 * xi
 
 
 def test_determinism_and_graph_replay(env, scenes):
