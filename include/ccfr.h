@@ -199,6 +199,26 @@ int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const
                                const float* y_in_dev, const ccfr_params* params, float* y_out_dev,
                                uint8_t* halted_dev, ccfr_stream stream);
 
+/* ccfr_project_displacements for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, no context, and no allocation of
+ * any kind.  Its scratch (device counters, the list of deferred vertices, sort
+ * keys of large regions) is one file-scope device array of about 52 MB that
+ * every GPU the library runs on holds until the process ends, found with
+ * hipGetSymbolAddress on the first call on each device.
+ *  - Limits: regions->n_verts <= 2^20 and regions->cap <= 2^22 half-spaces;
+ *    larger calls return CCFR_ERR_CAPACITY before anything is enqueued.
+ *  - Arguments as in ccfr_project_displacements; status_dev (nullable, device
+ *    uint32) receives the call's device status bits (64 = a non-finite
+ *    proposal, which gets y = 0 and halted = 1), written on `stream` after the
+ *    projection.
+ *  - Every call on one GPU shares that GPU's array: calls ordered on one
+ *    stream are safe, calls that overlap on one GPU (several streams or host
+ *    threads) race. */
+int ccfr_project_displacements_noalloc(const ccfr_regions* regions, const float* inv_mass_dev,
+                                       const float* y_in_dev, const ccfr_params* params, float* y_out_dev,
+                                       uint8_t* halted_dev, uint32_t* status_dev, ccfr_stream stream);
+
 /* One substep (Alg. 4 without response, friction or early exit), in place on
  * x_dev and v_dev ([n_verts][3] device):
  *   x~ = x + dt v + dt^2 g for dynamic vertices; lambda = 0;

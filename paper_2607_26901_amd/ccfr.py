@@ -64,7 +64,8 @@ class StatusInfo(C.Structure):
 
 EXPORTS = ["ccfr_status_string", "ccfr_create", "ccfr_destroy", "ccfr_mesh_create", "ccfr_mesh_destroy",
            "ccfr_mesh_edges", "ccfr_mesh_inv_mass_dev", "ccfr_reserve", "ccfr_build_candidates",
-           "ccfr_build_regions", "ccfr_project_displacements", "ccfr_xpbd_step", "ccfr_xpbd_step_traced",
+           "ccfr_build_regions", "ccfr_project_displacements", "ccfr_project_displacements_noalloc",
+           "ccfr_xpbd_step", "ccfr_xpbd_step_traced",
            "ccfr_sync_status",
            "ccfr_profile_enable", "ccfr_profile_read", "ccfr_set_tuning", "ccfr_get_tuning",
            "ccfr_batch_create", "ccfr_batch_destroy", "ccfr_batch_footprint", "ccfr_batch_add",
@@ -98,6 +99,8 @@ def load():
     lib.ccfr_build_regions.argtypes = [vp, vp, vp, C.POINTER(Candidates), C.POINTER(Params),
                                        C.POINTER(Regions), vp]
     lib.ccfr_project_displacements.argtypes = [vp, C.POINTER(Regions), vp, vp, C.POINTER(Params), vp, vp, vp]
+    lib.ccfr_project_displacements_noalloc.argtypes = [C.POINTER(Regions), vp, vp, C.POINTER(Params), vp, vp,
+                                                       vp, vp]
     lib.ccfr_xpbd_step.argtypes = [vp, vp, vp, vp, C.POINTER(StepParams), vp]
     lib.ccfr_xpbd_step_traced.argtypes = [vp, vp, vp, vp, C.POINTER(StepParams), vp, vp]
     lib.ccfr_sync_status.argtypes = [vp, vp, C.POINTER(StatusInfo), C.c_int]
@@ -400,6 +403,23 @@ def project_displacements(ctx: Context, regions: Regions, inv_mass, y_in, params
     _check(ctx.lib.ccfr_project_displacements(ctx.h, C.byref(regions), wp, yp, C.byref(prm), op, hp,
                                               _stream(stream)),
            "ccfr_project_displacements")
+
+
+def project_displacements_noalloc(regions: Regions, inv_mass, y_in, params, y_out, halted=None, status=None,
+                                  stream=None):
+    """ccfr_project_displacements_noalloc: the projection without a context and
+    without any allocation (status: optional device uint32 of one element)."""
+    lib = load()
+    prm = params if isinstance(params, Params) else make_params(params)
+    n = regions.n_verts
+    wp = _dev(inv_mass, "float32", n, "inv_mass")
+    yp = _dev(y_in, "float32", 3 * n, "y_in")
+    op = _dev(y_out, "float32", 3 * n, "y_out")
+    hp = _dev(halted, "uint8", n, "halted", optional=True)
+    sp = _dev(status, "int32", 1, "status", optional=True)
+    _check(lib.ccfr_project_displacements_noalloc(C.byref(regions), wp, yp, C.byref(prm), op, hp, sp,
+                                                  _stream(stream)),
+           "ccfr_project_displacements_noalloc")
 
 
 def xpbd_step(ctx: Context, mesh: Mesh, x, v, step_params: StepParams, stream=None):
