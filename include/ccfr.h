@@ -55,41 +55,57 @@ typedef enum {
     CCFR_ERR_NO_MEMORY = -7      /* a device allocation failed                          */
 } ccfr_status;
 
-/* Collision parameters of one mesh (Sec. 3.1-3.2, Sec. 4.1, App. A-B). */
+/* Collision parameters of one mesh (Sec. 3.1-3.3, Sec. 4.1, App. A-B). */
 typedef struct {
     float r;            /* search radius; pairs are kept while phi < 2r, and no vertex
                            moves more than r per iteration (Alg. 4 clamp)              */
     float xi;           /* offset: minimum separation (phi = distance - xi)             */
-    float delta;        /* repulsion range: only widens the boxes here (Sec. 4.1)       */
+    float delta;        /* repulsion range (Sec. 3.3): widens the boxes (Sec. 4.1) and,
+                           with CCFR_FLAG_RESPONSE, is the range of the soft response  */
     float guard;        /* extra box padding keeping the FP32 box test conservative     */
     float eps_retract;  /* retraction margin of Alg. 2 (Sec. 3.2), e.g. 1e-6 m          */
     float eps_plesnik;  /* tolerance of Alg. 1, e.g. 1e-6                                */
     int32_t max_passes; /* pass budget of Alg. 2 (its n_maxIterations), >= 1            */
-    int32_t flags;      /* reserved, 0                                                   */
+    int32_t flags;      /* CCFR_FLAG_RESPONSE or 0                                       */
+    /* soft response and friction (Sec. 3.3), used with CCFR_FLAG_RESPONSE only */
+    float resp_compliance; /* alpha = 1/k of the response constraint, >= 0           */
+    float vis_width;    /* delta_v of the visibility weights (0: every weight is 1)     */
+    float mu_s, mu_k;   /* static and kinetic friction coefficients, >= 0              */
 } ccfr_params;
+
+/* ccfr_params.flags: run applyResponse of Alg. 4 (the soft response with
+ * visibility weights and friction of Sec. 3.3) between the XPBD constraints and
+ * the projection of every iteration.  Needs 0 < delta <= 2r (the response acts
+ * on the pairs of the vertex's region). */
+#define CCFR_FLAG_RESPONSE 1
 
 /* One half-space of a vertex region (Alg. 2's constraint tuple): a displacement
  * y of the vertex is admissible iff n . y + d >= 0.  phi is the pair's
- * separation measure (distance - xi), key = kind << 62 | a << 31 | b names the
- * primitive pair (kind 1 = vertex-face (vertex a, triangle b), 2 = edge-edge
- * (edges a < b), 3 = point-point (particles a < b)).  32 bytes. */
+ * separation measure (distance - xi), share the vertex side's share s of it
+ * (d = s phi, Eq. 2), key = kind << 62 | a << 31 | b names the primitive pair
+ * (kind 0 = particle-edge (free particle a, edge b), 1 = vertex-face (vertex a,
+ * triangle b), 2 = edge-edge (edges a < b), 3 = point-point (particles a < b)).
+ * 32 bytes. */
 typedef struct {
     float n[3];
     float d;
     float phi;
-    uint32_t flags;
+    float share;
     uint64_t key;
 } ccfr_halfspace;
 
-/* Candidate pair lists (Sec. 4.1, Alg. 3 inputs).  Pointers are device memory.
- * counts_dev[0..2] hold |VF|, |EE|, |VV| on the device after the build; a count
- * above its capacity means the list overflowed (CCFR_ERR_CAPACITY). */
+/* Candidate pair lists (Sec. 4.1, Alg. 3 inputs, and the point interactions
+ * of Sec. 4.2).  Pointers are device memory.  counts_dev[0..3] hold |VF|, |EE|,
+ * |VV|, |VE| on the device after the build; a count above its capacity means
+ * the list overflowed (CCFR_ERR_CAPACITY). */
 typedef struct {
     int32_t* vf;          /* [cap_vf][2]: (vertex, triangle), vertex not in triangle  */
     int32_t* ee;          /* [cap_ee][2]: (e, e') with e < e', sharing no vertex       */
     int32_t* vv;          /* [cap_vv][2]: free particles (i, j), i < j                 */
-    int32_t* counts_dev;  /* [3]                                                       */
+    int32_t* counts_dev;  /* [4]                                                       */
     int64_t cap_vf, cap_ee, cap_vv;
+    int32_t* ve;          /* [cap_ve][2]: (free particle, edge)                        */
+    int64_t cap_ve;
 } ccfr_candidates;
 
 /* Per-vertex regions in CSR form.  Pointers are device memory: the half-spaces
@@ -110,12 +126,20 @@ typedef struct {
                             stretch pass and the projection                        */
     float alpha;         /* stretch compliance (XPBD distance constraints)         */
     ccfr_params collision;
+    int32_t early_exit;  /* 0: exactly `iters` iterations.  1: the convergence
+                            check of Alg. 4 ends them early: after an iteration
+                            whose every dynamic vertex's step |y*| came within
+                            conv_tol of its proposal |p - x| (the expected
+                            advancement: nothing clamped or projected away),
+                            the remaining iterations are skipped on the device */
+    float conv_tol;      /* metres, >= 0 (early_exit only)                          */
 } ccfr_step_params;
 
 /* Device-side status and counters, copied out by ccfr_sync_status. */
 typedef struct {
-    uint32_t status_bits;   /* sticky: 1 VF, 2 EE, 4 VV, 8 half-spaces, 16 large
-                               primitives, 32 contacts overflowed; 64 non-finite    */
+    uint32_t status_bits;   /* sticky: 1 VF, 2 EE, 4 VV, 128 VE, 8 half-spaces, 16
+                               large primitives, 32 contacts overflowed; 64
+                               non-finite                                           */
     int32_t last_counts[3]; /* |VF|, |EE|, |VV| of the last candidate build          */
     int32_t last_contacts;  /* pairs with phi < 2r in the last region build          */
     int32_t last_halfspaces;/* half-spaces in the last region build                  */
@@ -128,6 +152,15 @@ typedef struct {
                                region builds                                        */
     int64_t candidate_builds; /* candidate builds closed since the last reset (the
                                pair totals are summed over these)                   */
+    int64_t iterations_run; /* solver iterations of substeps run since the last
+                               reset (fewer than iters x substeps with early_exit)  */
+    int64_t halt_runs[2];   /* halts that made a vertex halt in 2, and in 3 or more,
+                               consecutive iterations of one substep                */
+    int32_t max_halt_run;   /* longest such run of one vertex (Sec. 4.3 reports at
+                               most 2 consecutive halts)                            */
+    int32_t last_ve;        /* |VE| of the last candidate build                       */
+    int64_t need_ve;        /* largest |VE| seen since the last reset                 */
+    int64_t total_ve;       /* VE pairs accumulated since the last reset              */
 } ccfr_status_info;
 
 typedef struct ccfr_ctx ccfr_ctx;
@@ -148,7 +181,9 @@ void ccfr_destroy(ccfr_ctx* ctx);
  *  triangles, unique and sorted), inv_mass [n_verts] (0 = static or pinned),
  *  rest_x [n_verts][3] (NULL: no stretch constraints).  Builds the stretch rest
  *  lengths, the greedy edge colouring used by the Gauss-Seidel pass, the list of
- *  free particles (vertices in no edge and no triangle) and the grid cell size. */
+ *  free particles (vertices in no edge and no triangle) and the grid cell size.
+ *  Vertex, triangle and (derived) edge counts are at most 2^30; more, an index
+ *  out of range or an edge (a, a) is CCFR_ERR_INVALID_ARG. */
 int ccfr_mesh_create(ccfr_ctx* ctx, int32_t n_verts, const int32_t* tris, int32_t n_tris,
                      const int32_t* edges, int32_t n_edges, const float* inv_mass,
                      const float* rest_x, ccfr_mesh** out);
@@ -160,11 +195,11 @@ const float* ccfr_mesh_inv_mass_dev(const ccfr_mesh* mesh);
 
 /* Grow the workspace so that lists of the given sizes fit (0 keeps a size).
  * Waits for the context's previous work.  Invalidates captured step graphs. */
-int ccfr_reserve(ccfr_ctx* ctx, int64_t vf, int64_t ee, int64_t vv, int64_t contacts,
+int ccfr_reserve(ccfr_ctx* ctx, int64_t vf, int64_t ee, int64_t vv, int64_t ve, int64_t contacts,
                  int64_t halfspaces, ccfr_stream stream);
 
-/* Broad phase (Sec. 4.1): every vertex-face, edge-edge and particle-particle pair
- * whose padded FP32 boxes overlap, with pad = fl32(r + xi/2 + delta/2 + guard)
+/* Broad phase (Sec. 4.1): every vertex-face, edge-edge, particle-particle and
+ * particle-edge pair whose padded FP32 boxes overlap, with pad = fl32(r + xi/2 + delta/2 + guard)
  * and per axis lo = fl32(min - pad), hi = fl32(max + pad); pairs whose vertices
  * all have zero inverse mass are skipped.  x_anchor_dev: [n_verts][3] device
  * (may be NULL for a mesh with no vertices).  A primitive with a non-finite
@@ -199,6 +234,22 @@ int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const
                                const float* y_in_dev, const ccfr_params* params, float* y_out_dev,
                                uint8_t* halted_dev, ccfr_stream stream);
 
+/* applyResponse of Alg. 4 (Sec. 3.3) per vertex v with proposed displacement
+ * y_in[v] and its region (built at the anchor): the contacts whose gap beyond
+ * the offset at the proposal, d_c = (n_c . y + d_c) / share_c, is below delta
+ * get the XPBD update of the response constraint max(0, delta - d_c) with
+ * compliance resp_compliance / (w_c dt^2), w_c the product of the visibility
+ * factors 1 - S((d_c - d_j) / vis_width) over the vertex's other active
+ * contacts (S the cubic smoothstep); the vertex takes its share of each
+ * correction, innermost contact first, each followed by friction on the
+ * tangential part t of the displacement (removed if |t| < mu_s times the
+ * correction, else shortened by mu_k times it).  Arguments as in
+ * ccfr_project_displacements, plus dt > 0; params->flags must hold
+ * CCFR_FLAG_RESPONSE (else y_out = y_in).  y_out may alias y_in. */
+int ccfr_apply_response(ccfr_ctx* ctx, const ccfr_regions* regions, const float* inv_mass_dev,
+                        const float* y_in_dev, const ccfr_params* params, float dt, float* y_out_dev,
+                        ccfr_stream stream);
+
 /* ccfr_project_displacements for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same kernels and results, no context, and no allocation of
@@ -219,12 +270,13 @@ int ccfr_project_displacements_noalloc(const ccfr_regions* regions, const float*
                                        const float* y_in_dev, const ccfr_params* params, float* y_out_dev,
                                        uint8_t* halted_dev, uint32_t* status_dev, ccfr_stream stream);
 
-/* One substep (Alg. 4 without response, friction or early exit), in place on
- * x_dev and v_dev ([n_verts][3] device):
+/* One substep (Alg. 4), in place on x_dev and v_dev ([n_verts][3] device):
  *   x~ = x + dt v + dt^2 g for dynamic vertices; lambda = 0;
  *   per iteration: candidates and regions at the anchor x; p = x~; one
  *   Gauss-Seidel pass of XPBD distance constraints over the edge colours
- *   (lambda kept across iterations); x += project(p - x);
+ *   (lambda kept across iterations); with CCFR_FLAG_RESPONSE the response and
+ *   friction of ccfr_apply_response on p; x += project(p - x); with
+ *   sp->early_exit, the convergence check (see ccfr_step_params);
  *   finally v = (x - x_start) / dt.
  * The first call for a (mesh, x, v, parameters) combination records a HIP graph
  * of the whole substep; later calls replay it.  A mesh with no vertices is a
@@ -303,6 +355,10 @@ typedef struct {
     int32_t pair_split;
     int32_t pair_reuse;
     int32_t pair_skin;
+    int32_t broad_phase; /* 0 (default): the multi-level hash grid; 1: a linear
+                            bounding-volume hierarchy over the padded boxes of the
+                            targets (the analogue of the paper's AABB tree, Sec.
+                            4.1), rebuilt with every candidate build; the same pairs */
 } ccfr_tuning;
 int ccfr_set_tuning(ccfr_ctx* ctx, const ccfr_tuning* tuning);
 int ccfr_get_tuning(const ccfr_ctx* ctx, ccfr_tuning* tuning);
@@ -333,7 +389,9 @@ int64_t ccfr_batch_footprint(int32_t n_verts, int32_t n_tris, int32_t n_edges);
 /* Admit a mesh: host arrays as in ccfr_mesh_create, plus initial x and v
  * ([n_verts][3] float32, finite) and its step parameters.  The collision part
  * of `sp` is per mesh; dt, gravity, iters and alpha must equal those of the
- * meshes already resident (else CCFR_ERR_INVALID_ARG).  *slot receives the
+ * meshes already resident, early_exit must be 0 (a batch runs its meshes'
+ * iterations together) and the collision flags must not ask for the response
+ * (else CCFR_ERR_INVALID_ARG).  *slot receives the
  * lowest free slot id.  CCFR_ERR_CAPACITY if no slot or pool space is free;
  * nothing changes then.  Copies are made on `stream`, and the call waits for
  * them. */

@@ -16,17 +16,18 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libccfr_oracle.so")
 
-KIND_VF, KIND_EE, KIND_VV = 1, 2, 3
+KIND_VE, KIND_VF, KIND_EE, KIND_VV = 0, 1, 2, 3
 
-HS_DTYPE = np.dtype([("n", "<f8", (3,)), ("d", "<f8"), ("phi", "<f8"), ("key", "<u8"),
+HS_DTYPE = np.dtype([("n", "<f8", (3,)), ("d", "<f8"), ("phi", "<f8"), ("share", "<f8"), ("key", "<u8"),
                      ("fragile", "<i4"), ("pad", "<i4")])
-assert HS_DTYPE.itemsize == 56
+assert HS_DTYPE.itemsize == 64
 
 
 class OrcParams(C.Structure):
     _fields_ = [("r", C.c_double), ("xi", C.c_double), ("delta", C.c_double), ("guard", C.c_double),
                 ("eps_retract", C.c_double), ("eps_plesnik", C.c_double),
-                ("max_passes", C.c_int32), ("pad_", C.c_int32)]
+                ("max_passes", C.c_int32), ("response", C.c_int32), ("resp_compliance", C.c_double),
+                ("vis_width", C.c_double), ("mu_s", C.c_double), ("mu_k", C.c_double)]
 
 
 class OrcMesh(C.Structure):
@@ -37,7 +38,8 @@ class OrcMesh(C.Structure):
 
 class OrcStepParams(C.Structure):
     _fields_ = [("dt", C.c_double), ("g", C.c_double * 3), ("iters", C.c_int32),
-                ("n_colors", C.c_int32), ("alpha", C.c_double)]
+                ("n_colors", C.c_int32), ("alpha", C.c_double), ("early_exit", C.c_int32),
+                ("pad_", C.c_int32), ("conv_tol", C.c_double)]
 
 
 _lib = None
@@ -53,13 +55,13 @@ def load():
         vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         lib.orc_box_pad.restype = C.c_float
         lib.orc_box_pad.argtypes = [vp]
-        lib.orc_candidates.argtypes = [vp, vp, vp, i64, vp, i64, vp, i64, vp]
+        lib.orc_candidates.argtypes = [vp, vp, vp, i64, vp, i64, vp, i64, vp, i64, vp]
         for f in ("orc_vf_tris_of_vertex", "orc_vf_verts_of_tri", "orc_ee_partners_of_edge",
-                  "orc_vv_partners_of_vertex"):
+                  "orc_vv_partners_of_vertex", "orc_ve_edges_of_vertex", "orc_ve_verts_of_edge"):
             getattr(lib, f).restype = i64
             getattr(lib, f).argtypes = [vp, vp, i32, vp, i64]
         lib.orc_regions.restype = i64
-        lib.orc_regions.argtypes = [vp, vp, vp, i64, vp, i64, vp, i64, vp, vp, i64, vp]
+        lib.orc_regions.argtypes = [vp, vp, vp, i64, vp, i64, vp, i64, vp, i64, vp, vp, i64, vp]
         lib.orc_vertex_region.restype = i64
         lib.orc_vertex_region.argtypes = [vp, vp, i32, vp, i64]
         lib.orc_project.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -67,6 +69,8 @@ def load():
         lib.orc_project_one.argtypes = [vp, dbl, vp, vp, i64, vp, vp, vp]
         lib.orc_project_branches.restype = C.c_int
         lib.orc_project_branches.argtypes = [vp, dbl, vp, vp, i64, vp, vp, vp, C.c_int, vp]
+        lib.orc_apply_response.argtypes = [vp, dbl, vp, i64, dbl, vp, vp]
+        lib.orc_response.argtypes = [vp, vp, vp, vp, dbl, vp, vp]
         lib.orc_orthogonal_projection.argtypes = [vp, vp, vp, dbl, vp, dbl]
         lib.orc_closest_point_triangle.restype = C.c_int
         lib.orc_closest_point_triangle.argtypes = [vp] * 6
@@ -88,6 +92,7 @@ def load():
         lib.orc_orient2d_sign.restype = C.c_int
         lib.orc_orient2d_sign.argtypes = [vp] * 3
         lib.orc_num_threads.restype = C.c_int
+        lib.orc_set_num_threads.argtypes = [C.c_int]
         lib.orc_fragile_reasons.argtypes = [vp, C.c_int]
         _lib = lib
     return _lib
@@ -100,8 +105,10 @@ def _p(a: np.ndarray):
 def params(p) -> OrcParams:
     """From a scenes.Params (its float values are used as given)."""
     f = lambda v: float(np.float32(v))  # the GPU path receives these as FP32
+    g = lambda name, default=0.0: f(getattr(p, name, default))
     return OrcParams(f(p.r), f(p.xi), f(p.delta), f(p.guard), f(p.eps_retract), f(p.eps_plesnik),
-                     int(p.max_passes), 0)
+                     int(p.max_passes), int(bool(getattr(p, "response", False))), g("resp_compliance"),
+                     g("vis_width"), g("mu_s"), g("mu_k"))
 
 
 class Mesh:
@@ -127,17 +134,17 @@ def box_pad(p) -> np.float32:
 def candidates(mesh: Mesh, p) -> dict:
     lib = load()
     prm = params(p)
-    counts = np.zeros(3, np.int64)
+    counts = np.zeros(4, np.int64)
     n = len(mesh.x)
-    caps = [8 * n + 64, 8 * len(mesh.edges) + 64, 8 * n + 64]
+    caps = [8 * n + 64, 8 * len(mesh.edges) + 64, 8 * n + 64, 8 * n + 64]
     while True:
         bufs = [np.zeros((c, 2), np.int32) for c in caps]
         lib.orc_candidates(mesh.ref, C.byref(prm), _p(bufs[0]), caps[0], _p(bufs[1]), caps[1],
-                           _p(bufs[2]), caps[2], _p(counts))
-        if all(counts[k] <= caps[k] for k in range(3)):
+                           _p(bufs[2]), caps[2], _p(bufs[3]), caps[3], _p(counts))
+        if all(counts[k] <= caps[k] for k in range(4)):
             return {"vf": bufs[0][:counts[0]].copy(), "ee": bufs[1][:counts[1]].copy(),
-                    "vv": bufs[2][:counts[2]].copy()}
-        caps = [int(max(counts[k], caps[k])) for k in range(3)]
+                    "vv": bufs[2][:counts[2]].copy(), "ve": bufs[3][:counts[3]].copy()}
+        caps = [int(max(counts[k], caps[k])) for k in range(4)]
 
 
 def _partners(fn, mesh, p, idx) -> np.ndarray:
@@ -167,6 +174,14 @@ def vv_partners_of_vertex(mesh, p, v):
     return _partners(load().orc_vv_partners_of_vertex, mesh, p, v)
 
 
+def ve_edges_of_vertex(mesh, p, v):
+    return _partners(load().orc_ve_edges_of_vertex, mesh, p, v)
+
+
+def ve_verts_of_edge(mesh, p, e):
+    return _partners(load().orc_ve_verts_of_edge, mesh, p, e)
+
+
 def regions(mesh: Mesh, p, cands: dict):
     """Returns (offsets [N+1] int64, half-spaces [H] HS_DTYPE, n_degenerate)."""
     lib = load()
@@ -174,14 +189,15 @@ def regions(mesh: Mesh, p, cands: dict):
     vf = np.ascontiguousarray(cands["vf"], np.int32)
     ee = np.ascontiguousarray(cands["ee"], np.int32)
     vv = np.ascontiguousarray(cands["vv"], np.int32)
+    ve = np.ascontiguousarray(cands.get("ve", np.zeros((0, 2))), np.int32).reshape(-1, 2)
     n = len(mesh.x)
     offsets = np.zeros(n + 1, np.int64)
     stats = np.zeros(4, np.int64)
     H = lib.orc_regions(mesh.ref, C.byref(prm), _p(vf), len(vf), _p(ee), len(ee), _p(vv), len(vv),
-                        _p(offsets), None, 0, _p(stats))
+                        _p(ve), len(ve), _p(offsets), None, 0, _p(stats))
     hs = np.zeros(max(H, 1), HS_DTYPE)
     lib.orc_regions(mesh.ref, C.byref(prm), _p(vf), len(vf), _p(ee), len(ee), _p(vv), len(vv),
-                    _p(offsets), _p(hs), H, _p(stats))
+                    _p(ve), len(ve), _p(offsets), _p(hs), H, _p(stats))
     return offsets, hs[:H], int(stats[0])
 
 
@@ -250,12 +266,37 @@ def project_branches(p, inv_mass, x, hs, y, cap=256):
     return outs[:n].copy(), halts[:n].copy(), bool(comp.value)
 
 
-def make_halfspaces(n, d, keys=None, phi=None) -> np.ndarray:
+def apply_response(p, inv_mass, hs, dt, y):
+    """applyResponse (Sec. 3.3) for one vertex: the displacement after the
+    response and friction of its active contacts."""
+    prm = params(p)
+    hs = np.ascontiguousarray(hs, HS_DTYPE)
+    hs1 = hs if len(hs) else np.zeros(1, HS_DTYPE)
+    y = np.ascontiguousarray(y, np.float64)
+    out = np.zeros(3)
+    load().orc_apply_response(C.byref(prm), float(inv_mass), _p(hs1), len(hs), float(dt), _p(y), _p(out))
+    return out
+
+
+def response(mesh: "Mesh", p, offsets, hs, dt, y):
+    """applyResponse for every vertex of a mesh."""
+    prm = params(p)
+    offsets = np.ascontiguousarray(offsets, np.int64)
+    hs = np.ascontiguousarray(hs, HS_DTYPE)
+    hs1 = hs if len(hs) else np.zeros(1, HS_DTYPE)
+    y = np.ascontiguousarray(y, np.float64).reshape(-1, 3)
+    out = np.zeros_like(y)
+    load().orc_response(mesh.ref, C.byref(prm), _p(offsets), _p(hs1), float(dt), _p(y), _p(out))
+    return out
+
+
+def make_halfspaces(n, d, keys=None, phi=None, share=None) -> np.ndarray:
     n = np.asarray(n, np.float64).reshape(-1, 3)
     hs = np.zeros(len(n), HS_DTYPE)
     hs["n"] = n
     hs["d"] = np.asarray(d, np.float64).reshape(-1)
     hs["phi"] = hs["d"] if phi is None else phi
+    hs["share"] = 1.0 if share is None else share
     hs["key"] = np.arange(len(n), dtype=np.uint64) if keys is None else np.asarray(keys, np.uint64)
     return hs
 
@@ -316,7 +357,7 @@ class Sim:
         self.rest = np.linalg.norm(rx[self.edges[:, 0]] - rx[self.edges[:, 1]], axis=1) \
             if len(self.edges) else np.zeros(1)
         self.color, self.n_colors = color_edges(len(self.x), self.edges)
-        self.counters = np.zeros(8, np.int64)
+        self.counters = np.zeros(12, np.int64)
 
     def step(self, iters=None, trace=False):
         """One substep; with trace=True returns the anchor after every iteration
@@ -324,7 +365,8 @@ class Sim:
         sp = self.scene.step
         osp = OrcStepParams(float(np.float32(sp.dt)), (C.c_double * 3)(*[float(np.float32(g)) for g in sp.gravity]),
                             int(sp.iters if iters is None else iters), self.n_colors,
-                            float(np.float32(sp.alpha)))
+                            float(np.float32(sp.alpha)), int(bool(getattr(sp, "early_exit", False))), 0,
+                            float(np.float32(getattr(sp, "conv_tol", 0.0))))
         prm = params(self.scene.params)
         tr = np.zeros((osp.iters, len(self.x), 3)) if trace else None
         load().orc_xpbd_step(len(self.x), len(self.tris), len(self.edges), _p(self.tris),
@@ -344,12 +386,12 @@ def count_intersections(x, tris, edges) -> int:
 
 
 def min_separation(x, inv_mass, tris, edges, reach, below):
-    """Returns (min distance (capped at reach), counts below [VF, EE, VV])."""
+    """Returns (min distance (capped at reach), counts below [VF, EE, VV, VE])."""
     x = np.ascontiguousarray(x, np.float64)
     w = np.ascontiguousarray(inv_mass, np.float64)
     tris = np.ascontiguousarray(tris, np.int32)
     edges = np.ascontiguousarray(edges, np.int32)
-    cnt = np.zeros(3, np.int64)
+    cnt = np.zeros(4, np.int64)
     d = load().orc_min_separation(len(x), _p(x), _p(w), len(tris), _p(tris), len(edges), _p(edges),
                                   float(reach), float(below), _p(cnt))
     return float(d), cnt
@@ -361,7 +403,7 @@ def min_separation_grid(x, inv_mass, tris, edges, reach, below):
     w = np.ascontiguousarray(inv_mass, np.float64)
     tris = np.ascontiguousarray(tris, np.int32)
     edges = np.ascontiguousarray(edges, np.int32)
-    cnt = np.zeros(3, np.int64)
+    cnt = np.zeros(4, np.int64)
     d = load().orc_min_separation_grid(len(x), _p(x), _p(w), len(tris), _p(tris), len(edges), _p(edges),
                                        float(reach), float(below), _p(cnt))
     return float(d), cnt
@@ -396,6 +438,10 @@ def orient2d_sign(a, b, c) -> int:
 
 def num_threads() -> int:
     return int(load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    load().orc_set_num_threads(int(n))
 
 
 def fragile_reasons(reset=True) -> np.ndarray:

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libccfr_oracle.so")
 SOURCES = ["oracle_geometry.c", "oracle_candidates.c", "oracle_regions.c",
-           "oracle_projection.c", "oracle_xpbd.c", "oracle_checks.c"]
+           "oracle_projection.c", "oracle_response.c", "oracle_xpbd.c", "oracle_checks.c"]
 
 
 def build(verbose: bool = False) -> str:

@@ -16,7 +16,9 @@
  * Pair kinds (Alg. 3 inputs plus the point-point interactions of Sec. 4.2):
  *   VF (v, t): v is not a vertex of t;
  *   EE (e, e'), e < e': the edges share no vertex;
- *   VV (i, j), i < j: both are free particles (in no edge and no triangle).
+ *   VV (i, j), i < j: both are free particles (in no edge and no triangle);
+ *   VE (p, e): p is a free particle, e an edge (a particle against a strand
+ *       or a cloth edge: no other kind brings the two together).
  * A pair whose vertices all have zero inverse mass is skipped.
  *
  * Everything here is brute force over all primitive pairs: no grid or tree, so
@@ -126,6 +128,11 @@ static int is_ee(const orc_mesh* m, const boxes_t* B, int32_t e, int32_t f) {
     if (B->estat[e] && B->estat[f]) return 0;
     return overlap(&B->ebox[e], &B->ebox[f]);
 }
+static int is_ve(const boxes_t* B, int32_t p, int32_t e) {
+    if (!B->vfree[p]) return 0;
+    if (B->vstat[p] && B->estat[e]) return 0;
+    return overlap(&B->vbox[p], &B->ebox[e]);
+}
 static int is_vv(const boxes_t* B, int32_t i, int32_t j) {
     if (i == j || !B->vfree[i] || !B->vfree[j]) return 0;
     if (B->vstat[i] && B->vstat[j]) return 0;
@@ -136,7 +143,7 @@ static int is_vv(const boxes_t* B, int32_t i, int32_t j) {
  * lists in ascending order whatever the thread schedule. */
 void orc_candidates(const orc_mesh* m, const orc_params* prm,
                     int32_t* vf, int64_t cap_vf, int32_t* ee, int64_t cap_ee,
-                    int32_t* vv, int64_t cap_vv, int64_t counts[3]) {
+                    int32_t* vv, int64_t cap_vv, int32_t* ve, int64_t cap_ve, int64_t counts[4]) {
     boxes_t B;
     boxes_build(m, prm, &B);
     int nmax = m->n_verts > m->n_edges ? m->n_verts : m->n_edges;
@@ -208,8 +215,71 @@ void orc_candidates(const orc_mesh* m, const orc_params* prm,
                 }
         }
     }
+
+    /* VE */
+    memset(cnt, 0, sizeof(int64_t) * ((size_t)nmax + 1));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int p = 0; p < m->n_verts; ++p) {
+        int64_t c = 0;
+        if (B.vfree[p])
+            for (int e = 0; e < m->n_edges; ++e) c += is_ve(&B, p, e);
+        cnt[p + 1] = c;
+    }
+    for (int p = 0; p < m->n_verts; ++p) cnt[p + 1] += cnt[p];
+    counts[3] = cnt[m->n_verts];
+    if (ve && cap_ve > 0) {
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int p = 0; p < m->n_verts; ++p) {
+            int64_t o = cnt[p];
+            if (!B.vfree[p]) continue;
+            for (int e = 0; e < m->n_edges; ++e)
+                if (is_ve(&B, p, e)) {
+                    if (o < cap_ve) { ve[2 * o] = p; ve[2 * o + 1] = e; }
+                    ++o;
+                }
+        }
+    }
     free(cnt);
     boxes_free(&B);
+}
+
+int64_t orc_ve_edges_of_vertex(const orc_mesh* m, const orc_params* prm, int32_t v, int32_t* out, int64_t cap) {
+    unsigned char* fr = free_particle_flags(m);
+    int64_t n = 0;
+    if (fr[v]) {
+        float pad = orc_box_pad(prm);
+        fbox bv = box_of(m, &v, 1, pad);
+        int sv = all_static(m, &v, 1);
+        for (int e = 0; e < m->n_edges; ++e) {
+            const int32_t* ev = m->edges + 2 * e;
+            if (sv && all_static(m, ev, 2)) continue;
+            fbox be = box_of(m, ev, 2, pad);
+            if (!overlap(&bv, &be)) continue;
+            if (n < cap) out[n] = e;
+            ++n;
+        }
+    }
+    free(fr);
+    return n;
+}
+
+int64_t orc_ve_verts_of_edge(const orc_mesh* m, const orc_params* prm, int32_t e, int32_t* out, int64_t cap) {
+    unsigned char* fr = free_particle_flags(m);
+    float pad = orc_box_pad(prm);
+    const int32_t* ev = m->edges + 2 * e;
+    fbox be = box_of(m, ev, 2, pad);
+    int se = all_static(m, ev, 2);
+    int64_t n = 0;
+    for (int v = 0; v < m->n_verts; ++v) {
+        if (!fr[v]) continue;
+        if (se && all_static(m, &v, 1)) continue;
+        fbox bv = box_of(m, &v, 1, pad);
+        if (!overlap(&bv, &be)) continue;
+        if (n < cap) out[n] = v;
+        ++n;
+    }
+    free(fr);
+    return n;
 }
 
 int64_t orc_vf_tris_of_vertex(const orc_mesh* m, const orc_params* prm, int32_t v,

@@ -317,7 +317,7 @@ int64_t orc_count_edge_tri_intersections(int32_t n_verts, const double* x, int32
 
 double orc_min_separation(int32_t n_verts, const double* x, const double* inv_mass, int32_t n_tris,
                           const int32_t* tris, int32_t n_edges, const int32_t* edges, double reach,
-                          double below, int64_t out_counts[3]) {
+                          double below, int64_t out_counts[4]) {
     unsigned char* fr = (unsigned char*)malloc((size_t)n_verts + 1);
     memset(fr, 1, (size_t)n_verts);
     for (int32_t t = 0; t < 3 * n_tris; ++t) fr[tris[t]] = 0;
@@ -339,9 +339,9 @@ double orc_min_separation(int32_t n_verts, const double* x, const double* inv_ma
     }
     qsort(it, (size_t)n, sizeof(item_t), cmp_lo);
     double best2 = reach * reach;
-    int64_t c0 = 0, c1 = 0, c2 = 0;
+    int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
     const double below2 = below * below;
-#pragma omp parallel for schedule(dynamic, 256) reduction(min : best2) reduction(+ : c0, c1, c2)
+#pragma omp parallel for schedule(dynamic, 256) reduction(min : best2) reduction(+ : c0, c1, c2, c3)
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t j = i + 1; j < n && it[j].lo[0] <= it[i].hi[0]; ++j) {
             if (it[j].lo[1] > it[i].hi[1] || it[i].lo[1] > it[j].hi[1]) continue;
@@ -369,6 +369,12 @@ double orc_min_separation(int32_t n_verts, const double* x, const double* inv_ma
                 double dv[3] = {x[3 * a] - x[3 * b], x[3 * a + 1] - x[3 * b + 1], x[3 * a + 2] - x[3 * b + 2]};
                 dist2 = d3(dv, dv);
                 kind = 2;
+            } else if ((ki == 0 && kj == 2) || (ki == 2 && kj == 0)) {    /* particle - edge */
+                int32_t p = ki == 0 ? it[i].id : it[j].id;
+                const int32_t* e = edges + 2 * (ki == 2 ? it[i].id : it[j].id);
+                if (!fr[p]) continue;
+                dist2 = pt_seg2(x + 3 * p, x + 3 * e[0], x + 3 * e[1]);
+                kind = 3;
             } else {
                 continue;
             }
@@ -376,11 +382,12 @@ double orc_min_separation(int32_t n_verts, const double* x, const double* inv_ma
             if (dist2 < below2) {
                 if (kind == 0) c0++;
                 else if (kind == 1) c1++;
-                else c2++;
+                else if (kind == 2) c2++;
+                else c3++;
             }
         }
     }
-    if (out_counts) { out_counts[0] = c0; out_counts[1] = c1; out_counts[2] = c2; }
+    if (out_counts) { out_counts[0] = c0; out_counts[1] = c1; out_counts[2] = c2; out_counts[3] = c3; }
     free(it);
     free(fr);
     return sqrt(best2);
@@ -389,8 +396,8 @@ double orc_min_separation(int32_t n_verts, const double* x, const double* inv_ma
 /* Certified sampled check of a straight-line motion x(t) = (1 - t) x0 + t x1,
  * t in [0, 1] (one solver iteration moves every vertex along such a line: the
  * anchor update of Alg. 4).  The distance between a vertex and a triangle, two
- * edges or two particles whose vertices move linearly changes with t at a rate
- * of at most L = 2 max_v |x1_v - x0_v|, since each closest point is a convex
+ * edges, two particles or a particle and an edge whose vertices move
+ * linearly changes with t at a rate of at most L = 2 max_v |x1_v - x0_v|, since each closest point is a convex
  * combination of vertices that move at most that far.  So from a sample at t
  * with minimum distance d > floor, no pair can come closer than floor before
  * t + (d - floor) / L: the samples advance by exactly that step (conservative
@@ -485,6 +492,13 @@ static double item_pair_dist2(const item_t* A, const item_t* B, const double* x,
         *kind = 2;
         return d3(dv, dv);
     }
+    if ((ki == 0 && kj == 2) || (ki == 2 && kj == 0)) {
+        int32_t p = ki == 0 ? A->id : B->id;
+        const int32_t* e = edges + 2 * (ki == 2 ? A->id : B->id);
+        if (!fr[p]) return -1.0;
+        *kind = 3;
+        return pt_seg2(x + 3 * p, x + 3 * e[0], x + 3 * e[1]);
+    }
     return -1.0;
 }
 
@@ -496,7 +510,7 @@ static int boxes_overlap(const item_t* A, const item_t* B) {
 
 double orc_min_separation_grid(int32_t n_verts, const double* x, const double* inv_mass, int32_t n_tris,
                                const int32_t* tris, int32_t n_edges, const int32_t* edges, double reach,
-                               double below, int64_t out_counts[3]) {
+                               double below, int64_t out_counts[4]) {
     unsigned char* fr = (unsigned char*)malloc((size_t)n_verts + 1);
     memset(fr, 1, (size_t)n_verts);
     for (int32_t t = 0; t < 3 * n_tris; ++t) fr[tris[t]] = 0;
@@ -540,9 +554,9 @@ double orc_min_separation_grid(int32_t n_verts, const double* x, const double* i
     }
     qsort(cells, (size_t)nc, sizeof(cell_ref), cmp_cell);
     double best2 = reach * reach;
-    int64_t c0 = 0, c1 = 0, c2 = 0;
+    int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
     const double below2 = below * below;
-#pragma omp parallel for schedule(dynamic, 512) reduction(min : best2) reduction(+ : c0, c1, c2)
+#pragma omp parallel for schedule(dynamic, 512) reduction(min : best2) reduction(+ : c0, c1, c2, c3)
     for (int64_t q = 0; q < nc; ++q) {
         const int64_t i = cells[q].item;
         const int64_t cx = (int64_t)floor(it[i].lo[0] / h), cy = (int64_t)floor(it[i].lo[1] / h),
@@ -564,12 +578,17 @@ double orc_min_separation_grid(int32_t n_verts, const double* x, const double* i
                         double dist2 = item_pair_dist2(&it[i], &it[j], x, tris, edges, fr, &kind);
                         if (dist2 < 0.0) continue;
                         if (dist2 < best2) best2 = dist2;
-                        if (dist2 < below2) { if (kind == 0) c0++; else if (kind == 1) c1++; else c2++; }
+                        if (dist2 < below2) {
+                            if (kind == 0) c0++;
+                            else if (kind == 1) c1++;
+                            else if (kind == 2) c2++;
+                            else c3++;
+                        }
                     }
                 }
     }
     /* large items against every item (each large-large pair once) */
-#pragma omp parallel for schedule(dynamic, 4096) reduction(min : best2) reduction(+ : c0, c1, c2)
+#pragma omp parallel for schedule(dynamic, 4096) reduction(min : best2) reduction(+ : c0, c1, c2, c3)
     for (int64_t j = 0; j < n; ++j) {
         for (int64_t a = 0; a < nl; ++a) {
             const int64_t i = large[a];
@@ -579,10 +598,10 @@ double orc_min_separation_grid(int32_t n_verts, const double* x, const double* i
             double dist2 = item_pair_dist2(&it[i], &it[j], x, tris, edges, fr, &kind);
             if (dist2 < 0.0) continue;
             if (dist2 < best2) best2 = dist2;
-            if (dist2 < below2) { if (kind == 0) c0++; else if (kind == 1) c1++; else c2++; }
+            if (dist2 < below2) { if (kind == 0) c0++; else if (kind == 1) c1++; else if (kind == 2) c2++; else c3++; }
         }
     }
-    if (out_counts) { out_counts[0] = c0; out_counts[1] = c1; out_counts[2] = c2; }
+    if (out_counts) { out_counts[0] = c0; out_counts[1] = c1; out_counts[2] = c2; out_counts[3] = c3; }
     free(it); free(fr); free(ext); free(large); free(cells);
     return sqrt(best2);
 }

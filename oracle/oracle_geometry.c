@@ -114,3 +114,16 @@ int orc_closest_points_segments(const double a[3], const double b[3], const doub
     *t_out = t;
     return 0;
 }
+
+/* Closest point q = (1 - t) a + t b on segment ab to p (Ericson Sec. 5.1.2:
+ * the projection parameter clamped to [0, 1]).  Returns -1 for a segment of
+ * zero length (reading A8). */
+int orc_closest_point_segment(const double p[3], const double a[3], const double b[3], double* t) {
+    double ab[3], ap[3];
+    sub3(b, a, ab);
+    sub3(p, a, ap);
+    const double L = dot3(ab, ab);
+    if (L <= 0.0) return -1;
+    *t = clamp01(dot3(ap, ab) / L);
+    return 0;
+}

@@ -28,6 +28,10 @@
  *       are skipped and counted.
  *   VV  free particles i, j (Sec. 4.2 point-point interactions) use Eq. 1-2
  *       directly: n = x_p - x_q, d = w_p / (w_p + w_q) phi.
+ *   VE  a free particle p against an edge e (closest point x_B = (1-t) x_a +
+ *       t x_b on e): for p, n = x_p - x_B and d = w_p / (w_p + w_e) phi with
+ *       w_e = (1-t) w_a + t w_b; for the edge's endpoints (EV, as FV for a
+ *       face) n = x_B - x_p and d = w_e / (w_e + w_p) phi.
  * The paper's passive sets T, E, Q come from the broad phase: here they are
  * read from the candidate lists (orc_regions) or recomputed by brute force for
  * one vertex (orc_vertex_region).
@@ -56,6 +60,7 @@ static void emit(sink_t* s, const double nvec[3], double D, double phi, double s
         for (int k = 0; k < 3; ++k) h->n[k] = nvec[k] / D;
         h->d = share * phi;
         h->phi = phi;
+        h->share = share;
         h->key = key;
         h->fragile = fragile;
         h->pad_ = 0;
@@ -71,6 +76,8 @@ typedef struct {
     int n_inc_faces; const int32_t* inc_faces;             /* AdjFaces(p)                   */
     const int32_t** face_partners; const int64_t* n_face_partners; /* Q per incident face  */
     const int32_t* particles; int64_t n_particles;        /* VV partners                   */
+    const int32_t* pedges; int64_t n_pedges;              /* VE: edges passive to particle p */
+    const int32_t** edge_particles; const int64_t* n_edge_particles; /* EV per incident edge */
 } passive_t;
 
 static void narrow_phase_vertex(const orc_mesh* m, const orc_params* prm, int32_t p,
@@ -170,6 +177,47 @@ static void narrow_phase_vertex(const orc_mesh* m, const orc_params* prm, int32_
         }
     }
 
+    /* VE: free particle p against its passive edges */
+    for (int64_t i = 0; i < P->n_pedges; ++i) {
+        int32_t e = P->pedges[i];
+        const int32_t* ev = m->edges + 2 * (size_t)e;
+        double t;
+        if (orc_closest_point_segment(X(m, p), X(m, ev[0]), X(m, ev[1]), &t) < 0) { s->n_degenerate++; continue; }
+        double xb[3];
+        for (int k = 0; k < 3; ++k) xb[k] = (1.0 - t) * X(m, ev[0])[k] + t * X(m, ev[1])[k];
+        double nvec[3] = {X(m, p)[0] - xb[0], X(m, p)[1] - xb[1], X(m, p)[2] - xb[2]};
+        double D = sqrt(nvec[0] * nvec[0] + nvec[1] * nvec[1] + nvec[2] * nvec[2]);
+        double phi = D - xi;
+        if (!(phi < 2.0 * r)) continue;
+        if (D == 0.0) { s->n_degenerate++; continue; }
+        double we = (1.0 - t) * w[ev[0]] + t * w[ev[1]];
+        double wsum = w[p] + we;
+        if (wsum == 0.0) continue;
+        emit(s, nvec, D, phi, w[p] / wsum, make_key(ORC_KIND_VE, p, e), 0);
+    }
+
+    /* EV: each incident edge of p against its passive particles */
+    for (int ie = 0; ie < P->n_inc_edges && P->edge_particles; ++ie) {
+        int32_t e = P->inc_edges[ie];
+        const int32_t* ev = m->edges + 2 * (size_t)e;
+        for (int64_t i = 0; i < P->n_edge_particles[ie]; ++i) {
+            int32_t q = P->edge_particles[ie][i];
+            double t;
+            if (orc_closest_point_segment(X(m, q), X(m, ev[0]), X(m, ev[1]), &t) < 0) { s->n_degenerate++; continue; }
+            double xa[3];
+            for (int k = 0; k < 3; ++k) xa[k] = (1.0 - t) * X(m, ev[0])[k] + t * X(m, ev[1])[k];
+            double nvec[3] = {xa[0] - X(m, q)[0], xa[1] - X(m, q)[1], xa[2] - X(m, q)[2]};
+            double D = sqrt(nvec[0] * nvec[0] + nvec[1] * nvec[1] + nvec[2] * nvec[2]);
+            double phi = D - xi;
+            if (!(phi < 2.0 * r)) continue;
+            if (D == 0.0) { s->n_degenerate++; continue; }
+            double we = (1.0 - t) * w[ev[0]] + t * w[ev[1]];
+            double wsum = we + w[q];
+            if (wsum == 0.0) continue;
+            emit(s, nvec, D, phi, we / wsum, make_key(ORC_KIND_VE, q, e), 0);
+        }
+    }
+
     /* VV: free particle p against its partners (Eq. 1-2) */
     for (int64_t i = 0; i < P->n_particles; ++i) {
         int32_t q = P->particles[i];
@@ -208,7 +256,7 @@ static void csr_free(csr_t* c) { free(c->off); free(c->idx); }
 
 int64_t orc_regions(const orc_mesh* m, const orc_params* prm,
                     const int32_t* vf, int64_t n_vf, const int32_t* ee, int64_t n_ee,
-                    const int32_t* vv, int64_t n_vv,
+                    const int32_t* vv, int64_t n_vv, const int32_t* vpe, int64_t n_ve,
                     int64_t* offsets, orc_halfspace* hs, int64_t cap, int64_t stats[4]) {
     const int32_t N = m->n_verts;
     /* passive faces of each vertex, passive vertices of each face */
@@ -227,6 +275,9 @@ int64_t orc_regions(const orc_mesh* m, const orc_params* prm,
         vv2[4 * i + 2] = vv[2 * i + 1]; vv2[4 * i + 3] = vv[2 * i];
     }
     csr_t Vv = csr_build(N, 2 * n_vv, vv2, 2, vv2 + 1, 2);
+    /* VE: the edges of each free particle, the particles of each edge */
+    csr_t Pv = csr_build(N, n_ve, vpe, 2, vpe + 1, 2);
+    csr_t Pe = csr_build(m->n_edges, n_ve, vpe + 1, 2, vpe, 2);
     /* incidence */
     int32_t* ve = (int32_t*)malloc(sizeof(int32_t) * (size_t)(4 * m->n_edges + 2));
     for (int32_t e = 0; e < m->n_edges; ++e) {
@@ -250,11 +301,15 @@ int64_t orc_regions(const orc_mesh* m, const orc_params* prm,
             int64_t* nep = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ne + 1));
             const int32_t** fp = (const int32_t**)malloc(sizeof(void*) * (size_t)(nf + 1));
             int64_t* nfp = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nf + 1));
+            const int32_t** pp = (const int32_t**)malloc(sizeof(void*) * (size_t)(ne + 1));
+            int64_t* npp = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ne + 1));
             const int32_t* incE = AdjE.idx + AdjE.off[p];
             const int32_t* incF = AdjF.idx + AdjF.off[p];
             for (int i = 0; i < ne; ++i) {
                 ep[i] = Ee.idx + Ee.off[incE[i]];
                 nep[i] = Ee.off[incE[i] + 1] - Ee.off[incE[i]];
+                pp[i] = Pe.idx + Pe.off[incE[i]];
+                npp[i] = Pe.off[incE[i] + 1] - Pe.off[incE[i]];
             }
             for (int i = 0; i < nf; ++i) {
                 fp[i] = Qf.idx + Qf.off[incF[i]];
@@ -262,7 +317,8 @@ int64_t orc_regions(const orc_mesh* m, const orc_params* prm,
             }
             passive_t P = {Tv.idx + Tv.off[p], Tv.off[p + 1] - Tv.off[p],
                            ne, incE, ep, nep, nf, incF, fp, nfp,
-                           Vv.idx + Vv.off[p], Vv.off[p + 1] - Vv.off[p]};
+                           Vv.idx + Vv.off[p], Vv.off[p + 1] - Vv.off[p],
+                           Pv.idx + Pv.off[p], Pv.off[p + 1] - Pv.off[p], pp, npp};
             sink_t s;
             if (phase == 0) { s.out = NULL; s.cap = 0; }
             else {
@@ -274,7 +330,7 @@ int64_t orc_regions(const orc_mesh* m, const orc_params* prm,
             s.n_degenerate = 0;
             narrow_phase_vertex(m, prm, p, &P, &s);
             if (phase == 0) { cnt[p + 1] = s.n; ndeg_total += s.n_degenerate; }
-            free(ep); free(nep); free(fp); free(nfp);
+            free(ep); free(nep); free(fp); free(nfp); free(pp); free(npp);
         }
         if (phase == 0) {
             for (int32_t p = 0; p < N; ++p) cnt[p + 1] += cnt[p];
@@ -286,6 +342,7 @@ int64_t orc_regions(const orc_mesh* m, const orc_params* prm,
     if (stats) { stats[0] = ndeg_total; stats[1] = H; stats[2] = 0; stats[3] = 0; }
     free(cnt);
     csr_free(&Tv); csr_free(&Qf); csr_free(&Ee); csr_free(&Vv); csr_free(&AdjE); csr_free(&AdjF);
+    csr_free(&Pv); csr_free(&Pe);
     free(ee2); free(vv2); free(ve); free(vt);
     return H;
 }
@@ -324,13 +381,25 @@ int64_t orc_vertex_region(const orc_mesh* m, const orc_params* prm, int32_t v,
     }
     int32_t* parts = (int32_t*)malloc(sizeof(int32_t) * (size_t)big);
     int64_t n_parts = orc_vv_partners_of_vertex(m, prm, v, parts, big);
+    int32_t* pedges = (int32_t*)malloc(sizeof(int32_t) * (size_t)big);
+    int64_t n_pedges = orc_ve_edges_of_vertex(m, prm, v, pedges, big);
+    const int32_t** pp = (const int32_t**)malloc(sizeof(void*) * (size_t)(ne + 1));
+    int64_t* npp = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ne + 1));
+    for (int i = 0; i < ne; ++i) {
+        int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)big);
+        npp[i] = orc_ve_verts_of_edge(m, prm, incE[i], buf, big);
+        pp[i] = buf;
+    }
 
-    passive_t P = {faces, n_faces, ne, incE, ep, nep, nf, incF, fp, nfp, parts, n_parts};
+    passive_t P = {faces, n_faces, ne, incE, ep, nep, nf, incF, fp, nfp, parts, n_parts,
+                   pedges, n_pedges, pp, npp};
     sink_t s = {hs, cap, 0, 0};
     narrow_phase_vertex(m, prm, v, &P, &s);
 
     for (int i = 0; i < ne; ++i) free((void*)ep[i]);
+    for (int i = 0; i < ne; ++i) free((void*)pp[i]);
     for (int i = 0; i < nf; ++i) free((void*)fp[i]);
+    free(pp); free(npp); free(pedges);
     free(ep); free(nep); free(fp); free(nfp); free(faces); free(parts); free(incE); free(incF);
     return s.n;
 }

@@ -13,9 +13,24 @@
  *       p = x~                                           ("initialize solve")
  *       one Gauss-Seidel pass over the stretch constraints, colour by colour,
  *         lambda carried over from the previous iterations
+ *       applyResponse per vertex (with prm->response; oracle_response.c)
  *       y* = projectOntoConvexRegion(p - x), clamped to |y*| <= r
  *       x = x + y*
+ *       evaluateConvergence (only with early_exit): stop once no dynamic
+ *         vertex's step falls short of its expected advancement by more
+ *         than conv_tol, max_v (|p_v - x_v| - |y*_v|) <= conv_tol
  *   v = (x - x_old) / dt
+ *
+ * Reading A23 of the convergence check: the paper runs more iterations while
+ * "the current step size falls short of the expected advancement"; the
+ * expected advancement of an iteration is taken as the proposal displacement
+ * p - x that the XPBD constraints ask for, the current step as y* after the
+ * projection and the clamp, and the loop ends once every dynamic vertex's step
+ * comes within conv_tol of its proposal.
+ * Reading A24 of the halting statistics: a run is a sequence of consecutive
+ * iterations of one substep in which the same vertex halts; the step reports
+ * the longest run and how many halts extended a run to length 2 or to 3 and
+ * more.
  *
  * The stretch constraint of an edge (i, j) with rest length L is the XPBD
  * distance constraint C = |p_i - p_j| - L with compliance alpha (Macklin et al.
@@ -38,6 +53,14 @@ int orc_num_threads(void) {
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }
 
@@ -89,7 +112,7 @@ void orc_xpbd_step(int32_t n_verts, int32_t n_tris, int32_t n_edges,
                    const int32_t* tris, const int32_t* edges, const double* inv_mass,
                    const double* rest_len, const int32_t* color, int32_t n_colors,
                    double* x, double* v, const orc_params* prm, const orc_step_params* sp,
-                   int64_t counters[8], double* trace) {
+                   int64_t counters[12], double* trace) {
     const size_t N3 = 3 * (size_t)n_verts;
     double* x_old = (double*)malloc(sizeof(double) * N3);
     double* xt = (double*)malloc(sizeof(double) * N3);
@@ -98,6 +121,9 @@ void orc_xpbd_step(int32_t n_verts, int32_t n_tris, int32_t n_edges,
     double* ys = (double*)malloc(sizeof(double) * N3);
     double* lambda = (double*)calloc((size_t)n_edges + 1, sizeof(double));
     int64_t* offsets = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n_verts + 1));
+    int8_t* halted = (int8_t*)malloc((size_t)n_verts + 1);
+    int32_t* run = (int32_t*)calloc((size_t)n_verts + 1, sizeof(int32_t));   /* consecutive halts */
+    int64_t iters_run = 0, max_run = 0, runs2 = 0, runs3 = 0;
     memcpy(x_old, x, sizeof(double) * N3);
     const double dt = sp->dt;
     for (int32_t i = 0; i < n_verts; ++i)
@@ -109,33 +135,64 @@ void orc_xpbd_step(int32_t n_verts, int32_t n_tris, int32_t n_edges,
 
     for (int32_t it = 0; it < sp->iters; ++it) {
         /* broad phase at the anchor */
-        int64_t cnt[3];
-        orc_candidates(&m, prm, NULL, 0, NULL, 0, NULL, 0, cnt);
+        int64_t cnt[4];
+        orc_candidates(&m, prm, NULL, 0, NULL, 0, NULL, 0, NULL, 0, cnt);
         int32_t* vf = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * cnt[0] + 2));
         int32_t* ee = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * cnt[1] + 2));
         int32_t* vv = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * cnt[2] + 2));
-        orc_candidates(&m, prm, vf, cnt[0], ee, cnt[1], vv, cnt[2], cnt);
+        int32_t* ve = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * cnt[3] + 2));
+        orc_candidates(&m, prm, vf, cnt[0], ee, cnt[1], vv, cnt[2], ve, cnt[3], cnt);
         /* narrow phase */
         int64_t rstats[4];
-        int64_t H = orc_regions(&m, prm, vf, cnt[0], ee, cnt[1], vv, cnt[2], offsets, NULL, 0, rstats);
+        int64_t H = orc_regions(&m, prm, vf, cnt[0], ee, cnt[1], vv, cnt[2], ve, cnt[3], offsets, NULL, 0, rstats);
         orc_halfspace* hs = (orc_halfspace*)malloc(sizeof(orc_halfspace) * (size_t)(H + 1));
-        orc_regions(&m, prm, vf, cnt[0], ee, cnt[1], vv, cnt[2], offsets, hs, H, rstats);
+        orc_regions(&m, prm, vf, cnt[0], ee, cnt[1], vv, cnt[2], ve, cnt[3], offsets, hs, H, rstats);
         /* XPBD constraints from the prediction */
         memcpy(p, xt, sizeof(double) * N3);
         stretch_pass(n_edges, edges, inv_mass, rest_len, color, n_colors, p, lambda, alpha_t);
-        /* projection of the proposed displacement, then the anchor update */
+        /* response and friction (Sec. 3.3), then the projection of the
+         * proposed displacement and the anchor update */
         for (size_t k = 0; k < N3; ++k) y[k] = p[k] - x[k];
+        if (prm->response) {
+            orc_response(&m, prm, offsets, hs, dt, y, ys);
+            memcpy(y, ys, sizeof(double) * N3);
+        }
         int64_t pstats[4];
-        orc_project(&m, prm, offsets, hs, y, ys, NULL, NULL, pstats);
+        orc_project(&m, prm, offsets, hs, y, ys, halted, NULL, pstats);
         for (size_t k = 0; k < N3; ++k) x[k] += ys[k];
         if (trace) memcpy(trace + (size_t)it * N3, x, sizeof(double) * N3);
+        iters_run++;
+        double shortfall = 0.0;
+        for (int32_t i = 0; i < n_verts; ++i) {
+            if (inv_mass[i] == 0.0) continue;
+            const double* a = y + 3 * (size_t)i;
+            const double* b = ys + 3 * (size_t)i;
+            double sf = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]) - sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+            if (sf > shortfall) shortfall = sf;
+            if (halted[i]) {
+                run[i]++;
+                if (run[i] > max_run) max_run = run[i];
+                if (run[i] == 2) runs2++;
+                if (run[i] >= 3) runs3++;
+            } else {
+                run[i] = 0;
+            }
+        }
         if (counters) {
-            counters[0] += cnt[0]; counters[1] += cnt[1]; counters[2] += cnt[2];
+            counters[0] += cnt[0]; counters[1] += cnt[1]; counters[2] += cnt[2] + cnt[3];
             counters[3] += H; counters[4] += pstats[0]; counters[5] += pstats[1];
             counters[6] += pstats[2]; counters[7] += rstats[0];
         }
-        free(vf); free(ee); free(vv); free(hs);
+        free(vf); free(ee); free(vv); free(ve); free(hs);
+        if (sp->early_exit && shortfall <= sp->conv_tol) break;
     }
+    if (counters) {
+        counters[8] += iters_run;
+        if (max_run > counters[9]) counters[9] = max_run;
+        counters[10] += runs2;
+        counters[11] += runs3;
+    }
+    free(halted); free(run);
     for (size_t k = 0; k < N3; ++k) v[k] = (x[k] - x_old[k]) / dt;
     free(x_old); free(xt); free(p); free(y); free(ys); free(lambda); free(offsets);
 }

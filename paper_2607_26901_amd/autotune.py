@@ -4,7 +4,9 @@ The knobs are the grid cell size (`cell_scale`, a multiple of the default
 cell: 1.2 x the typical edge length + 2 pad), the number of lanes that share
 one broad-phase query (`pair_split`) and how solver iterations share candidate
 builds inside a substep: a fixed number per build (`pair_reuse`) or as many as
-the measured motion allows within a widening of s r (`pair_skin` = s).  Smaller cells put
+the measured motion allows within a widening of s r (`pair_skin` = s), and
+the broad phase itself (`broad_phase`: the hash grid, or the bounding-volume
+hierarchy, which has no cell or split knob).  Smaller cells put
 fewer entries in the buckets a query scans but bin long primitives one level
 up; more lanes per query shorten the walks of queries in dense folds at the
 price of more lanes; sharing a build saves grid builds and queries at the price
@@ -23,11 +25,12 @@ import sys
 
 from . import ccfr
 
-CELL_SCALES = (0.5, 0.6, 0.7, 0.85, 1.0, 1.2)
+CELL_SCALES = (0.35, 0.5, 0.6, 0.7, 0.85, 1.0, 1.2)
 PAIR_SPLITS = (1, 3, 9)
 # (pair_reuse, pair_skin): fixed groups of 1-4 iterations, or builds that follow
 # the motion with a skin of 1-3 r
 PAIR_MODES = ((1, 0), (2, 0), (3, 0), (4, 0), (1, 1), (1, 2), (1, 3))
+BROAD_PHASES = (0, 1)
 
 
 def size_class(n_verts, n_tris, n_edges, r, kind="mesh") -> str:
@@ -80,38 +83,47 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _settings(candidates, splits, modes, broad_phases):
+    """(cell scale, split, reuse, skin, broad phase) to time: the grid at every
+    cell scale and split, the hierarchy (no cell or split knob) once per mode."""
+    for bp in broad_phases:
+        for c in (candidates if bp == 0 else (1.0,)):
+            for sp in (splits if bp == 0 else (1,)):
+                for ru, sk in modes:
+                    yield c, sp, ru, sk, bp
+
+
 def tune(ctx: ccfr.Context, run, candidates=CELL_SCALES, splits=PAIR_SPLITS, modes=((1, 0),),
-         repeats: int = 2, log=_log, grow_factor: float = 4.0) -> dict:
+         repeats: int = 2, log=_log, grow_factor: float = 4.0, broad_phases=(0,)) -> dict:
     """Time `run(limit)` (device milliseconds of a fixed piece of work, starting
     from the same state every call, and the list bytes it needed) under each
-    (cell scale, split, (reuse, skin)); leave the fastest set.  A setting whose
-    lists would need more than grow_factor times those of the first setting is
-    skipped (run raises TooLarge), and one whose first timing is three times the
-    best so far is not timed again."""
+    (cell scale, split, (reuse, skin), broad phase); leave the fastest set.  A
+    setting whose lists would need more than grow_factor times those of the
+    first setting is skipped (run raises TooLarge), and one whose first timing
+    is three times the best so far is not timed again."""
     times = {}
     limit = None
     best_ms = math.inf
-    for c in candidates:
-        for sp in splits:
-            for ru, sk in modes:
-                key = (c, sp, ru, sk)
-                ctx.set_tuning(cell_scale=c, pair_split=sp, pair_reuse=ru, pair_skin=sk)
-                try:
-                    ms, nbytes = run(limit)     # records the graph for this setting
-                    if limit is None:
-                        limit = grow_factor * max(nbytes, 1 << 28)
-                    if ms < 3.0 * best_ms:
-                        ms = min(run(limit)[0] for _ in range(repeats))
-                except TooLarge:
-                    ms = math.inf
-                times[key] = ms
-                best_ms = min(best_ms, ms)
-                if log:
-                    log(f"[tune] cell {c} split {sp} reuse {ru} skin {sk}: {ms:.3f} ms")
+    for key in _settings(candidates, splits, modes, broad_phases):
+        c, sp, ru, sk, bp = key
+        ctx.set_tuning(cell_scale=c, pair_split=sp, pair_reuse=ru, pair_skin=sk, broad_phase=bp)
+        try:
+            ms, nbytes = run(limit)     # records the graph for this setting
+            if limit is None:
+                limit = grow_factor * max(nbytes, 1 << 28)
+            if ms < 3.0 * best_ms:
+                ms = min(run(limit)[0] for _ in range(repeats))
+        except TooLarge:
+            ms = math.inf
+        times[key] = ms
+        best_ms = min(best_ms, ms)
+        if log:
+            log(f"[tune] cell {c} split {sp} reuse {ru} skin {sk} broad phase {bp}: {ms:.3f} ms")
     best = min(times, key=times.get)
-    ctx.set_tuning(cell_scale=best[0], pair_split=best[1], pair_reuse=best[2], pair_skin=best[3])
+    ctx.set_tuning(cell_scale=best[0], pair_split=best[1], pair_reuse=best[2], pair_skin=best[3],
+                   broad_phase=best[4])
     return {"cell_scale": best[0], "pair_split": best[1], "pair_reuse": best[2], "pair_skin": best[3],
-            "ms": {f"{k[0]}/{k[1]}/{k[2]}/{k[3]}": v for k, v in times.items()}}
+            "broad_phase": best[4], "ms": {"/".join(str(q) for q in k): v for k, v in times.items()}}
 
 
 def _events():
@@ -121,14 +133,15 @@ def _events():
 
 def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, steps: int = 4,
               candidates=CELL_SCALES, splits=PAIR_SPLITS, modes=PAIR_MODES, cache: Cache | None = None,
-              key: str | None = None, log=_log) -> dict:
+              key: str | None = None, log=_log, broad_phases=BROAD_PHASES) -> dict:
     """Tune on `steps` single-mesh steps from the state (x, v), which is restored."""
     import torch
     if cache is not None and key is not None:
         hit = cache.get(key)
         if hit is not None:
             ctx.set_tuning(cell_scale=hit["cell_scale"], pair_split=hit["pair_split"],
-                           pair_reuse=hit.get("pair_reuse", 1), pair_skin=hit.get("pair_skin", 0))
+                           pair_reuse=hit.get("pair_reuse", 1), pair_skin=hit.get("pair_skin", 0),
+                           broad_phase=hit.get("broad_phase", 0))
             return dict(hit, cached=True)
     x0, v0 = x.clone(), v.clone()
 
@@ -151,7 +164,7 @@ def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, ste
             ctx.grow(info)                      # lists too small: grow and time again
         raise ccfr.CcfrError(-2, "tuning run")
 
-    out = tune(ctx, run, candidates, splits, modes, log=log)
+    out = tune(ctx, run, candidates, splits, modes, log=log, broad_phases=broad_phases)
     x.copy_(x0)
     v.copy_(v0)
     torch.cuda.synchronize()

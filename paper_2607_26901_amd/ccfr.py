@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libccfr.so")
 
-HALFSPACE_DTYPE = np.dtype([("n", "<f4", (3,)), ("d", "<f4"), ("phi", "<f4"), ("flags", "<u4"),
+HALFSPACE_DTYPE = np.dtype([("n", "<f4", (3,)), ("d", "<f4"), ("phi", "<f4"), ("share", "<f4"),
                             ("key", "<u8")])
 assert HALFSPACE_DTYPE.itemsize == 32
 
@@ -30,15 +30,20 @@ class CcfrError(RuntimeError):
         self.code = code
 
 
+FLAG_RESPONSE = 1
+
+
 class Params(C.Structure):
     _fields_ = [("r", C.c_float), ("xi", C.c_float), ("delta", C.c_float), ("guard", C.c_float),
                 ("eps_retract", C.c_float), ("eps_plesnik", C.c_float), ("max_passes", C.c_int32),
-                ("flags", C.c_int32)]
+                ("flags", C.c_int32), ("resp_compliance", C.c_float), ("vis_width", C.c_float),
+                ("mu_s", C.c_float), ("mu_k", C.c_float)]
 
 
 class Candidates(C.Structure):
     _fields_ = [("vf", C.c_void_p), ("ee", C.c_void_p), ("vv", C.c_void_p), ("counts_dev", C.c_void_p),
-                ("cap_vf", C.c_int64), ("cap_ee", C.c_int64), ("cap_vv", C.c_int64)]
+                ("cap_vf", C.c_int64), ("cap_ee", C.c_int64), ("cap_vv", C.c_int64), ("ve", C.c_void_p),
+                ("cap_ve", C.c_int64)]
 
 
 class Regions(C.Structure):
@@ -48,23 +53,26 @@ class Regions(C.Structure):
 
 class StepParams(C.Structure):
     _fields_ = [("dt", C.c_float), ("gravity", C.c_float * 3), ("iters", C.c_int32), ("alpha", C.c_float),
-                ("collision", Params)]
+                ("collision", Params), ("early_exit", C.c_int32), ("conv_tol", C.c_float)]
 
 
 class Tuning(C.Structure):
     _fields_ = [("cell_scale", C.c_float), ("pair_split", C.c_int32), ("pair_reuse", C.c_int32),
-                ("pair_skin", C.c_int32)]
+                ("pair_skin", C.c_int32), ("broad_phase", C.c_int32)]
 
 
 class StatusInfo(C.Structure):
     _fields_ = [("status_bits", C.c_uint32), ("last_counts", C.c_int32 * 3), ("last_contacts", C.c_int32),
                 ("last_halfspaces", C.c_int32), ("need", C.c_int64 * 6), ("totals", C.c_int64 * 10),
-                ("candidate_builds", C.c_int64)]
+                ("candidate_builds", C.c_int64), ("iterations_run", C.c_int64), ("halt_runs", C.c_int64 * 2),
+                ("max_halt_run", C.c_int32), ("last_ve", C.c_int32), ("need_ve", C.c_int64),
+                ("total_ve", C.c_int64)]
 
 
 EXPORTS = ["ccfr_status_string", "ccfr_create", "ccfr_destroy", "ccfr_mesh_create", "ccfr_mesh_destroy",
            "ccfr_mesh_edges", "ccfr_mesh_inv_mass_dev", "ccfr_reserve", "ccfr_build_candidates",
            "ccfr_build_regions", "ccfr_project_displacements", "ccfr_project_displacements_noalloc",
+           "ccfr_apply_response",
            "ccfr_xpbd_step", "ccfr_xpbd_step_traced",
            "ccfr_sync_status",
            "ccfr_profile_enable", "ccfr_profile_read", "ccfr_set_tuning", "ccfr_get_tuning",
@@ -94,13 +102,14 @@ def load():
     lib.ccfr_mesh_edges.argtypes = [vp, C.POINTER(i32), vp]
     lib.ccfr_mesh_inv_mass_dev.restype = vp
     lib.ccfr_mesh_inv_mass_dev.argtypes = [vp]
-    lib.ccfr_reserve.argtypes = [vp, i64, i64, i64, i64, i64, vp]
+    lib.ccfr_reserve.argtypes = [vp, i64, i64, i64, i64, i64, i64, vp]
     lib.ccfr_build_candidates.argtypes = [vp, vp, vp, C.POINTER(Params), C.POINTER(Candidates), vp]
     lib.ccfr_build_regions.argtypes = [vp, vp, vp, C.POINTER(Candidates), C.POINTER(Params),
                                        C.POINTER(Regions), vp]
     lib.ccfr_project_displacements.argtypes = [vp, C.POINTER(Regions), vp, vp, C.POINTER(Params), vp, vp, vp]
     lib.ccfr_project_displacements_noalloc.argtypes = [C.POINTER(Regions), vp, vp, C.POINTER(Params), vp, vp,
                                                        vp, vp]
+    lib.ccfr_apply_response.argtypes = [vp, C.POINTER(Regions), vp, vp, C.POINTER(Params), C.c_float, vp, vp]
     lib.ccfr_xpbd_step.argtypes = [vp, vp, vp, vp, C.POINTER(StepParams), vp]
     lib.ccfr_xpbd_step_traced.argtypes = [vp, vp, vp, vp, C.POINTER(StepParams), vp, vp]
     lib.ccfr_sync_status.argtypes = [vp, vp, C.POINTER(StatusInfo), C.c_int]
@@ -173,12 +182,17 @@ def _stream(stream=None):
 
 
 def make_params(p) -> Params:
-    """From anything with r, xi, delta, guard, eps_retract, eps_plesnik, max_passes."""
-    return Params(p.r, p.xi, p.delta, p.guard, p.eps_retract, p.eps_plesnik, int(p.max_passes), 0)
+    """From anything with r, xi, delta, guard, eps_retract, eps_plesnik, max_passes
+    (and optionally response, resp_compliance, vis_width, mu_s, mu_k)."""
+    g = lambda name: float(getattr(p, name, 0.0))
+    return Params(p.r, p.xi, p.delta, p.guard, p.eps_retract, p.eps_plesnik, int(p.max_passes),
+                  FLAG_RESPONSE if getattr(p, "response", False) else 0, g("resp_compliance"), g("vis_width"),
+                  g("mu_s"), g("mu_k"))
 
 
 def make_step_params(step, p) -> StepParams:
-    return StepParams(step.dt, (C.c_float * 3)(*step.gravity), int(step.iters), step.alpha, make_params(p))
+    return StepParams(step.dt, (C.c_float * 3)(*step.gravity), int(step.iters), step.alpha, make_params(p),
+                      int(bool(getattr(step, "early_exit", False))), float(getattr(step, "conv_tol", 0.0)))
 
 
 class Context:
@@ -200,8 +214,8 @@ class Context:
         except Exception:
             pass
 
-    def reserve(self, vf=0, ee=0, vv=0, contacts=0, halfspaces=0, stream=None):
-        _check(self.lib.ccfr_reserve(self.h, int(vf), int(ee), int(vv), int(contacts), int(halfspaces),
+    def reserve(self, vf=0, ee=0, vv=0, contacts=0, halfspaces=0, ve=0, stream=None):
+        _check(self.lib.ccfr_reserve(self.h, int(vf), int(ee), int(vv), int(ve), int(contacts), int(halfspaces),
                                      _stream(stream)), "ccfr_reserve")
 
     def sync_status(self, reset=False, stream=None, raise_on_error=False):
@@ -217,6 +231,12 @@ class Context:
             "need": list(info.need),
             "totals": list(info.totals),
             "candidate_builds": int(info.candidate_builds),
+            "iterations_run": int(info.iterations_run),
+            "halt_runs": list(info.halt_runs),
+            "max_halt_run": int(info.max_halt_run),
+            "last_ve": int(info.last_ve),
+            "need_ve": int(info.need_ve),
+            "total_ve": int(info.total_ve),
         }
 
 
@@ -228,22 +248,24 @@ class Context:
             raise CcfrError(-2, "a primitive's box is too large to bin (coordinates out of range)")
         nd = info["need"]
         self.reserve(vf=int(nd[0] * factor) + 1024, ee=int(nd[1] * factor) + 1024, vv=int(nd[2] * factor) + 1024,
-                     contacts=int(nd[3] * factor) + 1024, halfspaces=int(nd[4] * factor) + 1024)
+                     ve=int(info.get("need_ve", 0) * factor) + 1024, contacts=int(nd[3] * factor) + 1024,
+                     halfspaces=int(nd[4] * factor) + 1024)
 
-    def set_tuning(self, cell_scale=None, pair_split=None, pair_reuse=None, pair_skin=None):
+    def set_tuning(self, cell_scale=None, pair_split=None, pair_reuse=None, pair_skin=None, broad_phase=None):
         """Change any of the speed-only knobs (None keeps the current value)."""
         cur = self.get_tuning()
         t = Tuning(float(cur["cell_scale"] if cell_scale is None else cell_scale),
                    int(cur["pair_split"] if pair_split is None else pair_split),
                    int(cur["pair_reuse"] if pair_reuse is None else pair_reuse),
-                   int(cur["pair_skin"] if pair_skin is None else pair_skin))
+                   int(cur["pair_skin"] if pair_skin is None else pair_skin),
+                   int(cur["broad_phase"] if broad_phase is None else broad_phase))
         _check(self.lib.ccfr_set_tuning(self.h, C.byref(t)), "ccfr_set_tuning")
 
     def get_tuning(self) -> dict:
         t = Tuning()
         _check(self.lib.ccfr_get_tuning(self.h, C.byref(t)), "ccfr_get_tuning")
         return {"cell_scale": float(t.cell_scale), "pair_split": int(t.pair_split),
-                "pair_reuse": int(t.pair_reuse), "pair_skin": int(t.pair_skin)}
+                "pair_reuse": int(t.pair_reuse), "pair_skin": int(t.pair_skin), "broad_phase": int(t.broad_phase)}
 
     def profile_enable(self, on=True):
         _check(self.lib.ccfr_profile_enable(self.h, int(bool(on))), "ccfr_profile_enable")
@@ -405,6 +427,19 @@ def project_displacements(ctx: Context, regions: Regions, inv_mass, y_in, params
            "ccfr_project_displacements")
 
 
+def apply_response(ctx: Context, regions: Regions, inv_mass, y_in, params, dt, y_out, stream=None):
+    """applyResponse of Alg. 4 (soft response, visibility weights, friction) on
+    the regions; y_out may be y_in."""
+    prm = params if isinstance(params, Params) else make_params(params)
+    n = int(regions.n_verts)
+    wp = _dev(inv_mass, "float32", n, "inv_mass")
+    yp = _dev(y_in, "float32", 3 * n, "y_in")
+    op = _dev(y_out, "float32", 3 * n, "y_out")
+    _check(ctx.lib.ccfr_apply_response(ctx.h, C.byref(regions), wp, yp, C.byref(prm), float(dt), op,
+                                       _stream(stream)),
+           "ccfr_apply_response")
+
+
 def project_displacements_noalloc(regions: Regions, inv_mass, y_in, params, y_out, halted=None, status=None,
                                   stream=None):
     """ccfr_project_displacements_noalloc: the projection without a context and
@@ -439,17 +474,19 @@ def xpbd_step_traced(ctx: Context, mesh: Mesh, x, v, step_params: StepParams, tr
            "ccfr_xpbd_step_traced")
 
 
-def caller_candidates(vf, ee, vv, counts) -> Candidates:
-    """Candidates view over caller-owned device tensors ([P][2] int32 each, counts [3] int32).
+def caller_candidates(vf, ee, vv, counts, ve=None) -> Candidates:
+    """Candidates view over caller-owned device tensors ([P][2] int32 each, counts [4] int32:
+    |VF|, |EE|, |VV|, |VE|; ve None: no particle-edge pairs, counts[3] must be 0).
     The view keeps the tensors alive."""
-    for name, t in (("vf", vf), ("ee", ee), ("vv", vv)):
+    lists = (("vf", vf), ("ee", ee), ("vv", vv)) + ((("ve", ve),) if ve is not None else ())
+    for name, t in lists:
         _dev(t, "int32", t.numel(), name)
         if t.dim() != 2 or t.shape[1] != 2:
             raise ValueError(f"{name}: shape {tuple(t.shape)}, expected [P][2]")
-    _dev(counts, "int32", 3, "counts")
+    _dev(counts, "int32", 4, "counts")
     c = Candidates(vf.data_ptr(), ee.data_ptr(), vv.data_ptr(), counts.data_ptr(), vf.shape[0], ee.shape[0],
-                   vv.shape[0])
-    c._keep = (vf, ee, vv, counts)
+                   vv.shape[0], ve.data_ptr() if ve is not None else None, ve.shape[0] if ve is not None else 0)
+    c._keep = (vf, ee, vv, counts, ve)
     return c
 
 
@@ -505,10 +542,10 @@ def _hiprt():
 
 def read_candidates(c: Candidates) -> dict:
     """Synchronous copy of the candidate lists (the stream must be synchronised)."""
-    counts = _dev_view(c.counts_dev, 3, np.int32, None)
-    caps = (c.cap_vf, c.cap_ee, c.cap_vv)
+    counts = _dev_view(c.counts_dev, 4, np.int32, None)
+    caps = (c.cap_vf, c.cap_ee, c.cap_vv, c.cap_ve)
     out = {}
-    for k, (name, ptr) in enumerate((("vf", c.vf), ("ee", c.ee), ("vv", c.vv))):
+    for k, (name, ptr) in enumerate((("vf", c.vf), ("ee", c.ee), ("vv", c.vv), ("ve", c.ve))):
         n = int(counts[k])
         if n > caps[k]:
             raise CcfrError(-2, f"{name} list overflow ({n} > {caps[k]})")

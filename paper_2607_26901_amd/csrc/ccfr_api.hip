@@ -68,6 +68,33 @@ int ensure_grid(ccfr_ctx* ctx, long long T, long long E, long long F, long long 
         }
         ctx->generation++;
     }
+    const long long leaves = T + E + F;
+    if (ctx->broad_phase == 1 && leaves > ctx->cap_lbvh) {
+        LbvhWs& w = ctx->lbvh;
+        dev_free(w.leaf_lo); dev_free(w.leaf_hi); dev_free(w.leaf_meta); dev_free(w.keys_in); dev_free(w.keys_out);
+        dev_free(w.idx_in); dev_free(w.idx_out); dev_free(w.leaf_parent); dev_free(w.child);
+        dev_free(w.node_parent); dev_free(w.node_flag); dev_free(w.node_lo); dev_free(w.node_hi);
+        dev_free(ctx->lbvh_sort_temp);
+        const long long L = std::max(leaves, 2LL);
+        HIP_ALLOC(dev_alloc(&w.leaf_lo, 3 * L));
+        HIP_ALLOC(dev_alloc(&w.leaf_hi, 3 * L));
+        HIP_ALLOC(dev_alloc(&w.leaf_meta, L));
+        HIP_ALLOC(dev_alloc(&w.keys_in, L));
+        HIP_ALLOC(dev_alloc(&w.keys_out, L));
+        HIP_ALLOC(dev_alloc(&w.idx_in, L));
+        HIP_ALLOC(dev_alloc(&w.idx_out, L));
+        HIP_ALLOC(dev_alloc(&w.leaf_parent, L));
+        HIP_ALLOC(dev_alloc(&w.child, 2 * L));
+        HIP_ALLOC(dev_alloc(&w.node_parent, L));
+        HIP_ALLOC(dev_alloc(&w.node_flag, L));
+        HIP_ALLOC(dev_alloc(&w.node_lo, 3 * L));
+        HIP_ALLOC(dev_alloc(&w.node_hi, 3 * L));
+        w.sort_temp_bytes = std::max<size_t>(lbvh_sort_temp_bytes((int)L), 16);
+        HIP_ALLOC(dev_alloc(&ctx->lbvh_sort_temp, (long long)w.sort_temp_bytes));
+        w.sort_temp = ctx->lbvh_sort_temp;
+        ctx->cap_lbvh = L;
+        ctx->generation++;
+    }
     const long long targets = T + E + F + N;
     if (targets > ctx->cap_targets) {
         dev_free(ctx->rank);
@@ -96,7 +123,7 @@ int ensure_meshes(ccfr_ctx* ctx, int n_meshes) {
     return CCFR_OK;
 }
 
-int ensure_pairs(ccfr_ctx* ctx, long long vf, long long ee, long long vv) {
+int ensure_pairs(ccfr_ctx* ctx, long long vf, long long ee, long long vv, long long ve) {
     if (vf > ctx->cap_vf) {
         dev_free(ctx->vf);
         HIP_ALLOC(dev_alloc(&ctx->vf, 2 * vf));
@@ -113,6 +140,12 @@ int ensure_pairs(ccfr_ctx* ctx, long long vf, long long ee, long long vv) {
         dev_free(ctx->vv);
         HIP_ALLOC(dev_alloc(&ctx->vv, 2 * vv));
         ctx->cap_vv = vv;
+        ctx->generation++;
+    }
+    if (ve > ctx->cap_ve) {
+        dev_free(ctx->ve);
+        HIP_ALLOC(dev_alloc(&ctx->ve, 2 * ve));
+        ctx->cap_ve = ve;
         ctx->generation++;
     }
     return CCFR_OK;
@@ -161,10 +194,12 @@ int ensure_step(ccfr_ctx* ctx, long long n_verts) {
         dev_free(ctx->x_start);
         dev_free(ctx->p);
         dev_free(ctx->y_def);
+        dev_free(ctx->halt_run);
         HIP_ALLOC(dev_alloc(&ctx->x_pred, 3 * n_verts));
         HIP_ALLOC(dev_alloc(&ctx->x_start, 3 * n_verts));
         HIP_ALLOC(dev_alloc(&ctx->p, 3 * n_verts));
         HIP_ALLOC(dev_alloc(&ctx->y_def, 3 * n_verts));
+        HIP_ALLOC(dev_alloc(&ctx->halt_run, n_verts));
         ctx->cap_step = n_verts;
         ctx->generation++;
     }
@@ -180,20 +215,29 @@ int ensure_sizes(ccfr_ctx* ctx, long long n_verts, long long n_tris, long long n
     rc = ensure_meshes(ctx, n_meshes);
     if (rc) return rc;
     const long long vf = 8LL * n_verts + 4096, ee = 8LL * n_edges + 4096, vv = 16LL * n_free + 4096;
-    rc = ensure_pairs(ctx, vf, ee, vv);
+    const long long ve = 8LL * n_free + 4096;
+    rc = ensure_pairs(ctx, vf, ee, vv, ve);
     if (rc) return rc;
-    return ensure_regions(ctx, n_verts, (vf + ee + vv) / 2, 2 * (vf + ee + vv));
+    return ensure_regions(ctx, n_verts, (vf + ee + vv + ve) / 2, 2 * (vf + ee + vv + ve));
 }
 
 bool params_ok(const ccfr_params* p) {
-    return p && std::isfinite(p->r) && p->r > 0.f && std::isfinite(p->xi) && p->xi >= 0.f &&
-           std::isfinite(p->delta) && p->delta >= 0.f && std::isfinite(p->guard) && p->guard >= 0.f &&
-           std::isfinite(p->eps_retract) && p->eps_retract >= 0.f && std::isfinite(p->eps_plesnik) &&
-           p->eps_plesnik >= 0.f && p->max_passes >= 1;
+    if (!(p && std::isfinite(p->r) && p->r > 0.f && std::isfinite(p->xi) && p->xi >= 0.f &&
+          std::isfinite(p->delta) && p->delta >= 0.f && std::isfinite(p->guard) && p->guard >= 0.f &&
+          std::isfinite(p->eps_retract) && p->eps_retract >= 0.f && std::isfinite(p->eps_plesnik) &&
+          p->eps_plesnik >= 0.f && p->max_passes >= 1))
+        return false;
+    if (p->flags & ~CCFR_FLAG_RESPONSE) return false;
+    if (p->flags & CCFR_FLAG_RESPONSE)
+        return p->delta > 0.f && p->delta <= 2.0f * p->r && std::isfinite(p->resp_compliance) &&
+               p->resp_compliance >= 0.f && std::isfinite(p->vis_width) && p->vis_width >= 0.f &&
+               std::isfinite(p->mu_s) && p->mu_s >= 0.f && std::isfinite(p->mu_k) && p->mu_k >= 0.f;
+    return true;
 }
 
 bool step_params_ok(const ccfr_step_params* sp) {
     return sp && params_ok(&sp->collision) && sp->dt > 0.f && std::isfinite(sp->dt) && sp->iters >= 0 &&
+           (sp->early_exit == 0 || sp->early_exit == 1) && std::isfinite(sp->conv_tol) && sp->conv_tol >= 0.f &&
            std::isfinite(sp->alpha) && sp->alpha >= 0.f && std::isfinite(sp->gravity[0]) &&
            std::isfinite(sp->gravity[1]) && std::isfinite(sp->gravity[2]);
 }
@@ -227,6 +271,12 @@ MeshParams mesh_params(const ccfr_params* p, float typ_len, int salt, float cell
     m.inv_h = (float)(1.0 / h);
     m.max_passes = p->max_passes;
     m.mesh_salt = salt;
+    m.response = (p->flags & CCFR_FLAG_RESPONSE) ? 1 : 0;
+    m.delta = p->delta;
+    m.resp_compliance = p->resp_compliance;
+    m.vis_width = p->vis_width;
+    m.mu_s = p->mu_s;
+    m.mu_k = p->mu_k;
     return m;
 }
 
@@ -279,6 +329,11 @@ struct Marks {
     }
 };
 
+// The context's candidate lists.
+PairLists ctx_lists(const ccfr_ctx* ctx) {
+    return PairLists{ctx->vf, ctx->ee, ctx->vv, ctx->ve, ctx->cap_vf, ctx->cap_ee, ctx->cap_vv, ctx->cap_ve};
+}
+
 // broad phase into the context's lists; `standalone` brackets it with its own
 // counter reset and build close (inside a substep the neighbouring kernels do both)
 void enqueue_candidates(ccfr_ctx* ctx, const Scene& sc, int n_meshes, hipStream_t s, const Marks& mk,
@@ -286,12 +341,23 @@ void enqueue_candidates(ccfr_ctx* ctx, const Scene& sc, int n_meshes, hipStream_
     GridWs g = grid_ws(ctx, sc, n_meshes);
     mk.mark(0, 0);
     if (standalone) launch_reset_build(ctx->counters_d, g.level_mask, g.n_meshes, s);
+    if (ctx->broad_phase == 1) {
+        // the hierarchy: build (stage 0), then the queries (stage 1)
+        launch_lbvh_build(sc, ctx->lbvh, ctx->counters_d, s);
+        mk.mark(0, 1);
+        const PairLists pl = ctx_lists(ctx);
+        mk.mark(1, 0);
+        launch_lbvh_query(sc, ctx->lbvh, pl, ctx->counters_d, s);
+        mk.mark(1, 1);
+        if (standalone) launch_finalize_pairs(g, pl, ctx->counters_d, s);
+        return;
+    }
     launch_grid_count(sc, g, ctx->counters_d, s);
     launch_scan(g.cnt, g.start, g.cnt, g.off[TB_COUNT], g.scan_tmp, s,
-                sc.build_gated ? &ctx->counters_d->rebuild : nullptr);
+                sc.build_gated ? &ctx->counters_d->rebuild : nullptr, sc.skip);
     launch_grid_scatter(sc, g, ctx->counters_d, s);
     mk.mark(0, 1);
-    PairLists pl{ctx->vf, ctx->ee, ctx->vv, ctx->cap_vf, ctx->cap_ee, ctx->cap_vv};
+    const PairLists pl = ctx_lists(ctx);
     mk.mark(1, 0);
     launch_pairs(sc, g, pl, ctx->counters_d, ctx->pair_split, s);
     mk.mark(1, 1);
@@ -308,14 +374,13 @@ int32_t step_slot_stride(const ccfr_ctx* ctx, int n_verts) {
 // narrow phase into the context's regions; inside a substep (`in_step`) both
 // builds are closed by launch_close_iteration, and with slot_stride > 0 the
 // half-spaces go into per-vertex slots (no scan or fill)
-void enqueue_regions(ccfr_ctx* ctx, const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
-                     const int32_t* counts, long long cap_vf, long long cap_ee, long long cap_vv, hipStream_t s,
+void enqueue_regions(ccfr_ctx* ctx, const Scene& sc, const PairLists& pl, const int32_t* counts, hipStream_t s,
                      const Marks& mk, bool in_step, int32_t slot_stride = 0,
                      const ColourJob* job_contacts = nullptr, const ColourJob* job_fill = nullptr) {
     const bool slots = in_step && slot_stride > 0;
     mk.mark(2, 0);
-    launch_contacts(sc, vf, ee, vv, counts, cap_vf, cap_ee, cap_vv, ctx->contacts, ctx->cap_contacts, ctx->vcount,
-                    ctx->counters_d, s, slots, job_contacts);
+    launch_contacts(sc, pl, counts, ctx->contacts, ctx->cap_contacts, ctx->vcount, ctx->counters_d, s, slots,
+                    job_contacts);
     mk.mark(2, 1);
     mk.mark(3, 0);
     if (slots) {
@@ -349,9 +414,14 @@ int ensure_prof_events(ccfr_ctx* ctx, int iters) {
 
 // The substep of Alg. 4 (without response, friction or early exit).
 void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
-    const Scene& sc = plan.sc;
+    // with the convergence check every kernel of an iteration returns at once
+    // once the substep's iterations have ended
+    const uint32_t* skip = plan.early_exit ? &ctx->counters_d->converged : nullptr;
+    Scene sc = plan.sc;
+    sc.skip = skip;
     const int n = sc.n_verts;
-    launch_predict(n, plan.x, plan.v, sc.inv_mass, plan.dt, plan.gx, plan.gy, plan.gz, ctx->x_pred, ctx->x_start, s);
+    launch_predict(n, plan.x, plan.v, sc.inv_mass, plan.dt, plan.gx, plan.gy, plan.gz, ctx->x_pred, ctx->x_start, s,
+                   ctx->halt_run, ctx->counters_d, plan.early_exit ? 0 : plan.iters);
     if (plan.has_stretch) launch_fill_zero(plan.lambda, plan.n_edges, s);
     // counters and level masks start clear; each iteration's close clears them
     // for the next one
@@ -365,7 +435,7 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
     // and return at once when no build is asked for.
     const bool adaptive = plan.skin > 0.0;
     const int reuse = adaptive ? 1 : std::max(1, ctx->pair_reuse);
-    const PairCaps caps{ctx->cap_vf, ctx->cap_ee, ctx->cap_vv};
+    const PairCaps caps = ctx_lists(ctx).caps();
     const int32_t slots = step_slot_stride(ctx, n);
     // The stretch pass: the first colour runs with p's reset to the
     // prediction, the last one (of two or more) inside the projection's fast
@@ -381,7 +451,10 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
         c0 = StretchColor0{plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[0], plan.col_nseg[0],
                            plan.col_total[0], sc.inv_mass, plan.lambda, plan.alpha_t, sc.vflags};
     const int n_col = (int)plan.col_total.size();
-    const bool fold = plan.has_stretch && n_col >= 2 && plan.last_edge && plan.lambda_alt;
+    // with the response (Sec. 3.3), which acts on the whole pass's result, no
+    // stretch colour is folded into the projection
+    const bool response = !sc.prm.table && sc.prm.one.response;
+    const bool fold = plan.has_stretch && n_col >= 2 && plan.last_edge && plan.lambda_alt && !response;
     const bool fold2 = fold && n_col >= 3 && plan.prev_edge;
     const int n_launched = n_col - (fold2 ? 2 : fold ? 1 : 0);     // colours before the folded ones
     const bool hosted = fold && slots > 0;
@@ -401,8 +474,9 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
         const Marks mk{ctx, it, s};
         const int first = it - it % reuse;
         const int group = std::min(reuse, plan.iters - first);
+        if (plan.early_exit) launch_decide_converged(ctx->counters_d, plan.conv_tol, it == 0 ? 1 : 0, s);
         if (adaptive) {
-            if (it > 0) launch_decide_build(ctx->counters_d, ctx->level_mask, plan.n_meshes, plan.skin, caps, s);
+            if (it > 0) launch_decide_build(ctx->counters_d, ctx->level_mask, plan.n_meshes, plan.skin, caps, s, skip);
             Scene sb = sc;
             sb.skin_wide = 1;
             sb.build_gated = 1;
@@ -417,22 +491,37 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
                 mk.mark(st, 1);
             }
         }
-        enqueue_regions(ctx, sc, ctx->vf, ctx->ee, ctx->vv, counts_ptr(ctx), ctx->cap_vf, ctx->cap_ee,
-                        ctx->cap_vv, s, mk, true, slots, &job_contacts, &job_fill);
+        enqueue_regions(ctx, sc, ctx_lists(ctx), counts_ptr(ctx), s, mk, true, slots, &job_contacts, &job_fill);
         mk.mark(4, 0);
         const bool close_pairs = adaptive ? it == plan.iters - 1 : it == first + group - 1;
         if (hosted)
             launch_close_iteration(nullptr, nullptr, 0, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
                                    ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs, close_pairs, s, slots, nullptr,
-                                   true, &job_close);
+                                   true, &job_close, skip);
         else
             launch_close_iteration(ctx->x_pred, ctx->p, 3LL * n, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
-                                   ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs, close_pairs, s, slots, &c0);
+                                   ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs, close_pairs, s, slots, &c0,
+                                   true, nullptr, skip);
         if (plan.has_stretch)
             for (int c = hosted ? 4 : 1; c < n_launched; ++c)
                 launch_stretch_segments(plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[c],
                                         plan.col_nseg[c], plan.col_total[c], sc.inv_mass, ctx->p, plan.lambda,
-                                        plan.alpha_t, s);
+                                        plan.alpha_t, s, skip);
+        if (response) {
+            ResponseArgs ra{};
+            ra.n_verts = n;
+            ra.offsets = ctx->offsets;
+            ra.hs = ctx->hs;
+            ra.slot_counts = ctx->vcount;
+            ra.slot_stride = slots;
+            ra.inv_mass = sc.inv_mass;
+            ra.x_anchor = plan.x;
+            ra.p = ctx->p;
+            ra.dt = plan.dt;
+            ra.prm = sc.prm;
+            ra.skip = skip;
+            launch_response(ra, s);
+        }
         mk.mark(4, 1);
         ProjectArgs pa{};
         pa.n_verts = n;
@@ -452,6 +541,9 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
         pa.slot_counts = ctx->vcount;
         pa.slot_stride = slots;
         pa.prm = sc.prm;
+        pa.skip = skip;
+        pa.shortfall_max = plan.early_exit ? &ctx->counters_d->shortfall_max : nullptr;
+        pa.halt_run = ctx->halt_run;
         if (fold)   // the multipliers of the folded colour alternate between two arrays
             pa.sl = StretchLast{plan.last_edge, fold2 ? plan.prev_edge : nullptr, plan.rest_sorted,
                                 (it & 1) ? plan.lambda_alt : plan.lambda, (it & 1) ? plan.lambda : plan.lambda_alt,
@@ -496,6 +588,8 @@ int launch_recorded(ccfr_ctx* ctx, StepGraph& G, const StepPlan& plan, const voi
 int prepare_mesh(int32_t n_verts, const int32_t* tris, int32_t n_tris, const int32_t* edges, int32_t n_edges,
                  const float* inv_mass, const float* rest_x, MeshHost* out) {
     if (n_verts < 0 || n_tris < 0 || n_edges < 0 || !inv_mass || !out) return CCFR_ERR_INVALID_ARG;
+    // pair records keep a primitive index in 30 bits
+    if (n_verts > kMaxPrims || n_tris > kMaxPrims || n_edges > kMaxPrims) return CCFR_ERR_INVALID_ARG;
     if (n_tris > 0 && !tris) return CCFR_ERR_INVALID_ARG;
     for (long long i = 0; i < 3LL * n_tris; ++i)
         if (tris[i] < 0 || tris[i] >= n_verts) return CCFR_ERR_INVALID_ARG;
@@ -527,6 +621,7 @@ int prepare_mesh(int32_t n_verts, const int32_t* tris, int32_t n_tris, const int
             E.push_back((int32_t)(k >> 32));
             E.push_back((int32_t)(k & 0xffffffffLL));
         }
+        if ((long long)(E.size() / 2) > kMaxPrims) return CCFR_ERR_INVALID_ARG;
         n_edges = (int32_t)(E.size() / 2);
     }
     m.n_edges = n_edges;
@@ -633,6 +728,8 @@ StepPlan mesh_plan(ccfr_ctx* ctx, const ccfr_mesh* m, float* x, float* v, const 
     plan.gz = sp->gravity[2];
     plan.alpha_t = sp->alpha / (sp->dt * sp->dt);
     plan.iters = sp->iters;
+    plan.early_exit = sp->early_exit != 0;
+    plan.conv_tol = sp->conv_tol;
     (void)ctx;
     return plan;
 }
@@ -687,11 +784,18 @@ void ccfr_destroy(ccfr_ctx* ctx) {
     dev_free(ctx->counters_d);
     dev_free(ctx->cnt); dev_free(ctx->start); dev_free(ctx->rank); dev_free(ctx->key);
     dev_free(ctx->entries); dev_free(ctx->staged); dev_free(ctx->level_mask); dev_free(ctx->scan_tmp);
-    dev_free(ctx->vf); dev_free(ctx->ee); dev_free(ctx->vv);
+    dev_free(ctx->vf); dev_free(ctx->ee); dev_free(ctx->vv); dev_free(ctx->ve);
     dev_free(ctx->contacts); dev_free(ctx->vcount); dev_free(ctx->offsets); dev_free(ctx->slow_list);
     dev_free(ctx->hs);
     dev_free(ctx->sort_key); dev_free(ctx->sort_idx);
-    dev_free(ctx->x_pred); dev_free(ctx->x_start); dev_free(ctx->p); dev_free(ctx->y_def);
+    dev_free(ctx->x_pred); dev_free(ctx->x_start); dev_free(ctx->p); dev_free(ctx->y_def); dev_free(ctx->halt_run);
+    {
+        LbvhWs& w = ctx->lbvh;
+        dev_free(w.leaf_lo); dev_free(w.leaf_hi); dev_free(w.leaf_meta); dev_free(w.keys_in); dev_free(w.keys_out);
+        dev_free(w.idx_in); dev_free(w.idx_out); dev_free(w.leaf_parent); dev_free(w.child);
+        dev_free(w.node_parent); dev_free(w.node_flag); dev_free(w.node_lo); dev_free(w.node_hi);
+        dev_free(ctx->lbvh_sort_temp);
+    }
     for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     delete ctx;
@@ -781,13 +885,13 @@ int ccfr_mesh_edges(const ccfr_mesh* m, int32_t* n_edges, int32_t* edges_host) {
 
 const float* ccfr_mesh_inv_mass_dev(const ccfr_mesh* m) { return m ? m->inv_mass_d : nullptr; }
 
-int ccfr_reserve(ccfr_ctx* ctx, int64_t vf, int64_t ee, int64_t vv, int64_t contacts, int64_t halfspaces,
-                 ccfr_stream stream) {
-    if (!ctx || vf < 0 || ee < 0 || vv < 0 || contacts < 0 || halfspaces < 0) return CCFR_ERR_INVALID_ARG;
+int ccfr_reserve(ccfr_ctx* ctx, int64_t vf, int64_t ee, int64_t vv, int64_t ve, int64_t contacts,
+                 int64_t halfspaces, ccfr_stream stream) {
+    if (!ctx || vf < 0 || ee < 0 || vv < 0 || ve < 0 || contacts < 0 || halfspaces < 0) return CCFR_ERR_INVALID_ARG;
     HIP_OK(hipStreamSynchronize((hipStream_t)stream));
     if (ctx->vcount) HIP_OK(hipMemset(ctx->vcount, 0, sizeof(int32_t) * (size_t)ctx->cap_verts));
     const long long gen = ctx->generation;
-    int rc = ensure_pairs(ctx, vf, ee, vv);
+    int rc = ensure_pairs(ctx, vf, ee, vv, ve);
     if (rc) return rc;
     rc = ensure_regions(ctx, 0, contacts, halfspaces);
     if (rc) return rc;
@@ -811,6 +915,8 @@ int ccfr_build_candidates(ccfr_ctx* ctx, const ccfr_mesh* mesh, const float* x_a
     out->cap_vf = ctx->cap_vf;
     out->cap_ee = ctx->cap_ee;
     out->cap_vv = ctx->cap_vv;
+    out->ve = ctx->ve;
+    out->cap_ve = ctx->cap_ve;
     return CCFR_OK;
 }
 
@@ -818,14 +924,16 @@ int ccfr_build_regions(ccfr_ctx* ctx, const ccfr_mesh* mesh, const float* x_anch
                        const ccfr_params* params, ccfr_regions* out, ccfr_stream stream) {
     if (!ctx || !mesh || !c || !out || !params_ok(params)) return CCFR_ERR_INVALID_ARG;
     if (!x_anchor_dev && mesh->n_verts > 0) return CCFR_ERR_INVALID_ARG;
-    if (!c->counts_dev || c->cap_vf < 0 || c->cap_ee < 0 || c->cap_vv < 0) return CCFR_ERR_INVALID_ARG;
-    if ((c->cap_vf > 0 && !c->vf) || (c->cap_ee > 0 && !c->ee) || (c->cap_vv > 0 && !c->vv))
+    if (!c->counts_dev || c->cap_vf < 0 || c->cap_ee < 0 || c->cap_vv < 0 || c->cap_ve < 0)
+        return CCFR_ERR_INVALID_ARG;
+    if ((c->cap_vf > 0 && !c->vf) || (c->cap_ee > 0 && !c->ee) || (c->cap_vv > 0 && !c->vv) ||
+        (c->cap_ve > 0 && !c->ve))
         return CCFR_ERR_INVALID_ARG;
     if (mesh->ctx != ctx) return CCFR_ERR_INVALID_ARG;
     const hipStream_t s = (hipStream_t)stream;
     const Scene sc = make_scene(mesh, x_anchor_dev, params);
-    enqueue_regions(ctx, sc, c->vf, c->ee, c->vv, c->counts_dev, c->cap_vf, c->cap_ee, c->cap_vv, s,
-                    Marks{ctx, -1, s}, false);
+    const PairLists pl{c->vf, c->ee, c->vv, c->ve, c->cap_vf, c->cap_ee, c->cap_vv, c->cap_ve};
+    enqueue_regions(ctx, sc, pl, c->counts_dev, s, Marks{ctx, -1, s}, false);
     HIP_OK(hipGetLastError());
     out->n_verts = mesh->n_verts;
     out->pad_ = 0;
@@ -873,6 +981,29 @@ int ccfr_project_displacements(ccfr_ctx* ctx, const ccfr_regions* regions, const
     return CCFR_OK;
 }
 
+int ccfr_apply_response(ccfr_ctx* ctx, const ccfr_regions* regions, const float* inv_mass_dev,
+                        const float* y_in_dev, const ccfr_params* params, float dt, float* y_out_dev,
+                        ccfr_stream stream) {
+    if (!ctx || !regions || !params_ok(params) || !(dt > 0.f) || !std::isfinite(dt)) return CCFR_ERR_INVALID_ARG;
+    if ((!inv_mass_dev || !y_in_dev || !y_out_dev) && regions->n_verts > 0) return CCFR_ERR_INVALID_ARG;
+    if (regions->n_verts < 0 || !regions->offsets || (regions->cap > 0 && !regions->hs) || regions->cap < 0)
+        return CCFR_ERR_INVALID_ARG;
+    ResponseArgs ra{};
+    ra.n_verts = regions->n_verts;
+    ra.offsets = regions->offsets;
+    ra.hs = regions->hs;
+    ra.inv_mass = inv_mass_dev;
+    ra.y_in = y_in_dev;
+    ra.y_out = y_out_dev;
+    ra.dt = dt;
+    ra.prm.table = nullptr;
+    ra.prm.vmesh = nullptr;
+    ra.prm.one = mesh_params(params, 0.f, 0, 1.0f);
+    launch_response(ra, (hipStream_t)stream);
+    HIP_OK(hipGetLastError());
+    return CCFR_OK;
+}
+
 int ccfr_xpbd_step(ccfr_ctx* ctx, const ccfr_mesh* mesh, float* x_dev, float* v_dev, const ccfr_step_params* sp,
                    ccfr_stream stream) {
     if (!ctx || !mesh || !step_params_ok(sp)) return CCFR_ERR_INVALID_ARG;
@@ -894,7 +1025,9 @@ int ccfr_xpbd_step(ccfr_ctx* ctx, const ccfr_mesh* mesh, float* x_dev, float* v_
         ctx->prof_last_reuse = ctx->pair_skin > 0 ? 1 : ctx->pair_reuse;
     }
     // profiled steps run eagerly: the stage events bracket the launches on `s`
-    if (!ctx->use_graphs || ctx->profiling) {
+    // the hierarchy's radix sort clears its scratch with memset operations,
+    // which are not recorded into graphs here: those steps run directly
+    if (!ctx->use_graphs || ctx->profiling || ctx->broad_phase == 1) {
         enqueue_step(ctx, plan, s);
         HIP_OK(hipGetLastError());
         return CCFR_OK;
@@ -935,11 +1068,18 @@ int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, 
     if (info) {
         info->status_bits = h.status;
         for (int k = 0; k < 3; ++k) info->last_counts[k] = h.last_pairs[k];
+        info->last_ve = h.last_pairs[3];
         info->last_contacts = h.last_nc;
         info->last_halfspaces = h.last_hs;
         for (int k = 0; k < 6; ++k) info->need[k] = h.need[k];
         for (int k = 0; k < 10; ++k) info->totals[k] = h.totals[k];
         info->candidate_builds = h.builds;
+        info->iterations_run = h.iters_run;
+        info->halt_runs[0] = h.halt_runs[0];
+        info->halt_runs[1] = h.halt_runs[1];
+        info->max_halt_run = h.max_halt_run;
+        info->need_ve = h.need[6];
+        info->total_ve = h.totals[10];
         const int slot_of[3] = {4, 5, 7};
         for (int w = 0; w < 3; ++w)
             for (int k = 0; k < 64; ++k) info->totals[slot_of[w]] += h.spread[w][k];
@@ -952,22 +1092,23 @@ int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, 
         HIP_OK(hipMemcpy(ctx->counters_d, &z, sizeof(z), hipMemcpyHostToDevice));
     }
     if (h.status & ST_NONFINITE) return CCFR_ERR_NONFINITE;
-    if (h.status & (ST_VF | ST_EE | ST_VV | ST_HS | ST_LARGE | ST_CONTACTS)) return CCFR_ERR_CAPACITY;
+    if (h.status & (ST_VF | ST_EE | ST_VV | ST_VE | ST_HS | ST_LARGE | ST_CONTACTS)) return CCFR_ERR_CAPACITY;
     return CCFR_OK;
 }
 
 int ccfr_set_tuning(ccfr_ctx* ctx, const ccfr_tuning* t) {
     if (!ctx || !t || !std::isfinite(t->cell_scale) || t->cell_scale < 0.25f || t->cell_scale > 4.0f ||
         (t->pair_split != 1 && t->pair_split != 3 && t->pair_split != 9) || t->pair_reuse < 0 || t->pair_reuse > 4 ||
-        t->pair_skin < 0 || t->pair_skin > 4)
+        t->pair_skin < 0 || t->pair_skin > 4 || (t->broad_phase != 0 && t->broad_phase != 1))
         return CCFR_ERR_INVALID_ARG;
     const int reuse = std::max(1, (int)t->pair_reuse);
     if (t->cell_scale != ctx->cell_scale || t->pair_split != ctx->pair_split || reuse != ctx->pair_reuse ||
-        t->pair_skin != ctx->pair_skin) {
+        t->pair_skin != ctx->pair_skin || t->broad_phase != ctx->broad_phase) {
         ctx->cell_scale = t->cell_scale;
         ctx->pair_split = t->pair_split;
         ctx->pair_reuse = reuse;
         ctx->pair_skin = t->pair_skin;
+        ctx->broad_phase = t->broad_phase;
         ctx->tune_generation++;
         ctx->generation++;          // recorded graphs carry the old settings
         drop_graph(ctx);
@@ -982,6 +1123,7 @@ int ccfr_get_tuning(const ccfr_ctx* ctx, ccfr_tuning* t) {
     t->pair_split = ctx->pair_split;
     t->pair_reuse = ctx->pair_reuse;
     t->pair_skin = ctx->pair_skin;
+    t->broad_phase = ctx->broad_phase;
     return CCFR_OK;
 }
 

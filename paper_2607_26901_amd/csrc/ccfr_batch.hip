@@ -330,10 +330,11 @@ int64_t ccfr_batch_footprint(int32_t n_verts, int32_t n_tris, int32_t n_edges) {
     // region CSR (12), grid entry twice (sorted and staged) + rank + key (104
     // per binned primitive or vertex) and at most 8 bucket counters and 8
     // offsets (4 B each) per entry,
-    // 8 B per candidate pair slot,
+    // 8 B per candidate pair slot (vertex-face, edge-edge, particle-particle
+    // and particle-edge lists at their default sizes),
     // 48 B per contact slot (half the pair slots) and 44 B per half-space slot
     // (twice the pair slots: record, sort key, sort index)
-    const long long pairs = 8 * N + 8 * E + 16 * F;
+    const long long pairs = 8 * N + 8 * E + 24 * F;
     bytes += 48 * N + 168 * (T + E + F + N) + 8 * pairs + 48 * (pairs / 2) + 44 * (2 * pairs);
     return bytes;
 }
@@ -400,6 +401,8 @@ int ccfr_batch_add(ccfr_batch* b, int32_t n_verts, const int32_t* tris, int32_t 
                    int32_t n_edges, const float* inv_mass, const float* rest_x, const float* x, const float* v,
                    const ccfr_step_params* sp, int32_t* slot, ccfr_stream stream) {
     if (!b || !x || !v || !slot || !step_params_ok(sp)) return CCFR_ERR_INVALID_ARG;
+    if (sp->early_exit) return CCFR_ERR_INVALID_ARG;     // a batch runs its meshes' iterations together
+    if (sp->collision.flags & CCFR_FLAG_RESPONSE) return CCFR_ERR_INVALID_ARG;
     if (b->has_sp && !b->meshes.empty() && !same_step(b->sp, *sp)) return CCFR_ERR_INVALID_ARG;
     for (long long i = 0; i < 3LL * n_verts; ++i)
         if (!std::isfinite(x[i]) || !std::isfinite(v[i])) return CCFR_ERR_INVALID_ARG;
@@ -522,7 +525,9 @@ int ccfr_batch_step(ccfr_batch* b, ccfr_stream stream) {
         HIP_OK(hipGetLastError());
         b->snap_valid = true;
     }
-    if (!ctx->use_graphs || ctx->profiling) {
+    // the hierarchy's radix sort clears its scratch with memset operations,
+    // which are not recorded into graphs here: those steps run directly
+    if (!ctx->use_graphs || ctx->profiling || ctx->broad_phase == 1) {
         enqueue_step(ctx, b->plan, s);
         HIP_OK(hipGetLastError());
         return CCFR_OK;

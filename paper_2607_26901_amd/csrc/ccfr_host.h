@@ -12,6 +12,10 @@
 namespace ccfr {
 namespace host {
 
+// Largest vertex, triangle or edge count of a mesh: pair records keep a
+// primitive index in 30 bits.
+constexpr int32_t kMaxPrims = 1 << 30;
+
 inline int ceil_log2(long long v) {
     int k = 0;
     while ((1LL << k) < v) ++k;
@@ -99,7 +103,13 @@ struct ccfr_ctx {
     int pair_split = 1;         // lanes per broad-phase query (1, 3 or 9)
     int pair_reuse = 1;         // solver iterations per candidate build inside a substep
     int pair_skin = 0;          // > 0: builds widened by pair_skin r, rebuilt when the motion needs it
+    int broad_phase = 0;        // 0: multi-level hash grid, 1: bounding-volume hierarchy
     long long tune_generation = 0;
+
+    // bounding-volume hierarchy (broad_phase 1), sized for cap_lbvh leaves
+    ccfr::LbvhWs lbvh{};
+    long long cap_lbvh = 0;
+    unsigned char* lbvh_sort_temp = nullptr;
 
     // grid
     long long cap_buckets = 0;
@@ -119,7 +129,8 @@ struct ccfr_ctx {
     int32_t* vf = nullptr;
     int32_t* ee = nullptr;
     int32_t* vv = nullptr;
-    long long cap_vf = 0, cap_ee = 0, cap_vv = 0;
+    int32_t* ve = nullptr;
+    long long cap_vf = 0, cap_ee = 0, cap_vv = 0, cap_ve = 0;
 
     // regions
     ccfr::Contact* contacts = nullptr;
@@ -138,6 +149,7 @@ struct ccfr_ctx {
     float* x_start = nullptr;
     float* p = nullptr;
     float* y_def = nullptr;      // proposals the fast projection hands to the slow one
+    uint8_t* halt_run = nullptr; // per vertex: consecutive halts within the current substep
     long long cap_step = 0;
 
     StepGraph graph;
@@ -195,6 +207,10 @@ struct StepPlan {
     double skin = 0.0;
     // nullable: [iters][N][3] receives the anchor after every iteration
     float* trace = nullptr;
+    // evaluateConvergence: end the iterations once the largest shortfall of a
+    // projection is at most conv_tol
+    bool early_exit = false;
+    float conv_tol = 0.f;
 };
 
 void drop_graph(ccfr_ctx* ctx);

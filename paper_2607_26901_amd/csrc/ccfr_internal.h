@@ -23,7 +23,9 @@
 
 namespace ccfr {
 
-enum : int { KIND_VF = 1, KIND_EE = 2, KIND_VV = 3 };
+// pair kinds (the top bits of a half-space key): particle-edge, vertex-face,
+// edge-edge, particle-particle
+enum : int { KIND_VE = 0, KIND_VF = 1, KIND_EE = 2, KIND_VV = 3 };
 
 // Per-vertex flags: a free particle (in no edge and no triangle); an endpoint
 // of an edge of the first stretch colour (the pass starts in the iteration's
@@ -33,7 +35,7 @@ enum : uint8_t { VF_FREE = 1, VF_COLOR0 = 2 };
 // status bits (sticky)
 enum : uint32_t {
     ST_VF = 1u, ST_EE = 2u, ST_VV = 4u, ST_HS = 8u, ST_LARGE = 16u, ST_CONTACTS = 32u,
-    ST_NONFINITE = 64u,
+    ST_NONFINITE = 64u, ST_VE = 128u,
 };
 
 struct MeshParams {
@@ -41,21 +43,23 @@ struct MeshParams {
     float eps_retract, eps_plesnik, h, inv_h;   // h: grid cell size of this mesh
     int32_t max_passes, mesh_salt;
     float pad_wide;     // box pad of moving primitives in builds widened by a fixed skin
-    int32_t pad1;
+    int32_t response;   // 1: soft response and friction before the projection (Sec. 3.3)
+    float delta, resp_compliance, vis_width, mu_s, mu_k;
+    int32_t pad2[3];
 };
 
 // Device counters shared by all kernels of a context.
 struct DevCounters {
     uint32_t status;
-    int32_t n_vf, n_ee, n_vv;          // pair counts of the current build
+    int32_t n_vf, n_ee, n_vv, n_ve;    // pair counts of the current build (in this order: the
+                                       // candidate lists' counts_dev points at n_vf)
     int32_t n_large_t, n_large_e;      // large primitives of the current build
     int32_t n_contacts;                // pairs inside the range
     int32_t n_viol;                    // deferred vertices with small regions (slow list front)
     int32_t last_hs;
     int32_t n_viol_b;                  // deferred vertices with larger regions (slow list back)
     int32_t last_nc;                   // contacts of the last closed region build
-    int32_t last_pairs[3];             // VF, EE, VV of the last closed candidate build
-    int32_t pad0;
+    int32_t last_pairs[4];             // VF, EE, VV, VE of the last closed candidate build
     // substeps whose candidate builds adapt to the motion: whether this
     // iteration builds, the largest coordinate move of the last projection
     // (FP32 bits, rounded up), and the moves summed since the last build
@@ -65,32 +69,51 @@ struct DevCounters {
     // number any vertex received (beyond its slots they are dropped)
     int32_t n_hs, max_slot;
     long long builds;                  // candidate builds closed
-    long long need[6];                 // max sizes seen: vf, ee, vv, contacts, hs, large
-    long long totals[10];              // vf, ee, vv, hs, violating, halted, degenerate, projected,
-                                       // contacts, region builds
+    // the convergence check of a substep (evaluateConvergence of Alg. 4, with
+    // early exit): the largest shortfall |p - x| - |y*| of the last projection
+    // (FP32 bits, rounded up), whether the substep's iterations have ended,
+    // and the iterations run
+    uint32_t shortfall_max, converged;
+    long long iters_run;
+    // consecutive halts of one vertex within a substep: the longest run seen,
+    // and the halts that extended a run to 2 or to 3 and more
+    int32_t max_halt_run, pad3;
+    long long halt_runs[2];
+    long long need[7];                 // max sizes seen: vf, ee, vv, contacts, hs, large, ve
+    long long totals[11];              // vf, ee, vv, hs, violating, halted, degenerate, projected,
+                                       // contacts, region builds, ve
     // per-vertex tallies of the projection (violating, halted, projected),
     // spread over 64 slots by block so that the atomics do not queue on one
     // address; the host adds them into totals[4], [5], [7]
     long long spread[3][64];
 };
 
+// Capacities of the four candidate lists.
+struct PairCaps {
+    int64_t vf, ee, vv, ve;
+};
+
 // End of a candidate build (one thread): overflow bits, largest sizes, totals.
-__device__ __forceinline__ void finalize_pairs_body(DevCounters* c, int64_t cap_vf, int64_t cap_ee, int64_t cap_vv) {
-    const long long nvf = c->n_vf, nee = c->n_ee, nvv = c->n_vv;
+__device__ __forceinline__ void finalize_pairs_body(DevCounters* c, const PairCaps& caps) {
+    const long long nvf = c->n_vf, nee = c->n_ee, nvv = c->n_vv, nve = c->n_ve;
     uint32_t st = 0;
-    if (nvf > cap_vf) st |= ST_VF;
-    if (nee > cap_ee) st |= ST_EE;
-    if (nvv > cap_vv) st |= ST_VV;
+    if (nvf > caps.vf) st |= ST_VF;
+    if (nee > caps.ee) st |= ST_EE;
+    if (nvv > caps.vv) st |= ST_VV;
+    if (nve > caps.ve) st |= ST_VE;
     if (st) c->status |= st;
     c->need[0] = max(c->need[0], nvf);
     c->need[1] = max(c->need[1], nee);
     c->need[2] = max(c->need[2], nvv);
+    c->need[6] = max(c->need[6], nve);
     c->totals[0] += nvf;
     c->totals[1] += nee;
     c->totals[2] += nvv;
+    c->totals[10] += nve;
     c->last_pairs[0] = (int32_t)nvf;
     c->last_pairs[1] = (int32_t)nee;
     c->last_pairs[2] = (int32_t)nvv;
+    c->last_pairs[3] = (int32_t)nve;
     c->builds += 1;
 }
 
@@ -140,7 +163,7 @@ __device__ __forceinline__ void finalize_slot_regions_body(DevCounters* c, int32
 }
 
 __device__ __forceinline__ void reset_build_counters(DevCounters* c) {
-    c->n_vf = c->n_ee = c->n_vv = 0;
+    c->n_vf = c->n_ee = c->n_vv = c->n_ve = 0;
     c->n_large_t = c->n_large_e = 0;
     reset_region_counters(c);
 }
@@ -170,6 +193,8 @@ struct alignas(16) Contact {
     // the vertices that receive a half-space, side A first (one for a vertex or
     // particle, two for an edge), then side B; -1 for a static vertex or none
     int32_t rv[4];
+    float sA, sB;      // the shares s of side A and side B (Eq. 2)
+    int32_t pad[2];
 };
 
 struct ParamSrc {
@@ -229,6 +254,8 @@ struct Scene {
     int32_t skin_iters;         // candidate builds: further iterations the lists must cover
     int32_t skin_wide;          // candidate builds: moving boxes padded by MeshParams::pad_wide
     int32_t build_gated;        // candidate builds: run only when DevCounters::rebuild is set
+    const uint32_t* skip;       // nullable: kernels return at once when *skip != 0 (the
+                                // substep's iterations ended at the convergence check)
     ParamSrc prm;
 };
 
@@ -268,16 +295,44 @@ struct GridWs {
     }
 };
 
+// The candidate lists: (vertex, triangle), (edge, edge), (particle, particle)
+// and (particle, edge) pairs.
 struct PairLists {
-    int32_t* vf; int32_t* ee; int32_t* vv;
-    int64_t cap_vf, cap_ee, cap_vv;
+    int32_t* vf; int32_t* ee; int32_t* vv; int32_t* ve;
+    int64_t cap_vf, cap_ee, cap_vv, cap_ve;
+    __host__ __device__ PairCaps caps() const { return PairCaps{cap_vf, cap_ee, cap_vv, cap_ve}; }
 };
+
+// The hierarchy broad phase (k_lbvh.hip): buffers for L = T + E + F leaves.
+struct LbvhWs {
+    float* leaf_lo;          // [L][3] padded boxes, in target order
+    float* leaf_hi;          // [L][3]
+    uint32_t* leaf_meta;     // [L] bit 0 static, bits 8.. mesh id; ~0 = not binned
+    uint64_t* keys_in;       // [L] Morton codes, target order
+    uint64_t* keys_out;      // [L] sorted
+    int32_t* idx_in;         // [L] target indices
+    int32_t* idx_out;        // [L] target of each sorted position
+    int32_t* leaf_parent;    // [L] by sorted position
+    int32_t* child;          // [L - 1][2] children (bit 31: a leaf's sorted position)
+    int32_t* node_parent;    // [L - 1]
+    int32_t* node_flag;      // [L - 1] refit arrivals
+    float* node_lo;          // [L - 1][3]
+    float* node_hi;          // [L - 1][3]
+    void* sort_temp;
+    size_t sort_temp_bytes;
+};
+size_t lbvh_sort_temp_bytes(int n);
+// Build the hierarchy over the targets of `sc`; then emit every candidate pair
+// into pl (counts in c->n_vf, n_ee, n_vv, n_ve; list overflow as for the grid).
+void launch_lbvh_build(const Scene& sc, LbvhWs& w, DevCounters* c, hipStream_t s);
+void launch_lbvh_query(const Scene& sc, const LbvhWs& w, PairLists pl, DevCounters* c, hipStream_t s);
 
 void launch_reset_build(DevCounters* c, uint32_t* level_mask, int n_meshes, hipStream_t s);
 void launch_grid_count(const Scene& sc, GridWs& g, DevCounters* c, hipStream_t s);
-// run_flag (nullable): the scan does nothing when *run_flag is 0
+// run_flag (nullable): the scan does nothing when *run_flag is 0; skip
+// (nullable): nor when *skip is not 0
 void launch_scan(const int32_t* in, int32_t* out, int32_t* zero_in, int n, int32_t* tmp, hipStream_t s,
-                 const uint32_t* run_flag = nullptr);
+                 const uint32_t* run_flag = nullptr, const uint32_t* skip = nullptr);
 void launch_grid_scatter(const Scene& sc, GridWs& g, DevCounters* c, hipStream_t s);
 void launch_pairs(const Scene& sc, const GridWs& g, PairLists pl, DevCounters* c, int split, hipStream_t s);
 void launch_finalize_pairs(const GridWs& g, PairLists pl, DevCounters* c, hipStream_t s);
@@ -285,10 +340,10 @@ void launch_finalize_pairs(const GridWs& g, PairLists pl, DevCounters* c, hipStr
 // The contact list of the candidate pairs; vcount counts each vertex's
 // half-spaces for the CSR unless `for_slots` (launch_fill_slots counts them)
 struct ColourJob;
-void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
-                     const int32_t* counts, int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
-                     Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s,
-                     bool for_slots = false, const ColourJob* job = nullptr);
+// (counts: the four list lengths, VF, EE, VV, VE, on the device)
+void launch_contacts(const Scene& sc, const PairLists& pl, const int32_t* counts, Contact* contacts,
+                     int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s, bool for_slots = false,
+                     const ColourJob* job = nullptr);
 // The contacts' half-spaces into per-vertex slots: slot_hs[v * slot_stride + k]
 // for the k-th one vertex v receives (vcount[v] counts them)
 void launch_fill_slots(const Scene& sc, const Contact* contacts, int64_t cap_contacts, int32_t* vcount,
@@ -448,38 +503,66 @@ struct ProjectArgs {
     ParamSrc prm;
     StretchLast sl;
     RestartJob next;         // the next iteration's stretch start, in extra blocks of the slow kernel
+    const uint32_t* skip;    // nullable: return at once when *skip != 0
+    uint32_t* shortfall_max; // nullable: largest |proposal| - |result| (FP32 bits, rounded up)
+    uint8_t* halt_run;       // nullable: per-vertex consecutive halts, updated with every result
 };
 // zero_counters: clear the slow-list counters first (the substep clears them
 // in launch_close_iteration instead)
 void launch_project(const ProjectArgs& a, DevCounters* c, bool zero_counters, hipStream_t s);
 
+// applyResponse of Alg. 4 (Sec. 3.3) per vertex on its region: proposals read
+// from y_in (or p - x_anchor when y_in is null), results written to y_out (or
+// into p, as the new proposal, when y_out is null).
+struct ResponseArgs {
+    int32_t n_verts;
+    const int32_t* offsets;          // CSR regions (slot_stride == 0)
+    const ccfr_halfspace* hs;
+    const int32_t* slot_counts;      // per-vertex slots (slot_stride > 0)
+    int32_t slot_stride;
+    const float* inv_mass;
+    const float* y_in;
+    const float* x_anchor;
+    float* p;
+    float* y_out;
+    float dt;
+    ParamSrc prm;
+    const uint32_t* skip;
+};
+void launch_response(const ResponseArgs& a, hipStream_t s);
+
+// halt_run (nullable): per-vertex consecutive-halt counts, cleared for the
+// substep; iters_add: iterations the substep runs for certain (added to the
+// counters' iterations run; 0 when its convergence check counts them)
 void launch_predict(int n, const float* x, const float* v, const float* inv_mass, float dt,
-                    float gx, float gy, float gz, float* x_pred, float* x_start, hipStream_t s);
+                    float gx, float gy, float gz, float* x_pred, float* x_start, hipStream_t s,
+                    uint8_t* halt_run = nullptr, DevCounters* c = nullptr, int iters_add = 0);
 void launch_fill_zero(float* p, int64_t n, hipStream_t s);
 void launch_copy(const float* src, float* dst, int64_t n, hipStream_t s);
 // Between the region build and the stretch pass of a substep iteration: close
 // the region build and, unless the next iteration reuses the lists, the
 // candidate build (overflow bits, totals), clear the per-build counters (and
 // then the level masks) for the next build, and copy the prediction into p.
-struct PairCaps {
-    int64_t vf, ee, vv;
-};
 // slot_stride > 0: the region build went into per-vertex slots (offsets unused)
 void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounters* c, uint32_t* level_mask,
                             int n_meshes, int32_t n_verts, const int32_t* offsets, PairCaps caps,
                             int64_t cap_contacts, int64_t cap_hs, bool close_pairs, hipStream_t s,
                             int32_t slot_stride = 0, const StretchColor0* c0 = nullptr, bool finalize = true,
-                            const ColourJob* job = nullptr);
+                            const ColourJob* job = nullptr, const uint32_t* skip = nullptr);
 // Before the candidate stage of an iteration in a substep whose builds adapt to
 // the motion: adds the last projection's largest move to the moves summed
 // since the last build; if the sum may exceed `skin` (the least widening of
 // any mesh's moving boxes), closes the last build and asks for a new one
 // (DevCounters::rebuild), else the stage's kernels leave the lists as they are.
 void launch_decide_build(DevCounters* c, uint32_t* level_mask, int n_meshes, double skin, PairCaps caps,
-                         hipStream_t s);
+                         hipStream_t s, const uint32_t* skip = nullptr);
+// evaluateConvergence of Alg. 4 (one thread): at the start of iteration
+// `first == 0`, the substep's iterations end (DevCounters::converged) once the
+// last projection's largest shortfall is at most tol; counts the iterations run.
+void launch_decide_converged(DevCounters* c, float tol, int first, hipStream_t s);
 void launch_stretch_segments(const int32_t* edges_sorted, const float* rest_sorted, const int2* segs, int32_t nseg,
                              int32_t total, const float* inv_mass, float* p, float* lambda_sorted, float alpha_t,
-                             hipStream_t s);
+                             hipStream_t s, const uint32_t* skip = nullptr);
 // last_edge[v] for the colour class (edges as in a stretch colour: nseg
 // segments, total edges) as StretchLast reads it; n_verts entries.
 void launch_last_colour_map(const int32_t* edges_sorted, const int2* segs, int32_t nseg, int32_t total,

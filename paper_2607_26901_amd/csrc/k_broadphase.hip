@@ -4,8 +4,9 @@
 // box is lo = fl32(min_v x_v - pad), hi = fl32(max_v x_v + pad) per axis; two
 // primitives are a candidate pair iff their boxes overlap on all three axes.
 // Pair kinds: vertex-face (vertex not in the triangle), edge-edge (no shared
-// vertex, e < e'), free particle pairs (i < j); pairs whose vertices all have
-// zero inverse mass are skipped, and primitives of different meshes never pair.
+// vertex, e < e'), free particle pairs (i < j), free particle and edge; pairs
+// whose vertices all have zero inverse mass are skipped, and primitives of
+// different meshes never pair.
 // The grid below only decides which pairs are tested; the set is decided by the
 // box test alone.
 //
@@ -43,6 +44,7 @@
 //                slices out when one is nearly full, and what is left at the
 //                end goes out with one atomic per block and list
 #include "ccfr_internal.h"
+#include "pair_emit.h"
 
 #include <algorithm>
 
@@ -220,6 +222,8 @@ __global__ void k_reset_build(DevCounters* c, uint32_t* level_mask, int n_meshes
         c->rebuild = 1u;            // the first build of a substep or a standalone build
         c->motion_max = 0u;
         c->motion_acc = 0.0;
+        c->converged = 0u;          // a substep's iterations run until its convergence check ends them
+        c->shortfall_max = 0u;
     }
     for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n_meshes; m += gridDim.x * blockDim.x)
         level_mask[m] = 0u;
@@ -237,6 +241,7 @@ __device__ __forceinline__ int entry_level(const Target& tg, const float lo[3], 
 }
 
 __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCounters* c) {
+    if (sc.skip && *sc.skip) return;             // the substep's iterations have ended
     if (sc.build_gated && !c->rebuild) return;   // the lists of an earlier build still hold
     const int n_all = sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts;
     const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -281,6 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_count(Scene sc, GridWs g, DevCo
 }
 
 __global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g, const DevCounters* c) {
+    if (sc.skip && *sc.skip) return;
     if (sc.build_gated && !c->rebuild) return;
     const int n_all = sc.n_tris + sc.n_edges + sc.n_free + sc.n_verts;
     const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -290,115 +296,13 @@ __global__ __launch_bounds__(kBlock) void k_grid_scatter(Scene sc, GridWs g, con
     g.entries[g.start[key] + g.rank[t]] = g.staged[t];
 }
 
-// Found pairs are staged in LDS.  Vertex-face and edge-edge pairs: every lane
-// owns a slice of kLaneCap pairs of the block's array lane_pairs[slot][thread]
-// and counts its pairs in a register, so an append is one LDS store and needs
-// no exchange with other lanes.  A slice holds only the partner of each pair,
-// the other primitive being the lane's own query, so that the block's LDS
-// leaves room for every block of a launch at once: a vertex query's partners
-// are triangles (vertex-face list) and, for a free particle, particles (the
-// particle list; tagged by the top bit), an edge query's are edges.  Before a
-// round of kRound entries, a wavefront whose lanes might overflow their slices
-// writes them out (one atomic per list).
-constexpr int kWaves = kBlock / 64;
+// Found pairs are staged in per-lane LDS slices (pair_emit.h).
+static_assert(kBlock == kEmitBlock, "the pair kernel stages pairs in blocks of kEmitBlock lanes");
 constexpr int kRound = 4;      // entries read per round of a bucket walk
-constexpr int kLaneCap = 32;   // pairs per lane slice
-
-#define LDS_PTR __attribute__((address_space(3)))
-
-struct LaneBuf {
-    LDS_PTR int32_t* slot0;    // &lane_pairs[0][thread]; slot s at slot0[s * kBlock]: a partner
-    int fill;                  // entries in the slice
-    int n_vv;                  // of them particle partners (top bit set)
-    bool vert;                 // vertex query: pairs (self, triangle); edge query: edge pairs (min, max)
-    int self;                  // the query: vertex or edge
-};
-
-__device__ __forceinline__ void lane_put(LaneBuf& lb, int partner, bool pred) {
-    if (pred) {
-        lb.slot0[lb.fill * kBlock] = partner;
-        ++lb.fill;
-    }
-}
-
-__device__ __forceinline__ void lane_put_vv(LaneBuf& lb, int partner, bool pred) {
-    if (pred) {
-        lb.slot0[lb.fill * kBlock] = partner | (int)0x80000000;
-        ++lb.fill;
-        ++lb.n_vv;
-    }
-}
-
-// Exclusive prefix (over the lanes below this one) and total of `n`
-// (0..kLaneCap) among the active lanes for which `mine` holds; lanes outside
-// take no part.
-__device__ __forceinline__ void wave_prefix(int n, bool mine, int& pre, int& tot) {
-    const unsigned long long below = (1ull << __lane_id()) - 1ull;
-    pre = tot = 0;
-#pragma unroll
-    for (int bit = 0; (1 << bit) <= kLaneCap; ++bit) {
-        const unsigned long long m = __ballot(mine && ((n >> bit) & 1));
-        pre += __popcll(m & below) << bit;
-        tot += __popcll(m) << bit;
-    }
-}
-
-// Writes a lane's slice: its first-list pairs (vertex-face or edge-edge) from
-// position `at`, its particle pairs from `at_vv`.
-__device__ __forceinline__ void lane_write(const LaneBuf& lb, const PairLists& pl, long long at, long long at_vv) {
-    int32_t* list = lb.vert ? pl.vf : pl.ee;
-    const int64_t cap = lb.vert ? pl.cap_vf : pl.cap_ee;
-    for (int s = 0; s < lb.fill; ++s) {
-        const int pr = lb.slot0[s * kBlock];
-        if (pr < 0) {
-            const int q = pr & 0x7fffffff;
-            if (at_vv < pl.cap_vv) {
-                pl.vv[2 * at_vv + 0] = min(lb.self, q);
-                pl.vv[2 * at_vv + 1] = max(lb.self, q);
-            }
-            ++at_vv;
-        } else {
-            if (at < cap) {
-                list[2 * at + 0] = lb.vert ? lb.self : min(lb.self, pr);
-                list[2 * at + 1] = lb.vert ? pr : max(lb.self, pr);
-            }
-            ++at;
-        }
-    }
-}
-
-// The slice counts' prefix and total per list among the active lanes.
-struct KindPrefix {
-    int pv, tv, pe, te, pp, tp;
-    __device__ __forceinline__ explicit KindPrefix(const LaneBuf& lb) {
-        const int main = lb.fill - lb.n_vv;
-        wave_prefix(main, lb.vert, pv, tv);
-        wave_prefix(main, !lb.vert, pe, te);
-        wave_prefix(lb.n_vv, true, pp, tp);
-    }
-};
-
-// The active lanes of a wavefront write their slices out.
-__device__ __forceinline__ void lane_flush(LaneBuf& lb, const PairLists& pl, DevCounters* c) {
-    const KindPrefix kp(lb);
-    const int lead = __ffsll((long long)__ballot(true)) - 1;
-    int bv = 0, be = 0, bp = 0;
-    if (__lane_id() == lead) {
-        if (kp.tv) bv = atomicAdd(&c->n_vf, kp.tv);
-        if (kp.te) be = atomicAdd(&c->n_ee, kp.te);
-        if (kp.tp) bp = atomicAdd(&c->n_vv, kp.tp);
-    }
-    bv = __shfl(bv, lead);
-    be = __shfl(be, lead);
-    bp = __shfl(bp, lead);
-    lane_write(lb, pl, lb.vert ? (long long)bv + kp.pv : (long long)be + kp.pe, (long long)bp + kp.pp);
-    lb.fill = 0;
-    lb.n_vv = 0;
-}
 
 // Called by the active lanes before a round that may append up to kRound pairs each.
 __device__ __forceinline__ void lane_room(LaneBuf& lb, const PairLists& pl, DevCounters* c) {
-    if (__ballot(lb.fill > kLaneCap - kRound) != 0ull) lane_flush(lb, pl, c);
+    lane_room_for(lb, pl, c, kRound);
 }
 
 // Cells of the stencil [clo - 1, chi] that work item `part` of `split` walks:
@@ -530,6 +434,24 @@ __device__ __forceinline__ void scan_vv(Src src, int i0, int i1, int ord, const 
     }
 }
 
+// Free particle v against the edge entries [i0, i1) of one cell of level l (a
+// free particle is in no edge, so no shared vertex is possible).
+template <class Src>
+__device__ __forceinline__ void scan_ve(Src src, int i0, int i1, const GridEntry& me, int mesh, int l, bool q_static,
+                                        LaneBuf& lb, const PairLists& pl, DevCounters* c) {
+    for (int i = i0; i < i1; i += kRound) {
+        lane_room(lb, pl, c);
+        GridEntry e[kRound];
+#pragma unroll
+        for (int u = 0; u < kRound; ++u) e[u] = src.get(min(i + u, i1 - 1));
+#pragma unroll
+        for (int u = 0; u < kRound; ++u) {
+            const bool hit = (i + u < i1) & entry_ok(e[u], mesh, l, q_static) & overlap(me.lo, me.hi, e[u].lo, e[u].hi);
+            lane_put_ve(lb, e[u].idx, hit);
+        }
+    }
+}
+
 // Edge query eq = (a, bb) of level lq against the edge entries [i0, i1) of one
 // cell of level l (half shell with the cell's order `ord` when l == lq).
 template <class Src>
@@ -577,6 +499,23 @@ __device__ void walk_vf_global(const GridWs& g, const GridEntry& me, int v, int 
     }
 }
 
+__device__ void walk_ve_global(const GridWs& g, const GridEntry& me, int mesh, int l, int salt, bool q_static,
+                               const int clo[3], const int r0[3], const int r1[3], LaneBuf& lb,
+                               const PairLists& pl, DevCounters* c) {
+    const GlobalSrc src{g.entries};
+    const int tb = table_of(1, l);
+    for (int cz = r0[2]; cz <= r1[2]; ++cz) {
+        Layer L;
+        layer_ranges(g, tb, salt, cz, r0, r1, clo, false, L);
+#pragma unroll 1
+        for (int k = 0; k < 9; ++k) {
+            const int s0 = L.s0[0], s1 = L.s1[0];
+            L.shift();
+            scan_ve(src, s0, s1, me, mesh, l, q_static, lb, pl, c);
+        }
+    }
+}
+
 __device__ void walk_vv_global(const GridWs& g, const GridEntry& me, int v, int mesh, int salt, bool q_static,
                                const int clo[3], const int r0[3], const int r1[3], LaneBuf& lb,
                                const PairLists& pl, DevCounters* c) {
@@ -607,36 +546,6 @@ __device__ void walk_ee_global(const GridWs& g, const GridEntry& me, int eq, int
     }
 }
 
-// The block is done: what is left in the lane slices goes out with one atomic
-// per list for the whole block.  Every thread of the block calls it.
-__device__ void block_flush(LaneBuf& lb, const PairLists& pl, DevCounters* c) {
-    __shared__ int wsum[kWaves][3];
-    __shared__ int base[kWaves][3];
-    const int wave = threadIdx.x / 64;
-    const KindPrefix kp(lb);
-    if (__lane_id() == 0) {
-        wsum[wave][0] = kp.tv;
-        wsum[wave][1] = kp.te;
-        wsum[wave][2] = kp.tp;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t* counters[3] = {&c->n_vf, &c->n_ee, &c->n_vv};
-        for (int k = 0; k < 3; ++k) {
-            int acc = 0;
-            for (int w = 0; w < kWaves; ++w) {
-                base[w][k] = acc;
-                acc += wsum[w][k];
-            }
-            const int b0 = acc ? atomicAdd(counters[k], acc) : 0;
-            for (int w = 0; w < kWaves; ++w) base[w][k] += b0;
-        }
-    }
-    __syncthreads();
-    lane_write(lb, pl, lb.vert ? (long long)base[wave][0] + kp.pv : (long long)base[wave][1] + kp.pe,
-               (long long)base[wave][2] + kp.pp);
-}
-
 // Work item = (query, part of its stencil) with `split` lanes per query; every
 // lane walks its stencil through global memory.  A wavefront takes 64
 // consecutive items of one kind: vertex items (vertex-face and particle pairs)
@@ -646,10 +555,11 @@ __device__ void block_flush(LaneBuf& lb, const PairLists& pl, DevCounters* c) {
 // queries.
 __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists pl, DevCounters* c, int split,
                                                   long long vwaves, long long waves) {
+    if (sc.skip && *sc.skip) return;
     if (sc.build_gated && !c->rebuild) return;
-    __shared__ int32_t lane_pairs[kLaneCap][kBlock];
-    LaneBuf lb{(LDS_PTR int32_t*)&lane_pairs[0][threadIdx.x], 0, 0, true, 0};
-    const long long w = (long long)xcd_block(blockIdx.x, gridDim.x) * kWaves + threadIdx.x / 64;
+    __shared__ int32_t lane_pairs[kLaneCap][kEmitBlock];
+    LaneBuf lb{(LDS_PTR int32_t*)&lane_pairs[0][threadIdx.x], 0, 0, 0, true, 0};
+    const long long w = (long long)xcd_block(blockIdx.x, gridDim.x) * kEmitWaves + threadIdx.x / 64;
     const long long vw = w * vwaves / waves;                 // vertex wavefronts before w
     const bool vwave = (w + 1) * vwaves / waves > vw;
     const long long item = (vwave ? vw : w - vw) * 64 + __lane_id();
@@ -660,7 +570,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
     if (w >= waves) {
         // past the last wavefront: no query
     } else if (vwave && q < nv_q) {
-        // ---- vertex query: vertex-face pairs, and particle pairs for free particles
+        // ---- vertex query: vertex-face pairs, and for a free particle its
+        //      particle pairs and particle-edge pairs
         const GridEntry me = g.entries[v0 + q];
         const int v = me.idx;
         lb.self = v;
@@ -677,7 +588,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
             stencil_cells(me, ldexpf(P.inv_h, -l), clo, chi);
             if (!part_range(split, part, clo, chi, r0, r1)) continue;
             walk_vf_global(g, me, v, mesh, l, salt, q_static, clo, r0, r1, lb, pl, c);
-            if (q_free && l == 0) walk_vv_global(g, me, v, mesh, salt, q_static, clo, r0, r1, lb, pl, c);
+            if (q_free) {
+                walk_ve_global(g, me, mesh, l, salt, q_static, clo, r0, r1, lb, pl, c);
+                if (l == 0) walk_vv_global(g, me, v, mesh, salt, q_static, clo, r0, r1, lb, pl, c);
+            }
         }
     } else if (!vwave && q < ne_q) {
         // ---- edge query: edge-edge pairs
@@ -705,7 +619,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(Scene sc, GridWs g, PairLists 
 }
 
 __global__ void k_finalize_pairs(PairLists pl, DevCounters* c) {
-    if (threadIdx.x == 0) finalize_pairs_body(c, pl.cap_vf, pl.cap_ee, pl.cap_vv);
+    if (threadIdx.x == 0) finalize_pairs_body(c, pl.caps());
 }
 
 }  // namespace
@@ -736,7 +650,7 @@ void launch_pairs(const Scene& sc, const GridWs& g, PairLists pl, DevCounters* c
     // on the device only: the items cover every vertex and every edge)
     const long long vwaves = ((long long)sc.n_verts * split + 63) / 64;
     const long long waves = vwaves + ((long long)sc.n_edges * split + 63) / 64;
-    hipLaunchKernelGGL(k_pairs, dim3((unsigned)((waves + kWaves - 1) / kWaves)), dim3(kBlock), 0, s, sc, g, pl, c,
+    hipLaunchKernelGGL(k_pairs, dim3((unsigned)((waves + kEmitWaves - 1) / kEmitWaves)), dim3(kBlock), 0, s, sc, g, pl, c,
                        split, vwaves, waves);
 }
 

@@ -275,10 +275,29 @@ __device__ __forceinline__ d3 load_prop_first(const ProjectArgs& a, int v) {
 
 // Writes the clamped displacement (or adds it to the anchor) and returns the
 // largest coordinate move of the anchor, exact in FP64 and rounded up to FP32
-// (0 when the anchor is not updated).
-__device__ __forceinline__ float write_result(const ProjectArgs& a, int v, d3 y, double r, bool halted) {
+// (0 when the anchor is not updated).  With a.shortfall_max, sf takes the
+// larger of itself and the vertex's shortfall nprop - |y| (nprop = |proposal|,
+// 0 for a vertex that does not count); with a.halt_run, the vertex's run of
+// consecutive halts grows or ends, and runs of 2 and more are tallied.
+__device__ __forceinline__ float write_result(const ProjectArgs& a, DevCounters* c, int v, d3 y, double r,
+                                              bool halted, double nprop, float& sf) {
     const double ny = norm(y);
     if (ny > r) y = (r / ny) * y;                      // r-ball clamp
+    if (a.shortfall_max && nprop > 0.0) {
+        const double f = nprop - fmin(ny, r);
+        float ff = (float)f;
+        if ((double)ff < f) ff = __int_as_float(__float_as_int(ff) + 1);
+        sf = fmaxf(sf, ff);
+    }
+    if (a.halt_run) {
+        const int prev = a.halt_run[v];
+        const int run = halted ? min(prev + 1, 255) : 0;
+        if (run != prev) a.halt_run[v] = (uint8_t)run;
+        if (run >= 2) {
+            atomicAdd((unsigned long long*)&c->halt_runs[run >= 3 ? 1 : 0], 1ull);
+            atomicMax(&c->max_halt_run, run);
+        }
+    }
     float move = 0.0f;
     if (a.y_out) {
         a.y_out[3 * v] = (float)y.x;
@@ -305,8 +324,15 @@ __device__ __forceinline__ float wave_max(float x) {
     return x;
 }
 
-// Largest move of a wavefront's lanes into the device maximum (non-negative
-// floats order like their bit patterns).
+// Largest shortfall of a wavefront's vertices into the launch-wide maximum
+// (non-negative floats order like their bit patterns).
+__device__ __forceinline__ void record_shortfall(const ProjectArgs& a, float sf) {
+    if (!a.shortfall_max) return;
+    const float m = wave_max(sf);
+    if (__lane_id() == 0 && m > 0.0f) atomicMax(a.shortfall_max, __float_as_uint(m));
+}
+
+// Largest move of a wavefront's lanes into the device maximum.
 __device__ __forceinline__ void record_motion(const ProjectArgs& a, float move) {
     if (!a.motion_max) return;
     const float m = wave_max(move);
@@ -402,10 +428,11 @@ __device__ __forceinline__ bool one_plane_regs(const float4 (&R)[kSmall], int K,
 // (none: done); larger ones go to the wavefront path unexamined, so that no
 // lane walks a long region while the rest of its wavefront waits.
 __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCounters* c) {
+    if (a.skip && *a.skip) return;                 // the substep's iterations have ended
     const int v = blockIdx.x * kBlock + threadIdx.x;
     const bool active = v < a.n_verts;
     bool violated = false, deferred = false, big = false, moved = false, bad = false;
-    float move = 0.0f;
+    float move = 0.0f, sf = 0.0f;
     d3 ykeep = mk(0.0, 0.0, 0.0);
     if (active) {
         const d3 yprop = load_prop_first(a, v);
@@ -413,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
         bad = !(isfinite(yprop.x) && isfinite(yprop.y) && isfinite(yprop.z));
         if (bad) {
             // a non-finite proposal is not moved and raises the status bit
-            move = write_result(a, v, mk(0.0, 0.0, 0.0), 0.0, true);
+            move = write_result(a, c, v, mk(0.0, 0.0, 0.0), 0.0, true, 0.0, sf);
         } else if (a.inv_mass[v] > 0.0f) {
             moved = true;
             const MeshParams P = a.prm.get(a.prm.mesh_of(v));
@@ -436,7 +463,7 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
                     for (int k = 0; k < 4; ++k) any = any || (k0 + k < K && rho_at(R4[k], yprop) < 0.0);
                 }
                 deferred = any;
-                if (!deferred) move = write_result(a, v, yprop, (double)P.r, false);
+                if (!deferred) move = write_result(a, c, v, yprop, (double)P.r, false, norm(yprop), sf);
             } else {
                 float4 R[kSmall];
 #pragma unroll
@@ -454,10 +481,10 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
                 d3 y = yprop;
                 if (n_viol == 1) deferred = !one_plane_regs(R, K, hv, yprop, P, y);
                 else deferred = n_viol > 1;
-                if (!deferred) move = write_result(a, v, y, (double)P.r, false);
+                if (!deferred) move = write_result(a, c, v, y, (double)P.r, false, norm(yprop), sf);
             }
         } else {
-            move = write_result(a, v, mk(0.0, 0.0, 0.0), 0.0, false);
+            move = write_result(a, c, v, mk(0.0, 0.0, 0.0), 0.0, false, 0.0, sf);
         }
     }
     if (active && !deferred) slots_consumed(a, v);
@@ -468,6 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
         a.sl.y_def[3 * v + 2] = (float)ykeep.z;
     }
     record_motion(a, move);
+    record_shortfall(a, sf);
     // vertices that need the full Alg. 2 go to the slow list, one atomic per
     // block and list: small regions from the front, larger ones from the back
     const unsigned long long md = __ballot(deferred && !big);
@@ -622,7 +650,8 @@ __device__ __forceinline__ float4 take(const float4 (&R)[kChunks], int chunk, in
 // the rest of it runs on the length of yt (one subtraction per violation; the
 // result differs from the step-by-step rescaling by rounding only).
 // Returns the anchor's largest coordinate move (on lane 0; 0 elsewhere).
-__device__ __forceinline__ float project_wave_vertex(const ProjectArgs& a, DevCounters* c, WaveLds* L, int v) {
+__device__ __forceinline__ float project_wave_vertex(const ProjectArgs& a, DevCounters* c, WaveLds* L, int v,
+                                                     float& sf) {
     const int lane = __lane_id();
     long long o0;
     const int K = region_size(a, v, &o0);
@@ -775,7 +804,7 @@ __device__ __forceinline__ float project_wave_vertex(const ProjectArgs& a, DevCo
     }
     float move = 0.0f;
     if (lane == 0) {
-        move = write_result(a, v, y, (double)P.r, halted);
+        move = write_result(a, c, v, y, (double)P.r, halted, norm(yprop), sf);
         if (halted) spread_add(c, 1, 1ull);
         slots_consumed(a, v);
     }
@@ -788,6 +817,7 @@ __device__ __forceinline__ float project_wave_vertex(const ProjectArgs& a, DevCo
 // half-spaces), one lane per vertex, the sort and the passes in registers.
 __global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCounters* c, int wave_blocks,
                                                          int lane_blocks) {
+    if (a.skip && *a.skip) return;
     __shared__ WaveLds lds[kBlock / 64];
     if ((int)blockIdx.x >= wave_blocks + lane_blocks) {
         // the next iteration's stretch start: the slow path reads no p
@@ -800,14 +830,15 @@ __global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCount
         const int n_list = c->n_viol_b;
         const int workers = wave_blocks * (kBlock / 64);
         WaveLds* L = &lds[wave];
-        float move = 0.0f;
+        float move = 0.0f, sf = 0.0f;
         for (int i = blockIdx.x * (kBlock / 64) + wave; i < n_list; i += workers)
-            move = fmaxf(move, project_wave_vertex(a, c, L, a.slow_list[a.n_verts - 1 - i]));
+            move = fmaxf(move, project_wave_vertex(a, c, L, a.slow_list[a.n_verts - 1 - i], sf));
         record_motion(a, move);
+        record_shortfall(a, sf);
         return;
     }
     const int n_list = c->n_viol;
-    float move = 0.0f;
+    float move = 0.0f, sf = 0.0f;
     for (int i0 = (blockIdx.x - wave_blocks) * kBlock; i0 < n_list; i0 += lane_blocks * kBlock) {
         const int i = i0 + threadIdx.x;
         bool halted = false;
@@ -817,14 +848,16 @@ __global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCount
             const int K = region_size(a, v, &o0);
             const MeshParams P = a.prm.get(a.prm.mesh_of(v));
             d3 y;
-            halted = project_small(a.hs + o0, K, load_prop(a, v), P, y);
-            move = fmaxf(move, write_result(a, v, y, (double)P.r, halted));
+            const d3 yp = load_prop(a, v);
+            halted = project_small(a.hs + o0, K, yp, P, y);
+            move = fmaxf(move, write_result(a, c, v, y, (double)P.r, halted, norm(yp), sf));
             slots_consumed(a, v);
         }
         const unsigned long long mh = __ballot(halted);
         if (__lane_id() == 0 && mh) spread_add(c, 1, (unsigned long long)__popcll(mh));
     }
     record_motion(a, move);
+    record_shortfall(a, sf);
 }
 
 __global__ void k_zero_viol(DevCounters* c) {

@@ -5,13 +5,16 @@
 // with non-zero inverse mass.  This yields exactly the union of Alg. 3's three
 // per-vertex loops (VF for the vertex, EE for both edges' endpoints, FV for the
 // face's vertices), because all of them evaluate the same closest points of the
-// same pair.  Two passes build the CSR:
+// same pair; the point interactions of Sec. 4.2 (particle-particle, and a free
+// particle against an edge: the particle on one side, the edge's endpoints
+// with their barycentric share on the other) are built the same way.  Two
+// passes build the CSR:
 //
 //   contacts  per pair: closest points in pair-local coordinates (one vertex
 //             subtracted first), phi = |x_A - x_B| - xi, kept while phi < 2r;
-//             kept pairs are compacted into 32 B Contact records (normal, phi,
-//             the two sides' d = s phi) and every receiving vertex's count is
-//             incremented.  The arithmetic runs in FP64 registers by default
+//             kept pairs are compacted into 64 B Contact records (normal, phi,
+//             the two sides' d = s phi and shares s, the receiving vertices)
+//             and every receiving vertex's count is incremented.  The arithmetic runs in FP64 registers by default
 //             (FP32 in, FP32 out): near-parallel edges make the FP32 closest
 //             points lose digits as 1/sin^2 of their angle, and CDNA's FP64
 //             rate keeps this memory-bound kernel's cost unchanged.
@@ -149,7 +152,7 @@ __device__ __forceinline__ void block_append(Contact* list, int32_t* counter, in
     __syncthreads();
 }
 
-// Evaluate pair i of the concatenated lists [VF | EE | VV].  On success fills
+// Evaluate pair i of the concatenated lists [VF | EE | VV | VE].  On success fills
 // the contact (normal from side B towards side A) and the vertices of both sides.
 struct PairVerts {
     int nA, nB;
@@ -194,6 +197,22 @@ __device__ bool eval_pair(const Scene& sc, int kind, int pa, int pb, Contact* re
         }
         pv->nA = 2; pv->a[0] = e0; pv->a[1] = e1;
         pv->nB = 2; pv->b[0] = f0; pv->b[1] = f1;
+    } else if (kind == KIND_VE) {
+        // particle p against edge (e0, e1): the closest point e0 + t (e1 - e0),
+        // t clamped to [0, 1], in coordinates relative to p
+        const int p = pa, e = pb;
+        const int e0 = sc.edges[2 * e], e1 = sc.edges[2 * e + 1];
+        mesh = sc.prm.mesh_of(p);
+        R P0[3], A[3], B[3];
+        ld3(sc.x, p, P0); ld3(sc.x, e0, A); ld3(sc.x, e1, B);
+        R ab[3];
+        for (int k = 0; k < 3; ++k) { A[k] -= P0[k]; B[k] -= P0[k]; ab[k] = B[k] - A[k]; }
+        const R L = dot3(ab, ab);
+        if (!(L > R(0))) { *degenerate = true; return false; }
+        t = clamp01(-dot3(A, ab) / L);
+        for (int k = 0; k < 3; ++k) nvec[k] = -(A[k] + t * ab[k]);
+        pv->nA = 1; pv->a[0] = p;
+        pv->nB = 2; pv->b[0] = e0; pv->b[1] = e1;
     } else {
         const int i = pa, j = pb;
         mesh = sc.prm.mesh_of(i);
@@ -220,6 +239,9 @@ __device__ bool eval_pair(const Scene& sc, int kind, int pa, int pb, Contact* re
     } else if (kind == KIND_EE) {
         wA = (R(1) - s) * (R)pv->wa[0] + s * (R)pv->wa[1];
         wB = (R(1) - t) * (R)pv->wb[0] + t * (R)pv->wb[1];
+    } else if (kind == KIND_VE) {
+        wA = (R)pv->wa[0];
+        wB = (R(1) - t) * (R)pv->wb[0] + t * (R)pv->wb[1];
     } else {
         wA = (R)pv->wa[0];
         wB = (R)pv->wb[0];
@@ -232,27 +254,30 @@ __device__ bool eval_pair(const Scene& sc, int kind, int pa, int pb, Contact* re
     // d = s phi, formed in the working precision and stored
     rec->dA = (float)(wA / wsum * phi);
     rec->dB = (float)(wB / wsum * phi);
+    rec->sA = (float)(wA / wsum);
+    rec->sB = (float)(wB / wsum);
+    rec->pad[0] = rec->pad[1] = 0;
     rec->a = pa | (kind << 30);
     rec->b = pb;
     return true;
 }
 
 template <class R>
-__global__ __launch_bounds__(kBlock, 5) void k_contacts(Scene sc, const int32_t* vf, const int32_t* ee,
-                                                     const int32_t* vv, const int32_t* counts,
-                                                     int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
+__global__ __launch_bounds__(kBlock, 5) void k_contacts(Scene sc, PairLists pl, const int32_t* counts,
                                                      Contact* contacts, int64_t cap_contacts,
                                                      int32_t* vcount, DevCounters* c, ColourJob job,
                                                      int job_blocks) {
+    if (sc.skip && *sc.skip) return;              // the substep's iterations have ended
     // the first job_blocks blocks run a stretch colour (the pairs read no p)
     if ((int)blockIdx.x < job_blocks) {
         run_colour_job(job, blockIdx.x * kBlock + threadIdx.x);
         return;
     }
-    const long long nvf = min((long long)counts[0], (long long)cap_vf);
-    const long long nee = min((long long)counts[1], (long long)cap_ee);
-    const long long nvv = min((long long)counts[2], (long long)cap_vv);
-    const long long total = nvf + nee + nvv;
+    const long long nvf = min((long long)counts[0], (long long)pl.cap_vf);
+    const long long nee = min((long long)counts[1], (long long)pl.cap_ee);
+    const long long nvv = min((long long)counts[2], (long long)pl.cap_vv);
+    const long long nve = min((long long)counts[3], (long long)pl.cap_ve);
+    const long long total = nvf + nee + nvv + nve;
     __shared__ int wave_cnt[kWavesPerBlock];
     __shared__ int block_base;
     int n_degenerate = 0;
@@ -268,13 +293,24 @@ __global__ __launch_bounds__(kBlock, 5) void k_contacts(Scene sc, const int32_t*
         PairVerts pv;
         if (i < total) {
             int kind, pa, pb;
-            if (i < nvf) { kind = KIND_VF; pa = vf[2 * i]; pb = vf[2 * i + 1]; }
-            else if (i < nvf + nee) { const long long j = i - nvf; kind = KIND_EE; pa = ee[2 * j]; pb = ee[2 * j + 1]; }
-            else { const long long j = i - nvf - nee; kind = KIND_VV; pa = vv[2 * j]; pb = vv[2 * j + 1]; }
+            if (i < nvf) {
+                kind = KIND_VF; pa = pl.vf[2 * i]; pb = pl.vf[2 * i + 1];
+            } else if (i < nvf + nee) {
+                const long long j = i - nvf;
+                kind = KIND_EE; pa = pl.ee[2 * j]; pb = pl.ee[2 * j + 1];
+            } else if (i < nvf + nee + nvv) {
+                const long long j = i - nvf - nee;
+                kind = KIND_VV; pa = pl.vv[2 * j]; pb = pl.vv[2 * j + 1];
+            } else {
+                const long long j = i - nvf - nee - nvv;
+                kind = KIND_VE; pa = pl.ve[2 * j]; pb = pl.ve[2 * j + 1];
+            }
             bool deg;
             keep = eval_pair<R>(sc, kind, pa, pb, &rec, &pv, &deg);
             if (keep) {
-                // the receiving vertices, so that the fill reads no topology or masses
+                // the receiving vertices, so that the fill reads no topology or
+                // masses: side A's (two for an edge-edge pair, else one), then
+                // side B's (three for a face, two for an edge, one for a particle)
                 const int a1 = kind == KIND_EE ? pv.a[1] : pv.b[0];
                 const float wa1 = kind == KIND_EE ? pv.wa[1] : pv.wb[0];
                 const int b0 = kind == KIND_EE ? pv.b[0] : pv.b[1];
@@ -284,7 +320,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_contacts(Scene sc, const int32_t*
                 rec.rv[0] = pv.wa[0] > 0.f ? pv.a[0] : -1;
                 rec.rv[1] = wa1 > 0.f ? a1 : -1;
                 rec.rv[2] = kind != KIND_VV && wb0 > 0.f ? b0 : -1;
-                rec.rv[3] = kind != KIND_VV && wb1 > 0.f ? b1 : -1;
+                rec.rv[3] = (kind == KIND_VF || kind == KIND_EE) && wb1 > 0.f ? b1 : -1;
             }
             n_degenerate += deg ? 1 : 0;
             if (keep && vcount) {
@@ -308,6 +344,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_contacts(Scene sc, const int32_t*
 __global__ __launch_bounds__(kBlock) void k_fill_slots(Scene sc, const Contact* contacts, int64_t cap_contacts,
                                                        int32_t* counts, ccfr_halfspace* hs, int32_t stride,
                                                        DevCounters* c, ColourJob job, int job_blocks) {
+    if (sc.skip && *sc.skip) return;
     if ((int)blockIdx.x < job_blocks) {
         run_colour_job(job, blockIdx.x * kBlock + threadIdx.x);
         return;
@@ -325,7 +362,6 @@ __global__ __launch_bounds__(kBlock) void k_fill_slots(Scene sc, const Contact* 
         for (int k = 0; k < 4; ++k) slot[k] = rec.rv[k] >= 0 ? atomicAdd(&counts[rec.rv[k]], 1) : 0;
         ccfr_halfspace h;
         h.phi = rec.phi;
-        h.flags = 0u;
         h.key = ((uint64_t)kind << 62) | ((uint64_t)(uint32_t)pa << 31) | (uint64_t)(uint32_t)pb;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -333,6 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_slots(Scene sc, const Contact* 
             const float sg = k < nA ? 1.0f : -1.0f;
             h.n[0] = sg * rec.n[0]; h.n[1] = sg * rec.n[1]; h.n[2] = sg * rec.n[2];
             h.d = k < nA ? rec.dA : rec.dB;
+            h.share = k < nA ? rec.sA : rec.sB;
             top = max(top, slot[k] + 1);
             if (slot[k] < stride) {
                 hs[(long long)rec.rv[k] * stride + slot[k]] = h;
@@ -365,6 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_slots(Scene sc, const Contact* 
 __global__ __launch_bounds__(kBlock) void k_fill(Scene sc, const Contact* contacts, int64_t cap_contacts,
                                                  const int32_t* offsets, int32_t* vcount, ccfr_halfspace* hs,
                                                  int64_t cap_hs, DevCounters* c) {
+    if (sc.skip && *sc.skip) return;
     const long long n = min((long long)c->n_contacts, (long long)cap_contacts);
     const long long stride = (long long)gridDim.x * kBlock;
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
@@ -374,7 +412,6 @@ __global__ __launch_bounds__(kBlock) void k_fill(Scene sc, const Contact* contac
         const int nA = kind == KIND_EE ? 2 : 1;     // receiving vertices of side A come first
         ccfr_halfspace h;
         h.phi = rec.phi;
-        h.flags = 0u;
         h.key = ((uint64_t)kind << 62) | ((uint64_t)(uint32_t)pa << 31) | (uint64_t)(uint32_t)pb;
         for (int k = 0; k < 4; ++k) {
             const int v = rec.rv[k];
@@ -383,6 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(Scene sc, const Contact* contac
             const long long pos = (long long)offsets[v] + atomicSub(&vcount[v], 1) - 1;
             h.n[0] = sg * rec.n[0]; h.n[1] = sg * rec.n[1]; h.n[2] = sg * rec.n[2];
             h.d = k < nA ? rec.dA : rec.dB;
+            h.share = k < nA ? rec.sA : rec.sB;
             if (pos < cap_hs) hs[pos] = h;
         }
     }
@@ -402,17 +440,16 @@ int grid_for(long long n) {
 
 }  // namespace
 
-void launch_contacts(const Scene& sc, const int32_t* vf, const int32_t* ee, const int32_t* vv,
-                     const int32_t* counts, int64_t cap_vf, int64_t cap_ee, int64_t cap_vv,
-                     Contact* contacts, int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s,
-                     bool for_slots, const ColourJob* job) {
+void launch_contacts(const Scene& sc, const PairLists& pl, const int32_t* counts, Contact* contacts,
+                     int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s, bool for_slots,
+                     const ColourJob* job) {
     ColourJob hosted{};
     if (job) hosted = *job;
     const int jb = colour_job_blocks(hosted, kBlock);
-    const int blocks = grid_for(cap_vf + cap_ee + cap_vv) + jb;
+    const int blocks = grid_for(pl.cap_vf + pl.cap_ee + pl.cap_vv + pl.cap_ve) + jb;
     int32_t* per_vertex = for_slots ? nullptr : vcount;     // slots: counted by the fill
-    hipLaunchKernelGGL(k_contacts<double>, dim3(blocks), dim3(kBlock), 0, s, sc, vf, ee, vv, counts, cap_vf,
-                       cap_ee, cap_vv, contacts, cap_contacts, per_vertex, c, hosted, jb);
+    hipLaunchKernelGGL(k_contacts<double>, dim3(blocks), dim3(kBlock), 0, s, sc, pl, counts, contacts, cap_contacts,
+                       per_vertex, c, hosted, jb);
 }
 
 void launch_fill_slots(const Scene& sc, const Contact* contacts, int64_t cap_contacts, int32_t* vcount,

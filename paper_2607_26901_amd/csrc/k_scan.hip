@@ -56,8 +56,8 @@ __device__ __forceinline__ void load_items(const int32_t* in, long long base, in
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const int32_t* in, int n, int32_t* partial,
-                                                          const uint32_t* run_flag) {
-    if (run_flag && !*run_flag) return;
+                                                          const uint32_t* run_flag, const uint32_t* skip) {
+    if ((run_flag && !*run_flag) || (skip && *skip)) return;
     __shared__ int lds[kThreads / 64 + 1];
     const long long base = (long long)blockIdx.x * kTile + (long long)threadIdx.x * kItems;
     int v[kItems];
@@ -84,8 +84,9 @@ __device__ __forceinline__ int block_base(const int32_t* partial, int b, int* ld
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_down(const int32_t* in, int32_t* out, int32_t* zero_in, int n,
-                                                        const int32_t* partial, int nb, const uint32_t* run_flag) {
-    if (run_flag && !*run_flag) return;
+                                                        const int32_t* partial, int nb, const uint32_t* run_flag,
+                                                        const uint32_t* skip) {
+    if ((run_flag && !*run_flag) || (skip && *skip)) return;
     __shared__ int lds[kThreads / 64 + 1];
     const int block_base_v = block_base(partial, blockIdx.x, lds);
     const long long base = (long long)blockIdx.x * kTile + (long long)threadIdx.x * kItems;
@@ -125,10 +126,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const int32_t* in, int32
 
 // tmp must hold ceil(n / 4096) ints
 void launch_scan(const int32_t* in, int32_t* out, int32_t* zero_in, int n, int32_t* tmp, hipStream_t s,
-                 const uint32_t* run_flag) {
+                 const uint32_t* run_flag, const uint32_t* skip) {
     const int nb = n > 0 ? (n + kTile - 1) / kTile : 1;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, in, n, tmp, run_flag);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kThreads), 0, s, in, out, zero_in, n, tmp, nb, run_flag);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, in, n, tmp, run_flag, skip);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kThreads), 0, s, in, out, zero_in, n, tmp, nb, run_flag, skip);
 }
 
 }  // namespace ccfr

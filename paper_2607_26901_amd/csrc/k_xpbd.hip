@@ -18,9 +18,11 @@ constexpr int kBlock = 256;
 
 __global__ __launch_bounds__(kBlock) void k_predict(int n, const float* x, const float* v, const float* w,
                                                     float dt, float gx, float gy, float gz, float* xp,
-                                                    float* xs) {
+                                                    float* xs, uint8_t* halt_run, DevCounters* c, int iters_add) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0 && c && iters_add) c->iters_run += iters_add;     // a fixed iteration count
     if (i >= n) return;
+    if (halt_run) halt_run[i] = 0;
     const float g[3] = {gx, gy, gz};
     const bool dyn = w[i] > 0.0f;
     for (int k = 0; k < 3; ++k) {
@@ -51,7 +53,8 @@ __global__ __launch_bounds__(kBlock) void k_close_iteration(const float* x_pred,
                                                             PairCaps caps, int64_t cap_contacts, int64_t cap_hs,
                                                             int close_pairs, int32_t slot_stride,
                                                             StretchColor0 c0, int finalize, ColourJob job,
-                                                            int job_blocks) {
+                                                            int job_blocks, const uint32_t* skip) {
+    if (skip && *skip) return;
     if ((int)blockIdx.x < job_blocks) {
         run_colour_job(job, blockIdx.x * kBlock + threadIdx.x);
         return;
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_close_iteration(const float* x_pred,
     const long long i = (long long)(blockIdx.x - job_blocks) * kBlock + threadIdx.x;
     const long long n_threads = (long long)(gridDim.x - job_blocks) * kBlock;
     if (i == 0 && finalize) {
-        if (close_pairs) finalize_pairs_body(c, caps.vf, caps.ee, caps.vv);
+        if (close_pairs) finalize_pairs_body(c, caps);
         if (slot_stride > 0) finalize_slot_regions_body(c, n_verts, slot_stride, cap_contacts);
         else finalize_regions_body(c, n_verts, offsets, cap_contacts, cap_hs);
         if (close_pairs) reset_build_counters(c);
@@ -73,14 +76,15 @@ __global__ __launch_bounds__(kBlock) void k_close_iteration(const float* x_pred,
 // One block.  Thread 0 decides (only it reads and writes the motion fields);
 // the block then clears the level masks of a build to come.
 __global__ __launch_bounds__(kBlock) void k_decide_build(DevCounters* c, uint32_t* level_mask, int n_meshes,
-                                                         double skin, PairCaps caps) {
+                                                         double skin, PairCaps caps, const uint32_t* skip) {
+    if (skip && *skip) return;
     __shared__ int go;
     if (threadIdx.x == 0) {
         const double acc = c->motion_acc + (double)__uint_as_float(c->motion_max);
         // the sum is rounded: compare with a relative margin far above its error
         const bool rebuild = acc * (1.0 + 1e-12) > skin;
         if (rebuild) {
-            finalize_pairs_body(c, caps.vf, caps.ee, caps.vv);
+            finalize_pairs_body(c, caps);
             c->n_vf = c->n_ee = c->n_vv = 0;
             c->n_large_t = c->n_large_e = 0;
         }
@@ -94,10 +98,23 @@ __global__ __launch_bounds__(kBlock) void k_decide_build(DevCounters* c, uint32_
         for (int m = threadIdx.x; m < n_meshes; m += kBlock) level_mask[m] = 0u;
 }
 
+// evaluateConvergence (Alg. 4), one thread: the iterations of the substep end
+// once no dynamic vertex's last step fell short of its proposal by more than
+// tol (reading of the check: the expected advancement of an iteration is the
+// proposal p - x, the step taken is the projected and clamped y*).
+__global__ void k_decide_converged(DevCounters* c, float tol, int first) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (first) c->converged = 0u;
+    else if (!c->converged && __uint_as_float(c->shortfall_max) <= tol) c->converged = 1u;
+    c->shortfall_max = 0u;
+    if (!c->converged) c->iters_run += 1;
+}
+
 // Colour class of the stretch pass (edges as in colour_edge), one thread per edge.
 __global__ __launch_bounds__(kBlock) void k_stretch(const int32_t* edges, const float* rest, const int2* segs,
                                                     int nseg, int total, const float* w, float* p, float* lambda,
-                                                    float alpha_t) {
+                                                    float alpha_t, const uint32_t* skip) {
+    if (skip && *skip) return;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= total) return;
     stretch_edge(colour_edge(segs, nseg, t), edges, rest, w, p, p, lambda, alpha_t, false);
@@ -132,10 +149,11 @@ inline int blocks_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
 }  // namespace
 
 void launch_predict(int n, const float* x, const float* v, const float* inv_mass, float dt, float gx, float gy,
-                    float gz, float* x_pred, float* x_start, hipStream_t s) {
+                    float gz, float* x_pred, float* x_start, hipStream_t s, uint8_t* halt_run, DevCounters* c,
+                    int iters_add) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_predict, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, x, v, inv_mass, dt, gx, gy, gz,
-                       x_pred, x_start);
+                       x_pred, x_start, halt_run, c, iters_add);
 }
 
 void launch_fill_zero(float* p, int64_t n, hipStream_t s) {
@@ -151,7 +169,8 @@ void launch_copy(const float* src, float* dst, int64_t n, hipStream_t s) {
 void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounters* c, uint32_t* level_mask,
                             int n_meshes, int32_t n_verts, const int32_t* offsets, PairCaps caps,
                             int64_t cap_contacts, int64_t cap_hs, bool close_pairs, hipStream_t s,
-                            int32_t slot_stride, const StretchColor0* c0, bool finalize, const ColourJob* job) {
+                            int32_t slot_stride, const StretchColor0* c0, bool finalize, const ColourJob* job,
+                            const uint32_t* skip) {
     StretchColor0 first{};
     if (c0 && c0->total > 0 && c0->nseg > 0) first = *c0;
     ColourJob hosted{};
@@ -161,20 +180,24 @@ void launch_close_iteration(const float* x_pred, float* p, int64_t n3, DevCounte
         std::max<long long>(std::max<long long>(n3, finalize ? n_meshes : 0), first.total), 1);
     hipLaunchKernelGGL(k_close_iteration, dim3(blocks_for(n) + jb), dim3(kBlock), 0, s, x_pred, p, (long long)n3, c,
                        level_mask, n_meshes, n_verts, offsets, caps, cap_contacts, cap_hs, close_pairs ? 1 : 0,
-                       slot_stride, first, finalize ? 1 : 0, hosted, jb);
+                       slot_stride, first, finalize ? 1 : 0, hosted, jb, skip);
 }
 
 void launch_decide_build(DevCounters* c, uint32_t* level_mask, int n_meshes, double skin, PairCaps caps,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_decide_build, dim3(1), dim3(kBlock), 0, s, c, level_mask, n_meshes, skin, caps);
+                         hipStream_t s, const uint32_t* skip) {
+    hipLaunchKernelGGL(k_decide_build, dim3(1), dim3(kBlock), 0, s, c, level_mask, n_meshes, skin, caps, skip);
+}
+
+void launch_decide_converged(DevCounters* c, float tol, int first, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide_converged, dim3(1), dim3(64), 0, s, c, tol, first);
 }
 
 void launch_stretch_segments(const int32_t* edges_sorted, const float* rest_sorted, const int2* segs, int32_t nseg,
                              int32_t total, const float* inv_mass, float* p, float* lambda_sorted, float alpha_t,
-                             hipStream_t s) {
+                             hipStream_t s, const uint32_t* skip) {
     if (total <= 0 || nseg <= 0) return;
     hipLaunchKernelGGL(k_stretch, dim3(blocks_for(total)), dim3(kBlock), 0, s, edges_sorted, rest_sorted, segs, nseg,
-                       total, inv_mass, p, lambda_sorted, alpha_t);
+                       total, inv_mass, p, lambda_sorted, alpha_t, skip);
 }
 
 void launch_last_colour_map(const int32_t* edges_sorted, const int2* segs, int32_t nseg, int32_t total,

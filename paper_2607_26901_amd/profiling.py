@@ -2,8 +2,8 @@
 
     python -m paper_2607_26901_amd.profiling --stats STATS.csv \\
         --fetch FETCH.csv --write WRITE.csv --copy-fetch CF.csv --copy-write CW.csv \\
-        --copy-mib 512 --kernel k_pairs --source paper_2607_26901_amd/csrc/k_broadphase.hip \\
-        --bench BENCH.json --command "..." --out profiles/pair_emission_c1.md
+        --copy-mib 512 --occupancy OCC.csv --source paper_2607_26901_amd/csrc/k_broadphase.hip ... \\
+        --bench BENCH.json --command "..." --out profiles/c1_kernels.md
 
 * STATS.csv: `rocprofv3 --kernel-trace --stats --output-format csv` kernel
   statistics (per-kernel calls and durations);
@@ -11,10 +11,13 @@
   counter collections (KiB per dispatch) of the same workload;
 * CF.csv / CW.csv: the same counters for a plain device copy of --copy-mib MiB
   (`bench.py --copy-calibration MIB`), which gives the scale from counter
-  KiB to bytes actually moved.
+  KiB to bytes actually moved;
+* OCC.csv: `rocprofv3 --pmc OccupancyPercent` (waves resident as a share of
+  the maximum, per dispatch).
 
-The summary records the SHA-256 of the kernel's source file; `bench.py` uses the
-traffic figure only while the source is unchanged.
+The summary records every kernel's calls, durations, copy-scaled HBM bytes per
+dispatch and occupancy, the SHA-256 of the kernel sources and the speed knobs;
+`bench.py` uses the traffic figures only while those are unchanged.
 """
 from __future__ import annotations
 
@@ -70,8 +73,11 @@ def sha256(path: str) -> str:
 
 def knobs_key(t: dict) -> str:
     """The speed knobs a profile was taken with, as one comparable string."""
-    return f"cell_scale={float(t['cell_scale']):.3f} pair_split={int(t['pair_split'])} " \
-           f"pair_reuse={int(t.get('pair_reuse', 1))} pair_skin={int(t.get('pair_skin', 0))}"
+    key = f"cell_scale={float(t['cell_scale']):.3f} pair_split={int(t['pair_split'])} " \
+          f"pair_reuse={int(t.get('pair_reuse', 1))} pair_skin={int(t.get('pair_skin', 0))}"
+    if int(t.get("broad_phase", 0)):
+        key += f" broad_phase={int(t['broad_phase'])}"
+    return key
 
 
 def read_summary(path: str) -> dict:
@@ -88,6 +94,21 @@ def read_summary(path: str) -> dict:
     return out
 
 
+def occupancy_per_dispatch(path: str) -> dict:
+    """kernel -> mean of a per-dispatch occupancy counter (e.g. OccupancyPercent)."""
+    return {k: v for k, (n, v) in counter_per_dispatch(path).items()}
+
+
+def read_kernel_summary(path: str) -> dict:
+    """The JSON block of a kernel summary written by main()."""
+    try:
+        text = open(path).read()
+    except OSError:
+        return {}
+    m = re.search(r"```json\n(.*?)\n```", text, flags=re.S)
+    return json.loads(m.group(1)) if m else {}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--stats", required=True)
@@ -96,54 +117,73 @@ def main(argv=None) -> int:
     ap.add_argument("--copy-fetch")
     ap.add_argument("--copy-write")
     ap.add_argument("--copy-mib", type=int, default=512)
-    ap.add_argument("--kernel", default="k_pairs")
-    ap.add_argument("--stage", default="pair_emission",
-                    help="bench.py's name of the kernel's stage; the bench figures are recorded only when the "
-                         "bench's roofline is for this stage")
-    ap.add_argument("--source", required=True)
-    ap.add_argument("--bench", help="bench.py JSON line of the same workload")
+    ap.add_argument("--occupancy", help="rocprofv3 --pmc OccupancyPercent collection of the same workload")
+    ap.add_argument("--source", action="append", default=[], help="a kernel source file the figures depend on")
+    ap.add_argument("--bench", required=True, help="bench.py JSON line of the profiled command")
     ap.add_argument("--command", action="append", default=[], help="a command that produced the inputs")
     ap.add_argument("--title", default="")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
 
     stats = kernel_stats(a.stats)
-    lines = [f"# {a.title or a.kernel}", "", "Commands (run from the repository root on the GPU host):", ""]
+    with open(a.bench) as f:
+        b = json.loads(f.readline())
+    iters_per_step = int(b.get("config", {}).get("iters_per_step", 1))
+    calls = {r["name"]: r for r in stats}
+    # k_predict runs once per substep: substeps x iterations = iterations profiled
+    iterations = calls["k_predict"]["calls"] * iters_per_step if "k_predict" in calls else 0
+    fd = counter_per_dispatch(a.fetch) if a.fetch else {}
+    wd = counter_per_dispatch(a.write) if a.write else {}
+    fs = copy_scale(a.copy_fetch, a.copy_mib) if a.copy_fetch else float("nan")
+    ws = copy_scale(a.copy_write, a.copy_mib) if a.copy_write else float("nan")
+    occ = occupancy_per_dispatch(a.occupancy) if a.occupancy else {}
+    kernels = {}
+    for r in stats:
+        k = r["name"]
+        rec = {"calls": r["calls"], "avg_us": r["avg_us"], "total_ms": r["total_ms"], "pct": r["pct"]}
+        if k in fd and k in wd and fs == fs and ws == ws:
+            rec["fetch_kib"] = fd[k][1]
+            rec["write_kib"] = wd[k][1]
+            rec["traffic_bytes"] = fd[k][1] * fs + wd[k][1] * ws
+        if k in occ:
+            rec["occupancy_pct"] = occ[k]
+        kernels[k] = rec
+    facts = {"workload": b.get("config", {}).get("workload", ""), "knobs": knobs_key(b.get("tuning", {})),
+             "iterations": iterations, "sources": {src: sha256(src) for src in a.source},
+             "fetch_scale": fs / 1024 if fs == fs else None, "write_scale": ws / 1024 if ws == ws else None,
+             "kernels": kernels}
+    lines = [f"# {a.title or 'Kernels of one workload'}", "",
+             "Commands (run from the repository root on the GPU host, each under `cd /tmp && export "
+             "TMPDIR=/tmp` for rocprofv3; output directories under gpurun_out/):", ""]
     lines += [f"    {c}" for c in a.command]
-    lines += ["", "## Kernel statistics (rocprofv3 --kernel-trace --stats)", "",
-              "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
-    for r in stats[:14]:
-        lines.append(f"| {r['name']} | {r['calls']} | {r['avg_us']:.1f} | {r['total_ms']:.2f} | {r['pct']:.1f} |")
-    mine = [r for r in stats if r["name"] == a.kernel]
-    facts = {"kernel": a.kernel, "source": a.source, "source_sha256": sha256(a.source)}
-    if mine:
-        facts["rocprof_avg_us"] = f"{mine[0]['avg_us']:.2f}"
-    if a.bench:
-        with open(a.bench) as f:
-            b = json.loads(f.readline())
-        rl = b.get("roofline", {})
-        if "tuning" in b:
-            facts["knobs"] = knobs_key(b["tuning"])
-        if rl.get("kernel") == a.stage:
-            facts["bench_avg_launch_us"] = f"{rl.get('avg_launch_us', float('nan')):.2f}"
-            facts["algorithmic_bytes_per_launch"] = f"{rl.get('algorithmic_bytes', float('nan')):.0f}"
-    if a.fetch and a.write and a.copy_fetch and a.copy_write:
-        fs, ws = copy_scale(a.copy_fetch, a.copy_mib), copy_scale(a.copy_write, a.copy_mib)
-        fd, wd = counter_per_dispatch(a.fetch), counter_per_dispatch(a.write)
-        nf, f_kib = fd.get(a.kernel, (0, float("nan")))
-        nw, w_kib = wd.get(a.kernel, (0, float("nan")))
-        facts.update({"fetch_kib_per_dispatch": f"{f_kib:.1f}", "write_kib_per_dispatch": f"{w_kib:.1f}",
-                      "fetch_scale": f"{fs / 1024:.4f}", "write_scale": f"{ws / 1024:.4f}",
-                      "traffic_bytes_per_launch": f"{f_kib * fs + w_kib * ws:.0f}",
-                      "dispatches_counted": f"{nf}/{nw}"})
-        lines += ["", "## HBM traffic per dispatch (rocprofv3 --pmc, separate runs)", "",
-                  "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---|---|---|"]
-        for k in sorted(fd, key=lambda k: -fd[k][1])[:10]:
-            lines.append(f"| {k} | {fd[k][1]:.1f} | {wd.get(k, (0, float('nan')))[1]:.1f} |")
-        lines += ["", f"Scale from a plain {a.copy_mib} MiB device copy: FETCH_SIZE x{fs / 1024:.4f}, "
-                  f"WRITE_SIZE x{ws / 1024:.4f} (bytes per counted byte)."]
-    lines += ["", "## Figures used by bench.py", ""]
-    lines += [f"- `{k}`: `{v}`" for k, v in facts.items()]
+    lines += ["", f"Profiled: {iterations} solver iterations ({iters_per_step} per substep); knobs "
+              f"`{facts['knobs']}`.", "",
+              "## Kernel statistics and counters (rocprofv3)", "",
+              "| kernel | calls | per iteration | avg us | total ms | % | FETCH KiB | WRITE KiB | HBM MB / dispatch "
+              "| occupancy % |", "|---|---|---|---|---|---|---|---|---|---|"]
+    for r in stats[:20]:
+        k = r["name"]
+        rec = kernels[k]
+        per_it = r["calls"] / iterations if iterations else float("nan")
+        tb = rec.get("traffic_bytes")
+        lines.append(f"| {k} | {r['calls']} | {per_it:.3f} | {r['avg_us']:.1f} | {r['total_ms']:.2f} | "
+                     f"{r['pct']:.1f} | {rec.get('fetch_kib', float('nan')):.1f} | "
+                     f"{rec.get('write_kib', float('nan')):.1f} | "
+                     f"{(tb / 1e6) if tb is not None else float('nan'):.2f} | "
+                     f"{rec.get('occupancy_pct', float('nan')):.1f} |")
+    if fs == fs:
+        lines += ["", f"HBM bytes per dispatch = FETCH_SIZE KiB x {fs / 1024:.4f} KiB + WRITE_SIZE KiB x "
+                  f"{ws / 1024:.4f} KiB: the factors a plain {a.copy_mib} MiB device copy gives on the same "
+                  "counters (bytes moved per counted byte)."]
+    rl = b.get("stage_rooflines", {})
+    if rl:
+        lines += ["", "## The bench line's stage rooflines of the same configuration", "",
+                  "| stage | us per iteration (HIP events) | algorithmic bytes | achieved GB/s | fraction of 8 TB/s |",
+                  "|---|---|---|---|---|"]
+        for st, r in rl.items():
+            lines.append(f"| {st} | {r['us_per_iteration']:.1f} | {r['algorithmic_bytes']:.0f} | "
+                         f"{r['achieved']:.1f} | {r['frac']:.4f} |")
+    lines += ["", "## Figures read by bench.py", "", "```json", json.dumps(facts, indent=1, sort_keys=True), "```"]
     with open(a.out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))

@@ -38,6 +38,11 @@ class Params:
     eps_retract: float = 1e-6   # retraction margin of the projection
     eps_plesnik: float = 1e-6   # tolerance of the ERO-line update
     max_passes: int = 4         # passes of the per-vertex projection
+    response: bool = False      # soft response and friction before the projection
+    resp_compliance: float = 0.0  # compliance 1/k of the response constraint
+    vis_width: float = 0.0      # transition width of the visibility weights (0: none)
+    mu_s: float = 0.0           # static friction coefficient
+    mu_k: float = 0.0           # kinetic friction coefficient
 
 
 @dataclass(frozen=True)
@@ -47,6 +52,8 @@ class StepParams:
     iters: int = 10
     steps: int = 10
     alpha: float = 1e-6         # stretch compliance
+    early_exit: bool = False    # end a step's iterations at the convergence check
+    conv_tol: float = 0.0       # shortfall (m) below which the check counts a vertex as converged
 
 
 @dataclass
@@ -253,6 +260,7 @@ BENCH_KNOBS = {
     "c1": dict(cell_scale=0.7, pair_split=1, pair_reuse=3, pair_skin=0),
     "c2": dict(cell_scale=0.85, pair_split=1, pair_reuse=4, pair_skin=0),
     "c3": dict(cell_scale=0.85, pair_split=1, pair_reuse=1, pair_skin=0),
+    "c5": dict(cell_scale=0.7, pair_split=9, pair_reuse=1, pair_skin=1),
 }
 
 
@@ -470,6 +478,102 @@ def c2(seed=1002) -> Scene:
     return sc
 
 
+def rod_lattice(n_per_layer=16, seg=60, length=30.0, pitch=2.0, z0=1.0, dz=0.15, inv_mass=50.0) -> _Mesh:
+    """Two crossing layers of straight rods (a wire structure): n_per_layer rods
+    along x at height z0, n_per_layer along y at z0 + dz, each of `seg`
+    segments spanning `length`, `pitch` apart, both ends pinned."""
+    k = seg + 1
+    t = np.linspace(-0.5 * length, 0.5 * length, k)
+    off = (np.arange(n_per_layer) - 0.5 * (n_per_layer - 1)) * pitch
+    pts = np.empty((2 * n_per_layer, k, 3))
+    for r, o in enumerate(off):
+        pts[r, :, 0], pts[r, :, 1], pts[r, :, 2] = t, o, z0
+        pts[n_per_layer + r, :, 0], pts[n_per_layer + r, :, 1], pts[n_per_layer + r, :, 2] = o, t, z0 + dz
+    w = np.full((2 * n_per_layer, k), inv_mass)
+    w[:, 0] = w[:, -1] = 0.0
+    return strands_mesh(pts, w)
+
+
+def octopus(center, radius=3.0, level=3, arms=8, arm_seg=12, arm_len=0.4, arm_z=1.35, phase=0.0,
+            inv_mass=20.0) -> _Mesh:
+    """A deformable closed surface with strand arms (a synthetic stand-in for a
+    tentacled soft body): a dynamic icosphere and `arms` polylines, each
+    attached to the sphere vertex nearest its root direction on the lower
+    hemisphere and running radially outwards, dropping to height arm_z."""
+    body = icosphere(level, radius, center)
+    c = np.asarray(center, np.float64)
+    xs = [body.x]
+    edges = []
+    n0 = len(body.x)
+    for a in range(arms):
+        th = phase + 2.0 * np.pi * a / arms
+        d = np.array([math.cos(th), math.sin(th)])
+        root_dir = np.array([0.5 * d[0], 0.5 * d[1], -math.sqrt(0.75)])   # 30 degrees from the bottom
+        root = int(np.argmax((body.x - c) @ root_dir))
+        r0 = body.x[root]
+        rh = float(np.hypot(*(r0[:2] - c[:2])))
+        pts = np.empty((arm_seg, 3))
+        for j in range(1, arm_seg + 1):
+            h = rh + arm_len * j
+            pts[j - 1, :2] = c[:2] + h * d
+            pts[j - 1, 2] = max(arm_z, r0[2] - arm_len * j)
+        first = n0 + sum(len(q) for q in xs[1:])
+        edges.append([root, first])
+        edges += [[first + j, first + j + 1] for j in range(arm_seg - 1)]
+        xs.append(pts)
+    m = _Mesh(np.concatenate(xs, 0), body.tris, np.full(n0 + arms * arm_seg, inv_mass))
+    m.extra_edges = np.asarray(edges, np.int64)
+    return m
+
+
+def c5(seed=1005, n_rods=16, rod_seg=60, side=95.0, body_level=3, body_radius=9.0, arm_seg=12, arm_len=1.2,
+       n_paper=64, part=(39, 39, 4), part_spacing=0.8, name="c5") -> Scene:
+    """Coupled codimensional scene: a floor, a pinned two-layer rod lattice
+    (2 x n_rods rods of rod_seg segments spanning `side`), two soft tentacled
+    bodies resting on it, a paper sheet over their tops and a block of free
+    particles (`part` = nx x ny x nz, `part_spacing` apart) over the sheet's
+    centre; each layer lies 0.15 (the particles 0.2) above the one below,
+    inside the interaction range 2r + xi = 0.86 (13,612 vertices at the
+    defaults; rod, arm and sheet segments about 1.5 long).  Lengths are in the
+    units of the contact parameters r = 0.4, xi = 0.06, delta = 0.01; the
+    paper sheet and the particles start with small random velocities."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    floor = ground_quad(2.0 * side, 0.0)
+    pitch = side / (n_rods - 0.5)
+    rods = rod_lattice(n_per_layer=n_rods, seg=rod_seg, length=side, pitch=pitch)
+    top_rods = 1.15
+    gap = 0.15
+    R = body_radius
+    zc = top_rods + gap + R
+    octo = [octopus((-0.27 * side, -0.1 * side, zc), radius=R, level=body_level, arm_seg=arm_seg, arm_len=arm_len,
+                    phase=0.0),
+            octopus((0.27 * side, 0.1 * side, zc), radius=R, level=body_level, arm_seg=arm_seg, arm_len=arm_len,
+                    phase=np.pi / 8)]
+    z_paper = zc + R + gap
+    paper = cloth_grid(n_paper, side, (0.0, 0.0, z_paper))
+    paper.inv_mass = np.full(len(paper.x), 100.0)
+    paper.v = rng.normal(0.0, 0.3, paper.x.shape)
+    nx, ny, nz = part
+    g = np.stack(np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij"), -1).reshape(-1, 3)
+    p = (g - np.array([0.5 * (nx - 1), 0.5 * (ny - 1), 0.0])) * part_spacing
+    p[:, 2] += z_paper + 0.2
+    p += rng.uniform(-0.03, 0.03, p.shape)
+    parts = particles_mesh(p, 80.0)
+    parts.v = rng.normal(0.0, 0.3, parts.x.shape)
+    return assemble(name, [floor, rods] + octo + [paper, parts], Params(r=0.4, xi=0.06, delta=0.01),
+                    StepParams(dt=1.0 / 120.0, iters=10, steps=30),
+                    meta=dict(n_particles=len(p), n_paper=n_paper * n_paper))
+
+
+def c5_small(seed=1006) -> Scene:
+    """The coupled scene at a size the oracle steps in a fraction of a second:
+    2 x 4 rods of 20 segments over 30 units, two bodies of radius 4.5
+    (162-vertex spheres, arms of 5 segments), a 21 x 21 paper sheet and an
+    8 x 8 x 3 particle block."""
+    return c5(seed=seed, n_rods=4, rod_seg=20, side=30.0, body_level=2, body_radius=4.5, arm_seg=5,
+              n_paper=21, part=(8, 8, 3), name="c5_small")
+
+
 # --------------------------------------------------------------------------
 # the batched / served workload
 # --------------------------------------------------------------------------
@@ -506,4 +610,5 @@ SCENES = {
     "c1": c1,
     "c2": c2,
     "c3": c3,
+    "c5": c5,
 }

@@ -138,11 +138,15 @@ class Server:
 
     def __init__(self, ctx, budget_bytes: int, max_slots: int = 4096, max_verts: int | None = None,
                  max_tris: int | None = None, max_edges: int | None = None, batch=None, timer=None,
-                 footprint_fn=None, tune_at: int | None = None):
+                 footprint_fn=None, tune_at: int | None = None, step_verts_cap: int | None = None):
         """tune_at: once this many requests are resident, pick the grid cell
-        size by timing one rolled-back step per candidate (autotune)."""
+        size by timing one rolled-back step per candidate (autotune).
+        step_verts_cap: no request is admitted while the resident vertices
+        would exceed this many (a step's time, which every resident request
+        waits for, grows with them); a request larger than the cap runs alone."""
         self.ctx = ctx
         self.tune_at = tune_at
+        self.step_verts_cap = step_verts_cap
         self.tuning = None
         self.budget = int(budget_bytes)
         self.footprint = footprint_fn or footprint
@@ -174,10 +178,14 @@ class Server:
                 waiting.append(jobs[nxt])
                 nxt += 1
             # admission, first come first served
+            resident_verts = sum(r[0].scene.n_verts for r in resident.values())
             while waiting:
                 j = waiting[0]
                 fp = self.footprint(j.scene)
                 if used + fp > self.budget and resident:
+                    break
+                if (self.step_verts_cap is not None and resident
+                        and resident_verts + j.scene.n_verts > self.step_verts_cap):
                     break
                 sp = ccfr.make_step_params(j.scene.step, j.scene.params)
                 try:
@@ -188,6 +196,7 @@ class Server:
                     raise
                 waiting.pop(0)
                 used += fp
+                resident_verts += j.scene.n_verts
                 res = JobResult(j.id, j.scene.n_verts, j.scene.n_dynamic, j.steps, j.arrival,
                                 admitted=clock() - t0)
                 resident[slot] = (j, 0, fp, res)

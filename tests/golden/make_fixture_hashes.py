@@ -1,5 +1,5 @@
 """Write tests/golden/fixtures_sha256.json: SHA-256 of every array of the
-workload generators' outputs (C0-C3 and the first requests of C4), so that a
+workload generators' outputs (C0-C3, C5 and the first requests of C4), so that a
 change to a generator or to the random streams it draws from shows up.
 
 Calls only paper_2607_26901_amd.scenes (no oracle, no GPU code).

@@ -80,6 +80,7 @@ def to_oracle_halfspaces(off, hs_g_like):
     out["n"] = hs_g_like["n"].astype(np.float64)
     out["d"] = hs_g_like["d"].astype(np.float64)
     out["phi"] = hs_g_like["phi"].astype(np.float64)
+    out["share"] = hs_g_like["share"].astype(np.float64)
     out["key"] = hs_g_like["key"]
     return np.asarray(off, np.int64), out
 
@@ -91,6 +92,7 @@ def oracle_to_fp32(hs_o):
     out["n"] = hs_o["n"].astype(np.float32)
     out["d"] = hs_o["d"].astype(np.float32)
     out["phi"] = hs_o["phi"].astype(np.float32)
+    out["share"] = hs_o["share"].astype(np.float32)
     out["key"] = hs_o["key"]
     return out
 
@@ -117,3 +119,23 @@ def match_projection(oracle, params, inv_mass, x, hv, y, yg, hg, tol):
         return "branch"
     assert not complete, ("no branch matches", yg, hg, outs, halts)
     return "unresolved"
+
+
+def steps_with_growth(ctx, mesh, sc, v0, sp, n_steps, tries=4):
+    """n_steps substeps from the scene's state; a CAPACITY status grows the
+    context's lists and runs the substeps again from the start.  Returns the
+    final (x, v) as numpy arrays."""
+    from paper_2607_26901_amd import ccfr
+    import torch
+    for _ in range(tries):
+        x = torch.from_numpy(sc.x.copy()).cuda()
+        v = torch.from_numpy(np.asarray(v0, np.float32).copy()).cuda()
+        for _ in range(n_steps):
+            ccfr.xpbd_step(ctx, mesh, x, v, sp)
+        torch.cuda.synchronize()
+        code, info = ctx.sync_status(reset=True)
+        if code == 0:
+            return x.cpu().numpy(), v.cpu().numpy()
+        assert code == -2, info
+        ctx.grow(info)
+    raise AssertionError(f"lists still overflow after {tries} growths: {info}")

@@ -51,6 +51,18 @@ def seg_seg(a, b, c, d):
     return np.where(inside, np.minimum(best, np.linalg.norm(q, axis=1)), best)
 
 
+def pt_seg_foot(p, a, b):
+    """Point-segment distance as the least of the two endpoint distances and,
+    where the perpendicular foot falls strictly inside, the foot distance."""
+    best = np.minimum(np.linalg.norm(p - a, axis=1), np.linalg.norm(p - b, axis=1))
+    u = b - a
+    uu = np.einsum("ij,ij->i", u, u)
+    s = np.einsum("ij,ij->i", p - a, u) / np.where(uu > 0, uu, 1)
+    inside = (uu > 0) & (s > 0) & (s < 1)
+    foot = np.linalg.norm(a + s[:, None] * u - p, axis=1)
+    return np.where(inside, np.minimum(best, foot), best)
+
+
 def free_particles(n_verts, tris, edges):
     f = np.ones(n_verts, bool)
     f[np.asarray(tris).ravel()] = False
@@ -59,8 +71,9 @@ def free_particles(n_verts, tris, edges):
 
 
 def all_pair_distances(x, w, tris, edges):
-    """All non-adjacent, not-all-static VF, EE and free-particle VV pairs with
-    their FP64 distances: dict kind -> (pairs [P,2], dist [P])."""
+    """All non-adjacent, not-all-static VF, EE, free-particle VV and
+    particle-edge VE pairs with their FP64 distances: dict kind -> (pairs
+    [P,2], dist [P])."""
     x = np.asarray(x, np.float64)
     w = np.asarray(w, np.float64)
     tris = np.asarray(tris, np.int64)
@@ -100,4 +113,14 @@ def all_pair_distances(x, w, tris, edges):
         out["vv"] = (np.stack([a, b], 1), np.linalg.norm(x[a] - x[b], axis=1))
     else:
         out["vv"] = (np.zeros((0, 2), np.int64), np.zeros(0))
+    # VE: a free particle and any edge (the particle is in no edge)
+    if len(fr) and E:
+        p, e = np.meshgrid(fr, np.arange(E), indexing="ij")
+        p, e = p.ravel(), e.ravel()
+        ev = edges[e]
+        keep = ~((w[p] == 0) & (w[ev] == 0).all(1))
+        p, e, ev = p[keep], e[keep], ev[keep]
+        out["ve"] = (np.stack([p, e], 1), pt_seg_foot(x[p], x[ev[:, 0]], x[ev[:, 1]]))
+    else:
+        out["ve"] = (np.zeros((0, 2), np.int64), np.zeros(0))
     return out

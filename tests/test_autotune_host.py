@@ -8,7 +8,7 @@ from paper_2607_26901_amd import autotune
 
 class FakeCtx:
     def __init__(self):
-        self.t = {"cell_scale": 1.0, "pair_split": 1, "pair_reuse": 1, "pair_skin": 0}
+        self.t = {"cell_scale": 1.0, "pair_split": 1, "pair_reuse": 1, "pair_skin": 0, "broad_phase": 0}
         self.calls = []
 
     def set_tuning(self, **kw):
@@ -37,7 +37,7 @@ def test_tune_picks_fastest_and_skips():
     out = autotune.tune(ctx, run, candidates=(1.0, 0.5), splits=(1,), modes=list(cost), log=logs.append)
     assert (out["cell_scale"], out["pair_reuse"], out["pair_skin"]) == (0.5, 3, 0)
     assert ctx.t["cell_scale"] == 0.5 and ctx.t["pair_reuse"] == 3
-    assert math.isinf(out["ms"]["1.0/1/4/0"]) and math.isinf(out["ms"]["0.5/1/4/0"])
+    assert math.isinf(out["ms"]["1.0/1/4/0/0"]) and math.isinf(out["ms"]["0.5/1/4/0/0"])
     # the first run sets the limit: four times its bytes
     assert runs[0][1] is None and all(l == 4 * (1 << 30) for _, l in runs[1:])
     # (1, 0) at cell 1.0 is timed three times (first record, then two repeats)
@@ -57,3 +57,25 @@ def test_slow_setting_timed_once():
     out = autotune.tune(ctx, run, candidates=(1.0,), splits=(1,), modes=[(1, 0), (2, 0)], log=None)
     assert out["pair_reuse"] == 1
     assert runs.count(2) == 1 and runs.count(1) == 3
+
+
+def test_hierarchy_timed_once_per_mode_and_chosen_when_faster():
+    """The hierarchy has no cell or split knob: it is timed once per mode (at
+    the neutral cell scale and one lane), and kept when it is the fastest."""
+    ctx = FakeCtx()
+    seen = []
+
+    def run(limit):
+        t = dict(ctx.t)
+        seen.append(t)
+        if t["broad_phase"] == 1:
+            return 2.0 + t["pair_reuse"], 1 << 20
+        return 5.0 * t["cell_scale"] + t["pair_split"], 1 << 20
+
+    out = autotune.tune(ctx, run, candidates=(0.5, 1.0), splits=(1, 3), modes=[(1, 0), (2, 0)], log=None,
+                        broad_phases=(0, 1))
+    assert (out["broad_phase"], out["pair_reuse"]) == (1, 1) and ctx.t["broad_phase"] == 1
+    lbvh = {(t["cell_scale"], t["pair_split"]) for t in seen if t["broad_phase"] == 1}
+    assert lbvh == {(1.0, 1)}
+    assert set(out["ms"]) == {f"{c}/{sp}/{ru}/0/0" for c in (0.5, 1.0) for sp in (1, 3) for ru in (1, 2)} | \
+        {"1.0/1/1/0/1", "1.0/1/2/0/1"}

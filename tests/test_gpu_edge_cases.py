@@ -72,7 +72,7 @@ def test_capacity_overflow_then_exact(env):
     ctx.sync_status(reset=True)
     got, r, overflows = _build_with_growth(ctx, ccfr, torch, mesh, x, prm)
     assert overflows >= 1                    # contacts and half-spaces outgrow their room too
-    for kind in ("vf", "ee", "vv"):
+    for kind in ("vf", "ee", "vv", "ve"):
         assert np.array_equal(H.sorted_pairs(got[kind]), H.sorted_pairs(ref[kind])), kind
     off, hs = ccfr.read_regions(r)
     off_o, hs_o, _ = oracle.regions(om, sc.params, ref)
@@ -92,8 +92,8 @@ def test_reserve_up_front(env):
     ref = oracle.candidates(om, sc.params)
     off_o, hs_o, _ = oracle.regions(om, sc.params, ref)
     mesh = ccfr.mesh_from_scene(ctx, sc)
-    ctx.reserve(vf=len(ref["vf"]), ee=len(ref["ee"]), vv=len(ref["vv"]),
-                contacts=len(ref["vf"]) + len(ref["ee"]) + len(ref["vv"]), halfspaces=len(hs_o))
+    ctx.reserve(vf=len(ref["vf"]), ee=len(ref["ee"]), vv=len(ref["vv"]), ve=len(ref["ve"]),
+                contacts=sum(len(ref[k]) for k in ("vf", "ee", "vv", "ve")), halfspaces=len(hs_o))
     x = torch.from_numpy(sc.x).cuda()
     got, r, overflows = _build_with_growth(ctx, ccfr, torch, mesh, x, ccfr.make_params(sc.params))
     assert overflows == 0
@@ -121,11 +121,11 @@ def test_nonfinite_position(env):
     code, info = ctx.sync_status(reset=True)
     assert code == -4 and (info["status_bits"] & 64), info
     ref = oracle.candidates(oracle.Mesh(sc), sc.params)      # the same scene, all finite
-    for kind in ("vf", "ee", "vv"):
+    for kind in ("vf", "ee", "vv", "ve"):
         want = H.sorted_pairs(ref[kind])
         if kind == "vv":
             want = want[~np.isin(want, bad).any(1)]
-        elif kind == "vf":
+        elif kind in ("vf", "ve"):
             want = want[~np.isin(want[:, 0], bad)]
         assert np.array_equal(H.sorted_pairs(got[kind]), want), kind
     # a clean build on the same context
@@ -251,7 +251,7 @@ def test_degenerate_primitives(env):
     mesh = ccfr.mesh_from_scene(ctx, sc)
     x = torch.from_numpy(sc.x).cuda()
     c, got, _ = H.gpu_candidates(ctx, mesh, x, sc.params)
-    for kind in ("vf", "ee", "vv"):
+    for kind in ("vf", "ee", "vv", "ve"):
         assert np.array_equal(H.sorted_pairs(got[kind]), H.sorted_pairs(ref[kind])), kind
     _, off, hs, info = H.gpu_regions(ctx, mesh, x, c, sc.params)
     assert info["totals"][6] == n_deg, (info["totals"][6], n_deg)
@@ -272,11 +272,11 @@ def test_all_static_and_empty(env):
     sc = S.two_layers(n=8, seed=2)
     sc.inv_mass = np.zeros_like(sc.inv_mass)
     assert sum(len(v) for k, v in oracle.candidates(oracle.Mesh(sc), sc.params).items()
-               if k in ("vf", "ee", "vv")) == 0
+               if k in ("vf", "ee", "vv", "ve")) == 0
     mesh = ccfr.mesh_from_scene(ctx, sc)
     x = torch.from_numpy(sc.x).cuda()
     c, got, _ = H.gpu_candidates(ctx, mesh, x, sc.params)
-    assert all(len(got[k]) == 0 for k in ("vf", "ee", "vv"))
+    assert all(len(got[k]) == 0 for k in ("vf", "ee", "vv", "ve"))
     r, off, hs, _ = H.gpu_regions(ctx, mesh, x, c, sc.params)
     assert off[-1] == 0 and len(hs) == 0
     y = torch.full((sc.n_verts, 3), 1e-3, dtype=torch.float32).cuda()
@@ -295,7 +295,7 @@ def test_all_static_and_empty(env):
     empty = ccfr.Mesh(ctx, 0, np.zeros((0, 3), np.int32), None, np.zeros(0, np.float32))
     x0 = torch.zeros((0, 3), dtype=torch.float32).cuda()
     c, got, _ = H.gpu_candidates(ctx, empty, x0, sc.params)
-    assert all(len(got[k]) == 0 for k in ("vf", "ee", "vv"))
+    assert all(len(got[k]) == 0 for k in ("vf", "ee", "vv", "ve"))
     r, off, hs, _ = H.gpu_regions(ctx, empty, x0, c, sc.params)
     assert list(off) == [0] and len(hs) == 0
     ccfr.project_displacements(ctx, r, torch.zeros(0).cuda(), x0, sc.params, torch.zeros((0, 3)).cuda())

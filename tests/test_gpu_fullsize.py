@@ -60,12 +60,15 @@ def check_sampled(oracle, sc, x32, got, off_g, hs_g, y, yg, n_sample=48, seed=0,
     vf_by_v, vf_by_t = _index(got["vf"], 0), _index(got["vf"], 1)
     vv_a, vv_b = _index(got["vv"], 0), _index(got["vv"], 1)
     ee_a, ee_b = _index(got["ee"], 0), _index(got["ee"], 1)
+    ve_p, ve_e = _index(got["ve"], 0), _index(got["ve"], 1)
     for v in verts:
         want = np.sort(oracle.vf_tris_of_vertex(om, sc.params, v))
         assert np.array_equal(_partners(vf_by_v, v), want), ("vf of vertex", v)
         want = np.sort(oracle.vv_partners_of_vertex(om, sc.params, v))
         have = np.sort(np.concatenate([_partners(vv_a, v), _partners(vv_b, v)]))
         assert np.array_equal(have, want), ("vv of vertex", v)
+        want = np.sort(oracle.ve_edges_of_vertex(om, sc.params, v))
+        assert np.array_equal(_partners(ve_p, v), want), ("ve of vertex", v)
     if sc.n_tris:
         for t in _sample(rng, sc.n_tris, n_sample):
             want = np.sort(oracle.vf_verts_of_tri(om, sc.params, t))
@@ -75,6 +78,8 @@ def check_sampled(oracle, sc, x32, got, off_g, hs_g, y, yg, n_sample=48, seed=0,
             want = np.sort(oracle.ee_partners_of_edge(om, sc.params, e))
             have = np.sort(np.concatenate([_partners(ee_a, e), _partners(ee_b, e)]))
             assert np.array_equal(have, want), ("ee of edge", e)
+            want = np.sort(oracle.ve_verts_of_edge(om, sc.params, e))
+            assert np.array_equal(_partners(ve_e, e), want), ("ve of edge", e)
     # regions of the sampled vertices
     xi32, r32 = float(np.float32(sc.params.xi)), float(np.float32(sc.params.r))
     ref = {v: oracle.vertex_region(om, sc.params, v) for v in verts}

@@ -66,9 +66,9 @@ def test_candidates_bit_exact(env, scenes, k):
     x = torch.from_numpy(sc.x).cuda()
     _, got, _ = H.gpu_candidates(ctx, mesh, x, sc.params)
     ref = oracle.candidates(oracle.Mesh(sc), sc.params)
-    for kind in ("vf", "ee", "vv"):
+    for kind in ("vf", "ee", "vv", "ve"):
         assert np.array_equal(H.sorted_pairs(got[kind]), H.sorted_pairs(ref[kind])), kind
-    assert sum(len(ref[q]) for q in ("vf", "ee", "vv")) > 0
+    assert sum(len(ref[q]) for q in ("vf", "ee", "vv", "ve")) > 0
 
 
 @pytest.mark.parametrize("k", range(len(SCENE_IDS)), ids=SCENE_IDS)
@@ -106,7 +106,7 @@ def test_regions_against_independent_distances(env, scenes, k):
     xi32, r32 = float(np.float32(sc.params.xi)), float(np.float32(sc.params.r))
     allp = all_pair_distances(sc.x, sc.inv_mass, sc.tris, sc.edges)
     dist = {}
-    for kind, code in (("vf", 1), ("ee", 2), ("vv", 3)):
+    for kind, code in (("vf", 1), ("ee", 2), ("vv", 3), ("ve", 0)):
         pairs, d = allp[kind]
         for (a, b), dd in zip(pairs.tolist(), d.tolist()):
             dist[(code << 62) | (a << 31) | b] = dd
@@ -124,7 +124,8 @@ def test_regions_against_independent_distances(env, scenes, k):
         if not dd - xi32 < 2 * r32 - H.DTOL * diag:
             continue
         kind, a, b = key >> 62, (key >> 31) & 0x7FFFFFFF, key & 0x7FFFFFFF
-        vs = ([a] + tris[b].tolist()) if kind == 1 else (edges[a].tolist() + edges[b].tolist() if kind == 2 else [a, b])
+        vs = ([a] + tris[b].tolist()) if kind == 1 else (
+            edges[a].tolist() + edges[b].tolist() if kind == 2 else ([a] + edges[b].tolist() if kind == 0 else [a, b]))
         if min(w[v] for v in vs) == 0:      # a static side can make both shares' weights zero
             continue
         assert set(vs) <= got.get(key, set()), (key, vs, got.get(key))
@@ -142,9 +143,9 @@ def test_regions_from_caller_candidates(env, scenes):
     mesh = ccfr.mesh_from_scene(ctx, sc)
     x = torch.from_numpy(sc.x).cuda()
     t = {k: torch.from_numpy(np.ascontiguousarray(ref[k], np.int32).reshape(-1, 2) if len(ref[k])
-                             else np.zeros((1, 2), np.int32)).cuda() for k in ("vf", "ee", "vv")}
-    counts = torch.tensor([len(ref["vf"]), len(ref["ee"]), len(ref["vv"])], dtype=torch.int32).cuda()
-    cands = ccfr.caller_candidates(t["vf"], t["ee"], t["vv"], counts)
+                             else np.zeros((1, 2), np.int32)).cuda() for k in ("vf", "ee", "vv", "ve")}
+    counts = torch.tensor([len(ref[k]) for k in ("vf", "ee", "vv", "ve")], dtype=torch.int32).cuda()
+    cands = ccfr.caller_candidates(t["vf"], t["ee"], t["vv"], counts, ve=t["ve"])
     _, off, hs, _ = H.gpu_regions(ctx, mesh, x, cands, sc.params)
     off_o, hs_o, _ = oracle.regions(om, sc.params, ref)
     assert H.compare_regions(sc, sc.params, off, hs, off_o, hs_o, float(np.float32(sc.params.xi)),

@@ -36,7 +36,7 @@ def test_candidates_exact_at_any_cell_size(env, scale, split, name):
         x = torch.from_numpy(sc.x.copy()).cuda()
         _, got, _ = H.gpu_candidates(ctx, mesh, x, ccfr.make_params(sc.params))
         want = oracle.candidates(oracle.Mesh(sc), sc.params)
-        for k in ("vf", "ee", "vv"):
+        for k in ("vf", "ee", "vv", "ve"):
             assert np.array_equal(H.sorted_pairs(got[k]), H.sorted_pairs(want[k])), (k, scale)
     finally:
         ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1, pair_skin=0)
@@ -76,4 +76,5 @@ def test_autotuner_picks_a_candidate_and_restores_state(env):
     assert ctx.get_tuning()["pair_split"] == out["pair_split"]
     assert ctx.get_tuning()["cell_scale"] == pytest.approx(out["cell_scale"], rel=1e-6)
     assert np.array_equal(x.cpu().numpy(), sc.x) and np.array_equal(v.cpu().numpy(), sc.v)
-    ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1, pair_skin=0)
+    assert out["broad_phase"] in (0, 1) and ctx.get_tuning()["broad_phase"] == out["broad_phase"]
+    ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1, pair_skin=0, broad_phase=0)

@@ -78,7 +78,7 @@ def test_candidates_conservative_for_range(orc, sc):
     c = orc.candidates(m, sc.params)
     allp = all_pair_distances(sc.x, sc.inv_mass, sc.tris, sc.edges)
     reach = 2 * sc.params.r + sc.params.xi
-    for kind in ("vf", "ee", "vv"):
+    for kind in ("vf", "ee", "vv", "ve"):
         pairs, d = allp[kind]
         need = {tuple(p) for p in pairs[d < reach].tolist()}
         got = {tuple(p) for p in c[kind].tolist()}
@@ -175,7 +175,8 @@ def test_regions_share_conservation(orc, sc):
     checked = 0
     for key, idx in groups.items():
         k, A, B = int(kind[idx[0]]), int(a[idx[0]]), int(b[idx[0]])
-        sideA = [A] if k in (1, 3) else list(sc.edges[A])
+        # kinds: 0 particle-edge, 1 vertex-face, 2 edge-edge, 3 particle-particle
+        sideA = [A] if k in (0, 1, 3) else list(sc.edges[A])
         sideB = list(sc.tris[B]) if k == 1 else ([B] if k == 3 else list(sc.edges[B]))
         ia = [i for i in idx if owner[i] in sideA]
         ib = [i for i in idx if owner[i] in sideB]
@@ -205,7 +206,7 @@ def test_regions_complete(orc, sc):
     reach = 2 * p.r + p.xi
     allp = all_pair_distances(sc.x, sc.inv_mass, sc.tris, sc.edges)
     have = set(zip(owner.tolist(), hs["key"].tolist()))
-    kmap = {"vf": 1, "ee": 2, "vv": 3}
+    kmap = {"ve": 0, "vf": 1, "ee": 2, "vv": 3}
     w = sc.inv_mass
     for kname, (pairs, d) in allp.items():
         far = d > reach + 1e-9
@@ -214,7 +215,8 @@ def test_regions_complete(orc, sc):
         assert not (set(keys[far].tolist()) & set(hs["key"].tolist()))
         for (A, B), dist, key in zip(pairs[d < reach - 1e-9].tolist(), d[d < reach - 1e-9], keys[d < reach - 1e-9].tolist()):
             verts = ([A] + list(sc.tris[B])) if kname == "vf" else \
-                (list(sc.edges[A]) + list(sc.edges[B]) if kname == "ee" else [A, B])
+                (list(sc.edges[A]) + list(sc.edges[B]) if kname == "ee" else
+                 ([A] + list(sc.edges[B]) if kname == "ve" else [A, B]))
             for v in verts:
                 if w[v] > 0 and (v, key) not in have:
                     # allowed only when the pair gives this side a zero effective mass

@@ -128,17 +128,17 @@ def test_min_separation_finds_vf_pair_with_static_geometry(orc):
     edges = np.array([[0, 1], [0, 2], [1, 2]], np.int32)
     d, below = orc.min_separation(x, w, tris, edges, reach=8e-3, below=xi)
     assert np.isclose(d, 0.9 * xi, rtol=1e-12)
-    assert below.tolist() == [1, 0, 0]
+    assert below.tolist() == [1, 0, 0, 0]
     # the triangle static, the vertex moving: still a pair
     w2 = w.copy()
     w2[:3] = 0.0
     d, below = orc.min_separation(x, w2, tris, edges, reach=8e-3, below=xi)
-    assert np.isclose(d, 0.9 * xi, rtol=1e-12) and below.tolist() == [1, 0, 0]
+    assert np.isclose(d, 0.9 * xi, rtol=1e-12) and below.tolist() == [1, 0, 0, 0]
     # both static: never moves, not reported
     w3 = w2.copy()
     w3[3] = 0.0
     d, below = orc.min_separation(x, w3, tris, edges, reach=8e-3, below=xi)
-    assert d == 8e-3 and below.tolist() == [0, 0, 0]
+    assert d == 8e-3 and below.tolist() == [0, 0, 0, 0]
 
 
 def test_min_separation_finds_ee_and_vv_pairs(orc):
@@ -150,12 +150,39 @@ def test_min_separation_finds_ee_and_vv_pairs(orc):
     edges = np.array([[0, 1], [2, 3]], np.int32)
     tris = np.zeros((0, 3), np.int32)
     d, below = orc.min_separation(x, w, tris, edges, reach=4e-3, below=xi)
-    assert np.isclose(d, 0.9 * xi, rtol=1e-12) and below.tolist() == [0, 1, 0]
+    assert np.isclose(d, 0.9 * xi, rtol=1e-12) and below.tolist() == [0, 1, 0, 0]
     # free particles: a moving pair at 0.9 xi, a static pair at 0.5 xi (skipped)
     x = np.vstack([[[0, 0, 0], [0.9 * xi, 0, 0], [1, 1, 1], [1, 1, 1 + 0.5 * xi]], _far_static(5)])
     w = np.concatenate([[1.0, 2.0, 0.0, 0.0], np.zeros(5)])
     d, below = orc.min_separation(x, w, tris, np.zeros((0, 2), np.int32), reach=4e-3, below=xi)
-    assert np.isclose(d, 0.9 * xi, rtol=1e-12) and below.tolist() == [0, 0, 1]
+    assert np.isclose(d, 0.9 * xi, rtol=1e-12) and below.tolist() == [0, 0, 1, 0]
+
+
+def test_min_separation_finds_particle_edge_pairs(orc):
+    """A free particle 0.9 xi from the interior of a segment and 0.7 xi beyond
+    the end of another (the foot clamps to the endpoint: distance 0.7 xi along
+    the diagonal); a vertex of a strand is no free particle and is not paired
+    with the other strand."""
+    xi = 1e-3
+    c = 0.7 * xi / np.sqrt(2)
+    x = np.array([[-1, 0, 0], [1, 0, 0],                      # edge 0 along x
+                  [0, 0.9 * xi, 0],                            # particle over its interior
+                  [2.0 + c, 1.0, c], [4.0, 1.0, 0.0],          # edge 1 along x, from (2+c, 1, c)
+                  [2.0, 1.0, 0.0]], float)                     # particle 0.7 xi before edge 1's start
+    edges = np.array([[0, 1], [3, 4]], np.int32)
+    tris = np.zeros((0, 3), np.int32)
+    d, below = orc.min_separation(x, np.ones(len(x)), tris, edges, reach=4e-3, below=0.95 * xi)
+    assert np.isclose(d, 0.7 * xi, rtol=1e-12) and below.tolist() == [0, 0, 0, 2]
+    d, below = orc.min_separation(x, np.ones(len(x)), tris, edges, reach=4e-3, below=0.8 * xi)
+    assert below.tolist() == [0, 0, 0, 1]
+    # both sides static: skipped
+    d, below = orc.min_separation(x, np.zeros(len(x)), tris, edges, reach=4e-3, below=xi)
+    assert d == 4e-3 and below.sum() == 0
+    # a particle moving through an edge is not certified
+    x1 = x.copy()
+    x1[2, 1] = -0.9 * xi
+    _, cert, _, _ = orc.motion_check(x, x1, np.ones(len(x)), tris, edges, 0.5 * xi, 4e-3)
+    assert not cert
 
 
 def test_motion_check_catches_crossing_between_separated_end_states(orc):

@@ -66,6 +66,56 @@ def test_vf_share_with_dynamic_face_and_interior_foot(orc):
         assert np.isclose(hv[0]["d"], 0.4 * phi, rtol=1e-12, atol=0)
 
 
+def test_ve_share_particle_over_edge_interior(orc):
+    """A free particle H above the point t = 1/4 of a dynamic edge (w 1 and 3:
+    w_e = 3/4 + 3/4 = 3/2), w_p = 3: s_p = 2/3, the edge side 1/3 (a swapped
+    share gives 1/3, a beta^2 weighting w_e = 3/4 gives 4/5).  Every vertex of
+    the pair receives a half-space under the particle-edge key (kind 0)."""
+    u = 2.0 ** -7
+    m = S._Mesh(np.array([[-u, 0, 0], [3 * u, 0, 0], [0, 0, H]], float), np.zeros((0, 3), np.int64),
+                [1.0, 3.0, 3.0])
+    m.extra_edges = np.array([[0, 1]], np.int64)
+    sc = S.assemble("ve_share", [m], PRM, S.StepParams(dt=1e-2, iters=1, gravity=(0, 0, 0)))
+    p = int(np.nonzero(np.all(np.isclose(sc.x, [0, 0, H]), axis=1))[0][0])
+    e = 0
+    phi = _phi()
+    key = (p << 31) | e
+    hp = _region(orc, sc, p)
+    assert len(hp) == 1 and int(hp[0]["key"]) == key
+    assert np.allclose(hp[0]["n"], [0, 0, 1], atol=1e-15)
+    assert np.isclose(hp[0]["d"], 2.0 / 3.0 * phi, rtol=1e-12, atol=0)
+    assert np.isclose(hp[0]["share"], 2.0 / 3.0, rtol=1e-12, atol=0)
+    for v in sc.edges[e]:
+        hv = _region(orc, sc, int(v))
+        assert len(hv) == 1 and int(hv[0]["key"]) == key
+        assert np.allclose(hv[0]["n"], [0, 0, -1], atol=1e-15)
+        assert np.isclose(hv[0]["d"], phi / 3.0, rtol=1e-12, atol=0)
+
+
+def test_ve_share_particle_beyond_edge_end(orc):
+    """The particle 3k behind the first endpoint and 4k above it (distance 5k):
+    the foot clamps to t = 0, the normal is (-3/5, 0, 4/5) and the edge side's
+    mass is its first endpoint's alone (w 1): s_p = 3/4.  The second endpoint
+    carries zero weight in the split yet still receives the edge side's
+    half-space (share 1/4)."""
+    u, k = 2.0 ** -7, 2.0 ** -12
+    m = S._Mesh(np.array([[-u, 0, 0], [3 * u, 0, 0], [-u - 3 * k, 0, 4 * k]], float), np.zeros((0, 3), np.int64),
+                [1.0, 3.0, 3.0])
+    m.extra_edges = np.array([[0, 1]], np.int64)
+    sc = S.assemble("ve_end", [m], PRM, S.StepParams(dt=1e-2, iters=1, gravity=(0, 0, 0)))
+    p = int(np.nonzero(np.all(np.isclose(sc.x, [-u - 3 * k, 0, 4 * k]), axis=1))[0][0])
+    phi = 5 * k - float(np.float32(PRM.xi))
+    hp = _region(orc, sc, p)
+    assert len(hp) == 1
+    assert np.allclose(hp[0]["n"], [-0.6, 0, 0.8], atol=1e-15)
+    assert np.isclose(hp[0]["d"], 0.75 * phi, rtol=1e-12, atol=0)
+    for v in sc.edges[0]:
+        hv = _region(orc, sc, int(v))
+        assert len(hv) == 1 and hv[0]["key"] == hp[0]["key"]
+        assert np.allclose(hv[0]["n"], [0.6, 0, -0.8], atol=1e-15)
+        assert np.isclose(hv[0]["d"], 0.25 * phi, rtol=1e-12, atol=0)
+
+
 @pytest.mark.parametrize("active_first", [True, False], ids=["lower_index", "higher_index"])
 def test_ee_share_with_interior_closest_points(orc, active_first):
     """Edge A along x with its closest point at s = 1/4 (w 1 and 3: w_A = 3/2),

@@ -159,3 +159,79 @@ def test_contact_scenes_no_penetration(orc, make):
         _check_state(orc, sc, sim.x)
         _check_motions(orc, sc, x0, trace)
     assert sim.counters[4] > 0
+
+
+def test_convergence_check_free_fall_closed_form(orc):
+    """Reading A23 of evaluateConvergence.  Far from everything, each iteration
+    moves a vertex by min(|x~ - x|, r) towards the prediction; the check ends
+    the step after the first iteration whose step is no longer shortened by
+    the clamp, i.e. after ceil(|x~ - x| / r) iterations, at the same position
+    the full iteration count reaches."""
+    from dataclasses import replace
+    sc = S.drape(n=6, side=0.1, sphere_level=1, sphere_radius=0.05, height=0.5, jitter=1e-3, r=2e-3, xi=2e-3)
+    r = float(np.float32(sc.params.r))
+    v0 = np.array([0.3, -0.1, 0.2])
+    dt = float(np.float32(sc.step.dt))
+    g = np.array([float(np.float32(c)) for c in sc.step.gravity])
+    delta = dt * v0 + dt * dt * g
+    need = int(np.ceil(np.linalg.norm(delta) / r))
+    assert 1 < need < sc.step.iters
+    full = orc.Sim(sc)
+    full.v[:36] = v0
+    full.step()
+    early = orc.Sim(sc.with_state())
+    early.scene = replace(sc, step=replace(sc.step, early_exit=True, conv_tol=0.01 * r))
+    early.v[:36] = v0
+    early.step()
+    assert early.counters[8] == need and full.counters[8] == sc.step.iters
+    assert np.array_equal(early.x, full.x)
+    # a vertex resting on a static triangle under gravity keeps falling short:
+    # the check never ends the step early
+    tri = S._Mesh(np.array([[-1, -1, 0.0], [1, -1, 0.0], [0, 1, 0.0]]), np.array([[0, 1, 2]]), [0, 0, 0])
+    pt = S.particles_mesh(np.array([[0.0, 0.0, 1.5e-3]]), 1.0)
+    rest = S.assemble("rest", [tri, pt], S.Params(r=1e-3, xi=1e-3),
+                      S.StepParams(dt=1 / 60, iters=6, early_exit=True, conv_tol=1e-5))
+    sim = orc.Sim(rest)
+    sim.step()
+    assert sim.counters[8] == 6 and sim.counters[4] > 0
+
+
+def test_consecutive_halt_statistics(orc):
+    """Reading A24: a vertex whose region cannot be satisfied within the pass
+    budget halts every iteration (a run as long as the substep), one that never
+    halts has none."""
+    from dataclasses import replace
+    # a particle squeezed between two static triangles closer than 2 xi: no
+    # displacement keeps it xi from both, so every projection of a downward
+    # proposal halts (max_passes = 1 leaves no verification pass)
+    lo = S._Mesh(np.array([[-1, -1, 0.0], [1, -1, 0.0], [0, 1, 0.0]]), np.array([[0, 1, 2]]), [0, 0, 0])
+    hi = S._Mesh(np.array([[-1, -1, 2.5e-3], [0, 1, 2.5e-3], [1, -1, 2.5e-3]]), np.array([[0, 1, 2]]), [0, 0, 0])
+    pt = S.particles_mesh(np.array([[0.0, 0.0, 1.25e-3]]), 1.0)
+    sc = S.assemble("squeeze", [lo, hi, pt], S.Params(r=1e-3, xi=1e-3, max_passes=1),
+                    S.StepParams(dt=1 / 60, iters=5))
+    sim = orc.Sim(sc)
+    sim.step()
+    c = sim.counters
+    assert c[5] == 5 and c[9] == 5 and c[10] == 1 and c[11] == 3
+    assert np.array_equal(sim.x, sc.x.astype(np.float64))        # halted every time: never moved
+
+
+def test_coupled_scene_steps_stay_valid(orc):
+    """The small coupled codimensional scene (rods, soft bodies with arms, a
+    paper sheet, particles; all four pair kinds) through two oracle substeps:
+    no penetration, every non-adjacent pair (particle-edge included) at least
+    xi apart, and every iteration's straight-line motion certified."""
+    sc = S.c5_small()
+    sim = orc.Sim(sc)
+    xi = float(np.float32(sc.params.xi))
+    for step in range(2):
+        prev = sim.x.copy()
+        tr = sim.step(trace=True)
+        assert orc.count_intersections(sim.x, sc.tris, sc.edges) == 0
+        d, below = orc.min_separation(sim.x, sc.inv_mass, sc.tris, sc.edges, 4 * xi, xi * (1 - 1e-6))
+        assert below.sum() == 0, (step, d, below)
+        for it in range(len(tr)):
+            dmin, cert, _, _ = orc.motion_check(prev, tr[it], sc.inv_mass, sc.tris, sc.edges, 0.5 * xi, 4 * xi)
+            assert cert and dmin >= xi * (1 - 1e-6), (step, it, dmin)
+            prev = tr[it]
+    assert sim.counters[3] > 0                  # half-spaces were built

@@ -1,8 +1,9 @@
 """The workload generators: every configuration starts valid (reading A20: no
 initial-intersection exclusion, so the minimum non-adjacent vertex-face,
-edge-edge and particle-particle distance must be at least xi + 0.1 mm), the
-strand generator's curl-halving rule fires where the spacing clip alone would
-leave strands too close, and the generators reproduce the recorded SHA-256 of
+edge-edge, particle-particle and particle-edge distance must be at least
+xi + 0.1 mm), the strand generator's curl-halving rule fires where the
+spacing clip alone would leave strands too close, and the generators
+reproduce the recorded SHA-256 of
 their arrays (tests/golden/fixtures_sha256.json, written by
 tests/golden/make_fixture_hashes.py)."""
 import json
@@ -22,7 +23,7 @@ def _min_gap(orc, sc, need):
     return d, below
 
 
-@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3"])
+@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3", "c5"])
 def test_workload_starts_valid(orc, name):
     sc = S.SCENES[name]()
     xi = float(np.float32(sc.params.xi))
