@@ -359,6 +359,13 @@ typedef struct {
                             bounding-volume hierarchy over the padded boxes of the
                             targets (the analogue of the paper's AABB tree, Sec.
                             4.1), rebuilt with every candidate build; the same pairs */
+    int32_t direct_regions; /* substeps with per-vertex slot regions: 0 (default)
+                            the narrow phase compacts the pairs in range into a
+                            contact list and a fill launch writes their
+                            half-spaces; 1 the narrow phase writes them into the
+                            slots itself (one launch and the list fewer, but its
+                            wavefronts wait on the writes: faster when most
+                            candidate pairs are in range).  The same regions. */
 } ccfr_tuning;
 int ccfr_set_tuning(ccfr_ctx* ctx, const ccfr_tuning* tuning);
 int ccfr_get_tuning(const ccfr_ctx* ctx, ccfr_tuning* tuning);

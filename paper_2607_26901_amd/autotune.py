@@ -6,7 +6,9 @@ one broad-phase query (`pair_split`) and how solver iterations share candidate
 builds inside a substep: a fixed number per build (`pair_reuse`) or as many as
 the measured motion allows within a widening of s r (`pair_skin` = s), and
 the broad phase itself (`broad_phase`: the hash grid, or the bounding-volume
-hierarchy, which has no cell or split knob).  Smaller cells put
+hierarchy, which has no cell or split knob), and whether the narrow phase
+writes a substep's slot regions itself (`direct_regions`, tried on the best
+of the other settings).  Smaller cells put
 fewer entries in the buckets a query scans but bin long primitives one level
 up; more lanes per query shorten the walks of queries in dense folds at the
 price of more lanes; sharing a build saves grid builds and queries at the price
@@ -31,6 +33,7 @@ PAIR_SPLITS = (1, 3, 9)
 # the motion with a skin of 1-3 r
 PAIR_MODES = ((1, 0), (2, 0), (3, 0), (4, 0), (1, 1), (1, 2), (1, 3))
 BROAD_PHASES = (0, 1)
+DIRECT_REGIONS = (0, 1)
 
 
 def size_class(n_verts, n_tris, n_edges, r, kind="mesh") -> str:
@@ -94,7 +97,7 @@ def _settings(candidates, splits, modes, broad_phases):
 
 
 def tune(ctx: ccfr.Context, run, candidates=CELL_SCALES, splits=PAIR_SPLITS, modes=((1, 0),),
-         repeats: int = 2, log=_log, grow_factor: float = 4.0, broad_phases=(0,)) -> dict:
+         repeats: int = 2, log=_log, grow_factor: float = 4.0, broad_phases=(0,), directs=(0,)) -> dict:
     """Time `run(limit)` (device milliseconds of a fixed piece of work, starting
     from the same state every call, and the list bytes it needed) under each
     (cell scale, split, (reuse, skin), broad phase); leave the fastest set.  A
@@ -120,10 +123,27 @@ def tune(ctx: ccfr.Context, run, candidates=CELL_SCALES, splits=PAIR_SPLITS, mod
         if log:
             log(f"[tune] cell {c} split {sp} reuse {ru} skin {sk} broad phase {bp}: {ms:.3f} ms")
     best = min(times, key=times.get)
+    times = {k + (directs[0],): v for k, v in times.items()}
+    best = best + (directs[0],)
+    for d in directs[1:]:
+        key = best[:5] + (d,)
+        ctx.set_tuning(cell_scale=key[0], pair_split=key[1], pair_reuse=key[2], pair_skin=key[3], broad_phase=key[4],
+                       direct_regions=d)
+        try:
+            run(limit)
+            ms = min(run(limit)[0] for _ in range(repeats))
+        except TooLarge:
+            ms = math.inf
+        times[key] = ms
+        if log:
+            log(f"[tune] best setting with direct regions {d}: {ms:.3f} ms")
+        if ms < times[best]:
+            best = key
     ctx.set_tuning(cell_scale=best[0], pair_split=best[1], pair_reuse=best[2], pair_skin=best[3],
-                   broad_phase=best[4])
+                   broad_phase=best[4], direct_regions=best[5])
     return {"cell_scale": best[0], "pair_split": best[1], "pair_reuse": best[2], "pair_skin": best[3],
-            "broad_phase": best[4], "ms": {"/".join(str(q) for q in k): v for k, v in times.items()}}
+            "broad_phase": best[4], "direct_regions": best[5],
+            "ms": {"/".join(str(q) for q in k): v for k, v in times.items()}}
 
 
 def _events():
@@ -133,7 +153,7 @@ def _events():
 
 def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, steps: int = 4,
               candidates=CELL_SCALES, splits=PAIR_SPLITS, modes=PAIR_MODES, cache: Cache | None = None,
-              key: str | None = None, log=_log, broad_phases=BROAD_PHASES) -> dict:
+              key: str | None = None, log=_log, broad_phases=BROAD_PHASES, directs=DIRECT_REGIONS) -> dict:
     """Tune on `steps` single-mesh steps from the state (x, v), which is restored."""
     import torch
     if cache is not None and key is not None:
@@ -141,7 +161,7 @@ def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, ste
         if hit is not None:
             ctx.set_tuning(cell_scale=hit["cell_scale"], pair_split=hit["pair_split"],
                            pair_reuse=hit.get("pair_reuse", 1), pair_skin=hit.get("pair_skin", 0),
-                           broad_phase=hit.get("broad_phase", 0))
+                           broad_phase=hit.get("broad_phase", 0), direct_regions=hit.get("direct_regions", 0))
             return dict(hit, cached=True)
     x0, v0 = x.clone(), v.clone()
 
@@ -164,7 +184,7 @@ def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, ste
             ctx.grow(info)                      # lists too small: grow and time again
         raise ccfr.CcfrError(-2, "tuning run")
 
-    out = tune(ctx, run, candidates, splits, modes, log=log, broad_phases=broad_phases)
+    out = tune(ctx, run, candidates, splits, modes, log=log, broad_phases=broad_phases, directs=directs)
     x.copy_(x0)
     v.copy_(v0)
     torch.cuda.synchronize()

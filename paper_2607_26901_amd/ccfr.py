@@ -58,7 +58,7 @@ class StepParams(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("cell_scale", C.c_float), ("pair_split", C.c_int32), ("pair_reuse", C.c_int32),
-                ("pair_skin", C.c_int32), ("broad_phase", C.c_int32)]
+                ("pair_skin", C.c_int32), ("broad_phase", C.c_int32), ("direct_regions", C.c_int32)]
 
 
 class StatusInfo(C.Structure):
@@ -251,21 +251,24 @@ class Context:
                      ve=int(info.get("need_ve", 0) * factor) + 1024, contacts=int(nd[3] * factor) + 1024,
                      halfspaces=int(nd[4] * factor) + 1024)
 
-    def set_tuning(self, cell_scale=None, pair_split=None, pair_reuse=None, pair_skin=None, broad_phase=None):
+    def set_tuning(self, cell_scale=None, pair_split=None, pair_reuse=None, pair_skin=None, broad_phase=None,
+                   direct_regions=None):
         """Change any of the speed-only knobs (None keeps the current value)."""
         cur = self.get_tuning()
         t = Tuning(float(cur["cell_scale"] if cell_scale is None else cell_scale),
                    int(cur["pair_split"] if pair_split is None else pair_split),
                    int(cur["pair_reuse"] if pair_reuse is None else pair_reuse),
                    int(cur["pair_skin"] if pair_skin is None else pair_skin),
-                   int(cur["broad_phase"] if broad_phase is None else broad_phase))
+                   int(cur["broad_phase"] if broad_phase is None else broad_phase),
+                   int(cur["direct_regions"] if direct_regions is None else direct_regions))
         _check(self.lib.ccfr_set_tuning(self.h, C.byref(t)), "ccfr_set_tuning")
 
     def get_tuning(self) -> dict:
         t = Tuning()
         _check(self.lib.ccfr_get_tuning(self.h, C.byref(t)), "ccfr_get_tuning")
         return {"cell_scale": float(t.cell_scale), "pair_split": int(t.pair_split),
-                "pair_reuse": int(t.pair_reuse), "pair_skin": int(t.pair_skin), "broad_phase": int(t.broad_phase)}
+                "pair_reuse": int(t.pair_reuse), "pair_skin": int(t.pair_skin), "broad_phase": int(t.broad_phase),
+                "direct_regions": int(t.direct_regions)}
 
     def profile_enable(self, on=True):
         _check(self.lib.ccfr_profile_enable(self.h, int(bool(on))), "ccfr_profile_enable")

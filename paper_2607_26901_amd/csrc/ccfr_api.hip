@@ -373,19 +373,23 @@ int32_t step_slot_stride(const ccfr_ctx* ctx, int n_verts) {
 
 // narrow phase into the context's regions; inside a substep (`in_step`) both
 // builds are closed by launch_close_iteration, and with slot_stride > 0 the
-// half-spaces go into per-vertex slots (no scan or fill)
+// half-spaces go into per-vertex slots (no count scan): from the contact list
+// by a fill launch, or with the direct_regions knob straight from the narrow
+// phase (no contact list, one launch fewer)
 void enqueue_regions(ccfr_ctx* ctx, const Scene& sc, const PairLists& pl, const int32_t* counts, hipStream_t s,
                      const Marks& mk, bool in_step, int32_t slot_stride = 0,
                      const ColourJob* job_contacts = nullptr, const ColourJob* job_fill = nullptr) {
     const bool slots = in_step && slot_stride > 0;
+    const bool direct = slots && ctx->direct_regions;
     mk.mark(2, 0);
-    launch_contacts(sc, pl, counts, ctx->contacts, ctx->cap_contacts, ctx->vcount, ctx->counters_d, s, slots,
-                    job_contacts);
+    launch_contacts(sc, pl, counts, ctx->contacts, ctx->cap_contacts, slots && !direct ? nullptr : ctx->vcount,
+                    ctx->counters_d, s, direct ? ctx->hs : nullptr, direct ? slot_stride : 0, job_contacts);
     mk.mark(2, 1);
     mk.mark(3, 0);
     if (slots) {
-        launch_fill_slots(sc, ctx->contacts, ctx->cap_contacts, ctx->vcount, ctx->hs, slot_stride, ctx->counters_d, s,
-                          job_fill);
+        if (!direct)
+            launch_fill_slots(sc, ctx->contacts, ctx->cap_contacts, ctx->vcount, ctx->hs, slot_stride,
+                              ctx->counters_d, s, job_fill);
         mk.mark(3, 1);
         return;
     }
@@ -445,7 +449,8 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
     // next iteration's reset and first colour in extra blocks of the slow
     // projection (the first iteration's in a launch of their own), the second,
     // third and fourth colours in the first blocks of the narrow phase, the
-    // slot fill and the closing kernel; further colours get launches of their own.
+    // slot fill (when there is one) and the closing kernel; further colours
+    // get launches of their own.
     StretchColor0 c0{};
     if (plan.has_stretch && !plan.col_total.empty())
         c0 = StretchColor0{plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[0], plan.col_nseg[0],
@@ -466,10 +471,13 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
                           plan.col_total[c], sc.inv_mass, ctx->p, plan.lambda, plan.alpha_t};
         return j;
     };
-    const ColourJob job_contacts = colour_job(1), job_fill = colour_job(2), job_close = colour_job(3);
+    const bool direct = slots > 0 && ctx->direct_regions;     // no slot fill launch to host a colour
+    const ColourJob job_contacts = colour_job(1), job_fill = direct ? ColourJob{} : colour_job(2),
+                    job_close = colour_job(direct ? 2 : 3);
+    const int first_launched = direct ? 3 : 4;                   // first colour with a launch of its own
     if (hosted)
         launch_close_iteration(ctx->x_pred, ctx->p, 3LL * n, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
-                               ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs, false, s, slots, &c0, false);
+                               ctx->offsets, caps, direct ? -1 : ctx->cap_contacts, ctx->cap_hs, false, s, slots, &c0, false);
     for (int it = 0; it < plan.iters; ++it) {
         const Marks mk{ctx, it, s};
         const int first = it - it % reuse;
@@ -496,14 +504,14 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
         const bool close_pairs = adaptive ? it == plan.iters - 1 : it == first + group - 1;
         if (hosted)
             launch_close_iteration(nullptr, nullptr, 0, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
-                                   ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs, close_pairs, s, slots, nullptr,
+                                   ctx->offsets, caps, direct ? -1 : ctx->cap_contacts, ctx->cap_hs, close_pairs, s, slots, nullptr,
                                    true, &job_close, skip);
         else
             launch_close_iteration(ctx->x_pred, ctx->p, 3LL * n, ctx->counters_d, ctx->level_mask, plan.n_meshes, n,
-                                   ctx->offsets, caps, ctx->cap_contacts, ctx->cap_hs, close_pairs, s, slots, &c0,
+                                   ctx->offsets, caps, direct ? -1 : ctx->cap_contacts, ctx->cap_hs, close_pairs, s, slots, &c0,
                                    true, nullptr, skip);
         if (plan.has_stretch)
-            for (int c = hosted ? 4 : 1; c < n_launched; ++c)
+            for (int c = hosted ? first_launched : 1; c < n_launched; ++c)
                 launch_stretch_segments(plan.edges_sorted, plan.rest_sorted, plan.segs + plan.col_first[c],
                                         plan.col_nseg[c], plan.col_total[c], sc.inv_mass, ctx->p, plan.lambda,
                                         plan.alpha_t, s, skip);
@@ -1099,16 +1107,19 @@ int ccfr_sync_status(ccfr_ctx* ctx, ccfr_stream stream, ccfr_status_info* info, 
 int ccfr_set_tuning(ccfr_ctx* ctx, const ccfr_tuning* t) {
     if (!ctx || !t || !std::isfinite(t->cell_scale) || t->cell_scale < 0.25f || t->cell_scale > 4.0f ||
         (t->pair_split != 1 && t->pair_split != 3 && t->pair_split != 9) || t->pair_reuse < 0 || t->pair_reuse > 4 ||
-        t->pair_skin < 0 || t->pair_skin > 4 || (t->broad_phase != 0 && t->broad_phase != 1))
+        t->pair_skin < 0 || t->pair_skin > 4 || (t->broad_phase != 0 && t->broad_phase != 1) ||
+        (t->direct_regions != 0 && t->direct_regions != 1))
         return CCFR_ERR_INVALID_ARG;
     const int reuse = std::max(1, (int)t->pair_reuse);
     if (t->cell_scale != ctx->cell_scale || t->pair_split != ctx->pair_split || reuse != ctx->pair_reuse ||
-        t->pair_skin != ctx->pair_skin || t->broad_phase != ctx->broad_phase) {
+        t->pair_skin != ctx->pair_skin || t->broad_phase != ctx->broad_phase ||
+        t->direct_regions != ctx->direct_regions) {
         ctx->cell_scale = t->cell_scale;
         ctx->pair_split = t->pair_split;
         ctx->pair_reuse = reuse;
         ctx->pair_skin = t->pair_skin;
         ctx->broad_phase = t->broad_phase;
+        ctx->direct_regions = t->direct_regions;
         ctx->tune_generation++;
         ctx->generation++;          // recorded graphs carry the old settings
         drop_graph(ctx);
@@ -1124,6 +1135,7 @@ int ccfr_get_tuning(const ccfr_ctx* ctx, ccfr_tuning* t) {
     t->pair_reuse = ctx->pair_reuse;
     t->pair_skin = ctx->pair_skin;
     t->broad_phase = ctx->broad_phase;
+    t->direct_regions = ctx->direct_regions;
     return CCFR_OK;
 }
 

@@ -104,6 +104,7 @@ struct ccfr_ctx {
     int pair_reuse = 1;         // solver iterations per candidate build inside a substep
     int pair_skin = 0;          // > 0: builds widened by pair_skin r, rebuilt when the motion needs it
     int broad_phase = 0;        // 0: multi-level hash grid, 1: bounding-volume hierarchy
+    int direct_regions = 0;     // substeps: the narrow phase writes the slots itself (no contact list)
     long long tune_generation = 0;
 
     // bounding-volume hierarchy (broad_phase 1), sized for cap_lbvh leaves

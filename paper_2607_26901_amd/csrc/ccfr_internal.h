@@ -147,12 +147,14 @@ __device__ __forceinline__ void reset_region_counters(DevCounters* c) {
 // End of a region build into per-vertex slots of `stride` entries (one thread):
 // a vertex that received more half-spaces than its slots sets the overflow bit,
 // and the need is reported as the half-space buffer that would hold them all.
+// cap_contacts: the contact list's room (-1 when the narrow phase wrote the
+// slots itself and stored no list).
 __device__ __forceinline__ void finalize_slot_regions_body(DevCounters* c, int32_t n_verts, int32_t stride,
                                                            int64_t cap_contacts) {
     const long long H = c->n_hs;
     const long long nc = c->n_contacts;
     if (c->max_slot > stride) c->status |= ST_HS;
-    if (nc > cap_contacts) c->status |= ST_CONTACTS;
+    if (cap_contacts >= 0 && nc > cap_contacts) c->status |= ST_CONTACTS;
     c->need[3] = max(c->need[3], nc);
     c->need[4] = max(c->need[4], (long long)c->max_slot * (long long)n_verts);
     c->totals[3] += H;
@@ -337,14 +339,17 @@ void launch_grid_scatter(const Scene& sc, GridWs& g, DevCounters* c, hipStream_t
 void launch_pairs(const Scene& sc, const GridWs& g, PairLists pl, DevCounters* c, int split, hipStream_t s);
 void launch_finalize_pairs(const GridWs& g, PairLists pl, DevCounters* c, hipStream_t s);
 
-// The contact list of the candidate pairs; vcount counts each vertex's
-// half-spaces for the CSR unless `for_slots` (launch_fill_slots counts them)
+// The narrow phase over the candidate pairs (counts: the four list lengths,
+// VF, EE, VV, VE, on the device).  slot_stride == 0: the kept pairs go into
+// the contact list and vcount counts each vertex's half-spaces for the CSR;
+// slot_stride > 0: their half-spaces go straight into per-vertex slots,
+// slot_hs[v * slot_stride + k] for the k-th one vertex v receives, vcount[v]
+// counting them (no contact list)
 struct ColourJob;
-// (counts: the four list lengths, VF, EE, VV, VE, on the device)
 void launch_contacts(const Scene& sc, const PairLists& pl, const int32_t* counts, Contact* contacts,
-                     int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s, bool for_slots = false,
-                     const ColourJob* job = nullptr);
-// The contacts' half-spaces into per-vertex slots: slot_hs[v * slot_stride + k]
+                     int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s,
+                     ccfr_halfspace* slot_hs = nullptr, int32_t slot_stride = 0, const ColourJob* job = nullptr);
+// The contact list's half-spaces into per-vertex slots: slot_hs[v * slot_stride + k]
 // for the k-th one vertex v receives (vcount[v] counts them)
 void launch_fill_slots(const Scene& sc, const Contact* contacts, int64_t cap_contacts, int32_t* vcount,
                        ccfr_halfspace* slot_hs, int32_t slot_stride, DevCounters* c, hipStream_t s,

@@ -23,6 +23,11 @@
 //             side B's, each at offsets[v] + (atomic decrement of its count),
 //             which also returns the counts to zero for the next build
 //
+// Inside a substep the regions go into per-vertex slots instead: every kept
+// pair's half-spaces go into the next free slot of each receiving vertex (one
+// atomic each), either from the contact list by a fill launch or, with the
+// direct_regions knob, straight from the narrow phase (no contact list).
+//
 // Readings of the printed Alg. 3: d = s (|n| - xi) (A1); for the face side of a
 // vertex-face pair the normal points from the vertex towards the face and the
 // share is w_f / (w_f + w_q) (A5); effective inverse masses are
@@ -262,11 +267,72 @@ __device__ bool eval_pair(const Scene& sc, int kind, int pa, int pb, Contact* re
     return true;
 }
 
+// A contact's half-spaces into per-vertex slots: every receiving vertex claims
+// its next slot of `stride` with one atomic on its count; a vertex that
+// receives more than its slots keeps the first ones it got (the largest count
+// is reported and the step is repeated with more room).  Counts the
+// half-spaces written and the largest slot claimed.
+__device__ __forceinline__ void put_slots(const Contact& rec, int32_t* counts, ccfr_halfspace* hs, int32_t stride,
+                                          int& n_hs, int& top) {
+    const int kind = (int)((uint32_t)rec.a >> 30);
+    const int pa = rec.a & 0x3fffffff, pb = rec.b;
+    const int nA = kind == KIND_EE ? 2 : 1;     // receiving vertices of side A come first
+    int slot[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) slot[k] = rec.rv[k] >= 0 ? atomicAdd(&counts[rec.rv[k]], 1) : 0;
+    ccfr_halfspace h;
+    h.phi = rec.phi;
+    h.key = ((uint64_t)kind << 62) | ((uint64_t)(uint32_t)pa << 31) | (uint64_t)(uint32_t)pb;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (rec.rv[k] < 0) continue;
+        const float sg = k < nA ? 1.0f : -1.0f;
+        h.n[0] = sg * rec.n[0]; h.n[1] = sg * rec.n[1]; h.n[2] = sg * rec.n[2];
+        h.d = k < nA ? rec.dA : rec.dB;
+        h.share = k < nA ? rec.sA : rec.sB;
+        top = max(top, slot[k] + 1);
+        if (slot[k] < stride) {
+            hs[(long long)rec.rv[k] * stride + slot[k]] = h;
+            ++n_hs;
+        }
+    }
+}
+
+// Block sums of the slot writes (half-spaces written, largest slot, pairs
+// kept) added to the counters with one atomic each.  Every thread of the
+// block calls it.
+__device__ __forceinline__ void flush_slot_counts(DevCounters* c, int n_hs, int top, int n_kept) {
+    for (int off = 32; off > 0; off >>= 1) {
+        n_hs += __shfl_xor(n_hs, off);
+        top = max(top, __shfl_xor(top, off));
+        n_kept += __shfl_xor(n_kept, off);
+    }
+    __shared__ int red[kBlock / 64][3];
+    const int wave = threadIdx.x / 64;
+    if (__lane_id() == 0) {
+        red[wave][0] = n_hs;
+        red[wave][1] = top;
+        red[wave][2] = n_kept;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int b = 0, t = 0, k = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            b += red[w][0];
+            t = max(t, red[w][1]);
+            k += red[w][2];
+        }
+        if (b) atomicAdd(&c->n_hs, b);
+        if (t > 0) atomicMax(&c->max_slot, t);
+        if (k) atomicAdd(&c->n_contacts, k);
+    }
+}
+
 template <class R>
 __global__ __launch_bounds__(kBlock, 5) void k_contacts(Scene sc, PairLists pl, const int32_t* counts,
                                                      Contact* contacts, int64_t cap_contacts,
-                                                     int32_t* vcount, DevCounters* c, ColourJob job,
-                                                     int job_blocks) {
+                                                     int32_t* vcount, ccfr_halfspace* slot_hs, int32_t slot_stride,
+                                                     DevCounters* c, ColourJob job, int job_blocks) {
     if (sc.skip && *sc.skip) return;              // the substep's iterations have ended
     // the first job_blocks blocks run a stretch colour (the pairs read no p)
     if ((int)blockIdx.x < job_blocks) {
@@ -280,7 +346,8 @@ __global__ __launch_bounds__(kBlock, 5) void k_contacts(Scene sc, PairLists pl, 
     const long long total = nvf + nee + nvv + nve;
     __shared__ int wave_cnt[kWavesPerBlock];
     __shared__ int block_base;
-    int n_degenerate = 0;
+    const bool slots = slot_stride > 0;      // half-spaces straight into per-vertex slots
+    int n_degenerate = 0, n_hs = 0, top = 0, n_kept = 0;
     // grid-stride: every thread of the block runs the same number of rounds so
     // that the block-level append sees all of them together
     const long long stride = (long long)(gridDim.x - job_blocks) * kBlock;
@@ -323,24 +390,26 @@ __global__ __launch_bounds__(kBlock, 5) void k_contacts(Scene sc, PairLists pl, 
                 rec.rv[3] = (kind == KIND_VF || kind == KIND_EE) && wb1 > 0.f ? b1 : -1;
             }
             n_degenerate += deg ? 1 : 0;
-            if (keep && vcount) {
+            if (keep && slots) {
+                put_slots(rec, vcount, slot_hs, slot_stride, n_hs, top);
+                ++n_kept;
+            } else if (keep && vcount) {
                 for (int k = 0; k < pv.nA; ++k)
                     if (pv.wa[k] > 0.f) atomicAdd(&vcount[pv.a[k]], 1);
                 for (int k = 0; k < pv.nB; ++k)
                     if (pv.wb[k] > 0.f) atomicAdd(&vcount[pv.b[k]], 1);
             }
         }
-        block_append(contacts, &c->n_contacts, cap_contacts, rec, keep, wave_cnt, &block_base);
+        if (!slots) block_append(contacts, &c->n_contacts, cap_contacts, rec, keep, wave_cnt, &block_base);
     }
+    if (slots) flush_slot_counts(c, n_hs, top, n_kept);
     if (n_degenerate) atomicAdd((unsigned long long*)&c->totals[6], (unsigned long long)n_degenerate);
 }
 
-// Inside a substep the regions go into per-vertex slots instead of a CSR: the
+// Inside a substep, unless the narrow phase writes the slots itself: the
 // contact list is built as for the CSR (without per-vertex counts), then every
-// contact claims the next slot of each receiving vertex with one atomic and
-// writes its half-space there, so no count scan is needed.  A vertex that
-// receives more half-spaces than it has slots keeps the first ones it got and
-// the largest count is reported (the step is then repeated with more room).
+// contact claims the next slot of each receiving vertex (put_slots), so no
+// count scan is needed.
 __global__ __launch_bounds__(kBlock) void k_fill_slots(Scene sc, const Contact* contacts, int64_t cap_contacts,
                                                        int32_t* counts, ccfr_halfspace* hs, int32_t stride,
                                                        DevCounters* c, ColourJob job, int job_blocks) {
@@ -352,51 +421,9 @@ __global__ __launch_bounds__(kBlock) void k_fill_slots(Scene sc, const Contact* 
     const long long n = min((long long)c->n_contacts, (long long)cap_contacts);
     const long long stride_g = (long long)(gridDim.x - job_blocks) * kBlock;
     int n_hs = 0, top = 0;
-    for (long long i = (long long)(blockIdx.x - job_blocks) * kBlock + threadIdx.x; i < n; i += stride_g) {
-        const Contact rec = contacts[i];
-        const int kind = (int)((uint32_t)rec.a >> 30);
-        const int pa = rec.a & 0x3fffffff, pb = rec.b;
-        const int nA = kind == KIND_EE ? 2 : 1;     // receiving vertices of side A come first
-        int slot[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) slot[k] = rec.rv[k] >= 0 ? atomicAdd(&counts[rec.rv[k]], 1) : 0;
-        ccfr_halfspace h;
-        h.phi = rec.phi;
-        h.key = ((uint64_t)kind << 62) | ((uint64_t)(uint32_t)pa << 31) | (uint64_t)(uint32_t)pb;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (rec.rv[k] < 0) continue;
-            const float sg = k < nA ? 1.0f : -1.0f;
-            h.n[0] = sg * rec.n[0]; h.n[1] = sg * rec.n[1]; h.n[2] = sg * rec.n[2];
-            h.d = k < nA ? rec.dA : rec.dB;
-            h.share = k < nA ? rec.sA : rec.sB;
-            top = max(top, slot[k] + 1);
-            if (slot[k] < stride) {
-                hs[(long long)rec.rv[k] * stride + slot[k]] = h;
-                ++n_hs;
-            }
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        n_hs += __shfl_xor(n_hs, off);
-        top = max(top, __shfl_xor(top, off));
-    }
-    __shared__ int red[kWavesPerBlock][2];
-    const int wave = threadIdx.x / 64;
-    if (__lane_id() == 0) {
-        red[wave][0] = n_hs;
-        red[wave][1] = top;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int b = 0, t = 0;
-        for (int w = 0; w < kWavesPerBlock; ++w) {
-            b += red[w][0];
-            t = max(t, red[w][1]);
-        }
-        if (b) atomicAdd(&c->n_hs, b);
-        if (t > 0) atomicMax(&c->max_slot, t);
-    }
+    for (long long i = (long long)(blockIdx.x - job_blocks) * kBlock + threadIdx.x; i < n; i += stride_g)
+        put_slots(contacts[i], counts, hs, stride, n_hs, top);
+    flush_slot_counts(c, n_hs, top, 0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill(Scene sc, const Contact* contacts, int64_t cap_contacts,
@@ -441,15 +468,15 @@ int grid_for(long long n) {
 }  // namespace
 
 void launch_contacts(const Scene& sc, const PairLists& pl, const int32_t* counts, Contact* contacts,
-                     int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s, bool for_slots,
-                     const ColourJob* job) {
+                     int64_t cap_contacts, int32_t* vcount, DevCounters* c, hipStream_t s, ccfr_halfspace* slot_hs,
+                     int32_t slot_stride, const ColourJob* job) {
     ColourJob hosted{};
     if (job) hosted = *job;
     const int jb = colour_job_blocks(hosted, kBlock);
     const int blocks = grid_for(pl.cap_vf + pl.cap_ee + pl.cap_vv + pl.cap_ve) + jb;
-    int32_t* per_vertex = for_slots ? nullptr : vcount;     // slots: counted by the fill
     hipLaunchKernelGGL(k_contacts<double>, dim3(blocks), dim3(kBlock), 0, s, sc, pl, counts, contacts, cap_contacts,
-                       per_vertex, c, hosted, jb);
+                       vcount, slot_stride > 0 ? slot_hs : nullptr, slot_stride > 0 ? slot_stride : 0, c, hosted,
+                       jb);
 }
 
 void launch_fill_slots(const Scene& sc, const Contact* contacts, int64_t cap_contacts, int32_t* vcount,

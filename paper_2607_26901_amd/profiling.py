@@ -77,6 +77,8 @@ def knobs_key(t: dict) -> str:
           f"pair_reuse={int(t.get('pair_reuse', 1))} pair_skin={int(t.get('pair_skin', 0))}"
     if int(t.get("broad_phase", 0)):
         key += f" broad_phase={int(t['broad_phase'])}"
+    if int(t.get("direct_regions", 0)):
+        key += f" direct_regions={int(t['direct_regions'])}"
     return key
 
 

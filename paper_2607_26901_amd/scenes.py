@@ -259,7 +259,7 @@ BENCH_KNOBS = {
     "c0": dict(cell_scale=0.7, pair_split=9, pair_reuse=4, pair_skin=0),
     "c1": dict(cell_scale=0.7, pair_split=1, pair_reuse=3, pair_skin=0),
     "c2": dict(cell_scale=0.85, pair_split=1, pair_reuse=4, pair_skin=0),
-    "c3": dict(cell_scale=0.85, pair_split=1, pair_reuse=1, pair_skin=0),
+    "c3": dict(cell_scale=0.85, pair_split=1, pair_reuse=1, pair_skin=0, direct_regions=1),
     "c5": dict(cell_scale=0.7, pair_split=9, pair_reuse=1, pair_skin=1),
 }
 

@@ -78,3 +78,26 @@ def test_autotuner_picks_a_candidate_and_restores_state(env):
     assert np.array_equal(x.cpu().numpy(), sc.x) and np.array_equal(v.cpu().numpy(), sc.v)
     assert out["broad_phase"] in (0, 1) and ctx.get_tuning()["broad_phase"] == out["broad_phase"]
     ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1, pair_skin=0, broad_phase=0)
+
+
+@pytest.mark.parametrize("name", ["c0", "two_layers", "particles", "strands", "c5_small"])
+@pytest.mark.parametrize("reuse", [1, 3])
+def test_direct_regions_give_the_same_substeps(env, name, reuse):
+    """Slot regions written by the narrow phase itself (direct_regions) or by a
+    fill launch from the contact list: the same half-spaces in another order,
+    which the projection sorts, so substeps are bitwise equal; with six stretch
+    colours (C0's cloth) the colours move to other host kernels and the pass
+    is the same."""
+    ctx, ccfr, oracle, torch = env
+    sc = S.c0() if name == "c0" else S.c5_small() if name == "c5_small" else SCENES[name]()
+    v0 = sc.v.copy()
+    if name == "two_layers":
+        v0[sc.n_verts // 2:, 2] = -0.4
+    sp = ccfr.make_step_params(sc.step, sc.params)
+    outs = []
+    for direct in (0, 1):
+        ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=reuse, pair_skin=0, direct_regions=direct)
+        mesh = ccfr.mesh_from_scene(ctx, sc)
+        outs.append(H.steps_with_growth(ctx, mesh, sc, v0, sp, 3))
+    ctx.set_tuning(cell_scale=1.0, pair_split=1, pair_reuse=1, pair_skin=0, direct_regions=0)
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
