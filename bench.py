@@ -38,7 +38,7 @@ if ROOT not in sys.path:
 METRIC = "vertex region build+project updates/s (65k cloth); p50/p99 step latency"
 # the served stream's cap on resident vertices per batched step (a step's time,
 # which every resident request waits for, grows with them)
-SERVED_VERTS_CAP = 300000
+SERVED_VERTS_CAP = 250000
 HBM_PEAK_GBS = 8000.0
 
 
