@@ -100,7 +100,7 @@ STAGE_PARTS = {"a1_candidates": ("grid_build", "pair_emission"),
 # The kernels of each stage, for the counter summary.
 STAGE_KERNELS = {"a1_candidates": ("k_reset_build", "k_grid_count", "k_scan_reduce", "k_scan_down",
                                    "k_grid_scatter", "k_pairs"),
-                 "a2_regions": ("k_contacts",),
+                 "a2_regions": ("k_contacts", "k_fill_slots"),
                  "a4_projection": ("k_project_fast", "k_project_slow")}
 
 
