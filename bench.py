@@ -10,14 +10,19 @@ from 0.1 m onto a static 4 m ground quad with N(0, 0.5 m/s) random initial
 velocities, 20 iterations per step, dt = 1/120 s, r = xi = 1 mm; the timed
 region is its 60 steps from the initial state.
 
-value = dynamic vertices x iterations x steps / wall time of the timed region
-(each update is one vertex through candidates, regions and projection in one
-iteration; the stretch pass and the glue kernels are inside the timed time).
-The roofline object covers the single kernel with the largest share of GPU time;
-its duration is measured with HIP events on the stream in a second pass over the
-same steps, run as individual launches (stage events cannot be read back from
-inside a replayed graph).
-cpu_baseline times the FP64 oracle on a bounded sample of the same workload.
+value = dynamic vertices x solver iterations run / wall time of the timed
+region (each update is one vertex through candidates, regions and projection in
+one iteration; the stretch pass and the glue kernels are inside the timed
+time).  stage_rooflines gives every stage of the path (candidates, regions,
+projection) against the HBM peak, from HIP events on the stream in a second
+pass over the same steps run as individual launches (events cannot be read back
+from inside a replayed graph), with HBM traffic from the committed rocprofv3
+summary; roofline repeats the stage with the most time.  cpu_baseline times the
+FP64 oracle on a bounded sample of the same workload.  The default line also
+carries the coupled codimensional workload (coupled_c5) and the served request
+stream against one mesh at a time (served_c4).  Other workloads: --workload c0,
+c2, c3, c5, c4 (the served stream as the whole line), c1r (c1 with the soft
+response and friction), c2e (c2 with the convergence check).
 """
 from __future__ import annotations
 
@@ -62,6 +67,20 @@ def workload(name):
     elif name == "c2":
         sc = S.c2()
         desc = "c2: 10,000 pinned helical strands x 64 segments (650,000 vertices), edge-edge only"
+    elif name == "c1r":
+        from dataclasses import replace
+        sc = S.c1()
+        sc = replace(sc, params=replace(sc.params, delta=5e-4, response=True, resp_compliance=1e-6, vis_width=1e-4,
+                                        mu_s=0.4, mu_k=0.3))
+        desc = ("c1r: the c1 cloth with the soft response, visibility weights and friction of Sec. 3.3 before every "
+                "projection: delta = 0.5 mm (boxes padded by delta / 2 more), compliance 1e-6, visibility width "
+                "0.1 mm, mu_s = 0.4, mu_k = 0.3")
+    elif name == "c2e":
+        from dataclasses import replace
+        sc = S.c2()
+        sc = replace(sc, step=replace(sc.step, early_exit=True, conv_tol=1e-6))
+        desc = ("c2e: the c2 strands with the convergence check of Alg. 4: a substep's iterations end after the "
+                "first one in which no vertex falls short of its proposal by more than 1 um (at most 10)")
     elif name == "c5":
         sc = S.c5()
         desc = ("c5: coupled codimensional scene (13,612 vertices): floor, pinned two-layer rod lattice (32 rods x "
@@ -105,8 +124,9 @@ STAGE_KERNELS = {"a1_candidates": ("k_reset_build", "k_grid_count", "k_scan_redu
 
 
 # Speed knobs the autotuner chose per workload (bench.py --tune, on four steps
-# from the middle of the run); the default run times these.
-TUNED = S_BENCH_KNOBS
+# from the middle of the run); the default run times these.  The variants of a
+# workload with a row after the core path switched on take its knobs.
+TUNED = dict(S_BENCH_KNOBS, c1r=S_BENCH_KNOBS["c1"], c2e=S_BENCH_KNOBS["c2"])
 
 
 # rocprofv3 summaries of every kernel of a workload (per-dispatch durations,
@@ -385,7 +405,10 @@ def measure(args, name, profile=True):
 
     n_dyn = sc.n_dynamic
     iters = sc.step.iters
-    updates = n_dyn * iters * K
+    # solver iterations the timed steps ran (fewer than iters per step when
+    # the convergence check ends a step early)
+    iters_run = int(info.get("iterations_run") or iters * K)
+    updates = n_dyn * iters_run
     value = updates / wall
     tot = info["totals"]
     n_builds = max(tot[9], 1)
@@ -412,6 +435,7 @@ def measure(args, name, profile=True):
         "data": "synthetic",
         "config": {"workload": desc, "n_verts": sc.n_verts, "n_dynamic": n_dyn, "n_tris": sc.n_tris,
                    "n_edges": sc.n_edges, "iters_per_step": iters, "dt": sc.step.dt},
+        "iterations_run_per_step": iters_run / K,
         "p50_step_ms": float(np.percentile(step_ms, 50)),
         "p99_step_ms": float(np.percentile(step_ms, 99)),
         "gpu_ms_per_step": float(step_ms.mean()),

@@ -528,6 +528,8 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
             ra.dt = plan.dt;
             ra.prm = sc.prm;
             ra.skip = skip;
+            ra.list = ctx->slow_list;         // free until the projection lists its vertices
+            ra.c = ctx->counters_d;
             launch_response(ra, s);
         }
         mk.mark(4, 1);
@@ -545,12 +547,12 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
         pa.sort_key = ctx->sort_key;
         pa.sort_idx = ctx->sort_idx;
         pa.slow_list = ctx->slow_list;
-        pa.motion_max = adaptive ? &ctx->counters_d->motion_max : nullptr;
+        pa.motion_max = adaptive ? &ctx->counters_d->maxima[0][kMaxMotion] : nullptr;
         pa.slot_counts = ctx->vcount;
         pa.slot_stride = slots;
         pa.prm = sc.prm;
         pa.skip = skip;
-        pa.shortfall_max = plan.early_exit ? &ctx->counters_d->shortfall_max : nullptr;
+        pa.shortfall_max = plan.early_exit ? &ctx->counters_d->maxima[0][kMaxShortfall] : nullptr;
         pa.halt_run = ctx->halt_run;
         if (fold)   // the multipliers of the folded colour alternate between two arrays
             pa.sl = StretchLast{plan.last_edge, fold2 ? plan.prev_edge : nullptr, plan.rest_sorted,
@@ -996,8 +998,18 @@ int ccfr_apply_response(ccfr_ctx* ctx, const ccfr_regions* regions, const float*
     if ((!inv_mass_dev || !y_in_dev || !y_out_dev) && regions->n_verts > 0) return CCFR_ERR_INVALID_ARG;
     if (regions->n_verts < 0 || !regions->offsets || (regions->cap > 0 && !regions->hs) || regions->cap < 0)
         return CCFR_ERR_INVALID_ARG;
+    // the list of vertices with large regions needs room for every vertex
+    if (regions->n_verts > ctx->cap_verts) {
+        HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+        const long long gen = ctx->generation;
+        int rc = ensure_regions(ctx, regions->n_verts, 0, 0);
+        if (rc) return rc;
+        if (gen != ctx->generation) drop_graph(ctx);
+    }
     ResponseArgs ra{};
     ra.n_verts = regions->n_verts;
+    ra.list = ctx->slow_list;
+    ra.c = ctx->counters_d;
     ra.offsets = regions->offsets;
     ra.hs = regions->hs;
     ra.inv_mass = inv_mass_dev;

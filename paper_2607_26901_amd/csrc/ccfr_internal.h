@@ -61,24 +61,24 @@ struct DevCounters {
     int32_t last_nc;                   // contacts of the last closed region build
     int32_t last_pairs[4];             // VF, EE, VV, VE of the last closed candidate build
     // substeps whose candidate builds adapt to the motion: whether this
-    // iteration builds, the largest coordinate move of the last projection
-    // (FP32 bits, rounded up), and the moves summed since the last build
-    uint32_t rebuild, motion_max;
+    // iteration builds (the last projection's largest coordinate move is in
+    // maxima), and the moves summed since the last build
+    uint32_t rebuild, pad1;
     double motion_acc;
     // region builds into per-vertex slots: half-spaces written, and the largest
     // number any vertex received (beyond its slots they are dropped)
     int32_t n_hs, max_slot;
     long long builds;                  // candidate builds closed
     // the convergence check of a substep (evaluateConvergence of Alg. 4, with
-    // early exit): the largest shortfall |p - x| - |y*| of the last projection
-    // (FP32 bits, rounded up), whether the substep's iterations have ended,
-    // and the iterations run
-    uint32_t shortfall_max, converged;
+    // early exit): whether the substep's iterations have ended (the last
+    // projection's largest shortfall is in maxima), and the iterations run
+    uint32_t converged, pad2;
     long long iters_run;
     // consecutive halts of one vertex within a substep: the longest run seen,
     // and the halts that extended a run to 2 or to 3 and more
     int32_t max_halt_run, pad3;
     long long halt_runs[2];
+    int32_t n_resp, pad4;              // vertices whose response a wavefront takes (list)
     long long need[7];                 // max sizes seen: vf, ee, vv, contacts, hs, large, ve
     long long totals[11];              // vf, ee, vv, hs, violating, halted, degenerate, projected,
                                        // contacts, region builds, ve
@@ -86,7 +86,15 @@ struct DevCounters {
     // spread over 64 slots by block so that the atomics do not queue on one
     // address; the host adds them into totals[4], [5], [7]
     long long spread[3][64];
+    // the last projection's largest coordinate move (word kMaxMotion) and
+    // largest shortfall |p - x| - |y*| (word kMaxShortfall), FP32 bits rounded
+    // up, spread over 64 slots a cache line apart by block: the wavefronts of
+    // a launch would otherwise queue on one address.  The decision kernels
+    // take the maxima and clear the slots.
+    uint32_t maxima[64][32];
 };
+
+constexpr int kMaxMotion = 0, kMaxShortfall = 1;
 
 // Capacities of the four candidate lists.
 struct PairCaps {
@@ -172,6 +180,16 @@ __device__ __forceinline__ void reset_build_counters(DevCounters* c) {
 
 __device__ __forceinline__ void spread_add(DevCounters* c, int which, unsigned long long n) {
     atomicAdd((unsigned long long*)&c->spread[which][blockIdx.x & 63], n);
+}
+
+// Maximum of one word of the 64 maxima slots, which it clears; called by the
+// 64 lanes of one wavefront, after the launches that wrote the slots.
+__device__ __forceinline__ uint32_t take_maximum(DevCounters* c, int word) {
+    const int lane = threadIdx.x & 63;
+    uint32_t m = c->maxima[lane][word];
+    c->maxima[lane][word] = 0u;
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    return m;
 }
 
 // One binned entry of the grid: its padded box, index, flags and vertices (48 B).
@@ -499,7 +517,8 @@ struct ProjectArgs {
     double* sort_key;        // [cap_hs] scratch of regions larger than a wavefront sorts
     int32_t* sort_idx;       // [cap_hs]
     int32_t* slow_list;      // [n_verts] vertices with a violated half-space
-    uint32_t* motion_max;    // nullable: largest coordinate move of an anchor update (FP32 bits)
+    uint32_t* motion_max;    // nullable: slot words (32 apart) of the largest coordinate move of
+                             // an anchor update (FP32 bits); a block writes slot blockIdx & 63
     // regions in per-vertex slots (slot_stride > 0, offsets unused): vertex v's
     // half-spaces are hs[v * slot_stride ...] and slot_counts[v] of them; the
     // projection sets each count back to zero once it has read it
@@ -509,7 +528,8 @@ struct ProjectArgs {
     StretchLast sl;
     RestartJob next;         // the next iteration's stretch start, in extra blocks of the slow kernel
     const uint32_t* skip;    // nullable: return at once when *skip != 0
-    uint32_t* shortfall_max; // nullable: largest |proposal| - |result| (FP32 bits, rounded up)
+    uint32_t* shortfall_max; // nullable: slot words (as motion_max) of the largest
+                             // |proposal| - |result| (FP32 bits, rounded up)
     uint8_t* halt_run;       // nullable: per-vertex consecutive halts, updated with every result
 };
 // zero_counters: clear the slow-list counters first (the substep clears them
@@ -533,7 +553,11 @@ struct ResponseArgs {
     float dt;
     ParamSrc prm;
     const uint32_t* skip;
+    int32_t* list;                   // [n_verts] scratch: vertices with large regions
+    DevCounters* c;                  // its length (n_resp)
 };
+// One lane per vertex; a vertex with more than 32 half-spaces is listed and
+// taken by a wavefront in a second launch, and a third clears the list.
 void launch_response(const ResponseArgs& a, hipStream_t s);
 
 // halt_run (nullable): per-vertex consecutive-halt counts, cleared for the

@@ -220,13 +220,15 @@ __global__ void k_reset_build(DevCounters* c, uint32_t* level_mask, int n_meshes
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         reset_build_counters(c);
         c->rebuild = 1u;            // the first build of a substep or a standalone build
-        c->motion_max = 0u;
         c->motion_acc = 0.0;
         c->converged = 0u;          // a substep's iterations run until its convergence check ends them
-        c->shortfall_max = 0u;
     }
     for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n_meshes; m += gridDim.x * blockDim.x)
         level_mask[m] = 0u;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 64; k += gridDim.x * blockDim.x) {
+        c->maxima[k][kMaxMotion] = 0u;
+        c->maxima[k][kMaxShortfall] = 0u;
+    }
 }
 
 // Level and lower-corner cell of an entry (vertex entries: level 0, their box

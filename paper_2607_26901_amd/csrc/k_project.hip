@@ -324,19 +324,27 @@ __device__ __forceinline__ float wave_max(float x) {
     return x;
 }
 
-// Largest shortfall of a wavefront's vertices into the launch-wide maximum
-// (non-negative floats order like their bit patterns).
+// A wavefront's maximum into its block's slot of a launch-wide maximum of
+// non-negative floats (which order like their bit patterns).  A slot only
+// grows during a launch, so a wavefront whose value the slot already holds or
+// exceeds writes nothing.
+__device__ __forceinline__ void max_into(uint32_t* slots, float m) {
+    if (__lane_id() != 0 || !(m > 0.0f)) return;
+    uint32_t* word = slots + 32 * (blockIdx.x & 63);
+    const uint32_t bits = __float_as_uint(m);
+    if (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < bits) atomicMax(word, bits);
+}
+
+// Largest shortfall of a wavefront's vertices into the launch-wide maximum.
 __device__ __forceinline__ void record_shortfall(const ProjectArgs& a, float sf) {
     if (!a.shortfall_max) return;
-    const float m = wave_max(sf);
-    if (__lane_id() == 0 && m > 0.0f) atomicMax(a.shortfall_max, __float_as_uint(m));
+    max_into(a.shortfall_max, wave_max(sf));
 }
 
 // Largest move of a wavefront's lanes into the device maximum.
 __device__ __forceinline__ void record_motion(const ProjectArgs& a, float move) {
     if (!a.motion_max) return;
-    const float m = wave_max(move);
-    if (__lane_id() == 0 && m > 0.0f) atomicMax(a.motion_max, __float_as_uint(m));
+    max_into(a.motion_max, wave_max(move));
 }
 
 // The vertex's CSR range, clipped to the half-space buffer (an offset outside

@@ -4,7 +4,7 @@
 //
 // The response energy k/2 w_c max(0, delta - d_c)^2 is the XPBD constraint
 // C_c = max(0, delta - d_c) with compliance alpha = 1/k.  Constraints are
-// owned per vertex (Sec. 3.4), so one thread handles one vertex with no
+// owned per vertex (Sec. 3.4), so each vertex is handled on its own, with no
 // colouring:
 //   d_c = (n_c . y + d_c) / s_c     the pair's gap beyond the offset at the
 //                                   proposal y when both sides advance in
@@ -16,16 +16,27 @@
 //   along n_c, then friction (Macklin et al. 2014) on the tangential part t
 //   of the displacement: removed if |t| < mu_s dn, else shortened by mu_k dn.
 // The multiplier starts at zero every iteration (the constraint set is
-// rebuilt by every iteration's narrow phase).  The active contacts are found
-// again for every step of the ordered walk instead of being stored, so the
-// kernel keeps no per-vertex list; regions are small.  Arithmetic in FP64
-// registers from the FP32 region and proposal.
+// rebuilt by every iteration's narrow phase).  The gaps are taken at the
+// proposal, so the order and the weights are known before any update.  Only
+// contacts within delta_v of the innermost one can have a weight above zero
+// (the innermost one's factor for the others is 1 - S(1) = 0), and the factors
+// of a contact come from the contacts before it in the order.  Arithmetic in
+// FP64 registers from the FP32 region and proposal.
+//
+// Regions of up to kLaneK half-spaces: one lane, the relevant contacts sorted
+// in registers (up to kRel of them; more: an ordered walk).  Larger regions
+// are listed and taken by a wavefront each: every lane holds a slice of the
+// region, and each step selects the next contact by a wave-wide minimum and
+// forms its weight by a wave-wide product.
 #include "ccfr_internal.h"
 
 namespace ccfr {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kLaneK = 32;         // regions up to this size by one lane
+constexpr int kRel = 16;           // relevant contacts a lane sorts in registers
+constexpr int kChunks = 4;         // entries per lane of the wavefront path (256 per wavefront)
 
 __device__ __forceinline__ double smoothstep(double t) {
     if (t <= 0.0) return 0.0;
@@ -59,42 +70,82 @@ __device__ __forceinline__ double gap_of(const Plane& p, const double y0[3]) {
     return (dot3(p.n, y0) + p.d) / p.share;
 }
 
-__global__ __launch_bounds__(kBlock) void k_response(ResponseArgs a) {
-    if (a.skip && *a.skip) return;
-    const int v = blockIdx.x * kBlock + threadIdx.x;
-    if (v >= a.n_verts) return;
-    const MeshParams P = a.prm.get(a.prm.mesh_of(v));
-    float yf[3];
-    for (int k = 0; k < 3; ++k) yf[k] = a.y_in ? a.y_in[3 * v + k] : a.p[3 * v + k] - a.x_anchor[3 * v + k];
-    const double w = a.inv_mass[v];
-    int K = 0;
-    const ccfr_halfspace* H = nullptr;
+// Whether a contact at gap d may have a weight above zero: active, and, with
+// delta_v > 0, closer than delta_v to the innermost gap d_min (the ratio is
+// formed as in the weight, so a contact left out has weight 0).
+__device__ __forceinline__ bool relevant(double d, double d_min, double delta, double dv) {
+    return d < delta && (dv == 0.0 || (d - d_min) / dv < 1.0);
+}
+
+// One contact's update of y: its share of the XPBD correction of the response
+// constraint with weight wc, then friction on the tangential part.
+__device__ __forceinline__ void apply_contact(const MeshParams& P, double w, double dt, const Plane& p, double wc,
+                                              double y[3]) {
+    const double delta = P.delta;
+    const double rho = dot3(p.n, y) + p.d;
+    const double cv = p.share * delta - rho;
+    if (!(cv > 0.0)) return;
+    const double at = (double)P.resp_compliance / (wc * dt * dt);
+    const double dn = w * cv / (w + at);
+    for (int k = 0; k < 3; ++k) y[k] += dn * p.n[k];
+    if (P.mu_s > 0.0f || P.mu_k > 0.0f) {
+        const double yn = dot3(p.n, y);
+        const double t[3] = {y[0] - yn * p.n[0], y[1] - yn * p.n[1], y[2] - yn * p.n[2]};
+        const double lt = sqrt(dot3(t, t));
+        double f = 0.0;
+        if (lt < (double)P.mu_s * dn) f = 1.0;
+        else if (lt > 0.0) f = fmin((double)P.mu_k * dn / lt, 1.0);
+        for (int k = 0; k < 3; ++k) y[k] -= f * t[k];
+    }
+}
+
+struct Vertex {
+    MeshParams P;
+    float yf[3];          // the proposal
+    double w;
+    int K;
+    const ccfr_halfspace* H;
+    bool idle;            // nothing to do: the proposal is the result
+};
+
+__device__ __forceinline__ Vertex vertex_of(const ResponseArgs& a, int v) {
+    Vertex x;
+    x.P = a.prm.get(a.prm.mesh_of(v));
+    for (int k = 0; k < 3; ++k) x.yf[k] = a.y_in ? a.y_in[3 * v + k] : a.p[3 * v + k] - a.x_anchor[3 * v + k];
+    x.w = a.inv_mass[v];
     if (a.slot_stride > 0) {
-        K = min(a.slot_counts[v], a.slot_stride);
-        H = a.hs + (long long)v * a.slot_stride;
+        x.K = min(a.slot_counts[v], a.slot_stride);
+        x.H = a.hs + (long long)v * a.slot_stride;
     } else {
-        K = a.offsets[v + 1] - a.offsets[v];
-        H = a.hs + a.offsets[v];
+        x.K = a.offsets[v + 1] - a.offsets[v];
+        x.H = a.hs + a.offsets[v];
     }
-    if (!(w > 0.0) || !P.response || K == 0 || !(P.delta > 0.0f) ||
-        !(isfinite(yf[0]) && isfinite(yf[1]) && isfinite(yf[2]))) {
-        if (a.y_out)
-            for (int k = 0; k < 3; ++k) a.y_out[3 * v + k] = yf[k];
-        return;
+    x.idle = !(x.w > 0.0) || !x.P.response || x.K == 0 || !(x.P.delta > 0.0f) ||
+             !(isfinite(x.yf[0]) && isfinite(x.yf[1]) && isfinite(x.yf[2]));
+    return x;
+}
+
+__device__ __forceinline__ void write_out(const ResponseArgs& a, int v, const double y[3]) {
+    if (a.y_out) {
+        for (int k = 0; k < 3; ++k) a.y_out[3 * v + k] = (float)y[k];
+    } else {
+        for (int k = 0; k < 3; ++k) a.p[3 * v + k] = a.x_anchor[3 * v + k] + (float)y[k];
     }
-    const double y0[3] = {yf[0], yf[1], yf[2]};
-    const double delta = P.delta, dv = P.vis_width, dt = a.dt;
-    double y[3] = {y0[0], y0[1], y0[2]};
+}
+
+// The ordered walk over a region: the next active contact in (gap, key) order
+// is found again for every step.
+__device__ void ordered_walk(const Vertex& x, double dt, const double y0[3], double y[3]) {
+    const double delta = x.P.delta, dv = x.P.vis_width;
     double last_d = -__longlong_as_double(0x7ff0000000000000ll);
     uint64_t last_key = 0;
     bool first = true;
     for (;;) {
-        // the next active contact in (gap, key) order
         int c = -1;
         double dc = 0.0;
         uint64_t kc = 0;
-        for (int k = 0; k < K; ++k) {
-            const Plane p = plane_at(H, k);
+        for (int k = 0; k < x.K; ++k) {
+            const Plane p = plane_at(x.H, k);
             const double d = gap_of(p, y0);
             if (!(d < delta)) continue;
             const bool after = first || d > last_d || (d == last_d && p.key > last_key);
@@ -109,37 +160,200 @@ __global__ __launch_bounds__(kBlock) void k_response(ResponseArgs a) {
         first = false;
         last_d = dc;
         last_key = kc;
-        // its visibility weight over the other active contacts
         double wc = 1.0;
         if (dv > 0.0)
-            for (int j = 0; j < K; ++j) {
+            for (int j = 0; j < x.K; ++j) {
                 if (j == c) continue;
-                const double dj = gap_of(plane_at(H, j), y0);
+                const double dj = gap_of(plane_at(x.H, j), y0);
                 if (dj < delta) wc *= 1.0 - smoothstep((dc - dj) / dv);
             }
         if (!(wc > 0.0)) continue;
-        const Plane p = plane_at(H, c);
-        const double rho = dot3(p.n, y) + p.d;
-        const double cv = p.share * delta - rho;
-        if (!(cv > 0.0)) continue;
-        const double at = (double)P.resp_compliance / (wc * dt * dt);
-        const double dn = w * cv / (w + at);
-        for (int k = 0; k < 3; ++k) y[k] += dn * p.n[k];
-        if (P.mu_s > 0.0f || P.mu_k > 0.0f) {
-            const double yn = dot3(p.n, y);
-            const double t[3] = {y[0] - yn * p.n[0], y[1] - yn * p.n[1], y[2] - yn * p.n[2]};
-            const double lt = sqrt(dot3(t, t));
-            double f = 0.0;
-            if (lt < (double)P.mu_s * dn) f = 1.0;
-            else if (lt > 0.0) f = fmin((double)P.mu_k * dn / lt, 1.0);
-            for (int k = 0; k < 3; ++k) y[k] -= f * t[k];
+        apply_contact(x.P, x.w, dt, plane_at(x.H, c), wc, y);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_response(ResponseArgs a) {
+    if (a.skip && *a.skip) return;
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    const bool in = v < a.n_verts;
+    Vertex x{};
+    if (in) x = vertex_of(a, v);
+    // large regions go to the wavefront launch (one atomic per wavefront)
+    const bool listed = in && !x.idle && x.K > kLaneK && a.list;
+    const unsigned long long m = __ballot(listed);
+    if (m) {
+        const int lead = __ffsll((long long)m) - 1;
+        int base = 0;
+        if (__lane_id() == lead) base = atomicAdd(&a.c->n_resp, __popcll(m));
+        base = __shfl(base, lead);
+        if (listed) a.list[base + __popcll(m & ((1ull << __lane_id()) - 1ull))] = v;
+    }
+    if (!in || listed) return;
+    if (x.idle) {
+        if (a.y_out)
+            for (int k = 0; k < 3; ++k) a.y_out[3 * v + k] = x.yf[k];
+        return;
+    }
+    const double y0[3] = {x.yf[0], x.yf[1], x.yf[2]};
+    const double delta = x.P.delta, dv = x.P.vis_width, dt = a.dt;
+    double y[3] = {y0[0], y0[1], y0[2]};
+    double d_min = __longlong_as_double(0x7ff0000000000000ll);
+    for (int k = 0; k < x.K; ++k) {
+        const double d = gap_of(plane_at(x.H, k), y0);
+        if (d < delta) d_min = fmin(d_min, d);
+    }
+    // the relevant contacts, sorted by (gap, key) in registers (constant
+    // indices keep the arrays there)
+    double rd[kRel];
+    uint64_t rk[kRel];
+    int ri[kRel];
+    int n_rel = 0;
+    bool overflow = false;
+    for (int k = 0; k < x.K; ++k) {
+        const Plane p = plane_at(x.H, k);
+        const double d = gap_of(p, y0);
+        if (!relevant(d, d_min, delta, dv)) continue;
+        if (n_rel == kRel) {
+            overflow = true;
+            break;
+        }
+        int pos = n_rel;
+#pragma unroll
+        for (int q = kRel - 1; q >= 0; --q)
+            if (q < n_rel && (rd[q] > d || (rd[q] == d && rk[q] > p.key))) pos = q;
+#pragma unroll
+        for (int q = kRel - 1; q > 0; --q)
+            if (q > pos && q <= n_rel) {
+                rd[q] = rd[q - 1];
+                rk[q] = rk[q - 1];
+                ri[q] = ri[q - 1];
+            }
+#pragma unroll
+        for (int q = 0; q < kRel; ++q)
+            if (q == pos) {
+                rd[q] = d;
+                rk[q] = p.key;
+                ri[q] = k;
+            }
+        ++n_rel;
+    }
+    if (overflow) {
+        ordered_walk(x, dt, y0, y);
+    } else {
+#pragma unroll
+        for (int c = 0; c < kRel; ++c) {
+            if (c >= n_rel) break;
+            // the factors of the contacts before it (equal gaps give 1)
+            double wc = 1.0;
+            if (dv > 0.0)
+#pragma unroll
+                for (int j = 0; j < kRel; ++j)
+                    if (j < c) wc *= 1.0 - smoothstep((rd[c] - rd[j]) / dv);
+            if (!(wc > 0.0)) continue;
+            apply_contact(x.P, x.w, dt, plane_at(x.H, ri[c]), wc, y);
         }
     }
-    if (a.y_out) {
-        for (int k = 0; k < 3; ++k) a.y_out[3 * v + k] = (float)y[k];
-    } else {
-        for (int k = 0; k < 3; ++k) a.p[3 * v + k] = a.x_anchor[3 * v + k] + (float)y[k];
+    write_out(a, v, y);
+}
+
+__device__ __forceinline__ double wave_min(double x) {
+    for (int off = 32; off > 0; off >>= 1) x = fmin(x, __shfl_xor(x, off));
+    return x;
+}
+
+__device__ __forceinline__ double wave_prod(double x) {
+    for (int off = 32; off > 0; off >>= 1) x *= __shfl_xor(x, off);
+    return x;
+}
+
+// One listed vertex by one wavefront (every lane runs it; y is the same on all).
+__device__ void response_wave_vertex(const ResponseArgs& a, int v) {
+    const int lane = __lane_id();
+    const Vertex x = vertex_of(a, v);
+    const double y0[3] = {x.yf[0], x.yf[1], x.yf[2]};
+    const double delta = x.P.delta, dv = x.P.vis_width, dt = a.dt;
+    double y[3] = {y0[0], y0[1], y0[2]};
+    if (x.K > 64 * kChunks) {
+        // beyond the wavefront's registers: one lane walks the region
+        if (lane == 0) {
+            ordered_walk(x, dt, y0, y);
+            write_out(a, v, y);
+        }
+        return;
     }
+    double g[kChunks];
+    uint64_t key[kChunks];
+    bool rel[kChunks], done[kChunks];
+    double d_min = __longlong_as_double(0x7ff0000000000000ll);
+#pragma unroll
+    for (int ch = 0; ch < kChunks; ++ch) {
+        const int j = ch * 64 + lane;
+        g[ch] = __longlong_as_double(0x7ff0000000000000ll);
+        key[ch] = ~0ull;
+        if (j < x.K) {
+            const Plane p = plane_at(x.H, j);
+            g[ch] = gap_of(p, y0);
+            key[ch] = p.key;
+            if (g[ch] < delta) d_min = fmin(d_min, g[ch]);
+        }
+    }
+    d_min = wave_min(d_min);
+#pragma unroll
+    for (int ch = 0; ch < kChunks; ++ch) {
+        rel[ch] = ch * 64 + lane < x.K && relevant(g[ch], d_min, delta, dv);
+        done[ch] = false;
+    }
+    for (;;) {
+        // the next relevant contact in (gap, key) order: the lane's own first,
+        // then the wave-wide minimum (gaps first, then keys among equal gaps)
+        double bg = __longlong_as_double(0x7ff0000000000000ll);
+        uint64_t bk = ~0ull;
+        int bj = -1;
+#pragma unroll
+        for (int ch = 0; ch < kChunks; ++ch)
+            if (rel[ch] && !done[ch] && (g[ch] < bg || (g[ch] == bg && key[ch] < bk))) {
+                bg = g[ch];
+                bk = key[ch];
+                bj = ch * 64 + lane;
+            }
+        const double gmin = wave_min(bg);
+        if (!(gmin < delta)) break;                    // no relevant contact left
+        const bool tie = bj >= 0 && bg == gmin;
+        uint64_t km = tie ? bk : ~0ull;
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint64_t o = __shfl_xor(km, off);
+            km = o < km ? o : km;
+        }
+        const unsigned long long owner = __ballot(tie && bk == km);
+        const int src = __ffsll((long long)owner) - 1;
+        const int c = __shfl(bj, src);
+        // its weight: the factors of the relevant contacts before it
+        double f = 1.0;
+        if (dv > 0.0)
+#pragma unroll
+            for (int ch = 0; ch < kChunks; ++ch)
+                if (rel[ch] && g[ch] < gmin) f *= 1.0 - smoothstep((gmin - g[ch]) / dv);
+        const double wc = dv > 0.0 ? wave_prod(f) : 1.0;
+        if (lane == src) {
+#pragma unroll
+            for (int ch = 0; ch < kChunks; ++ch)
+                if (ch * 64 + lane == c) done[ch] = true;
+        }
+        if (wc > 0.0) apply_contact(x.P, x.w, dt, plane_at(x.H, c), wc, y);
+    }
+    if (lane == 0) write_out(a, v, y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_response_waves(ResponseArgs a, int waves) {
+    if (a.skip && *a.skip) return;
+    const int n = a.c->n_resp;
+    for (int i = blockIdx.x * (kBlock / 64) + threadIdx.x / 64; i < n; i += waves)
+        response_wave_vertex(a, a.list[i]);
+}
+
+__global__ void k_response_clear(DevCounters* c, const uint32_t* skip) {
+    if (skip && *skip) return;
+    if (threadIdx.x == 0) c->n_resp = 0;
 }
 
 }  // namespace
@@ -147,6 +361,12 @@ __global__ __launch_bounds__(kBlock) void k_response(ResponseArgs a) {
 void launch_response(const ResponseArgs& a, hipStream_t s) {
     if (a.n_verts <= 0) return;
     hipLaunchKernelGGL(k_response, dim3((a.n_verts + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+    if (!a.list || !a.c) return;
+    // the list's length is known on the device only: a wavefront per 64
+    // vertices, at most 4096, which take the listed vertices in turn
+    const int blocks = std::max(1, std::min(1024, (a.n_verts + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_response_waves, dim3(blocks), dim3(kBlock), 0, s, a, blocks * (kBlock / 64));
+    hipLaunchKernelGGL(k_response_clear, dim3(1), dim3(64), 0, s, a.c, a.skip);
 }
 
 }  // namespace ccfr

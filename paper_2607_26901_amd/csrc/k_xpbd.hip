@@ -73,14 +73,17 @@ __global__ __launch_bounds__(kBlock) void k_close_iteration(const float* x_pred,
     restart_pass(x_pred, p, n3, c0, i);
 }
 
-// One block.  Thread 0 decides (only it reads and writes the motion fields);
-// the block then clears the level masks of a build to come.
+// One block.  The first wavefront takes the last projection's largest move,
+// thread 0 decides (only it reads and writes the motion fields); the block
+// then clears the level masks of a build to come.
 __global__ __launch_bounds__(kBlock) void k_decide_build(DevCounters* c, uint32_t* level_mask, int n_meshes,
                                                          double skin, PairCaps caps, const uint32_t* skip) {
     if (skip && *skip) return;
     __shared__ int go;
+    uint32_t moved = 0u;
+    if (threadIdx.x < 64) moved = take_maximum(c, kMaxMotion);
     if (threadIdx.x == 0) {
-        const double acc = c->motion_acc + (double)__uint_as_float(c->motion_max);
+        const double acc = c->motion_acc + (double)__uint_as_float(moved);
         // the sum is rounded: compare with a relative margin far above its error
         const bool rebuild = acc * (1.0 + 1e-12) > skin;
         if (rebuild) {
@@ -89,7 +92,6 @@ __global__ __launch_bounds__(kBlock) void k_decide_build(DevCounters* c, uint32_
             c->n_large_t = c->n_large_e = 0;
         }
         c->motion_acc = rebuild ? 0.0 : acc;
-        c->motion_max = 0u;
         c->rebuild = rebuild ? 1u : 0u;
         go = rebuild ? 1 : 0;
     }
@@ -98,15 +100,16 @@ __global__ __launch_bounds__(kBlock) void k_decide_build(DevCounters* c, uint32_
         for (int m = threadIdx.x; m < n_meshes; m += kBlock) level_mask[m] = 0u;
 }
 
-// evaluateConvergence (Alg. 4), one thread: the iterations of the substep end
-// once no dynamic vertex's last step fell short of its proposal by more than
-// tol (reading of the check: the expected advancement of an iteration is the
-// proposal p - x, the step taken is the projected and clamped y*).
+// evaluateConvergence (Alg. 4), one wavefront: the iterations of the substep
+// end once no dynamic vertex's last step fell short of its proposal by more
+// than tol (reading of the check: the expected advancement of an iteration is
+// the proposal p - x, the step taken is the projected and clamped y*).
 __global__ void k_decide_converged(DevCounters* c, float tol, int first) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (blockIdx.x != 0 || threadIdx.x >= 64) return;
+    const uint32_t shortfall = take_maximum(c, kMaxShortfall);
+    if (threadIdx.x != 0) return;
     if (first) c->converged = 0u;
-    else if (!c->converged && __uint_as_float(c->shortfall_max) <= tol) c->converged = 1u;
-    c->shortfall_max = 0u;
+    else if (!c->converged && __uint_as_float(shortfall) <= tol) c->converged = 1u;
     if (!c->converged) c->iters_run += 1;
 }
 

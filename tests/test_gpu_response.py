@@ -108,3 +108,56 @@ def test_response_substep_parity_and_no_penetration(env):
                 compared += 1
             assert np.abs(sim.x - plain.x).max() > 1e-6      # the response changed the step
     assert compared == 1
+
+
+@pytest.mark.parametrize("vis", [0.0, 0.5e-3, 2e-3])
+@pytest.mark.parametrize("alpha", [0.0, 1e-6])
+def test_apply_response_many_active_contacts(env, vis, alpha):
+    """Vertices with 2 to 300 active contacts: regions a lane takes (sorted in
+    registers, or walked in order past 16 relevant contacts), regions a
+    wavefront takes (33 to 256) and one beyond the wavefront's registers;
+    random normals, gaps inside the repulsion range with ties, several
+    visibility widths (0: every weight 1) and compliances, against the oracle
+    vertex by vertex on the same FP32 regions."""
+    ctx, ccfr, oracle, torch = env
+    from paper_2607_26901_amd import scenes as S
+    rng = np.random.default_rng(31)
+    sizes = [2, 5, 15, 16, 17, 24, 33, 40, 70, 256, 300]
+    delta = 1e-3
+    prm = S.Params(r=2e-3, xi=1e-3, delta=delta, response=True, resp_compliance=alpha, vis_width=vis,
+                   mu_s=0.4, mu_k=0.3)
+    recs, off = [], [0]
+    for v, K in enumerate(sizes):
+        n = rng.normal(size=(K, 3))
+        n /= np.linalg.norm(n, axis=1, keepdims=True)
+        share = rng.uniform(0.2, 1.0, K)
+        gap = rng.uniform(0.0, 0.9 * delta, K)
+        gap[K // 2:] = gap[0]                      # ties of the gap
+        h = np.zeros(K, ccfr.HALFSPACE_DTYPE)
+        h["n"] = n.astype(np.float32)
+        h["share"] = share.astype(np.float32)
+        h["d"] = (share * gap).astype(np.float32)  # d = s * gap at y = 0
+        h["phi"] = h["d"] / h["share"]
+        h["key"] = (np.uint64(2) << np.uint64(62)) | (np.uint64(v) << np.uint64(31)) | np.arange(K, dtype=np.uint64)
+        recs.append(h)
+        off.append(off[-1] + K)
+    hs32 = np.concatenate(recs)
+    off = np.asarray(off, np.int32)
+    nv = len(sizes)
+    w = rng.uniform(0.5, 2.0, nv).astype(np.float32)
+    y = (rng.normal(0.0, 0.3e-3, (nv, 3))).astype(np.float32)
+    regions = ccfr.caller_regions(torch.from_numpy(off).cuda(), torch.from_numpy(hs32.view(np.uint8)).cuda())
+    y_t = torch.from_numpy(y).cuda()
+    out = torch.empty_like(y_t)
+    dt = float(np.float32(1.0 / 120.0))
+    ccfr.apply_response(ctx, regions, torch.from_numpy(w).cuda(), y_t, ccfr.make_params(prm), dt, out)
+    torch.cuda.synchronize()
+    assert ctx.sync_status(reset=True)[0] == 0
+    yg = out.cpu().numpy().astype(np.float64)
+    _, hs_w = H.to_oracle_halfspaces(off, hs32)
+    moved = 0
+    for v in range(nv):
+        yo = oracle.apply_response(prm, float(w[v]), hs_w[off[v]:off[v + 1]], dt, y[v].astype(np.float64))
+        assert np.abs(yg[v] - yo).max() <= 1e-9, (v, sizes[v], yg[v], yo)
+        moved += np.abs(yo - y[v]).max() > 1e-9
+    assert moved >= nv // 2
