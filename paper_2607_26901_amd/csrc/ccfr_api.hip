@@ -158,7 +158,7 @@ int ensure_regions(ccfr_ctx* ctx, long long n_verts, long long contacts, long lo
         dev_free(ctx->slow_list);
         HIP_ALLOC(dev_alloc(&ctx->vcount, n_verts));
         HIP_ALLOC(dev_alloc(&ctx->offsets, n_verts + 1));
-        HIP_ALLOC(dev_alloc(&ctx->slow_list, n_verts));
+        HIP_ALLOC(dev_alloc(&ctx->slow_list, 2 * n_verts));
         HIP_OK(hipMemset(ctx->vcount, 0, sizeof(int32_t) * (size_t)n_verts));
         const long long ntmp = (n_verts + 1023) / 1024 + 2;
         if (ntmp > ctx->cap_scan_tmp) {

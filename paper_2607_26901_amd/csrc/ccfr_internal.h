@@ -78,7 +78,8 @@ struct DevCounters {
     // and the halts that extended a run to 2 or to 3 and more
     int32_t max_halt_run, pad3;
     long long halt_runs[2];
-    int32_t n_resp, pad4;              // vertices whose response a wavefront takes (list)
+    int32_t n_resp;                    // vertices whose response a wavefront takes (list)
+    int32_t n_viol_m;                  // deferred vertices with mid-size regions (second half of the slow list)
     long long need[7];                 // max sizes seen: vf, ee, vv, contacts, hs, large, ve
     long long totals[11];              // vf, ee, vv, hs, violating, halted, degenerate, projected,
                                        // contacts, region builds, ve
@@ -148,6 +149,7 @@ __device__ __forceinline__ void reset_region_counters(DevCounters* c) {
     c->n_contacts = 0;
     c->n_viol = 0;
     c->n_viol_b = 0;
+    c->n_viol_m = 0;
     c->n_hs = 0;
     c->max_slot = 0;
 }
@@ -516,7 +518,9 @@ struct ProjectArgs {
     uint8_t* halted;
     double* sort_key;        // [cap_hs] scratch of regions larger than a wavefront sorts
     int32_t* sort_idx;       // [cap_hs]
-    int32_t* slow_list;      // [n_verts] vertices with a violated half-space
+    int32_t* slow_list;      // [2 n_verts] vertices with a violated half-space: small regions from
+                             // the front, large ones from the back of the first half, mid-size
+                             // ones in the second half
     uint32_t* motion_max;    // nullable: slot words (32 apart) of the largest coordinate move of
                              // an anchor update (FP32 bits); a block writes slot blockIdx & 63
     // regions in per-vertex slots (slot_stride > 0, offsets unused): vertex v's

@@ -22,8 +22,8 @@ namespace {
 constexpr long long kNaMaxVerts = 1LL << 20;   // vertices per call
 constexpr long long kNaMaxHs = 1LL << 22;      // half-spaces (regions->cap) per call
 constexpr size_t kNaCounters = (sizeof(DevCounters) + 255) / 256 * 256;
-constexpr size_t kNaSlowList = kNaCounters;                                  // int32 [kNaMaxVerts]
-constexpr size_t kNaSortKey = kNaSlowList + 4 * (size_t)kNaMaxVerts;         // double [kNaMaxHs]
+constexpr size_t kNaSlowList = kNaCounters;                                  // int32 [2 kNaMaxVerts]
+constexpr size_t kNaSortKey = kNaSlowList + 8 * (size_t)kNaMaxVerts;         // double [kNaMaxHs]
 constexpr size_t kNaSortIdx = kNaSortKey + 8 * (size_t)kNaMaxHs;             // int32 [kNaMaxHs]
 constexpr size_t kNaBytes = kNaSortIdx + 4 * (size_t)kNaMaxHs;
 constexpr int kNaDevices = 64;

@@ -14,9 +14,9 @@
 // pass); a vertex with exactly one violated half-space whose projection leaves
 // every other one satisfied returns that projection (the first two passes of
 // Alg. 2, which need no sort in that case).  All other vertices are compacted
-// into a list for the slow kernel: their half-spaces are sorted by initial rho
-// ascending, ties by key (in registers up to 8, by a wavefront in LDS up to 256,
-// in a scratch range parallel to the CSR range beyond), exact duplicates
+// into lists for the slow kernel: their half-spaces are sorted by initial rho
+// ascending, ties by key (by one lane in registers up to 16, by a wavefront in
+// LDS up to 256, in a scratch range parallel to the CSR range beyond), exact duplicates
 // (bitwise-equal n and d) are dropped, then up to max_passes passes of Alg. 1
 // over the violated ones, each followed by the retraction by eps; a pass without
 // violation returns its start point, and otherwise the vertex halts at y = 0.
@@ -35,6 +35,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kSmall = 8;      // regions up to this size stay in registers
+constexpr int kMid = 16;       // up to this size a violated region is projected by one lane
 constexpr int kScan = 32;      // up to this size the fast kernel checks for a violation
 constexpr int kWave = 256;     // up to this size a wavefront sorts them in LDS
 
@@ -439,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
     if (a.skip && *a.skip) return;                 // the substep's iterations have ended
     const int v = blockIdx.x * kBlock + threadIdx.x;
     const bool active = v < a.n_verts;
-    bool violated = false, deferred = false, big = false, moved = false, bad = false;
+    bool violated = false, deferred = false, big = false, mid = false, moved = false, bad = false;
     float move = 0.0f, sf = 0.0f;
     d3 ykeep = mk(0.0, 0.0, 0.0);
     if (active) {
@@ -471,6 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
                     for (int k = 0; k < 4; ++k) any = any || (k0 + k < K && rho_at(R4[k], yprop) < 0.0);
                 }
                 deferred = any;
+                mid = any && K <= kMid;          // one lane of the slow kernel takes it
                 if (!deferred) move = write_result(a, c, v, yprop, (double)P.r, false, norm(yprop), sf);
             } else {
                 float4 R[kSmall];
@@ -504,48 +506,52 @@ __global__ __launch_bounds__(kBlock) void k_project_fast(ProjectArgs a, DevCount
     }
     record_motion(a, move);
     record_shortfall(a, sf);
-    // vertices that need the full Alg. 2 go to the slow list, one atomic per
-    // block and list: small regions from the front, larger ones from the back
+    // vertices that need the full Alg. 2 go to the slow lists, one atomic per
+    // block and list: small regions from the front of the first half, large
+    // ones from its back, mid-size ones into the second half (the slow kernel
+    // counts the violating vertices of the two latter lists).
     const unsigned long long md = __ballot(deferred && !big);
-    const unsigned long long mb = __ballot(deferred && big);
+    const unsigned long long mb = __ballot(deferred && big && !mid);
+    const unsigned long long mi = __ballot(mid);
     const unsigned long long mv = __ballot(violated);
     const unsigned long long mm = __ballot(moved);
     const int lane = __lane_id();
     if (__ballot(bad) && lane == 0) atomicOr(&c->status, ST_NONFINITE);
     const int wave = threadIdx.x / 64;
     constexpr int kW = kBlock / 64;
-    __shared__ int pre[kW][2];
+    __shared__ int pre[kW][3];
     __shared__ int tally[kW][2];
-    __shared__ int bases[2];
+    __shared__ int bases[3];
     if (lane == 0) {
         pre[wave][0] = __popcll(md);
         pre[wave][1] = __popcll(mb);
+        pre[wave][2] = __popcll(mi);
         tally[wave][0] = __popcll(mv);
         tally[wave][1] = __popcll(mm);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int acc0 = 0, acc1 = 0, nv = 0, nm = 0;
+        int acc[3] = {0, 0, 0}, nv = 0, nm = 0;
         for (int w = 0; w < kW; ++w) {
-            const int t0 = pre[w][0], t1 = pre[w][1];
-            pre[w][0] = acc0;
-            pre[w][1] = acc1;
-            acc0 += t0;
-            acc1 += t1;
+            for (int l = 0; l < 3; ++l) {
+                const int t = pre[w][l];
+                pre[w][l] = acc[l];
+                acc[l] += t;
+            }
             nv += tally[w][0];
             nm += tally[w][1];
         }
-        bases[0] = acc0 ? atomicAdd(&c->n_viol, acc0) : 0;
-        bases[1] = acc1 ? atomicAdd(&c->n_viol_b, acc1) : 0;
+        bases[0] = acc[0] ? atomicAdd(&c->n_viol, acc[0]) : 0;
+        bases[1] = acc[1] ? atomicAdd(&c->n_viol_b, acc[1]) : 0;
+        bases[2] = acc[2] ? atomicAdd(&c->n_viol_m, acc[2]) : 0;
         if (nv) spread_add(c, 0, (unsigned long long)nv);
         if (nm) spread_add(c, 2, (unsigned long long)nm);
     }
     __syncthreads();
-    const int base = bases[0] + pre[wave][0];
-    const int base_b = bases[1] + pre[wave][1];
     const unsigned long long lt = (1ull << lane) - 1ull;
-    if (deferred && !big) a.slow_list[base + __popcll(md & lt)] = v;
-    if (deferred && big) a.slow_list[a.n_verts - 1 - (base_b + __popcll(mb & lt))] = v;
+    if (deferred && !big) a.slow_list[bases[0] + pre[wave][0] + __popcll(md & lt)] = v;
+    if (deferred && big && !mid) a.slow_list[a.n_verts - 1 - (bases[1] + pre[wave][1] + __popcll(mb & lt))] = v;
+    if (mid) a.slow_list[a.n_verts + bases[2] + pre[wave][2] + __popcll(mi & lt)] = v;
 }
 
 // ---- slow path: one lane per listed vertex; bigger regions cooperatively ----
@@ -563,6 +569,10 @@ __device__ __forceinline__ bool before(double ra, uint64_t ka, double rb, uint64
         float4 tn = R[i]; R[i] = R[j]; R[j] = tn;                                   \
     }
 
+// A region of at most 8 half-spaces projected by one lane: the records in
+// registers (every index a constant after unrolling), sorted by (rho, key)
+// with Batcher's odd-even merge sort, exact duplicates after the first of
+// their rho run dropped, then Alg. 2's passes.
 __device__ bool project_small(const ccfr_halfspace* H, int K, const d3 yprop, const MeshParams& P, d3& yres) {
     float4 R[kSmall];
     uint64_t key[kSmall];
@@ -611,6 +621,75 @@ __device__ bool project_small(const ccfr_halfspace* H, int K, const d3 yprop, co
     return run_passes(K, get, yprop, P, yres);
 }
 #undef CE
+
+// A region of kSmall < K <= kMid half-spaces projected by one lane.  Only
+// (rho, index) pairs go through the sorting network (a bitonic one, every
+// index a constant after unrolling); the keys that break ties of rho are read
+// from memory when a tie occurs, and the records are gathered in sorted order
+// afterwards, so the sort holds 3 registers per entry instead of 8.  Keys are
+// unique within a region, so the order is that of the other paths; duplicates
+// and passes as in project_small.
+__device__ __forceinline__ uint64_t key_at(const ccfr_halfspace* H, int K, int q) {
+    return q < K ? H[q].key : ~0ull;
+}
+
+#define CEI(i, j)                                                                            \
+    {                                                                                        \
+        bool sw = rho[j] < rho[i];                                                           \
+        if (rho[j] == rho[i]) sw = key_at(H, K, idx[j]) < key_at(H, K, idx[i]);              \
+        if (sw) {                                                                            \
+            const double tr = rho[i]; rho[i] = rho[j]; rho[j] = tr;                          \
+            const int ti = idx[i]; idx[i] = idx[j]; idx[j] = ti;                             \
+        }                                                                                    \
+    }
+
+__device__ bool project_mid(const ccfr_halfspace* H, int K, const d3 yprop, const MeshParams& P, d3& yres) {
+    double rho[kMid];
+    int idx[kMid];
+#pragma unroll
+    for (int j = 0; j < kMid; ++j) {
+        idx[j] = j;
+        rho[j] = j < K ? rho_at(load_plane(H + j), yprop) : __longlong_as_double(0x7ff0000000000000ll);
+    }
+#pragma unroll
+    for (int size = 2; size <= kMid; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+            for (int i = 0; i < kMid; ++i) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    if ((i & size) == 0) CEI(i, j) else CEI(j, i)
+                }
+            }
+        }
+    }
+    float4 R[kMid];
+#pragma unroll
+    for (int j = 0; j < kMid; ++j)    // (a NaN rho can leave padding before K: the index is clamped)
+        R[j] = j < K ? load_plane(H + min(idx[j], K - 1)) : make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t drop = 0u;
+#pragma unroll
+    for (int j = 1; j < kMid; ++j) {
+        bool dj = false;
+#pragma unroll
+        for (int i = 0; i < j; ++i)
+            dj = dj || (rho[i] == rho[j] && R[i].x == R[j].x && R[i].y == R[j].y && R[i].z == R[j].z &&
+                        R[i].w == R[j].w);
+        if (dj) drop |= 1u << j;
+    }
+    auto get = [&](int q, d3& n, double& d) -> bool {
+#pragma unroll
+        for (int j = 0; j < kMid; ++j)
+            if (j == q) {
+                n = mk(R[j].x, R[j].y, R[j].z);
+                d = (double)R[j].w;
+            }
+        return ((drop >> q) & 1u) == 0u;
+    };
+    return run_passes(K, get, yprop, P, yres);
+}
+#undef CEI
 
 struct WaveLds {
     float4 rec[kWave];
@@ -819,59 +898,85 @@ __device__ __forceinline__ float project_wave_vertex(const ProjectArgs& a, DevCo
     return move;
 }
 
-// Both slow lists in one launch.  Blocks [0, wave_blocks) run list B (larger
-// regions), one vertex per wavefront, first, since their vertices take the
-// longest; the remaining blocks run list A (regions of at most kSmall
-// half-spaces), one lane per vertex, the sort and the passes in registers.
-__global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCounters* c, int wave_blocks,
-                                                         int lane_blocks) {
-    if (a.skip && *a.skip) return;
-    __shared__ WaveLds lds[kBlock / 64];
-    if ((int)blockIdx.x >= wave_blocks + lane_blocks) {
-        // the next iteration's stretch start: the slow path reads no p
-        restart_pass(a.next.x_pred, a.next.p, a.next.n3, a.next.c0,
-                     (long long)(blockIdx.x - wave_blocks - lane_blocks) * kBlock + threadIdx.x);
-        return;
-    }
-    if ((int)blockIdx.x < wave_blocks) {
-        const int wave = threadIdx.x / 64;
-        const int n_list = c->n_viol_b;
-        const int workers = wave_blocks * (kBlock / 64);
-        WaveLds* L = &lds[wave];
-        float move = 0.0f, sf = 0.0f;
-        for (int i = blockIdx.x * (kBlock / 64) + wave; i < n_list; i += workers)
-            move = fmaxf(move, project_wave_vertex(a, c, L, a.slow_list[a.n_verts - 1 - i], sf));
-        record_motion(a, move);
-        record_shortfall(a, sf);
-        return;
-    }
-    const int n_list = c->n_viol;
+// One lane per listed vertex of a list of regions of at most N half-spaces,
+// the sort and the passes in registers; block lb of the list's nb.
+template <int N>
+__device__ __forceinline__ void project_lane_list(const ProjectArgs& a, DevCounters* c, const int32_t* list,
+                                                  int n_list, int lb, int nb) {
     float move = 0.0f, sf = 0.0f;
-    for (int i0 = (blockIdx.x - wave_blocks) * kBlock; i0 < n_list; i0 += lane_blocks * kBlock) {
+    for (int i0 = lb * kBlock; i0 < n_list; i0 += nb * kBlock) {
         const int i = i0 + threadIdx.x;
         bool halted = false;
         if (i < n_list) {
-            const int v = a.slow_list[i];
+            const int v = list[i];
             long long o0;
             const int K = region_size(a, v, &o0);
             const MeshParams P = a.prm.get(a.prm.mesh_of(v));
             d3 y;
             const d3 yp = load_prop(a, v);
-            halted = project_small(a.hs + o0, K, yp, P, y);
+            halted = N == kSmall ? project_small(a.hs + o0, K, yp, P, y) : project_mid(a.hs + o0, K, yp, P, y);
             move = fmaxf(move, write_result(a, c, v, y, (double)P.r, halted, norm(yp), sf));
             slots_consumed(a, v);
         }
         const unsigned long long mh = __ballot(halted);
         if (__lane_id() == 0 && mh) spread_add(c, 1, (unsigned long long)__popcll(mh));
+        if (N != kSmall) {      // every vertex of the mid-size list has a violated half-space
+            const unsigned long long ml = __ballot(i < n_list);
+            if (__lane_id() == 0 && ml) spread_add(c, 0, (unsigned long long)__popcll(ml));
+        }
     }
     record_motion(a, move);
     record_shortfall(a, sf);
+}
+
+// The three slow lists in one launch.  Blocks [0, wave_blocks) run list B
+// (regions above kMid half-spaces), one vertex per wavefront, first, since
+// their vertices take the longest; the next mid_blocks run the mid-size list
+// (kSmall < K <= kMid) and the next lane_blocks list A (K <= kSmall), one lane
+// per vertex, the sort and the passes in registers.
+__global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCounters* c, int wave_blocks,
+                                                         int mid_blocks, int lane_blocks) {
+    if (a.skip && *a.skip) return;
+    __shared__ WaveLds lds[kBlock / 64];
+    const int b = (int)blockIdx.x;
+    if (b >= wave_blocks + mid_blocks + lane_blocks) {
+        // the next iteration's stretch start: the slow path reads no p
+        restart_pass(a.next.x_pred, a.next.p, a.next.n3, a.next.c0,
+                     (long long)(b - wave_blocks - mid_blocks - lane_blocks) * kBlock + threadIdx.x);
+        return;
+    }
+    // The mid-size list goes to the wavefronts too when they are enough for
+    // every listed vertex of both lists (a wavefront per vertex finishes one
+    // sooner than a lane does); when they are not, its lanes take it, 64
+    // vertices per wavefront.  The choice is the same for every block.
+    const int n_b = c->n_viol_b, n_m = c->n_viol_m;
+    const int workers = wave_blocks * (kBlock / 64);
+    const bool mid_by_waves = (long long)n_b + n_m <= workers;
+    if (b < wave_blocks) {
+        const int wave = threadIdx.x / 64;
+        const int n_list = n_b + (mid_by_waves ? n_m : 0);
+        WaveLds* L = &lds[wave];
+        float move = 0.0f, sf = 0.0f;
+        for (int i = b * (kBlock / 64) + wave; i < n_list; i += workers) {
+            const int v = i < n_b ? a.slow_list[a.n_verts - 1 - i] : a.slow_list[a.n_verts + (i - n_b)];
+            move = fmaxf(move, project_wave_vertex(a, c, L, v, sf));
+        }
+        record_motion(a, move);
+        record_shortfall(a, sf);
+        return;
+    }
+    if (b < wave_blocks + mid_blocks) {
+        if (!mid_by_waves)
+            project_lane_list<kMid>(a, c, a.slow_list + a.n_verts, n_m, b - wave_blocks, mid_blocks);
+    } else
+        project_lane_list<kSmall>(a, c, a.slow_list, c->n_viol, b - wave_blocks - mid_blocks, lane_blocks);
 }
 
 __global__ void k_zero_viol(DevCounters* c) {
     if (threadIdx.x == 0) {
         c->n_viol = 0;
         c->n_viol_b = 0;
+        c->n_viol_m = 0;
     }
 }
 
@@ -884,10 +989,11 @@ void launch_project(const ProjectArgs& a, DevCounters* c, bool zero_counters, hi
     // list sizes are known on the device only: enough blocks for a few
     // thousand wavefront vertices and a grid-stride over the lane list
     const int lane_blocks = std::max(1, std::min(1024, (a.n_verts + kBlock - 1) / kBlock));
+    const int mid_blocks = lane_blocks;
     const int wave_blocks = std::max(1, std::min(1024, (a.n_verts + kBlock / 64 - 1) / (kBlock / 64)));
     const int restart_blocks = restart_job_blocks(a.next, kBlock);
-    hipLaunchKernelGGL(k_project_slow, dim3(wave_blocks + lane_blocks + restart_blocks), dim3(kBlock), 0, s, a, c,
-                       wave_blocks, lane_blocks);
+    hipLaunchKernelGGL(k_project_slow, dim3(wave_blocks + mid_blocks + lane_blocks + restart_blocks), dim3(kBlock),
+                       0, s, a, c, wave_blocks, mid_blocks, lane_blocks);
 }
 
 }  // namespace ccfr

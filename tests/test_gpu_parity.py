@@ -316,23 +316,31 @@ def test_determinism_and_graph_replay(env, scenes):
 
 
 def test_projection_tiers(env):
-    """Regions of every size the projection handles differently (in registers,
-    sorted by a wavefront in LDS, sorted in global scratch), including exact
-    duplicates and ties, against the oracle on identical FP32 inputs."""
+    """Regions of every size the projection handles differently (in registers
+    by one lane up to 8 and up to 16, sorted by a wavefront in LDS, sorted in
+    global scratch), including exact duplicates and ties, against the oracle on
+    identical FP32 inputs.  The last vertices of sizes 12 and 16 have two
+    distinct violated half-spaces with exactly equal rho (normals orthogonal
+    to a proposal along x), so that the key decides their order."""
     ctx, ccfr, oracle, torch = env
     rng = np.random.default_rng(42)
-    sizes = [0, 1, 2, 5, 8, 9, 17, 64, 200, 256, 257, 300]
+    sizes = [0, 1, 2, 5, 8, 9, 12, 15, 16, 17, 64, 200, 256, 257, 300]
     verts_per_size = 6
     Ks = np.repeat(sizes, verts_per_size)
     N = len(Ks)
     r = 4e-3
     n_list, d_list = [], []
-    for K in Ks:
+    tie = np.zeros(N, bool)
+    for v, K in enumerate(Ks):
         n = rng.normal(size=(K, 3))
         n /= np.maximum(np.linalg.norm(n, axis=1, keepdims=True), 1e-12)
         d = rng.uniform(0, 2e-3, K)
         if K >= 4:                      # an exact duplicate and an exact rho tie
             n[1], d[1] = n[0], d[0]
+        if K in (12, 16) and (v + 1 == N or Ks[v + 1] != K):
+            tie[v] = True
+            n[2], n[3] = (0.0, 0.6, 0.8), (0.0, 0.8, -0.6)
+            d[2] = d[3] = -0.5e-3
         n_list.append(n)
         d_list.append(d)
     off = np.zeros(N + 1, np.int64)
@@ -343,6 +351,7 @@ def test_projection_tiers(env):
     hs32["d"] = np.concatenate(d_list).astype(np.float32)
     hs32["key"] = (np.uint64(1) << np.uint64(62)) + np.arange(nh, dtype=np.uint64)
     y = (rng.normal(size=(N, 3)) * 3e-3).astype(np.float32)
+    y[tie, 1:] = 0.0                    # n . y = 0 exactly for the tied pair
     w = np.ones(N, np.float32)
     w[3] = 0.0
     prm = S.Params(r=r, xi=1e-3)
