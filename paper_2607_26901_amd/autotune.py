@@ -194,7 +194,7 @@ def tune_mesh(ctx: ccfr.Context, mesh: ccfr.Mesh, x, v, sp: ccfr.StepParams, ste
 
 
 def tune_batch(ctx: ccfr.Context, batch: ccfr.Batch, candidates=CELL_SCALES, splits=PAIR_SPLITS,
-               modes=PAIR_MODES, log=_log) -> dict:
+               modes=PAIR_MODES, log=_log, directs=(0,)) -> dict:
     """Tune on one step of the resident batch; every trial is rolled back."""
     def run(limit=None):
         for _ in range(4):
@@ -213,4 +213,4 @@ def tune_batch(ctx: ccfr.Context, batch: ccfr.Batch, candidates=CELL_SCALES, spl
             ctx.grow(info)
         raise ccfr.CcfrError(-2, "tuning run")
 
-    return tune(ctx, run, candidates, splits, modes, log=log)
+    return tune(ctx, run, candidates, splits, modes, log=log, directs=directs)

@@ -35,7 +35,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kSmall = 8;      // regions up to this size stay in registers
-constexpr int kMid = 16;       // up to this size a violated region is projected by one lane
+constexpr int kMid = 32;       // up to this size a violated region is projected by one lane
 constexpr int kScan = 32;      // up to this size the fast kernel checks for a violation
 constexpr int kWave = 256;     // up to this size a wavefront sorts them in LDS
 
@@ -625,10 +625,12 @@ __device__ bool project_small(const ccfr_halfspace* H, int K, const d3 yprop, co
 // A region of kSmall < K <= kMid half-spaces projected by one lane.  Only
 // (rho, index) pairs go through the sorting network (a bitonic one, every
 // index a constant after unrolling); the keys that break ties of rho are read
-// from memory when a tie occurs, and the records are gathered in sorted order
-// afterwards, so the sort holds 3 registers per entry instead of 8.  Keys are
-// unique within a region, so the order is that of the other paths; duplicates
-// and passes as in project_small.
+// from memory when a tie occurs.  The sorted indices go to the lane's column
+// of LDS (entry q at col[q * kBlock], so that the lanes of a wavefront read
+// neighbouring bytes), and the passes gather each record from the region in
+// sorted order, the next one loaded while the current one is evaluated.  Keys
+// are unique within a region, so the order is that of the other paths;
+// duplicates and passes as in project_small.
 __device__ __forceinline__ uint64_t key_at(const ccfr_halfspace* H, int K, int q) {
     return q < K ? H[q].key : ~0ull;
 }
@@ -643,7 +645,8 @@ __device__ __forceinline__ uint64_t key_at(const ccfr_halfspace* H, int K, int q
         }                                                                                    \
     }
 
-__device__ bool project_mid(const ccfr_halfspace* H, int K, const d3 yprop, const MeshParams& P, d3& yres) {
+__device__ bool project_mid(const ccfr_halfspace* H, int K, const d3 yprop, const MeshParams& P, d3& yres,
+                            uint8_t* col) {
     double rho[kMid];
     int idx[kMid];
 #pragma unroll
@@ -664,27 +667,33 @@ __device__ bool project_mid(const ccfr_halfspace* H, int K, const d3 yprop, cons
             }
         }
     }
-    float4 R[kMid];
+    // (a NaN rho can leave padding before K: the index is clamped)
 #pragma unroll
-    for (int j = 0; j < kMid; ++j)    // (a NaN rho can leave padding before K: the index is clamped)
-        R[j] = j < K ? load_plane(H + min(idx[j], K - 1)) : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int j = 0; j < kMid; ++j) col[j * kBlock] = (uint8_t)min(idx[j], K - 1);
+    auto rec = [&](int q) { return load_plane(H + col[q * kBlock]); };
+    // an exact duplicate shares its rho with the entry before it (the order is
+    // sorted), and is then compared with every earlier entry of that rho
     uint32_t drop = 0u;
 #pragma unroll
     for (int j = 1; j < kMid; ++j) {
-        bool dj = false;
-#pragma unroll
-        for (int i = 0; i < j; ++i)
-            dj = dj || (rho[i] == rho[j] && R[i].x == R[j].x && R[i].y == R[j].y && R[i].z == R[j].z &&
-                        R[i].w == R[j].w);
-        if (dj) drop |= 1u << j;
-    }
-    auto get = [&](int q, d3& n, double& d) -> bool {
-#pragma unroll
-        for (int j = 0; j < kMid; ++j)
-            if (j == q) {
-                n = mk(R[j].x, R[j].y, R[j].z);
-                d = (double)R[j].w;
+        if (j < K && rho[j - 1] == rho[j]) {
+            const float4 rj = rec(j);
+            for (int i = 0; i < j; ++i) {
+                const float4 ri = rec(i);
+                if (rho_at(ri, yprop) == rho[j] && ri.x == rj.x && ri.y == rj.y && ri.z == rj.z && ri.w == rj.w) {
+                    drop |= 1u << j;
+                    break;
+                }
             }
+        }
+    }
+    // run_passes asks for entries 0, 1, ..., K - 1 in order in every pass
+    float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto get = [&](int q, d3& n, double& d) -> bool {
+        const float4 cur = q == 0 ? rec(0) : nxt;
+        if (q + 1 < K) nxt = rec(q + 1);
+        n = mk(cur.x, cur.y, cur.z);
+        d = (double)cur.w;
         return ((drop >> q) & 1u) == 0u;
     };
     return run_passes(K, get, yprop, P, yres);
@@ -902,7 +911,7 @@ __device__ __forceinline__ float project_wave_vertex(const ProjectArgs& a, DevCo
 // the sort and the passes in registers; block lb of the list's nb.
 template <int N>
 __device__ __forceinline__ void project_lane_list(const ProjectArgs& a, DevCounters* c, const int32_t* list,
-                                                  int n_list, int lb, int nb) {
+                                                  int n_list, int lb, int nb, uint8_t* col) {
     float move = 0.0f, sf = 0.0f;
     for (int i0 = lb * kBlock; i0 < n_list; i0 += nb * kBlock) {
         const int i = i0 + threadIdx.x;
@@ -914,7 +923,7 @@ __device__ __forceinline__ void project_lane_list(const ProjectArgs& a, DevCount
             const MeshParams P = a.prm.get(a.prm.mesh_of(v));
             d3 y;
             const d3 yp = load_prop(a, v);
-            halted = N == kSmall ? project_small(a.hs + o0, K, yp, P, y) : project_mid(a.hs + o0, K, yp, P, y);
+            halted = N == kSmall ? project_small(a.hs + o0, K, yp, P, y) : project_mid(a.hs + o0, K, yp, P, y, col);
             move = fmaxf(move, write_result(a, c, v, y, (double)P.r, halted, norm(yp), sf));
             slots_consumed(a, v);
         }
@@ -965,11 +974,14 @@ __global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCount
         record_shortfall(a, sf);
         return;
     }
+    // the lane paths' blocks use the wavefronts' LDS for the sorted indices
+    static_assert(sizeof(lds) >= (size_t)kMid * kBlock, "LDS of a block holds the sorted indices");
+    uint8_t* col = reinterpret_cast<uint8_t*>(lds) + threadIdx.x;
     if (b < wave_blocks + mid_blocks) {
         if (!mid_by_waves)
-            project_lane_list<kMid>(a, c, a.slow_list + a.n_verts, n_m, b - wave_blocks, mid_blocks);
+            project_lane_list<kMid>(a, c, a.slow_list + a.n_verts, n_m, b - wave_blocks, mid_blocks, col);
     } else
-        project_lane_list<kSmall>(a, c, a.slow_list, c->n_viol, b - wave_blocks - mid_blocks, lane_blocks);
+        project_lane_list<kSmall>(a, c, a.slow_list, c->n_viol, b - wave_blocks - mid_blocks, lane_blocks, col);
 }
 
 __global__ void k_zero_viol(DevCounters* c) {

@@ -209,7 +209,7 @@ class Server:
                 from . import autotune
                 # a short search: every setting re-records the step graph while requests wait
                 self.tuning = autotune.tune_batch(self.ctx, self.batch, candidates=(0.7, 0.85, 1.0), splits=(1,),
-                                                  modes=((1, 0),))
+                                                  modes=((1, 0), (2, 0)), directs=(0, 1))
             st.max_resident_verts = max(st.max_resident_verts, sum(r[0].scene.n_verts for r in resident.values()))
             # one step of every resident request
             while True:

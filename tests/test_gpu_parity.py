@@ -214,6 +214,69 @@ def test_projection_parity(env, scenes, k):
         assert st[0] > 0, "no vertex violated its region: the case tests nothing"
 
 
+def test_projection_lane_path_many_vertices(env):
+    """Enough violated regions of 9 to 32 half-spaces (8,192 vertices) that the
+    slow kernel's wavefronts are too few and one lane per vertex takes them:
+    every vertex against the oracle's projection of the same FP32 regions, with
+    exact duplicates and exact rho ties of distinct half-spaces among them."""
+    ctx, ccfr, oracle, torch = env
+    rng = np.random.default_rng(77)
+    N = 8192
+    Ks = rng.integers(9, 33, N)
+    r = 4e-3
+    y = (rng.normal(size=(N, 3)) * 3e-3).astype(np.float32)
+    tie = rng.random(N) < 0.1
+    y[tie, 1:] = 0.0
+    n_list, d_list = [], []
+    for v, K in enumerate(Ks):
+        n = rng.normal(size=(K, 3))
+        n /= np.linalg.norm(n, axis=1, keepdims=True)
+        d = rng.uniform(0.0, 2e-3, K)
+        d[0] = -float(n[0] @ y[v].astype(np.float64)) - 2e-4          # at least one violated
+        if v % 3 == 0:
+            n[4], d[4] = n[2], d[2]                                    # an exact duplicate
+        if tie[v]:                      # only the tied pair violated: n . y = 0 exactly for both
+            d[:] = 5e-3
+            n[5], n[6] = (0.0, 0.6, 0.8), (0.0, 0.8, -0.6)
+            d[5] = d[6] = -0.5e-3
+        n_list.append(n)
+        d_list.append(d)
+    off = np.zeros(N + 1, np.int64)
+    off[1:] = np.cumsum(Ks)
+    nh = int(off[-1])
+    hs32 = np.zeros(nh, ccfr.HALFSPACE_DTYPE)
+    hs32["n"] = np.concatenate(n_list).astype(np.float32)
+    hs32["d"] = np.concatenate(d_list).astype(np.float32)
+    hs32["key"] = (np.uint64(1) << np.uint64(62)) + rng.permutation(nh).astype(np.uint64)
+    prm = S.Params(r=r, xi=1e-3)
+    pts = S.assemble("points", [S._Mesh(np.zeros((N, 3)), np.zeros((0, 3), np.int64), np.ones(N))], prm,
+                     S.StepParams(dt=1 / 60))
+    regions = ccfr.caller_regions(torch.from_numpy(off.astype(np.int32)).cuda(),
+                                  torch.from_numpy(hs32.view(np.uint8)).cuda())
+    y_t = torch.from_numpy(y).cuda()
+    out = torch.empty_like(y_t)
+    halted = torch.zeros(N, dtype=torch.uint8).cuda()
+    ccfr.project_displacements(ctx, regions, torch.ones(N, dtype=torch.float32).cuda(), y_t, prm, out, halted)
+    torch.cuda.synchronize()
+    code, info = ctx.sync_status(reset=True)
+    assert code == 0, info
+    assert info["totals"][4] == N                       # every vertex counted as violating once
+    yg = out.cpu().numpy().astype(np.float64)
+    hg = halted.cpu().numpy()
+    _, hs_w = H.to_oracle_halfspaces(off, hs32)
+    yo, ho, fo, _ = oracle.project(oracle.Mesh(pts), prm, off, hs_w, y.astype(np.float64))
+    stable = fo == 0
+    err = np.linalg.norm(yg - yo, axis=1)
+    assert np.all(err[stable] <= H.DTOL * 1.0), float(err[stable].max())
+    assert np.array_equal(hg[stable], ho[stable].astype(np.uint8))
+    kinds = {"branch": 0, "unresolved": 0}
+    for v in np.nonzero(~stable)[0]:
+        kinds[H.match_projection(oracle, prm, 1.0, np.zeros(3), hs_w[off[v]:off[v + 1]], y[v].astype(np.float64),
+                                 yg[v], hg[v], H.DTOL * 1.0)] += 1
+    print(f"lane path: {int(stable.sum())} stable, {kinds}, {int(ho.sum())} halted of {N}")
+    assert kinds["unresolved"] == 0
+
+
 def test_xpbd_step_parity_and_no_penetration(env, scenes):
     """Single substeps from identical FP32 states match the oracle's FP64 substep."""
     ctx, ccfr, oracle, torch = env
