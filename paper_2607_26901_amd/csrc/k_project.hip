@@ -111,34 +111,79 @@ __device__ __forceinline__ bool same_plane(const ccfr_halfspace& a, const ccfr_h
     return a.n[0] == b.n[0] && a.n[1] == b.n[1] && a.n[2] == b.n[2] && a.d == b.d;
 }
 
-// Alg. 2 for a vertex with at least one violated half-space.  Returns true if it halted.
+__device__ __forceinline__ double rho_of(const ccfr_halfspace& h, const d3 y) {
+    return dot(load_n(h), y) + (double)h.d;
+}
+
+// Orders one wavefront's global-memory writes before its later reads (all of
+// its lanes run together; the workgroup's L1 serves them all).
+__device__ __forceinline__ void scratch_sync() {
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int orig_index(int i) { return i < 0 ? -1 - i : i; }
+
+// Alg. 2 for a region larger than a wavefront's LDS holds, by the 64 lanes of
+// one wavefront in the scratch range parallel to the region (skey, sidx).
+// (rho, index) pairs are sorted by (rho, key) with a bitonic network in the
+// form whose comparators all put the smaller element first (each merge opens
+// with a comparison of mirrored positions), so entries beyond K, taken as
+// +inf, never move and the range needs no padding; exact duplicates after the
+// first of their rho run get a negative index; the passes advance by ballots
+// over 64 sorted entries at a time, visiting exactly the half-spaces the
+// sequential pass would, in the same order, with the same arithmetic.
+// Returns true (on every lane) if the vertex halted.
 __device__ bool project_slow(const ccfr_halfspace* H, int K, const d3 yprop, const MeshParams& P,
                              double* skey, int32_t* sidx, d3& yres) {
-    // sort by (initial rho, key) ascending: insertion sort into the scratch range
-    for (int i = 0; i < K; ++i) {
-        const ccfr_halfspace hi = H[i];
-        const double rho = dot(load_n(hi), yprop) + (double)hi.d;
-        int j = i;
-        while (j > 0) {
-            const double pr = skey[j - 1];
-            const int pi = sidx[j - 1];
-            if (pr < rho || (pr == rho && H[pi].key < hi.key)) break;
-            skey[j] = pr;
-            sidx[j] = pi;
-            --j;
-        }
-        skey[j] = rho;
-        sidx[j] = i;
+    const int lane = __lane_id();
+    for (int j = lane; j < K; j += 64) {
+        skey[j] = rho_of(H[j], yprop);
+        sidx[j] = j;
     }
-    // drop exact duplicates: they share rho, so they sit in the same run
-    for (int q = 1; q < K; ++q) {
-        const ccfr_halfspace hq = H[sidx[q]];
-        for (int r = q - 1; r >= 0 && skey[r] == skey[q]; --r) {
-            if (sidx[r] >= 0 && same_plane(H[sidx[r]], hq)) {
-                sidx[q] = -1 - sidx[q];   // keep the index recoverable, mark dropped
-                break;
+    scratch_sync();
+    int Kp = 1;
+    while (Kp < K) Kp <<= 1;
+    for (int size = 2; size <= Kp; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = lane; t < (Kp >> 1); t += 64) {
+                const int p = 2 * t - (t & (stride - 1));              // bit `stride` of p is clear
+                const int q = stride == (size >> 1) ? (p ^ (size - 1)) : (p | stride);
+                if (q >= K) continue;
+                const double rp = skey[p], rq = skey[q];
+                bool sw = rq < rp;
+                const int ip = sidx[p], iq = sidx[q];
+                if (rq == rp) sw = H[iq].key < H[ip].key;
+                if (sw) {
+                    skey[p] = rq; skey[q] = rp;
+                    sidx[p] = iq; sidx[q] = ip;
+                }
             }
+            scratch_sync();
         }
+    }
+    // exact duplicates share rho, so they sit in one run; 64 entries per lane
+    // at a time are checked against the earlier entries of their run, then marked
+    for (int seg = 0; seg < K; seg += 64 * 64) {
+        uint64_t dropm = 0ull;
+        for (int k = 0; k < 64; ++k) {
+            const int q = seg + 64 * k + lane;
+            if (q >= K) break;
+            if (q == 0 || skey[q - 1] != skey[q]) continue;
+            const ccfr_halfspace hq = H[orig_index(sidx[q])];
+            for (int r = q - 1; r >= 0 && skey[r] == skey[q]; --r)
+                if (same_plane(H[orig_index(sidx[r])], hq)) {
+                    dropm |= 1ull << k;
+                    break;
+                }
+        }
+        scratch_sync();
+        for (int k = 0; k < 64; ++k)
+            if ((dropm >> k) & 1ull) {
+                const int q = seg + 64 * k + lane;
+                sidx[q] = -1 - sidx[q];
+            }
+        scratch_sync();
     }
     const double eps_r = (double)P.eps_retract;
     const double eps_p = (double)P.eps_plesnik;
@@ -149,17 +194,30 @@ __device__ bool project_slow(const ccfr_halfspace* H, int K, const d3 yprop, con
         Ero S;
         S.m = 0;
         int nviol = 0;
-        for (int q = 0; q < K; ++q) {
-            const int idx = sidx[q];
-            if (idx < 0) continue;
-            const ccfr_halfspace h = H[idx];
-            const d3 n = load_n(h);
-            const double d = (double)h.d;
-            if (dot(n, yt) + d >= 0.0) continue;
+        int from = 0;
+        while (true) {
+            // lowest violated entry at or after `from`, at the current point
+            int hit = -1;
+            for (int base = from & ~63; base < K; base += 64) {
+                const int q = base + lane;
+                bool viol = false;
+                if (q >= from && q < K) {
+                    const int idx = sidx[q];
+                    viol = idx >= 0 && rho_of(H[idx], yt) < 0.0;
+                }
+                const unsigned long long m = __ballot(viol);
+                if (m) {
+                    hit = base + __ffsll((long long)m) - 1;
+                    break;
+                }
+            }
+            if (hit < 0) break;
+            const ccfr_halfspace h = H[sidx[hit]];
             ++nviol;
-            orthogonal_projection(yt, y0, n, -d, S, eps_p);
+            orthogonal_projection(yt, y0, load_n(h), -(double)h.d, S, eps_p);
             const double nd = norm(yt);
             yt = (nd > eps_r) ? ((nd - eps_r) / nd) * yt : mk(0.0, 0.0, 0.0);
+            from = hit + 1;
         }
         if (nviol == 0) {
             yres = yp;
@@ -757,15 +815,12 @@ __device__ __forceinline__ float project_wave_vertex(const ProjectArgs& a, DevCo
     bool halted = false;
     const ccfr_halfspace* H = a.hs + o0;
     if (K > kWave) {
-        // beyond LDS: one lane sorts in the scratch range parallel to the CSR range
+        // beyond LDS: the wavefront sorts in the scratch range parallel to the region
         bool any = false;
         for (int j = lane; j < K; j += 64) any = any || rho_at(load_plane(H + j), yprop) < 0.0;
         if (__ballot(any)) {
-            if (lane == 0) {
-                halted = project_slow(H, K, yprop, P, a.sort_key + o0, a.sort_idx + o0, y);
-                spread_add(c, 0, 1ull);
-            }
-            halted = __shfl(halted ? 1 : 0, 0) != 0;
+            if (lane == 0) spread_add(c, 0, 1ull);
+            halted = project_slow(H, K, yprop, P, a.sort_key + o0, a.sort_idx + o0, y);
         }
     } else {
         int Kp = 1;

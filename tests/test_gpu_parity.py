@@ -380,14 +380,15 @@ def test_determinism_and_graph_replay(env, scenes):
 
 def test_projection_tiers(env):
     """Regions of every size the projection handles differently (in registers
-    by one lane up to 8 and up to 16, sorted by a wavefront in LDS, sorted in
-    global scratch), including exact duplicates and ties, against the oracle on
+    by one lane up to 8 and up to 16, sorted by a wavefront in LDS, sorted by a
+    wavefront in global scratch, beyond 4,096 entries in several duplicate
+    segments), including exact duplicates and ties, against the oracle on
     identical FP32 inputs.  The last vertices of sizes 12 and 16 have two
     distinct violated half-spaces with exactly equal rho (normals orthogonal
     to a proposal along x), so that the key decides their order."""
     ctx, ccfr, oracle, torch = env
     rng = np.random.default_rng(42)
-    sizes = [0, 1, 2, 5, 8, 9, 12, 15, 16, 17, 64, 200, 256, 257, 300]
+    sizes = [0, 1, 2, 5, 8, 9, 12, 15, 16, 17, 64, 200, 256, 257, 300, 600, 1500, 5000]
     verts_per_size = 6
     Ks = np.repeat(sizes, verts_per_size)
     N = len(Ks)
