@@ -28,8 +28,12 @@ def _hipcc() -> str:
 
 
 def flags() -> list:
+    # -ffp-contract=on: a multiply and an add are fused only within one source
+    # expression, never across the inlined operators of the vector type, so
+    # that the same source gives the same rounding wherever it is inlined (the
+    # projection's paths then agree bit for bit)
     return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno-bitwise-instead-of-logical", "-Wno-unused-function",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(HERE, "..", "include")]
 
 

@@ -132,7 +132,8 @@ __device__ __forceinline__ int orig_index(int i) { return i < 0 ? -1 - i : i; }
 // +inf, never move and the range needs no padding; exact duplicates after the
 // first of their rho run get a negative index; the passes advance by ballots
 // over 64 sorted entries at a time, visiting exactly the half-spaces the
-// sequential pass would, in the same order, with the same arithmetic.
+// sequential pass of run_passes would, in the same order, with the same
+// arithmetic (its scalar tail once three planes are stored included).
 // Returns true (on every lane) if the vertex halted.
 __device__ bool project_slow(const ccfr_halfspace* H, int K, const d3 yprop, const MeshParams& P,
                              double* skey, int32_t* sidx, d3& yres) {
@@ -218,6 +219,37 @@ __device__ bool project_slow(const ccfr_halfspace* H, int K, const d3 yprop, con
             const double nd = norm(yt);
             yt = (nd > eps_r) ? ((nd - eps_r) / nd) * yt : mk(0.0, 0.0, 0.0);
             from = hit + 1;
+            if (S.m == 3) {
+                // the rest of the pass on the scalar length, as in run_passes
+                double lam = norm(yt);
+                const d3 u = lam > 0.0 ? (1.0 / lam) * yt : mk(0.0, 0.0, 0.0);
+                while (true) {
+                    int hit2 = -1;
+                    for (int base = from & ~63; base < K; base += 64) {
+                        const int q = base + lane;
+                        bool viol = false;
+                        if (q >= from && q < K) {
+                            const int idx = sidx[q];
+                            if (idx >= 0) {
+                                const ccfr_halfspace hq = H[idx];
+                                const double au = dot(load_n(hq), u);
+                                viol = lam * au + (double)hq.d < 0.0;
+                            }
+                        }
+                        const unsigned long long m = __ballot(viol);
+                        if (m) {
+                            hit2 = base + __ffsll((long long)m) - 1;
+                            break;
+                        }
+                    }
+                    if (hit2 < 0) break;
+                    ++nviol;
+                    lam = lam > eps_r ? lam - eps_r : 0.0;
+                    from = hit2 + 1;
+                }
+                yt = lam * u;
+                break;
+            }
         }
         if (nviol == 0) {
             yres = yp;
@@ -424,7 +456,14 @@ __device__ __forceinline__ int region_size(const ProjectArgs& a, int v, long lon
 }
 
 // Alg. 2's passes over a sorted, de-duplicated sequence: entry q of K gives a
-// plane (n, d) or is skipped.  Returns true if the vertex halted.
+// plane (n, d) or is skipped (get is asked for 0, 1, ..., K - 1 in order in
+// every pass).  Once Alg. 1 holds three planes it returns its input for the
+// rest of the pass, so every further violation only retracts: yt = lam u
+// keeps its direction and loses eps in length, and rho of an entry is
+// lam (n . u) + d.  The rest of the pass runs on the scalar lam (the result
+// differs from rescaling yt step by step by rounding only); every path of the
+// projection takes this same step, so a vertex's result does not depend on
+// which path takes it.  Returns true if the vertex halted.
 template <class Get>
 __device__ __forceinline__ bool run_passes(int K, const Get& get, const d3 yprop, const MeshParams& P, d3& yres) {
     const double eps_r = (double)P.eps_retract;
@@ -445,6 +484,20 @@ __device__ __forceinline__ bool run_passes(int K, const Get& get, const d3 yprop
             orthogonal_projection(yt, y0, n, -d, S, eps_p);
             const double nd = norm(yt);
             yt = (nd > eps_r) ? ((nd - eps_r) / nd) * yt : mk(0.0, 0.0, 0.0);
+            if (S.m == 3) {
+                double lam = norm(yt);
+                const d3 u = lam > 0.0 ? (1.0 / lam) * yt : mk(0.0, 0.0, 0.0);
+                for (int q2 = q + 1; q2 < K; ++q2) {
+                    if (!get(q2, n, d)) continue;
+                    const double au = dot(n, u);
+                    if (lam * au + d < 0.0) {
+                        ++nviol;
+                        lam = lam > eps_r ? lam - eps_r : 0.0;
+                    }
+                }
+                yt = lam * u;
+                break;
+            }
         }
         if (nviol == 0) {
             yres = yp;
@@ -799,10 +852,8 @@ __device__ __forceinline__ float4 take(const float4 (&R)[kChunks], int chunk, in
 // point for its entries at or after the last hit, the lowest violated one is
 // the next hit, and all lanes apply the same Alg. 1 update and retraction to
 // their (identical) copies of the state.  This visits exactly the half-spaces
-// the sequential pass would, in the same order, with the same arithmetic up to
-// the third stored plane of a pass; from there on the pass only retracts, and
-// the rest of it runs on the length of yt (one subtraction per violation; the
-// result differs from the step-by-step rescaling by rounding only).
+// the sequential pass of run_passes would, in the same order, with the same
+// arithmetic, its scalar tail once three planes are stored included.
 // Returns the anchor's largest coordinate move (on lane 0; 0 elsewhere).
 __device__ __forceinline__ float project_wave_vertex(const ProjectArgs& a, DevCounters* c, WaveLds* L, int v,
                                                      float& sf) {

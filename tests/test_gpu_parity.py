@@ -218,7 +218,9 @@ def test_projection_lane_path_many_vertices(env):
     """Enough violated regions of 9 to 32 half-spaces (8,192 vertices) that the
     slow kernel's wavefronts are too few and one lane per vertex takes them:
     every vertex against the oracle's projection of the same FP32 regions, with
-    exact duplicates and exact rho ties of distinct half-spaces among them."""
+    exact duplicates and exact rho ties of distinct half-spaces among them;
+    then the first 64 of them alone, which the wavefronts take, bit for bit
+    equal to the lanes' results."""
     ctx, ccfr, oracle, torch = env
     rng = np.random.default_rng(77)
     N = 8192
@@ -275,6 +277,19 @@ def test_projection_lane_path_many_vertices(env):
                                  yg[v], hg[v], H.DTOL * 1.0)] += 1
     print(f"lane path: {int(stable.sum())} stable, {kinds}, {int(ho.sum())} halted of {N}")
     assert kinds["unresolved"] == 0
+    # the first 64 regions alone, few enough for the wavefronts to take them:
+    # the same results bit for bit (a vertex's result does not depend on the path)
+    m = 64
+    regions_m = ccfr.caller_regions(torch.from_numpy(off[:m + 1].astype(np.int32)).cuda(),
+                                    torch.from_numpy(hs32[:off[m]].view(np.uint8)).cuda())
+    y_m = torch.from_numpy(y[:m].copy()).cuda()
+    out_m = torch.empty_like(y_m)
+    halted_m = torch.zeros(m, dtype=torch.uint8).cuda()
+    ccfr.project_displacements(ctx, regions_m, torch.ones(m, dtype=torch.float32).cuda(), y_m, prm, out_m, halted_m)
+    torch.cuda.synchronize()
+    assert ctx.sync_status(reset=True)[0] == 0
+    assert np.array_equal(out_m.cpu().numpy(), out.cpu().numpy()[:m])
+    assert np.array_equal(halted_m.cpu().numpy(), hg[:m])
 
 
 def test_xpbd_step_parity_and_no_penetration(env, scenes):
