@@ -292,7 +292,8 @@ def bench_served(args):
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": sv["workload"], "requests": sv["requests"], "vertices": sv["vertices"],
-                   "budget_bytes": sv["budget_bytes"]},
+                   "budget_bytes": sv["budget_bytes"], "iters_per_step": 10},
+        "tuning": bs.get("tuning"),
         "p50_step_ms": bs["p50_request_step_ms"],
         "p99_step_ms": bs["p99_request_step_ms"],
         "served": sv,

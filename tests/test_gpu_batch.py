@@ -217,3 +217,52 @@ def test_batch_rollback_and_errors(env):
     code, info = ctx.sync_status(reset=True)
     assert code == 0, info
     b.close()
+
+
+def _steps_grown(ctx, step, restore, steps):
+    """`steps` steps, each run again after growing the lists when they overflow."""
+    for _ in range(steps):
+        for _ in range(4):
+            step()
+            code, info = ctx.sync_status(reset=True)
+            if code == 0:
+                break
+            assert code == -2, info
+            ctx.grow(info)
+            restore()
+        else:
+            raise AssertionError("capacity did not converge")
+
+
+def test_served_request_alone_equals_mixed_bitwise(env):
+    """A request of the served stream whose crumpled regions reach 300
+    half-spaces, run for all its steps alone and batched with three others:
+    the same positions and velocities bit for bit (the projection's result for
+    a vertex does not depend on how many vertices the launch lists)."""
+    ctx, ccfr, oracle, torch = env
+    reqs = S.c4_requests(n_requests=64)
+    sc = reqs[24].scene
+    steps = sc.step.steps
+    mesh = ccfr.mesh_from_scene(ctx, sc)
+    x = torch.from_numpy(sc.x.copy()).cuda()
+    v = torch.from_numpy(sc.v.copy()).cuda()
+    sp = _step_params(ccfr, sc)
+    keep = {}
+
+    def step_alone():
+        keep["x"], keep["v"] = x.clone(), v.clone()
+        ccfr.xpbd_step(ctx, mesh, x, v, sp)
+
+    def restore_alone():
+        x.copy_(keep["x"])
+        v.copy_(keep["v"])
+
+    _steps_grown(ctx, step_alone, restore_alone, steps)
+    xa, va = x.cpu().numpy(), v.cpu().numpy()
+    scs = [sc] + [reqs[k].scene for k in (3, 5, 7)]
+    b = ccfr.Batch(ctx, 8, *_sizes(scs))
+    slots = [b.add_scene(s, _step_params(ccfr, s)) for s in scs]
+    _steps_grown(ctx, b.step, b.rollback, steps)
+    xb, vb = b.read(slots[0])
+    b.close()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
