@@ -254,7 +254,7 @@ int ccfr_apply_response(ccfr_ctx* ctx, const ccfr_regions* regions, const float*
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same kernels and results, no context, and no allocation of
  * any kind.  Its scratch (device counters, the list of deferred vertices, sort
- * keys of large regions) is one file-scope device array of about 52 MB that
+ * keys of large regions) is one file-scope device array of about 56 MiB that
  * every GPU the library runs on holds until the process ends, found with
  * hipGetSymbolAddress on the first call on each device.
  *  - Limits: regions->n_verts <= 2^20 and regions->cap <= 2^22 half-spaces;
