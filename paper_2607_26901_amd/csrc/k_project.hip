@@ -782,18 +782,23 @@ __device__ bool project_mid(const ccfr_halfspace* H, int K, const d3 yprop, cons
 #pragma unroll
     for (int j = 0; j < kMid; ++j) col[j * kBlock] = (uint8_t)min(idx[j], K - 1);
     auto rec = [&](int q) { return load_plane(H + col[q * kBlock]); };
-    // an exact duplicate shares its rho with the entry before it (the order is
-    // sorted), and is then compared with every earlier entry of that rho
+    // an exact duplicate shares its rho with the entries before it in its run
+    // of equal rho (the order is sorted), and is compared with those only
     uint32_t drop = 0u;
+    int run = 0;                               // first entry of the current run
 #pragma unroll
     for (int j = 1; j < kMid; ++j) {
-        if (j < K && rho[j - 1] == rho[j]) {
-            const float4 rj = rec(j);
-            for (int i = 0; i < j; ++i) {
-                const float4 ri = rec(i);
-                if (rho_at(ri, yprop) == rho[j] && ri.x == rj.x && ri.y == rj.y && ri.z == rj.z && ri.w == rj.w) {
-                    drop |= 1u << j;
-                    break;
+        if (j < K) {
+            if (rho[j - 1] != rho[j]) {
+                run = j;
+            } else {
+                const float4 rj = rec(j);
+                for (int i = run; i < j; ++i) {
+                    const float4 ri = rec(i);
+                    if (ri.x == rj.x && ri.y == rj.y && ri.z == rj.z && ri.w == rj.w) {
+                        drop |= 1u << j;
+                        break;
+                    }
                 }
             }
         }
