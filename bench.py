@@ -240,7 +240,12 @@ def run_served(args, seq_stride=1):
     # warm-up: kernels loaded, graphs recorded once, workspace grown, on a few
     # small requests
     warm = [serve.Job(j.id, 0.0, j.scene, 2) for j in sorted(jobs, key=lambda j: j.scene.n_verts)[:4]]
-    srv = serve.Server(ctx, budget, tune_at=None if args.no_tune else 16, step_verts_cap=cap)
+    # the serving loop's stored tuner choice (TUNED), or with --tune its tuner
+    # run live once 16 requests are resident, or with --no-tune the defaults
+    knobs = None if (args.tune or args.no_tune) else TUNED["c4"]
+    if knobs:
+        ctx.set_tuning(**knobs)
+    srv = serve.Server(ctx, budget, tune_at=16 if args.tune else None, step_verts_cap=cap)
     srv.run(warm)
     serve.run_sequential(ctx, warm)
     torch.cuda.synchronize()
@@ -267,6 +272,9 @@ def run_served(args, seq_stride=1):
             "budget_bytes": budget, "step_verts_cap": cap,
             "sequential_sample": (f"every {seq_stride}th request by arrival ({len(seq_jobs)} of {len(jobs)})"
                                   if seq_stride > 1 else "all requests"),
+            "knobs": dict(ctx.get_tuning(), source=("stored choice of the serving loop's tuner (bench.py --tune "
+                                                   "runs it live)") if knobs else
+                          ("the serving loop's tuner, live" if args.tune else "defaults")),
             "batched": bs, "sequential": ss,
             "throughput_ratio": bs["throughput"] / ss["throughput"] if ss["throughput"] else None,
             "p99_request_step_ratio": (bs["p99_request_step_ms"] / ss["p99_request_step_ms"]
@@ -293,7 +301,7 @@ def bench_served(args):
         "data": "synthetic",
         "config": {"workload": sv["workload"], "requests": sv["requests"], "vertices": sv["vertices"],
                    "budget_bytes": sv["budget_bytes"], "iters_per_step": 10},
-        "tuning": bs.get("tuning"),
+        "tuning": sv["knobs"],
         "p50_step_ms": bs["p50_request_step_ms"],
         "p99_step_ms": bs["p99_request_step_ms"],
         "served": sv,

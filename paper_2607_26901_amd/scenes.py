@@ -261,6 +261,9 @@ BENCH_KNOBS = {
     "c2": dict(cell_scale=0.85, pair_split=1, pair_reuse=4, pair_skin=0),
     "c3": dict(cell_scale=0.85, pair_split=1, pair_reuse=1, pair_skin=0, direct_regions=1),
     "c5": dict(cell_scale=0.7, pair_split=9, pair_reuse=1, pair_skin=1),
+    # the served stream: the serving loop's tuner (16 requests resident) on
+    # the 512-request stream
+    "c4": dict(cell_scale=0.7, pair_split=1, pair_reuse=2, pair_skin=0, direct_regions=1),
 }
 
 
