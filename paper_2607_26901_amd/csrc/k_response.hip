@@ -24,10 +24,12 @@
 // FP64 registers from the FP32 region and proposal.
 //
 // Regions of up to kLaneK half-spaces: one lane, the relevant contacts sorted
-// in registers (up to kRel of them; more: an ordered walk).  Larger regions
-// are listed and taken by a wavefront each: every lane holds a slice of the
-// region, and each step selects the next contact by a wave-wide minimum and
-// forms its weight by a wave-wide product.
+// in registers (up to kRel of them).  Larger regions, and regions with more
+// relevant contacts, are listed and taken by a wavefront each: every lane
+// holds a slice of the region, and each step selects the next contact by a
+// wave-wide minimum and forms its weight by a wave-wide product.  (Without a
+// list, or beyond the wavefront's 256 entries, one lane walks the region in
+// order, finding each next contact by a scan.)
 #include "ccfr_internal.h"
 
 namespace ccfr {
@@ -179,7 +181,8 @@ __global__ __launch_bounds__(kBlock) void k_response(ResponseArgs a) {
     Vertex x{};
     if (in) x = vertex_of(a, v);
     // large regions go to the wavefront launch (one atomic per wavefront)
-    const bool listed = in && !x.idle && x.K > kLaneK && a.list;
+    const bool can_list = a.list && a.c;
+    const bool listed = in && !x.idle && x.K > kLaneK && can_list;
     const unsigned long long m = __ballot(listed);
     if (m) {
         const int lead = __ffsll((long long)m) - 1;
@@ -236,6 +239,20 @@ __global__ __launch_bounds__(kBlock) void k_response(ResponseArgs a) {
                 ri[q] = k;
             }
         ++n_rel;
+    }
+    // more relevant contacts than the registers hold: listed for the
+    // wavefront launch too (a lane's ordered walk would hold its whole
+    // wavefront for the region's K x relevant gap evaluations)
+    const unsigned long long mo = __ballot(overflow && can_list);
+    if (mo) {
+        const int lead = __ffsll((long long)mo) - 1;
+        int base = 0;
+        if (__lane_id() == lead) base = atomicAdd(&a.c->n_resp, __popcll(mo));
+        base = __shfl(base, lead);
+        if (overflow) {
+            a.list[base + __popcll(mo & ((1ull << __lane_id()) - 1ull))] = v;
+            return;
+        }
     }
     if (overflow) {
         ordered_walk(x, dt, y0, y);
