@@ -2,7 +2,7 @@
 // (Alg. 2 calling Alg. 1, the retraction and halt fallback of Sec. 3.2, and the
 // r-ball clamp of Alg. 4) on gfx950.
 //
-// One lane per vertex.  Region data stays FP32 in HBM; the arithmetic of the
+// Region data stays FP32 in HBM; the arithmetic of the
 // projection runs in FP64 registers, working in displacement coordinates (the
 // anchor is the origin, so a constraint n . x' >= b with b = n . x - d reads
 // n . y + d >= 0).  This removes the cancellation of world coordinates, which
@@ -15,11 +15,15 @@
 // every other one satisfied returns that projection (the first two passes of
 // Alg. 2, which need no sort in that case).  All other vertices are compacted
 // into lists for the slow kernel: their half-spaces are sorted by initial rho
-// ascending, ties by key (by one lane in registers up to 16, by a wavefront in
-// LDS up to 256, in a scratch range parallel to the CSR range beyond), exact duplicates
-// (bitwise-equal n and d) are dropped, then up to max_passes passes of Alg. 1
-// over the violated ones, each followed by the retraction by eps; a pass without
-// violation returns its start point, and otherwise the vertex halts at y = 0.
+// ascending, ties by key (by one lane in registers up to 8; up to 32 by one
+// lane, (rho, index) in registers and the records gathered in sorted order,
+// when the listed vertices outnumber the wavefronts, else by a wavefront; by
+// a wavefront in LDS up to 256 and in a scratch range parallel to the region
+// beyond), exact duplicates (bitwise-equal n and d) are dropped, then up to
+// max_passes passes of Alg. 1 over the violated ones, each followed by the
+// retraction by eps; a pass without violation returns its start point, and
+// otherwise the vertex halts at y = 0.  Every path takes the same arithmetic
+// in the same order, so a vertex's result does not depend on the path.
 //
 // Readings: A12 (Alg. 1's entry j = m is the new plane, and the stored plane is
 // that plane), A14 (Alg. 1 returns its input once three planes are stored), A15
