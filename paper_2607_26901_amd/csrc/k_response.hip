@@ -25,9 +25,9 @@
 //
 // Regions of up to kLaneK half-spaces: one lane, the relevant contacts sorted
 // in registers (up to kRel of them).  Larger regions, and regions with more
-// relevant contacts, are listed and taken by a wavefront each: every lane
-// holds a slice of the region, and each step selects the next contact by a
-// wave-wide minimum and forms its weight by a wave-wide product.  (Without a
+// relevant contacts, are listed and taken by a wavefront each: the relevant
+// contacts sorted in LDS, their weights formed in parallel, then applied in
+// order.  (Without a
 // list, or beyond the wavefront's 256 entries, one lane walks the region in
 // order, finding each next contact by a scan.)
 #include "ccfr_internal.h"
@@ -283,15 +283,35 @@ __device__ __forceinline__ double wave_prod(double x) {
     return x;
 }
 
-// One listed vertex by one wavefront (every lane runs it; y is the same on all).
-__device__ void response_wave_vertex(const ResponseArgs& a, int v) {
+// A wavefront's LDS for one listed vertex: its relevant contacts in (gap,
+// key) order with their region index and weight.
+struct RespLds {
+    double g[64 * kChunks];
+    uint64_t key[64 * kChunks];
+    double w[64 * kChunks];
+    int16_t idx[64 * kChunks];
+};
+
+// Orders the LDS writes and reads of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// One listed vertex by one wavefront (every lane runs it; y is the same on
+// all).  The gaps are taken at the proposal, so the order of the relevant
+// contacts and every weight are known before any update: the lanes compact
+// the relevant contacts into LDS, sort them by (gap, key) with a bitonic
+// network, form each contact's weight from the contacts before it (in that
+// order, as the lane path does), and then apply them one after the other.
+__device__ void response_wave_vertex(const ResponseArgs& a, int v, RespLds* L) {
     const int lane = __lane_id();
     const Vertex x = vertex_of(a, v);
     const double y0[3] = {x.yf[0], x.yf[1], x.yf[2]};
     const double delta = x.P.delta, dv = x.P.vis_width, dt = a.dt;
     double y[3] = {y0[0], y0[1], y0[2]};
     if (x.K > 64 * kChunks) {
-        // beyond the wavefront's registers: one lane walks the region
+        // beyond the wavefront's LDS: one lane walks the region
         if (lane == 0) {
             ordered_walk(x, dt, y0, y);
             write_out(a, v, y);
@@ -300,7 +320,6 @@ __device__ void response_wave_vertex(const ResponseArgs& a, int v) {
     }
     double g[kChunks];
     uint64_t key[kChunks];
-    bool rel[kChunks], done[kChunks];
     double d_min = __longlong_as_double(0x7ff0000000000000ll);
 #pragma unroll
     for (int ch = 0; ch < kChunks; ++ch) {
@@ -315,57 +334,73 @@ __device__ void response_wave_vertex(const ResponseArgs& a, int v) {
         }
     }
     d_min = wave_min(d_min);
+    // the relevant contacts, compacted in region order
+    int n_rel = 0;
+    const unsigned long long below = (1ull << lane) - 1ull;
 #pragma unroll
     for (int ch = 0; ch < kChunks; ++ch) {
-        rel[ch] = ch * 64 + lane < x.K && relevant(g[ch], d_min, delta, dv);
-        done[ch] = false;
+        const bool r = ch * 64 + lane < x.K && relevant(g[ch], d_min, delta, dv);
+        const unsigned long long m = __ballot(r);
+        if (r) {
+            const int q = n_rel + __popcll(m & below);
+            L->g[q] = g[ch];
+            L->key[q] = key[ch];
+            L->idx[q] = (int16_t)(ch * 64 + lane);
+        }
+        n_rel += __popcll(m);
     }
-    for (;;) {
-        // the next relevant contact in (gap, key) order: the lane's own first,
-        // then the wave-wide minimum (gaps first, then keys among equal gaps)
-        double bg = __longlong_as_double(0x7ff0000000000000ll);
-        uint64_t bk = ~0ull;
-        int bj = -1;
-#pragma unroll
-        for (int ch = 0; ch < kChunks; ++ch)
-            if (rel[ch] && !done[ch] && (g[ch] < bg || (g[ch] == bg && key[ch] < bk))) {
-                bg = g[ch];
-                bk = key[ch];
-                bj = ch * 64 + lane;
+    if (n_rel > 0) {
+        int np = 1;
+        while (np < n_rel) np <<= 1;
+        for (int q = n_rel + lane; q < np; q += 64) {
+            L->g[q] = __longlong_as_double(0x7ff0000000000000ll);   // +inf: sorts last
+            L->key[q] = ~0ull;
+            L->idx[q] = 0;
+        }
+        wave_sync();
+        for (int size = 2; size <= np; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int t = lane; t < (np >> 1); t += 64) {
+                    const int p = 2 * t - (t & (stride - 1));
+                    const int q = p + stride;
+                    const bool up = (p & size) == 0;
+                    const double gp = L->g[p], gq = L->g[q];
+                    const uint64_t kp = L->key[p], kq = L->key[q];
+                    const bool q_first = gq < gp || (gq == gp && kq < kp);
+                    if (up ? q_first : !q_first) {
+                        L->g[p] = gq; L->g[q] = gp;
+                        L->key[p] = kq; L->key[q] = kp;
+                        const int16_t ti = L->idx[p]; L->idx[p] = L->idx[q]; L->idx[q] = ti;
+                    }
+                }
+                wave_sync();
             }
-        const double gmin = wave_min(bg);
-        if (!(gmin < delta)) break;                    // no relevant contact left
-        const bool tie = bj >= 0 && bg == gmin;
-        uint64_t km = tie ? bk : ~0ull;
-        for (int off = 32; off > 0; off >>= 1) {
-            const uint64_t o = __shfl_xor(km, off);
-            km = o < km ? o : km;
         }
-        const unsigned long long owner = __ballot(tie && bk == km);
-        const int src = __ffsll((long long)owner) - 1;
-        const int c = __shfl(bj, src);
-        // its weight: the factors of the relevant contacts before it
-        double f = 1.0;
-        if (dv > 0.0)
-#pragma unroll
-            for (int ch = 0; ch < kChunks; ++ch)
-                if (rel[ch] && g[ch] < gmin) f *= 1.0 - smoothstep((gmin - g[ch]) / dv);
-        const double wc = dv > 0.0 ? wave_prod(f) : 1.0;
-        if (lane == src) {
-#pragma unroll
-            for (int ch = 0; ch < kChunks; ++ch)
-                if (ch * 64 + lane == c) done[ch] = true;
+        // each contact's weight: the factors of the contacts before it
+        for (int c = lane; c < n_rel; c += 64) {
+            double wc = 1.0;
+            if (dv > 0.0) {
+                const double gc = L->g[c];
+                for (int j = 0; j < c; ++j) wc *= 1.0 - smoothstep((gc - L->g[j]) / dv);
+            }
+            L->w[c] = wc;
         }
-        if (wc > 0.0) apply_contact(x.P, x.w, dt, plane_at(x.H, c), wc, y);
+        wave_sync();
+        for (int c = 0; c < n_rel; ++c) {
+            const double wc = L->w[c];
+            if (wc > 0.0) apply_contact(x.P, x.w, dt, plane_at(x.H, L->idx[c]), wc, y);
+        }
     }
     if (lane == 0) write_out(a, v, y);
+    wave_sync();   // the LDS is reused by the wavefront's next vertex
 }
 
 __global__ __launch_bounds__(kBlock) void k_response_waves(ResponseArgs a, int waves) {
     if (a.skip && *a.skip) return;
+    __shared__ RespLds lds[kBlock / 64];
     const int n = a.c->n_resp;
     for (int i = blockIdx.x * (kBlock / 64) + threadIdx.x / 64; i < n; i += waves)
-        response_wave_vertex(a, a.list[i]);
+        response_wave_vertex(a, a.list[i], &lds[threadIdx.x / 64]);
 }
 
 __global__ void k_response_clear(DevCounters* c, const uint32_t* skip) {
