@@ -36,8 +36,8 @@ namespace ccfr {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kLaneK = 32;         // regions up to this size by one lane
-constexpr int kRel = 16;           // relevant contacts a lane sorts in registers
+constexpr int kLaneK = 8;          // regions up to this size by one lane
+constexpr int kRel = 8;            // relevant contacts a lane sorts in registers
 constexpr int kChunks = 4;         // entries per lane of the wavefront path (256 per wavefront)
 
 __device__ __forceinline__ double smoothstep(double t) {

@@ -113,12 +113,12 @@ def test_response_substep_parity_and_no_penetration(env):
 @pytest.mark.parametrize("vis", [0.0, 0.5e-3, 2e-3])
 @pytest.mark.parametrize("alpha", [0.0, 1e-6])
 def test_apply_response_many_active_contacts(env, vis, alpha):
-    """Vertices with 2 to 300 active contacts: regions a lane takes (sorted in
-    registers, or walked in order past 16 relevant contacts), regions a
-    wavefront takes (33 to 256) and one beyond the wavefront's registers;
-    random normals, gaps inside the repulsion range with ties, several
-    visibility widths (0: every weight 1) and compliances, against the oracle
-    vertex by vertex on the same FP32 regions."""
+    """Vertices with 2 to 300 active contacts: regions a lane takes (up to 8,
+    sorted in registers), regions a wavefront takes (9 to 256: sorted in LDS,
+    weights formed in parallel) and one beyond the wavefront's LDS (walked in
+    order by one lane); random normals, gaps inside the repulsion range with
+    ties, several visibility widths (0: every weight 1) and compliances,
+    against the oracle vertex by vertex on the same FP32 regions."""
     ctx, ccfr, oracle, torch = env
     from paper_2607_26901_amd import scenes as S
     rng = np.random.default_rng(31)
