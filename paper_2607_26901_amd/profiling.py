@@ -156,7 +156,7 @@ def main(argv=None) -> int:
              "kernels": kernels}
     lines = [f"# {a.title or 'Kernels of one workload'}", "",
              "Commands (run from the repository root on the GPU host, each under `cd /tmp && export "
-             "TMPDIR=/tmp` for rocprofv3; output directories under gpurun_out/):", ""]
+             "TMPDIR=/tmp` for rocprofv3; `<out>` is a folder of the caller's choice):", ""]
     lines += [f"    {c}" for c in a.command]
     lines += ["", f"Profiled: {iterations} solver iterations ({iters_per_step} per substep); knobs "
               f"`{facts['knobs']}`.", "",
