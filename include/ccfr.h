@@ -396,9 +396,9 @@ int64_t ccfr_batch_footprint(int32_t n_verts, int32_t n_tris, int32_t n_edges);
 /* Admit a mesh: host arrays as in ccfr_mesh_create, plus initial x and v
  * ([n_verts][3] float32, finite) and its step parameters.  The collision part
  * of `sp` is per mesh; dt, gravity, iters and alpha must equal those of the
- * meshes already resident, early_exit must be 0 (a batch runs its meshes'
- * iterations together) and the collision flags must not ask for the response
- * (else CCFR_ERR_INVALID_ARG).  *slot receives the
+ * meshes already resident and early_exit must be 0 (a batch runs its meshes'
+ * iterations together; else CCFR_ERR_INVALID_ARG).  The response
+ * (CCFR_FLAG_RESPONSE) is per mesh too.  *slot receives the
  * lowest free slot id.  CCFR_ERR_CAPACITY if no slot or pool space is free;
  * nothing changes then.  Copies are made on `stream`, and the call waits for
  * them. */

@@ -457,8 +457,9 @@ void enqueue_step(ccfr_ctx* ctx, const StepPlan& plan, hipStream_t s) {
                            plan.col_total[0], sc.inv_mass, plan.lambda, plan.alpha_t, sc.vflags};
     const int n_col = (int)plan.col_total.size();
     // with the response (Sec. 3.3), which acts on the whole pass's result, no
-    // stretch colour is folded into the projection
-    const bool response = !sc.prm.table && sc.prm.one.response;
+    // stretch colour is folded into the projection; in a batch the response
+    // kernel runs when any mesh asks for it and passes the others' vertices by
+    const bool response = sc.prm.table ? plan.response_any : sc.prm.one.response != 0;
     const bool fold = plan.has_stretch && n_col >= 2 && plan.last_edge && plan.lambda_alt && !response;
     const bool fold2 = fold && n_col >= 3 && plan.prev_edge;
     const int n_launched = n_col - (fold2 ? 2 : fold ? 1 : 0);     // colours before the folded ones

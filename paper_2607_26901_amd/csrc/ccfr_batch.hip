@@ -245,6 +245,8 @@ int rebuild_plan(ccfr_batch* b, hipStream_t s) {
     pl.x = P.x;
     pl.v = P.v;
     pl.n_meshes = b->max_slots;
+    for (int k = 0; k < b->max_slots; ++k)
+        if (b->slot_busy[k] && b->table_h[k].response) pl.response_any = true;
     // builds that adapt to the motion: the least widening over the resident meshes
     if (ctx_skin_mult(ctx) > 0) {
         double skin = 0.0;
@@ -402,7 +404,6 @@ int ccfr_batch_add(ccfr_batch* b, int32_t n_verts, const int32_t* tris, int32_t 
                    const ccfr_step_params* sp, int32_t* slot, ccfr_stream stream) {
     if (!b || !x || !v || !slot || !step_params_ok(sp)) return CCFR_ERR_INVALID_ARG;
     if (sp->early_exit) return CCFR_ERR_INVALID_ARG;     // a batch runs its meshes' iterations together
-    if (sp->collision.flags & CCFR_FLAG_RESPONSE) return CCFR_ERR_INVALID_ARG;
     if (b->has_sp && !b->meshes.empty() && !same_step(b->sp, *sp)) return CCFR_ERR_INVALID_ARG;
     for (long long i = 0; i < 3LL * n_verts; ++i)
         if (!std::isfinite(x[i]) || !std::isfinite(v[i])) return CCFR_ERR_INVALID_ARG;

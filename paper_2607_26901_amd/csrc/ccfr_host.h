@@ -212,6 +212,9 @@ struct StepPlan {
     // projection is at most conv_tol
     bool early_exit = false;
     float conv_tol = 0.f;
+    // a batch: some resident mesh asks for the response (a single mesh reads
+    // its own parameters)
+    bool response_any = false;
 };
 
 void drop_graph(ccfr_ctx* ctx);

@@ -266,3 +266,36 @@ def test_served_request_alone_equals_mixed_bitwise(env):
     xb, vb = b.read(slots[0])
     b.close()
     assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+
+
+def test_batch_with_response_equals_alone_bitwise(env):
+    """Requests with the soft response, visibility weights and friction
+    batched with one without: every request ends bit for bit as alone (the
+    response runs over the pool and passes the plain request's vertices by;
+    without folded stretch colours the plain request takes the same bits)."""
+    from dataclasses import replace
+    ctx, ccfr, oracle, torch = env
+    base = _requests()
+    scs = []
+    for i, sc in enumerate(base[:3]):
+        if i < 2:
+            r = float(sc.params.r)
+            prm = replace(sc.params, delta=0.8 * r, response=True, resp_compliance=1e-6, vis_width=0.2 * r,
+                          mu_s=0.4, mu_k=0.3)
+            sc = replace(sc, params=prm)
+        scs.append(sc)
+    steps = 6
+    alone = [_run_single(ctx, ccfr, torch, sc, steps) for sc in scs]
+    b = ccfr.Batch(ctx, 4, *_sizes(scs))
+    slots = [b.add_scene(sc, _step_params(ccfr, sc)) for sc in scs]
+    for _ in range(steps):
+        b.step()
+    code, info = ctx.sync_status(reset=True)
+    assert code == 0, info
+    for (xa, va), k, sc in zip(alone, slots, scs):
+        xb, vb = b.read(k)
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb), sc.name
+    b.close()
+    # the response changed the requests that ask for it
+    plain = _run_single(ctx, ccfr, torch, base[0], steps)
+    assert not np.array_equal(plain[0], alone[0][0])
