@@ -1022,32 +1022,34 @@ __device__ __forceinline__ float project_wave_vertex(const ProjectArgs& a, DevCo
     return move;
 }
 
-// One lane per listed vertex of a list of regions of at most N half-spaces,
-// the sort and the passes in registers; block lb of the list's nb.
-template <int N>
-__device__ __forceinline__ void project_lane_list(const ProjectArgs& a, DevCounters* c, const int32_t* list,
-                                                  int n_list, int lb, int nb, uint8_t* col) {
+// One lane per listed vertex, the sort and the passes in registers, over list
+// A (regions of at most kSmall half-spaces) and then the n_m entries of the
+// mid-size list (kSmall < K <= kMid; none when the wavefronts take it);
+// block lb of the lane path's nb.
+__device__ __forceinline__ void project_lane_lists(const ProjectArgs& a, DevCounters* c, int n_a, int n_m, int lb,
+                                                   int nb, uint8_t* col) {
     float move = 0.0f, sf = 0.0f;
+    const int n_list = n_a + n_m;
     for (int i0 = lb * kBlock; i0 < n_list; i0 += nb * kBlock) {
         const int i = i0 + threadIdx.x;
         bool halted = false;
+        const bool mid = i >= n_a && i < n_list;
         if (i < n_list) {
-            const int v = list[i];
+            const int v = mid ? a.slow_list[a.n_verts + (i - n_a)] : a.slow_list[i];
             long long o0;
             const int K = region_size(a, v, &o0);
             const MeshParams P = a.prm.get(a.prm.mesh_of(v));
             d3 y;
             const d3 yp = load_prop(a, v);
-            halted = N == kSmall ? project_small(a.hs + o0, K, yp, P, y) : project_mid(a.hs + o0, K, yp, P, y, col);
+            halted = mid ? project_mid(a.hs + o0, K, yp, P, y, col) : project_small(a.hs + o0, K, yp, P, y);
             move = fmaxf(move, write_result(a, c, v, y, (double)P.r, halted, norm(yp), sf));
             slots_consumed(a, v);
         }
         const unsigned long long mh = __ballot(halted);
         if (__lane_id() == 0 && mh) spread_add(c, 1, (unsigned long long)__popcll(mh));
-        if (N != kSmall) {      // every vertex of the mid-size list has a violated half-space
-            const unsigned long long ml = __ballot(i < n_list);
-            if (__lane_id() == 0 && ml) spread_add(c, 0, (unsigned long long)__popcll(ml));
-        }
+        // every vertex of the mid-size list has a violated half-space
+        const unsigned long long ml = __ballot(mid);
+        if (__lane_id() == 0 && ml) spread_add(c, 0, (unsigned long long)__popcll(ml));
     }
     record_motion(a, move);
     record_shortfall(a, sf);
@@ -1055,24 +1057,24 @@ __device__ __forceinline__ void project_lane_list(const ProjectArgs& a, DevCount
 
 // The three slow lists in one launch.  Blocks [0, wave_blocks) run list B
 // (regions above kMid half-spaces), one vertex per wavefront, first, since
-// their vertices take the longest; the next mid_blocks run the mid-size list
-// (kSmall < K <= kMid) and the next lane_blocks list A (K <= kSmall), one lane
-// per vertex, the sort and the passes in registers.
+// their vertices take the longest; the next lane_blocks run list A (K <=
+// kSmall) and then the mid-size list (kSmall < K <= kMid), one lane per
+// vertex, the sort and the passes in registers.
 __global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCounters* c, int wave_blocks,
-                                                         int mid_blocks, int lane_blocks) {
+                                                         int lane_blocks) {
     if (a.skip && *a.skip) return;
     __shared__ WaveLds lds[kBlock / 64];
     const int b = (int)blockIdx.x;
-    if (b >= wave_blocks + mid_blocks + lane_blocks) {
+    if (b >= wave_blocks + lane_blocks) {
         // the next iteration's stretch start: the slow path reads no p
         restart_pass(a.next.x_pred, a.next.p, a.next.n3, a.next.c0,
-                     (long long)(b - wave_blocks - mid_blocks - lane_blocks) * kBlock + threadIdx.x);
+                     (long long)(b - wave_blocks - lane_blocks) * kBlock + threadIdx.x);
         return;
     }
     // The mid-size list goes to the wavefronts too when they are enough for
     // every listed vertex of both lists (a wavefront per vertex finishes one
-    // sooner than a lane does); when they are not, its lanes take it, 64
-    // vertices per wavefront.  The choice is the same for every block.
+    // sooner than a lane does); when they are not, the lanes take it after
+    // list A, 64 vertices per wavefront.  The choice is the same for every block.
     const int n_b = c->n_viol_b, n_m = c->n_viol_m;
     const int workers = wave_blocks * (kBlock / 64);
     const bool mid_by_waves = (long long)n_b + n_m <= workers;
@@ -1089,14 +1091,10 @@ __global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCount
         record_shortfall(a, sf);
         return;
     }
-    // the lane paths' blocks use the wavefronts' LDS for the sorted indices
+    // the lane path uses the wavefronts' LDS for the sorted indices
     static_assert(sizeof(lds) >= (size_t)kMid * kBlock, "LDS of a block holds the sorted indices");
     uint8_t* col = reinterpret_cast<uint8_t*>(lds) + threadIdx.x;
-    if (b < wave_blocks + mid_blocks) {
-        if (!mid_by_waves)
-            project_lane_list<kMid>(a, c, a.slow_list + a.n_verts, n_m, b - wave_blocks, mid_blocks, col);
-    } else
-        project_lane_list<kSmall>(a, c, a.slow_list, c->n_viol, b - wave_blocks - mid_blocks, lane_blocks, col);
+    project_lane_lists(a, c, c->n_viol, mid_by_waves ? 0 : n_m, b - wave_blocks, lane_blocks, col);
 }
 
 __global__ void k_zero_viol(DevCounters* c) {
@@ -1116,11 +1114,10 @@ void launch_project(const ProjectArgs& a, DevCounters* c, bool zero_counters, hi
     // list sizes are known on the device only: enough blocks for a few
     // thousand wavefront vertices and a grid-stride over the lane list
     const int lane_blocks = std::max(1, std::min(1024, (a.n_verts + kBlock - 1) / kBlock));
-    const int mid_blocks = lane_blocks;
     const int wave_blocks = std::max(1, std::min(1024, (a.n_verts + kBlock / 64 - 1) / (kBlock / 64)));
     const int restart_blocks = restart_job_blocks(a.next, kBlock);
-    hipLaunchKernelGGL(k_project_slow, dim3(wave_blocks + mid_blocks + lane_blocks + restart_blocks), dim3(kBlock),
-                       0, s, a, c, wave_blocks, mid_blocks, lane_blocks);
+    hipLaunchKernelGGL(k_project_slow, dim3(wave_blocks + lane_blocks + restart_blocks), dim3(kBlock), 0, s, a, c,
+                       wave_blocks, lane_blocks);
 }
 
 }  // namespace ccfr
