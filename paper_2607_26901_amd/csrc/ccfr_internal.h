@@ -472,7 +472,12 @@ __device__ __forceinline__ void restart_pass(const float* x_pred, float* p, long
         stretch_edge(colour_edge(c0.segs, c0.nseg, (int)i), c0.edges_sorted, c0.rest_sorted, c0.inv_mass, x_pred, p,
                      c0.lambda_sorted, c0.alpha_t, true);
 }
-// restart_pass run by extra blocks of another kernel (n3 == 0: none)
+// restart_pass run by extra blocks of another kernel (n3 == 0: none).  The
+// host kernel may hold few wavefronts per SIMD, so each thread copies
+// kRestartWide entries (block q covers kRestartWide * block consecutive ones,
+// every load coalesced, all loads issued before the stores) and takes one
+// edge of colour 0.
+constexpr int kRestartWide = 4;
 struct RestartJob {
     const float* x_pred;
     float* p;
@@ -480,8 +485,31 @@ struct RestartJob {
     StretchColor0 c0;
 };
 inline int restart_job_blocks(const RestartJob& r, int block) {
-    const long long n = r.n3 > r.c0.total ? r.n3 : (long long)r.c0.total;
-    return r.n3 > 0 ? (int)((n + block - 1) / block) : 0;
+    if (r.n3 <= 0) return 0;
+    const long long span = (long long)kRestartWide * block;
+    const long long copy_blocks = (r.n3 + span - 1) / span;
+    const long long edge_blocks = ((long long)r.c0.total + block - 1) / block;
+    return (int)(copy_blocks > edge_blocks ? copy_blocks : edge_blocks);
+}
+__device__ __forceinline__ void restart_pass_wide(const RestartJob& r, long long q, int t, int block) {
+    const long long i0 = q * kRestartWide * block + t;
+    float xv[kRestartWide];
+    uint8_t fl[kRestartWide];
+#pragma unroll
+    for (int j = 0; j < kRestartWide; ++j) {
+        const long long i = i0 + (long long)j * block;
+        xv[j] = i < r.n3 ? r.x_pred[i] : 0.0f;
+        fl[j] = (i < r.n3 && r.c0.total > 0) ? r.c0.vflags[i / 3] : (uint8_t)0;
+    }
+#pragma unroll
+    for (int j = 0; j < kRestartWide; ++j) {
+        const long long i = i0 + (long long)j * block;
+        if (i < r.n3 && !(fl[j] & VF_COLOR0)) r.p[i] = xv[j];
+    }
+    const long long e = q * block + t;
+    if (e < r.c0.total)
+        stretch_edge(colour_edge(r.c0.segs, r.c0.nseg, (int)e), r.c0.edges_sorted, r.c0.rest_sorted, r.c0.inv_mass,
+                     r.x_pred, r.p, r.c0.lambda_sorted, r.c0.alpha_t, true);
 }
 
 // The last colour of the stretch pass, folded into the projection that reads

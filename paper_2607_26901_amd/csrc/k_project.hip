@@ -1067,8 +1067,7 @@ __global__ __launch_bounds__(kBlock) void k_project_slow(ProjectArgs a, DevCount
     const int b = (int)blockIdx.x;
     if (b >= wave_blocks + lane_blocks) {
         // the next iteration's stretch start: the slow path reads no p
-        restart_pass(a.next.x_pred, a.next.p, a.next.n3, a.next.c0,
-                     (long long)(b - wave_blocks - lane_blocks) * kBlock + threadIdx.x);
+        restart_pass_wide(a.next, b - wave_blocks - lane_blocks, threadIdx.x, kBlock);
         return;
     }
     // The mid-size list goes to the wavefronts too when they are enough for
