@@ -162,7 +162,7 @@ typedef struct {
     int32_t iters;
     int32_t n_colors;      /* filled by orc_color_edges */
     double alpha;          /* stretch compliance */
-    int32_t early_exit;    /* 1: evaluateConvergence ends the iterations (reading A23) */
+    int32_t early_exit;    /* 1: evaluateConvergence ends the iterations (the reading in oracle_xpbd.c) */
     int32_t pad_;
     double conv_tol;       /* largest shortfall |p - x| - |y*| that counts as converged */
 } orc_step_params;

@@ -5,8 +5,8 @@
  *
  * Sec. 4.1: every primitive's axis-aligned box is expanded by
  * r + xi/2 + delta/2, and primitive pairs whose expanded boxes overlap are
- * passed to the narrow phase.  The contract this file implements (readings A4,
- * O1, O2) fixes the arithmetic so that the set is exact:
+ * passed to the narrow phase.  The contract this file implements fixes the
+ * arithmetic so that the set is exact:
  *
  *   pad = fl32(r + xi/2 + delta/2 + guard)          (sum in FP64, one rounding)
  *   lo  = fl32(min_v x_v - pad),  hi = fl32(max_v x_v + pad)   per axis, with

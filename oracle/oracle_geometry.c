@@ -8,7 +8,7 @@
  * regions, then the face interior), as in Ericson, "Real-Time Collision
  * Detection", Sec. 5.1.5.  Segment-segment: the clamped minimisation of the
  * squared distance over [0,1]^2 (Ericson Sec. 5.1.9), plus the parallel-segment
- * rule the paper leaves open (reading A7): when |d1 x d2|^2 <= 1e-10 |d1|^2 |d2|^2,
+ * rule the paper leaves open: when |d1 x d2|^2 <= 1e-10 |d1|^2 |d2|^2,
  * s is the midpoint of the overlap of the second segment projected onto the first
  * (clamped to [0,1]) and t is the clamped projection of the resulting point.
  */
@@ -31,7 +31,7 @@ int orc_closest_point_triangle(const double p[3], const double a[3], const doubl
     sub3(b, a, ab);
     sub3(c, a, ac);
     cross3(ab, ac, nrm);
-    /* reading A8: a triangle of (numerically) zero area has no face region */
+    /* a triangle of (numerically) zero area has no face region */
     if (dot3(nrm, nrm) <= 1e-12 * dot3(ab, ab) * dot3(ac, ac)) return -1;
 
     sub3(p, a, ap);
@@ -80,11 +80,11 @@ int orc_closest_points_segments(const double a[3], const double b[3], const doub
     sub3(d, c, d2);
     sub3(a, c, r);
     double A = dot3(d1, d1), E = dot3(d2, d2), F = dot3(d2, r);
-    if (A <= 0.0 || E <= 0.0) return -1;            /* reading A8: zero-length edge */
+    if (A <= 0.0 || E <= 0.0) return -1;            /* zero-length edge */
     double C = dot3(d1, r), B = dot3(d1, d2);
     cross3(d1, d2, cr);
     double s, t;
-    if (dot3(cr, cr) <= 1e-10 * A * E) {             /* reading A7: parallel */
+    if (dot3(cr, cr) <= 1e-10 * A * E) {             /* parallel */
         double ca[3], da[3];
         sub3(c, a, ca);
         sub3(d, a, da);
@@ -117,7 +117,7 @@ int orc_closest_points_segments(const double a[3], const double b[3], const doub
 
 /* Closest point q = (1 - t) a + t b on segment ab to p (Ericson Sec. 5.1.2:
  * the projection parameter clamped to [0, 1]).  Returns -1 for a segment of
- * zero length (reading A8). */
+ * zero length. */
 int orc_closest_point_segment(const double p[3], const double a[3], const double b[3], double* t) {
     double ab[3], ap[3];
     sub3(b, a, ab);

@@ -8,18 +8,18 @@
  * TEST INFRASTRUCTURE ONLY (see ccfr_oracle.h).
  *
  * Readings of the printed algorithms:
- *   A9   exact duplicate half-spaces (bitwise-equal n and d) are dropped before
+ *   -    exact duplicate half-spaces (bitwise-equal n and d) are dropped before
  *        sorting; the one with the smallest key is kept.
- *   A10  the ascending sort by rho breaks ties by ascending key.
- *   A12  in Alg. 1's loop over j = 1..m, entry m is the plane being added
+ *   -    the ascending sort by rho breaks ties by ascending key.
+ *   -    in Alg. 1's loop over j = 1..m, entry m is the plane being added
  *        (n_m, b_m), and the plane stored at the end is that same (n_m, b_m).
- *   A13  one tolerance eps_plesnik for Alg. 1 and eps_retract for Alg. 2.
- *   A14  once three independent planes are stored, Alg. 1 returns its input
+ *   -    one tolerance eps_plesnik for Alg. 1 and eps_retract for Alg. 2.
+ *   -    once three independent planes are stored, Alg. 1 returns its input
  *        unchanged (in R^3 a fourth plane cannot be independent).
- *   A15  max_passes is the literal loop count of Alg. 2: a pass that finds no
+ *   -    max_passes is the literal loop count of Alg. 2: a pass that finds no
  *        violated half-space returns the position it started from; after
  *        max_passes passes with violations the vertex falls back to x (halt).
- *   A16  the clamp |x* - x| <= r of Alg. 4 is applied after the projection, also
+ *   -    the clamp |x* - x| <= r of Alg. 4 is applied after the projection, also
  *        to vertices with no half-space; static vertices (w = 0) do not move.
  *
  * Fragility.  A vertex is reported fragile when one of its discrete decisions
@@ -100,7 +100,7 @@ static void orthogonal_projection(double xt[3], const double x0[3], const double
         push(S, v0, n, b);
         return;
     }
-    if (S->m == 3) return;                                         /* A14 */
+    if (S->m == 3) return;                                         /* three planes stored */
     const int m = S->m;
     const double* n0 = S->A[0];
     const double b0 = S->B[0];
@@ -114,7 +114,7 @@ static void orthogonal_projection(double xt[3], const double x0[3], const double
     for (int k = 0; k < 3; ++k) u[k] = xt[k] + (alpha_u / beta_u) * S->V[m - 1][k];
     for (int k = 0; k < 3; ++k) w[k] = x0[k] + nm[k];
     for (int j = 1; j <= m; ++j) {
-        const double* nj = (j < m) ? S->A[j] : nm;                 /* A12 */
+        const double* nj = (j < m) ? S->A[j] : nm;                 /* entry m: the new plane */
         const double bj = (j < m) ? S->B[j] : bm;
         double dnj[3] = {nj[0] - n0[0], nj[1] - n0[1], nj[2] - n0[2]};
         double beta_w = dot3(dnj, S->V[j - 1]);
@@ -132,7 +132,7 @@ static void orthogonal_projection(double xt[3], const double x0[3], const double
             double alpha_new = b0 - dot3(n0, u);
             for (int k = 0; k < 3; ++k) xt[k] = u[k] + (alpha_new / beta_new) * vnew[k];
         }
-        push(S, vnew, nm, bm);                                     /* A12 */
+        push(S, vnew, nm, bm);                                     /* stored: the new plane */
     }
 }
 
@@ -171,11 +171,11 @@ static int project_vertex(const orc_params* prm, double w, const double x[3], co
                           int64_t nC, const double y_in[3], double y_out[3], int* violated,
                           flags_t* fl) {
     *violated = 0;
-    if (w == 0.0) { y_out[0] = y_out[1] = y_out[2] = 0.0; return 0; }   /* A16 */
+    if (w == 0.0) { y_out[0] = y_out[1] = y_out[2] = 0.0; return 0; }   /* static: no move */
     double xp[3] = {x[0] + y_in[0], x[1] + y_in[1], x[2] + y_in[2]};   /* x' */
     int halted = 0;
     if (nC > 0) {
-        /* initial rho, sort ascending (A10), drop exact duplicates (A9) */
+        /* initial rho, sort ascending, drop exact duplicates */
         sort_item* it = (sort_item*)malloc(sizeof(sort_item) * (size_t)nC);
         for (int64_t k = 0; k < nC; ++k) {
             double dx[3] = {xp[0] - x[0], xp[1] - x[1], xp[2] - x[2]};

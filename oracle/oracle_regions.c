@@ -15,16 +15,16 @@
  *        d = w_f / (w_f + w_q) phi;
  * and stores (d, n / |n|, phi) for p.  This is Eq. 2/3 (Sec. 3.1) written for
  * mesh primitives.  Readings of the printed algorithm:
- *   A1  d = s (|n| - xi): the separation after the step is at least xi.
- *   A5  (FV) the normal points from the vertex q towards the face,
+ *   -   d = s (|n| - xi): the separation after the step is at least xi.
+ *   -   (FV) the normal points from the vertex q towards the face,
  *       n = x_A - x_q, and the share is w_f / (w_f + w_q): the printed
  *       x_q - x_A and w_p would let a face vertex move towards q.
- *   A6  effective inverse masses are sum bary * w as printed; a pair whose two
+ *   -   effective inverse masses are sum bary * w as printed; a pair whose two
  *       sides both have zero effective inverse mass gives no half-space; static
  *       vertices (w = 0) get no region.
- *   A7  EE closest points are computed once per pair with the lower edge index
+ *   -   EE closest points are computed once per pair with the lower edge index
  *       first, so both sides of a pair see the same two points.
- *   A8  zero-area triangles, zero-length edges and coincident closest points
+ *   -   zero-area triangles, zero-length edges and coincident closest points
  *       are skipped and counted.
  *   VV  free particles i, j (Sec. 4.2 point-point interactions) use Eq. 1-2
  *       directly: n = x_p - x_q, d = w_p / (w_p + w_q) phi.
@@ -84,7 +84,7 @@ static void narrow_phase_vertex(const orc_mesh* m, const orc_params* prm, int32_
                                 const passive_t* P, sink_t* s) {
     const double* w = m->inv_mass;
     const double r = prm->r, xi = prm->xi;
-    if (w[p] == 0.0) return;                                  /* A6 */
+    if (w[p] == 0.0) return;                                  /* static: no region */
 
     /* VF: p against its passive faces */
     for (int64_t i = 0; i < P->n_faces; ++i) {
@@ -165,13 +165,13 @@ static void narrow_phase_vertex(const orc_mesh* m, const orc_params* prm, int32_
                 s->n_degenerate++;
                 continue;
             }
-            double nvec[3] = {xA[0] - X(m, q)[0], xA[1] - X(m, q)[1], xA[2] - X(m, q)[2]};   /* A5 */
+            double nvec[3] = {xA[0] - X(m, q)[0], xA[1] - X(m, q)[1], xA[2] - X(m, q)[2]};   /* towards the face */
             double D = sqrt(nvec[0] * nvec[0] + nvec[1] * nvec[1] + nvec[2] * nvec[2]);
             double phi = D - xi;
             if (!(phi < 2.0 * r)) continue;
             if (D == 0.0) { s->n_degenerate++; continue; }
             double wf = bary[0] * w[fv[0]] + bary[1] * w[fv[1]] + bary[2] * w[fv[2]];
-            double wsum = wf + w[q];                                                      /* A5 */
+            double wsum = wf + w[q];                                                      /* face share */
             if (wsum == 0.0) continue;
             emit(s, nvec, D, phi, wf / wsum, make_key(ORC_KIND_VF, q, f), 0);
         }

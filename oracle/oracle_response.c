@@ -11,7 +11,7 @@
  * cubic smoothstep, lets the innermost contacts occlude farther ones; friction
  * follows Macklin et al. 2014 on the same active contacts.  Readings of what
  * the paper leaves open:
- *   A25  d_c is the pair's gap beyond the offset at the vertex's proposal y,
+ *   -    d_c is the pair's gap beyond the offset at the vertex's proposal y,
  *        with the two sides advancing in proportion to their shares of the
  *        gap: d_c = rho_c / s_c, rho_c = n_c . y + d_c(half-space), s_c the
  *        vertex side's share (so d_c = phi_c at y = 0).  A contact is active
@@ -21,14 +21,14 @@
  *        starting at zero (the constraint set is rebuilt every iteration):
  *        dn = w (s_c C_c) / (w + alpha~_c), alpha~_c = alpha / (w_c dt^2).
  *        A contact with w_c = 0 is fully occluded and skipped.
- *   A26  the visibility product runs over the vertex's other active
+ *   -    the visibility product runs over the vertex's other active
  *        contacts; delta_v = 0 gives every weight 1.
- *   A27  the active contacts are applied one after another, innermost first
+ *   -    the active contacts are applied one after another, innermost first
  *        (ascending d_c at the proposal, ties by key), each on the
  *        displacement the previous ones left; friction after each: with t the
  *        tangential part of the current displacement, t is removed if
  *        |t| < mu_s dn (static), else scaled down by min(mu_k dn / |t|, 1).
- *   A28  the response acts on the pairs of the vertex's region (phi < 2r);
+ *   -    the response acts on the pairs of the vertex's region (phi < 2r);
  *        every repulsion range of the paper's scenes is below 2r.
  */
 #include "ccfr_oracle.h"
@@ -65,7 +65,7 @@ void orc_apply_response(const orc_params* prm, double w, const orc_halfspace* C,
     for (int64_t k = 0; k < nC; ++k) {
         if (!(C[k].share > 0.0)) continue;
         const double rho = dot3(C[k].n, y_in) + C[k].d;
-        const double d = rho / C[k].share;                         /* A25 */
+        const double d = rho / C[k].share;                         /* gap at the proposal */
         if (d < prm->delta) {
             A[na].d = d;
             A[na].key = C[k].key;
@@ -73,14 +73,14 @@ void orc_apply_response(const orc_params* prm, double w, const orc_halfspace* C,
             na++;
         }
     }
-    for (int64_t i = 0; i < na; ++i) {                             /* A26 */
+    for (int64_t i = 0; i < na; ++i) {                             /* visibility weights */
         double wc = 1.0;
         if (prm->vis_width > 0.0)
             for (int64_t j = 0; j < na; ++j)
                 if (j != i) wc *= 1.0 - smoothstep((A[i].d - A[j].d) / prm->vis_width);
         A[i].weight = wc;
     }
-    qsort(A, (size_t)na, sizeof(active_t), cmp_active);            /* A27 */
+    qsort(A, (size_t)na, sizeof(active_t), cmp_active);            /* innermost first */
     double y[3] = {y_in[0], y_in[1], y_in[2]};
     for (int64_t i = 0; i < na; ++i) {
         if (!(A[i].weight > 0.0)) continue;

@@ -4,7 +4,7 @@
  *
  * TEST INFRASTRUCTURE ONLY (see ccfr_oracle.h).
  *
- * Reading A17 of Algorithm 4 (no response, friction or early exit):
+ * Reading of Algorithm 4 (no response, friction or early exit):
  *
  *   x~ = x + dt v + dt^2 g          (static / pinned vertices keep x)
  *   lambda = 0
@@ -21,13 +21,13 @@
  *         than conv_tol, max_v (|p_v - x_v| - |y*_v|) <= conv_tol
  *   v = (x - x_old) / dt
  *
- * Reading A23 of the convergence check: the paper runs more iterations while
+ * Reading of the convergence check: the paper runs more iterations while
  * "the current step size falls short of the expected advancement"; the
  * expected advancement of an iteration is taken as the proposal displacement
  * p - x that the XPBD constraints ask for, the current step as y* after the
  * projection and the clamp, and the loop ends once every dynamic vertex's step
  * comes within conv_tol of its proposal.
- * Reading A24 of the halting statistics: a run is a sequence of consecutive
+ * Reading of the halting statistics: a run is a sequence of consecutive
  * iterations of one substep in which the same vertex halts; the step reports
  * the longest run and how many halts extended a run to length 2 or to 3 and
  * more.

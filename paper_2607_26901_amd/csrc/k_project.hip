@@ -25,10 +25,10 @@
 // otherwise the vertex halts at y = 0.  Every path takes the same arithmetic
 // in the same order, so a vertex's result does not depend on the path.
 //
-// Readings: A12 (Alg. 1's entry j = m is the new plane, and the stored plane is
-// that plane), A14 (Alg. 1 returns its input once three planes are stored), A15
-// (max_passes is the literal loop count), A16 (the clamp also applies without
-// half-spaces; zero inverse mass gives y = 0).
+// Readings of the paper taken here: Alg. 1's entry j = m is the new plane, and
+// the stored plane is that plane; Alg. 1 returns its input once three planes
+// are stored; max_passes is the literal loop count; the clamp also applies
+// without half-spaces, and zero inverse mass gives y = 0.
 #include "ccfr_internal.h"
 
 #include <algorithm>

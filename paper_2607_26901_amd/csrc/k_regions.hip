@@ -28,13 +28,13 @@
 // atomic each), either from the contact list by a fill launch or, with the
 // direct_regions knob, straight from the narrow phase (no contact list).
 //
-// Readings of the printed Alg. 3: d = s (|n| - xi) (A1); for the face side of a
+// Readings of the printed Alg. 3: d = s (|n| - xi); for the face side of a
 // vertex-face pair the normal points from the vertex towards the face and the
-// share is w_f / (w_f + w_q) (A5); effective inverse masses are
-// sum_i bary_i w_i (A6) and a pair with w_A + w_B = 0 gives no half-space;
-// parallel edges (|d1 x d2|^2 <= 1e-10 |d1|^2 |d2|^2) take the midpoint of
-// their overlap (A7); zero-area triangles, zero-length edges and coincident
-// closest points are skipped and counted (A8).
+// share is w_f / (w_f + w_q); effective inverse masses are sum_i bary_i w_i,
+// and a pair with w_A + w_B = 0 gives no half-space; parallel edges
+// (|d1 x d2|^2 <= 1e-10 |d1|^2 |d2|^2) take the midpoint of their overlap;
+// zero-area triangles, zero-length edges and coincident closest points are
+// skipped and counted.
 #include "ccfr_internal.h"
 
 namespace ccfr {

@@ -1,5 +1,5 @@
-"""The convergence check of Alg. 4 (evaluateConvergence, reading A23) and the
-halting statistics (reading A24) on the GPU against the oracle, through the C
+"""The convergence check of Alg. 4 (evaluateConvergence) and the
+halting statistics on the GPU against the oracle, through the C
 ABI: a substep that ends early runs the same number of iterations as the
 oracle's and ends at its positions within the substep tolerance, whether it is
 replayed from the recorded graph or traced; a vertex that halts every

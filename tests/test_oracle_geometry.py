@@ -104,7 +104,7 @@ def test_segments_skew_common_perpendicular(orc):
 
 
 def test_segments_parallel_rule(orc):
-    """Reading A7: parallel segments take the midpoint of the overlap."""
+    """Parallel segments take the midpoint of the overlap."""
     a, b = np.array([0, 0, 0.]), np.array([1, 0, 0.])
     c, d = np.array([0.4, 0.1, 0]), np.array([1.6, 0.1, 0])
     rc, s, t = orc.closest_points_segments(a, b, c, d)
@@ -112,6 +112,6 @@ def test_segments_parallel_rule(orc):
     # disjoint along the line: endpoint to endpoint
     rc, s, t = orc.closest_points_segments(a, b, np.array([2, 0.1, 0]), np.array([3, 0.1, 0]))
     assert rc == 1 and s == 1.0 and t == 0.0
-    # zero-length edge is degenerate (reading A8)
+    # zero-length edge is degenerate
     rc, _, _ = orc.closest_points_segments(a, a, c, d)
     assert rc == -1

@@ -68,7 +68,7 @@ def test_alg1_dependent_plane_skipped(orc):
 
 
 def test_alg1_fourth_plane_returns_unchanged(orc):
-    """Reading A14: with three planes stored the fourth changes nothing."""
+    """Alg. 1 with three planes stored: the fourth changes nothing."""
     st = orc.EroState()
     x0 = np.array([0.3, -0.2, 0.9])
     xt = x0.copy()
@@ -172,7 +172,7 @@ def test_w8_corner(orc):
 
 def test_w7_halt(orc):
     """W7 (Sec. 3.2): without a clean pass within max_passes the vertex falls back
-    to x.  With the literal loop count 1 (reading A15) every violated vertex halts;
+    to x.  With the literal loop count 1 (the literal reading of max_passes) every violated vertex halts;
     an inconsistent set (no admissible point besides numerical noise) halts too."""
     hs = orc.make_halfspaces([[0, 0, 1.0]], [1e-3])
     y, h, _ = orc.project_one(_prm(1.0, 1e-3, max_passes=1), 1.0, np.zeros(3), hs, np.array([0, 0, -0.01]))
@@ -250,7 +250,7 @@ def test_alg2_invariants_and_exact_projection(orc):
 
 
 def test_alg2_sort_order_and_duplicates(orc):
-    """Reading A9/A10: exact duplicates do not change the result, and the result
+    """Exact duplicates do not change the result, and the result
     does not depend on the storage order of the half-spaces."""
     rng = np.random.default_rng(8)
     p = _prm(r=1.0, xi=1e-3)

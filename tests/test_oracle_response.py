@@ -1,5 +1,5 @@
 """Closed-form pins of the oracle's soft response, visibility weights and
-friction (Sec. 3.3; readings A25-A28 in oracle_response.c).
+friction (Sec. 3.3, as oracle_response.c reads it).
 
 The response energy k/2 w_c max(0, delta - d_c)^2 is the XPBD constraint
 C_c = max(0, delta - d_c) with compliance 1/k; a vertex takes its share s_c of

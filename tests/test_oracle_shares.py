@@ -4,13 +4,13 @@
    dynamic with unequal masses: w_side = sum_i beta_i w_i over the side's
    vertices (barycentric weights of the closest point, as printed), share
    s_A = w_A / (w_A + w_B), and every dynamic vertex of side A receives
-   (n, s_A phi), of side B (-n, s_B phi) (Eq. 2 with reading A1, A5, A6).
+   (n, s_A phi), of side B (-n, s_B phi) (Eq. 2 as Alg. 3 reads it).
    The geometry is dyadic so that the FP32 scene stores it exactly and the
    closest points, barycentrics and distances are known by construction; the
    masses are chosen so that a swapped share or a sum of beta^2 w gives other
    values.
 
-2. The XPBD compliance recurrence of the stretch pass (Alg. 4, reading A17):
+2. The XPBD compliance recurrence of the stretch pass (Alg. 4):
    for a lone edge restarted from the prediction every iteration, the
    multiplier follows lambda_k = lambda* (1 - rho^k) with
    lambda* = -C / alpha~ and rho = W / (W + alpha~), so the k-th update is

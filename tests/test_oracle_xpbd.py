@@ -1,4 +1,4 @@
-"""Pins of the oracle's plain XPBD substep (Alg. 4, reading A17) and end-to-end
+"""Pins of the oracle's plain XPBD substep (Alg. 4) and end-to-end
 checks of the property the method exists for: no interpenetration and a
 separation of at least xi after every step (Sec. 4.3: zero remaining
 violations at the end of every frame)."""
@@ -162,7 +162,7 @@ def test_contact_scenes_no_penetration(orc, make):
 
 
 def test_convergence_check_free_fall_closed_form(orc):
-    """Reading A23 of evaluateConvergence.  Far from everything, each iteration
+    """The reading of evaluateConvergence.  Far from everything, each iteration
     moves a vertex by min(|x~ - x|, r) towards the prediction; the check ends
     the step after the first iteration whose step is no longer shortened by
     the clamp, i.e. after ceil(|x~ - x| / r) iterations, at the same position
@@ -197,7 +197,7 @@ def test_convergence_check_free_fall_closed_form(orc):
 
 
 def test_consecutive_halt_statistics(orc):
-    """Reading A24: a vertex whose region cannot be satisfied within the pass
+    """Halting statistics: a vertex whose region cannot be satisfied within the pass
     budget halts every iteration (a run as long as the substep), one that never
     halts has none."""
     from dataclasses import replace

@@ -1,4 +1,4 @@
-"""The workload generators: every configuration starts valid (reading A20: no
+"""The workload generators: every configuration starts valid (the paper states no
 initial-intersection exclusion, so the minimum non-adjacent vertex-face,
 edge-edge, particle-particle and particle-edge distance must be at least
 xi + 0.1 mm), the strand generator's curl-halving rule fires where the
